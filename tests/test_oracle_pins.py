@@ -1,0 +1,450 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics
+(closed forms, brute force on tiny inputs, invariants, published test
+vectors).  None of these re-types the oracle's own formula: each compares it
+with an independent route to the same value."""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle as O
+from paper_1805_00569_amd import datagen
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------- SplitMix64
+
+def test_splitmix64_published_vectors():
+    for case in _load("splitmix64.json")["cases"]:
+        got = O.splitmix64_outputs(case["seed"], len(case["outputs"]))
+        assert got == [int(v) for v in case["outputs"]]
+
+
+def test_uniforms_are_top53_bits():
+    u = O.uniforms(1234567, 3)
+    z = O.splitmix64_outputs(1234567, 3)
+    for ui, zi in zip(u, z):
+        assert Fraction(ui) == Fraction(zi >> 11, 1 << 53)
+        assert 0.0 <= ui < 1.0
+
+
+# ---------------------------------------------------------------- distances
+
+def _py_dist2(a, b):
+    # Python floats are IEEE doubles and never contract a*b+c, so this is the
+    # sequential, separately rounded sum by construction.
+    acc = 0.0
+    for x, y in zip(a, b):
+        t = float(x) - float(y)
+        acc = acc + t * t
+    return acc
+
+
+def test_dist2_matches_python_scalar_loop_bitwise():
+    g = np.random.default_rng(0)
+    A = g.standard_normal((17, 23)) * g.uniform(0.1, 100, 23)
+    B = g.standard_normal((5, 23))
+    D = O.dist2(A, B)
+    for i in range(A.shape[0]):
+        for j in range(B.shape[0]):
+            assert D[i, j] == _py_dist2(A[i], B[j])
+
+
+def test_dist2_is_sequential_not_pairwise():
+    # sequential: ((2^53 + 1) + 1) ... each +1 is lost; pairwise would keep them
+    a = np.array([[2.0 ** 26.5] + [1.0] * 8])
+    b = np.zeros((1, 9))
+    seq = _py_dist2(a[0], b[0])
+    assert O.dist2(a, b)[0, 0] == seq
+    assert seq != float(sum(Fraction(v) ** 2 for v in a[0]))  # exact differs
+
+
+def test_dist2_exact_on_integers():
+    g = np.random.default_rng(1)
+    A = g.integers(-50, 50, (6, 7)).astype(np.float64)
+    B = g.integers(-50, 50, (4, 7)).astype(np.float32)
+    D = O.dist2(A, B)
+    for i in range(6):
+        for j in range(4):
+            assert D[i, j] == sum((int(A[i, k]) - int(B[j, k])) ** 2 for k in range(7))
+
+
+# ---------------------------------------------------------------- assignment
+
+def test_assign_brute_force_and_ties():
+    g = np.random.default_rng(2)
+    X = g.standard_normal((200, 6)).astype(np.float32)
+    C = g.standard_normal((9, 6))
+    C[5] = C[2]              # planted duplicate: index 2 must win
+    C[8] = X[10]             # exact hit
+    idx, dmin = O.assign(X, C)
+    for i in range(X.shape[0]):
+        best, bd = -1, math.inf
+        for j in range(C.shape[0]):
+            dj = _py_dist2(X[i], C[j])
+            if dj < bd:
+                best, bd = j, dj
+        assert idx[i] == best and dmin[i] == bd
+    assert idx[10] == 8 and dmin[10] == 0.0
+    assert not np.any(idx == 5)
+
+
+# ---------------------------------------------------------------- k-means++
+
+def test_blocked_cumsum_against_python_and_sequential_when_one_block():
+    g = np.random.default_rng(3)
+    w = g.uniform(0, 1, 1000) * 10.0 ** g.integers(-8, 8, 1000)
+    S = O.blocked_cumsum(w, block=256)
+    # independent Python statement of the blocked order
+    off = 0.0
+    for b0 in range(0, 1000, 256):
+        inner = 0.0
+        for i in range(b0, min(b0 + 256, 1000)):
+            inner = inner + float(w[i])
+            assert S[i] == off + inner
+        off = off + inner
+    assert np.all(np.diff(S) >= 0)
+    S1 = O.blocked_cumsum(w[:200], block=256)
+    acc = 0.0
+    for i in range(200):
+        acc = acc + float(w[i])
+        assert S1[i] == acc
+
+
+def test_kmeanspp_is_d2_sampling():
+    """Inverse-CDF selection: the share of u in [0,1) that picks point i equals
+    D2_i / sum(D2) (exactly, up to the grid step)."""
+    X = np.array([[0.0], [1.0], [3.0], [6.0], [10.0]])
+    D2 = O.dist2(X, X[[0]])[:, 0]            # weights 0, 1, 9, 36, 100
+    S = O.blocked_cumsum(D2)
+    grid = (np.arange(20000) + 0.5) / 20000
+    picks = np.array([int(np.argmax(S > u * S[-1])) for u in grid])
+    freq = np.bincount(picks, minlength=5) / grid.size
+    assert freq[0] == 0.0
+    np.testing.assert_allclose(freq, D2 / D2.sum(), atol=1e-4)
+
+
+def test_kmeanspp_first_centre_and_distinct():
+    g = np.random.default_rng(4)
+    X = g.standard_normal((500, 3))
+    C, idx = O.kmeanspp(X, 12, seed=77)
+    u0 = O.uniforms(77, 1)[0]
+    assert idx[0] == math.floor(u0 * 500)
+    assert len(set(idx.tolist())) == 12
+    np.testing.assert_array_equal(C, X[idx])
+
+
+# ---------------------------------------------------------------- Lloyd
+
+def _py_lloyd(X, C0, iters):
+    X = [list(map(float, r)) for r in X]
+    C = [list(map(float, r)) for r in C0]
+    k, d = len(C), len(X[0])
+
+    def asg():
+        out = []
+        for x in X:
+            best, bd = 0, math.inf
+            for j in range(k):
+                dj = _py_dist2(x, C[j])
+                if dj < bd:
+                    best, bd = j, dj
+            out.append(best)
+        return out
+
+    prev = None
+    for _ in range(iters):
+        a = asg()
+        delta = len(a) if prev is None else sum(1 for u, v in zip(a, prev) if u != v)
+        prev = a
+        for j in range(k):
+            s = [0.0] * d
+            c = 0
+            for i, x in enumerate(X):
+                if a[i] == j:
+                    c += 1
+                    for f in range(d):
+                        s[f] = s[f] + x[f]
+            if c:
+                C[j] = [s[f] / c for f in range(d)]
+        if delta == 0:
+            break
+    return np.array(C), np.array(asg(), dtype=np.int32)
+
+
+def test_lloyd_bitwise_against_python_loops():
+    w = datagen.small(5, 120, 4, comps=4)
+    C0, _ = O.kmeanspp(w.X, 4, seed=5)
+    C, a, _, _ = O.lloyd(w.X, C0, 6)
+    Cp, ap = _py_lloyd(w.X, C0, 6)
+    np.testing.assert_array_equal(C, Cp)
+    np.testing.assert_array_equal(a, ap)
+
+
+def _objective(X, C, a):
+    return float(sum(_py_dist2(X[i], C[a[i]]) for i in range(X.shape[0])))
+
+
+def test_lloyd_objective_nonincreasing_and_fixed_point():
+    w = datagen.small(6, 300, 5, comps=6)
+    C, _ = O.kmeanspp(w.X, 6, seed=6)
+    last = math.inf
+    for _ in range(8):
+        a, _ = O.assign(w.X, C)
+        obj = _objective(w.X, C, a)
+        assert obj <= last * (1 + 1e-12)
+        last = obj
+        C, _ = O.member_means(w.X, a, C)
+    Cf, af, passes, deltas = O.lloyd(w.X, C, 50)
+    assert deltas[-1] == 0 or passes == 50
+    if deltas[-1] == 0:
+        C2, a2, passes2, d2 = O.lloyd(w.X, Cf, 5)
+        np.testing.assert_array_equal(Cf, C2)
+        np.testing.assert_array_equal(af, a2)
+
+
+def test_empty_cluster_keeps_centre():
+    X = np.array([[0.0, 0.0], [0.1, 0.0], [5.0, 5.0]])
+    C0 = np.array([[0.0, 0.0], [5.0, 5.0], [100.0, 100.0]])
+    C, counts = O.member_means(X, np.array([0, 0, 1]), C0)
+    assert counts.tolist() == [2, 1, 0]
+    np.testing.assert_array_equal(C[2], C0[2])
+    assert C[0, 0] == 0.05
+
+
+# ---------------------------------------------------------------- K-balance
+
+def test_kbalance_equal_sizes_and_greedy_rule():
+    w = datagen.small(7, 256, 6, comps=5)
+    p = 8
+    C, MB = O.kbalance(w.X, p, 10, seed=7)
+    assert np.bincount(MB, minlength=p).tolist() == [32] * p
+    # replay: each sample takes its nearest centre that is not yet full
+    Ck, _ = O.kmeans(w.X, p, 10, seed=7)
+    CS = [0] * p
+    for i in range(w.X.shape[0]):
+        d = [_py_dist2(w.X[i], Ck[j]) for j in range(p)]
+        open_ = [j for j in range(p) if CS[j] < 32]
+        best = min(open_, key=lambda j: (d[j], j))
+        assert MB[i] == best
+        CS[best] += 1
+    # recomputed centres are member means
+    for j in range(p):
+        np.testing.assert_allclose(C[j], w.X[MB == j].astype(np.float64).mean(0), rtol=1e-13, atol=1e-13)
+
+
+def test_kbalance_with_huge_capacity_is_kmeans_assignment():
+    w = datagen.small(8, 200, 3, comps=4)
+    C, _ = O.kmeans(w.X, 5, 10, seed=8)
+    MB = O.kbalance_greedy(w.X, C, cap=10 ** 9)
+    a, _ = O.assign(w.X, C)
+    np.testing.assert_array_equal(MB, a)
+
+
+def test_kbalance_ragged_capacity():
+    w = datagen.small(9, 103, 3, comps=3)
+    C, MB = O.kbalance(w.X, 4, 5, seed=9)
+    sizes = np.bincount(MB, minlength=4)
+    assert sizes.sum() == 103 and sizes.max() <= 26
+
+
+# ---------------------------------------------------------------- kernel
+
+def test_gaussian_kernel_hand_values():
+    g = _load("gaussian_3pt.json")
+    P = np.array(g["points"])
+    K = O.kernel_matrix(P, P, g["sigma"])
+    np.testing.assert_allclose(K, np.exp(np.array(g["K_exponents"])), rtol=1e-15, atol=0)
+    assert np.all(np.diag(K) == 1.0)
+
+
+def test_kernel_properties():
+    g = np.random.default_rng(10)
+    X = g.standard_normal((40, 5))
+    K = O.kernel_matrix(X, X, 0.7)
+    assert np.all(np.diag(K) == 1.0)
+    np.testing.assert_array_equal(K, K.T)
+    assert np.all(K > 0) and np.all(K <= 1)
+    np.testing.assert_allclose(O.kernel_matrix(X, X, 1e8), np.ones((40, 40)), rtol=0, atol=1e-14)
+
+
+# ---------------------------------------------------------------- solve
+
+def test_solve_matches_explicit_inverse():
+    g = np.random.default_rng(11)
+    X = g.standard_normal((48, 3))
+    y = g.standard_normal(48)
+    r = O.fit_one(X, y, 1.3, 1e-2)
+    K = np.exp(-np.array([[sum((a - b) ** 2) for b in X] for a in X]) / (2 * 1.3 ** 2))
+    alpha = np.linalg.inv(K + 1e-2 * np.eye(48)) @ y
+    kappa = np.linalg.cond(K + 1e-2 * np.eye(48))
+    assert np.linalg.norm(r["alpha"] - alpha) / np.linalg.norm(alpha) < 50 * kappa * 2.2e-16
+    assert r["backward_error"] < 48 * 2.2e-16 * 10
+
+
+def test_two_by_two_closed_form():
+    X = np.array([[0.0], [1.0]])
+    y = np.array([2.0, -1.0])
+    lam, s = 0.3, 0.8
+    k = math.exp(-1.0 / (2 * s * s))
+    a = 1 + lam
+    det = a * a - k * k
+    want = np.array([(a * 2.0 - k * -1.0) / det, (a * -1.0 - k * 2.0) / det])
+    np.testing.assert_allclose(O.fit_one(X, y, s, lam)["alpha"], want, rtol=1e-14)
+
+
+def test_lambda_to_infinity():
+    g = np.random.default_rng(12)
+    X = g.standard_normal((30, 4))
+    y = g.standard_normal(30)
+    lam = 1e6
+    alpha = O.fit_one(X, y, 1.0, lam)["alpha"]
+    K = O.kernel_matrix(X, X, 1.0)
+    bound = np.linalg.norm(K, 2) * np.linalg.norm(y) / lam ** 2
+    assert np.linalg.norm(alpha - y / lam) <= bound * (1 + 1e-6)
+
+
+def test_sigma_to_infinity_sherman_morrison():
+    g = np.random.default_rng(13)
+    X = g.standard_normal((25, 3))
+    y = g.standard_normal(25)
+    lam = 0.5
+    alpha = O.fit_one(X, y, 1e9, lam)["alpha"]
+    want = (y - (y.sum() / (lam + 25)) * np.ones(25)) / lam
+    np.testing.assert_allclose(alpha, want, rtol=1e-9, atol=1e-12)
+
+
+def test_far_apart_points_give_identity():
+    X = np.arange(10, dtype=np.float64)[:, None] * 1000.0
+    y = np.linspace(-1, 1, 10)
+    r = O.fit_one(X, y, 1.0, 0.25)
+    np.testing.assert_allclose(r["alpha"], y / 1.25, rtol=4e-16, atol=0)
+    assert np.all(O.predict_one(X, r["alpha"], X + 500.0, 1.0) == 0.0)
+
+
+def test_interpolation_as_lambda_vanishes():
+    g = np.random.default_rng(14)
+    X = g.standard_normal((20, 2)) * 3
+    y = g.standard_normal(20)
+    r = O.fit_one(X, y, 0.5, 1e-12)
+    np.testing.assert_allclose(O.predict_one(X, r["alpha"], X, 0.5), y, atol=1e-8)
+
+
+def test_lambda_times_m():
+    X = np.random.default_rng(15).standard_normal((12, 2))
+    y = np.ones(12)
+    a1 = O.fit_one(X, y, 1.0, 0.01, lambda_times_m=True)
+    a2 = O.fit_one(X, y, 1.0, 0.12)
+    assert a1["lambda_eff"] == 0.12
+    np.testing.assert_array_equal(a1["alpha"], a2["alpha"])
+
+
+def test_not_spd_reports_lapack_pivot():
+    X = np.array([[0.0], [0.0], [1.0], [2.0]])          # duplicate rows
+    r = O.fit_one(X, np.ones(4), 1.0, -0.5)             # 1 - 0.5 > 0, then fails
+    assert r["status"] == O.STATUS_NOT_SPD
+    A = O.kernel_matrix(X, X, 1.0) - 0.5 * np.eye(4)
+    with pytest.raises(np.linalg.LinAlgError) as e:
+        scipy.linalg.cholesky(A, lower=True)
+    assert str(r["pivot"]) in str(e.value)
+    assert r["pivot"] == 2
+
+
+# ---------------------------------------------------------------- fit + predict
+
+def test_linear_kernel_equals_primal_ridge():
+    """Eq. (2) with the linear kernel of Table 1: x^T (X^T X + lam I)^-1 X^T y."""
+    g = np.random.default_rng(16)
+    X = g.standard_normal((60, 5))
+    y = g.standard_normal(60)
+    Xt = g.standard_normal((7, 5))
+    lam = 0.3
+    w = np.linalg.solve(X.T @ X + lam * np.eye(5), X.T @ y)
+    a = np.zeros(60, dtype=np.int32)
+    m = O.fit(X, y, a, np.zeros((1, 5)), 1, 1.0, lam, kernel="linear")
+    yhat, _ = O.predict(m, Xt)
+    np.testing.assert_allclose(yhat, Xt @ w, rtol=1e-10, atol=1e-12)
+
+
+def test_single_partition_is_algorithm_1():
+    w = datagen.small(17, 150, 4, k=30, p=1)
+    C, a, sizes = O.partition(w.X, 1, "given", centroids=np.zeros((1, 4)))
+    assert sizes.tolist() == [150]
+    m = O.fit(w.X, w.y, a, C, 1, 1.0, 1e-2)
+    yhat, _ = O.predict(m, w.Xt)
+    K = O.kernel_matrix(w.X, w.X, 1.0) + 1e-2 * np.eye(150)
+    alpha = np.linalg.solve(K, w.y)
+    np.testing.assert_allclose(yhat, O.kernel_matrix(w.Xt, w.X, 1.0) @ alpha, rtol=1e-10, atol=1e-12)
+
+
+def test_average_of_identical_models_is_the_model():
+    w = datagen.small(18, 80, 3, k=20)
+    a = np.zeros(80, dtype=np.int32)
+    m1 = O.fit(w.X, w.y, a, np.zeros((1, 3)), 1, 0.9, 1e-2)
+    m3 = O.Model([m1.Xparts[0]] * 3, [m1.alphas[0]] * 3, np.zeros((3, 3)), 0.9, 1e-2, "gaussian", [])
+    ya, _ = O.predict(m3, w.Xt, "average")
+    y1, _ = O.predict(m1, w.Xt)
+    np.testing.assert_allclose(ya, y1, rtol=1e-14, atol=1e-15)
+
+
+def test_nearest_route_uses_assignment():
+    w = datagen.small(19, 200, 3, k=50, comps=4)
+    C, a, _ = O.partition(w.X, 4, "kmeans", iters=10, seed=19)
+    m = O.fit(w.X, w.y, a, C, 4, 1.0, 1e-2)
+    yhat, r = O.predict(m, w.Xt, "nearest")
+    r2, _ = O.assign(w.Xt, C)
+    np.testing.assert_array_equal(r, r2)
+    allp, _ = O.predict(m, w.Xt, "all")
+    np.testing.assert_allclose(yhat, allp[np.arange(50), r], rtol=1e-13, atol=1e-15)
+
+
+def test_mse_and_select():
+    assert O.mse([1.0, 2.0, 4.0], [1.0, 0.0, 1.0]) == (0 + 4 + 9) / 3
+    assert O.select([3.0, 1.0, 1.0, 2.0]) == 1
+    assert O.select([math.inf, math.nan, 5.0]) == 2
+
+
+def test_label_oracle_select_is_lower_bound():
+    g = np.random.default_rng(20)
+    allp = g.standard_normal((30, 4))
+    y = g.standard_normal(30)
+    best, idx = O.label_oracle_select(allp, y)
+    for j in range(4):
+        assert O.mse(best, y) <= O.mse(allp[:, j], y)
+
+
+# ---------------------------------------------------------------- accounting
+
+def test_paper_speedup_numbers():
+    for case in _load("paper_numbers.json")["theoretical_speedup"]:
+        n = 128 * 1024
+        got = O.partitioned_speedup(n, case["p"], case["n_scale"] * n)
+        assert got == pytest.approx(case["speedup"], rel=1e-12)
+
+
+def test_fit_flops():
+    assert O.fit_flops(3, 2) == 9 + 18 + 4.5 + 18
+
+
+# ---------------------------------------------------------------- generators
+
+def test_generators_shapes_and_determinism():
+    w1 = datagen.balanced(n=2048, k_test=256, p=4)
+    w2 = datagen.balanced(n=2048, k_test=256, p=4)
+    np.testing.assert_array_equal(w1.X, w2.X)
+    assert w1.X.dtype == np.float32 and w1.X.shape == (2048, 90)
+    assert w1.Xv.shape == (205, 90)
+    c = datagen.zipf_clipped_counts(131072, 32)
+    assert c.sum() == 131072 and c.min() >= 512 and c.max() <= 14000
+    w = datagen.plain_krr()
+    assert w.X.shape == (2048, 16) and w.X.dtype == np.float64
