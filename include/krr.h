@@ -1,0 +1,201 @@
+/*
+ * krr.h -- C ABI of a batched, partitioned kernel ridge regression library
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * Method: You, Demmel, Hsieh, Vuduc, "Accurate, Fast and Scalable Kernel
+ * Ridge Regression on Parallel and Distributed Systems" (ICS'18).  The
+ * training set is split into p partitions (K-means: Section 2.4, Algorithm 2;
+ * K-balance: Section 4.3, Algorithm 4); every partition gets its own kernel
+ * ridge regression model (Section 2.3, Eq. 6, Algorithm 1); a test point is
+ * predicted by the model of its nearest partition centre (KKRR2, Section 4.2;
+ * BKRR2, Algorithm 5) or by the average of all models (KKRR, Section 4.1);
+ * the best (sigma, lambda) is the one with the lowest MSE (Eq. 3,
+ * Algorithm 5).  On one GPU the p partition models of every (sigma, lambda)
+ * setting are solved as one ragged batch.
+ *
+ * Conventions shared by every call:
+ *   - Every call returns krr_status: 0 on success, a negative code on error.
+ *     No C++ exception crosses this interface.  krr_last_error() returns a
+ *     human-readable message for the last failing call on a context.
+ *   - Array arguments marked "device" are device pointers on the context's
+ *     GPU, owned by the caller, row-major, and must stay valid until the work
+ *     queued on `stream` has finished.  Arguments marked "host" are host
+ *     pointers.  Outputs are allocated by the caller with the stated sizes.
+ *   - Work is queued on `stream` (NULL = the default stream).  Calls that
+ *     return host outputs synchronise `stream` before returning; the others
+ *     are asynchronous unless stated.
+ *   - Argument errors (sizes < 1, p outside [1, n], sigma <= 0, a lambda that
+ *     is not finite, null pointers, unknown enum values) return KRR_EINVAL
+ *     before any work is queued.
+ *   - One host thread may use a context at a time.  Calls from several
+ *     threads on different contexts are independent.
+ */
+#ifndef KRR_H_
+#define KRR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct krr_ctx_s*   krr_ctx;    /* device, workspace pool, options, last error */
+typedef struct krr_model_s* krr_model;  /* one fitted (sigma, lambda) over all partitions */
+
+typedef enum {
+  KRR_OK = 0,
+  KRR_EINVAL = -1,    /* bad argument */
+  KRR_ENOMEM = -2,    /* device allocation failed */
+  KRR_EBUDGET = -3,   /* the call would exceed the context's HBM budget */
+  KRR_ENOTSPD = -4,   /* K + lambda I not positive definite in the working precision */
+  KRR_ENOCONV = -5,   /* iterative refinement did not reach refine_tol */
+  KRR_EDEVICE = -6,   /* a HIP runtime call failed */
+  KRR_ESTATE = -7     /* object used in a state that does not allow the call */
+} krr_status;
+
+typedef enum { KRR_F32 = 0, KRR_F64 = 1 } krr_dtype;
+
+/* Partitioning methods.  KMEANS: k-means++ seeding + Lloyd (Algorithm 2);
+ * KBALANCE: K-means followed by the capacity-ceil(n/p) greedy pass and the
+ * centre recompute (Algorithm 4); GIVEN: assign to caller-supplied centres
+ * (the assignment step of Algorithm 2). */
+typedef enum { KRR_PART_KMEANS = 0, KRR_PART_KBALANCE = 1, KRR_PART_GIVEN = 2 } krr_part;
+
+/* Working precision of a fit.
+ * FP64:  kernel matrix, Cholesky and solves in FP64.
+ * FP32:  kernel matrix stored and factored in FP32 (FP32 matrix cores),
+ *        diagonal blocks factored in FP64; no refinement.
+ * MIXED: FP32 storage, BF16 matrix-core trailing updates with FP32
+ *        accumulation, FP64 diagonal blocks, then iterative refinement with an
+ *        FP64 residual r = y - (K + lambda I) alpha until ||r|| / ||y|| <=
+ *        refine_tol. */
+typedef enum { KRR_PREC_FP64 = 0, KRR_PREC_FP32 = 1, KRR_PREC_MIXED = 2 } krr_prec;
+
+/* Prediction routes.  NEAREST: model of the nearest centre (KKRR2 / BKRR2,
+ * Section 4.2, Algorithm 5).  AVERAGE: mean of all p models (KKRR / DC-KRR,
+ * Section 4.1, Algorithm 3).  ALL: the k x p matrix of every model's
+ * prediction (input of the label-based choice of BKRR3, Algorithm 6). */
+typedef enum { KRR_ROUTE_NEAREST = 0, KRR_ROUTE_AVERAGE = 1, KRR_ROUTE_ALL = 2 } krr_route;
+
+/* Table 1: Gaussian exp(-||a-b||^2 / (2 sigma^2)); linear a^T b. */
+typedef enum { KRR_KERNEL_GAUSSIAN = 0, KRR_KERNEL_LINEAR = 1 } krr_kernel;
+
+typedef struct {
+  double  sigma;          /* Gaussian width (> 0; ignored by the linear kernel) */
+  double  lambda;         /* diagonal shift (finite; see lambda_times_m).  A negative
+                             shift can make the system indefinite, which is reported
+                             as KRR_ENOTSPD with the failing pivot */
+  int32_t kernel;         /* krr_kernel */
+  int32_t prec;           /* krr_prec */
+  double  refine_tol;     /* MIXED: stop when ||r||/||y|| <= refine_tol (e.g. 1e-6) */
+  int32_t max_refine;     /* MIXED: at most this many refinement steps (0 = none) */
+  int32_t lambda_times_m; /* 1: shift is lambda * m_j per partition (Algorithms 3, 5, 6);
+                             0: shift is lambda (Eq. 6 with the 1/n folded in) */
+} krr_fit_params;
+
+typedef struct {
+  int32_t partition;      /* partition index j */
+  int32_t param;          /* index into the params array */
+  int32_t m;              /* partition size */
+  int32_t status;         /* KRR_OK, KRR_ENOTSPD or KRR_ENOCONV */
+  int32_t failed_pivot;   /* 1-based column of the first non-positive pivot, 0 if none */
+  int32_t refine_iters;   /* refinement steps taken (MIXED) */
+  double  rel_residual;   /* ||y - (K + lambda I) alpha|| / ||y|| in FP64 (MIXED; -1 otherwise) */
+} krr_part_info;
+
+/* Tunables (krr_set_option).  Values apply to later calls on the context. */
+typedef enum {
+  KRR_OPT_PANEL_TILES = 0,  /* Cholesky panel width in 64-wide tiles (1..16, default 4) */
+  KRR_OPT_SERIAL_FIT = 1,   /* 1: factor the systems one after another, one launch
+                               sequence per (partition, setting) -- the plain per-partition
+                               baseline; 0 (default): one batched launch sequence */
+  KRR_OPT_SYNC_CHECK = 2    /* 1: synchronise after every launch and report faults (debug) */
+} krr_option;
+
+/* ---- context ------------------------------------------------------------
+ * krr_create: bind a context to `device` (HIP ordinal).  hbm_budget_bytes
+ * caps the device memory the context's workspace and models may hold
+ * (0 = no cap); calls that would exceed it return KRR_EBUDGET before
+ * allocating.  *out receives the handle.
+ * krr_destroy: frees the workspace; models created on the context must be
+ * freed first (KRR_ESTATE otherwise).  krr_last_error: message of the last
+ * failing call ("" if none); the string lives until the next call. */
+krr_status  krr_create(int device, size_t hbm_budget_bytes, krr_ctx* out);
+krr_status  krr_destroy(krr_ctx ctx);
+const char* krr_last_error(krr_ctx ctx);
+krr_status  krr_set_option(krr_ctx ctx, int32_t option, int64_t value);
+/* Bytes of device memory currently held by the context (workspace + models). */
+krr_status  krr_memory_in_use(krr_ctx ctx, size_t* bytes);
+
+/* ---- partition (Section 2.4 Algorithm 2; Section 4.3 Algorithm 4) --------
+ * X:         device, n x d row-major, dtype `dtype` (FP32 values are widened
+ *            exactly to FP64 for every distance).
+ * p:         number of partitions (1 <= p <= n, p <= 1024).
+ * method:    krr_part.  lloyd_iters: maximum Lloyd passes (KMEANS, KBALANCE);
+ *            a pass with no changed assignment ends the loop early.
+ * seed:      SplitMix64 seed of the k-means++ draws.
+ * centroids: device, p x d FP64; input for GIVEN, output otherwise.
+ * assign:    device, n int32 output: partition of each point.  For KMEANS and
+ *            GIVEN the nearest centre (squared FP64 distance, summed in feature
+ *            order without fused multiply-add, lowest index on ties); for
+ *            KBALANCE the greedy capacity-constrained choice.
+ * sizes:     device, p int64 output: points per partition.
+ * Asynchronous. */
+krr_status krr_partition(krr_ctx ctx, hipStream_t stream,
+                         const void* X, int32_t dtype, int64_t n, int32_t d,
+                         int32_t p, int32_t method, int32_t lloyd_iters, uint64_t seed,
+                         double* centroids, int32_t* assign, int64_t* sizes);
+
+/* ---- fit (Section 2.3 Eq. 6, Algorithm 1 per partition; Algorithm 5) -----
+ * X, y:      device, n x d and n, both of dtype `dtype`.
+ * assign:    device, n int32 in [0, p): partition of each point.
+ * centroids: device, p x d FP64 (kept in the models for routing).
+ * params:    host, n_params settings, all fitted in one batch of
+ *            n_params * p systems (K_j + lambda I) alpha_j = y_j.
+ * models_out: host array of n_params handles (one model per setting).
+ * info_out:  host array of n_params * p records, index param * p + j.
+ * Synchronises `stream`.  Returns KRR_ENOTSPD / KRR_ENOCONV if any system
+ * failed (its info record says which; the other systems' results stay
+ * valid and every model is still created), KRR_EBUDGET if the factor
+ * storage would exceed the budget.  Models copy what they need from X, y, so
+ * the caller may free them once the call returns. */
+krr_status krr_fit(krr_ctx ctx, hipStream_t stream,
+                   const void* X, const void* y, int32_t dtype, int64_t n, int32_t d,
+                   const int32_t* assign, const double* centroids, int32_t p,
+                   const krr_fit_params* params, int32_t n_params,
+                   krr_model* models_out, krr_part_info* info_out);
+
+/* ---- predict (Eq. 7; Sections 4.1, 4.2; Algorithm 5) ---------------------
+ * Xt:        device, k x d of dtype `dtype`.
+ * yhat:      device FP64 output: k values (NEAREST, AVERAGE) or k x p
+ *            row-major (ALL).
+ * route_out: device k int32 output (nearest centre), may be NULL.
+ * Asynchronous.  Predictions are evaluated in FP64 for every precision. */
+krr_status krr_predict(krr_ctx ctx, hipStream_t stream, krr_model model,
+                       const void* Xt, int32_t dtype, int64_t k, int32_t route,
+                       double* yhat, int32_t* route_out);
+
+/* ---- select (Eq. 3; Algorithm 5 model choice) ----------------------------
+ * Predicts the k validation points Xv with every model, mse_out[i] =
+ * mean((yhat_i - yv)^2) (host, n_models), *best_out = index of the lowest MSE
+ * (strict "<": the first model wins ties; host).  Synchronises `stream`. */
+krr_status krr_select(krr_ctx ctx, hipStream_t stream,
+                      const krr_model* models, int32_t n_models,
+                      const void* Xv, const void* yv, int32_t dtype, int64_t k, int32_t route,
+                      double* mse_out, int32_t* best_out);
+
+/* ---- models ---------------------------------------------------------------
+ * krr_model_alpha: copy alpha of partition j (m_j FP64 values, in the order
+ * of increasing original point index within the partition) to device memory
+ * `alpha` (asynchronous on `stream`); *m receives m_j (host).
+ * krr_model_free: release a model (NULL is accepted). */
+krr_status krr_model_alpha(krr_ctx ctx, hipStream_t stream, krr_model model, int32_t j,
+                           double* alpha, int64_t* m);
+krr_status krr_model_free(krr_model model);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KRR_H_ */

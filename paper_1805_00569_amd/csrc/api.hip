@@ -1,0 +1,286 @@
+// C ABI entry points (declared in include/krr.h): argument validation, the
+// context's workspace pool and budget accounting, and error translation.  No
+// C++ exception crosses the ABI.
+#include "common.hpp"
+
+#include <cstring>
+
+namespace krr {
+
+static void charge(krr_ctx ctx, size_t add) {
+  if (ctx->budget != 0 && ctx->ws_bytes + ctx->model_bytes + add > ctx->budget)
+    fail(KRR_EBUDGET, "HBM budget exceeded: holding " + std::to_string(ctx->ws_bytes + ctx->model_bytes) +
+                          " bytes, need " + std::to_string(add) + " more, budget " + std::to_string(ctx->budget));
+}
+
+void* ws_get(krr_ctx ctx, const std::string& name, size_t bytes) {
+  bytes = (bytes + 255) & ~size_t(255);
+  if (bytes == 0) bytes = 256;
+  DevBuf& b = ctx->ws[name];
+  if (b.bytes >= bytes) return b.ptr;
+  const size_t old = b.bytes;
+  charge(ctx, bytes - old);
+  if (b.ptr != nullptr) {
+    KRR_HIP(hipDeviceSynchronize());  // the old buffer may still be in use
+    KRR_HIP(hipFree(b.ptr));
+    b.ptr = nullptr;
+    b.bytes = 0;
+    ctx->ws_bytes -= old;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    fail(KRR_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed (" + name + ")");
+  }
+  b.ptr = p;
+  b.bytes = bytes;
+  ctx->ws_bytes += bytes;
+  return p;
+}
+
+void* model_alloc(krr_ctx ctx, size_t bytes) {
+  bytes = (bytes + 255) & ~size_t(255);
+  if (bytes == 0) bytes = 256;
+  charge(ctx, bytes);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    fail(KRR_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed (model)");
+  }
+  ctx->model_bytes += bytes;
+  return p;
+}
+
+void model_release(krr_ctx ctx, void* p, size_t bytes) {
+  if (p == nullptr) return;
+  bytes = (bytes + 255) & ~size_t(255);
+  if (bytes == 0) bytes = 256;
+  (void)hipFree(p);
+  ctx->model_bytes -= std::min(ctx->model_bytes, bytes);
+}
+
+void* pinned_get(krr_ctx ctx, size_t bytes) {
+  if (ctx->pinned_bytes >= bytes) return ctx->pinned;
+  if (ctx->pinned != nullptr) {
+    KRR_HIP(hipDeviceSynchronize());
+    (void)hipHostFree(ctx->pinned);
+    ctx->pinned = nullptr;
+    ctx->pinned_bytes = 0;
+  }
+  bytes = std::max(bytes, size_t(1) << 16);
+  KRR_HIP(hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault));
+  ctx->pinned_bytes = bytes;
+  return ctx->pinned;
+}
+
+void check_launch(krr_ctx ctx, hipStream_t s, const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) fail(KRR_EDEVICE, std::string("launch of ") + what + ": " + hipGetErrorString(e));
+  if (ctx->sync_check) {
+    const hipError_t e2 = hipStreamSynchronize(s);
+    if (e2 != hipSuccess) fail(KRR_EDEVICE, std::string("after ") + what + ": " + hipGetErrorString(e2));
+  }
+}
+
+struct DeviceGuard {
+  int old = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&old) != hipSuccess) old = -1;
+    KRR_HIP(hipSetDevice(dev));
+  }
+  ~DeviceGuard() {
+    if (old >= 0) (void)hipSetDevice(old);
+  }
+};
+
+template <typename F>
+static krr_status guarded(krr_ctx ctx, F&& f) {
+  if (ctx == nullptr) return KRR_EINVAL;
+  try {
+    DeviceGuard g(ctx->device);
+    f();
+    ctx->last_error.clear();
+    return KRR_OK;
+  } catch (const Error& e) {
+    ctx->last_error = e.msg;
+    return e.status;
+  } catch (const std::exception& e) {
+    ctx->last_error = e.what();
+    return KRR_EDEVICE;
+  } catch (...) {
+    ctx->last_error = "unknown error";
+    return KRR_EDEVICE;
+  }
+}
+
+}  // namespace krr
+
+krr_part_data::~krr_part_data() {
+  if (ctx != nullptr) {
+    krr::model_release(ctx, base, bytes);
+    ctx->n_datas -= 1;
+  }
+}
+
+using namespace krr;
+
+extern "C" {
+
+krr_status krr_create(int device, size_t hbm_budget_bytes, krr_ctx* out) {
+  if (out == nullptr) return KRR_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return KRR_EINVAL;
+  krr_ctx c = new (std::nothrow) krr_ctx_s();
+  if (c == nullptr) return KRR_ENOMEM;
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  *out = c;
+  return KRR_OK;
+}
+
+krr_status krr_destroy(krr_ctx ctx) {
+  if (ctx == nullptr) return KRR_EINVAL;
+  if (ctx->n_models > 0 || ctx->n_datas > 0) {
+    ctx->last_error = "models still alive on this context";
+    return KRR_ESTATE;
+  }
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : ctx->ws)
+    if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+  return KRR_OK;
+}
+
+const char* krr_last_error(krr_ctx ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+krr_status krr_set_option(krr_ctx ctx, int32_t option, int64_t value) {
+  return guarded(ctx, [&] {
+    switch (option) {
+      case KRR_OPT_PANEL_TILES:
+        KRR_REQUIRE(value >= 1 && value <= 16, "panel width must be 1..16 tiles");
+        ctx->panel_tiles = (int)value;
+        break;
+      case KRR_OPT_SERIAL_FIT:
+        ctx->serial_fit = value ? 1 : 0;
+        break;
+      case KRR_OPT_SYNC_CHECK:
+        ctx->sync_check = value ? 1 : 0;
+        break;
+      default:
+        fail(KRR_EINVAL, "unknown option");
+    }
+  });
+}
+
+krr_status krr_memory_in_use(krr_ctx ctx, size_t* bytes) {
+  if (ctx == nullptr || bytes == nullptr) return KRR_EINVAL;
+  *bytes = ctx->ws_bytes + ctx->model_bytes;
+  return KRR_OK;
+}
+
+krr_status krr_partition(krr_ctx ctx, hipStream_t stream, const void* X, int32_t dtype, int64_t n, int32_t d,
+                         int32_t p, int32_t method, int32_t lloyd_iters, uint64_t seed, double* centroids,
+                         int32_t* assign, int64_t* sizes) {
+  return guarded(ctx, [&] {
+    KRR_REQUIRE(X && centroids && assign && sizes, "null pointer argument");
+    KRR_REQUIRE(dtype == KRR_F32 || dtype == KRR_F64, "dtype must be KRR_F32 or KRR_F64");
+    KRR_REQUIRE(n >= 1 && d >= 1, "n and d must be >= 1");
+    KRR_REQUIRE(n < (int64_t(1) << 31) - 1, "n must fit in int32");
+    KRR_REQUIRE(p >= 1 && p <= n && p <= 1024, "p must be in [1, min(n, 1024)]");
+    KRR_REQUIRE(method == KRR_PART_KMEANS || method == KRR_PART_KBALANCE || method == KRR_PART_GIVEN,
+                "unknown partition method");
+    KRR_REQUIRE(lloyd_iters >= 0 && lloyd_iters <= 100000, "lloyd_iters out of range");
+    run_partition(ctx, stream, X, dtype, n, d, p, method, lloyd_iters, seed, centroids, assign, sizes);
+  });
+}
+
+krr_status krr_fit(krr_ctx ctx, hipStream_t stream, const void* X, const void* y, int32_t dtype, int64_t n,
+                   int32_t d, const int32_t* assign, const double* centroids, int32_t p,
+                   const krr_fit_params* params, int32_t n_params, krr_model* models_out,
+                   krr_part_info* info_out) {
+  krr_status st = KRR_OK;
+  krr_status g = guarded(ctx, [&] {
+    KRR_REQUIRE(X && y && assign && centroids && params && models_out && info_out, "null pointer argument");
+    KRR_REQUIRE(dtype == KRR_F32 || dtype == KRR_F64, "dtype must be KRR_F32 or KRR_F64");
+    KRR_REQUIRE(n >= 1 && d >= 1 && n < (int64_t(1) << 31) - 1, "bad n or d");
+    KRR_REQUIRE(p >= 1 && p <= n && p <= 1024, "p must be in [1, min(n, 1024)]");
+    KRR_REQUIRE(n_params >= 1 && n_params <= 4096, "n_params must be in [1, 4096]");
+    for (int q = 0; q < n_params; ++q) {
+      const krr_fit_params& P = params[q];
+      KRR_REQUIRE(P.kernel == KRR_KERNEL_GAUSSIAN || P.kernel == KRR_KERNEL_LINEAR, "unknown kernel");
+      KRR_REQUIRE(P.kernel != KRR_KERNEL_GAUSSIAN || P.sigma > 0.0, "sigma must be > 0");
+      KRR_REQUIRE(std::isfinite(P.lambda), "lambda must be finite");
+      KRR_REQUIRE(P.prec == KRR_PREC_FP64 || P.prec == KRR_PREC_FP32 || P.prec == KRR_PREC_MIXED,
+                  "unknown precision");
+      KRR_REQUIRE(P.prec == params[0].prec, "all settings of one call must share the precision");
+      KRR_REQUIRE(P.max_refine >= 0 && P.max_refine <= 1000, "max_refine out of range");
+    }
+    for (int q = 0; q < n_params; ++q) models_out[q] = nullptr;
+    run_fit(ctx, stream, X, y, dtype, n, d, assign, centroids, p, params, n_params, models_out, info_out);
+    for (int q = 0; q < n_params * p; ++q) {
+      if (info_out[q].status == KRR_ENOTSPD) st = KRR_ENOTSPD;
+      else if (info_out[q].status == KRR_ENOCONV && st == KRR_OK) st = KRR_ENOCONV;
+    }
+  });
+  if (g != KRR_OK) return g;
+  if (st != KRR_OK) ctx->last_error = "one or more systems failed; see info_out";
+  return st;
+}
+
+krr_status krr_predict(krr_ctx ctx, hipStream_t stream, krr_model model, const void* Xt, int32_t dtype, int64_t k,
+                       int32_t route, double* yhat, int32_t* route_out) {
+  return guarded(ctx, [&] {
+    KRR_REQUIRE(model && Xt && yhat, "null pointer argument");
+    KRR_REQUIRE(model->ctx == ctx, "model belongs to another context");
+    KRR_REQUIRE(dtype == KRR_F32 || dtype == KRR_F64, "dtype must be KRR_F32 or KRR_F64");
+    KRR_REQUIRE(k >= 1 && k < (int64_t(1) << 31) - 1, "k must be >= 1");
+    KRR_REQUIRE(route == KRR_ROUTE_NEAREST || route == KRR_ROUTE_AVERAGE || route == KRR_ROUTE_ALL,
+                "unknown route");
+    run_predict(ctx, stream, model, Xt, dtype, k, route, yhat, route_out);
+  });
+}
+
+krr_status krr_select(krr_ctx ctx, hipStream_t stream, const krr_model* models, int32_t n_models, const void* Xv,
+                      const void* yv, int32_t dtype, int64_t k, int32_t route, double* mse_out,
+                      int32_t* best_out) {
+  return guarded(ctx, [&] {
+    KRR_REQUIRE(models && Xv && yv && mse_out && best_out, "null pointer argument");
+    KRR_REQUIRE(n_models >= 1, "n_models must be >= 1");
+    for (int i = 0; i < n_models; ++i) KRR_REQUIRE(models[i] && models[i]->ctx == ctx, "bad model handle");
+    KRR_REQUIRE(dtype == KRR_F32 || dtype == KRR_F64, "dtype must be KRR_F32 or KRR_F64");
+    KRR_REQUIRE(k >= 1 && k < (int64_t(1) << 31) - 1, "k must be >= 1");
+    KRR_REQUIRE(route == KRR_ROUTE_NEAREST || route == KRR_ROUTE_AVERAGE, "route must be NEAREST or AVERAGE");
+    run_select(ctx, stream, models, n_models, Xv, yv, dtype, k, route, mse_out, best_out);
+  });
+}
+
+krr_status krr_model_alpha(krr_ctx ctx, hipStream_t stream, krr_model model, int32_t j, double* alpha,
+                           int64_t* m) {
+  return guarded(ctx, [&] {
+    KRR_REQUIRE(model && alpha && m, "null pointer argument");
+    KRR_REQUIRE(model->ctx == ctx, "model belongs to another context");
+    KRR_REQUIRE(j >= 0 && j < model->data->p, "partition index out of range");
+    const int64_t mj = model->data->offsets[j + 1] - model->data->offsets[j];
+    *m = mj;
+    if (mj > 0)
+      KRR_HIP(hipMemcpyAsync(alpha, model->alpha + model->voff[j], (size_t)mj * 8, hipMemcpyDeviceToDevice,
+                             stream));
+  });
+}
+
+krr_status krr_model_free(krr_model model) {
+  if (model == nullptr) return KRR_OK;
+  krr_ctx ctx = model->ctx;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  model_release(ctx, model->alpha, model->bytes);
+  model->data.reset();
+  ctx->n_models -= 1;
+  delete model;
+  return KRR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,158 @@
+// Shared host/device definitions of the KRR library (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/krr.h"
+
+namespace krr {
+
+// Square tile edge of every blocked matrix in the library.  A system of size m
+// holds T = ceil(m / NB) tile rows; its lower triangle is stored as T(T+1)/2
+// contiguous NB x NB tiles, tile (i, j) (i >= j) at index i(i+1)/2 + j, each
+// tile column-major (element (r, c) at c * NB + r).
+constexpr int NB = 64;
+
+struct Error {
+  krr_status status;
+  std::string msg;
+};
+
+[[noreturn]] inline void fail(krr_status s, const std::string& m) { throw Error{s, m}; }
+
+#define KRR_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      ::krr::fail(KRR_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+#define KRR_REQUIRE(cond, msg)                       \
+  do {                                                \
+    if (!(cond)) ::krr::fail(KRR_EINVAL, (msg));      \
+  } while (0)
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t tri(int64_t t) { return t * (t + 1) / 2; }
+
+// A grow-only device allocation.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+// Per-system descriptor of one batched solve (K_s + lambda_s I) alpha_s = y_s.
+struct SysDesc {
+  int32_t m;        // number of points in the partition
+  int32_t T;        // tile rows, ceil(m / NB)
+  int32_t part;     // partition index
+  int32_t param;    // setting index
+  int64_t a_off;    // element offset of the system's packed lower tiles
+  int64_t w_off;    // element offset of its T inverse diagonal tiles
+  int64_t v_off;    // offset of its padded vectors (T * NB entries)
+  int64_t x_off;    // first row of the partition in the grouped inputs
+  double neg_inv_2s2;  // -1 / (2 sigma^2)
+  double lambda;       // diagonal shift actually used
+  int32_t kernel;      // krr_kernel
+  int32_t pad_;
+};
+
+// Device-side status of one system.
+struct SysStatus {
+  int32_t status;        // KRR_OK or KRR_ENOTSPD
+  int32_t failed_pivot;  // 1-based, 0 = none
+  int32_t refine_iters;
+  int32_t converged;     // refinement reached the tolerance
+  double rel_residual;
+  double ynorm;
+};
+
+}  // namespace krr
+
+// Partitioned training data shared by the models of one krr_fit call.
+struct krr_part_data {
+  krr_ctx ctx = nullptr;
+  void* base = nullptr;         // one allocation holding the arrays below
+  int32_t p = 0, d = 0, dtype = 0;
+  int64_t n = 0;
+  void* X = nullptr;          // n x d grouped by partition, input dtype
+  double* centroids = nullptr;  // p x d
+  double* ct_t = nullptr;       // d x p (transposed, for routing)
+  std::vector<int64_t> offsets; // p + 1, host copy
+  int64_t* d_offsets = nullptr; // p + 1, device
+  size_t bytes = 0;
+  ~krr_part_data();
+};
+
+struct krr_model_s {
+  krr_ctx ctx = nullptr;
+  std::shared_ptr<krr_part_data> data;
+  krr_fit_params params{};
+  double* alpha = nullptr;      // sum_j T_j * NB padded FP64 coefficients (allocation base)
+  int64_t* d_voff = nullptr;    // p + 1 padded offsets into alpha (device)
+  std::vector<int64_t> voff;    // host copy
+  std::vector<double> lambda_eff;
+  size_t bytes = 0;
+};
+
+struct krr_ctx_s {
+  int device = 0;
+  size_t budget = 0;
+  std::string last_error;
+  std::map<std::string, krr::DevBuf> ws;
+  size_t ws_bytes = 0;
+  size_t model_bytes = 0;
+  int n_models = 0;
+  int n_datas = 0;
+  int panel_tiles = 4;
+  int serial_fit = 0;
+  int sync_check = 0;
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+};
+
+namespace krr {
+
+// Workspace buffer `name` of at least `bytes`, grown (never shrunk) inside the
+// context's budget.  Contents are not preserved across growth.
+void* ws_get(krr_ctx ctx, const std::string& name, size_t bytes);
+// Device allocation charged to the context's model memory.
+void* model_alloc(krr_ctx ctx, size_t bytes);
+void model_release(krr_ctx ctx, void* p, size_t bytes);
+void* pinned_get(krr_ctx ctx, size_t bytes);
+void check_launch(krr_ctx ctx, hipStream_t s, const char* what);
+
+// ---- partition.hip ----
+void assign_nearest(krr_ctx ctx, hipStream_t s, const void* X, int dtype, int64_t n, int d,
+                    const double* C, int p, int32_t* out, const int32_t* prev, int32_t* delta,
+                    const int32_t* skip);
+void group_by_key(krr_ctx ctx, hipStream_t s, const int32_t* key, int64_t n, int p,
+                  int32_t* perm, int64_t* offsets, int64_t* sizes64, const int32_t* skip);
+void gather_rows(krr_ctx ctx, hipStream_t s, const void* X, int dtype, int64_t n, int d,
+                 const int32_t* perm, void* Xout);
+void gather_vec_f64(krr_ctx ctx, hipStream_t s, const void* y, int dtype, int64_t n,
+                    const int32_t* perm, double* yout);
+void transpose_centroids(krr_ctx ctx, hipStream_t s, const double* C, int p, int d, double* CT);
+void run_partition(krr_ctx ctx, hipStream_t s, const void* X, int dtype, int64_t n, int d, int p,
+                   int method, int iters, uint64_t seed, double* C, int32_t* assign,
+                   int64_t* sizes);
+
+// ---- fit.hip ----
+void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype, int64_t n, int d,
+             const int32_t* assign, const double* centroids, int p, const krr_fit_params* params,
+             int n_params, krr_model* models, krr_part_info* info);
+
+// ---- predict.hip ----
+void run_predict(krr_ctx ctx, hipStream_t s, krr_model model, const void* Xt, int dtype, int64_t k,
+                 int route, double* yhat, int32_t* route_out);
+void run_select(krr_ctx ctx, hipStream_t s, const krr_model* models, int n_models, const void* Xv,
+                const void* yv, int dtype, int64_t k, int route, double* mse, int32_t* best);
+
+}  // namespace krr

@@ -1,0 +1,689 @@
+// Partitioning kernels: exact nearest-centre assignment, stable grouping by
+// partition, k-means++ seeding, Lloyd mean updates (Section 2.4, Algorithm 2)
+// and the K-balance capacity-constrained greedy pass (Section 4.3,
+// Algorithm 4).
+//
+// Every distance here is the FP64 squared Euclidean distance accumulated
+// sequentially over the feature index with separately rounded subtract,
+// multiply and add (explicit _rn intrinsics: no contraction into fused
+// multiply-add), so assignments are reproducible bit for bit.  Comparisons use
+// the squared value; the strict "<" over ascending centre index sends ties to
+// the lowest index, as in Algorithm 4.
+#include "common.hpp"
+
+#include <cmath>
+
+namespace krr {
+
+namespace {
+
+constexpr int GROUP_BLOCK = 256;
+constexpr int KPP_BLOCK = 256;   // k-means++ cumulative-weight block
+constexpr int CCHUNK = 16;       // centres per register chunk in assignment
+
+__device__ __forceinline__ double sqdiff_acc(double acc, double a, double b) {
+#pragma clang fp contract(off)
+  const double t = __dsub_rn(a, b);
+  return __dadd_rn(acc, __dmul_rn(t, t));
+}
+
+template <typename TX>
+__device__ __forceinline__ double dist2_rows(const TX* __restrict__ a, const TX* __restrict__ b, int d) {
+  double acc = 0.0;
+  for (int k = 0; k < d; ++k) acc = sqdiff_acc(acc, (double)a[k], (double)b[k]);
+  return acc;
+}
+
+__device__ __forceinline__ int first_active_lane() {
+  return __ffsll((unsigned long long)__ballot(1)) - 1;
+}
+
+// ---------------------------------------------------------------------------
+// Assignment of rows of X to the nearest of p centres (CT is d x p, i.e. the
+// centres transposed, so that the p values of one feature are contiguous).
+// MODE 0: argmin index (+ change count against `prev`); MODE 1: all p squared
+// distances into D (n x p).  Rows are staged in LDS feature-major.
+// ---------------------------------------------------------------------------
+template <typename TX, int MODE>
+__global__ __launch_bounds__(256) void k_assign(const TX* __restrict__ X, int64_t n, int d,
+                                                const double* __restrict__ CT, int p,
+                                                int32_t* __restrict__ out, double* __restrict__ D,
+                                                const int32_t* __restrict__ prev,
+                                                int32_t* __restrict__ delta,
+                                                const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip) return;
+  extern __shared__ unsigned char smem_raw[];
+  TX* sX = reinterpret_cast<TX*>(smem_raw);
+  const int R = blockDim.x;
+  const int ld = R + 1;
+  const int64_t row0 = (int64_t)blockIdx.x * R;
+  const int rows = (int)min((int64_t)R, n - row0);
+  const TX* src = X + row0 * d;
+  const int tot = rows * d;
+  for (int e = threadIdx.x; e < tot; e += R) {
+    const int r = e / d;
+    const int k = e - r * d;
+    sX[k * ld + r] = src[e];
+  }
+  __syncthreads();
+  const int r = threadIdx.x;
+  if (r >= rows) return;
+  const int64_t i = row0 + r;
+  double best = INFINITY;
+  int bj = -1;
+  for (int j0 = 0; j0 < p; j0 += CCHUNK) {
+    const int nj = min(CCHUNK, p - j0);
+    double acc[CCHUNK];
+#pragma unroll
+    for (int q = 0; q < CCHUNK; ++q) acc[q] = 0.0;
+    if (nj == CCHUNK) {
+      for (int k = 0; k < d; ++k) {
+        const double xk = (double)sX[k * ld + r];
+        const double* c = CT + (int64_t)k * p + j0;
+#pragma unroll
+        for (int q = 0; q < CCHUNK; ++q) acc[q] = sqdiff_acc(acc[q], xk, c[q]);
+      }
+    } else {
+      for (int k = 0; k < d; ++k) {
+        const double xk = (double)sX[k * ld + r];
+        const double* c = CT + (int64_t)k * p + j0;
+#pragma unroll
+        for (int q = 0; q < CCHUNK; ++q)
+          if (q < nj) acc[q] = sqdiff_acc(acc[q], xk, c[q]);
+      }
+    }
+    if (MODE == 1) {
+      for (int q = 0; q < nj; ++q) D[i * p + j0 + q] = acc[q];
+    } else {
+      for (int q = 0; q < nj; ++q)
+        if (acc[q] < best) {
+          best = acc[q];
+          bj = j0 + q;
+        }
+    }
+  }
+  if (MODE == 0) {
+    if (bj < 0) bj = 0;  // every distance +inf: first centre, as argmin does
+    out[i] = bj;
+    if (delta != nullptr) {
+      const bool changed = (prev == nullptr) || (prev[i] != bj);
+      const unsigned long long b = __ballot(changed);
+      if ((int)(threadIdx.x & 63) == first_active_lane()) atomicAdd(delta, (int32_t)__popcll(b));
+    }
+  }
+}
+
+// Unstaged variant for very wide rows (LDS cannot hold a block of rows).
+template <typename TX, int MODE>
+__global__ __launch_bounds__(256) void k_assign_wide(const TX* __restrict__ X, int64_t n, int d,
+                                                     const double* __restrict__ CT, int p,
+                                                     int32_t* __restrict__ out, double* __restrict__ D,
+                                                     const int32_t* __restrict__ prev,
+                                                     int32_t* __restrict__ delta,
+                                                     const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const TX* x = X + i * d;
+  double best = INFINITY;
+  int bj = -1;
+  for (int j = 0; j < p; ++j) {
+    double acc = 0.0;
+    for (int k = 0; k < d; ++k) acc = sqdiff_acc(acc, (double)x[k], CT[(int64_t)k * p + j]);
+    if (MODE == 1) {
+      D[i * p + j] = acc;
+    } else if (acc < best) {
+      best = acc;
+      bj = j;
+    }
+  }
+  if (MODE == 0) {
+    if (bj < 0) bj = 0;
+    out[i] = bj;
+    if (delta != nullptr) {
+      const bool changed = (prev == nullptr) || (prev[i] != bj);
+      const unsigned long long b = __ballot(changed);
+      if ((int)(threadIdx.x & 63) == first_active_lane()) atomicAdd(delta, (int32_t)__popcll(b));
+    }
+  }
+}
+
+__global__ void k_transpose(const double* __restrict__ C, int p, int d, double* __restrict__ CT) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= p * d) return;
+  const int j = e / d, k = e - j * d;
+  CT[(int64_t)k * p + j] = C[e];
+}
+
+// ---------------------------------------------------------------------------
+// Stable grouping of n keys in [0, p): perm lists the indices of key 0 in
+// increasing order, then key 1, ...; offsets[j] is where key j starts.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(GROUP_BLOCK) void k_group_local(const int32_t* __restrict__ key, int64_t n,
+                                                             int p, int32_t* __restrict__ local_rank,
+                                                             int32_t* __restrict__ blockcounts,
+                                                             const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip) return;
+  __shared__ int32_t sk[GROUP_BLOCK];
+  extern __shared__ int32_t cnt[];
+  for (int j = threadIdx.x; j < p; j += GROUP_BLOCK) cnt[j] = 0;
+  const int64_t i = (int64_t)blockIdx.x * GROUP_BLOCK + threadIdx.x;
+  const int kv = (i < n) ? key[i] : -1;
+  sk[threadIdx.x] = kv;
+  __syncthreads();
+  if (i < n) {
+    int rank = 0;
+    for (int l = 0; l < (int)threadIdx.x; ++l) rank += (sk[l] == kv);
+    local_rank[i] = rank;
+    atomicAdd(&cnt[kv], 1);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < p; j += GROUP_BLOCK)
+    blockcounts[(int64_t)blockIdx.x * p + j] = cnt[j];
+}
+
+__global__ __launch_bounds__(1024) void k_group_scan(const int32_t* __restrict__ blockcounts, int64_t nblocks,
+                                                     int p, int32_t* __restrict__ blockoffs,
+                                                     int64_t* __restrict__ offsets,
+                                                     int64_t* __restrict__ sizes64,
+                                                     const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip) return;
+  extern __shared__ int64_t tot[];
+  for (int j = threadIdx.x; j < p; j += blockDim.x) {
+    int64_t run = 0;
+    int64_t b = 0;
+    for (; b + 8 <= nblocks; b += 8) {
+      int32_t c[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) c[q] = blockcounts[(b + q) * p + j];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        blockoffs[(b + q) * p + j] = (int32_t)run;
+        run += c[q];
+      }
+    }
+    for (; b < nblocks; ++b) {
+      const int32_t c = blockcounts[b * p + j];
+      blockoffs[b * p + j] = (int32_t)run;
+      run += c;
+    }
+    tot[j] = run;
+    if (sizes64 != nullptr) sizes64[j] = run;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t o = 0;
+    for (int j = 0; j < p; ++j) {
+      offsets[j] = o;
+      o += tot[j];
+    }
+    offsets[p] = o;
+  }
+}
+
+__global__ __launch_bounds__(GROUP_BLOCK) void k_group_scatter(const int32_t* __restrict__ key, int64_t n,
+                                                               int p, const int32_t* __restrict__ local_rank,
+                                                               const int32_t* __restrict__ blockoffs,
+                                                               const int64_t* __restrict__ offsets,
+                                                               int32_t* __restrict__ perm,
+                                                               const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip) return;
+  const int64_t i = (int64_t)blockIdx.x * GROUP_BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const int kv = key[i];
+  perm[offsets[kv] + blockoffs[(int64_t)blockIdx.x * p + kv] + local_rank[i]] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// Means of the grouped members: C[j][f] = (sum of member values in increasing
+// point order, FP64) / count_j.  Empty partitions keep their centre.  If
+// `done_out` is given, it is set when the change count `delta` was zero
+// (Lloyd has reached a fixed point; later passes are skipped).
+// ---------------------------------------------------------------------------
+template <typename TX>
+__global__ __launch_bounds__(128) void k_means(const TX* __restrict__ X, int d, const int32_t* __restrict__ perm,
+                                               const int64_t* __restrict__ offsets, double* __restrict__ C,
+                                               const int32_t* __restrict__ skip,
+                                               const int32_t* __restrict__ delta,
+                                               int32_t* __restrict__ done_out) {
+  if (skip != nullptr && *skip) return;
+  const int j = blockIdx.x;
+  const int64_t o0 = offsets[j], o1 = offsets[j + 1];
+  const int64_t cnt = o1 - o0;
+  if (cnt > 0) {
+    for (int f = threadIdx.x; f < d; f += blockDim.x) {
+      double s = 0.0;
+      int64_t o = o0;
+      for (; o + 8 <= o1; o += 8) {
+        int32_t id[8];
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) id[q] = perm[o + q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = (double)X[(int64_t)id[q] * d + f];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s = __dadd_rn(s, v[q]);
+      }
+      for (; o < o1; ++o) s = __dadd_rn(s, (double)X[(int64_t)perm[o] * d + f]);
+      C[(int64_t)j * d + f] = __ddiv_rn(s, (double)cnt);
+    }
+  }
+  if (done_out != nullptr && j == 0 && threadIdx.x == 0 && *delta == 0) *done_out = 1;
+}
+
+// ---------------------------------------------------------------------------
+// k-means++ seeding with the cumulative D^2 weight formed in blocks of 256
+// points: sequential inside a block, block totals summed sequentially, and one
+// add of the block offset.  Centre t is the first point whose cumulative
+// weight exceeds u_t times the total.
+// ---------------------------------------------------------------------------
+template <typename TX>
+__global__ __launch_bounds__(KPP_BLOCK) void k_kpp_update(const TX* __restrict__ X, int64_t n, int d,
+                                                          const int64_t* __restrict__ cidx, int t,
+                                                          double* __restrict__ D2, double* __restrict__ P,
+                                                          double* __restrict__ Tb) {
+  __shared__ double sd[KPP_BLOCK];
+  const int64_t i = (int64_t)blockIdx.x * KPP_BLOCK + threadIdx.x;
+  const int64_t c = cidx[t];
+  double v = 0.0;
+  if (i < n) {
+    const double dd = dist2_rows(X + i * d, X + c * d, d);
+    if (t == 0) {
+      v = dd;
+    } else {
+      const double old = D2[i];
+      v = (dd < old) ? dd : old;
+    }
+    D2[i] = v;
+  }
+  sd[threadIdx.x] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int cnt = (int)min((int64_t)KPP_BLOCK, n - (int64_t)blockIdx.x * KPP_BLOCK);
+    double acc = sd[0];
+    for (int q = 1; q < cnt; ++q) {
+      acc = __dadd_rn(acc, sd[q]);
+      sd[q] = acc;
+    }
+    Tb[blockIdx.x] = acc;
+  }
+  __syncthreads();
+  if (i < n) P[i] = sd[threadIdx.x];
+}
+
+template <typename TX>
+__global__ __launch_bounds__(KPP_BLOCK) void k_kpp_select(const double* __restrict__ P,
+                                                          const double* __restrict__ Tb, int64_t nblk,
+                                                          int64_t n, double u, double* __restrict__ Ob,
+                                                          const TX* __restrict__ X, int d,
+                                                          int64_t* __restrict__ cidx, int t,
+                                                          double* __restrict__ C) {
+  __shared__ double s_thr;
+  __shared__ int64_t s_blk;
+  __shared__ int64_t s_idx[KPP_BLOCK];
+  __shared__ int s_mode;
+  if (threadIdx.x == 0) {
+    double o = 0.0;
+    for (int64_t b = 0; b < nblk; ++b) {
+      Ob[b] = o;
+      o = __dadd_rn(o, Tb[b]);
+    }
+    const double total = o;
+    int64_t blk = -1;
+    int mode = 0;
+    if (!(total > 0.0)) {
+      mode = 1;
+    } else {
+      const double thr = __dmul_rn(u, total);
+      s_thr = thr;
+      for (int64_t b = 0; b < nblk; ++b) {
+        if (__dadd_rn(Ob[b], Tb[b]) > thr) {
+          blk = b;
+          break;
+        }
+      }
+      if (blk < 0) mode = 2;
+    }
+    s_blk = blk;
+    s_mode = mode;
+  }
+  __syncthreads();
+  int64_t idx;
+  if (s_mode == 1) {
+    idx = (int64_t)floor(__dmul_rn(u, (double)n));
+    if (idx > n - 1) idx = n - 1;
+  } else if (s_mode == 2) {
+    idx = 0;  // no cumulative weight above the threshold: the first point
+  } else {
+    const int64_t b = s_blk;
+    const int64_t i = b * KPP_BLOCK + threadIdx.x;
+    int64_t cand = INT64_MAX;
+    if (i < n && __dadd_rn(Ob[b], P[i]) > s_thr) cand = i;
+    s_idx[threadIdx.x] = cand;
+    __syncthreads();
+    for (int w = KPP_BLOCK / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        const int64_t o = s_idx[threadIdx.x + w];
+        if (o < s_idx[threadIdx.x]) s_idx[threadIdx.x] = o;
+      }
+      __syncthreads();
+    }
+    idx = s_idx[0];
+  }
+  if (threadIdx.x == 0) cidx[t] = idx;
+  for (int f = threadIdx.x; f < d; f += KPP_BLOCK) C[(int64_t)t * d + f] = (double)X[idx * d + f];
+}
+
+template <typename TX>
+__global__ void k_kpp_first(int64_t n, double u0, const TX* __restrict__ X, int d,
+                            int64_t* __restrict__ cidx, double* __restrict__ C) {
+  int64_t idx = (int64_t)floor(__dmul_rn(u0, (double)n));
+  if (idx > n - 1) idx = n - 1;
+  if (threadIdx.x == 0) cidx[0] = idx;
+  for (int f = threadIdx.x; f < d; f += blockDim.x) C[f] = (double)X[idx * d + f];
+}
+
+// ---------------------------------------------------------------------------
+// K-balance greedy pass (Algorithm 4), one wavefront.  Points are visited in
+// input order; each takes the nearest centre whose count is below `cap`.
+// Chunks of 64 points are decided in parallel from the set of centres open at
+// the chunk start; when no centre would pass `cap` inside the chunk, that is
+// exactly the sequential result (a point's choice is minimal over a superset
+// that still contains it).  Otherwise the chunk is replayed point by point.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_argmin(double& v, int& j) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(v, off, 64);
+    const int oj = __shfl_xor(j, off, 64);
+    if (ov < v || (ov == v && oj < j)) {
+      v = ov;
+      j = oj;
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void k_kbalance(const double* __restrict__ D, const int32_t* __restrict__ a0,
+                                                 int64_t n, int p, int64_t cap, int32_t* __restrict__ MB) {
+  extern __shared__ int32_t sh[];
+  int32_t* cs = sh;        // p counts
+  int32_t* hist = sh + p;  // p per-chunk counts
+  const int lane = threadIdx.x;
+  for (int j = lane; j < p; j += 64) {
+    cs[j] = 0;
+    hist[j] = 0;
+  }
+  __syncthreads();
+  for (int64_t c0 = 0; c0 < n; c0 += 64) {
+    const int64_t i = c0 + lane;
+    const bool valid = i < n;
+    int bj = -1;
+    if (valid) {
+      bj = a0[i];
+      if (cs[bj] >= cap) {  // nearest centre already full: search the open ones
+        double bd = INFINITY;
+        bj = -1;
+        for (int j = 0; j < p; ++j) {
+          if (cs[j] < cap) {
+            const double v = D[i * p + j];
+            if (v < bd) {
+              bd = v;
+              bj = j;
+            }
+          }
+        }
+        if (bj < 0) bj = 0;
+      }
+      atomicAdd(&hist[bj], 1);
+    }
+    __syncthreads();
+    bool ok = true;
+    for (int j = lane; j < p; j += 64)
+      if ((int64_t)cs[j] + hist[j] > cap) ok = false;
+    ok = __all(ok);
+    __syncthreads();
+    if (ok) {
+      if (valid) MB[i] = bj;
+      for (int j = lane; j < p; j += 64) {
+        cs[j] += hist[j];
+        hist[j] = 0;
+      }
+      __syncthreads();
+    } else {
+      for (int j = lane; j < p; j += 64) hist[j] = 0;
+      __syncthreads();
+      const int cnt = (int)min((int64_t)64, n - c0);
+      for (int l = 0; l < cnt; ++l) {
+        const int64_t ii = c0 + l;
+        double v = INFINITY;
+        int jj = INT32_MAX;
+        for (int j = lane; j < p; j += 64) {
+          if (cs[j] < cap) {
+            const double dv = D[ii * p + j];
+            if (dv < v) {
+              v = dv;
+              jj = j;
+            }
+          }
+        }
+        wave_argmin(v, jj);
+        if (jj == INT32_MAX) jj = 0;
+        if (lane == 0) {
+          MB[ii] = jj;
+          cs[jj] += 1;
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+__global__ void k_cast_rows(const void* __restrict__ X, int dtype, const int32_t* __restrict__ perm,
+                            int64_t n, int d, void* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * d) return;
+  const int64_t r = e / d, k = e - r * d;
+  const int64_t src = (int64_t)perm[r] * d + k;
+  if (dtype == KRR_F64)
+    reinterpret_cast<double*>(out)[e] = reinterpret_cast<const double*>(X)[src];
+  else
+    reinterpret_cast<float*>(out)[e] = reinterpret_cast<const float*>(X)[src];
+}
+
+__global__ void k_gather_vec(const void* __restrict__ y, int dtype, const int32_t* __restrict__ perm,
+                             int64_t n, double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int64_t src = perm[e];
+  out[e] = (dtype == KRR_F64) ? reinterpret_cast<const double*>(y)[src]
+                              : (double)reinterpret_cast<const float*>(y)[src];
+}
+
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): state advances by the golden
+// gamma; the output mixes the state with two xor-shift-multiply rounds.
+struct SplitMix64 {
+  uint64_t state;
+  uint64_t next() {
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  double uniform() { return (double)(next() >> 11) * 0x1.0p-53; }
+};
+
+template <typename TX>
+void assign_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, const double* CT, int p,
+              int32_t* out, double* D, const int32_t* prev, int32_t* delta, const int32_t* skip,
+              bool all) {
+  // Rows per block: as many as fit in about 96 KiB of LDS, at least 64.
+  int R = 256;
+  while (R > 64 && (size_t)d * (R + 1) * sizeof(TX) > 96 * 1024) R /= 2;
+  const size_t lds = (size_t)d * (R + 1) * sizeof(TX);
+  const int64_t nblk = ceil_div(n, R);
+  if (lds <= 96 * 1024) {
+    if (all)
+      hipLaunchKernelGGL((k_assign<TX, 1>), dim3(nblk), dim3(R), lds, s, X, n, d, CT, p, out, D, prev,
+                         delta, skip);
+    else
+      hipLaunchKernelGGL((k_assign<TX, 0>), dim3(nblk), dim3(R), lds, s, X, n, d, CT, p, out, D, prev,
+                         delta, skip);
+  } else {
+    const int64_t nb = ceil_div(n, 256);
+    if (all)
+      hipLaunchKernelGGL((k_assign_wide<TX, 1>), dim3(nb), dim3(256), 0, s, X, n, d, CT, p, out, D, prev,
+                         delta, skip);
+    else
+      hipLaunchKernelGGL((k_assign_wide<TX, 0>), dim3(nb), dim3(256), 0, s, X, n, d, CT, p, out, D, prev,
+                         delta, skip);
+  }
+  check_launch(ctx, s, "assign");
+}
+
+template <typename TX>
+void means_t(krr_ctx ctx, hipStream_t s, const TX* X, int d, const int32_t* perm, const int64_t* offsets,
+             double* C, int p, const int32_t* skip, const int32_t* delta, int32_t* done) {
+  hipLaunchKernelGGL((k_means<TX>), dim3(p), dim3(128), 0, s, X, d, perm, offsets, C, skip, delta, done);
+  check_launch(ctx, s, "means");
+}
+
+template <typename TX>
+void kmeanspp_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, int k, uint64_t seed,
+                double* C) {
+  const int64_t nblk = ceil_div(n, KPP_BLOCK);
+  char* w = (char*)ws_get(ctx, "kpp", (size_t)(3 * n + 2 * nblk + 8) * 8 + (size_t)k * 8);
+  double* D2 = (double*)w;
+  double* P = D2 + n;
+  double* Tb = P + n;
+  double* Ob = Tb + nblk;
+  int64_t* cidx = (int64_t*)(Ob + nblk + 8);
+  SplitMix64 g{seed};
+  std::vector<double> u(k);
+  for (int t = 0; t < k; ++t) u[t] = g.uniform();
+  hipLaunchKernelGGL((k_kpp_first<TX>), dim3(1), dim3(128), 0, s, n, u[0], X, d, cidx, C);
+  check_launch(ctx, s, "kpp_first");
+  for (int t = 1; t < k; ++t) {
+    hipLaunchKernelGGL((k_kpp_update<TX>), dim3(nblk), dim3(KPP_BLOCK), 0, s, X, n, d,
+                       (const int64_t*)cidx, t - 1, D2, P, Tb);
+    check_launch(ctx, s, "kpp_update");
+    hipLaunchKernelGGL((k_kpp_select<TX>), dim3(1), dim3(KPP_BLOCK), 0, s, (const double*)P,
+                       (const double*)Tb, nblk, n, u[t], Ob, X, d, cidx, t, C);
+    check_launch(ctx, s, "kpp_select");
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host entry points used by the other modules
+// ---------------------------------------------------------------------------
+void transpose_centroids(krr_ctx ctx, hipStream_t s, const double* C, int p, int d, double* CT) {
+  const int tot = p * d;
+  hipLaunchKernelGGL(k_transpose, dim3(ceil_div(tot, 256)), dim3(256), 0, s, C, p, d, CT);
+  check_launch(ctx, s, "transpose");
+}
+
+void assign_nearest(krr_ctx ctx, hipStream_t s, const void* X, int dtype, int64_t n, int d,
+                    const double* CT, int p, int32_t* out, const int32_t* prev, int32_t* delta,
+                    const int32_t* skip) {
+  if (dtype == KRR_F64)
+    assign_t(ctx, s, (const double*)X, n, d, CT, p, out, nullptr, prev, delta, skip, false);
+  else
+    assign_t(ctx, s, (const float*)X, n, d, CT, p, out, nullptr, prev, delta, skip, false);
+}
+
+void group_by_key(krr_ctx ctx, hipStream_t s, const int32_t* key, int64_t n, int p, int32_t* perm,
+                  int64_t* offsets, int64_t* sizes64, const int32_t* skip) {
+  const int64_t nblk = ceil_div(n, GROUP_BLOCK);
+  char* w = (char*)ws_get(ctx, "group", (size_t)n * 4 + (size_t)nblk * p * 8 + 64);
+  int32_t* rank = (int32_t*)w;
+  int32_t* bc = rank + n;
+  int32_t* bo = bc + nblk * p;
+  hipLaunchKernelGGL(k_group_local, dim3(nblk), dim3(GROUP_BLOCK), (size_t)p * 4, s, key, n, p, rank, bc,
+                     skip);
+  check_launch(ctx, s, "group_local");
+  hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(std::min(1024, ((p + 63) / 64) * 64)), (size_t)p * 8, s,
+                     (const int32_t*)bc, nblk, p, bo, offsets, sizes64, skip);
+  check_launch(ctx, s, "group_scan");
+  hipLaunchKernelGGL(k_group_scatter, dim3(nblk), dim3(GROUP_BLOCK), 0, s, key, n, p, (const int32_t*)rank,
+                     (const int32_t*)bo, (const int64_t*)offsets, perm, skip);
+  check_launch(ctx, s, "group_scatter");
+}
+
+void gather_rows(krr_ctx ctx, hipStream_t s, const void* X, int dtype, int64_t n, int d,
+                 const int32_t* perm, void* Xout) {
+  const int64_t tot = n * d;
+  hipLaunchKernelGGL(k_cast_rows, dim3(ceil_div(tot, 256)), dim3(256), 0, s, X, dtype, perm, n, d, Xout);
+  check_launch(ctx, s, "gather_rows");
+}
+
+void gather_vec_f64(krr_ctx ctx, hipStream_t s, const void* y, int dtype, int64_t n, const int32_t* perm,
+                    double* yout) {
+  hipLaunchKernelGGL(k_gather_vec, dim3(ceil_div(n, 256)), dim3(256), 0, s, y, dtype, perm, n, yout);
+  check_launch(ctx, s, "gather_vec");
+}
+
+template <typename TX>
+static void partition_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, int p, int method,
+                        int iters, uint64_t seed, double* C, int32_t* assign, int64_t* sizes) {
+  double* CT = (double*)ws_get(ctx, "part_ct", (size_t)p * d * 8);
+  if (method == KRR_PART_GIVEN) {
+    transpose_centroids(ctx, s, C, p, d, CT);
+    assign_t(ctx, s, X, n, d, CT, p, assign, nullptr, nullptr, nullptr, nullptr, false);
+  } else {
+    // K-means: k-means++ seeding then Lloyd passes (Algorithm 2).
+    kmeanspp_t(ctx, s, X, n, d, p, seed, C);
+    char* w = (char*)ws_get(ctx, "lloyd", (size_t)n * 8 + (size_t)(p + 1) * 8 + (size_t)(iters + 2) * 4 + 64);
+    int32_t* perm = (int32_t*)w;
+    int32_t* prev = perm + n;
+    int64_t* off = (int64_t*)(prev + n + (n & 1));
+    int32_t* deltas = (int32_t*)(off + p + 1);
+    int32_t* done = deltas + iters + 1;
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, deltas, (int64_t)(iters + 2), 0);
+    check_launch(ctx, s, "fill");
+    int32_t* cur = assign;
+    int32_t* old = prev;
+    for (int it = 0; it < iters; ++it) {
+      transpose_centroids(ctx, s, C, p, d, CT);
+      assign_t(ctx, s, X, n, d, CT, p, cur, nullptr, it == 0 ? nullptr : old, deltas + it, done, false);
+      group_by_key(ctx, s, cur, n, p, perm, off, nullptr, done);
+      means_t(ctx, s, X, d, perm, off, C, p, done, deltas + it, done);
+      std::swap(cur, old);
+    }
+    transpose_centroids(ctx, s, C, p, d, CT);
+    assign_t(ctx, s, X, n, d, CT, p, assign, nullptr, nullptr, nullptr, nullptr, false);
+    if (method == KRR_PART_KBALANCE) {
+      // Greedy capacity pass over the exact distances to the K-means centres,
+      // then the centre recompute of Algorithm 4.
+      double* D = (double*)ws_get(ctx, "kbal_d", (size_t)n * p * 8);
+      assign_t(ctx, s, X, n, d, CT, p, nullptr, D, nullptr, nullptr, nullptr, true);
+      const int32_t* a0 = assign;  // unconstrained nearest centres
+      int32_t* MB = prev;
+      const int64_t cap = ceil_div(n, p);
+      hipLaunchKernelGGL(k_kbalance, dim3(1), dim3(64), (size_t)p * 8, s, (const double*)D, a0, n, p, cap, MB);
+      check_launch(ctx, s, "kbalance");
+      KRR_HIP(hipMemcpyAsync(assign, MB, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+      group_by_key(ctx, s, assign, n, p, perm, off, nullptr, nullptr);
+      means_t(ctx, s, X, d, perm, off, C, p, nullptr, nullptr, nullptr);
+    }
+  }
+  // sizes: histogram of the final assignment
+  int32_t* perm2 = (int32_t*)ws_get(ctx, "part_perm", (size_t)n * 4 + (size_t)(p + 1) * 8 + 16);
+  int64_t* off2 = (int64_t*)(perm2 + n + (n & 1));
+  group_by_key(ctx, s, assign, n, p, perm2, off2, sizes, nullptr);
+}
+
+void run_partition(krr_ctx ctx, hipStream_t s, const void* X, int dtype, int64_t n, int d, int p, int method,
+                   int iters, uint64_t seed, double* C, int32_t* assign, int64_t* sizes) {
+  if (dtype == KRR_F64)
+    partition_t(ctx, s, (const double*)X, n, d, p, method, iters, seed, C, assign, sizes);
+  else
+    partition_t(ctx, s, (const float*)X, n, d, p, method, iters, seed, C, assign, sizes);
+}
+
+}  // namespace krr

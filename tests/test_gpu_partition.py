@@ -1,0 +1,83 @@
+"""Parity of the partition kernels with the oracle: assignment indices, the
+k-means++ / Lloyd centres and the K-balance memberships must be identical bit
+for bit on the same seeded inputs."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1805_00569_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+@pytest.mark.parametrize("n,d,p,dtype", [(131072, 90, 32, np.float32), (2048, 16, 1, np.float64),
+                                         (1000, 7, 5, np.float64), (257, 90, 64, np.float32),
+                                         (300, 600, 9, np.float64), (5, 3, 5, np.float32)])
+def test_assign_given_bitexact(ctx, dev, n, d, p, dtype):
+    print(f"assign n={n} d={d} p={p} {dtype.__name__}", flush=True)
+    g = np.random.default_rng(n + d + p)
+    X = (g.standard_normal((n, d)) * g.uniform(0.5, 2, d)).astype(dtype)
+    C = g.standard_normal((p, d))
+    if p >= 3:
+        C[p - 1] = C[1]                      # planted duplicate centre
+        C[0] = X[min(3, n - 1)].astype(np.float64)   # a point sitting on a centre
+    Cg, a, sz = ctx.partition(_t(X, dev), p, "given", centroids=_t(C, dev))
+    ao, _ = O.assign(X, C)
+    np.testing.assert_array_equal(a.cpu().numpy(), ao)
+    np.testing.assert_array_equal(sz.cpu().numpy(), np.bincount(ao, minlength=p))
+    np.testing.assert_array_equal(Cg.cpu().numpy(), C)
+
+
+def test_kmeans_seeding_and_lloyd_bitexact(ctx, dev):
+    w = datagen.gaussian_mixture(seed=31, n=8192, d=90, comps=16, lo=128, hi=2000)
+    for iters in (0, 1, 7):
+        print(f"kmeans iters={iters}", flush=True)
+        C, a, sz = ctx.partition(_t(w.X, dev), 16, "kmeans", lloyd_iters=iters, seed=123)
+        C0, idx = O.kmeanspp(w.X, 16, 123)
+        Co, ao, _, _ = O.lloyd(w.X, C0, iters)
+        np.testing.assert_array_equal(C.cpu().numpy(), Co)
+        np.testing.assert_array_equal(a.cpu().numpy(), ao)
+        np.testing.assert_array_equal(sz.cpu().numpy(), np.bincount(ao, minlength=16))
+
+
+def test_kbalance_bitexact(ctx, dev):
+    w = datagen.balanced(seed=32, n=8192, k_test=16, p=16)
+    print("kbalance n=8192 p=16", flush=True)
+    C, a, sz = ctx.partition(_t(w.X, dev), 16, "kbalance", lloyd_iters=5, seed=7)
+    Co, ao = O.kbalance(w.X, 16, 5, 7)
+    np.testing.assert_array_equal(a.cpu().numpy(), ao)
+    np.testing.assert_array_equal(C.cpu().numpy(), Co)
+    assert sz.cpu().numpy().tolist() == [512] * 16
+
+
+def test_kbalance_ragged_capacity(ctx, dev):
+    w = datagen.small(33, 1003, 5, comps=3, dtype=np.float64)
+    C, a, sz = ctx.partition(_t(w.X, dev), 7, "kbalance", lloyd_iters=4, seed=3)
+    Co, ao = O.kbalance(w.X, 7, 4, 3)
+    np.testing.assert_array_equal(a.cpu().numpy(), ao)
+    np.testing.assert_array_equal(C.cpu().numpy(), Co)
+    assert sz.cpu().numpy().max() <= 144
+
+
+def test_kmeans_converges_early(ctx, dev):
+    # well separated clusters: Lloyd reaches a fixed point before the cap
+    w = datagen.small(34, 2000, 4, comps=4, spread=50.0)
+    C, a, _ = ctx.partition(_t(w.X, dev), 4, "kmeans", lloyd_iters=50, seed=1)
+    C0, _ = O.kmeanspp(w.X, 4, 1)
+    Co, ao, passes, deltas = O.lloyd(w.X, C0, 50)
+    assert passes < 50
+    np.testing.assert_array_equal(C.cpu().numpy(), Co)
+    np.testing.assert_array_equal(a.cpu().numpy(), ao)
+
+
+def test_partition_rejects_bad_arguments(ctx, dev):
+    from paper_1805_00569_amd import krr
+    X = torch.zeros((10, 3), dtype=torch.float32, device=dev)
+    with pytest.raises(krr.KrrError) as e:
+        ctx.partition(X, 11, "kmeans")
+    assert e.value.status == krr.KRR_EINVAL
