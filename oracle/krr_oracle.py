@@ -258,6 +258,9 @@ def fit_one(Xj, yj, sigma, lam, kernel="gaussian", lambda_times_m=False):
     Returns dict(alpha, status, pivot, backward_error, lambda_eff)."""
     m = Xj.shape[0]
     lam_eff = lam * m if lambda_times_m else lam
+    if m == 0:   # an empty partition (K-means may leave a cluster empty) has no system
+        return {"alpha": np.zeros(0), "status": STATUS_OK, "pivot": 0, "backward_error": 0.0,
+                "lambda_eff": lam_eff}
     A = kernel_matrix(Xj, Xj, sigma, kernel)
     A[np.diag_indices(m)] += lam_eff
     yj = np.asarray(yj, dtype=np.float64)

@@ -448,3 +448,10 @@ def test_generators_shapes_and_determinism():
     assert c.sum() == 131072 and c.min() >= 512 and c.max() <= 14000
     w = datagen.plain_krr()
     assert w.X.shape == (2048, 16) and w.X.dtype == np.float64
+
+
+def test_empty_partition_has_no_system():
+    m = O.fit(np.zeros((3, 2)), np.ones(3), np.array([0, 0, 0], dtype=np.int32), np.zeros((2, 2)), 2, 1.0, 0.1)
+    assert m.alphas[1].shape == (0,) and m.infos[1]["status"] == O.STATUS_OK
+    yhat, r = O.predict(m, np.zeros((2, 2)))
+    assert r.tolist() == [0, 0]
