@@ -102,6 +102,10 @@ typedef struct {
   int32_t status;         /* KRR_OK, KRR_ENOTSPD or KRR_ENOCONV */
   int32_t failed_pivot;   /* 1-based column of the first non-positive pivot, 0 if none */
   int32_t refine_iters;   /* refinement steps taken (MIXED) */
+  int32_t fallback;       /* MIXED: 0 = BF16 trailing updates sufficed; 1 = the system was
+                             refactored with FP32 trailing updates after its BF16 factor
+                             was not positive definite or refinement stalled */
+  int32_t reserved;
   double  rel_residual;   /* ||y - (K + lambda I) alpha|| / ||y|| in FP64 (MIXED; -1 otherwise) */
 } krr_part_info;
 

@@ -1,0 +1,408 @@
+// Batched ragged Cholesky factorisation A_s = L_s L_s^T of the systems
+// (K_s + lambda_s I) of one fit (Section 2.3, Eq. 6: the paper solves these
+// SPD systems by Cholesky, Section 5.5).
+//
+// Storage: every system keeps its lower triangle as T(T+1)/2 packed NB x NB
+// tiles (column-major inside a tile, see common.hpp).  The factorisation is
+// blocked right-looking with a panel of `W` tile columns:
+//
+//   for each panel [K0, K0+W):
+//     for k in the panel:
+//       column update   A(i,k) -= sum_{q in [K0,k)} L(i,q) L(k,q)^T   (i >= k)
+//       diagonal block  A(k,k) = L(k,k) L(k,k)^T in FP64, and Winv(k) = L(k,k)^-1
+//       panel solve     L(i,k) = A(i,k) Winv(k)^T                      (i > k)
+//     trailing update   A(i,j) -= sum_{q in panel} L(i,q) L(j,q)^T     (i >= j >= K0+W)
+//
+// Every launch covers all systems of the batch (blockIdx.y = system); tiles
+// beyond a system's own size exit at once, so one launch sequence serves a
+// ragged batch.  The products run on matrix cores: FP64 MFMA for FP64
+// storage, FP32 MFMA for FP32 storage, and BF16 MFMA with FP32 accumulation
+// for the mixed-precision trailing updates.  Diagonal blocks are always
+// factored and inverted in FP64.
+#include "common.hpp"
+
+#include <type_traits>
+
+namespace krr {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int TILE = NB * NB;
+
+__device__ __forceinline__ int64_t tile_index(int i, int j) { return (int64_t)i * (i + 1) / 2 + j; }
+
+// ---------------------------------------------------------------------------
+// Diagonal block: load A(k,k), factor in FP64, write L(k,k) and its inverse.
+// Thread t owns row r = t % 64 and columns c = t/64 + 4q (q = 0..15); the
+// current column of L is broadcast through LDS.  A pivot that is not
+// positive (or NaN) marks the system failed with the LAPACK-style 1-based
+// global column index.
+// ---------------------------------------------------------------------------
+template <typename TS>
+__global__ __launch_bounds__(256) void k_potrf_diag(const SysDesc* __restrict__ desc, SysStatus* __restrict__ st,
+                                                    TS* __restrict__ A, TS* __restrict__ Wt, int k, int level) {
+  const int s = blockIdx.x;
+  const SysDesc D = desc[s];
+  if (k >= D.T || st[s].status != 0 || D.level != level) return;
+  __shared__ double sL[TILE];
+  __shared__ double sW[TILE];
+  __shared__ double sdiag;
+  __shared__ int sfail;
+  TS* tile = A + D.a_off + tile_index(k, k) * TILE;
+  const int t = threadIdx.x;
+  const int r = t & 63;
+  const int g = t >> 6;
+  double a[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int c = g + 4 * q;
+    a[q] = (c <= r) ? (double)tile[c * NB + r] : 0.0;
+  }
+  if (t == 0) sfail = 0;
+  // owner of (0,0): r == 0, g == 0
+  if (t == 0) {
+    const double v = a[0];
+    if (!(v > 0.0)) sfail = 1;
+    sdiag = sqrt(v);
+  }
+  __syncthreads();
+  for (int j = 0; j < NB; ++j) {
+    if (sfail) break;
+    const double ljj = sdiag;
+    if (g == (j & 3)) {
+      const int qj = j >> 2;
+      double l;
+      if (r > j) l = a[qj] / ljj;
+      else if (r == j) l = ljj;
+      else l = 0.0;
+      a[qj] = l;
+      sL[j * NB + r] = l;
+    }
+    __syncthreads();
+    const double lr = sL[j * NB + r];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int c = g + 4 * q;
+      if (c > j && c <= r) a[q] = fma(-lr, sL[j * NB + c], a[q]);
+    }
+    if (j + 1 < NB && r == j + 1 && g == ((j + 1) & 3)) {
+      const double v = a[(j + 1) >> 2];
+      if (!(v > 0.0)) sfail = j + 2;
+      sdiag = sqrt(v);
+    }
+    __syncthreads();
+  }
+  if (sfail) {
+    if (t == 0) {
+      st[s].status = KRR_ENOTSPD;
+      st[s].failed_pivot = k * NB + sfail;
+    }
+    return;
+  }
+  // L back to the tile (upper part zeroed)
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int c = g + 4 * q;
+    tile[c * NB + r] = (TS)((c <= r) ? a[q] : 0.0);
+  }
+  // Inverse W = L^-1 by forward substitution, row by row of W:
+  // W(kk,:) /= L(kk,kk), then W(r,:) -= L(r,kk) W(kk,:) for r > kk.
+  double w[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) w[q] = (g + 4 * q == r) ? 1.0 : 0.0;
+  for (int kk = 0; kk < NB; ++kk) {
+    if (r == kk) {
+      const double d = sL[kk * NB + kk];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int c = g + 4 * q;
+        if (c <= kk) {
+          w[q] = w[q] / d;
+          sW[kk * NB + c] = w[q];
+        }
+      }
+    }
+    __syncthreads();
+    if (r > kk) {
+      const double lrk = sL[kk * NB + r];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int c = g + 4 * q;
+        if (c <= kk) w[q] = fma(-lrk, sW[kk * NB + c], w[q]);
+      }
+    }
+  }
+  TS* wt = Wt + D.w_off + (int64_t)k * TILE;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int c = g + 4 * q;
+    wt[c * NB + r] = (TS)((c <= r) ? w[q] : 0.0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tile products C = sum_q P_q Q_q^T on matrix cores, with P_q, Q_q, C packed
+// column-major NB x NB tiles.  The MFMA computes D' = Q P^T so that a lane's
+// result index along 16 consecutive lanes walks down a tile column (unit
+// stride in memory).  Wave w owns rows [32(w&1), +32) and columns
+// [32(w>>1), +32) of the output tile.
+//   MODE_TRSM:   C(i,k) <- A(i,k) Winv(k)^T         i = i0 + bx, j = k
+//   MODE_COL:    C(i,k) <- C(i,k) - sum_{q0<=q<q1} L(i,q) L(k,q)^T, i = i0 + bx
+//   MODE_TRI:    C(i,j) <- C(i,j) - sum_{q0<=q<q1} L(i,q) L(j,q)^T for the
+//                lower triangle j0 <= j <= i (bx = linear triangle index)
+// ---------------------------------------------------------------------------
+enum { MODE_TRSM = 0, MODE_COL = 1, MODE_TRI = 2 };
+
+__device__ __forceinline__ void mfma_step(d4& acc, double a, double b) {
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+}
+__device__ __forceinline__ void mfma_step(f4& acc, float a, float b) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+}
+// row of register v of a lane's 16x16 block result
+__device__ __forceinline__ int out_row(double*, int lane, int v) { return (lane >> 4) + 4 * v; }
+__device__ __forceinline__ int out_row(float*, int lane, int v) { return 4 * (lane >> 4) + v; }
+
+template <typename TS>
+struct AccT;
+template <>
+struct AccT<double> {
+  typedef d4 type;
+};
+template <>
+struct AccT<float> {
+  typedef f4 type;
+};
+
+__device__ __forceinline__ bool locate(int mode, int bx, int i0, int jc, int T, int& i, int& j) {
+  if (mode == MODE_TRI) {
+    // bx = ii (ii + 1) / 2 + jj, 0 <= jj <= ii
+    int ii = (int)((sqrt(8.0 * (double)bx + 1.0) - 1.0) * 0.5);
+    while ((int64_t)ii * (ii + 1) / 2 > bx) --ii;
+    while ((int64_t)(ii + 1) * (ii + 2) / 2 <= bx) ++ii;
+    const int jj = bx - ii * (ii + 1) / 2;
+    i = i0 + ii;
+    j = i0 + jj;
+  } else {
+    i = i0 + bx;
+    j = jc;
+  }
+  return i < T;
+}
+
+template <typename TS, int MODE>
+__global__ __launch_bounds__(256) void k_tile_gemm(const SysDesc* __restrict__ desc,
+                                                   const SysStatus* __restrict__ st, TS* __restrict__ A,
+                                                   const TS* __restrict__ Wt, int i0, int jc, int q0, int q1,
+                                                   int level) {
+  typedef typename AccT<TS>::type acc_t;
+  const int s = blockIdx.y;
+  const SysDesc D = desc[s];
+  if (st[s].status != 0 || D.level != level) return;
+  int i, j;
+  if (!locate(MODE, blockIdx.x, i0, jc, D.T, i, j)) return;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int r0 = 32 * (w & 1);
+  const int c0 = 32 * (w >> 1);
+  TS* Ab = A + D.a_off;
+  TS* C = Ab + tile_index(i, j) * TILE;
+  acc_t acc[2][2];
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[cb][rb][v] = 0;
+  const int kl = lane >> 4;   // k offset of this lane inside a 4-step
+  const int il = lane & 15;   // row offset inside a 16-block
+  int qa = q0, qb = q1;
+  if (MODE == MODE_TRSM) {
+    qa = 0;
+    qb = 1;
+  }
+  for (int q = qa; q < qb; ++q) {
+    const TS* P;
+    const TS* Q;
+    if (MODE == MODE_TRSM) {
+      P = C;
+      Q = Wt + D.w_off + (int64_t)jc * TILE;
+    } else {
+      P = Ab + tile_index(i, q) * TILE;
+      Q = Ab + tile_index(j, q) * TILE;
+    }
+#pragma unroll 4
+    for (int kb = 0; kb < NB; kb += 4) {
+      const int koff = (kb + kl) * NB;
+      TS pa[2], qv[2];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) pa[rb] = P[koff + r0 + 16 * rb + il];
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) qv[cb] = Q[koff + c0 + 16 * cb + il];
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) mfma_step(acc[cb][rb], qv[cb], pa[rb]);
+    }
+  }
+  if (MODE == MODE_TRSM) __syncthreads();  // C aliases P: every wave must finish reading
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = c0 + 16 * cb + out_row((TS*)nullptr, lane, v);
+        const int r = r0 + 16 * rb + il;
+        const int e = c * NB + r;
+        if (MODE == MODE_TRSM)
+          C[e] = (TS)acc[cb][rb][v];
+        else
+          C[e] = (TS)(C[e] - acc[cb][rb][v]);
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Mixed precision trailing/column updates: FP32 tiles, operands rounded to
+// BF16, products accumulated in FP32 on v_mfma_f32_16x16x32_bf16.  Operands
+// are staged through LDS row-major (32 consecutive k per row as BF16) so
+// that a lane reads its 8 consecutive k values with one 16-byte load.
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(256) void k_tile_gemm_bf16(const SysDesc* __restrict__ desc,
+                                                        const SysStatus* __restrict__ st, float* __restrict__ A,
+                                                        int i0, int jc, int q0, int q1, int level) {
+  const int s = blockIdx.y;
+  const SysDesc D = desc[s];
+  if (st[s].status != 0 || D.level != level) return;
+  int i, j;
+  if (!locate(MODE, blockIdx.x, i0, jc, D.T, i, j)) return;
+  constexpr int KC = NB;         // k per stage
+  constexpr int LDR = KC + 8;    // padded row length (bf16 elements)
+  __shared__ __attribute__((aligned(16))) __bf16 sP[NB * LDR];
+  __shared__ __attribute__((aligned(16))) __bf16 sQ[NB * LDR];
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int w = t >> 6;
+  const int r0 = 32 * (w & 1);
+  const int c0 = 32 * (w >> 1);
+  float* Ab = A + D.a_off;
+  float* C = Ab + tile_index(i, j) * TILE;
+  f4 acc[2][2];
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[cb][rb][v] = 0.f;
+  const int il = lane & 15;
+  const int kg = lane >> 4;  // 8-wide k group
+  for (int q = q0; q < q1; ++q) {
+    const float* P = Ab + tile_index(i, q) * TILE;
+    const float* Q = Ab + tile_index(j, q) * TILE;
+    for (int k0 = 0; k0 < NB; k0 += KC) {
+      // stage: element (row, k) of the chunk; consecutive threads walk rows
+      // (unit stride in the column-major tile)
+      __syncthreads();
+#pragma unroll
+      for (int e = t; e < NB * KC; e += 256) {
+        const int row = e & 63;
+        const int kk = e >> 6;
+        sP[row * LDR + kk] = (__bf16)P[(k0 + kk) * NB + row];
+        sQ[row * LDR + kk] = (__bf16)Q[(k0 + kk) * NB + row];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int ks = 0; ks < KC; ks += 32) {
+        bf8 pa[2], qv[2];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+          pa[rb] = *reinterpret_cast<const bf8*>(&sP[(r0 + 16 * rb + il) * LDR + ks + 8 * kg]);
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+          qv[cb] = *reinterpret_cast<const bf8*>(&sQ[(c0 + 16 * cb + il) * LDR + ks + 8 * kg]);
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+          for (int rb = 0; rb < 2; ++rb)
+            acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qv[cb], pa[rb], acc[cb][rb], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = c0 + 16 * cb + 4 * (lane >> 4) + v;
+        const int r = r0 + 16 * rb + il;
+        const int e = c * NB + r;
+        C[e] = C[e] - acc[cb][rb][v];
+      }
+}
+
+template <typename TS>
+void launch_update(krr_ctx ctx, hipStream_t s, bool bf16, int mode, const SysDesc* desc, SysStatus* st, TS* A,
+                   const TS* Wt, int n_sys, int64_t nblk, int i0, int jc, int q0, int q1, int level) {
+  if (nblk <= 0) return;
+  const dim3 grid((unsigned)nblk, (unsigned)n_sys);
+  if constexpr (std::is_same<TS, float>::value) {
+    if (bf16 && mode != MODE_TRSM) {
+      if (mode == MODE_COL)
+        hipLaunchKernelGGL((k_tile_gemm_bf16<MODE_COL>), grid, dim3(256), 0, s, desc, st, A, i0, jc, q0, q1, level);
+      else
+        hipLaunchKernelGGL((k_tile_gemm_bf16<MODE_TRI>), grid, dim3(256), 0, s, desc, st, A, i0, jc, q0, q1, level);
+      check_launch(ctx, s, "tile_gemm_bf16");
+      return;
+    }
+  }
+  const SysStatus* cst = st;
+  if (mode == MODE_TRSM)
+    hipLaunchKernelGGL((k_tile_gemm<TS, MODE_TRSM>), grid, dim3(256), 0, s, desc, cst, A, Wt, i0, jc, q0, q1, level);
+  else if (mode == MODE_COL)
+    hipLaunchKernelGGL((k_tile_gemm<TS, MODE_COL>), grid, dim3(256), 0, s, desc, cst, A, Wt, i0, jc, q0, q1, level);
+  else
+    hipLaunchKernelGGL((k_tile_gemm<TS, MODE_TRI>), grid, dim3(256), 0, s, desc, cst, A, Wt, i0, jc, q0, q1, level);
+  check_launch(ctx, s, "tile_gemm");
+}
+
+template <typename TS>
+void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, int n_sys, int Tmax, TS* A, TS* Wt,
+              bool bf16, int Wp, int level) {
+  for (int K0 = 0; K0 < Tmax; K0 += Wp) {
+    const int K1 = std::min(K0 + Wp, Tmax);
+    for (int k = K0; k < K1; ++k) {
+      if (k > K0) launch_update<TS>(ctx, s, bf16, MODE_COL, desc, st, A, Wt, n_sys, Tmax - k, k, k, K0, k, level);
+      hipLaunchKernelGGL((k_potrf_diag<TS>), dim3(n_sys), dim3(256), 0, s, desc, st, A, Wt, k, level);
+      check_launch(ctx, s, "potrf_diag");
+      if (k + 1 < Tmax)
+        launch_update<TS>(ctx, s, false, MODE_TRSM, desc, st, A, Wt, n_sys, Tmax - k - 1, k + 1, k, 0, 1, level);
+    }
+    if (K1 < Tmax) {
+      const int64_t R = Tmax - K1;
+      launch_update<TS>(ctx, s, bf16, MODE_TRI, desc, st, A, Wt, n_sys, R * (R + 1) / 2, K1, 0, K0, K1, level);
+    }
+  }
+}
+
+}  // namespace
+
+// Factor, in place, the systems of the batch whose descriptor carries
+// `level` (the others are left untouched).  prec: KRR_PREC_FP64 -> A, Wt are
+// double; FP32 / MIXED -> float.  bf16: BF16 trailing and column updates
+// (MIXED first pass); otherwise FP32 (or FP64) matrix-core updates.
+void cholesky_factor(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, SysStatus* st, int n_sys, int Tmax,
+                     void* A, void* Wt, int level, bool bf16) {
+  const int Wp = ctx->panel_tiles;
+  if (prec == KRR_PREC_FP64)
+    factor_t<double>(ctx, s, desc, st, n_sys, Tmax, (double*)A, (double*)Wt, false, Wp, level);
+  else
+    factor_t<float>(ctx, s, desc, st, n_sys, Tmax, (float*)A, (float*)Wt, bf16, Wp, level);
+}
+
+}  // namespace krr

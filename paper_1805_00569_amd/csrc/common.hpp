@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <cstring>
 #include <map>
 #include <memory>
 #include <string>
@@ -61,7 +62,7 @@ struct SysDesc {
   double neg_inv_2s2;  // -1 / (2 sigma^2)
   double lambda;       // diagonal shift actually used
   int32_t kernel;      // krr_kernel
-  int32_t pad_;
+  int32_t level;       // precision level that factors this system in the current pass
 };
 
 // Device-side status of one system.
@@ -70,7 +71,10 @@ struct SysStatus {
   int32_t failed_pivot;  // 1-based, 0 = none
   int32_t refine_iters;
   int32_t converged;     // refinement reached the tolerance
+  int32_t stalled;       // refinement stopped reducing the residual
+  int32_t pad_;
   double rel_residual;
+  double prev_rel;
   double ynorm;
 };
 

@@ -1,7 +1,470 @@
+// krr_fit: group the training points by partition, form every system
+// A_s = K_s + lambda_s I (Table 1 Gaussian or linear kernel, Eq. 6), factor
+// the whole batch (cholesky.hip), solve for alpha (solve.hip), refine in
+// mixed precision, and hand out one model per (sigma, lambda) setting
+// (Algorithm 5: p local models per setting).
 #include "common.hpp"
+
+#include <algorithm>
+#include <cmath>
+
 namespace krr {
-void run_fit(krr_ctx, hipStream_t, const void*, const void*, int, int64_t, int, const int32_t*, const double*, int,
-             const krr_fit_params*, int, krr_model*, krr_part_info*) {
-  fail(KRR_ESTATE, "fit not available in this build");
+
+void cholesky_factor(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, SysStatus* st, int n_sys, int Tmax,
+                     void* A, void* Wt, int level, bool bf16);
+void trsv_forward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, const SysStatus* st, int n_sys,
+                  const void* A, const void* Wt, const double* b, double* z, int skip_converged);
+void trsv_backward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, const SysStatus* st, int n_sys,
+                   const void* A, const void* Wt, const double* z, double* x, double* alpha_acc, int skip_converged);
+void residual_check(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, int n_sys, int Tmax,
+                    const double* K64, const double* alpha, const double* y, double* r, double* P,
+                    const int64_t* p_off, double* rn, double* yn, const int64_t* n_off, double tol,
+                    int will_refine, int32_t* active);
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int TILE = NB * NB;
+constexpr int KC = 32;        // feature chunk staged in LDS
+constexpr int LDX = NB + 1;   // padded LDS row (doubles)
+
+__device__ __forceinline__ int64_t tile_index(int i, int j) { return (int64_t)i * (i + 1) / 2 + j; }
+
+// Kernel formation for partition j = blockIdx.y, tile (ti, tj) = triangle
+// index blockIdx.x.  The Gram block G = X_ti X_tj^T is computed once in FP64
+// on matrix cores (v_mfma_f64_16x16x4f64) and reused by every setting of the
+// partition: A_s(r, c) = exp(-(|x_r|^2 + |x_c|^2 - 2 G(r, c)) / (2 sigma_s^2)),
+// the diagonal set to exactly 1 + lambda_s; rows/columns past m are the
+// identity.  STORE: 0 -> FP64 tiles; 1 -> FP32 tiles; 2 -> FP32 tiles plus an
+// FP64 copy (for the refinement residual).
+template <typename TX, int STORE>
+__global__ __launch_bounds__(256) void k_form(const TX* __restrict__ Xg, int d, const SysDesc* __restrict__ desc,
+                                              int p, int n_params, void* __restrict__ Aout,
+                                              double* __restrict__ K64) {
+  const int j = blockIdx.y;
+  const SysDesc D0 = desc[j];
+  const int T = D0.T;
+  if (T == 0) return;
+  const int bx = blockIdx.x;
+  int ti = (int)((sqrt(8.0 * (double)bx + 1.0) - 1.0) * 0.5);
+  while ((int64_t)ti * (ti + 1) / 2 > bx) --ti;
+  while ((int64_t)(ti + 1) * (ti + 2) / 2 <= bx) ++ti;
+  const int tj = bx - ti * (ti + 1) / 2;
+  if (ti >= T) return;
+  const int m = D0.m;
+  __shared__ double sXi[KC * LDX];
+  __shared__ double sXj[KC * LDX];
+  __shared__ double sNi[NB], sNj[NB];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int r0 = 32 * (w & 1), c0 = 32 * (w >> 1);
+  const int il = lane & 15, kl = lane >> 4;
+  const int rows_i = min(NB, m - ti * NB), rows_j = min(NB, m - tj * NB);
+  const TX* Xi = Xg + (D0.x_off + (int64_t)ti * NB) * d;
+  const TX* Xj = Xg + (D0.x_off + (int64_t)tj * NB) * d;
+  d4 acc[2][2];
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) acc[cb][rb] = d4{0.0, 0.0, 0.0, 0.0};
+  double nrm = 0.0;  // thread t < 64: |x_i(t)|^2, 64 <= t < 128: |x_j(t-64)|^2
+  for (int k0 = 0; k0 < d; k0 += KC) {
+    const int kc = min(KC, d - k0);
+    __syncthreads();
+    for (int e = t; e < NB * KC; e += 256) {
+      const int row = e / KC, kk = e - row * KC;
+      double vi = 0.0, vj = 0.0;
+      if (kk < kc) {
+        if (row < rows_i) vi = (double)Xi[(int64_t)row * d + k0 + kk];
+        if (row < rows_j) vj = (double)Xj[(int64_t)row * d + k0 + kk];
+      }
+      sXi[kk * LDX + row] = vi;
+      sXj[kk * LDX + row] = vj;
+    }
+    __syncthreads();
+    if (t < NB) {
+      for (int kk = 0; kk < kc; ++kk) nrm = fma(sXi[kk * LDX + t], sXi[kk * LDX + t], nrm);
+    } else if (t < 2 * NB) {
+      for (int kk = 0; kk < kc; ++kk) nrm = fma(sXj[kk * LDX + t - NB], sXj[kk * LDX + t - NB], nrm);
+    }
+    for (int kb = 0; kb < kc; kb += 4) {
+      const int ko = (kb + kl) * LDX;
+      double a[2], b[2];
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) a[cb] = sXj[ko + c0 + 16 * cb + il];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) b[rb] = sXi[ko + r0 + 16 * rb + il];
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+          acc[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[cb], b[rb], acc[cb][rb], 0, 0, 0);
+    }
+  }
+  if (t < NB) sNi[t] = nrm;
+  else if (t < 2 * NB) sNj[t - NB] = nrm;
+  __syncthreads();
+  const int64_t toff = tile_index(ti, tj) * TILE;
+  for (int q = 0; q < n_params; ++q) {
+    const SysDesc Dq = desc[q * p + j];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int c = c0 + 16 * cb + kl + 4 * v;   // FP64 MFMA result row of register v
+          const int r = r0 + 16 * rb + il;
+          const int gr = ti * NB + r, gc = tj * NB + c;
+          const double G = acc[cb][rb][v];
+          double val;
+          if (gr >= m || gc >= m) {
+            val = (gr == gc) ? 1.0 : 0.0;
+          } else if (Dq.kernel == KRR_KERNEL_GAUSSIAN) {
+            if (gr == gc) {
+              val = 1.0 + Dq.lambda;
+            } else {
+              const double d2 = fmax(0.0, (sNi[r] + sNj[c]) - 2.0 * G);
+              val = exp(d2 * Dq.neg_inv_2s2);
+            }
+          } else {
+            val = (gr == gc) ? G + Dq.lambda : G;
+          }
+          const int64_t e = Dq.a_off + toff + c * NB + r;
+          if (STORE == 0) {
+            reinterpret_cast<double*>(Aout)[e] = val;
+          } else {
+            reinterpret_cast<float*>(Aout)[e] = (float)val;
+            if (STORE == 2) K64[e] = val;
+          }
+        }
+  }
 }
+
+// Padded right-hand sides: b[v_off + r] = y_grouped[x_off + r] for r < m, else 0.
+__global__ void k_pad_rhs(const SysDesc* __restrict__ desc, int n_sys, const double* __restrict__ yg,
+                          double* __restrict__ b) {
+  const int s = blockIdx.y;
+  const SysDesc D = desc[s];
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= D.T * NB) return;
+  b[D.v_off + r] = (r < D.m) ? yg[D.x_off + r] : 0.0;
 }
+
+__global__ void k_zero_status(SysStatus* st, int n) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n) {
+    st[s].status = 0;
+    st[s].failed_pivot = 0;
+    st[s].refine_iters = 0;
+    st[s].converged = 0;
+    st[s].stalled = 0;
+    st[s].pad_ = 0;
+    st[s].rel_residual = -1.0;
+    st[s].prev_rel = -1.0;
+    st[s].ynorm = 0.0;
+  }
+}
+
+// Systems escalated to `level`: clear their failure / refinement state (the
+// refinement step count is kept) and copy the FP64 kernel tiles back into the
+// FP32 storage that the failed factorisation overwrote.
+__global__ void k_reset_level(const SysDesc* __restrict__ desc, SysStatus* __restrict__ st, int n, int level) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n && desc[s].level == level) {
+    st[s].status = 0;
+    st[s].failed_pivot = 0;
+    st[s].converged = 0;
+    st[s].stalled = 0;
+    st[s].prev_rel = -1.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_restore_tiles(const SysDesc* __restrict__ desc, const double* __restrict__ K64,
+                                                       float* __restrict__ A, int level) {
+  const int s = blockIdx.y;
+  const SysDesc D = desc[s];
+  if (D.level != level) return;
+  const int64_t ntiles = (int64_t)D.T * (D.T + 1) / 2;
+  if ((int64_t)blockIdx.x >= ntiles) return;
+  const int64_t base = D.a_off + (int64_t)blockIdx.x * TILE;
+  for (int e = threadIdx.x; e < TILE; e += 256) A[base + e] = (float)K64[base + e];
+}
+
+__global__ void k_zero_f64(double* a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0.0;
+}
+
+__global__ void k_zero_i32(int32_t* a, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0;
+}
+
+template <typename TX>
+void launch_form(krr_ctx ctx, hipStream_t s, int prec, const void* Xg, int d, const SysDesc* desc, int p,
+                 int n_params, int Tmax, void* A, double* K64) {
+  const int64_t ntri = (int64_t)Tmax * (Tmax + 1) / 2;
+  if (ntri == 0) return;
+  const dim3 grid((unsigned)ntri, (unsigned)p);
+  const TX* X = (const TX*)Xg;
+  if (prec == KRR_PREC_FP64)
+    hipLaunchKernelGGL((k_form<TX, 0>), grid, dim3(256), 0, s, X, d, desc, p, n_params, A, K64);
+  else if (prec == KRR_PREC_FP32)
+    hipLaunchKernelGGL((k_form<TX, 1>), grid, dim3(256), 0, s, X, d, desc, p, n_params, A, K64);
+  else
+    hipLaunchKernelGGL((k_form<TX, 2>), grid, dim3(256), 0, s, X, d, desc, p, n_params, A, K64);
+  check_launch(ctx, s, "form");
+}
+
+}  // namespace
+
+void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype, int64_t n, int d,
+             const int32_t* assign, const double* centroids, int p, const krr_fit_params* params, int n_params,
+             krr_model* models, krr_part_info* info) {
+  const int prec = params[0].prec;
+  const size_t xes = (dtype == KRR_F64) ? 8 : 4;
+  const size_t aes = (prec == KRR_PREC_FP64) ? 8 : 4;
+
+  // 1. stable grouping by partition
+  char* g = (char*)ws_get(ctx, "fit_group", (size_t)n * 4 + (size_t)(p + 1) * 8 + 64);
+  int32_t* perm = (int32_t*)g;
+  int64_t* off_d = (int64_t*)(g + (((size_t)n * 4 + 15) & ~size_t(15)));
+  group_by_key(ctx, s, assign, n, p, perm, off_d, nullptr, nullptr);
+  int64_t* off_h = (int64_t*)pinned_get(ctx, (size_t)(p + 1) * 8 + 4096);
+  KRR_HIP(hipMemcpyAsync(off_h, off_d, (size_t)(p + 1) * 8, hipMemcpyDeviceToHost, s));
+  KRR_HIP(hipStreamSynchronize(s));
+  std::vector<int64_t> off(off_h, off_h + p + 1);
+
+  // 2. partition data owned by the models
+  auto data = std::make_shared<krr_part_data>();
+  const size_t xbytes = ((size_t)n * d * xes + 255) & ~size_t(255);
+  const size_t cbytes = ((size_t)p * d * 8 + 255) & ~size_t(255);
+  const size_t obytes = ((size_t)(p + 1) * 8 + 255) & ~size_t(255);
+  data->bytes = xbytes + 2 * cbytes + obytes;
+  data->base = model_alloc(ctx, data->bytes);
+  data->ctx = ctx;
+  ctx->n_datas += 1;
+  data->p = p;
+  data->d = d;
+  data->dtype = dtype;
+  data->n = n;
+  data->X = data->base;
+  data->centroids = (double*)((char*)data->base + xbytes);
+  data->ct_t = (double*)((char*)data->base + xbytes + cbytes);
+  data->d_offsets = (int64_t*)((char*)data->base + xbytes + 2 * cbytes);
+  data->offsets = off;
+  gather_rows(ctx, s, X, dtype, n, d, perm, data->X);
+  KRR_HIP(hipMemcpyAsync(data->centroids, centroids, (size_t)p * d * 8, hipMemcpyDeviceToDevice, s));
+  transpose_centroids(ctx, s, centroids, p, d, data->ct_t);
+  KRR_HIP(hipMemcpyAsync(data->d_offsets, off_d, (size_t)(p + 1) * 8, hipMemcpyDeviceToDevice, s));
+
+  // 3. system descriptors
+  const int n_sys = n_params * p;
+  std::vector<SysDesc> desc(n_sys);
+  std::vector<int64_t> p_off(n_sys), n_off(n_sys);
+  int64_t a_tot = 0, w_tot = 0, v_tot = 0, p_tot = 0, n_tot = 0;
+  int Tmax = 0;
+  for (int q = 0; q < n_params; ++q)
+    for (int jp = 0; jp < p; ++jp) {
+      SysDesc& D = desc[q * p + jp];
+      const int64_t m = off[jp + 1] - off[jp];
+      D.m = (int32_t)m;
+      D.T = (int32_t)ceil_div(m, NB);
+      D.part = jp;
+      D.param = q;
+      D.a_off = a_tot;
+      D.w_off = w_tot;
+      D.v_off = v_tot;
+      D.x_off = off[jp];
+      D.neg_inv_2s2 = -1.0 / (2.0 * params[q].sigma * params[q].sigma);
+      D.lambda = params[q].lambda_times_m ? params[q].lambda * (double)m : params[q].lambda;
+      D.kernel = params[q].kernel;
+      D.level = 0;
+      a_tot += tri(D.T) * TILE;
+      w_tot += (int64_t)D.T * TILE;
+      v_tot += (int64_t)D.T * NB;
+      p_off[q * p + jp] = p_tot;
+      n_off[q * p + jp] = n_tot;
+      p_tot += (int64_t)D.T * D.T * NB;
+      n_tot += D.T;
+      Tmax = std::max(Tmax, (int)D.T);
+    }
+  const bool mixed = prec == KRR_PREC_MIXED;
+
+  // 4. workspace (grown inside the HBM budget, reused across calls)
+  void* A = ws_get(ctx, "fit_A", (size_t)std::max<int64_t>(a_tot, 1) * aes);
+  void* Wt = ws_get(ctx, "fit_W", (size_t)std::max<int64_t>(w_tot, 1) * aes);
+  double* K64 = mixed ? (double*)ws_get(ctx, "fit_K64", (size_t)std::max<int64_t>(a_tot, 1) * 8) : nullptr;
+  const size_t vb = (size_t)std::max<int64_t>(v_tot, 1) * 8;
+  char* vecs = (char*)ws_get(ctx, "fit_vec", 5 * vb);
+  double* yg = (double*)ws_get(ctx, "fit_yg", (size_t)n * 8);
+  double* rhs = (double*)vecs;
+  double* alpha = (double*)(vecs + vb);
+  double* zb = (double*)(vecs + 2 * vb);
+  double* rb = (double*)(vecs + 3 * vb);
+  double* db = (double*)(vecs + 4 * vb);
+  const size_t meta = (size_t)n_sys * (sizeof(SysDesc) + sizeof(SysStatus) + 16) + 64;
+  char* mb = (char*)ws_get(ctx, "fit_meta", meta);
+  SysDesc* d_desc = (SysDesc*)mb;
+  SysStatus* d_st = (SysStatus*)(mb + (size_t)n_sys * sizeof(SysDesc));
+  int64_t* d_poff = (int64_t*)(mb + (size_t)n_sys * (sizeof(SysDesc) + sizeof(SysStatus)));
+  int64_t* d_noff = d_poff + n_sys;
+  int32_t* d_active = (int32_t*)(d_noff + n_sys);
+  double* P = nullptr;
+  double* rn = nullptr;
+  double* yn = nullptr;
+  if (mixed) {
+    P = (double*)ws_get(ctx, "fit_P", (size_t)std::max<int64_t>(p_tot, 1) * 8);
+    char* nb = (char*)ws_get(ctx, "fit_norms", (size_t)std::max<int64_t>(n_tot, 1) * 16);
+    rn = (double*)nb;
+    yn = rn + std::max<int64_t>(n_tot, 1);
+  }
+
+  // host -> device descriptors through pinned staging (kept until the sync below)
+  const size_t up_bytes = (size_t)n_sys * (sizeof(SysDesc) + 16);
+  const size_t dn_bytes = (size_t)n_sys * sizeof(SysStatus);
+  char* pin = (char*)pinned_get(ctx, up_bytes + dn_bytes + 4096);
+  std::memcpy(pin, desc.data(), (size_t)n_sys * sizeof(SysDesc));
+  std::memcpy(pin + (size_t)n_sys * sizeof(SysDesc), p_off.data(), (size_t)n_sys * 8);
+  std::memcpy(pin + (size_t)n_sys * (sizeof(SysDesc) + 8), n_off.data(), (size_t)n_sys * 8);
+  KRR_HIP(hipMemcpyAsync(d_desc, pin, (size_t)n_sys * sizeof(SysDesc), hipMemcpyHostToDevice, s));
+  KRR_HIP(hipMemcpyAsync(d_poff, pin + (size_t)n_sys * sizeof(SysDesc), (size_t)n_sys * 16, hipMemcpyHostToDevice,
+                         s));
+  hipLaunchKernelGGL(k_zero_status, dim3((unsigned)ceil_div(n_sys, 128)), dim3(128), 0, s, d_st, n_sys);
+  check_launch(ctx, s, "zero_status");
+
+  // 5. grouped labels, padded right-hand sides
+  gather_vec_f64(ctx, s, y, dtype, n, perm, yg);
+  if (Tmax > 0) {
+    hipLaunchKernelGGL(k_pad_rhs, dim3((unsigned)ceil_div((int64_t)Tmax * NB, 256), (unsigned)n_sys), dim3(256), 0,
+                       s, (const SysDesc*)d_desc, n_sys, (const double*)yg, rhs);
+    check_launch(ctx, s, "pad_rhs");
+  }
+
+  // 6-8. form, factor, solve
+  auto form = [&](const SysDesc* dd, int pp, int nq, int tmax) {
+    if (dtype == KRR_F64)
+      launch_form<double>(ctx, s, prec, data->X, d, dd, pp, nq, tmax, A, K64);
+    else
+      launch_form<float>(ctx, s, prec, data->X, d, dd, pp, nq, tmax, A, K64);
+  };
+  if (!ctx->serial_fit) {
+    form(d_desc, p, n_params, Tmax);
+    cholesky_factor(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, 0, mixed);
+    trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, rhs, zb, 0);
+    trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, zb, alpha, nullptr, 0);
+  } else {
+    // plain per-system sequence: every system formed, factored and solved
+    // by its own launches, one after another
+    for (int sidx = 0; sidx < n_sys; ++sidx) {
+      if (desc[sidx].T == 0) continue;
+      form(d_desc + sidx, 1, 1, desc[sidx].T);
+      cholesky_factor(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, desc[sidx].T, A, Wt, 0, mixed);
+      trsv_forward(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, A, Wt, rhs, zb, 0);
+      trsv_backward(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, A, Wt, zb, alpha, nullptr, 0);
+    }
+  }
+
+  // 9. mixed precision: refine alpha with an FP64 residual; systems whose
+  // BF16-updated factor is not positive definite or whose refinement stalls
+  // are re-formed from the FP64 kernel and refactored with FP32 updates.
+  SysStatus* st_h = (SysStatus*)(pin + up_bytes);
+  std::vector<int> fallback(n_sys, 0);
+  if (mixed && Tmax > 0) {
+    const int maxr = params[0].max_refine;
+    const double tol = params[0].refine_tol;
+    int32_t* act_h = (int32_t*)(pin + up_bytes + dn_bytes);
+    auto refine = [&]() {
+      for (int it = 0;; ++it) {
+        const int will = it < maxr ? 1 : 0;
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, d_active, 1);
+        check_launch(ctx, s, "zero_active");
+        residual_check(ctx, s, d_desc, d_st, n_sys, Tmax, K64, alpha, rhs, rb, P, d_poff, rn, yn, d_noff, tol, will,
+                       d_active);
+        if (!will) break;
+        KRR_HIP(hipMemcpyAsync(act_h, d_active, 4, hipMemcpyDeviceToHost, s));
+        KRR_HIP(hipStreamSynchronize(s));
+        if (*act_h == 0) break;
+        trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, rb, zb, 1);
+        trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, zb, db, alpha, 1);
+      }
+    };
+    refine();
+    KRR_HIP(hipMemcpyAsync(st_h, d_st, dn_bytes, hipMemcpyDeviceToHost, s));
+    KRR_HIP(hipStreamSynchronize(s));
+    int n_esc = 0;
+    for (int sidx = 0; sidx < n_sys; ++sidx)
+      if (desc[sidx].T > 0 && !st_h[sidx].converged) {
+        desc[sidx].level = 1;
+        fallback[sidx] = 1;
+        ++n_esc;
+      }
+    if (n_esc > 0) {
+      std::memcpy(pin, desc.data(), (size_t)n_sys * sizeof(SysDesc));
+      KRR_HIP(hipMemcpyAsync(d_desc, pin, (size_t)n_sys * sizeof(SysDesc), hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_reset_level, dim3((unsigned)ceil_div(n_sys, 128)), dim3(128), 0, s,
+                         (const SysDesc*)d_desc, d_st, n_sys, 1);
+      check_launch(ctx, s, "reset_level");
+      hipLaunchKernelGGL(k_restore_tiles, dim3((unsigned)tri(Tmax), (unsigned)n_sys), dim3(256), 0, s,
+                         (const SysDesc*)d_desc, (const double*)K64, (float*)A, 1);
+      check_launch(ctx, s, "restore_tiles");
+      cholesky_factor(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, 1, false);
+      trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, rhs, zb, 1);
+      trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, zb, alpha, nullptr, 1);
+      refine();
+    }
+  }
+
+  // 10. status to host
+  KRR_HIP(hipMemcpyAsync(st_h, d_st, dn_bytes, hipMemcpyDeviceToHost, s));
+  KRR_HIP(hipStreamSynchronize(s));
+  for (int q = 0; q < n_params; ++q)
+    for (int jp = 0; jp < p; ++jp) {
+      const int sidx = q * p + jp;
+      krr_part_info& I = info[sidx];
+      const SysStatus& S = st_h[sidx];
+      I.partition = jp;
+      I.param = q;
+      I.m = desc[sidx].m;
+      I.status = S.status;
+      I.failed_pivot = S.failed_pivot;
+      I.refine_iters = S.refine_iters;
+      I.fallback = fallback[sidx];
+      I.reserved = 0;
+      I.rel_residual = mixed ? S.rel_residual : -1.0;
+      if (mixed && S.status == 0 && !S.converged && desc[sidx].T > 0) I.status = KRR_ENOCONV;
+    }
+
+  // 11. models: alpha of setting q is the contiguous range of its p systems
+  for (int q = 0; q < n_params; ++q) {
+    krr_model M = new krr_model_s();
+    M->ctx = ctx;
+    M->data = data;
+    M->params = params[q];
+    const int64_t v0 = desc[q * p].v_off;
+    const int64_t v1 = (q + 1 < n_params) ? desc[(q + 1) * p].v_off : v_tot;
+    const size_t abytes = (((size_t)(v1 - v0) * 8 + 255) & ~size_t(255));
+    M->bytes = abytes + (size_t)(p + 1) * 8;
+    try {
+      M->alpha = (double*)model_alloc(ctx, M->bytes);
+    } catch (...) {
+      delete M;
+      throw;
+    }
+    ctx->n_models += 1;
+    M->d_voff = (int64_t*)((char*)M->alpha + abytes);
+    M->voff.resize(p + 1);
+    for (int jp = 0; jp < p; ++jp) M->voff[jp] = desc[q * p + jp].v_off - v0;
+    M->voff[p] = v1 - v0;
+    M->lambda_eff.resize(p);
+    for (int jp = 0; jp < p; ++jp) M->lambda_eff[jp] = desc[q * p + jp].lambda;
+    if (v1 > v0)
+      KRR_HIP(hipMemcpyAsync(M->alpha, alpha + v0, (size_t)(v1 - v0) * 8, hipMemcpyDeviceToDevice, s));
+    std::memcpy(pin, M->voff.data(), (size_t)(p + 1) * 8);
+    KRR_HIP(hipMemcpyAsync(M->d_voff, pin, (size_t)(p + 1) * 8, hipMemcpyHostToDevice, s));
+    KRR_HIP(hipStreamSynchronize(s));
+    models[q] = M;
+  }
+}
+
+}  // namespace krr

@@ -43,7 +43,7 @@ class FitParams(ctypes.Structure):
 class PartInfo(ctypes.Structure):
     _fields_ = [("partition", ctypes.c_int32), ("param", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("failed_pivot", ctypes.c_int32), ("refine_iters", ctypes.c_int32),
-                ("rel_residual", ctypes.c_double)]
+                ("fallback", ctypes.c_int32), ("reserved", ctypes.c_int32), ("rel_residual", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p

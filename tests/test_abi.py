@@ -28,5 +28,5 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     # krr_fit_params: double, double, int32, int32, double, int32, int32 -> 40 bytes
     assert ctypes.sizeof(krr.FitParams) == 40
-    # krr_part_info: 6 x int32 + double -> 32 bytes
-    assert ctypes.sizeof(krr.PartInfo) == 32
+    # krr_part_info: 8 x int32 + double -> 40 bytes
+    assert ctypes.sizeof(krr.PartInfo) == 40
