@@ -115,7 +115,10 @@ typedef enum {
   KRR_OPT_SERIAL_FIT = 1,   /* 1: factor the systems one after another, one launch
                                sequence per (partition, setting) -- the plain per-partition
                                baseline; 0 (default): one batched launch sequence */
-  KRR_OPT_SYNC_CHECK = 2    /* 1: synchronise after every launch and report faults (debug) */
+  KRR_OPT_SYNC_CHECK = 2,   /* 1: synchronise after every launch and report faults (debug) */
+  KRR_OPT_TIMING = 3        /* HIP-event timing of kernel launches: 0 off, 1 the matrix-core
+                               factorisation updates only, 2 every timed kernel class;
+                               setting it clears the record (see krr_timing_report) */
 } krr_option;
 
 /* ---- context ------------------------------------------------------------
@@ -132,6 +135,14 @@ const char* krr_last_error(krr_ctx ctx);
 krr_status  krr_set_option(krr_ctx ctx, int32_t option, int64_t value);
 /* Bytes of device memory currently held by the context (workspace + models). */
 krr_status  krr_memory_in_use(krr_ctx ctx, size_t* bytes);
+/* Timing record of the launches made since timing was enabled or last
+ * reported: synchronises the device and writes a NUL-terminated JSON object
+ * {"<kernel class>": {"count": launches, "ms": summed event time, "flops":
+ * summed algorithmic flops}, ...} into buf (host, cap bytes, truncated if
+ * short).  *needed (host, nullable) receives the full length including the
+ * NUL.  The record is cleared when buf is given; buf = NULL only queries the
+ * length. */
+krr_status  krr_timing_report(krr_ctx ctx, char* buf, size_t cap, size_t* needed);
 
 /* ---- partition (Section 2.4 Algorithm 2; Section 4.3 Algorithm 4) --------
  * X:         device, n x d row-major, dtype `dtype` (FP32 values are widened

@@ -82,6 +82,48 @@ void check_launch(krr_ctx ctx, hipStream_t s, const char* what) {
   }
 }
 
+static hipEvent_t ev_get(krr_ctx ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+KernelTimer::KernelTimer(krr_ctx c, hipStream_t st, const char* name, double f, int major)
+    : ctx(c), s(st), cls(name), flops(f) {
+  if (ctx->timing == 0 || (ctx->timing == 1 && !major)) return;
+  a = ev_get(ctx);
+  b = ev_get(ctx);
+  if (a == nullptr || b == nullptr || hipEventRecord(a, s) != hipSuccess) {
+    a = b = nullptr;
+  }
+}
+
+KernelTimer::~KernelTimer() {
+  if (a == nullptr) return;
+  if (hipEventRecord(b, s) == hipSuccess) ctx->pending.push_back({cls, a, b, flops});
+}
+
+static void collect_timing(krr_ctx ctx) {
+  KRR_HIP(hipDeviceSynchronize());
+  for (auto& p : ctx->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      krr_timing_agg& g = ctx->timing_agg[p.cls];
+      g.count += 1;
+      g.ms += ms;
+      g.flops += p.flops;
+    }
+    ctx->ev_pool.push_back(p.a);
+    ctx->ev_pool.push_back(p.b);
+  }
+  ctx->pending.clear();
+}
+
 struct DeviceGuard {
   int old = -1;
   explicit DeviceGuard(int dev) {
@@ -149,6 +191,11 @@ krr_status krr_destroy(krr_ctx ctx) {
   (void)hipDeviceSynchronize();
   for (auto& kv : ctx->ws)
     if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+  for (auto& p : ctx->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
   return KRR_OK;
@@ -169,8 +216,37 @@ krr_status krr_set_option(krr_ctx ctx, int32_t option, int64_t value) {
       case KRR_OPT_SYNC_CHECK:
         ctx->sync_check = value ? 1 : 0;
         break;
+      case KRR_OPT_TIMING:
+        KRR_REQUIRE(value >= 0 && value <= 2, "timing must be 0, 1 or 2");
+        collect_timing(ctx);
+        ctx->timing_agg.clear();
+        ctx->timing = (int)value;
+        break;
       default:
         fail(KRR_EINVAL, "unknown option");
+    }
+  });
+}
+
+krr_status krr_timing_report(krr_ctx ctx, char* buf, size_t cap, size_t* needed) {
+  return guarded(ctx, [&] {
+    collect_timing(ctx);
+    std::string js = "{";
+    bool first = true;
+    char tmp[256];
+    for (auto& kv : ctx->timing_agg) {
+      std::snprintf(tmp, sizeof(tmp), "%s\"%s\": {\"count\": %lld, \"ms\": %.6f, \"flops\": %.6e}",
+                    first ? "" : ", ", kv.first.c_str(), (long long)kv.second.count, kv.second.ms, kv.second.flops);
+      js += tmp;
+      first = false;
+    }
+    js += "}";
+    if (needed != nullptr) *needed = js.size() + 1;
+    if (buf != nullptr && cap > 0) {
+      const size_t nb = std::min(cap - 1, js.size());
+      std::memcpy(buf, js.data(), nb);
+      buf[nb] = 0;
+      ctx->timing_agg.clear();
     }
   });
 }

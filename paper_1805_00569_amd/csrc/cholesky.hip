@@ -36,111 +36,126 @@ constexpr int TILE = NB * NB;
 __device__ __forceinline__ int64_t tile_index(int i, int j) { return (int64_t)i * (i + 1) / 2 + j; }
 
 // ---------------------------------------------------------------------------
-// Diagonal block: load A(k,k), factor in FP64, write L(k,k) and its inverse.
-// Thread t owns row r = t % 64 and columns c = t/64 + 4q (q = 0..15); the
-// current column of L is broadcast through LDS.  A pivot that is not
-// positive (or NaN) marks the system failed with the LAPACK-style 1-based
-// global column index.
+// Diagonal block: load A(k,k) into LDS, factor it in FP64 and form the
+// inverse Winv(k) = L(k,k)^-1, both right-looking with one barrier per
+// column.  Each of the 256 threads owns a fixed set of lower-triangle
+// positions (r, c).
+//   Factor, column j: every thread reads the pivot A(j,j) and scales column j
+//   on the fly (column j of A is not written during step j), writes the final
+//   L(:,j) into sL, and updates its positions with j < c <= r.
+//   Inverse, row kk of W: rows r > kk are updated with the scaled row kk read
+//   from the working copy (row kk is not written during step kk); the final
+//   scaled row goes to sW.
+// A pivot that is not positive (or NaN) marks the system failed with the
+// LAPACK-style 1-based global column index.
 // ---------------------------------------------------------------------------
+constexpr int DIAG_THREADS = 256;
+constexpr int DIAG_LD = NB + 1;                                  // padded LDS row
+constexpr int DIAG_PER = (NB * (NB + 1) / 2 + DIAG_THREADS - 1) / DIAG_THREADS;   // 9
+
 template <typename TS>
-__global__ __launch_bounds__(256) void k_potrf_diag(const SysDesc* __restrict__ desc, SysStatus* __restrict__ st,
-                                                    TS* __restrict__ A, TS* __restrict__ Wt, int k, int level) {
+__global__ __launch_bounds__(DIAG_THREADS) void k_potrf_diag(const SysDesc* __restrict__ desc,
+                                                             SysStatus* __restrict__ st, TS* __restrict__ A,
+                                                             TS* __restrict__ Wt, int k, int level) {
   const int s = blockIdx.x;
   const SysDesc D = desc[s];
   if (k >= D.T || st[s].status != 0 || D.level != level) return;
-  __shared__ double sL[TILE];
-  __shared__ double sW[TILE];
-  __shared__ double sdiag;
-  __shared__ int sfail;
+  __shared__ double sA[NB * DIAG_LD];   // working matrix, sA[c * DIAG_LD + r] = A(r, c)
+  __shared__ double sL[NB * DIAG_LD];   // final L, same layout
   TS* tile = A + D.a_off + tile_index(k, k) * TILE;
   const int t = threadIdx.x;
-  const int r = t & 63;
-  const int g = t >> 6;
-  double a[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int c = g + 4 * q;
-    a[q] = (c <= r) ? (double)tile[c * NB + r] : 0.0;
+  for (int e = t; e < TILE; e += DIAG_THREADS) {
+    const int c = e >> 6, r = e & 63;
+    sA[c * DIAG_LD + r] = (r >= c) ? (double)tile[e] : 0.0;
+    sL[c * DIAG_LD + r] = 0.0;
   }
-  if (t == 0) sfail = 0;
-  // owner of (0,0): r == 0, g == 0
-  if (t == 0) {
-    const double v = a[0];
-    if (!(v > 0.0)) sfail = 1;
-    sdiag = sqrt(v);
+  // this thread's lower-triangle positions: linear index e -> (r, c), r >= c
+  int pr[DIAG_PER], pc[DIAG_PER];
+#pragma unroll
+  for (int q = 0; q < DIAG_PER; ++q) {
+    const int e = t + q * DIAG_THREADS;
+    if (e < NB * (NB + 1) / 2) {
+      int r = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+      while (r * (r + 1) / 2 > e) --r;
+      while ((r + 1) * (r + 2) / 2 <= e) ++r;
+      pr[q] = r;
+      pc[q] = e - r * (r + 1) / 2;
+    } else {      // no position: a harmless in-range address, never stored
+      pr[q] = 0;
+      pc[q] = NB;
+    }
   }
   __syncthreads();
+  int fail = 0;
   for (int j = 0; j < NB; ++j) {
-    if (sfail) break;
-    const double ljj = sdiag;
-    if (g == (j & 3)) {
-      const int qj = j >> 2;
-      double l;
-      if (r > j) l = a[qj] / ljj;
-      else if (r == j) l = ljj;
-      else l = 0.0;
-      a[qj] = l;
-      sL[j * NB + r] = l;
+    const double piv = sA[j * DIAG_LD + j];
+    if (!(piv > 0.0)) {
+      fail = j + 1;
+      break;
     }
-    __syncthreads();
-    const double lr = sL[j * NB + r];
+    const double ljj = sqrt(piv);
+    const double inv = 1.0 / ljj;
+    if (t < NB) sL[j * DIAG_LD + t] = (t > j) ? sA[j * DIAG_LD + t] * inv : ((t == j) ? ljj : 0.0);
+    // all loads of this thread's positions first, unconditionally and from
+    // in-range addresses (a predicated load would wait on its own), then the
+    // stores; column j is read-only in step j and the positions are disjoint
+    double vr[DIAG_PER], vc[DIAG_PER], va[DIAG_PER];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int c = g + 4 * q;
-      if (c > j && c <= r) a[q] = fma(-lr, sL[j * NB + c], a[q]);
+    for (int q = 0; q < DIAG_PER; ++q) {
+      const int r = pr[q], c = min(pc[q], NB - 1);
+      vr[q] = sA[j * DIAG_LD + r];
+      vc[q] = sA[j * DIAG_LD + c];
+      va[q] = sA[c * DIAG_LD + r];
     }
-    if (j + 1 < NB && r == j + 1 && g == ((j + 1) & 3)) {
-      const double v = a[(j + 1) >> 2];
-      if (!(v > 0.0)) sfail = j + 2;
-      sdiag = sqrt(v);
+#pragma unroll
+    for (int q = 0; q < DIAG_PER; ++q) {
+      const int r = pr[q], c = pc[q];
+      if (c > j && r >= c) sA[c * DIAG_LD + r] = fma(-(vr[q] * inv), vc[q] * inv, va[q]);
     }
     __syncthreads();
   }
-  if (sfail) {
+  if (fail) {
     if (t == 0) {
       st[s].status = KRR_ENOTSPD;
-      st[s].failed_pivot = k * NB + sfail;
+      st[s].failed_pivot = k * NB + fail;
     }
     return;
   }
-  // L back to the tile (upper part zeroed)
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int c = g + 4 * q;
-    tile[c * NB + r] = (TS)((c <= r) ? a[q] : 0.0);
+  for (int e = t; e < TILE; e += DIAG_THREADS) {
+    const int c = e >> 6, r = e & 63;
+    tile[e] = (TS)sL[c * DIAG_LD + r];
   }
-  // Inverse W = L^-1 by forward substitution, row by row of W:
-  // W(kk,:) /= L(kk,kk), then W(r,:) -= L(r,kk) W(kk,:) for r > kk.
-  double w[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) w[q] = (g + 4 * q == r) ? 1.0 : 0.0;
+  // inverse: sA becomes the working W (identity), sW the final rows
+  double* sW = sA;
+  __syncthreads();
+  for (int e = t; e < TILE; e += DIAG_THREADS) {
+    const int c = e >> 6, r = e & 63;
+    sW[c * DIAG_LD + r] = (r == c) ? 1.0 : 0.0;
+  }
+  __shared__ double sWf[NB * DIAG_LD];
+  __syncthreads();
   for (int kk = 0; kk < NB; ++kk) {
-    if (r == kk) {
-      const double d = sL[kk * NB + kk];
+    const double inv = 1.0 / sL[kk * DIAG_LD + kk];
+    if (t < NB) sWf[t * DIAG_LD + kk] = (t <= kk) ? sW[t * DIAG_LD + kk] * inv : 0.0;   // row kk, column t
+    double vw[DIAG_PER], vl[DIAG_PER], va[DIAG_PER];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int c = g + 4 * q;
-        if (c <= kk) {
-          w[q] = w[q] / d;
-          sW[kk * NB + c] = w[q];
-        }
-      }
+    for (int q = 0; q < DIAG_PER; ++q) {
+      const int r = pr[q], c = min(pc[q], NB - 1);
+      vw[q] = sW[c * DIAG_LD + kk];   // W(kk, c), not written in step kk
+      vl[q] = sL[kk * DIAG_LD + r];
+      va[q] = sW[c * DIAG_LD + r];
+    }
+#pragma unroll
+    for (int q = 0; q < DIAG_PER; ++q) {
+      const int r = pr[q], c = pc[q];
+      if (r > kk && c <= kk) sW[c * DIAG_LD + r] = fma(-vl[q], vw[q] * inv, va[q]);
     }
     __syncthreads();
-    if (r > kk) {
-      const double lrk = sL[kk * NB + r];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int c = g + 4 * q;
-        if (c <= kk) w[q] = fma(-lrk, sW[kk * NB + c], w[q]);
-      }
-    }
   }
   TS* wt = Wt + D.w_off + (int64_t)k * TILE;
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int c = g + 4 * q;
-    wt[c * NB + r] = (TS)((c <= r) ? w[q] : 0.0);
+  for (int e = t; e < TILE; e += DIAG_THREADS) {
+    const int c = e >> 6, r = e & 63;
+    wt[e] = (TS)((r >= c) ? sWf[c * DIAG_LD + r] : 0.0);
   }
 }
 
@@ -373,18 +388,52 @@ void launch_update(krr_ctx ctx, hipStream_t s, bool bf16, int mode, const SysDes
 
 template <typename TS>
 void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, int n_sys, int Tmax, TS* A, TS* Wt,
-              bool bf16, int Wp, int level) {
+              bool bf16, int Wp, int level, const SysDesc* hdesc) {
+  // algorithmic flops of each launch (timing only), from the real sizes m
+  auto each = [&](auto&& f) {
+    double tot = 0.0;
+    if (ctx->timing == 0 || hdesc == nullptr) return 0.0;
+    for (int i = 0; i < n_sys; ++i)
+      if (hdesc[i].level == level) tot += f((double)hdesc[i].m);
+    return tot;
+  };
+  const bool f64 = std::is_same<TS, double>::value;
+  const char* trail_name = bf16 ? "chol_trailing_bf16" : (f64 ? "chol_trailing_f64" : "chol_trailing_f32");
+  const char* col_name = bf16 ? "chol_column_bf16" : (f64 ? "chol_column_f64" : "chol_column_f32");
+  const char* trsm_name = f64 ? "chol_trsm_f64" : "chol_trsm_f32";
   for (int K0 = 0; K0 < Tmax; K0 += Wp) {
     const int K1 = std::min(K0 + Wp, Tmax);
     for (int k = K0; k < K1; ++k) {
-      if (k > K0) launch_update<TS>(ctx, s, bf16, MODE_COL, desc, st, A, Wt, n_sys, Tmax - k, k, k, K0, k, level);
-      hipLaunchKernelGGL((k_potrf_diag<TS>), dim3(n_sys), dim3(256), 0, s, desc, st, A, Wt, k, level);
-      check_launch(ctx, s, "potrf_diag");
-      if (k + 1 < Tmax)
+      if (k > K0) {
+        KernelTimer kt(ctx, s, col_name, each([&](double m) {
+          const double rows = m - k * NB;
+          return rows > 0 ? 2.0 * rows * std::min<double>(NB, rows) * (k - K0) * NB : 0.0;
+        }), 1);
+        launch_update<TS>(ctx, s, bf16, MODE_COL, desc, st, A, Wt, n_sys, Tmax - k, k, k, K0, k, level);
+      }
+      {
+        KernelTimer kt(ctx, s, "chol_diag", each([&](double m) {
+          const double b = std::min<double>(NB, m - k * NB);
+          return b > 0 ? 2.0 * b * b * b / 3.0 : 0.0;
+        }), 0);
+        hipLaunchKernelGGL((k_potrf_diag<TS>), dim3(n_sys), dim3(DIAG_THREADS), 0, s, desc, st, A, Wt, k, level);
+        check_launch(ctx, s, "potrf_diag");
+      }
+      if (k + 1 < Tmax) {
+        KernelTimer kt(ctx, s, trsm_name, each([&](double m) {
+          const double rows = m - (k + 1) * NB;
+          return rows > 0 ? rows * (double)NB * NB : 0.0;
+        }), 1);
         launch_update<TS>(ctx, s, false, MODE_TRSM, desc, st, A, Wt, n_sys, Tmax - k - 1, k + 1, k, 0, 1, level);
+      }
     }
     if (K1 < Tmax) {
       const int64_t R = Tmax - K1;
+      KernelTimer kt(ctx, s, trail_name, each([&](double m) {
+        const double n = m - K1 * NB;
+        const double kk = std::min<double>(K1 * NB, m) - K0 * NB;
+        return n > 0 ? n * (n + 1.0) * kk : 0.0;
+      }), 1);
       launch_update<TS>(ctx, s, bf16, MODE_TRI, desc, st, A, Wt, n_sys, R * (R + 1) / 2, K1, 0, K0, K1, level);
     }
   }
@@ -395,14 +444,15 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
 // Factor, in place, the systems of the batch whose descriptor carries
 // `level` (the others are left untouched).  prec: KRR_PREC_FP64 -> A, Wt are
 // double; FP32 / MIXED -> float.  bf16: BF16 trailing and column updates
-// (MIXED first pass); otherwise FP32 (or FP64) matrix-core updates.
+// (MIXED first pass); otherwise FP32 (or FP64) matrix-core updates.  hdesc:
+// host copy of desc (used for the flop counts of timed launches; nullable).
 void cholesky_factor(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, SysStatus* st, int n_sys, int Tmax,
-                     void* A, void* Wt, int level, bool bf16) {
+                     void* A, void* Wt, int level, bool bf16, const SysDesc* hdesc) {
   const int Wp = ctx->panel_tiles;
   if (prec == KRR_PREC_FP64)
-    factor_t<double>(ctx, s, desc, st, n_sys, Tmax, (double*)A, (double*)Wt, false, Wp, level);
+    factor_t<double>(ctx, s, desc, st, n_sys, Tmax, (double*)A, (double*)Wt, false, Wp, level, hdesc);
   else
-    factor_t<float>(ctx, s, desc, st, n_sys, Tmax, (float*)A, (float*)Wt, bf16, Wp, level);
+    factor_t<float>(ctx, s, desc, st, n_sys, Tmax, (float*)A, (float*)Wt, bf16, Wp, level, hdesc);
 }
 
 }  // namespace krr

@@ -106,6 +106,18 @@ struct krr_model_s {
   size_t bytes = 0;
 };
 
+struct krr_timed_launch {
+  const char* cls;
+  hipEvent_t a, b;
+  double flops;
+};
+
+struct krr_timing_agg {
+  int64_t count = 0;
+  double ms = 0.0;
+  double flops = 0.0;
+};
+
 struct krr_ctx_s {
   int device = 0;
   size_t budget = 0;
@@ -120,6 +132,10 @@ struct krr_ctx_s {
   int sync_check = 0;
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
+  int timing = 0;   // 0 off, 1 matrix-core update kernels, 2 every timed kernel class
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<krr_timed_launch> pending;
+  std::map<std::string, krr_timing_agg> timing_agg;
 };
 
 namespace krr {
@@ -132,6 +148,19 @@ void* model_alloc(krr_ctx ctx, size_t bytes);
 void model_release(krr_ctx ctx, void* p, size_t bytes);
 void* pinned_get(krr_ctx ctx, size_t bytes);
 void check_launch(krr_ctx ctx, hipStream_t s, const char* what);
+
+// HIP events around one launch of kernel class `cls` (only when timing is on;
+// major = 1 marks the matrix-core update kernels), with the launch's
+// algorithmic flop count.  Results are collected by krr_timing_report.
+struct KernelTimer {
+  krr_ctx ctx;
+  hipStream_t s;
+  const char* cls;
+  double flops;
+  hipEvent_t a = nullptr, b = nullptr;
+  KernelTimer(krr_ctx c, hipStream_t st, const char* name, double f, int major);
+  ~KernelTimer();
+};
 
 // ---- partition.hip ----
 void assign_nearest(krr_ctx ctx, hipStream_t s, const void* X, int dtype, int64_t n, int d,

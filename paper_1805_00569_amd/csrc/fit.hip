@@ -11,7 +11,7 @@
 namespace krr {
 
 void cholesky_factor(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, SysStatus* st, int n_sys, int Tmax,
-                     void* A, void* Wt, int level, bool bf16);
+                     void* A, void* Wt, int level, bool bf16, const SysDesc* hdesc);
 void trsv_forward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, const SysStatus* st, int n_sys,
                   const void* A, const void* Wt, const double* b, double* z, int skip_converged);
 void trsv_backward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, const SysStatus* st, int n_sys,
@@ -70,15 +70,22 @@ __global__ __launch_bounds__(256) void k_form(const TX* __restrict__ Xg, int d, 
   for (int k0 = 0; k0 < d; k0 += KC) {
     const int kc = min(KC, d - k0);
     __syncthreads();
-    for (int e = t; e < NB * KC; e += 256) {
+    // unconditional loads from clamped addresses, then select and store
+    TX li[NB * KC / 256], lj[NB * KC / 256];
+#pragma unroll
+    for (int u = 0; u < NB * KC / 256; ++u) {
+      const int e = t + u * 256;
+      const int row = e / KC, kk = min(e - row * KC, kc - 1);
+      li[u] = Xi[(int64_t)min(row, rows_i - 1) * d + k0 + kk];
+      lj[u] = Xj[(int64_t)min(row, rows_j - 1) * d + k0 + kk];
+    }
+#pragma unroll
+    for (int u = 0; u < NB * KC / 256; ++u) {
+      const int e = t + u * 256;
       const int row = e / KC, kk = e - row * KC;
-      double vi = 0.0, vj = 0.0;
-      if (kk < kc) {
-        if (row < rows_i) vi = (double)Xi[(int64_t)row * d + k0 + kk];
-        if (row < rows_j) vj = (double)Xj[(int64_t)row * d + k0 + kk];
-      }
-      sXi[kk * LDX + row] = vi;
-      sXj[kk * LDX + row] = vj;
+      const bool ok = kk < kc;
+      sXi[kk * LDX + row] = (ok && row < rows_i) ? (double)li[u] : 0.0;
+      sXj[kk * LDX + row] = (ok && row < rows_j) ? (double)lj[u] : 0.0;
     }
     __syncthreads();
     if (t < NB) {
@@ -207,6 +214,7 @@ void launch_form(krr_ctx ctx, hipStream_t s, int prec, const void* Xg, int d, co
   if (ntri == 0) return;
   const dim3 grid((unsigned)ntri, (unsigned)p);
   const TX* X = (const TX*)Xg;
+  KernelTimer kt(ctx, s, "form_kernel", 0.0, 0);
   if (prec == KRR_PREC_FP64)
     hipLaunchKernelGGL((k_form<TX, 0>), grid, dim3(256), 0, s, X, d, desc, p, n_params, A, K64);
   else if (prec == KRR_PREC_FP32)
@@ -350,7 +358,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
   };
   if (!ctx->serial_fit) {
     form(d_desc, p, n_params, Tmax);
-    cholesky_factor(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, 0, mixed);
+    cholesky_factor(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, 0, mixed, desc.data());
     trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, rhs, zb, 0);
     trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, zb, alpha, nullptr, 0);
   } else {
@@ -359,7 +367,8 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
     for (int sidx = 0; sidx < n_sys; ++sidx) {
       if (desc[sidx].T == 0) continue;
       form(d_desc + sidx, 1, 1, desc[sidx].T);
-      cholesky_factor(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, desc[sidx].T, A, Wt, 0, mixed);
+      cholesky_factor(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, desc[sidx].T, A, Wt, 0, mixed,
+                      desc.data() + sidx);
       trsv_forward(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, A, Wt, rhs, zb, 0);
       trsv_backward(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, A, Wt, zb, alpha, nullptr, 0);
     }
@@ -408,7 +417,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
       hipLaunchKernelGGL(k_restore_tiles, dim3((unsigned)tri(Tmax), (unsigned)n_sys), dim3(256), 0, s,
                          (const SysDesc*)d_desc, (const double*)K64, (float*)A, 1);
       check_launch(ctx, s, "restore_tiles");
-      cholesky_factor(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, 1, false);
+      cholesky_factor(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, 1, false, desc.data());
       trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, rhs, zb, 1);
       trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, zb, alpha, nullptr, 1);
       refine();

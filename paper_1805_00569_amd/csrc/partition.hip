@@ -60,10 +60,20 @@ __global__ __launch_bounds__(256) void k_assign(const TX* __restrict__ X, int64_
   const int rows = (int)min((int64_t)R, n - row0);
   const TX* src = X + row0 * d;
   const int tot = rows * d;
-  for (int e = threadIdx.x; e < tot; e += R) {
-    const int r = e / d;
-    const int k = e - r * d;
-    sX[k * ld + r] = src[e];
+  // batches of 8 unconditional loads from clamped addresses, then the stores
+  for (int e0 = threadIdx.x; e0 < tot; e0 += 8 * R) {
+    TX v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src[min(e0 + u * R, tot - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * R;
+      if (e < tot) {
+        const int r = e / d;
+        const int k = e - r * d;
+        sX[k * ld + r] = v[u];
+      }
+    }
   }
   __syncthreads();
   const int r = threadIdx.x;
@@ -236,39 +246,91 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_group_scatter(const int32_t* __
 
 // ---------------------------------------------------------------------------
 // Means of the grouped members: C[j][f] = (sum of member values in increasing
-// point order, FP64) / count_j.  Empty partitions keep their centre.  If
-// `done_out` is given, it is set when the change count `delta` was zero
-// (Lloyd has reached a fixed point; later passes are skipped).
+// point order, FP64) / count_j.  Empty partitions keep their centre.
+// The members are first gathered into contiguous rows (Xg = X[perm], one
+// parallel pass); the mean kernel then streams a partition's rows in chunks
+// through LDS, loading chunk c+1 while it sums chunk c, so the sequential
+// FP64 sums never wait on memory.
+// Lloyd passes: `skip` is this pass's "fixed point reached" flag; block 0
+// writes the next pass's flag (set when this pass was skipped or changed no
+// assignment), so no block of a launch reads a flag that the launch writes.
 // ---------------------------------------------------------------------------
+constexpr int MEANS_THREADS = 256;
+constexpr int MEANS_LPT = 16;                               // staged values per thread and chunk
+constexpr int MEANS_CHUNK = MEANS_THREADS * MEANS_LPT;      // values per chunk
+
 template <typename TX>
-__global__ __launch_bounds__(128) void k_means(const TX* __restrict__ X, int d, const int32_t* __restrict__ perm,
-                                               const int64_t* __restrict__ offsets, double* __restrict__ C,
-                                               const int32_t* __restrict__ skip,
-                                               const int32_t* __restrict__ delta,
-                                               int32_t* __restrict__ done_out) {
+__global__ void k_gather_grouped(const TX* __restrict__ X, int64_t n, int d, const int32_t* __restrict__ perm,
+                                 TX* __restrict__ Xg, const int32_t* __restrict__ skip) {
   if (skip != nullptr && *skip) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * d) return;
+  const int64_t r = e / d;
+  Xg[e] = X[(int64_t)perm[r] * d + (e - r * d)];
+}
+
+template <typename TX>
+__global__ __launch_bounds__(MEANS_THREADS) void k_means(const TX* __restrict__ Xg, int d,
+                                                         const int64_t* __restrict__ offsets, double* __restrict__ C,
+                                                         const int32_t* __restrict__ skip,
+                                                         const int32_t* __restrict__ delta,
+                                                         int32_t* __restrict__ done_next) {
+  const int skipped = (skip != nullptr) ? *skip : 0;
+  if (done_next != nullptr && blockIdx.x == 0 && threadIdx.x == 0)
+    *done_next = (skipped || *delta == 0) ? 1 : 0;
+  if (skipped) return;
+  __shared__ double sv[MEANS_CHUNK];
   const int j = blockIdx.x;
   const int64_t o0 = offsets[j], o1 = offsets[j + 1];
   const int64_t cnt = o1 - o0;
-  if (cnt > 0) {
-    for (int f = threadIdx.x; f < d; f += blockDim.x) {
-      double s = 0.0;
-      int64_t o = o0;
-      for (; o + 8 <= o1; o += 8) {
-        int32_t id[8];
-        double v[8];
+  if (cnt == 0) return;
+  const int t = threadIdx.x;
+  const int rows = max(1, MEANS_CHUNK / d);            // members per chunk (whole rows)
+  const int64_t vals = cnt * d;                        // contiguous values of this partition
+  const TX* base = Xg + o0 * d;
+  const int64_t per = (int64_t)rows * d;
+  // features handled by this thread: f = t, t + 256, ...
+  constexpr int FMAX = MEANS_CHUNK / MEANS_THREADS;    // d <= 4096
+  double s[FMAX];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) id[q] = perm[o + q];
+  for (int u = 0; u < FMAX; ++u) s[u] = 0.0;
+  // loads are unconditional from clamped addresses (a predicated load would
+  // wait on its own), the value is selected afterwards
+  double nxt[MEANS_LPT];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = (double)X[(int64_t)id[q] * d + f];
+  for (int u = 0; u < MEANS_LPT; ++u) {
+    const int64_t e = t + (int64_t)u * MEANS_THREADS;
+    const double v = (double)base[min(e, vals - 1)];
+    nxt[u] = (e < min(per, vals)) ? v : 0.0;
+  }
+  for (int64_t c0 = 0; c0 < vals; c0 += per) {
+    const int64_t cl = min(per, vals - c0);
+    __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 8; ++q) s = __dadd_rn(s, v[q]);
+    for (int u = 0; u < MEANS_LPT; ++u) sv[t + u * MEANS_THREADS] = nxt[u];
+    __syncthreads();
+    // prefetch the next chunk, then sum this one in member order
+    const int64_t c1 = c0 + per;
+#pragma unroll
+    for (int u = 0; u < MEANS_LPT; ++u) {
+      const int64_t e = t + (int64_t)u * MEANS_THREADS;
+      const double v = (double)base[min(c1 + e, vals - 1)];
+      nxt[u] = (c1 + e < vals && e < per) ? v : 0.0;
+    }
+    const int nr = (int)(cl / d);
+    for (int q = 0; q < nr; ++q) {
+#pragma unroll
+      for (int u = 0; u < FMAX; ++u) {
+        const int f = min(t + u * MEANS_THREADS, d - 1);   // lanes past d compute a discarded copy
+        s[u] = __dadd_rn(s[u], sv[q * d + f]);
       }
-      for (; o < o1; ++o) s = __dadd_rn(s, (double)X[(int64_t)perm[o] * d + f]);
-      C[(int64_t)j * d + f] = __ddiv_rn(s, (double)cnt);
     }
   }
-  if (done_out != nullptr && j == 0 && threadIdx.x == 0 && *delta == 0) *done_out = 1;
+#pragma unroll
+  for (int u = 0; u < FMAX; ++u) {
+    const int f = t + u * MEANS_THREADS;
+    if (f < d) C[(int64_t)j * d + f] = __ddiv_rn(s[u], (double)cnt);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -412,13 +474,16 @@ __global__ __launch_bounds__(64) void k_kbalance(const double* __restrict__ D, c
     cs[j] = 0;
     hist[j] = 0;
   }
-  __syncthreads();
+  __builtin_amdgcn_wave_barrier();
+  int next_a = (lane < n) ? a0[lane] : 0;
   for (int64_t c0 = 0; c0 < n; c0 += 64) {
     const int64_t i = c0 + lane;
     const bool valid = i < n;
+    const int cur_a = next_a;
+    if (c0 + 64 + lane < n) next_a = a0[c0 + 64 + lane];   // prefetch the next chunk
     int bj = -1;
     if (valid) {
-      bj = a0[i];
+      bj = cur_a;
       if (cs[bj] >= cap) {  // nearest centre already full: search the open ones
         double bd = INFINITY;
         bj = -1;
@@ -435,22 +500,22 @@ __global__ __launch_bounds__(64) void k_kbalance(const double* __restrict__ D, c
       }
       atomicAdd(&hist[bj], 1);
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
     bool ok = true;
     for (int j = lane; j < p; j += 64)
       if ((int64_t)cs[j] + hist[j] > cap) ok = false;
     ok = __all(ok);
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
     if (ok) {
       if (valid) MB[i] = bj;
       for (int j = lane; j < p; j += 64) {
         cs[j] += hist[j];
         hist[j] = 0;
       }
-      __syncthreads();
+      __builtin_amdgcn_wave_barrier();
     } else {
       for (int j = lane; j < p; j += 64) hist[j] = 0;
-      __syncthreads();
+      __builtin_amdgcn_wave_barrier();
       const int cnt = (int)min((int64_t)64, n - c0);
       for (int l = 0; l < cnt; ++l) {
         const int64_t ii = c0 + l;
@@ -471,7 +536,7 @@ __global__ __launch_bounds__(64) void k_kbalance(const double* __restrict__ D, c
           MB[ii] = jj;
           cs[jj] += 1;
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
       }
     }
   }
@@ -526,6 +591,7 @@ void assign_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, const d
   while (R > 64 && (size_t)d * (R + 1) * sizeof(TX) > 96 * 1024) R /= 2;
   const size_t lds = (size_t)d * (R + 1) * sizeof(TX);
   const int64_t nblk = ceil_div(n, R);
+  KernelTimer kt(ctx, s, "assign", 0.0, 0);
   if (lds <= 96 * 1024) {
     if (all)
       hipLaunchKernelGGL((k_assign<TX, 1>), dim3(nblk), dim3(R), lds, s, X, n, d, CT, p, out, D, prev,
@@ -545,10 +611,39 @@ void assign_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, const d
   check_launch(ctx, s, "assign");
 }
 
+// Wide rows (d > MEANS_CHUNK): one thread per (partition, feature).
 template <typename TX>
-void means_t(krr_ctx ctx, hipStream_t s, const TX* X, int d, const int32_t* perm, const int64_t* offsets,
-             double* C, int p, const int32_t* skip, const int32_t* delta, int32_t* done) {
-  hipLaunchKernelGGL((k_means<TX>), dim3(p), dim3(128), 0, s, X, d, perm, offsets, C, skip, delta, done);
+__global__ void k_means_wide(const TX* __restrict__ Xg, int d, const int64_t* __restrict__ offsets,
+                             double* __restrict__ C, const int32_t* __restrict__ skip,
+                             const int32_t* __restrict__ delta, int32_t* __restrict__ done_next) {
+  const int skipped = (skip != nullptr) ? *skip : 0;
+  if (done_next != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+    *done_next = (skipped || *delta == 0) ? 1 : 0;
+  if (skipped) return;
+  const int j = blockIdx.y;
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= d) return;
+  const int64_t o0 = offsets[j], o1 = offsets[j + 1];
+  if (o1 == o0) return;
+  double acc = 0.0;
+  for (int64_t o = o0; o < o1; ++o) acc = __dadd_rn(acc, (double)Xg[o * d + f]);
+  C[(int64_t)j * d + f] = __ddiv_rn(acc, (double)(o1 - o0));
+}
+
+template <typename TX>
+void means_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, const int32_t* perm, const int64_t* offsets,
+             double* C, int p, const int32_t* skip, const int32_t* delta, int32_t* done_next) {
+  KernelTimer kt(ctx, s, "lloyd_means", 0.0, 0);
+  TX* Xg = (TX*)ws_get(ctx, "means_xg", (size_t)n * d * sizeof(TX));
+  hipLaunchKernelGGL((k_gather_grouped<TX>), dim3((unsigned)ceil_div(n * d, 256)), dim3(256), 0, s, X, n, d, perm,
+                     Xg, skip);
+  check_launch(ctx, s, "gather_grouped");
+  if (d <= MEANS_CHUNK)
+    hipLaunchKernelGGL((k_means<TX>), dim3((unsigned)p), dim3(MEANS_THREADS), 0, s, (const TX*)Xg, d, offsets, C,
+                       skip, delta, done_next);
+  else
+    hipLaunchKernelGGL((k_means_wide<TX>), dim3((unsigned)ceil_div(d, 256), (unsigned)p), dim3(256), 0, s,
+                       (const TX*)Xg, d, offsets, C, skip, delta, done_next);
   check_launch(ctx, s, "means");
 }
 
@@ -562,6 +657,7 @@ void kmeanspp_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, int k
   double* Tb = P + n;
   double* Ob = Tb + nblk;
   int64_t* cidx = (int64_t*)(Ob + nblk + 8);
+  KernelTimer kt(ctx, s, "kmeanspp", 0.0, 0);
   SplitMix64 g{seed};
   std::vector<double> u(k);
   for (int t = 0; t < k; ++t) u[t] = g.uniform();
@@ -600,6 +696,7 @@ void assign_nearest(krr_ctx ctx, hipStream_t s, const void* X, int dtype, int64_
 void group_by_key(krr_ctx ctx, hipStream_t s, const int32_t* key, int64_t n, int p, int32_t* perm,
                   int64_t* offsets, int64_t* sizes64, const int32_t* skip) {
   const int64_t nblk = ceil_div(n, GROUP_BLOCK);
+  KernelTimer kt(ctx, s, "group", 0.0, 0);
   char* w = (char*)ws_get(ctx, "group", (size_t)n * 4 + (size_t)nblk * p * 8 + 64);
   int32_t* rank = (int32_t*)w;
   int32_t* bc = rank + n;
@@ -638,21 +735,22 @@ static void partition_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int 
   } else {
     // K-means: k-means++ seeding then Lloyd passes (Algorithm 2).
     kmeanspp_t(ctx, s, X, n, d, p, seed, C);
-    char* w = (char*)ws_get(ctx, "lloyd", (size_t)n * 8 + (size_t)(p + 1) * 8 + (size_t)(iters + 2) * 4 + 64);
+    char* w = (char*)ws_get(ctx, "lloyd", (size_t)n * 8 + (size_t)(p + 1) * 8 + (size_t)(2 * iters + 4) * 4 + 64);
     int32_t* perm = (int32_t*)w;
     int32_t* prev = perm + n;
     int64_t* off = (int64_t*)(prev + n + (n & 1));
     int32_t* deltas = (int32_t*)(off + p + 1);
-    int32_t* done = deltas + iters + 1;
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, deltas, (int64_t)(iters + 2), 0);
+    int32_t* done = deltas + iters + 1;   // done[it]: pass `it` is past the fixed point
+    const int64_t nflags = 2 * (int64_t)iters + 3;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)ceil_div(nflags, 64)), dim3(64), 0, s, deltas, nflags, 0);
     check_launch(ctx, s, "fill");
     int32_t* cur = assign;
     int32_t* old = prev;
     for (int it = 0; it < iters; ++it) {
       transpose_centroids(ctx, s, C, p, d, CT);
-      assign_t(ctx, s, X, n, d, CT, p, cur, nullptr, it == 0 ? nullptr : old, deltas + it, done, false);
-      group_by_key(ctx, s, cur, n, p, perm, off, nullptr, done);
-      means_t(ctx, s, X, d, perm, off, C, p, done, deltas + it, done);
+      assign_t(ctx, s, X, n, d, CT, p, cur, nullptr, it == 0 ? nullptr : old, deltas + it, done + it, false);
+      group_by_key(ctx, s, cur, n, p, perm, off, nullptr, done + it);
+      means_t(ctx, s, X, n, d, perm, off, C, p, done + it, deltas + it, done + it + 1);
       std::swap(cur, old);
     }
     transpose_centroids(ctx, s, C, p, d, CT);
@@ -665,11 +763,12 @@ static void partition_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int 
       const int32_t* a0 = assign;  // unconstrained nearest centres
       int32_t* MB = prev;
       const int64_t cap = ceil_div(n, p);
+      KernelTimer kt(ctx, s, "kbalance_greedy", 0.0, 0);
       hipLaunchKernelGGL(k_kbalance, dim3(1), dim3(64), (size_t)p * 8, s, (const double*)D, a0, n, p, cap, MB);
       check_launch(ctx, s, "kbalance");
       KRR_HIP(hipMemcpyAsync(assign, MB, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
       group_by_key(ctx, s, assign, n, p, perm, off, nullptr, nullptr);
-      means_t(ctx, s, X, d, perm, off, C, p, nullptr, nullptr, nullptr);
+      means_t(ctx, s, X, n, d, perm, off, C, p, nullptr, nullptr, nullptr);
     }
   }
   // sizes: histogram of the final assignment

@@ -3,14 +3,19 @@
 //
 // NEAREST: each test point is assigned to its nearest centre with the exact
 // FP64 assignment kernel (the "MyCluster" step of Algorithm 5), the points
-// are grouped by partition, and every 64-point group is predicted by the
-// fused kernel below against its partition's training points only.
-// ALL / AVERAGE: every 64-point group is predicted by every partition model.
+// are grouped by partition, and every 64-point group is predicted against its
+// partition's training points only.  ALL / AVERAGE: every 64-point group is
+// predicted by every partition model.
 //
-// The fused kernel computes, for 64 test points against chunks of 64
-// training points, the Gram block on FP64 matrix cores, turns it into kernel
-// values and contracts them with alpha, so the k x m kernel matrix is never
-// stored.  Every sum has a fixed order (results do not depend on the batch).
+// The fused kernel takes 64 test points against 64-point chunks of one
+// partition's training points: the Gram block on FP64 matrix cores, then the
+// kernel values and their contraction with alpha, so the k x m kernel matrix
+// is never stored.  The Gram block does not depend on (sigma, lambda): the
+// models fitted together on one partitioning (up to MAXM per launch) share it
+// and only redo the exponential and the dot product.  The training chunks of
+// a partition are split over `nsplit` workgroups that write partial sums;
+// a second kernel adds the splits in a fixed order, so every result is
+// independent of the launch shape and of the batch.
 #include "common.hpp"
 
 namespace krr {
@@ -20,6 +25,16 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int KC = 32;
 constexpr int LDX = NB + 1;
+constexpr int MAXM = 8;
+
+struct PredModels {
+  const double* alpha[MAXM];
+  const int64_t* voff[MAXM];
+  double neg_inv_2s2[MAXM];
+  double* out[MAXM];
+  int nm;
+  int kernel;
+};
 
 template <typename TX>
 __global__ __launch_bounds__(256) void k_predict(const TX* __restrict__ Xt, int d, int64_t k,
@@ -27,32 +42,32 @@ __global__ __launch_bounds__(256) void k_predict(const TX* __restrict__ Xt, int 
                                                  const int64_t* __restrict__ toff,
                                                  const int32_t* __restrict__ tile_start, int route,
                                                  const TX* __restrict__ Xg, const int64_t* __restrict__ xoff,
-                                                 const double* __restrict__ alpha, const int64_t* __restrict__ voff,
-                                                 double neg_inv_2s2, int kernel, int p, double* __restrict__ out) {
-  int j, tt;
+                                                 const PredModels M, int p, int cps, int64_t npos,
+                                                 double* __restrict__ part_out) {
+  int j;
   int64_t t0, tcnt;
+  const int split = blockIdx.z;
   if (route == KRR_ROUTE_NEAREST) {
     const int b = blockIdx.x;
     if (b >= tile_start[p]) return;
-    int lo = 0, hi = p;  // find j with tile_start[j] <= b < tile_start[j+1]
+    int lo = 0, hi = p;  // tile_start[lo] <= b < tile_start[lo + 1]
     while (hi - lo > 1) {
       const int mid = (lo + hi) / 2;
       if (tile_start[mid] <= b) lo = mid;
       else hi = mid;
     }
     j = lo;
-    tt = b - tile_start[j];
-    t0 = toff[j] + (int64_t)tt * NB;
+    t0 = toff[j] + (int64_t)(b - tile_start[j]) * NB;
     tcnt = min((int64_t)NB, toff[j + 1] - t0);
   } else {
     j = blockIdx.y;
-    tt = blockIdx.x;
-    t0 = (int64_t)tt * NB;
+    t0 = (int64_t)blockIdx.x * NB;
     tcnt = min((int64_t)NB, k - t0);
   }
   const int64_t x0 = xoff[j];
   const int64_t m = xoff[j + 1] - x0;
-  const double* al = alpha + voff[j];
+  const int64_t xbeg = (int64_t)split * cps * NB;
+  const int64_t xend = min(m, xbeg + (int64_t)cps * NB);
   __shared__ double sT[KC * LDX];
   __shared__ double sX[KC * LDX];
   __shared__ double sNt[NB], sNx[NB];
@@ -64,10 +79,25 @@ __global__ __launch_bounds__(256) void k_predict(const TX* __restrict__ Xt, int 
     if (t < tcnt) src = (route == KRR_ROUTE_NEAREST) ? (int64_t)tperm[t0 + t] : t0 + t;
     srow[t] = src;
   }
+  // test-point norms
+  if (t < NB) {
+    double nrm = 0.0;
+    const int64_t sr = (t < tcnt) ? ((route == KRR_ROUTE_NEAREST) ? (int64_t)tperm[t0 + t] : t0 + t) : -1;
+    if (sr >= 0)
+      for (int kk = 0; kk < d; ++kk) {
+        const double v = (double)Xt[sr * d + kk];
+        nrm = fma(v, v, nrm);
+      }
+    sNt[t] = nrm;
+  }
   __syncthreads();
-  double part = 0.0;
-  for (int64_t xc = 0; xc < m; xc += NB) {
-    const int64_t xcnt = min((int64_t)NB, m - xc);
+  const int tl = 16 * w + il;
+  const double nt = sNt[tl];
+  double part[MAXM];
+#pragma unroll
+  for (int q = 0; q < MAXM; ++q) part[q] = 0.0;
+  for (int64_t xc = xbeg; xc < xend; xc += NB) {
+    const int64_t xcnt = min((int64_t)NB, xend - xc);
     d4 acc[4];
 #pragma unroll
     for (int xb = 0; xb < 4; ++xb) acc[xb] = d4{0.0, 0.0, 0.0, 0.0};
@@ -75,23 +105,27 @@ __global__ __launch_bounds__(256) void k_predict(const TX* __restrict__ Xt, int 
     for (int k0 = 0; k0 < d; k0 += KC) {
       const int kc = min(KC, d - k0);
       __syncthreads();
-      for (int e = t; e < NB * KC; e += 256) {
+      // unconditional loads from clamped addresses, then select and store
+      TX lt[NB * KC / 256], lx[NB * KC / 256];
+#pragma unroll
+      for (int u = 0; u < NB * KC / 256; ++u) {
+        const int e = t + u * 256;
+        const int row = e / KC, kk = min(e - row * KC, kc - 1);
+        const int64_t sr = srow[row];
+        lt[u] = Xt[max(sr, (int64_t)0) * d + k0 + kk];
+        lx[u] = Xg[(x0 + xc + min((int64_t)row, xcnt - 1)) * d + k0 + kk];
+      }
+#pragma unroll
+      for (int u = 0; u < NB * KC / 256; ++u) {
+        const int e = t + u * 256;
         const int row = e / KC, kk = e - row * KC;
-        double vt = 0.0, vx = 0.0;
-        if (kk < kc) {
-          const int64_t sr = srow[row];
-          if (sr >= 0) vt = (double)Xt[sr * d + k0 + kk];
-          if (row < xcnt) vx = (double)Xg[(x0 + xc + row) * d + k0 + kk];
-        }
-        sT[kk * LDX + row] = vt;
-        sX[kk * LDX + row] = vx;
+        const bool ok = kk < kc;
+        sT[kk * LDX + row] = (ok && srow[row] >= 0) ? (double)lt[u] : 0.0;
+        sX[kk * LDX + row] = (ok && row < xcnt) ? (double)lx[u] : 0.0;
       }
       __syncthreads();
-      if (t < NB) {
+      if (t < NB)
         for (int kk = 0; kk < kc; ++kk) nrm = fma(sX[kk * LDX + t], sX[kk * LDX + t], nrm);
-      } else if (t < 2 * NB && xc == 0) {
-        for (int kk = 0; kk < kc; ++kk) nrm = fma(sT[kk * LDX + t - NB], sT[kk * LDX + t - NB], nrm);
-      }
       for (int kb = 0; kb < kc; kb += 4) {
         const int ko = (kb + kl) * LDX;
         const double bt = sT[ko + 16 * w + il];
@@ -101,32 +135,51 @@ __global__ __launch_bounds__(256) void k_predict(const TX* __restrict__ Xt, int 
       }
     }
     if (t < NB) sNx[t] = nrm;
-    else if (t < 2 * NB && xc == 0) sNt[t - NB] = nrm;
     __syncthreads();
-    const int tl = 16 * w + il;
-    const double nt = sNt[tl];
 #pragma unroll
     for (int xb = 0; xb < 4; ++xb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int xl = 16 * xb + kl + 4 * v;
+        const int xl = 16 * xb + kl + 4 * v;   // FP64 MFMA result row of register v
         if (xl < xcnt) {
           const double G = acc[xb][v];
-          double kv;
-          if (kernel == KRR_KERNEL_GAUSSIAN) kv = exp(fmax(0.0, (nt + sNx[xl]) - 2.0 * G) * neg_inv_2s2);
-          else kv = G;
-          part = fma(al[xc + xl], kv, part);
+          const double d2 = fmax(0.0, (nt + sNx[xl]) - 2.0 * G);
+#pragma unroll
+          for (int q = 0; q < MAXM; ++q) {
+            if (q < M.nm) {
+              const double kv = (M.kernel == KRR_KERNEL_GAUSSIAN) ? exp(d2 * M.neg_inv_2s2[q]) : G;
+              part[q] = fma(M.alpha[q][M.voff[q][j] + xc + xl], kv, part[q]);
+            }
+          }
         }
       }
   }
   // lanes il, il+16, il+32, il+48 hold partial sums of the same test point
-  part += __shfl_xor(part, 16, 64);
-  part += __shfl_xor(part, 32, 64);
-  const int tl = 16 * w + il;
-  if (kl == 0 && tl < tcnt) {
-    if (route == KRR_ROUTE_NEAREST) out[srow[tl]] = part;
-    else out[(t0 + tl) * p + j] = part;
+#pragma unroll
+  for (int q = 0; q < MAXM; ++q) {
+    part[q] += __shfl_xor(part[q], 16, 64);
+    part[q] += __shfl_xor(part[q], 32, 64);
   }
+  if (kl == 0 && tl < tcnt) {
+    const int64_t pos = (route == KRR_ROUTE_NEAREST) ? (t0 + tl) : ((t0 + tl) * p + j);
+#pragma unroll
+    for (int q = 0; q < MAXM; ++q)
+      if (q < M.nm) part_out[((int64_t)split * npos + pos) * M.nm + q] = part[q];
+  }
+}
+
+// Sum the splits in order; NEAREST positions are scattered back to the
+// caller's point order.
+__global__ void k_predict_reduce(const double* __restrict__ part, int nsplit, int64_t npos, const PredModels M,
+                                 const int32_t* __restrict__ tperm) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= npos * M.nm) return;
+  const int64_t pos = e / M.nm;
+  const int q = (int)(e - pos * M.nm);
+  double s = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) s += part[((int64_t)sp * npos + pos) * M.nm + q];
+  const int64_t dst = (tperm != nullptr) ? (int64_t)tperm[pos] : pos;
+  M.out[q][dst] = s;
 }
 
 __global__ void k_tile_prefix(const int64_t* __restrict__ toff, int p, int32_t* __restrict__ tile_start) {
@@ -190,15 +243,15 @@ __global__ void k_best(const double* __restrict__ mse, int n, int32_t* __restric
 }
 
 struct Routing {
-  int32_t* route;
-  int32_t* tperm;
-  int64_t* toff;
-  int32_t* tile_start;
+  int32_t* route = nullptr;
+  int32_t* tperm = nullptr;
+  int64_t* toff = nullptr;
+  int32_t* tile_start = nullptr;
 };
 
-Routing route_points(krr_ctx ctx, hipStream_t s, krr_model model, const void* Xt, int dtype, int64_t k,
+Routing route_points(krr_ctx ctx, hipStream_t s, const krr_part_data& D, const void* Xt, int dtype, int64_t k,
                      const std::string& tag) {
-  const int p = model->data->p;
+  const int p = D.p;
   const size_t kb = ((size_t)k * 4 + 255) & ~size_t(255);
   char* w = (char*)ws_get(ctx, "route" + tag, 2 * kb + (size_t)(p + 1) * 8 + (size_t)(p + 1) * 4 + 512);
   Routing R;
@@ -206,47 +259,75 @@ Routing route_points(krr_ctx ctx, hipStream_t s, krr_model model, const void* Xt
   R.tperm = (int32_t*)(w + kb);
   R.toff = (int64_t*)(w + 2 * kb);
   R.tile_start = (int32_t*)(w + 2 * kb + (((size_t)(p + 1) * 8 + 255) & ~size_t(255)));
-  assign_nearest(ctx, s, Xt, dtype, k, model->data->d, model->data->ct_t, p, R.route, nullptr, nullptr, nullptr);
+  assign_nearest(ctx, s, Xt, dtype, k, D.d, D.ct_t, p, R.route, nullptr, nullptr, nullptr);
   group_by_key(ctx, s, R.route, k, p, R.tperm, R.toff, nullptr, nullptr);
   hipLaunchKernelGGL(k_tile_prefix, dim3(1), dim3(64), 0, s, (const int64_t*)R.toff, p, R.tile_start);
   check_launch(ctx, s, "tile_prefix");
   return R;
 }
 
-template <typename TX>
-void predict_launch(krr_ctx ctx, hipStream_t s, krr_model model, const TX* Xt, int64_t k, int route,
-                    const Routing* R, double* out) {
-  const krr_part_data& D = *model->data;
-  const double neg = -1.0 / (2.0 * model->params.sigma * model->params.sigma);
+// Predict with nm (<= MAXM) models that share one partitioning.  `dst[q]`
+// receives k values (NEAREST) or the k x p matrix (ALL) of model q.
+void predict_group(krr_ctx ctx, hipStream_t s, const krr_model* models, int nm, const void* Xt, int dtype, int64_t k,
+                   int route, const Routing& R, double* const* dst) {
+  const krr_part_data& D = *models[0]->data;
+  KRR_REQUIRE(dtype == D.dtype, "test inputs must have the dtype of the training inputs");
   const int p = D.p;
-  if (route == KRR_ROUTE_NEAREST) {
-    const unsigned nblk = (unsigned)(ceil_div(k, NB) + p);
-    hipLaunchKernelGGL((k_predict<TX>), dim3(nblk), dim3(256), 0, s, Xt, D.d, k, (const int32_t*)R->tperm,
-                       (const int64_t*)R->toff, (const int32_t*)R->tile_start, route, (const TX*)D.X,
-                       (const int64_t*)D.d_offsets, (const double*)model->alpha, (const int64_t*)model->d_voff, neg,
-                       model->params.kernel, p, out);
-  } else {
-    hipLaunchKernelGGL((k_predict<TX>), dim3((unsigned)ceil_div(k, NB), (unsigned)p), dim3(256), 0, s, Xt, D.d, k,
-                       nullptr, nullptr, nullptr, KRR_ROUTE_ALL, (const TX*)D.X, (const int64_t*)D.d_offsets,
-                       (const double*)model->alpha, (const int64_t*)model->d_voff, neg, model->params.kernel, p,
-                       out);
+  PredModels M{};
+  M.nm = nm;
+  M.kernel = models[0]->params.kernel;
+  for (int q = 0; q < nm; ++q) {
+    M.alpha[q] = models[q]->alpha;
+    M.voff[q] = models[q]->d_voff;
+    M.neg_inv_2s2[q] = -1.0 / (2.0 * models[q]->params.sigma * models[q]->params.sigma);
+    M.out[q] = dst[q];
+    KRR_REQUIRE(models[q]->params.kernel == M.kernel, "models of one call must share the kernel");
   }
-  check_launch(ctx, s, "predict");
+  int64_t max_m = 0;
+  for (int j = 0; j < p; ++j) max_m = std::max(max_m, D.offsets[j + 1] - D.offsets[j]);
+  const int64_t chunks = std::max<int64_t>(1, ceil_div(max_m, NB));
+  const int64_t base = (route == KRR_ROUTE_NEAREST) ? ceil_div(k, NB) + p : ceil_div(k, NB) * p;
+  const int64_t nsplit = std::max<int64_t>(1, std::min<int64_t>(chunks, 2048 / std::max<int64_t>(base, 1)));
+  const int cps = (int)ceil_div(chunks, nsplit);
+  const int64_t npos = (route == KRR_ROUTE_NEAREST) ? k : k * p;
+  double* part = (double*)ws_get(ctx, "pred_part", (size_t)nsplit * npos * nm * 8);
+  {
+    KernelTimer kt(ctx, s, "predict", 0.0, 0);
+    const dim3 grid = (route == KRR_ROUTE_NEAREST) ? dim3((unsigned)base, 1, (unsigned)nsplit)
+                                                   : dim3((unsigned)ceil_div(k, NB), (unsigned)p, (unsigned)nsplit);
+    if (dtype == KRR_F64)
+      hipLaunchKernelGGL((k_predict<double>), grid, dim3(256), 0, s, (const double*)Xt, D.d, k,
+                         (const int32_t*)R.tperm, (const int64_t*)R.toff, (const int32_t*)R.tile_start,
+                         route == KRR_ROUTE_NEAREST ? route : (int)KRR_ROUTE_ALL, (const double*)D.X,
+                         (const int64_t*)D.d_offsets, M, p, cps, npos, part);
+    else
+      hipLaunchKernelGGL((k_predict<float>), grid, dim3(256), 0, s, (const float*)Xt, D.d, k,
+                         (const int32_t*)R.tperm, (const int64_t*)R.toff, (const int32_t*)R.tile_start,
+                         route == KRR_ROUTE_NEAREST ? route : (int)KRR_ROUTE_ALL, (const float*)D.X,
+                         (const int64_t*)D.d_offsets, M, p, cps, npos, part);
+    check_launch(ctx, s, "predict");
+  }
+  hipLaunchKernelGGL(k_predict_reduce, dim3((unsigned)ceil_div(npos * nm, 256)), dim3(256), 0, s,
+                     (const double*)part, (int)nsplit, npos, M,
+                     route == KRR_ROUTE_NEAREST ? (const int32_t*)R.tperm : nullptr);
+  check_launch(ctx, s, "predict_reduce");
 }
 
-void predict_into(krr_ctx ctx, hipStream_t s, krr_model model, const void* Xt, int dtype, int64_t k, int route,
-                  const Routing* R, double* yhat) {
-  const int p = model->data->p;
-  KRR_REQUIRE(dtype == model->data->dtype, "test inputs must have the dtype of the training inputs");
-  double* dst = yhat;
-  if (route == KRR_ROUTE_AVERAGE) dst = (double*)ws_get(ctx, "pred_all", (size_t)k * p * 8);
-  if (dtype == KRR_F64)
-    predict_launch<double>(ctx, s, model, (const double*)Xt, k, route, R, dst);
-  else
-    predict_launch<float>(ctx, s, model, (const float*)Xt, k, route, R, dst);
-  if (route == KRR_ROUTE_AVERAGE) {
-    hipLaunchKernelGGL(k_row_mean, dim3((unsigned)ceil_div(k, 256)), dim3(256), 0, s, (const double*)dst, k, p,
-                       yhat);
+// route AVERAGE: ALL into a workspace, then the mean over the p models
+void predict_models(krr_ctx ctx, hipStream_t s, const krr_model* models, int nm, const void* Xt, int dtype, int64_t k,
+                    int route, const Routing& R, double* const* yhat) {
+  const int p = models[0]->data->p;
+  if (route != KRR_ROUTE_AVERAGE) {
+    predict_group(ctx, s, models, nm, Xt, dtype, k, route, R, yhat);
+    return;
+  }
+  double* all = (double*)ws_get(ctx, "pred_all", (size_t)k * p * nm * 8);
+  double* dst[MAXM];
+  for (int q = 0; q < nm; ++q) dst[q] = all + (size_t)q * k * p;
+  predict_group(ctx, s, models, nm, Xt, dtype, k, KRR_ROUTE_ALL, R, dst);
+  for (int q = 0; q < nm; ++q) {
+    hipLaunchKernelGGL(k_row_mean, dim3((unsigned)ceil_div(k, 256)), dim3(256), 0, s, (const double*)dst[q], k, p,
+                       yhat[q]);
     check_launch(ctx, s, "row_mean");
   }
 }
@@ -256,9 +337,10 @@ void predict_into(krr_ctx ctx, hipStream_t s, krr_model model, const void* Xt, i
 void run_predict(krr_ctx ctx, hipStream_t s, krr_model model, const void* Xt, int dtype, int64_t k, int route,
                  double* yhat, int32_t* route_out) {
   KRR_REQUIRE(model->data->d > 0, "empty model");
-  Routing R{};
-  if (route == KRR_ROUTE_NEAREST || route_out != nullptr) R = route_points(ctx, s, model, Xt, dtype, k, "");
-  predict_into(ctx, s, model, Xt, dtype, k, route, &R, yhat);
+  Routing R;
+  if (route == KRR_ROUTE_NEAREST || route_out != nullptr) R = route_points(ctx, s, *model->data, Xt, dtype, k, "");
+  double* dst[1] = {yhat};
+  predict_models(ctx, s, &model, 1, Xt, dtype, k, route, R, dst);
   if (route_out != nullptr)
     KRR_HIP(hipMemcpyAsync(route_out, R.route, (size_t)k * 4, hipMemcpyDeviceToDevice, s));
 }
@@ -266,35 +348,38 @@ void run_predict(krr_ctx ctx, hipStream_t s, krr_model model, const void* Xt, in
 void run_select(krr_ctx ctx, hipStream_t s, const krr_model* models, int n_models, const void* Xv, const void* yv,
                 int dtype, int64_t k, int route, double* mse, int32_t* best) {
   const int64_t nb = ceil_div(k, 256);
-  char* w = (char*)ws_get(ctx, "select", (size_t)k * 8 + (size_t)nb * 8 + (size_t)n_models * 8 + 512);
-  double* yhat = (double*)w;
-  double* partial = yhat + k;
+  char* w = (char*)ws_get(ctx, "select", (size_t)k * 8 * MAXM + (size_t)nb * 8 + (size_t)n_models * 8 + 512);
+  double* yh = (double*)w;
+  double* partial = yh + k * MAXM;
   double* d_mse = partial + nb;
   int32_t* d_best = (int32_t*)(d_mse + n_models);
-  // models fitted together share their partition: route the points once
-  std::map<const krr_part_data*, Routing> routes;
-  for (int i = 0; i < n_models; ++i) {
-    const krr_model M = models[i];
-    Routing R{};
-    if (route == KRR_ROUTE_NEAREST) {
-      auto it = routes.find(M->data.get());
-      if (it == routes.end()) {
-        R = route_points(ctx, s, M, Xv, dtype, k, "_sel" + std::to_string(routes.size()));
-        routes[M->data.get()] = R;
-      } else {
-        R = it->second;
-      }
+  // models fitted together share their partitioning: route the points once
+  // and predict up to MAXM of them per launch
+  int done = 0;
+  int tag = 0;
+  while (done < n_models) {
+    const krr_part_data* D = models[done]->data.get();
+    int nm = 0;
+    while (done + nm < n_models && nm < MAXM && models[done + nm]->data.get() == D &&
+           models[done + nm]->params.kernel == models[done]->params.kernel)
+      ++nm;
+    Routing R;
+    if (route == KRR_ROUTE_NEAREST) R = route_points(ctx, s, *D, Xv, dtype, k, "_sel" + std::to_string(tag++));
+    double* dst[MAXM];
+    for (int q = 0; q < nm; ++q) dst[q] = yh + (size_t)q * k;
+    predict_models(ctx, s, models + done, nm, Xv, dtype, k, route, R, dst);
+    for (int q = 0; q < nm; ++q) {
+      if (dtype == KRR_F64)
+        hipLaunchKernelGGL((k_sqerr<double>), dim3((unsigned)nb), dim3(256), 0, s, (const double*)dst[q],
+                           (const double*)yv, k, partial);
+      else
+        hipLaunchKernelGGL((k_sqerr<float>), dim3((unsigned)nb), dim3(256), 0, s, (const double*)dst[q],
+                           (const float*)yv, k, partial);
+      check_launch(ctx, s, "sqerr");
+      hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, s, (const double*)partial, nb, k, d_mse + done + q);
+      check_launch(ctx, s, "mse_final");
     }
-    predict_into(ctx, s, M, Xv, dtype, k, route, &R, yhat);
-    if (dtype == KRR_F64)
-      hipLaunchKernelGGL((k_sqerr<double>), dim3((unsigned)nb), dim3(256), 0, s, (const double*)yhat,
-                         (const double*)yv, k, partial);
-    else
-      hipLaunchKernelGGL((k_sqerr<float>), dim3((unsigned)nb), dim3(256), 0, s, (const double*)yhat,
-                         (const float*)yv, k, partial);
-    check_launch(ctx, s, "sqerr");
-    hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, s, (const double*)partial, nb, k, d_mse + i);
-    check_launch(ctx, s, "mse_final");
+    done += nm;
   }
   hipLaunchKernelGGL(k_best, dim3(1), dim3(64), 0, s, (const double*)d_mse, n_models, d_best);
   check_launch(ctx, s, "best");

@@ -229,6 +229,7 @@ __global__ void k_ir_check(const SysDesc* __restrict__ desc, SysStatus* __restri
 
 void trsv_forward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, const SysStatus* st, int n_sys,
                   const void* A, const void* Wt, const double* b, double* z, int skip_converged) {
+  KernelTimer kt(ctx, s, "trsv_forward", 0.0, 0);
   if (prec == KRR_PREC_FP64)
     hipLaunchKernelGGL((k_trsv_fwd<double>), dim3(n_sys), dim3(256), 0, s, desc, st, (const double*)A,
                        (const double*)Wt, b, z, skip_converged);
@@ -240,6 +241,7 @@ void trsv_forward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, con
 
 void trsv_backward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, const SysStatus* st, int n_sys,
                    const void* A, const void* Wt, const double* z, double* x, double* alpha_acc, int skip_converged) {
+  KernelTimer kt(ctx, s, "trsv_backward", 0.0, 0);
   if (prec == KRR_PREC_FP64)
     hipLaunchKernelGGL((k_trsv_bwd<double>), dim3(n_sys), dim3(256), 0, s, desc, st, (const double*)A,
                        (const double*)Wt, z, x, alpha_acc, skip_converged);
@@ -254,6 +256,7 @@ void residual_check(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* 
                     const int64_t* p_off, double* rn, double* yn, const int64_t* n_off, double tol,
                     int will_refine, int32_t* active) {
   const int64_t ntri = (int64_t)Tmax * (Tmax + 1) / 2;
+  KernelTimer kt(ctx, s, "ir_residual", 0.0, 0);
   hipLaunchKernelGGL(k_resid_tiles, dim3((unsigned)ntri, (unsigned)n_sys), dim3(256), 0, s, desc,
                      (const SysStatus*)st, K64, alpha, P, p_off);
   check_launch(ctx, s, "resid_tiles");

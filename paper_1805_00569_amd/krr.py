@@ -25,7 +25,7 @@ PART = {"kmeans": 0, "kbalance": 1, "given": 2}
 PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
 ROUTE = {"nearest": 0, "average": 1, "all": 2}
 KERNEL = {"gaussian": 0, "linear": 1}
-OPT_PANEL_TILES, OPT_SERIAL_FIT, OPT_SYNC_CHECK = 0, 1, 2
+OPT_PANEL_TILES, OPT_SERIAL_FIT, OPT_SYNC_CHECK, OPT_TIMING = 0, 1, 2, 3
 
 
 class KrrError(RuntimeError):
@@ -53,6 +53,7 @@ _SIGS = {
     "krr_last_error": ([_P], ctypes.c_char_p),
     "krr_set_option": ([_P, ctypes.c_int32, ctypes.c_int64], ctypes.c_int),
     "krr_memory_in_use": ([_P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "krr_timing_report": ([_P, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "krr_partition": ([_P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                        ctypes.c_int32, ctypes.c_uint64, _P, _P, _P], ctypes.c_int),
     "krr_fit": ([_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P, _P, ctypes.c_int32,
@@ -175,6 +176,16 @@ class Context:
         v = ctypes.c_size_t(0)
         self._check(self.lib.krr_memory_in_use(self.h, ctypes.byref(v)))
         return v.value
+
+    def timing_report(self):
+        """Per-kernel-class event timing since the last report (see
+        krr_timing_report): {class: {"count", "ms", "flops"}}."""
+        import json
+        need = ctypes.c_size_t(0)
+        self._check(self.lib.krr_timing_report(self.h, None, 0, ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(max(need.value, 2) + 4096)
+        self._check(self.lib.krr_timing_report(self.h, buf, len(buf), ctypes.byref(need)))
+        return json.loads(buf.value.decode() or "{}")
 
     def partition(self, X, p, method="kmeans", lloyd_iters=20, seed=0, centroids=None):
         """Returns (centroids p x d FP64, assign int32[n], sizes int64[p])."""
