@@ -361,6 +361,93 @@ __global__ __launch_bounds__(256) void k_tile_gemm_bf16(const SysDesc* __restric
       }
 }
 
+// ---------------------------------------------------------------------------
+// Mixed precision trailing update, operands pre-packed.
+// k_pack_panel writes the finished panel L(i, K0..K1-1) of every tile row
+// i >= K1 once, in BF16, as v_mfma_f32_16x16x32_bf16 operand fragments:
+// fragment (rb, ks) holds rows [K1*64 + 16 rb, +16) and panel columns
+// [32 ks, +32); lane l holds row 16 rb + (l & 15), columns 32 ks + 8 (l >> 4)
+// + e (e = 0..7), i.e. 16 contiguous bytes per lane, 1 KiB per fragment.
+// k_trailing_bf16 then updates the lower triangle of the trailing matrix in
+// 128 x 128 super-tiles, one 64 x 64 storage tile per wavefront: per 32-wide
+// k step a wave loads 4 + 4 fragments (one 16-byte load per lane each) and
+// issues 16 MFMAs; no LDS, no barriers, FP32 accumulation, C read and written
+// once per panel.
+// ---------------------------------------------------------------------------
+constexpr int FRAG = 512;   // bf16 elements per fragment
+
+__global__ __launch_bounds__(256) void k_pack_panel(const SysDesc* __restrict__ desc,
+                                                    const SysStatus* __restrict__ st, const float* __restrict__ A,
+                                                    __bf16* __restrict__ Pk, int K0, int K1, int level) {
+  const int s = blockIdx.y;
+  const SysDesc D = desc[s];
+  if (st[s].status != 0 || D.level != level || K1 >= D.T) return;
+  const int KS = 2 * (K1 - K0);
+  const int RB = (D.T - K1) * 4;
+  const int f = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (f >= RB * KS) return;
+  const int rb = f / KS, ks = f - rb * KS;
+  const int l = threadIdx.x & 63;
+  const int r = K1 * NB + rb * 16 + (l & 15);          // row of the system
+  const int c0 = K0 * NB + ks * 32 + 8 * (l >> 4);     // first of 8 columns (inside one tile)
+  const float* tile = A + D.a_off + tile_index(r >> 6, c0 >> 6) * TILE;
+  bf8 v;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = (__bf16)tile[((c0 & 63) + e) * NB + (r & 63)];
+  *reinterpret_cast<bf8*>(Pk + D.pk_off + (int64_t)f * FRAG + l * 8) = v;
+}
+
+__global__ __launch_bounds__(256) void k_trailing_bf16(const SysDesc* __restrict__ desc,
+                                                       const SysStatus* __restrict__ st, float* __restrict__ A,
+                                                       const __bf16* __restrict__ Pk, int K0, int K1, int level) {
+  const int s = blockIdx.y;
+  const SysDesc D = desc[s];
+  if (st[s].status != 0 || D.level != level || K1 >= D.T) return;
+  const int R = D.T - K1;
+  const int NS = (R + 1) / 2;
+  const int bx = blockIdx.x;
+  int I = (int)((sqrt(8.0 * (double)bx + 1.0) - 1.0) * 0.5);
+  while (I * (I + 1) / 2 > bx) --I;
+  while ((I + 1) * (I + 2) / 2 <= bx) ++I;
+  const int J = bx - I * (I + 1) / 2;
+  if (I >= NS) return;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ii = 2 * I + (w & 1), jj = 2 * J + (w >> 1);
+  if (ii >= R || jj > ii) return;          // waves are independent: no barrier follows
+  const int KS = 2 * (K1 - K0);
+  const __bf16* P = Pk + D.pk_off + lane * 8;
+  f4 acc[4][4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) acc[cb][rb] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int ks = 0; ks < KS; ++ks) {
+    bf8 pa[4], qv[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+      pa[rb] = *reinterpret_cast<const bf8*>(P + (int64_t)((ii * 4 + rb) * KS + ks) * FRAG);
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+      qv[cb] = *reinterpret_cast<const bf8*>(P + (int64_t)((jj * 4 + cb) * KS + ks) * FRAG);
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+        acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qv[cb], pa[rb], acc[cb][rb], 0, 0, 0);
+  }
+  float* C = A + D.a_off + tile_index(K1 + ii, K1 + jj) * TILE;
+  const int il = lane & 15, kg = lane >> 4;
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int e = (16 * cb + 4 * kg + v) * NB + 16 * rb + il;
+        C[e] = C[e] - acc[cb][rb][v];
+      }
+}
+
 template <typename TS>
 void launch_update(krr_ctx ctx, hipStream_t s, bool bf16, int mode, const SysDesc* desc, SysStatus* st, TS* A,
                    const TS* Wt, int n_sys, int64_t nblk, int i0, int jc, int q0, int q1, int level) {
@@ -388,7 +475,7 @@ void launch_update(krr_ctx ctx, hipStream_t s, bool bf16, int mode, const SysDes
 
 template <typename TS>
 void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, int n_sys, int Tmax, TS* A, TS* Wt,
-              bool bf16, int Wp, int level, const SysDesc* hdesc) {
+              bool bf16, int Wp, int level, const SysDesc* hdesc, __bf16* Pk) {
   // algorithmic flops of each launch (timing only), from the real sizes m
   auto each = [&](auto&& f) {
     double tot = 0.0;
@@ -429,6 +516,27 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
     }
     if (K1 < Tmax) {
       const int64_t R = Tmax - K1;
+      if constexpr (std::is_same<TS, float>::value) {
+        if (bf16 && Pk != nullptr) {
+          {
+            KernelTimer kt(ctx, s, "chol_pack_bf16", 0.0, 0);
+            const int64_t nfrag = R * 4 * 2 * (K1 - K0);
+            hipLaunchKernelGGL(k_pack_panel, dim3((unsigned)ceil_div(nfrag, 4), (unsigned)n_sys), dim3(256), 0, s,
+                               desc, (const SysStatus*)st, (const float*)A, Pk, K0, K1, level);
+            check_launch(ctx, s, "pack_panel");
+          }
+          KernelTimer kt(ctx, s, trail_name, each([&](double m) {
+            const double n = m - K1 * NB;
+            const double kk = std::min<double>(K1 * NB, m) - K0 * NB;
+            return n > 0 ? n * (n + 1.0) * kk : 0.0;
+          }), 1);
+          const int64_t NS = (R + 1) / 2;
+          hipLaunchKernelGGL(k_trailing_bf16, dim3((unsigned)(NS * (NS + 1) / 2), (unsigned)n_sys), dim3(256), 0, s,
+                             desc, (const SysStatus*)st, (float*)A, (const __bf16*)Pk, K0, K1, level);
+          check_launch(ctx, s, "trailing_bf16");
+          continue;
+        }
+      }
       KernelTimer kt(ctx, s, trail_name, each([&](double m) {
         const double n = m - K1 * NB;
         const double kk = std::min<double>(K1 * NB, m) - K0 * NB;
@@ -447,12 +555,19 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
 // (MIXED first pass); otherwise FP32 (or FP64) matrix-core updates.  hdesc:
 // host copy of desc (used for the flop counts of timed launches; nullable).
 void cholesky_factor(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, SysStatus* st, int n_sys, int Tmax,
-                     void* A, void* Wt, int level, bool bf16, const SysDesc* hdesc) {
+                     void* A, void* Wt, int level, bool bf16, const SysDesc* hdesc, void* pack) {
   const int Wp = ctx->panel_tiles;
   if (prec == KRR_PREC_FP64)
-    factor_t<double>(ctx, s, desc, st, n_sys, Tmax, (double*)A, (double*)Wt, false, Wp, level, hdesc);
+    factor_t<double>(ctx, s, desc, st, n_sys, Tmax, (double*)A, (double*)Wt, false, Wp, level, hdesc, nullptr);
   else
-    factor_t<float>(ctx, s, desc, st, n_sys, Tmax, (float*)A, (float*)Wt, bf16, Wp, level, hdesc);
+    factor_t<float>(ctx, s, desc, st, n_sys, Tmax, (float*)A, (float*)Wt, bf16, Wp, level, hdesc, (__bf16*)pack);
+}
+
+// BF16 elements of the panel pack slot of a system with T tile rows (the
+// first panel is the largest).
+int64_t pack_slot_elems(int T, int Wp) {
+  const int64_t R = std::max(0, T - std::min(Wp, T));
+  return R * 4 * 2 * (int64_t)Wp * FRAG;
 }
 
 }  // namespace krr

@@ -63,6 +63,7 @@ struct SysDesc {
   double lambda;       // diagonal shift actually used
   int32_t kernel;      // krr_kernel
   int32_t level;       // precision level that factors this system in the current pass
+  int64_t pk_off;      // element offset of its BF16 panel-pack slot (mixed precision)
 };
 
 // Device-side status of one system.

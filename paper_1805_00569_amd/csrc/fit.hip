@@ -11,7 +11,8 @@
 namespace krr {
 
 void cholesky_factor(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, SysStatus* st, int n_sys, int Tmax,
-                     void* A, void* Wt, int level, bool bf16, const SysDesc* hdesc);
+                     void* A, void* Wt, int level, bool bf16, const SysDesc* hdesc, void* pack);
+int64_t pack_slot_elems(int T, int Wp);
 void trsv_forward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, const SysStatus* st, int n_sys,
                   const void* A, const void* Wt, const double* b, double* z, int skip_converged);
 void trsv_backward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, const SysStatus* st, int n_sys,
@@ -52,8 +53,8 @@ __global__ __launch_bounds__(256) void k_form(const TX* __restrict__ Xg, int d, 
   const int tj = bx - ti * (ti + 1) / 2;
   if (ti >= T) return;
   const int m = D0.m;
-  __shared__ double sXi[KC * LDX];
-  __shared__ double sXj[KC * LDX];
+  __shared__ double sXi[KC * LDX + 1];   // + a spare slot for staged values past d
+  __shared__ double sXj[KC * LDX + 1];
   __shared__ double sNi[NB], sNj[NB];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int r0 = 32 * (w & 1), c0 = 32 * (w >> 1);
@@ -79,13 +80,23 @@ __global__ __launch_bounds__(256) void k_form(const TX* __restrict__ Xg, int d, 
       li[u] = Xi[(int64_t)min(row, rows_i - 1) * d + k0 + kk];
       lj[u] = Xj[(int64_t)min(row, rows_j - 1) * d + k0 + kk];
     }
+    // stored unconditionally: rows past m only feed entries that the
+    // epilogue overrides; the k slots past d read by the last 4-wide MFMA
+    // step are zeroed below (selecting on a loaded value would turn into a
+    // branch around the load)
 #pragma unroll
     for (int u = 0; u < NB * KC / 256; ++u) {
       const int e = t + u * 256;
       const int row = e / KC, kk = e - row * KC;
-      const bool ok = kk < kc;
-      sXi[kk * LDX + row] = (ok && row < rows_i) ? (double)li[u] : 0.0;
-      sXj[kk * LDX + row] = (ok && row < rows_j) ? (double)lj[u] : 0.0;
+      const int slot = (kk < kc) ? kk * LDX + row : KC * LDX;   // past d: the spare slot
+      sXi[slot] = (double)li[u];
+      sXj[slot] = (double)lj[u];
+    }
+    const int kc4 = (kc + 3) & ~3;
+    for (int e = t; e < (kc4 - kc) * NB; e += 256) {
+      const int kk = kc + e / NB, row = e % NB;
+      sXi[kk * LDX + row] = 0.0;
+      sXj[kk * LDX + row] = 0.0;
     }
     __syncthreads();
     if (t < NB) {
@@ -270,7 +281,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
   const int n_sys = n_params * p;
   std::vector<SysDesc> desc(n_sys);
   std::vector<int64_t> p_off(n_sys), n_off(n_sys);
-  int64_t a_tot = 0, w_tot = 0, v_tot = 0, p_tot = 0, n_tot = 0;
+  int64_t a_tot = 0, w_tot = 0, v_tot = 0, p_tot = 0, n_tot = 0, pk_tot = 0;
   int Tmax = 0;
   for (int q = 0; q < n_params; ++q)
     for (int jp = 0; jp < p; ++jp) {
@@ -288,6 +299,8 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
       D.lambda = params[q].lambda_times_m ? params[q].lambda * (double)m : params[q].lambda;
       D.kernel = params[q].kernel;
       D.level = 0;
+      D.pk_off = pk_tot;
+      pk_tot += (prec == KRR_PREC_MIXED) ? pack_slot_elems(D.T, ctx->panel_tiles) : 0;
       a_tot += tri(D.T) * TILE;
       w_tot += (int64_t)D.T * TILE;
       v_tot += (int64_t)D.T * NB;
@@ -303,6 +316,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
   void* A = ws_get(ctx, "fit_A", (size_t)std::max<int64_t>(a_tot, 1) * aes);
   void* Wt = ws_get(ctx, "fit_W", (size_t)std::max<int64_t>(w_tot, 1) * aes);
   double* K64 = mixed ? (double*)ws_get(ctx, "fit_K64", (size_t)std::max<int64_t>(a_tot, 1) * 8) : nullptr;
+  void* pack = mixed ? ws_get(ctx, "fit_pack", (size_t)std::max<int64_t>(pk_tot, 1) * 2) : nullptr;
   const size_t vb = (size_t)std::max<int64_t>(v_tot, 1) * 8;
   char* vecs = (char*)ws_get(ctx, "fit_vec", 5 * vb);
   double* yg = (double*)ws_get(ctx, "fit_yg", (size_t)n * 8);
@@ -358,7 +372,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
   };
   if (!ctx->serial_fit) {
     form(d_desc, p, n_params, Tmax);
-    cholesky_factor(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, 0, mixed, desc.data());
+    cholesky_factor(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, 0, mixed, desc.data(), pack);
     trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, rhs, zb, 0);
     trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, zb, alpha, nullptr, 0);
   } else {
@@ -368,7 +382,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
       if (desc[sidx].T == 0) continue;
       form(d_desc + sidx, 1, 1, desc[sidx].T);
       cholesky_factor(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, desc[sidx].T, A, Wt, 0, mixed,
-                      desc.data() + sidx);
+                      desc.data() + sidx, pack);
       trsv_forward(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, A, Wt, rhs, zb, 0);
       trsv_backward(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, A, Wt, zb, alpha, nullptr, 0);
     }
@@ -417,7 +431,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
       hipLaunchKernelGGL(k_restore_tiles, dim3((unsigned)tri(Tmax), (unsigned)n_sys), dim3(256), 0, s,
                          (const SysDesc*)d_desc, (const double*)K64, (float*)A, 1);
       check_launch(ctx, s, "restore_tiles");
-      cholesky_factor(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, 1, false, desc.data());
+      cholesky_factor(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, 1, false, desc.data(), pack);
       trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, rhs, zb, 1);
       trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, zb, alpha, nullptr, 1);
       refine();

@@ -21,10 +21,24 @@ constexpr int GROUP_BLOCK = 256;
 constexpr int KPP_BLOCK = 256;   // k-means++ cumulative-weight block
 constexpr int CCHUNK = 16;       // centres per register chunk in assignment
 
+// Plain operators: the library is compiled with -ffp-contract=off (and the
+// pragma keeps it off here), so every operation is rounded on its own.  The
+// __d*_rn intrinsics give the same results but compile to strict-FP
+// operations that the scheduler will not move loads across.
 __device__ __forceinline__ double sqdiff_acc(double acc, double a, double b) {
 #pragma clang fp contract(off)
-  const double t = __dsub_rn(a, b);
-  return __dadd_rn(acc, __dmul_rn(t, t));
+  const double t = a - b;
+  return acc + t * t;
+}
+
+__device__ __forceinline__ double add_sep(double a, double b) {
+#pragma clang fp contract(off)
+  return a + b;
+}
+
+__device__ __forceinline__ double mul_sep(double a, double b) {
+#pragma clang fp contract(off)
+  return a * b;
 }
 
 template <typename TX>
@@ -68,11 +82,11 @@ __global__ __launch_bounds__(256) void k_assign(const TX* __restrict__ X, int64_
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = e0 + u * R;
-      if (e < tot) {
-        const int r = e / d;
-        const int k = e - r * d;
-        sX[k * ld + r] = v[u];
-      }
+      // out-of-range elements go to a spare LDS row instead of a conditional store
+      const int ec = min(e, tot - 1);
+      const int r = ec / d;
+      const int k = ec - r * d;
+      sX[(e < tot) ? (k * ld + r) : d * ld] = v[u];
     }
   }
   __syncthreads();
@@ -289,19 +303,16 @@ __global__ __launch_bounds__(MEANS_THREADS) void k_means(const TX* __restrict__ 
   const int64_t vals = cnt * d;                        // contiguous values of this partition
   const TX* base = Xg + o0 * d;
   const int64_t per = (int64_t)rows * d;
-  // features handled by this thread: f = t, t + 256, ...
-  constexpr int FMAX = MEANS_CHUNK / MEANS_THREADS;    // d <= 4096
-  double s[FMAX];
-#pragma unroll
-  for (int u = 0; u < FMAX; ++u) s[u] = 0.0;
-  // loads are unconditional from clamped addresses (a predicated load would
-  // wait on its own), the value is selected afterwards
+  // one feature per thread (d <= MEANS_THREADS; wider rows use k_means_wide)
+  const int fcl = min(t, d - 1);   // threads past d sum a discarded copy
+  double s0 = 0.0;
+  // loads are unconditional (a predicated load waits on its own); values past
+  // the partition land in LDS slots that the sums never read
   double nxt[MEANS_LPT];
 #pragma unroll
   for (int u = 0; u < MEANS_LPT; ++u) {
     const int64_t e = t + (int64_t)u * MEANS_THREADS;
-    const double v = (double)base[min(e, vals - 1)];
-    nxt[u] = (e < min(per, vals)) ? v : 0.0;
+    nxt[u] = (double)base[e];   // the grouped buffer is padded: always in bounds
   }
   for (int64_t c0 = 0; c0 < vals; c0 += per) {
     const int64_t cl = min(per, vals - c0);
@@ -314,23 +325,20 @@ __global__ __launch_bounds__(MEANS_THREADS) void k_means(const TX* __restrict__ 
 #pragma unroll
     for (int u = 0; u < MEANS_LPT; ++u) {
       const int64_t e = t + (int64_t)u * MEANS_THREADS;
-      const double v = (double)base[min(c1 + e, vals - 1)];
-      nxt[u] = (c1 + e < vals && e < per) ? v : 0.0;
+      nxt[u] = (double)base[c1 + e];   // past the partition: padding, never summed
     }
     const int nr = (int)(cl / d);
-    for (int q = 0; q < nr; ++q) {
+    int q = 0;
+    for (; q + 8 <= nr; q += 8) {   // 8 independent LDS reads, then 8 ordered adds
+      double v[8];
 #pragma unroll
-      for (int u = 0; u < FMAX; ++u) {
-        const int f = min(t + u * MEANS_THREADS, d - 1);   // lanes past d compute a discarded copy
-        s[u] = __dadd_rn(s[u], sv[q * d + f]);
-      }
+      for (int u = 0; u < 8; ++u) v[u] = sv[(q + u) * d + fcl];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s0 = add_sep(s0, v[u]);
     }
+    for (; q < nr; ++q) s0 = add_sep(s0, sv[q * d + fcl]);
   }
-#pragma unroll
-  for (int u = 0; u < FMAX; ++u) {
-    const int f = t + u * MEANS_THREADS;
-    if (f < d) C[(int64_t)j * d + f] = __ddiv_rn(s[u], (double)cnt);
-  }
+  if (t < d) C[(int64_t)j * d + t] = s0 / (double)cnt;
 }
 
 // ---------------------------------------------------------------------------
@@ -364,7 +372,7 @@ __global__ __launch_bounds__(KPP_BLOCK) void k_kpp_update(const TX* __restrict__
     const int cnt = (int)min((int64_t)KPP_BLOCK, n - (int64_t)blockIdx.x * KPP_BLOCK);
     double acc = sd[0];
     for (int q = 1; q < cnt; ++q) {
-      acc = __dadd_rn(acc, sd[q]);
+      acc = add_sep(acc, sd[q]);
       sd[q] = acc;
     }
     Tb[blockIdx.x] = acc;
@@ -388,7 +396,7 @@ __global__ __launch_bounds__(KPP_BLOCK) void k_kpp_select(const double* __restri
     double o = 0.0;
     for (int64_t b = 0; b < nblk; ++b) {
       Ob[b] = o;
-      o = __dadd_rn(o, Tb[b]);
+      o = add_sep(o, Tb[b]);
     }
     const double total = o;
     int64_t blk = -1;
@@ -396,10 +404,10 @@ __global__ __launch_bounds__(KPP_BLOCK) void k_kpp_select(const double* __restri
     if (!(total > 0.0)) {
       mode = 1;
     } else {
-      const double thr = __dmul_rn(u, total);
+      const double thr = mul_sep(u, total);
       s_thr = thr;
       for (int64_t b = 0; b < nblk; ++b) {
-        if (__dadd_rn(Ob[b], Tb[b]) > thr) {
+        if (add_sep(Ob[b], Tb[b]) > thr) {
           blk = b;
           break;
         }
@@ -412,7 +420,7 @@ __global__ __launch_bounds__(KPP_BLOCK) void k_kpp_select(const double* __restri
   __syncthreads();
   int64_t idx;
   if (s_mode == 1) {
-    idx = (int64_t)floor(__dmul_rn(u, (double)n));
+    idx = (int64_t)floor(mul_sep(u, (double)n));
     if (idx > n - 1) idx = n - 1;
   } else if (s_mode == 2) {
     idx = 0;  // no cumulative weight above the threshold: the first point
@@ -420,7 +428,7 @@ __global__ __launch_bounds__(KPP_BLOCK) void k_kpp_select(const double* __restri
     const int64_t b = s_blk;
     const int64_t i = b * KPP_BLOCK + threadIdx.x;
     int64_t cand = INT64_MAX;
-    if (i < n && __dadd_rn(Ob[b], P[i]) > s_thr) cand = i;
+    if (i < n && add_sep(Ob[b], P[i]) > s_thr) cand = i;
     s_idx[threadIdx.x] = cand;
     __syncthreads();
     for (int w = KPP_BLOCK / 2; w > 0; w >>= 1) {
@@ -439,7 +447,7 @@ __global__ __launch_bounds__(KPP_BLOCK) void k_kpp_select(const double* __restri
 template <typename TX>
 __global__ void k_kpp_first(int64_t n, double u0, const TX* __restrict__ X, int d,
                             int64_t* __restrict__ cidx, double* __restrict__ C) {
-  int64_t idx = (int64_t)floor(__dmul_rn(u0, (double)n));
+  int64_t idx = (int64_t)floor(mul_sep(u0, (double)n));
   if (idx > n - 1) idx = n - 1;
   if (threadIdx.x == 0) cidx[0] = idx;
   for (int f = threadIdx.x; f < d; f += blockDim.x) C[f] = (double)X[idx * d + f];
@@ -588,8 +596,8 @@ void assign_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, const d
               bool all) {
   // Rows per block: as many as fit in about 96 KiB of LDS, at least 64.
   int R = 256;
-  while (R > 64 && (size_t)d * (R + 1) * sizeof(TX) > 96 * 1024) R /= 2;
-  const size_t lds = (size_t)d * (R + 1) * sizeof(TX);
+  while (R > 64 && ((size_t)d * (R + 1) + 1) * sizeof(TX) > 96 * 1024) R /= 2;
+  const size_t lds = ((size_t)d * (R + 1) + 1) * sizeof(TX);
   const int64_t nblk = ceil_div(n, R);
   KernelTimer kt(ctx, s, "assign", 0.0, 0);
   if (lds <= 96 * 1024) {
@@ -626,19 +634,20 @@ __global__ void k_means_wide(const TX* __restrict__ Xg, int d, const int64_t* __
   const int64_t o0 = offsets[j], o1 = offsets[j + 1];
   if (o1 == o0) return;
   double acc = 0.0;
-  for (int64_t o = o0; o < o1; ++o) acc = __dadd_rn(acc, (double)Xg[o * d + f]);
-  C[(int64_t)j * d + f] = __ddiv_rn(acc, (double)(o1 - o0));
+  for (int64_t o = o0; o < o1; ++o) acc = add_sep(acc, (double)Xg[o * d + f]);
+  C[(int64_t)j * d + f] = acc / (double)(o1 - o0);
 }
 
 template <typename TX>
 void means_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, const int32_t* perm, const int64_t* offsets,
              double* C, int p, const int32_t* skip, const int32_t* delta, int32_t* done_next) {
   KernelTimer kt(ctx, s, "lloyd_means", 0.0, 0);
-  TX* Xg = (TX*)ws_get(ctx, "means_xg", (size_t)n * d * sizeof(TX));
+  // padded by two chunks so that the unconditional prefetch stays in bounds
+  TX* Xg = (TX*)ws_get(ctx, "means_xg", ((size_t)n * d + 2 * MEANS_CHUNK) * sizeof(TX));
   hipLaunchKernelGGL((k_gather_grouped<TX>), dim3((unsigned)ceil_div(n * d, 256)), dim3(256), 0, s, X, n, d, perm,
                      Xg, skip);
   check_launch(ctx, s, "gather_grouped");
-  if (d <= MEANS_CHUNK)
+  if (d <= MEANS_THREADS)
     hipLaunchKernelGGL((k_means<TX>), dim3((unsigned)p), dim3(MEANS_THREADS), 0, s, (const TX*)Xg, d, offsets, C,
                        skip, delta, done_next);
   else

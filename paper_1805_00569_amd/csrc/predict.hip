@@ -68,8 +68,8 @@ __global__ __launch_bounds__(256) void k_predict(const TX* __restrict__ Xt, int 
   const int64_t m = xoff[j + 1] - x0;
   const int64_t xbeg = (int64_t)split * cps * NB;
   const int64_t xend = min(m, xbeg + (int64_t)cps * NB);
-  __shared__ double sT[KC * LDX];
-  __shared__ double sX[KC * LDX];
+  __shared__ double sT[KC * LDX + 1];   // + a spare slot for staged values past d
+  __shared__ double sX[KC * LDX + 1];
   __shared__ double sNt[NB], sNx[NB];
   __shared__ int64_t srow[NB];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -115,13 +115,22 @@ __global__ __launch_bounds__(256) void k_predict(const TX* __restrict__ Xt, int 
         lt[u] = Xt[max(sr, (int64_t)0) * d + k0 + kk];
         lx[u] = Xg[(x0 + xc + min((int64_t)row, xcnt - 1)) * d + k0 + kk];
       }
+      // stored unconditionally: test slots without a point and training rows
+      // past the chunk are never used; the k slots past d read by the last
+      // 4-wide MFMA step are zeroed below
 #pragma unroll
       for (int u = 0; u < NB * KC / 256; ++u) {
         const int e = t + u * 256;
         const int row = e / KC, kk = e - row * KC;
-        const bool ok = kk < kc;
-        sT[kk * LDX + row] = (ok && srow[row] >= 0) ? (double)lt[u] : 0.0;
-        sX[kk * LDX + row] = (ok && row < xcnt) ? (double)lx[u] : 0.0;
+        const int slot = (kk < kc) ? kk * LDX + row : KC * LDX;   // past d: the spare slot
+        sT[slot] = (double)lt[u];
+        sX[slot] = (double)lx[u];
+      }
+      const int kc4 = (kc + 3) & ~3;
+      for (int e = t; e < (kc4 - kc) * NB; e += 256) {
+        const int kk = kc + e / NB, row = e % NB;
+        sT[kk * LDX + row] = 0.0;
+        sX[kk * LDX + row] = 0.0;
       }
       __syncthreads();
       if (t < NB)
