@@ -56,6 +56,7 @@ def main():
     ap.add_argument("--no-baselines", action="store_true", help="skip the plain/batched comparisons")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing on the host")
     ap.add_argument("--cpu-fits", type=int, default=2, help="oracle fits timed for the CPU baseline")
+    ap.add_argument("--panel", type=int, default=0, help="Cholesky panel width in 64-wide tiles (0: library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
@@ -75,6 +76,8 @@ def main():
     Xt = torch.from_numpy(w.Xt).to(dev)
     print(f"# data ready in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     ctx = krr.Context(0)
+    if args.panel:
+        ctx.set_option(krr.OPT_PANEL_TILES, args.panel)
 
     def settings(prec):
         return [krr.Params(sigma=s, lam=l, prec=prec, refine_tol=1e-6, max_refine=30)

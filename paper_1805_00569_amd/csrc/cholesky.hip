@@ -362,80 +362,101 @@ __global__ __launch_bounds__(256) void k_tile_gemm_bf16(const SysDesc* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Mixed precision trailing update, operands pre-packed.
-// k_pack_panel writes the finished panel L(i, K0..K1-1) of every tile row
-// i >= K1 once, in BF16, as v_mfma_f32_16x16x32_bf16 operand fragments:
-// fragment (rb, ks) holds rows [K1*64 + 16 rb, +16) and panel columns
-// [32 ks, +32); lane l holds row 16 rb + (l & 15), columns 32 ks + 8 (l >> 4)
-// + e (e = 0..7), i.e. 16 contiguous bytes per lane, 1 KiB per fragment.
-// k_trailing_bf16 then updates the lower triangle of the trailing matrix in
-// 128 x 128 super-tiles, one 64 x 64 storage tile per wavefront: per 32-wide
-// k step a wave loads 4 + 4 fragments (one 16-byte load per lane each) and
-// issues 16 MFMAs; no LDS, no barriers, FP32 accumulation, C read and written
-// once per panel.
+// Mixed precision updates with pre-packed BF16 operands.
+// After the panel solve of column k, k_pack_column writes L(i, k) for every
+// tile row i >= k once, in BF16, as v_mfma_f32_16x16x32_bf16 operand
+// fragments.  The pack of a system holds the current panel [K0, K0 + W):
+// fragment (rb, ks) covers rows [K0*64 + 16 rb, +16) and panel columns
+// [32 ks, +32) (ks < 2W); lane l holds row 16 rb + (l & 15) and columns
+// 32 ks + 8 (l >> 4) + e (e = 0..7): 16 contiguous bytes per lane, 1 KiB per
+// fragment.
+// k_packed_update subtracts sum_q L(i,q) L(j,q)^T over the packed fragment
+// columns [ks0, ks1) from output tiles, one 64 x 64 tile per wavefront: per
+// 32-wide k step a wave loads 4 + 4 fragments (one 16-byte load per lane
+// each) and issues 16 MFMAs with FP32 accumulation; no LDS and no barriers,
+// so waves exit independently.  Systems run along blockIdx.z.
+//   MODE_COL (band): tiles (i, j), j = j0 + blockIdx.y,
+//             i = j + 4 * blockIdx.x + wave (the lower part of the columns
+//             [j0, j0 + gridDim.y) of the panel)
+//   MODE_TRI: the lower triangle of the trailing matrix from tile i0 in
+//             128 x 128 super-tiles (blockIdx.x = triangle index)
 // ---------------------------------------------------------------------------
 constexpr int FRAG = 512;   // bf16 elements per fragment
 
-__global__ __launch_bounds__(256) void k_pack_panel(const SysDesc* __restrict__ desc,
-                                                    const SysStatus* __restrict__ st, const float* __restrict__ A,
-                                                    __bf16* __restrict__ Pk, int K0, int K1, int level) {
+__global__ __launch_bounds__(256) void k_pack_column(const SysDesc* __restrict__ desc,
+                                                     const SysStatus* __restrict__ st, const float* __restrict__ A,
+                                                     __bf16* __restrict__ Pk, int K0, int k, int Wp, int level) {
   const int s = blockIdx.y;
   const SysDesc D = desc[s];
-  if (st[s].status != 0 || D.level != level || K1 >= D.T) return;
-  const int KS = 2 * (K1 - K0);
-  const int RB = (D.T - K1) * 4;
-  const int f = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (f >= RB * KS) return;
-  const int rb = f / KS, ks = f - rb * KS;
+  if (st[s].status != 0 || D.level != level || k >= D.T) return;
+  const int KSW = 2 * Wp;
+  const int nrb = (D.T - k) * 4;                       // row blocks of tile rows i >= k
+  const int f = blockIdx.x * 4 + (threadIdx.x >> 6);   // (row block, half) pair
+  if (f >= nrb * 2) return;
+  const int rbl = f >> 1, h = f & 1;
   const int l = threadIdx.x & 63;
-  const int r = K1 * NB + rb * 16 + (l & 15);          // row of the system
-  const int c0 = K0 * NB + ks * 32 + 8 * (l >> 4);     // first of 8 columns (inside one tile)
-  const float* tile = A + D.a_off + tile_index(r >> 6, c0 >> 6) * TILE;
+  const int r = k * NB + rbl * 16 + (l & 15);          // row of the system
+  const int cl = 32 * h + 8 * (l >> 4);                // first of 8 columns inside tile column k
+  const float* tile = A + D.a_off + tile_index(r >> 6, k) * TILE;
   bf8 v;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) v[e] = (__bf16)tile[((c0 & 63) + e) * NB + (r & 63)];
-  *reinterpret_cast<bf8*>(Pk + D.pk_off + (int64_t)f * FRAG + l * 8) = v;
+  for (int e = 0; e < 8; ++e) v[e] = (__bf16)tile[(cl + e) * NB + (r & 63)];
+  const int rb = (k - K0) * 4 + rbl;
+  const int ks = 2 * (k - K0) + h;
+  *reinterpret_cast<bf8*>(Pk + D.pk_off + ((int64_t)rb * KSW + ks) * FRAG + l * 8) = v;
 }
 
-__global__ __launch_bounds__(256) void k_trailing_bf16(const SysDesc* __restrict__ desc,
+template <int MODE>
+__global__ __launch_bounds__(256) void k_packed_update(const SysDesc* __restrict__ desc,
                                                        const SysStatus* __restrict__ st, float* __restrict__ A,
-                                                       const __bf16* __restrict__ Pk, int K0, int K1, int level) {
-  const int s = blockIdx.y;
+                                                       const __bf16* __restrict__ Pk, int K0, int ks0, int ks1,
+                                                       int i0, int j0, int Wp, int level) {
+  const int s = blockIdx.z;
   const SysDesc D = desc[s];
-  if (st[s].status != 0 || D.level != level || K1 >= D.T) return;
-  const int R = D.T - K1;
-  const int NS = (R + 1) / 2;
-  const int bx = blockIdx.x;
-  int I = (int)((sqrt(8.0 * (double)bx + 1.0) - 1.0) * 0.5);
-  while (I * (I + 1) / 2 > bx) --I;
-  while ((I + 1) * (I + 2) / 2 <= bx) ++I;
-  const int J = bx - I * (I + 1) / 2;
-  if (I >= NS) return;
+  if (st[s].status != 0 || D.level != level) return;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int ii = 2 * I + (w & 1), jj = 2 * J + (w >> 1);
-  if (ii >= R || jj > ii) return;          // waves are independent: no barrier follows
-  const int KS = 2 * (K1 - K0);
+  int i, j;
+  if (MODE == MODE_COL) {
+    j = j0 + blockIdx.y;
+    i = j + 4 * blockIdx.x + w;
+    if (i >= D.T) return;
+  } else {
+    const int R = D.T - i0;
+    if (R <= 0) return;
+    const int NS = (R + 1) / 2;
+    const int bx = blockIdx.x;
+    int I = (int)((sqrt(8.0 * (double)bx + 1.0) - 1.0) * 0.5);
+    while (I * (I + 1) / 2 > bx) --I;
+    while ((I + 1) * (I + 2) / 2 <= bx) ++I;
+    const int J = bx - I * (I + 1) / 2;
+    if (I >= NS) return;
+    i = i0 + 2 * I + (w & 1);
+    j = i0 + 2 * J + (w >> 1);
+    if (i >= D.T || j > i) return;       // waves are independent: no barrier follows
+  }
+  const int KSW = 2 * Wp;
   const __bf16* P = Pk + D.pk_off + lane * 8;
+  const int rbi = (i - K0) * 4, rbj = (j - K0) * 4;
   f4 acc[4][4];
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) acc[cb][rb] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int ks = 0; ks < KS; ++ks) {
+  for (int ks = ks0; ks < ks1; ++ks) {
     bf8 pa[4], qv[4];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
-      pa[rb] = *reinterpret_cast<const bf8*>(P + (int64_t)((ii * 4 + rb) * KS + ks) * FRAG);
+      pa[rb] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbi + rb) * KSW + ks) * FRAG);
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
-      qv[cb] = *reinterpret_cast<const bf8*>(P + (int64_t)((jj * 4 + cb) * KS + ks) * FRAG);
+      qv[cb] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbj + cb) * KSW + ks) * FRAG);
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb)
         acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qv[cb], pa[rb], acc[cb][rb], 0, 0, 0);
   }
-  float* C = A + D.a_off + tile_index(K1 + ii, K1 + jj) * TILE;
+  float* C = A + D.a_off + tile_index(i, j) * TILE;
   const int il = lane & 15, kg = lane >> 4;
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
@@ -488,6 +509,89 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
   const char* trail_name = bf16 ? "chol_trailing_bf16" : (f64 ? "chol_trailing_f64" : "chol_trailing_f32");
   const char* col_name = bf16 ? "chol_column_bf16" : (f64 ? "chol_column_f64" : "chol_column_f32");
   const char* trsm_name = f64 ? "chol_trsm_f64" : "chol_trsm_f32";
+  const bool packed = std::is_same<TS, float>::value && bf16 && Pk != nullptr;
+  auto diag_trsm = [&](int k) {
+    {
+      KernelTimer kt(ctx, s, "chol_diag", each([&](double m) {
+        const double b = std::min<double>(NB, m - k * NB);
+        return b > 0 ? 2.0 * b * b * b / 3.0 : 0.0;
+      }), 0);
+      hipLaunchKernelGGL((k_potrf_diag<TS>), dim3(n_sys), dim3(DIAG_THREADS), 0, s, desc, st, A, Wt, k, level);
+      check_launch(ctx, s, "potrf_diag");
+    }
+    if (k + 1 < Tmax) {
+      KernelTimer kt(ctx, s, trsm_name, each([&](double m) {
+        const double rows = m - (k + 1) * NB;
+        return rows > 0 ? rows * (double)NB * NB : 0.0;
+      }), 1);
+      launch_update<TS>(ctx, s, false, MODE_TRSM, desc, st, A, Wt, n_sys, Tmax - k - 1, k + 1, k, 0, 1, level);
+    }
+  };
+  if (packed) {
+    // The panel [K0, K1) is factored in sub-panels of WI tile columns, each
+    // followed by one band update of the panel's remaining columns; the wide
+    // panel then updates the trailing matrix once, which keeps the FP32
+    // read-modify-write traffic of the trailing tiles low.  Measured on the
+    // balanced workload, bands (WI < W) cost more than the column updates they
+    // replace, because every band re-reads and re-writes the panel tiles: WI
+    // is the largest panel width, i.e. one sub-panel per panel.
+    constexpr int WI = 16;
+    for (int K0 = 0; K0 < Tmax; K0 += Wp) {
+      const int K1 = std::min(K0 + Wp, Tmax);
+      for (int S0 = K0; S0 < K1; S0 += WI) {
+        const int S1 = std::min(S0 + WI, K1);
+        for (int k = S0; k < S1; ++k) {
+          if (k > S0) {
+            KernelTimer kt(ctx, s, col_name, each([&](double m) {
+              const double rows = m - k * NB;
+              return rows > 0 ? 2.0 * rows * std::min<double>(NB, rows) * (k - S0) * NB : 0.0;
+            }), 1);
+            hipLaunchKernelGGL((k_packed_update<MODE_COL>), dim3((unsigned)ceil_div(Tmax - k, 4), 1, (unsigned)n_sys),
+                               dim3(256), 0, s, desc, (const SysStatus*)st, (float*)A, (const __bf16*)Pk, K0,
+                               2 * (S0 - K0), 2 * (k - K0), 0, k, Wp, level);
+            check_launch(ctx, s, "packed_column");
+          }
+          diag_trsm(k);
+          if (k + 1 < K1 || K1 < Tmax) {   // column k feeds later updates: pack it
+            KernelTimer kt(ctx, s, "chol_pack_bf16", 0.0, 0);
+            const int64_t npairs = (int64_t)(Tmax - k) * 4 * 2;
+            hipLaunchKernelGGL(k_pack_column, dim3((unsigned)ceil_div(npairs, 4), (unsigned)n_sys), dim3(256), 0, s,
+                               desc, (const SysStatus*)st, (const float*)A, (__bf16*)Pk, K0, k, Wp, level);
+            check_launch(ctx, s, "pack_column");
+          }
+        }
+        if (S1 < K1) {   // band: columns [S1, K1), rows below the diagonal, sub-panel [S0, S1)
+          KernelTimer kt(ctx, s, col_name, each([&](double m) {
+            double f = 0.0;
+            for (int j = S1; j < K1; ++j) {
+              const double rows = m - j * NB;
+              if (rows > 0) f += 2.0 * rows * std::min<double>(NB, rows) * (S1 - S0) * NB;
+            }
+            return f;
+          }), 1);
+          hipLaunchKernelGGL((k_packed_update<MODE_COL>),
+                             dim3((unsigned)ceil_div(Tmax - S1, 4), (unsigned)(K1 - S1), (unsigned)n_sys), dim3(256),
+                             0, s, desc, (const SysStatus*)st, (float*)A, (const __bf16*)Pk, K0, 2 * (S0 - K0),
+                             2 * (S1 - K0), 0, S1, Wp, level);
+          check_launch(ctx, s, "packed_band");
+        }
+      }
+      if (K1 < Tmax) {
+        const int64_t R = Tmax - K1;
+        KernelTimer kt(ctx, s, trail_name, each([&](double m) {
+          const double n = m - K1 * NB;
+          const double kk = std::min<double>(K1 * NB, m) - K0 * NB;
+          return n > 0 ? n * (n + 1.0) * kk : 0.0;
+        }), 1);
+        const int64_t NS = (R + 1) / 2;
+        hipLaunchKernelGGL((k_packed_update<MODE_TRI>), dim3((unsigned)(NS * (NS + 1) / 2), 1, (unsigned)n_sys),
+                           dim3(256), 0, s, desc, (const SysStatus*)st, (float*)A, (const __bf16*)Pk, K0, 0,
+                           2 * (K1 - K0), K1, 0, Wp, level);
+        check_launch(ctx, s, "packed_trailing");
+      }
+    }
+    return;
+  }
   for (int K0 = 0; K0 < Tmax; K0 += Wp) {
     const int K1 = std::min(K0 + Wp, Tmax);
     for (int k = K0; k < K1; ++k) {
@@ -498,45 +602,10 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
         }), 1);
         launch_update<TS>(ctx, s, bf16, MODE_COL, desc, st, A, Wt, n_sys, Tmax - k, k, k, K0, k, level);
       }
-      {
-        KernelTimer kt(ctx, s, "chol_diag", each([&](double m) {
-          const double b = std::min<double>(NB, m - k * NB);
-          return b > 0 ? 2.0 * b * b * b / 3.0 : 0.0;
-        }), 0);
-        hipLaunchKernelGGL((k_potrf_diag<TS>), dim3(n_sys), dim3(DIAG_THREADS), 0, s, desc, st, A, Wt, k, level);
-        check_launch(ctx, s, "potrf_diag");
-      }
-      if (k + 1 < Tmax) {
-        KernelTimer kt(ctx, s, trsm_name, each([&](double m) {
-          const double rows = m - (k + 1) * NB;
-          return rows > 0 ? rows * (double)NB * NB : 0.0;
-        }), 1);
-        launch_update<TS>(ctx, s, false, MODE_TRSM, desc, st, A, Wt, n_sys, Tmax - k - 1, k + 1, k, 0, 1, level);
-      }
+      diag_trsm(k);
     }
     if (K1 < Tmax) {
       const int64_t R = Tmax - K1;
-      if constexpr (std::is_same<TS, float>::value) {
-        if (bf16 && Pk != nullptr) {
-          {
-            KernelTimer kt(ctx, s, "chol_pack_bf16", 0.0, 0);
-            const int64_t nfrag = R * 4 * 2 * (K1 - K0);
-            hipLaunchKernelGGL(k_pack_panel, dim3((unsigned)ceil_div(nfrag, 4), (unsigned)n_sys), dim3(256), 0, s,
-                               desc, (const SysStatus*)st, (const float*)A, Pk, K0, K1, level);
-            check_launch(ctx, s, "pack_panel");
-          }
-          KernelTimer kt(ctx, s, trail_name, each([&](double m) {
-            const double n = m - K1 * NB;
-            const double kk = std::min<double>(K1 * NB, m) - K0 * NB;
-            return n > 0 ? n * (n + 1.0) * kk : 0.0;
-          }), 1);
-          const int64_t NS = (R + 1) / 2;
-          hipLaunchKernelGGL(k_trailing_bf16, dim3((unsigned)(NS * (NS + 1) / 2), (unsigned)n_sys), dim3(256), 0, s,
-                             desc, (const SysStatus*)st, (float*)A, (const __bf16*)Pk, K0, K1, level);
-          check_launch(ctx, s, "trailing_bf16");
-          continue;
-        }
-      }
       KernelTimer kt(ctx, s, trail_name, each([&](double m) {
         const double n = m - K1 * NB;
         const double kk = std::min<double>(K1 * NB, m) - K0 * NB;
@@ -564,10 +633,9 @@ void cholesky_factor(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, 
 }
 
 // BF16 elements of the panel pack slot of a system with T tile rows (the
-// first panel is the largest).
+// first panel, rows [0, T*64) x 2W fragment columns, is the largest).
 int64_t pack_slot_elems(int T, int Wp) {
-  const int64_t R = std::max(0, T - std::min(Wp, T));
-  return R * 4 * 2 * (int64_t)Wp * FRAG;
+  return (int64_t)T * 4 * 2 * (int64_t)Wp * FRAG;
 }
 
 }  // namespace krr

@@ -128,7 +128,7 @@ struct krr_ctx_s {
   size_t model_bytes = 0;
   int n_models = 0;
   int n_datas = 0;
-  int panel_tiles = 4;
+  int panel_tiles = 16;
   int serial_fit = 0;
   int sync_check = 0;
   void* pinned = nullptr;

@@ -73,7 +73,7 @@ def test_ragged_partitions_fp64(ctx, dev, n, d, p, panel):
         params = [krr.Params(sigma=1.5, lam=1e-2, prec="fp64"), krr.Params(sigma=0.7, lam=1e-3, prec="fp64")]
         models, info, st, oms, X, a = _fit_both(ctx, dev, w, p, params, method="kmeans", iters=8, seed=n)
     finally:
-        ctx.set_option(krr.OPT_PANEL_TILES, 4)
+        ctx.set_option(krr.OPT_PANEL_TILES, 16)
     assert st == 0
     for q in range(2):
         for j in range(p):
