@@ -36,22 +36,57 @@ constexpr int TILE = NB * NB;
 __device__ __forceinline__ int64_t tile_index(int i, int j) { return (int64_t)i * (i + 1) / 2 + j; }
 
 // ---------------------------------------------------------------------------
-// Diagonal block: load A(k,k) into LDS, factor it in FP64 and form the
-// inverse Winv(k) = L(k,k)^-1, both right-looking with one barrier per
-// column.  Each of the 256 threads owns a fixed set of lower-triangle
-// positions (r, c).
-//   Factor, column j: every thread reads the pivot A(j,j) and scales column j
-//   on the fly (column j of A is not written during step j), writes the final
-//   L(:,j) into sL, and updates its positions with j < c <= r.
-//   Inverse, row kk of W: rows r > kk are updated with the scaled row kk read
-//   from the working copy (row kk is not written during step kk); the final
-//   scaled row goes to sW.
+// Diagonal block: A(k,k) = L L^T in FP64 and Winv(k) = L^-1, one workgroup of
+// two waves per system, with the matrix held in registers.
+//   Wave 0 (factor): lane r holds row r of the working matrix, shifted so
+//   that a[c] = A(r, j + c) at step j.  Step j takes the pivot from lane j,
+//   forms L(r, j), publishes column j of L through LDS and applies the rank-1
+//   update of the remaining columns, writing each result one register to the
+//   left so that the next step's column is again a[0].  The register index
+//   stays a compile-time constant, and only the live window of 64 - j
+//   columns (rounded up to a multiple of 8) is touched.
+//   Wave 1 (inverse): lane t holds column t of W = L^-1 as the right-hand
+//   side e_t of L w = e_t, shifted the same way, and runs forward
+//   substitution one step behind wave 0, reading the column of L that wave 0
+//   published in the previous step (a ring of two LDS slots, one barrier per
+//   step).
 // A pivot that is not positive (or NaN) marks the system failed with the
 // LAPACK-style 1-based global column index.
 // ---------------------------------------------------------------------------
-constexpr int DIAG_THREADS = 256;
-constexpr int DIAG_LD = NB + 1;                                  // padded LDS row
-constexpr int DIAG_PER = (NB * (NB + 1) / 2 + DIAG_THREADS - 1) / DIAG_THREADS;   // 9
+constexpr int DIAG_THREADS = 128;
+constexpr int SW_LD = NB + 1;   // padded LDS column of the staged inverse
+
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// v[c - 1] = v[c] - s * col[c] for 1 <= c < W (col[c] = L(j + c, j)); v[W - 1]
+// keeps a stale value outside the live window.
+template <int W>
+__device__ __forceinline__ void shift_update(double (&v)[NB], double s, const double* __restrict__ col) {
+#pragma unroll
+  for (int c = 0; c < W; c += 2) {
+    const double2 b = *reinterpret_cast<const double2*>(col + c);
+    if (c > 0) v[c - 1] = fma(-s, b.x, v[c]);
+    v[c] = fma(-s, b.y, v[c + 1]);
+  }
+}
+
+__device__ __forceinline__ void shift_update_step(int j, double (&v)[NB], double s, const double* col) {
+  switch (j >> 3) {
+    case 0: shift_update<64>(v, s, col); break;
+    case 1: shift_update<56>(v, s, col); break;
+    case 2: shift_update<48>(v, s, col); break;
+    case 3: shift_update<40>(v, s, col); break;
+    case 4: shift_update<32>(v, s, col); break;
+    case 5: shift_update<24>(v, s, col); break;
+    case 6: shift_update<16>(v, s, col); break;
+    default: shift_update<8>(v, s, col); break;
+  }
+}
 
 template <typename TS>
 __global__ __launch_bounds__(DIAG_THREADS) void k_potrf_diag(const SysDesc* __restrict__ desc,
@@ -60,102 +95,64 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_potrf_diag(const SysDesc* __re
   const int s = blockIdx.x;
   const SysDesc D = desc[s];
   if (k >= D.T || st[s].status != 0 || D.level != level) return;
-  __shared__ double sA[NB * DIAG_LD];   // working matrix, sA[c * DIAG_LD + r] = A(r, c)
-  __shared__ double sL[NB * DIAG_LD];   // final L, same layout
+  // slot[b][NB + c] = L(j + c, j) for the step j with j % 2 == b; slot[b][0] = 1 / L(j, j)
+  __shared__ __align__(16) double slot[2][2 * NB];
+  __shared__ double sW[NB * SW_LD];   // sW[t * SW_LD + i] = W(i, t)
+  __shared__ int sfail;
   TS* tile = A + D.a_off + tile_index(k, k) * TILE;
-  const int t = threadIdx.x;
-  for (int e = t; e < TILE; e += DIAG_THREADS) {
-    const int c = e >> 6, r = e & 63;
-    sA[c * DIAG_LD + r] = (r >= c) ? (double)tile[e] : 0.0;
-    sL[c * DIAG_LD + r] = 0.0;
-  }
-  // this thread's lower-triangle positions: linear index e -> (r, c), r >= c
-  int pr[DIAG_PER], pc[DIAG_PER];
+  const int lane = threadIdx.x & 63;
+  const bool factor_wave = threadIdx.x < 64;
+  double v[NB];
+  if (factor_wave) {
+    // row `lane` of A(k,k); entries above the diagonal are never consumed
 #pragma unroll
-  for (int q = 0; q < DIAG_PER; ++q) {
-    const int e = t + q * DIAG_THREADS;
-    if (e < NB * (NB + 1) / 2) {
-      int r = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-      while (r * (r + 1) / 2 > e) --r;
-      while ((r + 1) * (r + 2) / 2 <= e) ++r;
-      pr[q] = r;
-      pc[q] = e - r * (r + 1) / 2;
-    } else {      // no position: a harmless in-range address, never stored
-      pr[q] = 0;
-      pc[q] = NB;
-    }
+    for (int c = 0; c < NB; ++c) v[c] = (double)tile[c * NB + lane];
+  } else {
+#pragma unroll
+    for (int c = 0; c < NB; ++c) v[c] = (c == lane) ? 1.0 : 0.0;
   }
+  if (threadIdx.x == 0) sfail = 0;
   __syncthreads();
-  int fail = 0;
-  for (int j = 0; j < NB; ++j) {
-    const double piv = sA[j * DIAG_LD + j];
-    if (!(piv > 0.0)) {
-      fail = j + 1;
-      break;
-    }
-    const double ljj = sqrt(piv);
-    const double inv = 1.0 / ljj;
-    if (t < NB) sL[j * DIAG_LD + t] = (t > j) ? sA[j * DIAG_LD + t] * inv : ((t == j) ? ljj : 0.0);
-    // all loads of this thread's positions first, unconditionally and from
-    // in-range addresses (a predicated load would wait on its own), then the
-    // stores; column j is read-only in step j and the positions are disjoint
-    double vr[DIAG_PER], vc[DIAG_PER], va[DIAG_PER];
-#pragma unroll
-    for (int q = 0; q < DIAG_PER; ++q) {
-      const int r = pr[q], c = min(pc[q], NB - 1);
-      vr[q] = sA[j * DIAG_LD + r];
-      vc[q] = sA[j * DIAG_LD + c];
-      va[q] = sA[c * DIAG_LD + r];
-    }
-#pragma unroll
-    for (int q = 0; q < DIAG_PER; ++q) {
-      const int r = pr[q], c = pc[q];
-      if (c > j && r >= c) sA[c * DIAG_LD + r] = fma(-(vr[q] * inv), vc[q] * inv, va[q]);
+  double piv = factor_wave ? read_lane(v[0], 0) : 0.0;
+  for (int j = 0; j <= NB; ++j) {
+    if (factor_wave) {
+      if (j < NB) {
+        if (!(piv > 0.0)) {
+          if (lane == 0) sfail = j + 1;
+        } else {
+          const double ljj = sqrt(piv);
+          const double inv = 1.0 / ljj;
+          const double l = lane > j ? v[0] * inv : (lane == j ? ljj : 0.0);
+          double* sl = slot[j & 1];
+          sl[NB + lane - j] = l;
+          if (lane == 0) sl[0] = inv;
+          tile[j * NB + lane] = (TS)l;
+          __builtin_amdgcn_wave_barrier();
+          shift_update_step(j, v, l, sl + NB);
+          piv = read_lane(v[0], min(j + 1, NB - 1));
+        }
+      }
+    } else if (j > 0) {
+      const int i = j - 1;
+      const double* sl = slot[i & 1];
+      const double w = v[0] * sl[0];   // W(i, t)
+      sW[lane * SW_LD + i] = w;
+      shift_update_step(i, v, w, sl + NB);
     }
     __syncthreads();
+    if (sfail) break;
   }
-  if (fail) {
-    if (t == 0) {
+  if (sfail) {
+    if (threadIdx.x == 0) {
       st[s].status = KRR_ENOTSPD;
-      st[s].failed_pivot = k * NB + fail;
+      st[s].failed_pivot = k * NB + sfail;
     }
     return;
   }
-  for (int e = t; e < TILE; e += DIAG_THREADS) {
-    const int c = e >> 6, r = e & 63;
-    tile[e] = (TS)sL[c * DIAG_LD + r];
-  }
-  // inverse: sA becomes the working W (identity), sW the final rows
-  double* sW = sA;
-  __syncthreads();
-  for (int e = t; e < TILE; e += DIAG_THREADS) {
-    const int c = e >> 6, r = e & 63;
-    sW[c * DIAG_LD + r] = (r == c) ? 1.0 : 0.0;
-  }
-  __shared__ double sWf[NB * DIAG_LD];
-  __syncthreads();
-  for (int kk = 0; kk < NB; ++kk) {
-    const double inv = 1.0 / sL[kk * DIAG_LD + kk];
-    if (t < NB) sWf[t * DIAG_LD + kk] = (t <= kk) ? sW[t * DIAG_LD + kk] * inv : 0.0;   // row kk, column t
-    double vw[DIAG_PER], vl[DIAG_PER], va[DIAG_PER];
-#pragma unroll
-    for (int q = 0; q < DIAG_PER; ++q) {
-      const int r = pr[q], c = min(pc[q], NB - 1);
-      vw[q] = sW[c * DIAG_LD + kk];   // W(kk, c), not written in step kk
-      vl[q] = sL[kk * DIAG_LD + r];
-      va[q] = sW[c * DIAG_LD + r];
-    }
-#pragma unroll
-    for (int q = 0; q < DIAG_PER; ++q) {
-      const int r = pr[q], c = pc[q];
-      if (r > kk && c <= kk) sW[c * DIAG_LD + r] = fma(-vl[q], vw[q] * inv, va[q]);
-    }
-    __syncthreads();
-  }
   TS* wt = Wt + D.w_off + (int64_t)k * TILE;
-  for (int e = t; e < TILE; e += DIAG_THREADS) {
+  for (int e = threadIdx.x; e < TILE; e += DIAG_THREADS) {
     const int c = e >> 6, r = e & 63;
-    wt[e] = (TS)((r >= c) ? sWf[c * DIAG_LD + r] : 0.0);
+    wt[e] = (TS)((r >= c) ? sW[c * SW_LD + r] : 0.0);
   }
 }
 
