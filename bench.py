@@ -57,6 +57,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing on the host")
     ap.add_argument("--cpu-fits", type=int, default=2, help="oracle fits timed for the CPU baseline")
     ap.add_argument("--panel", type=int, default=0, help="Cholesky panel width in 64-wide tiles (0: library default)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-rates", default="100,500,2000", help="Poisson arrival rates (requests/s)")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="length of each rate's arrival trace")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
@@ -213,7 +216,98 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, state, ctx, params, args.cpu_fits)
 
+    if not args.no_serve:
+        del X, y, Xv, yv, Xt
+        torch.cuda.empty_cache()
+        out["serving"] = serving_leg([float(r) for r in args.serve_rates.split(",") if r], args.serve_seconds)
+        top = out["serving"]["rates"][-1]
+        out["p50_predict_ms"] = top["predict_p50_ms"]
+        out["p99_predict_ms"] = top["predict_p99_ms"]
+
     print(json.dumps(out))
+
+
+def serving_leg(rates, seconds, seed=5):
+    """Request loop over a resident BKRR2 model: n=262,144 points (d=90,
+    64-component Gaussian mixture) K-balanced into 64 partitions of 4,096 and
+    fitted in FP32 (sigma=2, lambda=1e-2).  For each rate, a seeded Poisson
+    stream of `seconds` mixes 10% fit requests (m uniform in [256, 8192],
+    d in {8, 32, 90}, FP32, same setting) and 90% predict requests (1..1024
+    points routed to the nearest of the 64 models), submitted open-loop at
+    their arrival times.  Latency = submit to completion, measured by the
+    server."""
+    import torch
+    from paper_1805_00569_amd import datagen, krr
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    pools = datagen.serving_pools(seed=seed)
+    w = pools.resident
+    X = torch.from_numpy(w.X).to(dev)
+    y = torch.from_numpy(w.y.astype(np.float32)).to(dev)
+    ctx = krr.Context(0)
+    setting = krr.Params(sigma=2.0, lam=1e-2, prec="fp32")
+    C, a, sz = ctx.partition(X, 64, "kbalance", lloyd_iters=LLOYD, seed=seed)
+    torch.cuda.synchronize()
+    tf = time.perf_counter()
+    models, info, st = ctx.fit(X, y, a, C, 64, [setting])
+    fit_s = time.perf_counter() - tf
+    print(f"# serving: resident model ready ({time.time() - t0:.1f}s, fit {fit_s * 1e3:.1f} ms, status {st})",
+          file=sys.stderr, flush=True)
+    del X, y
+    srv = krr.Server(ctx, models[0], predict_workers=2, fit_workers=2, max_batch_fits=16, max_batch_points=16384,
+                     hbm_budget=64 << 30)
+    res = {"resident": {"n": w.n, "d": w.d, "p": 64, "partition_size_range": [int(sz.min().item()), int(sz.max().item())], "precision": "fp32",
+                        "sigma": 2.0, "lambda": 1e-2, "fit_ms": round(fit_s * 1e3, 3), "fit_status": st},
+           "workers": {"predict": 2, "fit": 2, "max_batch_fits": 16, "max_batch_points": 16384},
+           "rates": []}
+    try:
+        # warm the workers' workspaces with one request of each kind and size class
+        for fd in (8, 32, 90):
+            srv.wait(srv.submit_fit(datagen.take_rows(pools.fit_X[fd], 0, 8192),
+                                    datagen.take_rows(pools.fit_y[fd][:, None], 0, 8192)[:, 0], setting))
+        for _ in range(4):
+            srv.wait(srv.submit_predict(datagen.take_rows(pools.queries, 0, 1024)))
+        srv.stats(reset=True)
+        for rate in rates:
+            trace = datagen.serving_trace(seed=seed, rate=rate, seconds=seconds)
+            tickets = []
+            start = time.perf_counter()
+            for r in trace:
+                while time.perf_counter() - start < r.t:
+                    pass
+                if r.kind == "predict":
+                    tickets.append(srv.submit_predict(datagen.take_rows(pools.queries, r.offset, r.rows)))
+                else:
+                    tickets.append(srv.submit_fit(datagen.take_rows(pools.fit_X[r.d], r.offset, r.rows),
+                                                  datagen.take_rows(pools.fit_y[r.d][:, None], r.offset, r.rows)[:, 0],
+                                                  setting))
+            submit_s = time.perf_counter() - start
+            bad = 0
+            for tk in tickets:
+                try:
+                    srv.wait(tk)
+                except krr.KrrError:
+                    bad += 1
+            s = srv.stats(reset=True)
+            span = max(s["span_ms"], 1e-9) / 1e3
+            n_fit = sum(r.kind == "fit" for r in trace)
+            row = {"rate": rate, "requests": len(trace), "fit_requests": n_fit,
+                   "achieved_rate": len(trace) / max(submit_s, 1e-9),
+                   "predict_p50_ms": s["predict_p50_ms"], "predict_p99_ms": s["predict_p99_ms"],
+                   "fit_p50_ms": s["fit_p50_ms"], "fit_p99_ms": s["fit_p99_ms"],
+                   "fits_per_s": s["fit_requests"] / span, "predictions_per_s": s["points"] / span,
+                   "mean_predict_batch": s["predict_requests"] / max(s["predict_batches"], 1),
+                   "mean_fit_batch": s["fit_requests"] / max(s["fit_batches"], 1),
+                   "failed": s["failed"] + bad, "max_inflight_bytes": s["max_inflight_bytes"]}
+            res["rates"].append(row)
+            print(f"# serving rate {rate:g}/s: {len(trace)} requests, predict p50 {row['predict_p50_ms']:.2f} ms "
+                  f"p99 {row['predict_p99_ms']:.2f} ms, fit p50 {row['fit_p50_ms']:.1f} ms",
+                  file=sys.stderr, flush=True)
+    finally:
+        srv.close()
+        models[0].free()
+        ctx.close()
+    return res
 
 
 def roofline(timed, steps):

@@ -210,6 +210,98 @@ krr_status krr_model_alpha(krr_ctx ctx, hipStream_t stream, krr_model model, int
                            double* alpha, int64_t* m);
 krr_status krr_model_free(krr_model model);
 
+/* ---- serving: continuous batching over a resident model ------------------
+ * A server keeps one fitted model resident (typically the p partition models
+ * of Algorithm 5 for one setting) and answers two kinds of request from
+ * host memory:
+ *   predict: k query points routed to the nearest centre's model (KKRR2 /
+ *            BKRR2, Section 4.2, Algorithm 5) and evaluated with Eq. 7;
+ *   fit:     an independent problem (K + lambda I) alpha = y of m points
+ *            (Eq. 6, Algorithm 1), returned as alpha.
+ * Requests queue per kind.  Worker threads, each with its own context and
+ * stream, take a batch whenever they are idle: a predict worker takes the
+ * queued predict requests in arrival order (at most max_batch_points points)
+ * and serves them with one routed prediction; a fit worker takes the oldest
+ * fit request and every later queued one with the same d and settings (at
+ * most max_batch_fits) and solves them as one ragged batch, one partition
+ * per request.  A request is admitted into a batch only while the estimated
+ * device memory of all admitted, unfinished requests stays within
+ * hbm_budget_bytes, so requests that arrive while others run wait until
+ * memory and a worker free up; batches of different workers run
+ * concurrently on the device.  A request's result depends only on its own
+ * data (the batch it joins changes no arithmetic of a fit, and only the
+ * summation split of a prediction).  Latency of a request = time from its
+ * submit call to the end of the batch that served it. */
+typedef struct krr_server_s* krr_server;
+
+typedef struct {
+  int32_t predict_workers;   /* >= 1 */
+  int32_t fit_workers;       /* >= 0 (0: fit requests are rejected) */
+  int32_t max_batch_fits;    /* >= 1: fit requests per batch */
+  int32_t reserved;          /* must be 0 */
+  int64_t max_batch_points;  /* >= 1: query points per predict batch */
+  size_t  hbm_budget_bytes;  /* admission budget of unfinished requests (0 = none);
+                                also the budget of every worker's context */
+} krr_server_config;
+
+typedef struct {
+  int32_t status;            /* KRR_OK or the error of the request's batch / system */
+  int32_t kind;              /* 0 predict, 1 fit */
+  int32_t batch_requests;    /* requests in the batch that served it */
+  int32_t reserved;
+  double  queue_ms;          /* submit -> batch start */
+  double  run_ms;            /* batch start -> batch end */
+  double  total_ms;          /* submit -> batch end */
+} krr_request_info;
+
+typedef struct {
+  int64_t predict_requests;  /* completed since creation or the last reset */
+  int64_t fit_requests;
+  int64_t points;            /* query points predicted */
+  int64_t fit_rows;          /* training points fitted */
+  int64_t predict_batches;
+  int64_t fit_batches;
+  int64_t failed;            /* completed requests with a status other than KRR_OK */
+  int64_t max_inflight_bytes;/* peak estimated memory of admitted, unfinished requests */
+  double  predict_p50_ms, predict_p99_ms;   /* nearest-rank percentiles of total_ms */
+  double  fit_p50_ms, fit_p99_ms;
+  double  span_ms;           /* first submit -> last completion */
+} krr_serve_stats;
+
+/* krr_server_create: start a server on the device of `owner` that answers
+ * predict requests with `model` (created on `owner`, whose dimension d fixes
+ * the query width).  The model and owner must outlive the server, and the
+ * owner context must not free the model meanwhile; the server itself never
+ * uses the owner context.  *out receives the handle.
+ * krr_server_destroy: waits for every submitted request, stops the workers
+ * and frees their contexts.  Results of requests not yet waited for stay
+ * written to their host buffers; their tickets are dropped. */
+krr_status  krr_server_create(krr_ctx owner, krr_model model, const krr_server_config* cfg,
+                              krr_server* out);
+krr_status  krr_server_destroy(krr_server server);
+/* Message of the last failing server call or request ("" if none). */
+const char* krr_server_last_error(krr_server server);
+
+/* Submit requests (thread-safe; returns at once).  Host buffers are owned by
+ * the caller and must stay valid until krr_server_wait returns for the ticket.
+ * predict: Xq host FP32 k x d (d of the resident model), yhat host FP64 k out.
+ * fit:     X host FP32 m x d, y host FP32 m, params host (one setting),
+ *          alpha host FP64 m out (in the order of the m points).
+ * *ticket receives the request's id.  KRR_EINVAL for bad sizes or null
+ * pointers; KRR_EBUDGET if the request alone would exceed the budget;
+ * KRR_ESTATE if the server has no fit workers (fit) or is stopping. */
+krr_status  krr_server_submit_predict(krr_server server, const float* Xq, int64_t k, double* yhat,
+                                      int64_t* ticket);
+krr_status  krr_server_submit_fit(krr_server server, const float* X, const float* y, int64_t m,
+                                  int32_t d, const krr_fit_params* params, double* alpha,
+                                  int64_t* ticket);
+/* Block until the request is done; *info (host, nullable) receives its record.
+ * Returns the request's status; the ticket is released (KRR_EINVAL if unknown). */
+krr_status  krr_server_wait(krr_server server, int64_t ticket, krr_request_info* info);
+/* Counters and latency percentiles of completed requests (host out); reset = 1
+ * clears them after reading. */
+krr_status  krr_server_stats(krr_server server, int32_t reset, krr_serve_stats* out);
+
 #ifdef __cplusplus
 }
 #endif

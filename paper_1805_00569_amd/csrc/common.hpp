@@ -179,9 +179,17 @@ void run_partition(krr_ctx ctx, hipStream_t s, const void* X, int dtype, int64_t
                    int64_t* sizes);
 
 // ---- fit.hip ----
+// Result of a fit that creates no model (one setting): alpha of partition j is
+// alpha[v_off[j], v_off[j] + m[j]) in the context's workspace, valid until the
+// next fit on the context.  The partition data then lives in the workspace
+// too, so no model memory is allocated or freed.
+struct FitDirect {
+  const double* alpha = nullptr;
+  std::vector<int64_t> v_off, m;
+};
 void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype, int64_t n, int d,
              const int32_t* assign, const double* centroids, int p, const krr_fit_params* params,
-             int n_params, krr_model* models, krr_part_info* info);
+             int n_params, krr_model* models, krr_part_info* info, FitDirect* direct = nullptr);
 
 // ---- predict.hip ----
 void run_predict(krr_ctx ctx, hipStream_t s, krr_model model, const void* Xt, int dtype, int64_t k,

@@ -239,7 +239,8 @@ void launch_form(krr_ctx ctx, hipStream_t s, int prec, const void* Xg, int d, co
 
 void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype, int64_t n, int d,
              const int32_t* assign, const double* centroids, int p, const krr_fit_params* params, int n_params,
-             krr_model* models, krr_part_info* info) {
+             krr_model* models, krr_part_info* info, FitDirect* direct) {
+  KRR_REQUIRE(direct == nullptr || n_params == 1, "a direct fit takes one setting");
   const int prec = params[0].prec;
   const size_t xes = (dtype == KRR_F64) ? 8 : 4;
   const size_t aes = (prec == KRR_PREC_FP64) ? 8 : 4;
@@ -260,9 +261,13 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
   const size_t cbytes = ((size_t)p * d * 8 + 255) & ~size_t(255);
   const size_t obytes = ((size_t)(p + 1) * 8 + 255) & ~size_t(255);
   data->bytes = xbytes + 2 * cbytes + obytes;
-  data->base = model_alloc(ctx, data->bytes);
-  data->ctx = ctx;
-  ctx->n_datas += 1;
+  if (direct != nullptr) {
+    data->base = ws_get(ctx, "fit_direct_data", data->bytes);   // not owned: ctx stays null
+  } else {
+    data->base = model_alloc(ctx, data->bytes);
+    data->ctx = ctx;
+    ctx->n_datas += 1;
+  }
   data->p = p;
   data->d = d;
   data->dtype = dtype;
@@ -457,6 +462,17 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
       I.rel_residual = mixed ? S.rel_residual : -1.0;
       if (mixed && S.status == 0 && !S.converged && desc[sidx].T > 0) I.status = KRR_ENOCONV;
     }
+
+  if (direct != nullptr) {
+    direct->alpha = alpha;
+    direct->v_off.resize(p);
+    direct->m.resize(p);
+    for (int jp = 0; jp < p; ++jp) {
+      direct->v_off[jp] = desc[jp].v_off;
+      direct->m[jp] = desc[jp].m;
+    }
+    return;
+  }
 
   // 11. models: alpha of setting q is the contiguous range of its p systems
   for (int q = 0; q < n_params; ++q) {

@@ -212,3 +212,73 @@ def small(seed, n, d, k=64, p=4, dtype=np.float64, comps=None, spread=3.0):
     yt = np.sin(Xt[:, 0].astype(np.float64) + Xt[:, min(1, d - 1)])
     return Workload(f"small_s{seed}_n{n}_d{d}", X, y, None, None, Xt, yt, p,
                     (1.0,), (1e-2,), {})
+
+
+# ---------------------------------------------------------------------------
+# serving workload: a request stream over a resident partitioned model
+# ---------------------------------------------------------------------------
+S_TRACE = 40   # arrival trace streams are S_TRACE + a per-rate offset
+
+
+@dataclasses.dataclass
+class ServingPools:
+    """Payload pools the requests of a trace slice from.
+
+    resident: the training set of the resident model (a `comps`-component
+    mixture, like the ragged-partition workload); queries: points from the
+    same distribution; fit_X[d], fit_y[d]: mixture points and labels of
+    dimension d for fit requests."""
+    resident: Workload
+    queries: np.ndarray
+    fit_X: dict
+    fit_y: dict
+
+
+def serving_pools(seed=5, n=262144, d=90, comps=64, n_queries=16384, fit_ds=(8, 32, 90), fit_rows=8192,
+                  fit_comps=32):
+    res = gaussian_mixture(seed=seed, n=n, d=d, comps=comps, lo=max(64, n // comps // 8),
+                           hi=max(n // comps * 4, 1), k_test=n_queries)
+    fit_X, fit_y = {}, {}
+    for fd in fit_ds:
+        w = gaussian_mixture(seed=seed * 1000 + fd, n=fit_rows, d=fd, comps=fit_comps,
+                             lo=max(1, fit_rows // fit_comps // 8), hi=fit_rows, k_test=1)
+        fit_X[fd] = w.X
+        fit_y[fd] = w.y.astype(np.float32)
+    return ServingPools(res, res.Xt, fit_X, fit_y)
+
+
+@dataclasses.dataclass
+class TraceRequest:
+    t: float        # arrival time, seconds from the start of the trace
+    kind: str       # "predict" or "fit"
+    rows: int       # query points (predict) or training points (fit)
+    d: int
+    offset: int     # first row in the pool (wrapping)
+
+
+def serving_trace(seed=5, rate=100.0, seconds=2.0, fit_frac=0.1, fit_rows=(256, 8192), fit_ds=(8, 32, 90),
+                  query_rows=(1, 1024), d_model=90, pool_queries=16384, pool_fit=8192):
+    """Poisson arrivals at `rate` per second for `seconds`; each request is a
+    fit with probability fit_frac (m uniform in fit_rows, d uniform over
+    fit_ds) and otherwise a prediction of a uniform number of query points in
+    query_rows.  Sizes and pool offsets only; payloads come from the pools."""
+    g = rng(seed, S_TRACE + int(round(rate)))
+    out, t = [], 0.0
+    while True:
+        t += g.exponential(1.0 / rate)
+        if t >= seconds:
+            break
+        if g.random() < fit_frac:
+            m = int(g.integers(fit_rows[0], fit_rows[1] + 1))
+            fd = int(fit_ds[g.integers(0, len(fit_ds))])
+            out.append(TraceRequest(t, "fit", m, fd, int(g.integers(0, pool_fit))))
+        else:
+            k = int(g.integers(query_rows[0], query_rows[1] + 1))
+            out.append(TraceRequest(t, "predict", k, d_model, int(g.integers(0, pool_queries))))
+    return out
+
+
+def take_rows(pool, offset, rows):
+    """rows consecutive rows of pool starting at offset, wrapping around."""
+    idx = (offset + np.arange(rows)) % pool.shape[0]
+    return np.ascontiguousarray(pool[idx])

@@ -46,6 +46,28 @@ class PartInfo(ctypes.Structure):
                 ("fallback", ctypes.c_int32), ("reserved", ctypes.c_int32), ("rel_residual", ctypes.c_double)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("predict_workers", ctypes.c_int32), ("fit_workers", ctypes.c_int32),
+                ("max_batch_fits", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_batch_points", ctypes.c_int64), ("hbm_budget_bytes", ctypes.c_size_t)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("kind", ctypes.c_int32), ("batch_requests", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("predict_requests", ctypes.c_int64), ("fit_requests", ctypes.c_int64),
+                ("points", ctypes.c_int64), ("fit_rows", ctypes.c_int64),
+                ("predict_batches", ctypes.c_int64), ("fit_batches", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("max_inflight_bytes", ctypes.c_int64),
+                ("predict_p50_ms", ctypes.c_double), ("predict_p99_ms", ctypes.c_double),
+                ("fit_p50_ms", ctypes.c_double), ("fit_p99_ms", ctypes.c_double),
+                ("span_ms", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 _SIGS = {
     "krr_create": ([ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(_P)], ctypes.c_int),
@@ -64,6 +86,14 @@ _SIGS = {
                     ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "krr_model_alpha": ([_P, _P, _P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "krr_model_free": ([_P], ctypes.c_int),
+    "krr_server_create": ([_P, _P, ctypes.POINTER(ServerConfig), ctypes.POINTER(_P)], ctypes.c_int),
+    "krr_server_destroy": ([_P], ctypes.c_int),
+    "krr_server_last_error": ([_P], ctypes.c_char_p),
+    "krr_server_submit_predict": ([_P, _P, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "krr_server_submit_fit": ([_P, _P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(FitParams), _P,
+                               ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "krr_server_wait": ([_P, ctypes.c_int64, ctypes.POINTER(RequestInfo)], ctypes.c_int),
+    "krr_server_stats": ([_P, ctypes.c_int32, ctypes.POINTER(ServeStats)], ctypes.c_int),
 }
 
 _lib = None
@@ -236,6 +266,81 @@ class Context:
         self._check(self.lib.krr_select(self.h, _stream(self.device), hs, len(models), _ptr(Xv), _ptr(yv),
                                         _dtype_code(Xv), k, ROUTE[route], mse, ctypes.byref(best)))
         return list(mse), best.value
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request server around a resident model (see the
+    serving section of include/krr.h).  Requests carry host numpy arrays;
+    the arrays are kept referenced here until the request is waited for."""
+
+    def __init__(self, ctx, model, predict_workers=2, fit_workers=1, max_batch_fits=16,
+                 max_batch_points=16384, hbm_budget=0):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.model = model
+        cfg = ServerConfig(int(predict_workers), int(fit_workers), int(max_batch_fits), 0,
+                           int(max_batch_points), int(hbm_budget))
+        h = ctypes.c_void_p()
+        st = self.lib.krr_server_create(ctx.h, model.handle, ctypes.byref(cfg), ctypes.byref(h))
+        if st != KRR_OK:
+            raise KrrError(st, "krr_server_create failed: " + ctx.lib.krr_last_error(ctx.h).decode())
+        self.h = h
+        self._keep = {}
+
+    def _check(self, st):
+        if st != KRR_OK:
+            raise KrrError(st, self.lib.krr_server_last_error(self.h).decode())
+
+    def submit_predict(self, Xq):
+        """Xq: host float32 k x d.  Returns a ticket."""
+        import numpy as np
+        Xq = np.ascontiguousarray(Xq, dtype=np.float32)
+        out = np.empty(Xq.shape[0], dtype=np.float64)
+        t = ctypes.c_int64(0)
+        self._check(self.lib.krr_server_submit_predict(self.h, Xq.ctypes.data, Xq.shape[0], out.ctypes.data,
+                                                        ctypes.byref(t)))
+        self._keep[t.value] = (Xq, out)
+        return t.value
+
+    def submit_fit(self, X, y, params):
+        """X: host float32 m x d, y: host float32 m, params: Params.  Returns a ticket."""
+        import numpy as np
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        out = np.empty(X.shape[0], dtype=np.float64)
+        cp = params.to_c()
+        t = ctypes.c_int64(0)
+        self._check(self.lib.krr_server_submit_fit(self.h, X.ctypes.data, y.ctypes.data, X.shape[0], X.shape[1],
+                                                    ctypes.byref(cp), out.ctypes.data, ctypes.byref(t)))
+        self._keep[t.value] = (X, y, out)
+        return t.value
+
+    def wait(self, ticket):
+        """Block until the request is done.  Returns (result array, info dict);
+        a failed request raises KrrError."""
+        info = RequestInfo()
+        st = self.lib.krr_server_wait(self.h, int(ticket), ctypes.byref(info))
+        keep = self._keep.pop(int(ticket), None)
+        if st != KRR_OK:
+            raise KrrError(st, self.lib.krr_server_last_error(self.h).decode())
+        return keep[-1], {f: getattr(info, f) for f, _ in RequestInfo._fields_}
+
+    def stats(self, reset=False):
+        s = ServeStats()
+        self._check(self.lib.krr_server_stats(self.h, int(bool(reset)), ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServeStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.krr_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
 
     def __del__(self):
         try:

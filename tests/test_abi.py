@@ -30,3 +30,9 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(krr.FitParams) == 40
     # krr_part_info: 8 x int32 + double -> 40 bytes
     assert ctypes.sizeof(krr.PartInfo) == 40
+    # krr_server_config: 4 x int32, int64, size_t -> 32 bytes
+    assert ctypes.sizeof(krr.ServerConfig) == 32
+    # krr_request_info: 4 x int32 + 3 doubles -> 40 bytes
+    assert ctypes.sizeof(krr.RequestInfo) == 40
+    # krr_serve_stats: 8 x int64 + 5 doubles -> 104 bytes
+    assert ctypes.sizeof(krr.ServeStats) == 104
