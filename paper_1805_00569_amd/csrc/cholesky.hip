@@ -37,24 +37,28 @@ __device__ __forceinline__ int64_t tile_index(int i, int j) { return (int64_t)i 
 
 // ---------------------------------------------------------------------------
 // Diagonal block: A(k,k) = L L^T in FP64 and Winv(k) = L^-1, one workgroup of
-// two waves per system, with the matrix held in registers.
-//   Wave 0 (factor): lane r holds row r of the working matrix, shifted so
-//   that a[c] = A(r, j + c) at step j.  Step j takes the pivot from lane j,
-//   forms L(r, j), publishes column j of L through LDS and applies the rank-1
-//   update of the remaining columns, writing each result one register to the
-//   left so that the next step's column is again a[0].  The register index
-//   stays a compile-time constant, and only the live window of 64 - j
-//   columns (rounded up to a multiple of 8) is touched.
-//   Wave 1 (inverse): lane t holds column t of W = L^-1 as the right-hand
-//   side e_t of L w = e_t, shifted the same way, and runs forward
-//   substitution one step behind wave 0, reading the column of L that wave 0
-//   published in the previous step (a ring of two LDS slots, one barrier per
-//   step).
+// two waves per system, with the matrix held in registers.  The block is
+// factored as A = U D^-1 U^T (U = L D^1/2: the columns of the successive
+// Schur complements, D the pivots), so a column step needs one reciprocal
+// and no square root on its dependency chain; L = U D^-1/2 and
+// L^-1 = D^-1/2 U~^-1 (U~ = U D^-1, unit lower triangular) are formed at the
+// end.
+//   Wave 0 (factor): lane r holds row r of the working matrix.  Step j takes
+//   the pivot d_j from lane j (computed by that lane at the end of step j-1),
+//   publishes column j of the Schur complement (u, zero at and above the
+//   diagonal) and 1/d_j through LDS, and applies a(r, c) -= (u_r / d_j) u_c.
+//   Wave 1 (inverse): lane t holds column t of X = U~^-1 as the right-hand
+//   side e_t of U~ x = e_t and runs the unit forward substitution step j
+//   right after the barrier that publishes column j (a ring of two LDS slots,
+//   one barrier per step).
+// The 64 steps run as 8 straight-line groups of 8; group g keeps only the
+// live columns [8g, 64) in registers (index c - 8g), so register indices are
+// compile-time constants and no step touches a finished column.
 // A pivot that is not positive (or NaN) marks the system failed with the
 // LAPACK-style 1-based global column index.
 // ---------------------------------------------------------------------------
 constexpr int DIAG_THREADS = 128;
-constexpr int SW_LD = NB + 1;   // padded LDS column of the staged inverse
+constexpr int SW_LD = NB + 1;   // padded LDS column of the staged results
 
 __device__ __forceinline__ double read_lane(double v, int lane) {
   const long long b = __double_as_longlong(v);
@@ -63,29 +67,72 @@ __device__ __forceinline__ double read_lane(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// v[c - 1] = v[c] - s * col[c] for 1 <= c < W (col[c] = L(j + c, j)); v[W - 1]
-// keeps a stale value outside the live window.
+// 1 / d: hardware reciprocal estimate refined by two Newton steps
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
+struct DiagShared {
+  double slot[2][NB + 2];   // slot[b][c] = u_c of step j (j % 2 == b), 0 for c <= j; slot[b][NB] = 1 / d_j
+  double sU[NB * SW_LD];    // sU[j * SW_LD + r] = u_r of step j (0 above the diagonal)
+  double sX[NB * SW_LD];    // sX[t * SW_LD + j] = X(j, t)
+  double sd[NB];            // pivots, then 1 / sqrt(pivot)
+  int fail;
+};
+
+// Steps [J0, J0 + 8) with J0 = NB - W; v[c] holds column J0 + c.
 template <int W>
-__device__ __forceinline__ void shift_update(double (&v)[NB], double s, const double* __restrict__ col) {
+__device__ __forceinline__ void diag_group(bool factor_wave, int lane, double (&v)[W], double& piv,
+                                           DiagShared& sh) {
+  constexpr int J0 = NB - W;
 #pragma unroll
-  for (int c = 0; c < W; c += 2) {
-    const double2 b = *reinterpret_cast<const double2*>(col + c);
-    if (c > 0) v[c - 1] = fma(-s, b.x, v[c]);
-    v[c] = fma(-s, b.y, v[c + 1]);
+  for (int q = 0; q < 8; ++q) {
+    const int j = J0 + q;
+    double* sl = sh.slot[q & 1];
+    double s = 0.0;
+    if (factor_wave) {
+      if (!(piv > 0.0)) {
+        if (lane == 0) sh.fail = j + 1;
+      } else {
+        const double rcp = recip(piv);
+        const double u = v[q];
+        s = lane > j ? u * rcp : 0.0;
+        sl[lane] = lane > j ? u : 0.0;
+        sh.sU[j * SW_LD + lane] = lane >= j ? u : 0.0;
+        if (lane == 0) {
+          sl[NB] = rcp;
+          sh.sd[j] = piv;
+        }
+        if (q + 1 < W) piv = read_lane(fma(-s, u, v[q + 1]), j + 1);   // next pivot, owned by lane j+1
+      }
+    }
+    __syncthreads();
+    if (sh.fail) return;
+    if (!factor_wave) {
+      const double x = v[q];   // X(j, t)
+      sh.sX[lane * SW_LD + j] = x;
+      s = x * sl[NB];
+    }
+    // a(., c) -= s * u_c for the columns c > j of the group's window
+    const double* col = sl + J0;
+#pragma unroll
+    for (int c = (q + 1) & ~1; c < W; c += 2) {
+      const double2 b = *reinterpret_cast<const double2*>(col + c);
+      if (c > q) v[c] = fma(-s, b.x, v[c]);
+      v[c + 1] = fma(-s, b.y, v[c + 1]);
+    }
   }
 }
 
-__device__ __forceinline__ void shift_update_step(int j, double (&v)[NB], double s, const double* col) {
-  switch (j >> 3) {
-    case 0: shift_update<64>(v, s, col); break;
-    case 1: shift_update<56>(v, s, col); break;
-    case 2: shift_update<48>(v, s, col); break;
-    case 3: shift_update<40>(v, s, col); break;
-    case 4: shift_update<32>(v, s, col); break;
-    case 5: shift_update<24>(v, s, col); break;
-    case 6: shift_update<16>(v, s, col); break;
-    default: shift_update<8>(v, s, col); break;
-  }
+// drop the group's 8 finished columns
+template <int W>
+__device__ __forceinline__ void diag_shift(const double (&v)[W], double (&w)[W - 8]) {
+#pragma unroll
+  for (int c = 0; c < W - 8; ++c) w[c] = v[c + 8];
 }
 
 template <typename TS>
@@ -95,64 +142,69 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_potrf_diag(const SysDesc* __re
   const int s = blockIdx.x;
   const SysDesc D = desc[s];
   if (k >= D.T || st[s].status != 0 || D.level != level) return;
-  // slot[b][NB + c] = L(j + c, j) for the step j with j % 2 == b; slot[b][0] = 1 / L(j, j)
-  __shared__ __align__(16) double slot[2][2 * NB];
-  __shared__ double sW[NB * SW_LD];   // sW[t * SW_LD + i] = W(i, t)
-  __shared__ int sfail;
+  __shared__ __align__(16) DiagShared sh;
   TS* tile = A + D.a_off + tile_index(k, k) * TILE;
   const int lane = threadIdx.x & 63;
   const bool factor_wave = threadIdx.x < 64;
-  double v[NB];
+  double v64[NB];
   if (factor_wave) {
     // row `lane` of A(k,k); entries above the diagonal are never consumed
 #pragma unroll
-    for (int c = 0; c < NB; ++c) v[c] = (double)tile[c * NB + lane];
+    for (int c = 0; c < NB; ++c) v64[c] = (double)tile[c * NB + lane];
   } else {
 #pragma unroll
-    for (int c = 0; c < NB; ++c) v[c] = (c == lane) ? 1.0 : 0.0;
+    for (int c = 0; c < NB; ++c) v64[c] = (c == lane) ? 1.0 : 0.0;
   }
-  if (threadIdx.x == 0) sfail = 0;
+  if (threadIdx.x == 0) sh.fail = 0;
   __syncthreads();
-  double piv = factor_wave ? read_lane(v[0], 0) : 0.0;
-  for (int j = 0; j <= NB; ++j) {
-    if (factor_wave) {
-      if (j < NB) {
-        if (!(piv > 0.0)) {
-          if (lane == 0) sfail = j + 1;
-        } else {
-          const double ljj = sqrt(piv);
-          const double inv = 1.0 / ljj;
-          const double l = lane > j ? v[0] * inv : (lane == j ? ljj : 0.0);
-          double* sl = slot[j & 1];
-          sl[NB + lane - j] = l;
-          if (lane == 0) sl[0] = inv;
-          tile[j * NB + lane] = (TS)l;
-          __builtin_amdgcn_wave_barrier();
-          shift_update_step(j, v, l, sl + NB);
-          piv = read_lane(v[0], min(j + 1, NB - 1));
-        }
-      }
-    } else if (j > 0) {
-      const int i = j - 1;
-      const double* sl = slot[i & 1];
-      const double w = v[0] * sl[0];   // W(i, t)
-      sW[lane * SW_LD + i] = w;
-      shift_update_step(i, v, w, sl + NB);
-    }
-    __syncthreads();
-    if (sfail) break;
-  }
-  if (sfail) {
+  double piv = factor_wave ? read_lane(v64[0], 0) : 0.0;
+  do {
+    diag_group<64>(factor_wave, lane, v64, piv, sh);
+    if (sh.fail) break;
+    double v56[56];
+    diag_shift<64>(v64, v56);
+    diag_group<56>(factor_wave, lane, v56, piv, sh);
+    if (sh.fail) break;
+    double v48[48];
+    diag_shift<56>(v56, v48);
+    diag_group<48>(factor_wave, lane, v48, piv, sh);
+    if (sh.fail) break;
+    double v40[40];
+    diag_shift<48>(v48, v40);
+    diag_group<40>(factor_wave, lane, v40, piv, sh);
+    if (sh.fail) break;
+    double v32[32];
+    diag_shift<40>(v40, v32);
+    diag_group<32>(factor_wave, lane, v32, piv, sh);
+    if (sh.fail) break;
+    double v24[24];
+    diag_shift<32>(v32, v24);
+    diag_group<24>(factor_wave, lane, v24, piv, sh);
+    if (sh.fail) break;
+    double v16[16];
+    diag_shift<24>(v24, v16);
+    diag_group<16>(factor_wave, lane, v16, piv, sh);
+    if (sh.fail) break;
+    double v8[8];
+    diag_shift<16>(v16, v8);
+    diag_group<8>(factor_wave, lane, v8, piv, sh);
+  } while (false);
+  if (sh.fail) {
     if (threadIdx.x == 0) {
       st[s].status = KRR_ENOTSPD;
-      st[s].failed_pivot = k * NB + sfail;
+      st[s].failed_pivot = k * NB + sh.fail;
     }
     return;
   }
+  __syncthreads();
+  if (threadIdx.x < NB) sh.sd[threadIdx.x] = 1.0 / sqrt(sh.sd[threadIdx.x]);
+  __syncthreads();
+  // L(r, c) = u_r(c) / sqrt(d_c); W(r, c) = X(r, c) / sqrt(d_r)
   TS* wt = Wt + D.w_off + (int64_t)k * TILE;
   for (int e = threadIdx.x; e < TILE; e += DIAG_THREADS) {
     const int c = e >> 6, r = e & 63;
-    wt[e] = (TS)((r >= c) ? sW[c * SW_LD + r] : 0.0);
+    tile[e] = (TS)(sh.sU[c * SW_LD + r] * sh.sd[c]);
+    wt[e] = (TS)((r >= c) ? sh.sX[c * SW_LD + r] * sh.sd[r] : 0.0);
   }
 }
 
