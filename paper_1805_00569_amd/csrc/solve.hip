@@ -26,99 +26,212 @@ __device__ __forceinline__ bool skip_system(const SysStatus& S, int skip_converg
   return S.status != 0 || (skip_converged && (S.converged || S.stalled));
 }
 
-// z = L^-1 b.  Thread (r = t % 64, g = t / 64) handles row r and the column
-// subset c = g + 4q of every tile.
+// Thread layout of both solves: a workgroup of TRSV_G groups of 256 threads
+// per system; group g reads the tiles j = g, g + TRSV_G, ... of a tile row,
+// and thread t of a group owns rows 4 (t & 15) .. +3 and columns
+// (t >> 4) + 16 q (q < 4) of every tile it reads, with four 4-row vector
+// loads per tile and TRSV_JB tiles in flight, so that one workgroup keeps
+// enough loads outstanding to stream its factor at a useful share of HBM
+// bandwidth.  Partial sums are combined in LDS in a fixed order.
+// tiles in flight per thread: FP32 tiles 4, FP64 tiles 2 (128 registers per thread)
 template <typename TS>
-__global__ __launch_bounds__(256) void k_trsv_fwd(const SysDesc* __restrict__ desc, const SysStatus* __restrict__ st,
-                                                  const TS* __restrict__ A, const TS* __restrict__ Wt,
-                                                  const double* __restrict__ b, double* __restrict__ z,
-                                                  int skip_converged) {
+struct TrsvJB {
+  static constexpr int value = sizeof(TS) == 4 ? 4 : 2;
+};
+constexpr int TRSV_G = 4;
+constexpr int TRSV_THREADS = 256 * TRSV_G;
+
+__device__ __forceinline__ void load4(const float* __restrict__ p, float (&o)[4]) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  o[0] = v.x;
+  o[1] = v.y;
+  o[2] = v.z;
+  o[3] = v.w;
+}
+__device__ __forceinline__ void load4(const double* __restrict__ p, double (&o)[4]) {
+  const double2 a = reinterpret_cast<const double2*>(p)[0];
+  const double2 b = reinterpret_cast<const double2*>(p)[1];
+  o[0] = a.x;
+  o[1] = a.y;
+  o[2] = b.x;
+  o[3] = b.y;
+}
+
+// sum over the 16 lanes that share (t >> 4) (fixed butterfly order)
+__device__ __forceinline__ double quad16_sum(double v) {
+  for (int off = 1; off < 16; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// z = L^-1 b, tile row by tile row: u = b_i - sum_{j<i} L(i,j) z_j, then
+// z_i = Winv(i) u.
+template <typename TS>
+__global__ __launch_bounds__(TRSV_THREADS) void k_trsv_fwd(const SysDesc* __restrict__ desc,
+                                                           const SysStatus* __restrict__ st,
+                                                           const TS* __restrict__ A, const TS* __restrict__ Wt,
+                                                           const double* __restrict__ b, double* __restrict__ z,
+                                                           int skip_converged) {
+  constexpr int TRSV_JB = TrsvJB<TS>::value;
   const int s = blockIdx.x;
   const SysDesc D = desc[s];
   if (skip_system(st[s], skip_converged)) return;
-  __shared__ double sred[4][NB];
+  __shared__ double sred[TRSV_G * 16][NB];
   __shared__ double sv[NB];
-  const int t = threadIdx.x, r = t & 63, g = t >> 6;
+  const int t = threadIdx.x, grp = t >> 8, rq = t & 15, cg = (t >> 4) & 15;
   const TS* Ab = A + D.a_off;
   const double* bb = b + D.v_off;
   double* zz = z + D.v_off;
   for (int i = 0; i < D.T; ++i) {
-    double acc = 0.0;
-    for (int j = 0; j < i; ++j) {
-      const TS* L = Ab + tile_index(i, j) * TILE;
-      const double* zj = zz + j * NB;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const TS* row = Ab + tile_index(i, 0) * TILE;   // tiles (i, 0 .. i-1) are contiguous
+    int j = grp;
+    for (; j + TRSV_G * (TRSV_JB - 1) < i; j += TRSV_G * TRSV_JB) {
+      TS lv[TRSV_JB][4][4];
+      double zv[TRSV_JB][4];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int c = g + 4 * q;
-        acc = fma((double)L[c * NB + r], zj[c], acc);
+      for (int u = 0; u < TRSV_JB; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c = cg + 16 * q;
+          load4(row + (int64_t)(j + TRSV_G * u) * TILE + c * NB + 4 * rq, lv[u][q]);
+          zv[u][q] = zz[(j + TRSV_G * u) * NB + c];
+        }
+#pragma unroll
+      for (int u = 0; u < TRSV_JB; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) acc[k] = fma((double)lv[u][q][k], zv[u][q], acc[k]);
+    }
+    for (; j < i; j += TRSV_G) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = cg + 16 * q;
+        TS lv[4];
+        load4(row + (int64_t)j * TILE + c * NB + 4 * rq, lv);
+        const double zc = zz[j * NB + c];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] = fma((double)lv[k], zc, acc[k]);
       }
     }
-    sred[g][r] = acc;
-    __syncthreads();
-    if (t < NB) sv[r] = bb[i * NB + r] - ((sred[0][r] + sred[1][r]) + (sred[2][r] + sred[3][r]));
-    __syncthreads();
-    const TS* W = Wt + D.w_off + (int64_t)i * TILE;
-    double acc2 = 0.0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int c = g + 4 * q;
-      acc2 = fma((double)W[c * NB + r], sv[c], acc2);
-    }
-    sred[g][r] = acc2;
+    for (int k = 0; k < 4; ++k) sred[grp * 16 + cg][4 * rq + k] = acc[k];
     __syncthreads();
-    if (t < NB) zz[i * NB + r] = (sred[0][r] + sred[1][r]) + (sred[2][r] + sred[3][r]);
+    if (t < NB) {
+      double sum = 0.0;
+#pragma unroll 16
+      for (int g = 0; g < TRSV_G * 16; ++g) sum += sred[g][t];
+      sv[t] = bb[i * NB + t] - sum;
+    }
+    __syncthreads();
+    if (grp == 0) {
+      const TS* W = Wt + D.w_off + (int64_t)i * TILE;
+      double acc2[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = cg + 16 * q;
+        TS wv[4];
+        load4(W + c * NB + 4 * rq, wv);
+        const double uc = sv[c];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc2[k] = fma((double)wv[k], uc, acc2[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sred[cg][4 * rq + k] = acc2[k];
+    }
+    __syncthreads();
+    if (t < NB) {
+      double sum = 0.0;
+#pragma unroll
+      for (int g = 0; g < 16; ++g) sum += sred[g][t];
+      zz[i * NB + t] = sum;
+    }
     __syncthreads();
   }
 }
 
-// x = L^-T z (and alpha += x when `alpha_acc` is given).  For the transposed
-// tiles every thread keeps one partial per column c = g + 4q and the 64 rows
-// are summed across the wavefront once per tile row.
+// x = L^-T z (and alpha += x when `alpha_acc` is given), tile row i from the
+// last: u = z_i - sum_{j>i} L(j,i)^T x_j, then x_i = Winv(i)^T u.
 template <typename TS>
-__global__ __launch_bounds__(256) void k_trsv_bwd(const SysDesc* __restrict__ desc, const SysStatus* __restrict__ st,
-                                                  const TS* __restrict__ A, const TS* __restrict__ Wt,
-                                                  const double* __restrict__ z, double* __restrict__ x,
-                                                  double* __restrict__ alpha_acc, int skip_converged) {
+__global__ __launch_bounds__(TRSV_THREADS) void k_trsv_bwd(const SysDesc* __restrict__ desc,
+                                                           const SysStatus* __restrict__ st,
+                                                           const TS* __restrict__ A, const TS* __restrict__ Wt,
+                                                           const double* __restrict__ z, double* __restrict__ x,
+                                                           double* __restrict__ alpha_acc, int skip_converged) {
+  constexpr int TRSV_JB = TrsvJB<TS>::value - (sizeof(TS) == 4 ? 1 : 0);   // the x blocks are FP64
   const int s = blockIdx.x;
   const SysDesc D = desc[s];
   if (skip_system(st[s], skip_converged)) return;
+  __shared__ double sp[TRSV_G][NB];
   __shared__ double su[NB];
-  const int t = threadIdx.x, lane = t & 63, g = t >> 6;
+  const int t = threadIdx.x, grp = t >> 8, rq = t & 15, cg = (t >> 4) & 15;
   const TS* Ab = A + D.a_off;
   const double* zz = z + D.v_off;
   double* xx = x + D.v_off;
   for (int i = D.T - 1; i >= 0; --i) {
-    double part[16];
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
+    int j = i + 1 + grp;
+    for (; j + TRSV_G * (TRSV_JB - 1) < D.T; j += TRSV_G * TRSV_JB) {
+      TS lv[TRSV_JB][4][4];
+      double xv[TRSV_JB][4];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) part[q] = 0.0;
-    for (int j = i + 1; j < D.T; ++j) {
-      const TS* L = Ab + tile_index(j, i) * TILE;   // (L^T)(i,j) = L(j,i)^T
-      const double xj = xx[j * NB + lane];
+      for (int u = 0; u < TRSV_JB; ++u) {
+        const TS* L = Ab + tile_index(j + TRSV_G * u, i) * TILE;   // (L^T)(i,j) = L(j,i)^T
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int c = g + 4 * q;
-        part[q] = fma((double)L[c * NB + lane], xj, part[q]);
+        for (int q = 0; q < 4; ++q) load4(L + (cg + 16 * q) * NB + 4 * rq, lv[u][q]);
+        load4(xx + (j + TRSV_G * u) * NB + 4 * rq, xv[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < TRSV_JB; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) part[q] = fma((double)lv[u][q][k], xv[u][k], part[q]);
+    }
+    for (; j < D.T; j += TRSV_G) {
+      const TS* L = Ab + tile_index(j, i) * TILE;
+      double xv[4];
+      load4(xx + j * NB + 4 * rq, xv);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        TS lv[4];
+        load4(L + (cg + 16 * q) * NB + 4 * rq, lv);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) part[q] = fma((double)lv[k], xv[k], part[q]);
       }
     }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const double v = wave_sum(part[q]);
-      if (lane == 0) {
-        const int c = g + 4 * q;
-        su[c] = zz[i * NB + c] - v;
-      }
+    for (int q = 0; q < 4; ++q) {
+      const double v = quad16_sum(part[q]);
+      if (rq == 0) sp[grp][cg + 16 * q] = v;
     }
     __syncthreads();
-    // x_i = Winv(i)^T u: x_i[c] = sum_r W(r, c) u[r], W(r, c) at c * NB + r
-    const TS* W = Wt + D.w_off + (int64_t)i * TILE;
-    const double ul = su[lane];
+    if (t < NB) {
+      double sum = 0.0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int c = g + 4 * q;
-      const double v = wave_sum((double)W[c * NB + lane] * ul);
-      if (lane == 0) {
-        xx[i * NB + c] = v;
-        if (alpha_acc != nullptr) alpha_acc[D.v_off + i * NB + c] += v;
+      for (int g = 0; g < TRSV_G; ++g) sum += sp[g][t];
+      su[t] = zz[i * NB + t] - sum;
+    }
+    __syncthreads();
+    if (grp == 0) {
+      // x_i[c] = sum_r W(r, c) u[r], W(r, c) at c * NB + r
+      const TS* W = Wt + D.w_off + (int64_t)i * TILE;
+      double ur[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) ur[k] = su[4 * rq + k];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = cg + 16 * q;
+        TS wv[4];
+        load4(W + c * NB + 4 * rq, wv);
+        double p = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) p = fma((double)wv[k], ur[k], p);
+        const double v = quad16_sum(p);
+        if (rq == 0) {
+          xx[i * NB + c] = v;
+          if (alpha_acc != nullptr) alpha_acc[D.v_off + i * NB + c] += v;
+        }
       }
     }
     __syncthreads();
@@ -231,10 +344,10 @@ void trsv_forward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, con
                   const void* A, const void* Wt, const double* b, double* z, int skip_converged) {
   KernelTimer kt(ctx, s, "trsv_forward", 0.0, 0);
   if (prec == KRR_PREC_FP64)
-    hipLaunchKernelGGL((k_trsv_fwd<double>), dim3(n_sys), dim3(256), 0, s, desc, st, (const double*)A,
+    hipLaunchKernelGGL((k_trsv_fwd<double>), dim3(n_sys), dim3(TRSV_THREADS), 0, s, desc, st, (const double*)A,
                        (const double*)Wt, b, z, skip_converged);
   else
-    hipLaunchKernelGGL((k_trsv_fwd<float>), dim3(n_sys), dim3(256), 0, s, desc, st, (const float*)A,
+    hipLaunchKernelGGL((k_trsv_fwd<float>), dim3(n_sys), dim3(TRSV_THREADS), 0, s, desc, st, (const float*)A,
                        (const float*)Wt, b, z, skip_converged);
   check_launch(ctx, s, "trsv_fwd");
 }
@@ -243,10 +356,10 @@ void trsv_backward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, co
                    const void* A, const void* Wt, const double* z, double* x, double* alpha_acc, int skip_converged) {
   KernelTimer kt(ctx, s, "trsv_backward", 0.0, 0);
   if (prec == KRR_PREC_FP64)
-    hipLaunchKernelGGL((k_trsv_bwd<double>), dim3(n_sys), dim3(256), 0, s, desc, st, (const double*)A,
+    hipLaunchKernelGGL((k_trsv_bwd<double>), dim3(n_sys), dim3(TRSV_THREADS), 0, s, desc, st, (const double*)A,
                        (const double*)Wt, z, x, alpha_acc, skip_converged);
   else
-    hipLaunchKernelGGL((k_trsv_bwd<float>), dim3(n_sys), dim3(256), 0, s, desc, st, (const float*)A,
+    hipLaunchKernelGGL((k_trsv_bwd<float>), dim3(n_sys), dim3(TRSV_THREADS), 0, s, desc, st, (const float*)A,
                        (const float*)Wt, z, x, alpha_acc, skip_converged);
   check_launch(ctx, s, "trsv_bwd");
 }
