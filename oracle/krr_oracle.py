@@ -145,9 +145,15 @@ def kmeanspp(X: np.ndarray, k: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
     return X[chosen].copy(), np.array(chosen, dtype=np.int64)
 
 
+MEANS_BLOCK = 256
+
+
 def member_means(X: np.ndarray, a: np.ndarray, C_prev: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
-    """Algorithm 2 mean step: CT_j = (sum of members, sequential in increasing
-    index) / count_j; an empty cluster keeps C_prev[j]."""
+    """Algorithm 2 mean step: CT_j = (sum of members) / count_j; an empty
+    cluster keeps C_prev[j].  Algorithm 2 leaves the order of the sum open;
+    here the members, in increasing index order, are summed in blocks of
+    MEANS_BLOCK consecutive members (sequentially inside a block), and the
+    block totals are summed sequentially."""
     X = np.asarray(X, dtype=np.float64)
     k = C_prev.shape[0]
     C = C_prev.copy()
@@ -156,8 +162,11 @@ def member_means(X: np.ndarray, a: np.ndarray, C_prev: np.ndarray) -> tuple[np.n
         if counts[j] == 0:
             continue
         members = X[a == j]                          # increasing index order
-        s = np.cumsum(members, axis=0)[-1]           # sequential accumulate
-        C[j] = s / float(counts[j])
+        total = np.zeros(X.shape[1])
+        for b0 in range(0, members.shape[0], MEANS_BLOCK):
+            block = np.cumsum(members[b0:b0 + MEANS_BLOCK], axis=0)[-1]   # sequential accumulate
+            total = total + block
+        C[j] = total / float(counts[j])
     return C, counts
 
 

@@ -213,6 +213,25 @@ def test_lloyd_objective_nonincreasing_and_fixed_point():
         np.testing.assert_array_equal(af, a2)
 
 
+def test_member_means_is_the_mean():
+    """Many members (several summation blocks): every centre is the mean of
+    its members within a few ulps of the exactly rounded sum (math.fsum), and
+    a constant cluster reproduces its value exactly."""
+    g = np.random.default_rng(3)
+    X = g.standard_normal((3000, 3)) * np.array([1.0, 1e3, 1e-3])
+    a = g.integers(0, 4, 3000).astype(np.int32)
+    X[a == 3] = 0.625
+    C, counts = O.member_means(X, a, np.zeros((4, 3)))
+    for j in range(4):
+        mem = X[a == j]
+        assert counts[j] == mem.shape[0] > 512
+        for f in range(3):
+            exact = math.fsum(mem[:, f]) / mem.shape[0]
+            scale = np.abs(mem[:, f]).sum() / mem.shape[0]
+            assert abs(C[j, f] - exact) <= 64 * np.finfo(float).eps * scale
+    assert np.all(C[3] == 0.625)
+
+
 def test_empty_cluster_keeps_centre():
     X = np.array([[0.0, 0.0], [0.1, 0.0], [5.0, 5.0]])
     C0 = np.array([[0.0, 0.0], [5.0, 5.0], [100.0, 100.0]])
