@@ -259,86 +259,99 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_group_scatter(const int32_t* __
 }
 
 // ---------------------------------------------------------------------------
-// Means of the grouped members: C[j][f] = (sum of member values in increasing
-// point order, FP64) / count_j.  Empty partitions keep their centre.
-// The members are first gathered into contiguous rows (Xg = X[perm], one
-// parallel pass); the mean kernel then streams a partition's rows in chunks
-// through LDS, loading chunk c+1 while it sums chunk c, so the sequential
-// FP64 sums never wait on memory.
-// Lloyd passes: `skip` is this pass's "fixed point reached" flag; block 0
-// writes the next pass's flag (set when this pass was skipped or changed no
-// assignment), so no block of a launch reads a flag that the launch writes.
+// Means of the grouped members: C[j][f] = (sum of member values) / count_j,
+// FP64; empty partitions keep their centre.  The members of partition j, in
+// increasing point order (the stable grouping perm), are summed in blocks of
+// MEANS_BLOCK consecutive members, sequentially inside a block, and the block
+// totals are summed in block order.  Three launches: block offsets per
+// partition, one workgroup per (partition, block) for the partial sums (rows
+// read through perm, no gathered copy), and the per-partition totals.
+// Lloyd passes: `skip` is this pass's "fixed point reached" flag; block 0 of
+// the final launch writes the next pass's flag (set when this pass was
+// skipped or changed no assignment), so no workgroup of a launch reads a flag
+// that the same launch writes.
 // ---------------------------------------------------------------------------
-constexpr int MEANS_THREADS = 256;
-constexpr int MEANS_LPT = 16;                               // staged values per thread and chunk
-constexpr int MEANS_CHUNK = MEANS_THREADS * MEANS_LPT;      // values per chunk
+constexpr int MEANS_BLOCK = 256;
+constexpr int MEANS_THREADS = 128;
 
-template <typename TX>
-__global__ void k_gather_grouped(const TX* __restrict__ X, int64_t n, int d, const int32_t* __restrict__ perm,
-                                 TX* __restrict__ Xg, const int32_t* __restrict__ skip) {
+// boff[j] = number of member blocks of partitions < j (boff[p] = total)
+__global__ __launch_bounds__(1024) void k_means_blockoff(const int64_t* __restrict__ offsets, int p,
+                                                         int32_t* __restrict__ boff,
+                                                         const int32_t* __restrict__ skip) {
   if (skip != nullptr && *skip) return;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * d) return;
-  const int64_t r = e / d;
-  Xg[e] = X[(int64_t)perm[r] * d + (e - r * d)];
+  __shared__ int32_t sc[1024];
+  const int t = threadIdx.x;
+  const int nb = t < p ? (int)((offsets[t + 1] - offsets[t] + MEANS_BLOCK - 1) / MEANS_BLOCK) : 0;
+  sc[t] = nb;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {   // inclusive scan
+    const int v = t >= off ? sc[t - off] : 0;
+    __syncthreads();
+    sc[t] += v;
+    __syncthreads();
+  }
+  if (t < p) boff[t + 1] = sc[t];
+  if (t == 0) boff[0] = 0;
 }
 
 template <typename TX>
-__global__ __launch_bounds__(MEANS_THREADS) void k_means(const TX* __restrict__ Xg, int d,
-                                                         const int64_t* __restrict__ offsets, double* __restrict__ C,
-                                                         const int32_t* __restrict__ skip,
-                                                         const int32_t* __restrict__ delta,
-                                                         int32_t* __restrict__ done_next) {
+__global__ __launch_bounds__(MEANS_THREADS) void k_means_partial(const TX* __restrict__ X, int d,
+                                                                 const int32_t* __restrict__ perm,
+                                                                 const int64_t* __restrict__ offsets, int p,
+                                                                 const int32_t* __restrict__ boff,
+                                                                 double* __restrict__ part,
+                                                                 const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip) return;
+  const int g = blockIdx.x;
+  if (g >= boff[p]) return;
+  int lo = 0, hi = p - 1;   // partition j: boff[j] <= g < boff[j + 1]
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (boff[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  const int j = lo;
+  const int64_t r0 = offsets[j] + (int64_t)(g - boff[j]) * MEANS_BLOCK;
+  const int nr = (int)min<int64_t>(MEANS_BLOCK, offsets[j + 1] - r0);
+  __shared__ int64_t rows[MEANS_BLOCK];
+  for (int q = threadIdx.x; q < MEANS_BLOCK; q += MEANS_THREADS)
+    rows[q] = (int64_t)perm[r0 + min(q, nr - 1)] * d;   // clamped: in range, never summed past nr
+  __syncthreads();
+  for (int f = threadIdx.x; f < d; f += MEANS_THREADS) {
+    double acc = 0.0;
+    int q = 0;
+    for (; q + 8 <= nr; q += 8) {   // 8 independent loads, then 8 ordered adds
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = (double)X[rows[q + u] + f];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = add_sep(acc, v[u]);
+    }
+    for (; q < nr; ++q) acc = add_sep(acc, (double)X[rows[q] + f]);
+    part[(int64_t)g * d + f] = acc;
+  }
+}
+
+__global__ __launch_bounds__(MEANS_THREADS) void k_means_total(const double* __restrict__ part, int d,
+                                                               const int64_t* __restrict__ offsets,
+                                                               const int32_t* __restrict__ boff,
+                                                               double* __restrict__ C,
+                                                               const int32_t* __restrict__ skip,
+                                                               const int32_t* __restrict__ delta,
+                                                               int32_t* __restrict__ done_next) {
   const int skipped = (skip != nullptr) ? *skip : 0;
   if (done_next != nullptr && blockIdx.x == 0 && threadIdx.x == 0)
     *done_next = (skipped || *delta == 0) ? 1 : 0;
   if (skipped) return;
-  __shared__ double sv[MEANS_CHUNK];
   const int j = blockIdx.x;
-  const int64_t o0 = offsets[j], o1 = offsets[j + 1];
-  const int64_t cnt = o1 - o0;
+  const int64_t cnt = offsets[j + 1] - offsets[j];
   if (cnt == 0) return;
-  const int t = threadIdx.x;
-  const int rows = max(1, MEANS_CHUNK / d);            // members per chunk (whole rows)
-  const int64_t vals = cnt * d;                        // contiguous values of this partition
-  const TX* base = Xg + o0 * d;
-  const int64_t per = (int64_t)rows * d;
-  // one feature per thread (d <= MEANS_THREADS; wider rows use k_means_wide)
-  const int fcl = min(t, d - 1);   // threads past d sum a discarded copy
-  double s0 = 0.0;
-  // loads are unconditional (a predicated load waits on its own); values past
-  // the partition land in LDS slots that the sums never read
-  double nxt[MEANS_LPT];
-#pragma unroll
-  for (int u = 0; u < MEANS_LPT; ++u) {
-    const int64_t e = t + (int64_t)u * MEANS_THREADS;
-    nxt[u] = (double)base[e];   // the grouped buffer is padded: always in bounds
+  const int b0 = boff[j], b1 = boff[j + 1];
+  for (int f = threadIdx.x; f < d; f += MEANS_THREADS) {
+    double acc = 0.0;
+    for (int b = b0; b < b1; ++b) acc = add_sep(acc, part[(int64_t)b * d + f]);
+    C[(int64_t)j * d + f] = acc / (double)cnt;
   }
-  for (int64_t c0 = 0; c0 < vals; c0 += per) {
-    const int64_t cl = min(per, vals - c0);
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < MEANS_LPT; ++u) sv[t + u * MEANS_THREADS] = nxt[u];
-    __syncthreads();
-    // prefetch the next chunk, then sum this one in member order
-    const int64_t c1 = c0 + per;
-#pragma unroll
-    for (int u = 0; u < MEANS_LPT; ++u) {
-      const int64_t e = t + (int64_t)u * MEANS_THREADS;
-      nxt[u] = (double)base[c1 + e];   // past the partition: padding, never summed
-    }
-    const int nr = (int)(cl / d);
-    int q = 0;
-    for (; q + 8 <= nr; q += 8) {   // 8 independent LDS reads, then 8 ordered adds
-      double v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = sv[(q + u) * d + fcl];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) s0 = add_sep(s0, v[u]);
-    }
-    for (; q < nr; ++q) s0 = add_sep(s0, sv[q * d + fcl]);
-  }
-  if (t < d) C[(int64_t)j * d + t] = s0 / (double)cnt;
 }
 
 // ---------------------------------------------------------------------------
@@ -619,41 +632,22 @@ void assign_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, const d
   check_launch(ctx, s, "assign");
 }
 
-// Wide rows (d > MEANS_CHUNK): one thread per (partition, feature).
-template <typename TX>
-__global__ void k_means_wide(const TX* __restrict__ Xg, int d, const int64_t* __restrict__ offsets,
-                             double* __restrict__ C, const int32_t* __restrict__ skip,
-                             const int32_t* __restrict__ delta, int32_t* __restrict__ done_next) {
-  const int skipped = (skip != nullptr) ? *skip : 0;
-  if (done_next != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
-    *done_next = (skipped || *delta == 0) ? 1 : 0;
-  if (skipped) return;
-  const int j = blockIdx.y;
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= d) return;
-  const int64_t o0 = offsets[j], o1 = offsets[j + 1];
-  if (o1 == o0) return;
-  double acc = 0.0;
-  for (int64_t o = o0; o < o1; ++o) acc = add_sep(acc, (double)Xg[o * d + f]);
-  C[(int64_t)j * d + f] = acc / (double)(o1 - o0);
-}
-
 template <typename TX>
 void means_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, const int32_t* perm, const int64_t* offsets,
              double* C, int p, const int32_t* skip, const int32_t* delta, int32_t* done_next) {
   KernelTimer kt(ctx, s, "lloyd_means", 0.0, 0);
-  // padded by two chunks so that the unconditional prefetch stays in bounds
-  TX* Xg = (TX*)ws_get(ctx, "means_xg", ((size_t)n * d + 2 * MEANS_CHUNK) * sizeof(TX));
-  hipLaunchKernelGGL((k_gather_grouped<TX>), dim3((unsigned)ceil_div(n * d, 256)), dim3(256), 0, s, X, n, d, perm,
-                     Xg, skip);
-  check_launch(ctx, s, "gather_grouped");
-  if (d <= MEANS_THREADS)
-    hipLaunchKernelGGL((k_means<TX>), dim3((unsigned)p), dim3(MEANS_THREADS), 0, s, (const TX*)Xg, d, offsets, C,
-                       skip, delta, done_next);
-  else
-    hipLaunchKernelGGL((k_means_wide<TX>), dim3((unsigned)ceil_div(d, 256), (unsigned)p), dim3(256), 0, s,
-                       (const TX*)Xg, d, offsets, C, skip, delta, done_next);
-  check_launch(ctx, s, "means");
+  const int64_t max_blocks = ceil_div(n, MEANS_BLOCK) + p;   // sum over partitions of ceil(m_j / MEANS_BLOCK)
+  char* w = (char*)ws_get(ctx, "means", (size_t)max_blocks * d * 8 + (size_t)(p + 1) * 4 + 256);
+  double* part = (double*)w;
+  int32_t* boff = (int32_t*)(w + (((size_t)max_blocks * d * 8 + 255) & ~size_t(255)));
+  hipLaunchKernelGGL(k_means_blockoff, dim3(1), dim3(1024), 0, s, offsets, p, boff, skip);
+  check_launch(ctx, s, "means_blockoff");
+  hipLaunchKernelGGL((k_means_partial<TX>), dim3((unsigned)max_blocks), dim3(MEANS_THREADS), 0, s, X, d, perm,
+                     offsets, p, (const int32_t*)boff, part, skip);
+  check_launch(ctx, s, "means_partial");
+  hipLaunchKernelGGL(k_means_total, dim3((unsigned)p), dim3(MEANS_THREADS), 0, s, (const double*)part, d, offsets,
+                     (const int32_t*)boff, C, skip, delta, done_next);
+  check_launch(ctx, s, "means_total");
 }
 
 template <typename TX>
