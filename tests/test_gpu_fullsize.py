@@ -1,0 +1,121 @@
+"""Full-size parity on sampled outputs, in the launch configuration the
+benchmark times.
+
+* Balanced workload (BKRR2, Algorithm 5): n = 65,536, d = 90, p = 16
+  K-balance partitions of 4,096, 3 sigma x 2 lambda = 96 systems in one
+  batch, mixed precision with refinement to 1e-6.
+* Ragged workload (KKRR2, Section 4.2): n = 131,072, d = 90, 32-component
+  Zipf-weighted Gaussian mixture, K-means with k-means++ and 20 Lloyd passes,
+  the 32 uneven systems in one batch, FP32.
+
+The oracle cannot factor every system of these sizes in seconds, so each test
+checks what it can compute one by one: the residual (K + lambda I) alpha - y
+on sampled rows (Eq. 6, kernel values by direct difference, FP64),
+predictions of sampled test points against Eq. 7 evaluated with the GPU's
+alpha, the partition relations (assignment = nearest final centre, sizes),
+and one full oracle solve per test."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1805_00569_amd import datagen, krr
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def _sampled_residual(Xj, yj, alpha, sigma, lam, rows):
+    K = O.kernel_matrix(Xj[rows], Xj, sigma)
+    r = yj[rows] - K @ alpha - lam * alpha[rows]
+    return float(np.linalg.norm(r) / np.linalg.norm(yj[rows]))
+
+
+def _check_predictions(ctx, dev, model, Xtr, a_np, C_np, alphas, sigma, Xt_in, yscale):
+    yhat = ctx.predict(model, _t(Xt_in, dev)).cpu().numpy()   # the training dtype
+    Xt = Xt_in.astype(np.float64)
+    route, _ = O.assign(Xt, C_np)
+    perm, off = O.gather(a_np, C_np.shape[0])
+    yo = np.zeros(Xt.shape[0])
+    for j in np.unique(route):
+        sel = np.nonzero(route == j)[0]
+        Xj = np.asarray(Xtr, np.float64)[perm[off[j]:off[j + 1]]]
+        yo[sel] = O.predict_one(Xj, alphas[j], Xt[sel], sigma)
+    den = max(np.linalg.norm(yo), 1e-3 * yscale)
+    assert np.linalg.norm(yhat - yo) / den < 1e-10
+
+
+def test_balanced_mixed_fullsize(ctx, dev):
+    print("full size: balanced n=65536 d=90 p=16, 96 mixed systems", flush=True)
+    w = datagen.balanced(seed=2)
+    X, y = _t(w.X, dev), _t(w.y.astype(np.float32), dev)
+    C, a, sz = ctx.partition(X, 16, "kbalance", lloyd_iters=20, seed=2)
+    a_np, C_np = a.cpu().numpy(), C.cpu().numpy()
+    assert sz.cpu().numpy().tolist() == [4096] * 16
+    params = [krr.Params(sigma=s, lam=l, prec="mixed", refine_tol=1e-6, max_refine=30)
+              for l in (1e-4, 1e-2) for s in (0.5, 1.0, 2.0)]
+    models, info, st = ctx.fit(X, y, a, C, 16, params)
+    assert st == 0 and all(r["status"] == 0 and r["rel_residual"] <= 1e-6 for r in info)
+    yo = w.y.astype(np.float32).astype(np.float64)
+    perm, off = O.gather(a_np, 16)
+    g = np.random.default_rng(0)
+    for q, prm in enumerate(params):
+        for j in (0, 7, 15):
+            idx = perm[off[j]:off[j + 1]]
+            Xj = w.X[idx].astype(np.float64)
+            alpha = models[q].alpha(j).cpu().numpy()
+            rows = g.choice(Xj.shape[0], 48, replace=False)
+            assert _sampled_residual(Xj, yo[idx], alpha, prm.sigma, prm.lam, rows) < 2e-6
+    # one full oracle solve: partition 3, sigma = 2, lambda = 1e-4 (the least diagonal setting)
+    idx = perm[off[3]:off[4]]
+    ref = O.fit_one(w.X[idx].astype(np.float64), yo[idx], 2.0, 1e-4)
+    assert _rel(models[2].alpha(3).cpu().numpy(), ref["alpha"]) < 1e-6
+    alphas = [models[2].alpha(j).cpu().numpy() for j in range(16)]
+    _check_predictions(ctx, dev, models[2], w.X, a_np, C_np, alphas, 2.0, w.Xt[:384],
+                       np.linalg.norm(w.yt[:384]))
+    for m in models:
+        m.free()
+
+
+def test_ragged_kmeans_fp32_fullsize(ctx, dev):
+    print("full size: ragged n=131072 d=90, 32 k-means partitions, FP32", flush=True)
+    w = datagen.gaussian_mixture(seed=3)
+    X, y = _t(w.X, dev), _t(w.y.astype(np.float32), dev)
+    C, a, sz = ctx.partition(X, 32, "kmeans", lloyd_iters=20, seed=3)
+    a_np, C_np, sz_np = a.cpu().numpy(), C.cpu().numpy(), sz.cpu().numpy()
+    # the partition is the assignment to the final centres (bit-exact) and its sizes
+    a_ref, _ = O.assign(w.X, C_np)
+    np.testing.assert_array_equal(a_np, a_ref)
+    np.testing.assert_array_equal(sz_np, np.bincount(a_np, minlength=32))
+    assert sz_np.max() > 4 * max(sz_np.min(), 1)   # ragged
+    prm = krr.Params(sigma=2.0, lam=1e-2, prec="fp32")
+    models, info, st = ctx.fit(X, y, a, C, 32, [prm])
+    assert st == 0 and all(r["status"] == 0 for r in info)
+    yo = w.y.astype(np.float32).astype(np.float64)
+    perm, off = O.gather(a_np, 32)
+    g = np.random.default_rng(1)
+    alphas = []
+    for j in range(32):
+        idx = perm[off[j]:off[j + 1]]
+        alpha = models[0].alpha(j).cpu().numpy()
+        alphas.append(alpha)
+        if idx.size == 0:
+            continue
+        Xj = w.X[idx].astype(np.float64)
+        rows = g.choice(Xj.shape[0], min(32, Xj.shape[0]), replace=False)
+        # FP32 factor of a well-conditioned K (sigma = 2 at d = 90: K close to I)
+        assert _sampled_residual(Xj, yo[idx], alpha, prm.sigma, prm.lam, rows) < 1e-5
+    j_small = int(np.argmin(np.where(sz_np > 0, sz_np, 1 << 30)))
+    idx = perm[off[j_small]:off[j_small + 1]]
+    ref = O.fit_one(w.X[idx].astype(np.float64), yo[idx], 2.0, 1e-2)
+    assert _rel(alphas[j_small], ref["alpha"]) < 1e-5
+    _check_predictions(ctx, dev, models[0], w.X, a_np, C_np, alphas, 2.0, w.Xt[:384],
+                       np.linalg.norm(w.yt[:384]))
+    models[0].free()
