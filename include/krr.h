@@ -167,8 +167,10 @@ krr_status krr_partition(krr_ctx ctx, hipStream_t stream,
  * X, y:      device, n x d and n, both of dtype `dtype`.
  * assign:    device, n int32 in [0, p): partition of each point.
  * centroids: device, p x d FP64 (kept in the models for routing).
- * params:    host, n_params settings, all fitted in one batch of
- *            n_params * p systems (K_j + lambda I) alpha_j = y_j.
+ * params:    host, n_params settings (1 <= n_params <= 4096,
+ *            n_params * p <= 65535), all fitted in one batch of
+ *            n_params * p systems (K_j + lambda I) alpha_j = y_j; all
+ *            settings of a call share the precision.
  * models_out: host array of n_params handles (one model per setting).
  * info_out:  host array of n_params * p records, index param * p + j.
  * Synchronises `stream`.  Returns KRR_ENOTSPD / KRR_ENOCONV if any system

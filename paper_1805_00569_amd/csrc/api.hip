@@ -284,6 +284,7 @@ krr_status krr_fit(krr_ctx ctx, hipStream_t stream, const void* X, const void* y
     KRR_REQUIRE(n >= 1 && d >= 1 && n < (int64_t(1) << 31) - 1, "bad n or d");
     KRR_REQUIRE(p >= 1 && p <= n && p <= 1024, "p must be in [1, min(n, 1024)]");
     KRR_REQUIRE(n_params >= 1 && n_params <= 4096, "n_params must be in [1, 4096]");
+    KRR_REQUIRE((int64_t)n_params * p <= 65535, "n_params * p must be <= 65535 (systems per batch)");
     for (int q = 0; q < n_params; ++q) {
       const krr_fit_params& P = params[q];
       KRR_REQUIRE(P.kernel == KRR_KERNEL_GAUSSIAN || P.kernel == KRR_KERNEL_LINEAR, "unknown kernel");

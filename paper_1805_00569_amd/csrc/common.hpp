@@ -64,6 +64,8 @@ struct SysDesc {
   int32_t kernel;      // krr_kernel
   int32_t level;       // precision level that factors this system in the current pass
   int64_t pk_off;      // element offset of its BF16 panel-pack slot (mixed precision)
+  int64_t k_off;       // mixed precision: element offset of the FP64 kernel tiles (without the
+                       // shift) shared by the settings of this partition with the same kernel and sigma
 };
 
 // Device-side status of one system.

@@ -17,10 +17,10 @@ void trsv_forward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, con
                   const void* A, const void* Wt, const double* b, double* z, int skip_converged);
 void trsv_backward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, const SysStatus* st, int n_sys,
                    const void* A, const void* Wt, const double* z, double* x, double* alpha_acc, int skip_converged);
-void residual_check(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, int n_sys, int Tmax,
-                    const double* K64, const double* alpha, const double* y, double* r, double* P,
-                    const int64_t* p_off, double* rn, double* yn, const int64_t* n_off, double tol,
-                    int will_refine, int32_t* active);
+void residual_check(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, int n_sys, int p, int n_groups,
+                    const int32_t* grp_first, const int32_t* grp_next, int Tmax, const double* K64,
+                    const double* alpha, const double* y, double* r, double* P, const int64_t* p_off, double* rn,
+                    double* yn, const int64_t* n_off, double tol, int will_refine, int32_t* active);
 
 namespace {
 
@@ -36,11 +36,17 @@ __device__ __forceinline__ int64_t tile_index(int i, int j) { return (int64_t)i 
 // on matrix cores (v_mfma_f64_16x16x4f64) and reused by every setting of the
 // partition: A_s(r, c) = exp(-(|x_r|^2 + |x_c|^2 - 2 G(r, c)) / (2 sigma_s^2)),
 // the diagonal set to exactly 1 + lambda_s; rows/columns past m are the
-// identity.  STORE: 0 -> FP64 tiles; 1 -> FP32 tiles; 2 -> FP32 tiles plus an
-// FP64 copy (for the refinement residual).
+// identity.  STORE: 0 -> FP64 tiles; 1 -> FP32 tiles; 2 -> FP32 tiles plus the
+// FP64 kernel tiles K (without the shift), written once for every group of
+// settings of the partition that share the kernel and sigma (settings that
+// differ only in lambda share K; the refinement residual adds each shift).
+// Settings are visited by group (grp_first[g], then grp_next[...]): the
+// kernel values are computed once per group and written to every setting of
+// the group with its own shift.
 template <typename TX, int STORE>
 __global__ __launch_bounds__(256) void k_form(const TX* __restrict__ Xg, int d, const SysDesc* __restrict__ desc,
-                                              int p, int n_params, void* __restrict__ Aout,
+                                              int p, int n_groups, const int32_t* __restrict__ grp_first,
+                                              const int32_t* __restrict__ grp_next, void* __restrict__ Aout,
                                               double* __restrict__ K64) {
   const int j = blockIdx.y;
   const SysDesc D0 = desc[j];
@@ -122,8 +128,10 @@ __global__ __launch_bounds__(256) void k_form(const TX* __restrict__ Xg, int d, 
   else if (t < 2 * NB) sNj[t - NB] = nrm;
   __syncthreads();
   const int64_t toff = tile_index(ti, tj) * TILE;
-  for (int q = 0; q < n_params; ++q) {
-    const SysDesc Dq = desc[q * p + j];
+  for (int g = 0; g < n_groups; ++g) {
+    int q = grp_first[g];
+    const SysDesc Dg = desc[q * p + j];
+    double kv[2][2][4];   // kernel values of the group (identity past m)
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
@@ -134,27 +142,31 @@ __global__ __launch_bounds__(256) void k_form(const TX* __restrict__ Xg, int d, 
           const int r = r0 + 16 * rb + il;
           const int gr = ti * NB + r, gc = tj * NB + c;
           const double G = acc[cb][rb][v];
-          double val;
-          if (gr >= m || gc >= m) {
-            val = (gr == gc) ? 1.0 : 0.0;
-          } else if (Dq.kernel == KRR_KERNEL_GAUSSIAN) {
-            if (gr == gc) {
-              val = 1.0 + Dq.lambda;
-            } else {
-              const double d2 = fmax(0.0, (sNi[r] + sNj[c]) - 2.0 * G);
-              val = exp(d2 * Dq.neg_inv_2s2);
-            }
-          } else {
-            val = (gr == gc) ? G + Dq.lambda : G;
-          }
-          const int64_t e = Dq.a_off + toff + c * NB + r;
-          if (STORE == 0) {
-            reinterpret_cast<double*>(Aout)[e] = val;
-          } else {
-            reinterpret_cast<float*>(Aout)[e] = (float)val;
-            if (STORE == 2) K64[e] = val;
-          }
+          double k;
+          if (gr >= m || gc >= m) k = (gr == gc) ? 1.0 : 0.0;
+          else if (Dg.kernel == KRR_KERNEL_GAUSSIAN)
+            k = (gr == gc) ? 1.0 : exp(fmax(0.0, (sNi[r] + sNj[c]) - 2.0 * G) * Dg.neg_inv_2s2);
+          else k = G;
+          kv[cb][rb][v] = k;
+          if (STORE == 2) K64[Dg.k_off + toff + c * NB + r] = k;
         }
+    for (; q >= 0; q = grp_next[q]) {
+      const SysDesc Dq = desc[q * p + j];
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int c = c0 + 16 * cb + kl + 4 * v;
+            const int r = r0 + 16 * rb + il;
+            const int gr = ti * NB + r, gc = tj * NB + c;
+            const double val = (gr == gc && gr < m) ? kv[cb][rb][v] + Dq.lambda : kv[cb][rb][v];
+            const int64_t e = Dq.a_off + toff + c * NB + r;
+            if (STORE == 0) reinterpret_cast<double*>(Aout)[e] = val;
+            else reinterpret_cast<float*>(Aout)[e] = (float)val;
+          }
+    }
   }
 }
 
@@ -184,8 +196,9 @@ __global__ void k_zero_status(SysStatus* st, int n) {
 }
 
 // Systems escalated to `level`: clear their failure / refinement state (the
-// refinement step count is kept) and copy the FP64 kernel tiles back into the
-// FP32 storage that the failed factorisation overwrote.
+// refinement step count is kept); k_restore_tiles rebuilds their FP32 tiles
+// from the shared FP64 kernel tiles plus the system's shift (the values
+// k_form wrote), since the failed factorisation overwrote them.
 __global__ void k_reset_level(const SysDesc* __restrict__ desc, SysStatus* __restrict__ st, int n, int level) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s < n && desc[s].level == level) {
@@ -202,10 +215,19 @@ __global__ __launch_bounds__(256) void k_restore_tiles(const SysDesc* __restrict
   const int s = blockIdx.y;
   const SysDesc D = desc[s];
   if (D.level != level) return;
-  const int64_t ntiles = (int64_t)D.T * (D.T + 1) / 2;
-  if ((int64_t)blockIdx.x >= ntiles) return;
-  const int64_t base = D.a_off + (int64_t)blockIdx.x * TILE;
-  for (int e = threadIdx.x; e < TILE; e += 256) A[base + e] = (float)K64[base + e];
+  const int bx = blockIdx.x;
+  int ti = (int)((sqrt(8.0 * (double)bx + 1.0) - 1.0) * 0.5);
+  while ((int64_t)ti * (ti + 1) / 2 > bx) --ti;
+  while ((int64_t)(ti + 1) * (ti + 2) / 2 <= bx) ++ti;
+  const int tj = bx - ti * (ti + 1) / 2;
+  if (ti >= D.T) return;
+  const int64_t toff = tile_index(ti, tj) * TILE;
+  for (int e = threadIdx.x; e < TILE; e += 256) {
+    const int c = e >> 6, r = e & 63;
+    const int gr = ti * NB + r, gc = tj * NB + c;
+    const double kv = K64[D.k_off + toff + e];
+    A[D.a_off + toff + e] = (float)((gr == gc && gr < D.m) ? kv + D.lambda : kv);
+  }
 }
 
 __global__ void k_zero_f64(double* a, int64_t n) {
@@ -220,18 +242,21 @@ __global__ void k_zero_i32(int32_t* a, int n) {
 
 template <typename TX>
 void launch_form(krr_ctx ctx, hipStream_t s, int prec, const void* Xg, int d, const SysDesc* desc, int p,
-                 int n_params, int Tmax, void* A, double* K64) {
+                 int n_groups, const int32_t* grp_first, const int32_t* grp_next, int Tmax, void* A, double* K64) {
   const int64_t ntri = (int64_t)Tmax * (Tmax + 1) / 2;
   if (ntri == 0) return;
   const dim3 grid((unsigned)ntri, (unsigned)p);
   const TX* X = (const TX*)Xg;
   KernelTimer kt(ctx, s, "form_kernel", 0.0, 0);
   if (prec == KRR_PREC_FP64)
-    hipLaunchKernelGGL((k_form<TX, 0>), grid, dim3(256), 0, s, X, d, desc, p, n_params, A, K64);
+    hipLaunchKernelGGL((k_form<TX, 0>), grid, dim3(256), 0, s, X, d, desc, p, n_groups, grp_first, grp_next, A,
+                       K64);
   else if (prec == KRR_PREC_FP32)
-    hipLaunchKernelGGL((k_form<TX, 1>), grid, dim3(256), 0, s, X, d, desc, p, n_params, A, K64);
+    hipLaunchKernelGGL((k_form<TX, 1>), grid, dim3(256), 0, s, X, d, desc, p, n_groups, grp_first, grp_next, A,
+                       K64);
   else
-    hipLaunchKernelGGL((k_form<TX, 2>), grid, dim3(256), 0, s, X, d, desc, p, n_params, A, K64);
+    hipLaunchKernelGGL((k_form<TX, 2>), grid, dim3(256), 0, s, X, d, desc, p, n_groups, grp_first, grp_next, A,
+                       K64);
   check_launch(ctx, s, "form");
 }
 
@@ -287,6 +312,33 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
   std::vector<SysDesc> desc(n_sys);
   std::vector<int64_t> p_off(n_sys), n_off(n_sys);
   int64_t a_tot = 0, w_tot = 0, v_tot = 0, p_tot = 0, n_tot = 0, pk_tot = 0;
+  // mixed precision: FP64 kernel tiles per (partition, group of settings with
+  // the same kernel and sigma); grp_first / grp_next list each group's settings
+  std::vector<int32_t> grp_of(n_params), grp_first, grp_next(n_params, -1);
+  for (int q = 0; q < n_params; ++q) {
+    int g = -1;
+    for (int h = 0; h < (int)grp_first.size() && g < 0; ++h) {
+      const krr_fit_params& P0 = params[grp_first[h]];
+      if (P0.kernel == params[q].kernel && (P0.kernel == KRR_KERNEL_LINEAR || P0.sigma == params[q].sigma)) g = h;
+    }
+    if (g < 0) {
+      g = (int)grp_first.size();
+      grp_first.push_back(q);
+    } else {
+      int last = grp_first[g];
+      while (grp_next[last] >= 0) last = grp_next[last];
+      grp_next[last] = q;
+    }
+    grp_of[q] = g;
+  }
+  const int n_groups = (int)grp_first.size();
+  std::vector<int64_t> k_off((size_t)n_groups * p);
+  int64_t k_tot = 0;
+  for (int g = 0; g < n_groups; ++g)
+    for (int jp = 0; jp < p; ++jp) {
+      k_off[(size_t)g * p + jp] = k_tot;
+      k_tot += tri(ceil_div(off[jp + 1] - off[jp], NB)) * TILE;
+    }
   int Tmax = 0;
   for (int q = 0; q < n_params; ++q)
     for (int jp = 0; jp < p; ++jp) {
@@ -306,6 +358,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
       D.level = 0;
       D.pk_off = pk_tot;
       pk_tot += (prec == KRR_PREC_MIXED) ? pack_slot_elems(D.T, ctx->panel_tiles) : 0;
+      D.k_off = k_off[(int64_t)grp_of[q] * p + jp];
       a_tot += tri(D.T) * TILE;
       w_tot += (int64_t)D.T * TILE;
       v_tot += (int64_t)D.T * NB;
@@ -320,7 +373,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
   // 4. workspace (grown inside the HBM budget, reused across calls)
   void* A = ws_get(ctx, "fit_A", (size_t)std::max<int64_t>(a_tot, 1) * aes);
   void* Wt = ws_get(ctx, "fit_W", (size_t)std::max<int64_t>(w_tot, 1) * aes);
-  double* K64 = mixed ? (double*)ws_get(ctx, "fit_K64", (size_t)std::max<int64_t>(a_tot, 1) * 8) : nullptr;
+  double* K64 = mixed ? (double*)ws_get(ctx, "fit_K64", (size_t)std::max<int64_t>(k_tot, 1) * 8) : nullptr;
   void* pack = mixed ? ws_get(ctx, "fit_pack", (size_t)std::max<int64_t>(pk_tot, 1) * 2) : nullptr;
   const size_t vb = (size_t)std::max<int64_t>(v_tot, 1) * 8;
   char* vecs = (char*)ws_get(ctx, "fit_vec", 5 * vb);
@@ -350,7 +403,17 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
   // host -> device descriptors through pinned staging (kept until the sync below)
   const size_t up_bytes = (size_t)n_sys * (sizeof(SysDesc) + 16);
   const size_t dn_bytes = (size_t)n_sys * sizeof(SysStatus);
-  char* pin = (char*)pinned_get(ctx, up_bytes + dn_bytes + 4096);
+  // groups: grp_first[n_groups], grp_next[n_params], then {0, -1}: the one-setting
+  // group that the plain per-system sequence forms each system with
+  const size_t grp_bytes = (size_t)(n_groups + n_params + 2) * 4;
+  int32_t* d_grp = (int32_t*)ws_get(ctx, "fit_groups", grp_bytes + 64);
+  char* pin = (char*)pinned_get(ctx, up_bytes + dn_bytes + 4096 + grp_bytes);
+  int32_t* gpin = (int32_t*)(pin + up_bytes + dn_bytes + 4096);
+  std::memcpy(gpin, grp_first.data(), (size_t)n_groups * 4);
+  std::memcpy(gpin + n_groups, grp_next.data(), (size_t)n_params * 4);
+  gpin[n_groups + n_params] = 0;
+  gpin[n_groups + n_params + 1] = -1;
+  KRR_HIP(hipMemcpyAsync(d_grp, gpin, grp_bytes, hipMemcpyHostToDevice, s));
   std::memcpy(pin, desc.data(), (size_t)n_sys * sizeof(SysDesc));
   std::memcpy(pin + (size_t)n_sys * sizeof(SysDesc), p_off.data(), (size_t)n_sys * 8);
   std::memcpy(pin + (size_t)n_sys * (sizeof(SysDesc) + 8), n_off.data(), (size_t)n_sys * 8);
@@ -369,14 +432,14 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
   }
 
   // 6-8. form, factor, solve
-  auto form = [&](const SysDesc* dd, int pp, int nq, int tmax) {
+  auto form = [&](const SysDesc* dd, int pp, int ng, const int32_t* gf, const int32_t* gn, int tmax) {
     if (dtype == KRR_F64)
-      launch_form<double>(ctx, s, prec, data->X, d, dd, pp, nq, tmax, A, K64);
+      launch_form<double>(ctx, s, prec, data->X, d, dd, pp, ng, gf, gn, tmax, A, K64);
     else
-      launch_form<float>(ctx, s, prec, data->X, d, dd, pp, nq, tmax, A, K64);
+      launch_form<float>(ctx, s, prec, data->X, d, dd, pp, ng, gf, gn, tmax, A, K64);
   };
   if (!ctx->serial_fit) {
-    form(d_desc, p, n_params, Tmax);
+    form(d_desc, p, n_groups, d_grp, d_grp + n_groups, Tmax);
     cholesky_factor(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, 0, mixed, desc.data(), pack);
     trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, rhs, zb, 0);
     trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, zb, alpha, nullptr, 0);
@@ -385,7 +448,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
     // by its own launches, one after another
     for (int sidx = 0; sidx < n_sys; ++sidx) {
       if (desc[sidx].T == 0) continue;
-      form(d_desc + sidx, 1, 1, desc[sidx].T);
+      form(d_desc + sidx, 1, 1, d_grp + n_groups + n_params, d_grp + n_groups + n_params + 1, desc[sidx].T);
       cholesky_factor(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, desc[sidx].T, A, Wt, 0, mixed,
                       desc.data() + sidx, pack);
       trsv_forward(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, A, Wt, rhs, zb, 0);
@@ -407,8 +470,8 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
         const int will = it < maxr ? 1 : 0;
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, d_active, 1);
         check_launch(ctx, s, "zero_active");
-        residual_check(ctx, s, d_desc, d_st, n_sys, Tmax, K64, alpha, rhs, rb, P, d_poff, rn, yn, d_noff, tol, will,
-                       d_active);
+        residual_check(ctx, s, d_desc, d_st, n_sys, p, n_groups, d_grp, d_grp + n_groups, Tmax, K64, alpha, rhs, rb,
+                       P, d_poff, rn, yn, d_noff, tol, will, d_active);
         if (!will) break;
         KRR_HIP(hipMemcpyAsync(act_h, d_active, 4, hipMemcpyDeviceToHost, s));
         KRR_HIP(hipStreamSynchronize(s));

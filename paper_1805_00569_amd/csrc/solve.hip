@@ -238,46 +238,92 @@ __global__ __launch_bounds__(TRSV_THREADS) void k_trsv_bwd(const SysDesc* __rest
   }
 }
 
-// Residual partials: tile (i, j) of the symmetric matrix (lower tiles only
-// stored) contributes K(i,j) alpha_j to row block i and, off the diagonal,
-// K(i,j)^T alpha_i to row block j.  Partials go to P[(row block, col block)]
-// and are summed in column-block order by k_resid_reduce.
+// Residual partials for the settings of one group (same kernel and sigma)
+// of partition j: blockIdx.y = group * p + j, tile (i, j) = triangle index
+// blockIdx.x.  The group's FP64 kernel tile K is read once (thread t holds
+// the 4 x 4 block of rows 4 (t >> 4) + k, columns 4 (t & 15) + l); each
+// setting adds its shift on the diagonal of its m x m system.  Tile (i, j)
+// contributes A(i,j) alpha_j to row block i and, off the diagonal,
+// A(i,j)^T alpha_i to row block j; partials go to P[(row block, col block)]
+// of the system and are summed in column-block order by k_resid_reduce.
+// Row sums combine the 16 column blocks with a butterfly over 16 lanes;
+// column sums combine the 16 row blocks with a butterfly over the 4 lane
+// groups of a wave and then over the 4 waves in LDS (fixed orders).
 __global__ __launch_bounds__(256) void k_resid_tiles(const SysDesc* __restrict__ desc,
-                                                     const SysStatus* __restrict__ st,
-                                                     const double* __restrict__ K, const double* __restrict__ alpha,
-                                                     double* __restrict__ P, const int64_t* __restrict__ p_off) {
-  const int s = blockIdx.y;
-  const SysDesc D = desc[s];
-  if (skip_system(st[s], 1)) return;
+                                                     const SysStatus* __restrict__ st, int p,
+                                                     const int32_t* __restrict__ grp_first,
+                                                     const int32_t* __restrict__ grp_next,
+                                                     const double* __restrict__ K64,
+                                                     const double* __restrict__ alpha, double* __restrict__ P,
+                                                     const int64_t* __restrict__ p_off) {
+  const int j = blockIdx.y % p, grp = blockIdx.y / p;
+  int q = grp_first[grp];
+  const SysDesc D0 = desc[q * p + j];
   const int bx = blockIdx.x;
   int ii = (int)((sqrt(8.0 * (double)bx + 1.0) - 1.0) * 0.5);
   while ((int64_t)ii * (ii + 1) / 2 > bx) --ii;
   while ((int64_t)(ii + 1) * (ii + 2) / 2 <= bx) ++ii;
   const int jj = bx - ii * (ii + 1) / 2;
-  if (ii >= D.T) return;
-  __shared__ double sred[4][NB];
-  const int t = threadIdx.x, lane = t & 63, g = t >> 6;
-  const double* Kt = K + D.a_off + tile_index(ii, jj) * TILE;
-  const double* aj = alpha + D.v_off + jj * NB;
-  const double* ai = alpha + D.v_off + ii * NB;
-  double* Pb = P + p_off[s];
-  // K(i,j) alpha_j
-  double acc = 0.0;
+  if (ii >= D0.T) return;
+  __shared__ double scol[4][NB];
+  const int t = threadIdx.x, cbk = t & 15, rbk = t >> 4, w = t >> 6;
+  const double* Kt = K64 + D0.k_off + tile_index(ii, jj) * TILE;
+  double K[4][4];   // K[l][k] = K(4 rbk + k, 4 cbk + l)
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int c = g + 4 * q;
-    acc = fma(Kt[c * NB + lane], aj[c], acc);
+  for (int l = 0; l < 4; ++l) {
+    const double2* src = reinterpret_cast<const double2*>(Kt + (4 * cbk + l) * NB + 4 * rbk);
+    const double2 u0 = src[0], u1 = src[1];
+    K[l][0] = u0.x;
+    K[l][1] = u0.y;
+    K[l][2] = u1.x;
+    K[l][3] = u1.y;
   }
-  sred[g][lane] = acc;
-  __syncthreads();
-  if (t < NB) Pb[((int64_t)ii * D.T + jj) * NB + lane] = (sred[0][lane] + sred[1][lane]) + (sred[2][lane] + sred[3][lane]);
-  if (ii != jj) {
-    const double al = ai[lane];
+  const bool diag_tile = ii == jj;
+  for (; q >= 0; q = grp_next[q]) {
+    const int s = q * p + j;
+    if (skip_system(st[s], 1)) continue;   // uniform over the workgroup
+    const SysDesc D = desc[s];
+    double* Pb = P + p_off[s];
+    const double* aj = alpha + D.v_off + jj * NB + 4 * cbk;
+    double av[4];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int c = g + 4 * q;
-      const double v = wave_sum(Kt[c * NB + lane] * al);
-      if (lane == 0) Pb[((int64_t)jj * D.T + ii) * NB + c] = v;
+    for (int l = 0; l < 4; ++l) av[l] = aj[l];
+    // rows: (K + lambda I)(i,j) alpha_j
+    double rs[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double acc = 0.0;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        double kv = K[l][k];
+        if (diag_tile && rbk == cbk && k == l && ii * NB + 4 * rbk + k < D.m) kv += D.lambda;
+        acc = fma(kv, av[l], acc);
+      }
+      for (int off = 1; off < 16; off <<= 1) acc += __shfl_xor(acc, off, 64);
+      rs[k] = acc;
+    }
+    if (cbk == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Pb[((int64_t)ii * D.T + jj) * NB + 4 * rbk + k] = rs[k];
+    }
+    if (!diag_tile) {   // columns: K(i,j)^T alpha_i (no shift off the diagonal)
+      const double* ai = alpha + D.v_off + ii * NB + 4 * rbk;
+      double bv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) bv[k] = ai[k];
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc = fma(K[l][k], bv[k], acc);
+        acc += __shfl_xor(acc, 16, 64);
+        acc += __shfl_xor(acc, 32, 64);
+        if ((t & 63) < 16) scol[w][4 * cbk + l] = acc;
+      }
+      __syncthreads();
+      if (t < NB)
+        Pb[((int64_t)jj * D.T + ii) * NB + t] = (scol[0][t] + scol[1][t]) + (scol[2][t] + scol[3][t]);
+      __syncthreads();
     }
   }
 }
@@ -364,14 +410,14 @@ void trsv_backward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, co
   check_launch(ctx, s, "trsv_bwd");
 }
 
-void residual_check(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, int n_sys, int Tmax,
-                    const double* K64, const double* alpha, const double* y, double* r, double* P,
-                    const int64_t* p_off, double* rn, double* yn, const int64_t* n_off, double tol,
-                    int will_refine, int32_t* active) {
+void residual_check(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, int n_sys, int p, int n_groups,
+                    const int32_t* grp_first, const int32_t* grp_next, int Tmax, const double* K64,
+                    const double* alpha, const double* y, double* r, double* P, const int64_t* p_off, double* rn,
+                    double* yn, const int64_t* n_off, double tol, int will_refine, int32_t* active) {
   const int64_t ntri = (int64_t)Tmax * (Tmax + 1) / 2;
   KernelTimer kt(ctx, s, "ir_residual", 0.0, 0);
-  hipLaunchKernelGGL(k_resid_tiles, dim3((unsigned)ntri, (unsigned)n_sys), dim3(256), 0, s, desc,
-                     (const SysStatus*)st, K64, alpha, P, p_off);
+  hipLaunchKernelGGL(k_resid_tiles, dim3((unsigned)ntri, (unsigned)(n_groups * p)), dim3(256), 0, s, desc,
+                     (const SysStatus*)st, p, grp_first, grp_next, K64, alpha, P, p_off);
   check_launch(ctx, s, "resid_tiles");
   hipLaunchKernelGGL(k_resid_reduce, dim3((unsigned)Tmax, (unsigned)n_sys), dim3(64), 0, s, desc,
                      (const SysStatus*)st, y, (const double*)P, p_off, r, rn, yn, n_off);
