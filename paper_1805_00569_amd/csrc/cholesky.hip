@@ -486,36 +486,54 @@ __global__ __launch_bounds__(256) void k_packed_update(const SysDesc* __restrict
   const int KSW = 2 * Wp;
   const __bf16* P = Pk + D.pk_off + lane * 8;
   const int rbi = (i - K0) * 4, rbj = (j - K0) * 4;
+  // the accumulators start as the C tile (MFMA output layout) and the
+  // products are subtracted by flipping the sign of one BF16 operand (exact)
+  float* C = A + D.a_off + tile_index(i, j) * TILE;
+  const int il = lane & 15, kg = lane >> 4;
   f4 acc[4][4];
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) acc[cb][rb] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int ks = ks0; ks < ks1; ++ks) {
-    bf8 pa[4], qv[4];
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[cb][rb][v] = C[(16 * cb + 4 * kg + v) * NB + 16 * rb + il];
+  auto load = [&](bf8 (&pa)[4], bf8 (&qv)[4], int ks) {
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
       pa[rb] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbi + rb) * KSW + ks) * FRAG);
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
       qv[cb] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbj + cb) * KSW + ks) * FRAG);
+  };
+  auto step = [&](const bf8 (&pa)[4], const bf8 (&qv)[4]) {
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
+    for (int cb = 0; cb < 4; ++cb) {
+      typedef unsigned u4v __attribute__((ext_vector_type(4)));
+      const u4v neg = __builtin_bit_cast(u4v, qv[cb]) ^ u4v{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+      const bf8 nq = __builtin_bit_cast(bf8, neg);
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb)
-        acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qv[cb], pa[rb], acc[cb][rb], 0, 0, 0);
+        acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nq, pa[rb], acc[cb][rb], 0, 0, 0);
+    }
+  };
+  // two register buffers: the next step's fragments load while this step's
+  // MFMAs run (the clamped extra load re-reads the last step, unused)
+  bf8 pa0[4], qv0[4], pa1[4], qv1[4];
+  int ks = ks0;
+  if (ks < ks1) load(pa0, qv0, ks);
+  for (; ks + 1 < ks1; ks += 2) {
+    load(pa1, qv1, ks + 1);
+    step(pa0, qv0);
+    load(pa0, qv0, min(ks + 2, ks1 - 1));
+    step(pa1, qv1);
   }
-  float* C = A + D.a_off + tile_index(i, j) * TILE;
-  const int il = lane & 15, kg = lane >> 4;
+  if (ks < ks1) step(pa0, qv0);
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int e = (16 * cb + 4 * kg + v) * NB + 16 * rb + il;
-        C[e] = C[e] - acc[cb][rb][v];
-      }
+      for (int v = 0; v < 4; ++v) C[(16 * cb + 4 * kg + v) * NB + 16 * rb + il] = acc[cb][rb][v];
 }
 
 template <typename TS>
