@@ -32,8 +32,51 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int TILE = NB * NB;
+constexpr int FRAG = 512;   // BF16 elements per packed MFMA operand fragment (16 rows x 32 columns)
 
 __device__ __forceinline__ int64_t tile_index(int i, int j) { return (int64_t)i * (i + 1) / 2 + j; }
+
+// acc[cb][rb] -= sum over the packed fragment columns ks in [ks0, ks1) of
+// P(rbj + cb, ks) P(rbi + rb, ks)^T with v_mfma_f32_16x16x32_bf16 (FP32
+// accumulation; the subtraction flips the sign of one BF16 operand, which is
+// exact).  P points at the system's pack plus lane * 8; one 16-byte load per
+// lane and fragment.  Two register buffers: the next step's fragments load
+// while this step's MFMAs run (the clamped extra load re-reads the last step
+// and is unused).  Output element (cb, rb, v) of a lane is row 16 rb +
+// (lane & 15), column 16 cb + 4 (lane >> 4) + v of the 16 x 64-column block.
+template <int NCB>
+__device__ __forceinline__ void packed_sub(f4 (&acc)[NCB][4], const __bf16* __restrict__ P, int rbi, int rbj,
+                                           int KSW, int ks0, int ks1) {
+  auto load = [&](bf8 (&pa)[4], bf8 (&qv)[NCB], int ks) {
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+      pa[rb] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbi + rb) * KSW + ks) * FRAG);
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+      qv[cb] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbj + cb) * KSW + ks) * FRAG);
+  };
+  auto step = [&](const bf8 (&pa)[4], const bf8 (&qv)[NCB]) {
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      typedef unsigned u4v __attribute__((ext_vector_type(4)));
+      const u4v neg = __builtin_bit_cast(u4v, qv[cb]) ^ u4v{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+      const bf8 nq = __builtin_bit_cast(bf8, neg);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+        acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nq, pa[rb], acc[cb][rb], 0, 0, 0);
+    }
+  };
+  bf8 pa0[4], qv0[NCB], pa1[4], qv1[NCB];
+  int ks = ks0;
+  if (ks < ks1) load(pa0, qv0, ks);
+  for (; ks + 1 < ks1; ks += 2) {
+    load(pa1, qv1, ks + 1);
+    step(pa0, qv0);
+    load(pa0, qv0, min(ks + 2, ks1 - 1));
+    step(pa1, qv1);
+  }
+  if (ks < ks1) step(pa0, qv0);
+}
 
 // ---------------------------------------------------------------------------
 // Diagonal block: A(k,k) = L L^T in FP64 and Winv(k) = L^-1, one workgroup of
@@ -135,10 +178,14 @@ __device__ __forceinline__ void diag_shift(const double (&v)[W], double (&w)[W -
   for (int c = 0; c < W - 8; ++c) w[c] = v[c + 8];
 }
 
+// With a BF16 panel pack (Pk != null, FP32 storage) and k > K0, the block
+// first receives its column update A(k,k) -= sum_{q in [K0,k)} L(k,q) L(k,q)^T
+// from the packed fragments (each wave 32 of the 64 columns), staged in LDS.
 template <typename TS>
 __global__ __launch_bounds__(DIAG_THREADS) void k_potrf_diag(const SysDesc* __restrict__ desc,
                                                              SysStatus* __restrict__ st, TS* __restrict__ A,
-                                                             TS* __restrict__ Wt, int k, int level) {
+                                                             TS* __restrict__ Wt, int k, int level,
+                                                             const __bf16* __restrict__ Pk, int K0, int Wp) {
   const int s = blockIdx.x;
   const SysDesc D = desc[s];
   if (k >= D.T || st[s].status != 0 || D.level != level) return;
@@ -146,11 +193,36 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_potrf_diag(const SysDesc* __re
   TS* tile = A + D.a_off + tile_index(k, k) * TILE;
   const int lane = threadIdx.x & 63;
   const bool factor_wave = threadIdx.x < 64;
+  const bool fused = std::is_same<TS, float>::value && Pk != nullptr && k > K0;
+  if (fused) {
+    const int w = threadIdx.x >> 6, il = lane & 15, kg = lane >> 4;
+    f4 acc[2][4];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[cb][rb][v] = (float)tile[(16 * (2 * w + cb) + 4 * kg + v) * NB + 16 * rb + il];
+    packed_sub<2>(acc, Pk + D.pk_off + lane * 8, (k - K0) * 4, (k - K0) * 4 + 2 * w, 2 * Wp, 0, 2 * (k - K0));
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          sh.sX[(16 * (2 * w + cb) + 4 * kg + v) * SW_LD + 16 * rb + il] = (double)acc[cb][rb][v];
+    __syncthreads();
+  }
   double v64[NB];
   if (factor_wave) {
     // row `lane` of A(k,k); entries above the diagonal are never consumed
+    if (fused) {
 #pragma unroll
-    for (int c = 0; c < NB; ++c) v64[c] = (double)tile[c * NB + lane];
+      for (int c = 0; c < NB; ++c) v64[c] = sh.sX[c * SW_LD + lane];
+    } else {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) v64[c] = (double)tile[c * NB + lane];
+    }
   } else {
 #pragma unroll
     for (int c = 0; c < NB; ++c) v64[c] = (c == lane) ? 1.0 : 0.0;
@@ -412,82 +484,129 @@ __global__ __launch_bounds__(256) void k_tile_gemm_bf16(const SysDesc* __restric
 
 // ---------------------------------------------------------------------------
 // Mixed precision updates with pre-packed BF16 operands.
-// After the panel solve of column k, k_pack_column writes L(i, k) for every
-// tile row i >= k once, in BF16, as v_mfma_f32_16x16x32_bf16 operand
-// fragments.  The pack of a system holds the current panel [K0, K0 + W):
-// fragment (rb, ks) covers rows [K0*64 + 16 rb, +16) and panel columns
-// [32 ks, +32) (ks < 2W); lane l holds row 16 rb + (l & 15) and columns
-// 32 ks + 8 (l >> 4) + e (e = 0..7): 16 contiguous bytes per lane, 1 KiB per
-// fragment.
-// k_packed_update subtracts sum_q L(i,q) L(j,q)^T over the packed fragment
-// columns [ks0, ks1) from output tiles, one 64 x 64 tile per wavefront: per
-// 32-wide k step a wave loads 4 + 4 fragments (one 16-byte load per lane
-// each) and issues 16 MFMAs with FP32 accumulation; no LDS and no barriers,
-// so waves exit independently.  Systems run along blockIdx.z.
-//   MODE_COL (band): tiles (i, j), j = j0 + blockIdx.y,
-//             i = j + 4 * blockIdx.x + wave (the lower part of the columns
-//             [j0, j0 + gridDim.y) of the panel)
-//   MODE_TRI: the lower triangle of the trailing matrix from tile i0 in
-//             128 x 128 super-tiles (blockIdx.x = triangle index)
+// The pack of a system holds the current panel [K0, K0 + W) as
+// v_mfma_f32_16x16x32_bf16 operand fragments: fragment (rb, ks) covers rows
+// [K0*64 + 16 rb, +16) and panel columns [32 ks, +32) (ks < 2W); lane l holds
+// row 16 rb + (l & 15) and columns 32 ks + 8 (l >> 4) + e (e = 0..7): 16
+// contiguous bytes per lane, 1 KiB per fragment.  Column k of the panel is
+// packed (rows below the diagonal block) by k_panel_col right after its
+// panel solve.
 // ---------------------------------------------------------------------------
-constexpr int FRAG = 512;   // bf16 elements per fragment
 
-__global__ __launch_bounds__(256) void k_pack_column(const SysDesc* __restrict__ desc,
-                                                     const SysStatus* __restrict__ st, const float* __restrict__ A,
-                                                     __bf16* __restrict__ Pk, int K0, int k, int Wp, int level) {
-  const int s = blockIdx.y;
-  const SysDesc D = desc[s];
-  if (st[s].status != 0 || D.level != level || k >= D.T) return;
-  const int KSW = 2 * Wp;
-  const int nrb = (D.T - k) * 4;                       // row blocks of tile rows i >= k
-  const int f = blockIdx.x * 4 + (threadIdx.x >> 6);   // (row block, half) pair
-  if (f >= nrb * 2) return;
-  const int rbl = f >> 1, h = f & 1;
-  const int l = threadIdx.x & 63;
-  const int r = k * NB + rbl * 16 + (l & 15);          // row of the system
-  const int cl = 32 * h + 8 * (l >> 4);                // first of 8 columns inside tile column k
-  const float* tile = A + D.a_off + tile_index(r >> 6, k) * TILE;
-  bf8 v;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) v[e] = (__bf16)tile[(cl + e) * NB + (r & 63)];
-  const int rb = (k - K0) * 4 + rbl;
-  const int ks = 2 * (k - K0) + h;
-  *reinterpret_cast<bf8*>(Pk + D.pk_off + ((int64_t)rb * KSW + ks) * FRAG + l * 8) = v;
-}
-
-template <int MODE>
-__global__ __launch_bounds__(256) void k_packed_update(const SysDesc* __restrict__ desc,
-                                                       const SysStatus* __restrict__ st, float* __restrict__ A,
-                                                       const __bf16* __restrict__ Pk, int K0, int ks0, int ks1,
-                                                       int i0, int j0, int Wp, int level) {
+// Column k of the panel [K0, K0 + Wp), tile rows i > k, one 64 x 64 tile per
+// wavefront (waves are independent: no barrier):
+//   C(i,k) -= sum_{q in [K0,k)} L(i,q) L(k,q)^T   BF16 packed operands, FP32 accumulation,
+//                                                 starting from the C tile in registers
+//   L(i,k)  = C(i,k) Winv(k)^T                    FP32 matrix cores, C through the wave's LDS
+//   L(i,k) -> the FP32 tile, and (do_pack) BF16 fragments of the pack
+constexpr int PC_LD = NB + 1;
+__global__ __launch_bounds__(256) void k_panel_col(const SysDesc* __restrict__ desc, const SysStatus* __restrict__ st,
+                                                   float* __restrict__ A, const float* __restrict__ Wt,
+                                                   __bf16* __restrict__ Pk, int K0, int k, int Wp, int level,
+                                                   int do_pack) {
   const int s = blockIdx.z;
   const SysDesc D = desc[s];
   if (st[s].status != 0 || D.level != level) return;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int i, j;
-  if (MODE == MODE_COL) {
-    j = j0 + blockIdx.y;
-    i = j + 4 * blockIdx.x + w;
-    if (i >= D.T) return;
-  } else {
-    const int R = D.T - i0;
-    if (R <= 0) return;
-    const int NS = (R + 1) / 2;
-    const int bx = blockIdx.x;
-    int I = (int)((sqrt(8.0 * (double)bx + 1.0) - 1.0) * 0.5);
-    while (I * (I + 1) / 2 > bx) --I;
-    while ((I + 1) * (I + 2) / 2 <= bx) ++I;
-    const int J = bx - I * (I + 1) / 2;
-    if (I >= NS) return;
-    i = i0 + 2 * I + (w & 1);
-    j = i0 + 2 * J + (w >> 1);
-    if (i >= D.T || j > i) return;       // waves are independent: no barrier follows
-  }
+  const int i = k + 1 + 4 * blockIdx.x + w;
+  if (i >= D.T) return;
+  __shared__ float sC[4][NB * PC_LD];
+  float* sc = sC[w];
   const int KSW = 2 * Wp;
-  const __bf16* P = Pk + D.pk_off + lane * 8;
-  const int rbi = (i - K0) * 4, rbj = (j - K0) * 4;
-  // the accumulators start as the C tile (MFMA output layout) and the
-  // products are subtracted by flipping the sign of one BF16 operand (exact)
+  const int il = lane & 15, kg = lane >> 4;
+  float* C = A + D.a_off + tile_index(i, k) * TILE;
+  f4 acc[4][4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[cb][rb][v] = C[(16 * cb + 4 * kg + v) * NB + 16 * rb + il];
+  if (k > K0) packed_sub<4>(acc, Pk + D.pk_off + lane * 8, (i - K0) * 4, (k - K0) * 4, KSW, 0, 2 * (k - K0));
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sc[(16 * cb + 4 * kg + v) * PC_LD + 16 * rb + il] = acc[cb][rb][v];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // out(r, c) = sum_t C(r, t) W(c, t): A operand W(c0 + il, t), B operand C(r0 + il, t)
+  const float* Wk = Wt + D.w_off + (int64_t)k * TILE;
+  f4 o[4][4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) o[cb][rb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+  for (int kb = 0; kb < NB; kb += 4) {
+    float qv[4], pa[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) qv[cb] = Wk[(kb + kg) * NB + 16 * cb + il];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) pa[rb] = sc[(kb + kg) * PC_LD + 16 * rb + il];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) o[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(qv[cb], pa[rb], o[cb][rb], 0, 0, 0);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // f32 MFMA result: register v of a lane is column 4 (lane >> 4) + v, row lane & 15 of its 16 x 16 block
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = 16 * cb + 4 * kg + v, r = 16 * rb + il;
+        C[c * NB + r] = o[cb][rb][v];
+        sc[c * PC_LD + r] = o[cb][rb][v];
+      }
+  if (!do_pack) return;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  __bf16* Pout = Pk + D.pk_off + lane * 8;
+#pragma unroll
+  for (int rbl = 0; rbl < 4; ++rbl)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int r = 16 * rbl + il, cl = 32 * h + 8 * kg;
+      bf8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (__bf16)sc[(cl + e) * PC_LD + r];
+      const int rb = (i - K0) * 4 + rbl, ks = 2 * (k - K0) + h;
+      *reinterpret_cast<bf8*>(Pout + ((int64_t)rb * KSW + ks) * FRAG) = v;
+    }
+}
+
+// Trailing update A(i,j) -= sum_{q in panel} L(i,q) L(j,q)^T for the lower
+// triangle i >= j >= i0, from the packed fragment columns [ks0, ks1): 128 x 128
+// super-tiles (blockIdx.x = triangle index), one 64 x 64 tile per wavefront,
+// accumulators starting from the C tile; systems along blockIdx.z.
+__global__ __launch_bounds__(256) void k_packed_trailing(const SysDesc* __restrict__ desc,
+                                                         const SysStatus* __restrict__ st, float* __restrict__ A,
+                                                         const __bf16* __restrict__ Pk, int K0, int ks0, int ks1,
+                                                         int i0, int Wp, int level) {
+  const int s = blockIdx.z;
+  const SysDesc D = desc[s];
+  if (st[s].status != 0 || D.level != level) return;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int R = D.T - i0;
+  if (R <= 0) return;
+  const int NS = (R + 1) / 2;
+  const int bx = blockIdx.x;
+  int I = (int)((sqrt(8.0 * (double)bx + 1.0) - 1.0) * 0.5);
+  while (I * (I + 1) / 2 > bx) --I;
+  while ((I + 1) * (I + 2) / 2 <= bx) ++I;
+  const int J = bx - I * (I + 1) / 2;
+  if (I >= NS) return;
+  const int i = i0 + 2 * I + (w & 1);
+  const int j = i0 + 2 * J + (w >> 1);
+  if (i >= D.T || j > i) return;       // waves are independent: no barrier follows
   float* C = A + D.a_off + tile_index(i, j) * TILE;
   const int il = lane & 15, kg = lane >> 4;
   f4 acc[4][4];
@@ -497,37 +616,7 @@ __global__ __launch_bounds__(256) void k_packed_update(const SysDesc* __restrict
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[cb][rb][v] = C[(16 * cb + 4 * kg + v) * NB + 16 * rb + il];
-  auto load = [&](bf8 (&pa)[4], bf8 (&qv)[4], int ks) {
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
-      pa[rb] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbi + rb) * KSW + ks) * FRAG);
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
-      qv[cb] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbj + cb) * KSW + ks) * FRAG);
-  };
-  auto step = [&](const bf8 (&pa)[4], const bf8 (&qv)[4]) {
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-      typedef unsigned u4v __attribute__((ext_vector_type(4)));
-      const u4v neg = __builtin_bit_cast(u4v, qv[cb]) ^ u4v{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
-      const bf8 nq = __builtin_bit_cast(bf8, neg);
-#pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
-        acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nq, pa[rb], acc[cb][rb], 0, 0, 0);
-    }
-  };
-  // two register buffers: the next step's fragments load while this step's
-  // MFMAs run (the clamped extra load re-reads the last step, unused)
-  bf8 pa0[4], qv0[4], pa1[4], qv1[4];
-  int ks = ks0;
-  if (ks < ks1) load(pa0, qv0, ks);
-  for (; ks + 1 < ks1; ks += 2) {
-    load(pa1, qv1, ks + 1);
-    step(pa0, qv0);
-    load(pa0, qv0, min(ks + 2, ks1 - 1));
-    step(pa1, qv1);
-  }
-  if (ks < ks1) step(pa0, qv0);
+  packed_sub<4>(acc, Pk + D.pk_off + lane * 8, (i - K0) * 4, (j - K0) * 4, 2 * Wp, ks0, ks1);
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
@@ -583,7 +672,8 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
         const double b = std::min<double>(NB, m - k * NB);
         return b > 0 ? 2.0 * b * b * b / 3.0 : 0.0;
       }), 0);
-      hipLaunchKernelGGL((k_potrf_diag<TS>), dim3(n_sys), dim3(DIAG_THREADS), 0, s, desc, st, A, Wt, k, level);
+      hipLaunchKernelGGL((k_potrf_diag<TS>), dim3(n_sys), dim3(DIAG_THREADS), 0, s, desc, st, A, Wt, k, level,
+                         (const __bf16*)nullptr, 0, 1);
       check_launch(ctx, s, "potrf_diag");
     }
     if (k + 1 < Tmax) {
@@ -595,52 +685,32 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
     }
   };
   if (packed) {
-    // The panel [K0, K1) is factored in sub-panels of WI tile columns, each
-    // followed by one band update of the panel's remaining columns; the wide
-    // panel then updates the trailing matrix once, which keeps the FP32
-    // read-modify-write traffic of the trailing tiles low.  Measured on the
-    // balanced workload, bands (WI < W) cost more than the column updates they
-    // replace, because every band re-reads and re-writes the panel tiles: WI
-    // is the largest panel width, i.e. one sub-panel per panel.
-    constexpr int WI = 16;
+    // Two launches per panel column: the diagonal block with its own column
+    // update, then the fused column update + panel solve + BF16 packing of
+    // the tiles below it; after the panel, one trailing update.
     for (int K0 = 0; K0 < Tmax; K0 += Wp) {
       const int K1 = std::min(K0 + Wp, Tmax);
-      for (int S0 = K0; S0 < K1; S0 += WI) {
-        const int S1 = std::min(S0 + WI, K1);
-        for (int k = S0; k < S1; ++k) {
-          if (k > S0) {
-            KernelTimer kt(ctx, s, col_name, each([&](double m) {
-              const double rows = m - k * NB;
-              return rows > 0 ? 2.0 * rows * std::min<double>(NB, rows) * (k - S0) * NB : 0.0;
-            }), 1);
-            hipLaunchKernelGGL((k_packed_update<MODE_COL>), dim3((unsigned)ceil_div(Tmax - k, 4), 1, (unsigned)n_sys),
-                               dim3(256), 0, s, desc, (const SysStatus*)st, (float*)A, (const __bf16*)Pk, K0,
-                               2 * (S0 - K0), 2 * (k - K0), 0, k, Wp, level);
-            check_launch(ctx, s, "packed_column");
-          }
-          diag_trsm(k);
-          if (k + 1 < K1 || K1 < Tmax) {   // column k feeds later updates: pack it
-            KernelTimer kt(ctx, s, "chol_pack_bf16", 0.0, 0);
-            const int64_t npairs = (int64_t)(Tmax - k) * 4 * 2;
-            hipLaunchKernelGGL(k_pack_column, dim3((unsigned)ceil_div(npairs, 4), (unsigned)n_sys), dim3(256), 0, s,
-                               desc, (const SysStatus*)st, (const float*)A, (__bf16*)Pk, K0, k, Wp, level);
-            check_launch(ctx, s, "pack_column");
-          }
+      for (int k = K0; k < K1; ++k) {
+        {
+          KernelTimer kt(ctx, s, "chol_diag", each([&](double m) {
+            const double b = std::min<double>(NB, m - k * NB);
+            return b > 0 ? 2.0 * b * b * b / 3.0 : 0.0;
+          }), 0);
+          hipLaunchKernelGGL((k_potrf_diag<TS>), dim3(n_sys), dim3(DIAG_THREADS), 0, s, desc, st, A, Wt, k, level,
+                             (const __bf16*)Pk, K0, Wp);
+          check_launch(ctx, s, "potrf_diag");
         }
-        if (S1 < K1) {   // band: columns [S1, K1), rows below the diagonal, sub-panel [S0, S1)
+        if (k + 1 < Tmax) {
+          // credited: the column update of the tiles below the diagonal and their panel solve
           KernelTimer kt(ctx, s, col_name, each([&](double m) {
-            double f = 0.0;
-            for (int j = S1; j < K1; ++j) {
-              const double rows = m - j * NB;
-              if (rows > 0) f += 2.0 * rows * std::min<double>(NB, rows) * (S1 - S0) * NB;
-            }
-            return f;
+            const double rows = m - (k + 1) * NB;
+            return rows > 0 ? 2.0 * rows * NB * (k - K0) * NB + rows * (double)NB * NB : 0.0;
           }), 1);
-          hipLaunchKernelGGL((k_packed_update<MODE_COL>),
-                             dim3((unsigned)ceil_div(Tmax - S1, 4), (unsigned)(K1 - S1), (unsigned)n_sys), dim3(256),
-                             0, s, desc, (const SysStatus*)st, (float*)A, (const __bf16*)Pk, K0, 2 * (S0 - K0),
-                             2 * (S1 - K0), 0, S1, Wp, level);
-          check_launch(ctx, s, "packed_band");
+          const int do_pack = (k + 1 < K1 || K1 < Tmax) ? 1 : 0;
+          hipLaunchKernelGGL(k_panel_col, dim3((unsigned)ceil_div(Tmax - k - 1, 4), 1, (unsigned)n_sys), dim3(256), 0,
+                             s, desc, (const SysStatus*)st, (float*)A, (const float*)Wt, (__bf16*)Pk, K0, k, Wp, level,
+                             do_pack);
+          check_launch(ctx, s, "panel_col");
         }
       }
       if (K1 < Tmax) {
@@ -651,9 +721,9 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
           return n > 0 ? n * (n + 1.0) * kk : 0.0;
         }), 1);
         const int64_t NS = (R + 1) / 2;
-        hipLaunchKernelGGL((k_packed_update<MODE_TRI>), dim3((unsigned)(NS * (NS + 1) / 2), 1, (unsigned)n_sys),
-                           dim3(256), 0, s, desc, (const SysStatus*)st, (float*)A, (const __bf16*)Pk, K0, 0,
-                           2 * (K1 - K0), K1, 0, Wp, level);
+        hipLaunchKernelGGL(k_packed_trailing, dim3((unsigned)(NS * (NS + 1) / 2), 1, (unsigned)n_sys), dim3(256), 0,
+                           s, desc, (const SysStatus*)st, (float*)A, (const __bf16*)Pk, K0, 0, 2 * (K1 - K0), K1, Wp,
+                           level);
         check_launch(ctx, s, "packed_trailing");
       }
     }
