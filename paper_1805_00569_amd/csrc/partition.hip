@@ -5,8 +5,8 @@
 //
 // Every distance here is the FP64 squared Euclidean distance accumulated
 // sequentially over the feature index with separately rounded subtract,
-// multiply and add (explicit _rn intrinsics: no contraction into fused
-// multiply-add), so assignments are reproducible bit for bit.  Comparisons use
+// multiply and add (no contraction into fused multiply-add), so assignments
+// are reproducible bit for bit.  Comparisons use
 // the squared value; the strict "<" over ascending centre index sends ties to
 // the lowest index, as in Algorithm 4.
 #include "common.hpp"
@@ -19,7 +19,8 @@ namespace {
 
 constexpr int GROUP_BLOCK = 256;
 constexpr int KPP_BLOCK = 256;   // k-means++ cumulative-weight block
-constexpr int CCHUNK = 16;       // centres per register chunk in assignment
+constexpr int ACH = 4;           // centres per register chunk in assignment
+constexpr int AROWS = 64;        // rows per assignment block (one per lane)
 
 // Plain operators: the library is compiled with -ffp-contract=off (and the
 // pragma keeps it off here), so every operation is rounded on its own.  The
@@ -56,7 +57,11 @@ __device__ __forceinline__ int first_active_lane() {
 // Assignment of rows of X to the nearest of p centres (CT is d x p, i.e. the
 // centres transposed, so that the p values of one feature are contiguous).
 // MODE 0: argmin index (+ change count against `prev`); MODE 1: all p squared
-// distances into D (n x p).  Rows are staged in LDS feature-major.
+// distances into D (n x p).  A block stages 64 rows in LDS feature-major
+// (lane = row); its 4 waves take the centre chunks [4c, 4c + 4) with
+// c = wave, wave + 4, ..., so that a wave's centre loads are uniform (scalar)
+// and each SIMD holds several waves.  The per-wave minima are combined with
+// the rule of the sequential scan: lowest value, then lowest index.
 // ---------------------------------------------------------------------------
 template <typename TX, int MODE>
 __global__ __launch_bounds__(256) void k_assign(const TX* __restrict__ X, int64_t n, int d,
@@ -68,21 +73,22 @@ __global__ __launch_bounds__(256) void k_assign(const TX* __restrict__ X, int64_
   if (skip != nullptr && *skip) return;
   extern __shared__ unsigned char smem_raw[];
   TX* sX = reinterpret_cast<TX*>(smem_raw);
-  const int R = blockDim.x;
-  const int ld = R + 1;
-  const int64_t row0 = (int64_t)blockIdx.x * R;
-  const int rows = (int)min((int64_t)R, n - row0);
+  __shared__ double sbest[4][AROWS];
+  __shared__ int32_t sidx[4][AROWS];
+  constexpr int ld = AROWS + 1;
+  const int64_t row0 = (int64_t)blockIdx.x * AROWS;
+  const int rows = (int)min((int64_t)AROWS, n - row0);
   const TX* src = X + row0 * d;
   const int tot = rows * d;
   // batches of 8 unconditional loads from clamped addresses, then the stores
-  for (int e0 = threadIdx.x; e0 < tot; e0 += 8 * R) {
+  for (int e0 = threadIdx.x; e0 < tot; e0 += 8 * 256) {
     TX v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = src[min(e0 + u * R, tot - 1)];
+    for (int u = 0; u < 8; ++u) v[u] = src[min(e0 + u * 256, tot - 1)];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int e = e0 + u * R;
-      // out-of-range elements go to a spare LDS row instead of a conditional store
+      const int e = e0 + u * 256;
+      // out-of-range elements go to a spare LDS slot instead of a conditional store
       const int ec = min(e, tot - 1);
       const int r = ec / d;
       const int k = ec - r * d;
@@ -90,34 +96,36 @@ __global__ __launch_bounds__(256) void k_assign(const TX* __restrict__ X, int64_
     }
   }
   __syncthreads();
-  const int r = threadIdx.x;
-  if (r >= rows) return;
-  const int64_t i = row0 + r;
+  const int r = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const bool valid = r < rows;
+  const int64_t i = row0 + min(r, rows - 1);
   double best = INFINITY;
   int bj = -1;
-  for (int j0 = 0; j0 < p; j0 += CCHUNK) {
-    const int nj = min(CCHUNK, p - j0);
-    double acc[CCHUNK];
+  for (int j0 = ACH * w; j0 < p; j0 += 4 * ACH) {
+    const int nj = min(ACH, p - j0);
+    double acc[ACH];
 #pragma unroll
-    for (int q = 0; q < CCHUNK; ++q) acc[q] = 0.0;
-    if (nj == CCHUNK) {
+    for (int q = 0; q < ACH; ++q) acc[q] = 0.0;
+    if (nj == ACH) {
       for (int k = 0; k < d; ++k) {
         const double xk = (double)sX[k * ld + r];
         const double* c = CT + (int64_t)k * p + j0;
 #pragma unroll
-        for (int q = 0; q < CCHUNK; ++q) acc[q] = sqdiff_acc(acc[q], xk, c[q]);
+        for (int q = 0; q < ACH; ++q) acc[q] = sqdiff_acc(acc[q], xk, c[q]);
       }
     } else {
       for (int k = 0; k < d; ++k) {
         const double xk = (double)sX[k * ld + r];
         const double* c = CT + (int64_t)k * p + j0;
 #pragma unroll
-        for (int q = 0; q < CCHUNK; ++q)
+        for (int q = 0; q < ACH; ++q)
           if (q < nj) acc[q] = sqdiff_acc(acc[q], xk, c[q]);
       }
     }
     if (MODE == 1) {
-      for (int q = 0; q < nj; ++q) D[i * p + j0 + q] = acc[q];
+      if (valid)
+        for (int q = 0; q < nj; ++q) D[i * p + j0 + q] = acc[q];
     } else {
       for (int q = 0; q < nj; ++q)
         if (acc[q] < best) {
@@ -127,12 +135,28 @@ __global__ __launch_bounds__(256) void k_assign(const TX* __restrict__ X, int64_
     }
   }
   if (MODE == 0) {
-    if (bj < 0) bj = 0;  // every distance +inf: first centre, as argmin does
-    out[i] = bj;
-    if (delta != nullptr) {
-      const bool changed = (prev == nullptr) || (prev[i] != bj);
-      const unsigned long long b = __ballot(changed);
-      if ((int)(threadIdx.x & 63) == first_active_lane()) atomicAdd(delta, (int32_t)__popcll(b));
+    sbest[w][r] = best;
+    sidx[w][r] = bj;
+    __syncthreads();
+    if (w == 0) {
+      double bv = INFINITY;
+      int bi = -1;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int ju = sidx[u][r];
+        const double vu = sbest[u][r];
+        if (ju >= 0 && (vu < bv || (vu == bv && (bi < 0 || ju < bi)))) {
+          bv = vu;
+          bi = ju;
+        }
+      }
+      if (bi < 0) bi = 0;  // every distance +inf: first centre, as the sequential scan does
+      if (valid) out[i] = bi;
+      if (delta != nullptr) {
+        const bool changed = valid && ((prev == nullptr) || (prev[i] != bi));
+        const unsigned long long b = __ballot(changed);
+        if (r == 0) atomicAdd(delta, (int32_t)__popcll(b));
+      }
     }
   }
 }
@@ -563,6 +587,113 @@ __global__ __launch_bounds__(64) void k_kbalance(const double* __restrict__ D, c
   }
 }
 
+// Event-driven K-balance (same result as the sequential pass).  The set of
+// full centres only grows, and between two "a centre becomes full" events
+// every point takes the plain argmin over the open centres.  A round computes
+// the choices of all points from `start` on in parallel (k_kbal_choose), then
+// finds the first point that fills a centre (k_kbal_event): the choices up to
+// it are final, that centre closes, and the next round starts after it.
+// At most p + 1 rounds; rounds after the last event exit at once (`done`).
+// State: st[0] = start, st[1] = done; counts cs[p], full[p].
+constexpr int KB_BLOCK = 256;
+constexpr int KB_MAXP = 256;    // event kernel: one thread per centre
+
+__global__ __launch_bounds__(KB_BLOCK) void k_kbal_choose(const double* __restrict__ D, int64_t n, int p,
+                                                          const int32_t* __restrict__ full,
+                                                          const int64_t* __restrict__ st, int32_t* __restrict__ MB,
+                                                          int32_t* __restrict__ bc) {
+  if (st[1]) return;
+  extern __shared__ int32_t hist[];
+  for (int j = threadIdx.x; j < p; j += KB_BLOCK) hist[j] = 0;
+  __syncthreads();
+  const int64_t start = st[0];
+  const int64_t i = (int64_t)blockIdx.x * KB_BLOCK + threadIdx.x;
+  if (i >= start && i < n) {
+    double bd = INFINITY;
+    int bj = -1;
+    for (int j = 0; j < p; ++j) {
+      if (!full[j]) {
+        const double v = D[i * p + j];
+        if (v < bd) {
+          bd = v;
+          bj = j;
+        }
+      }
+    }
+    if (bj < 0) bj = 0;   // no open centre at a finite distance: centre 0, as the sequential pass does
+    MB[i] = bj;
+    atomicAdd(&hist[bj], 1);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < p; j += KB_BLOCK) bc[(int64_t)blockIdx.x * p + j] = hist[j];
+}
+
+__global__ __launch_bounds__(KB_MAXP) void k_kbal_event(const int32_t* __restrict__ MB, const int32_t* __restrict__ bc,
+                                                        int64_t nblk, int64_t n, int p, int64_t cap,
+                                                        int32_t* __restrict__ cs, int32_t* __restrict__ full,
+                                                        int64_t* __restrict__ st) {
+  if (st[1]) return;
+  __shared__ int64_t spos[KB_MAXP];
+  const int j = threadIdx.x;
+  const int64_t start = st[0];
+  // position of the point that would fill centre j, if any
+  int64_t pos = INT64_MAX;
+  if (j < p && !full[j]) {
+    const int64_t need = cap - cs[j];
+    int64_t cum = 0, b = start / KB_BLOCK;
+    for (; b < nblk; ++b) {
+      const int c = bc[b * p + j];
+      if (cum + c >= need) break;
+      cum += c;
+    }
+    if (b < nblk) {
+      const int64_t i0 = max(start, b * KB_BLOCK), i1 = min(n, (b + 1) * KB_BLOCK);
+      for (int64_t i = i0; i < i1; ++i)
+        if (MB[i] == j && ++cum == need) {
+          pos = i;
+          break;
+        }
+    }
+  }
+  spos[j] = pos;
+  __syncthreads();
+  for (int off = KB_MAXP / 2; off > 0; off >>= 1) {
+    if (j < off) spos[j] = min(spos[j], spos[j + off]);
+    __syncthreads();
+  }
+  const int64_t istar = spos[0];
+  const int64_t last = (istar == INT64_MAX) ? n - 1 : istar;   // choices in [start, last] are final
+  if (j < p) {
+    // counts of the final choices in [start, last]
+    int64_t cnt = 0;
+    const int64_t bl = last / KB_BLOCK;
+    for (int64_t b = start / KB_BLOCK; b < bl; ++b) cnt += bc[b * p + j];
+    for (int64_t i = max(start, bl * KB_BLOCK); i <= last; ++i) cnt += (MB[i] == j);
+    cs[j] += (int32_t)cnt;
+  }
+  __syncthreads();
+  if (j == 0) {
+    if (istar == INT64_MAX || istar + 1 >= n) {
+      st[1] = 1;
+    } else {
+      full[MB[istar]] = 1;
+      st[0] = istar + 1;
+    }
+  }
+}
+
+__global__ void k_kbal_init(int32_t* __restrict__ cs, int32_t* __restrict__ full, int p, int64_t* __restrict__ st) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < p) {
+    cs[j] = 0;
+    full[j] = 0;
+  }
+  if (j == 0) {
+    st[0] = 0;
+    st[1] = 0;
+  }
+}
+
 __global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = v;
@@ -607,18 +738,16 @@ template <typename TX>
 void assign_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, const double* CT, int p,
               int32_t* out, double* D, const int32_t* prev, int32_t* delta, const int32_t* skip,
               bool all) {
-  // Rows per block: as many as fit in about 96 KiB of LDS, at least 64.
-  int R = 256;
-  while (R > 64 && ((size_t)d * (R + 1) + 1) * sizeof(TX) > 96 * 1024) R /= 2;
-  const size_t lds = ((size_t)d * (R + 1) + 1) * sizeof(TX);
-  const int64_t nblk = ceil_div(n, R);
+  // 64 rows per block staged in LDS (plus a spare slot); very wide rows use the unstaged kernel
+  const size_t lds = ((size_t)d * (AROWS + 1) + 1) * sizeof(TX);
+  const int64_t nblk = ceil_div(n, AROWS);
   KernelTimer kt(ctx, s, "assign", 0.0, 0);
   if (lds <= 96 * 1024) {
     if (all)
-      hipLaunchKernelGGL((k_assign<TX, 1>), dim3(nblk), dim3(R), lds, s, X, n, d, CT, p, out, D, prev,
+      hipLaunchKernelGGL((k_assign<TX, 1>), dim3(nblk), dim3(256), lds, s, X, n, d, CT, p, out, D, prev,
                          delta, skip);
     else
-      hipLaunchKernelGGL((k_assign<TX, 0>), dim3(nblk), dim3(R), lds, s, X, n, d, CT, p, out, D, prev,
+      hipLaunchKernelGGL((k_assign<TX, 0>), dim3(nblk), dim3(256), lds, s, X, n, d, CT, p, out, D, prev,
                          delta, skip);
   } else {
     const int64_t nb = ceil_div(n, 256);
@@ -767,8 +896,27 @@ static void partition_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int 
       int32_t* MB = prev;
       const int64_t cap = ceil_div(n, p);
       KernelTimer kt(ctx, s, "kbalance_greedy", 0.0, 0);
-      hipLaunchKernelGGL(k_kbalance, dim3(1), dim3(64), (size_t)p * 8, s, (const double*)D, a0, n, p, cap, MB);
-      check_launch(ctx, s, "kbalance");
+      if (p <= KB_MAXP) {
+        const int64_t nblk = ceil_div(n, KB_BLOCK);
+        char* kw = (char*)ws_get(ctx, "kbal_ev", (size_t)nblk * p * 4 + (size_t)p * 8 + 64);
+        int64_t* kst = (int64_t*)kw;
+        int32_t* cs = (int32_t*)(kw + 16);
+        int32_t* full = cs + p;
+        int32_t* bc = full + p;
+        hipLaunchKernelGGL(k_kbal_init, dim3((unsigned)ceil_div(p, 256)), dim3(256), 0, s, cs, full, p, kst);
+        check_launch(ctx, s, "kbal_init");
+        for (int round = 0; round <= p; ++round) {
+          hipLaunchKernelGGL(k_kbal_choose, dim3((unsigned)nblk), dim3(KB_BLOCK), (size_t)p * 4, s, (const double*)D,
+                             n, p, (const int32_t*)full, (const int64_t*)kst, MB, bc);
+          check_launch(ctx, s, "kbal_choose");
+          hipLaunchKernelGGL(k_kbal_event, dim3(1), dim3(KB_MAXP), 0, s, (const int32_t*)MB, (const int32_t*)bc, nblk,
+                             n, p, cap, cs, full, kst);
+          check_launch(ctx, s, "kbal_event");
+        }
+      } else {
+        hipLaunchKernelGGL(k_kbalance, dim3(1), dim3(64), (size_t)p * 8, s, (const double*)D, a0, n, p, cap, MB);
+        check_launch(ctx, s, "kbalance");
+      }
       KRR_HIP(hipMemcpyAsync(assign, MB, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
       group_by_key(ctx, s, assign, n, p, perm, off, nullptr, nullptr);
       means_t(ctx, s, X, n, d, perm, off, C, p, nullptr, nullptr, nullptr);
