@@ -36,6 +36,41 @@ SEED = 2
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense TFLOP/s, MI355X
 HBM_PEAK = 8000.0  # GB/s
 
+# HBM traffic per launch of the roofline kernel, from two rocprofv3 counter
+# runs of this benchmark (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch,
+# averaged over the kernel's dispatches), each scaled by what the same counter
+# reads for a plain 1 GiB device copy (FETCH_SIZE reads 512 MiB: x2.0;
+# WRITE_SIZE reads 1 GiB: x1.0).  Valid only while the kernel's source is the
+# one measured (sha256 over the listed source regions); otherwise null.
+TRAFFIC = {
+    "chol_column_bf16": {
+        "kernel": "k_panel_col",
+        "source": "paper_1805_00569_amd/csrc/cholesky.hip",
+        "regions": ["template <int NCB>\n__device__ __forceinline__ void packed_sub(",
+                    "__global__ __launch_bounds__(256) void k_panel_col("],
+        "sha256": "414a8265193a8081a958a7885982e64cc1987595a6693f1d4ba52ded699fa81e",
+        "fetch_kib": 131025.86, "write_kib": 73738.84, "fetch_scale": 2.0, "write_scale": 1.0,
+    },
+}
+
+
+def _traffic_bytes(cls):
+    import hashlib
+    t = TRAFFIC.get(cls)
+    if t is None:
+        return None
+    try:
+        src = open(os.path.join(ROOT, t["source"])).read()
+        text = ""
+        for sig in t["regions"]:
+            a = src.index(sig)
+            text += src[a:src.index("\n}\n", a) + 3]
+    except (OSError, ValueError):
+        return None
+    if hashlib.sha256(text.encode()).hexdigest() != t["sha256"]:
+        return None
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
+
 
 def fit_flops(m, d):
     m = float(m)
@@ -312,18 +347,33 @@ def serving_leg(rates, seconds, seed=5):
 
 def roofline(timed, steps):
     """Roofline entry of the kernel class with the most event time in the
-    timed steps: algorithmic flops of its launches / their summed duration."""
+    timed steps.  The bound is the one its algorithmic intensity (flops per
+    algorithmic HBM byte) puts it under: HBM below the ridge point of the
+    class's matrix-core peak, the matrix cores above it.  achieved =
+    algorithmic bytes (or flops) of its launches / their summed duration."""
     if not timed:
         return None
     name, rec = max(timed.items(), key=lambda kv: kv[1]["ms"])
     prec = "bf16" if name.endswith("bf16") else ("fp64" if name.endswith("f64") else "fp32")
-    achieved = rec["flops"] / (rec["ms"] * 1e-3) / 1e12 if rec["ms"] > 0 else 0.0
-    peak = PEAK[prec]
-    return {"bound": "mfma", "kernel": name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None, "launches_per_step": rec["count"] / steps,
-            "ms_per_step": rec["ms"] / steps, "avg_launch_us": 1e3 * rec["ms"] / max(rec["count"], 1),
-            "algorithmic_flops_per_step": rec["flops"] / steps,
-            "other_timed_classes_ms_per_step": {k: v["ms"] / steps for k, v in timed.items() if k != name}}
+    sec = rec["ms"] * 1e-3
+    flops, byts, cnt = rec["flops"], rec.get("bytes", 0.0), max(rec["count"], 1)
+    ridge = PEAK[prec] * 1e12 / (HBM_PEAK * 1e9)
+    out = {"kernel": name, "launches_per_step": rec["count"] / steps, "ms_per_step": rec["ms"] / steps,
+           "avg_launch_us": 1e3 * rec["ms"] / cnt, "algorithmic_flops_per_launch": flops / cnt,
+           "algorithmic_bytes_per_launch": byts / cnt if byts > 0 else None,
+           "intensity_flop_per_byte": flops / byts if byts > 0 else None,
+           "ridge_flop_per_byte": ridge, "mfma_peak_tflops": PEAK[prec],
+           "achieved_tflops": flops / sec / 1e12 if sec > 0 else 0.0}
+    if byts > 0 and flops / byts < ridge:
+        achieved = byts / sec / 1e9 if sec > 0 else 0.0
+        out.update(bound="hbm", achieved=achieved, peak=HBM_PEAK, unit="GB/s", frac=achieved / HBM_PEAK)
+    else:
+        achieved = flops / sec / 1e12 if sec > 0 else 0.0
+        out.update(bound="mfma", achieved=achieved, peak=PEAK[prec], unit="TFLOP/s", frac=achieved / PEAK[prec])
+    out["traffic"] = _traffic_bytes(name)
+    out["other_timed_classes_ms_per_step"] = {k: v["ms"] / steps for k, v in timed.items() if k != name}
+    return {k: out[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")} | \
+        {k: v for k, v in out.items() if k not in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
 
 
 def cpu_baseline(w, state, ctx, params, n_fits):

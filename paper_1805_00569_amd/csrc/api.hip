@@ -93,8 +93,8 @@ static hipEvent_t ev_get(krr_ctx ctx) {
   return e;
 }
 
-KernelTimer::KernelTimer(krr_ctx c, hipStream_t st, const char* name, double f, int major)
-    : ctx(c), s(st), cls(name), flops(f) {
+KernelTimer::KernelTimer(krr_ctx c, hipStream_t st, const char* name, double f, int major, double by)
+    : ctx(c), s(st), cls(name), flops(f), bytes(by) {
   if (ctx->timing == 0 || (ctx->timing == 1 && !major)) return;
   a = ev_get(ctx);
   b = ev_get(ctx);
@@ -105,7 +105,7 @@ KernelTimer::KernelTimer(krr_ctx c, hipStream_t st, const char* name, double f, 
 
 KernelTimer::~KernelTimer() {
   if (a == nullptr) return;
-  if (hipEventRecord(b, s) == hipSuccess) ctx->pending.push_back({cls, a, b, flops});
+  if (hipEventRecord(b, s) == hipSuccess) ctx->pending.push_back({cls, a, b, flops, bytes});
 }
 
 static void collect_timing(krr_ctx ctx) {
@@ -117,6 +117,7 @@ static void collect_timing(krr_ctx ctx) {
       g.count += 1;
       g.ms += ms;
       g.flops += p.flops;
+      g.bytes += p.bytes;
     }
     ctx->ev_pool.push_back(p.a);
     ctx->ev_pool.push_back(p.b);
@@ -235,8 +236,9 @@ krr_status krr_timing_report(krr_ctx ctx, char* buf, size_t cap, size_t* needed)
     bool first = true;
     char tmp[256];
     for (auto& kv : ctx->timing_agg) {
-      std::snprintf(tmp, sizeof(tmp), "%s\"%s\": {\"count\": %lld, \"ms\": %.6f, \"flops\": %.6e}",
-                    first ? "" : ", ", kv.first.c_str(), (long long)kv.second.count, kv.second.ms, kv.second.flops);
+      std::snprintf(tmp, sizeof(tmp), "%s\"%s\": {\"count\": %lld, \"ms\": %.6f, \"flops\": %.6e, \"bytes\": %.6e}",
+                    first ? "" : ", ", kv.first.c_str(), (long long)kv.second.count, kv.second.ms, kv.second.flops,
+                    kv.second.bytes);
       js += tmp;
       first = false;
     }

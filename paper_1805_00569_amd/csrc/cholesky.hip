@@ -701,11 +701,15 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
           check_launch(ctx, s, "potrf_diag");
         }
         if (k + 1 < Tmax) {
-          // credited: the column update of the tiles below the diagonal and their panel solve
+          // credited: the column update of the tiles below the diagonal and their panel solve;
+          // algorithmic bytes: read those tiles and write their factor (FP32)
           KernelTimer kt(ctx, s, col_name, each([&](double m) {
             const double rows = m - (k + 1) * NB;
             return rows > 0 ? 2.0 * rows * NB * (k - K0) * NB + rows * (double)NB * NB : 0.0;
-          }), 1);
+          }), 1, each([&](double m) {
+            const double rows = m - (k + 1) * NB;
+            return rows > 0 ? 2.0 * rows * NB * sizeof(float) : 0.0;
+          }));
           const int do_pack = (k + 1 < K1 || K1 < Tmax) ? 1 : 0;
           hipLaunchKernelGGL(k_panel_col, dim3((unsigned)ceil_div(Tmax - k - 1, 4), 1, (unsigned)n_sys), dim3(256), 0,
                              s, desc, (const SysStatus*)st, (float*)A, (const float*)Wt, (__bf16*)Pk, K0, k, Wp, level,
@@ -715,11 +719,15 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
       }
       if (K1 < Tmax) {
         const int64_t R = Tmax - K1;
+        // algorithmic bytes: read and write the lower trailing triangle (FP32)
         KernelTimer kt(ctx, s, trail_name, each([&](double m) {
           const double n = m - K1 * NB;
           const double kk = std::min<double>(K1 * NB, m) - K0 * NB;
           return n > 0 ? n * (n + 1.0) * kk : 0.0;
-        }), 1);
+        }), 1, each([&](double m) {
+          const double n = m - K1 * NB;
+          return n > 0 ? n * (n + 1.0) * sizeof(float) : 0.0;
+        }));
         const int64_t NS = (R + 1) / 2;
         hipLaunchKernelGGL(k_packed_trailing, dim3((unsigned)(NS * (NS + 1) / 2), 1, (unsigned)n_sys), dim3(256), 0,
                            s, desc, (const SysStatus*)st, (float*)A, (const __bf16*)Pk, K0, 0, 2 * (K1 - K0), K1, Wp,

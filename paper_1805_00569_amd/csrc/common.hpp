@@ -113,12 +113,14 @@ struct krr_timed_launch {
   const char* cls;
   hipEvent_t a, b;
   double flops;
+  double bytes;
 };
 
 struct krr_timing_agg {
   int64_t count = 0;
   double ms = 0.0;
   double flops = 0.0;
+  double bytes = 0.0;
 };
 
 struct krr_ctx_s {
@@ -154,14 +156,17 @@ void check_launch(krr_ctx ctx, hipStream_t s, const char* what);
 
 // HIP events around one launch of kernel class `cls` (only when timing is on;
 // major = 1 marks the matrix-core update kernels), with the launch's
-// algorithmic flop count.  Results are collected by krr_timing_report.
+// algorithmic flop count and algorithmic HBM bytes (the bytes the algorithm
+// must move, not what the kernel moves).  Results are collected by
+// krr_timing_report.
 struct KernelTimer {
   krr_ctx ctx;
   hipStream_t s;
   const char* cls;
   double flops;
+  double bytes;
   hipEvent_t a = nullptr, b = nullptr;
-  KernelTimer(krr_ctx c, hipStream_t st, const char* name, double f, int major);
+  KernelTimer(krr_ctx c, hipStream_t st, const char* name, double f, int major, double by = 0.0);
   ~KernelTimer();
 };
 
