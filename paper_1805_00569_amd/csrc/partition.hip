@@ -418,64 +418,77 @@ __global__ __launch_bounds__(KPP_BLOCK) void k_kpp_update(const TX* __restrict__
   if (i < n) P[i] = sd[threadIdx.x];
 }
 
+// Selection of centre t.  Thread 0 forms the block offsets (sequential sum
+// of the block totals, loads batched) into LDS; every thread then scans its
+// share of the blocks for the first whose end weight exceeds the threshold,
+// and the first such block is searched point by point.  The offsets live in
+// LDS when nblk <= KPP_MAXBLK, else in the global buffer gOb.
+constexpr int KPP_MAXBLK = 4096;
+
 template <typename TX>
 __global__ __launch_bounds__(KPP_BLOCK) void k_kpp_select(const double* __restrict__ P,
                                                           const double* __restrict__ Tb, int64_t nblk,
-                                                          int64_t n, double u, double* __restrict__ Ob,
-                                                          const TX* __restrict__ X, int d,
+                                                          int64_t n, double u, const TX* __restrict__ X, int d,
                                                           int64_t* __restrict__ cidx, int t,
-                                                          double* __restrict__ C) {
-  __shared__ double s_thr;
-  __shared__ int64_t s_blk;
+                                                          double* __restrict__ C, double* __restrict__ gOb) {
+  extern __shared__ double shOb[];   // nblk block offsets (when gOb is null)
+  double* sOb = gOb != nullptr ? gOb : shOb;
+  __shared__ double s_total;
   __shared__ int64_t s_idx[KPP_BLOCK];
-  __shared__ int s_mode;
   if (threadIdx.x == 0) {
     double o = 0.0;
-    for (int64_t b = 0; b < nblk; ++b) {
-      Ob[b] = o;
-      o = add_sep(o, Tb[b]);
-    }
-    const double total = o;
-    int64_t blk = -1;
-    int mode = 0;
-    if (!(total > 0.0)) {
-      mode = 1;
-    } else {
-      const double thr = mul_sep(u, total);
-      s_thr = thr;
-      for (int64_t b = 0; b < nblk; ++b) {
-        if (add_sep(Ob[b], Tb[b]) > thr) {
-          blk = b;
-          break;
-        }
+    int64_t b = 0;
+    for (; b + 8 <= nblk; b += 8) {
+      double tv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) tv[q] = Tb[b + q];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        sOb[b + q] = o;
+        o = add_sep(o, tv[q]);
       }
-      if (blk < 0) mode = 2;
     }
-    s_blk = blk;
-    s_mode = mode;
+    for (; b < nblk; ++b) {
+      const double tv = Tb[b];
+      sOb[b] = o;
+      o = add_sep(o, tv);
+    }
+    s_total = o;
   }
   __syncthreads();
+  const double total = s_total;
   int64_t idx;
-  if (s_mode == 1) {
+  if (!(total > 0.0)) {
     idx = (int64_t)floor(mul_sep(u, (double)n));
     if (idx > n - 1) idx = n - 1;
-  } else if (s_mode == 2) {
-    idx = 0;  // no cumulative weight above the threshold: the first point
   } else {
-    const int64_t b = s_blk;
-    const int64_t i = b * KPP_BLOCK + threadIdx.x;
+    const double thr = mul_sep(u, total);
     int64_t cand = INT64_MAX;
-    if (i < n && add_sep(Ob[b], P[i]) > s_thr) cand = i;
+    for (int64_t b = threadIdx.x; b < nblk; b += KPP_BLOCK)
+      if (add_sep(sOb[b], Tb[b]) > thr) {
+        cand = b;
+        break;
+      }
     s_idx[threadIdx.x] = cand;
     __syncthreads();
     for (int w = KPP_BLOCK / 2; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) {
-        const int64_t o = s_idx[threadIdx.x + w];
-        if (o < s_idx[threadIdx.x]) s_idx[threadIdx.x] = o;
-      }
+      if ((int)threadIdx.x < w) s_idx[threadIdx.x] = min(s_idx[threadIdx.x], s_idx[threadIdx.x + w]);
       __syncthreads();
     }
-    idx = s_idx[0];
+    const int64_t blk = s_idx[0];
+    __syncthreads();
+    if (blk == INT64_MAX) {
+      idx = 0;  // no cumulative weight above the threshold: the first point
+    } else {
+      const int64_t i = blk * KPP_BLOCK + threadIdx.x;
+      s_idx[threadIdx.x] = (i < n && add_sep(sOb[blk], P[i]) > thr) ? i : INT64_MAX;
+      __syncthreads();
+      for (int w = KPP_BLOCK / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s_idx[threadIdx.x] = min(s_idx[threadIdx.x], s_idx[threadIdx.x + w]);
+        __syncthreads();
+      }
+      idx = s_idx[0];
+    }
   }
   if (threadIdx.x == 0) cidx[t] = idx;
   for (int f = threadIdx.x; f < d; f += KPP_BLOCK) C[(int64_t)t * d + f] = (double)X[idx * d + f];
@@ -799,8 +812,9 @@ void kmeanspp_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, int k
     hipLaunchKernelGGL((k_kpp_update<TX>), dim3(nblk), dim3(KPP_BLOCK), 0, s, X, n, d,
                        (const int64_t*)cidx, t - 1, D2, P, Tb);
     check_launch(ctx, s, "kpp_update");
-    hipLaunchKernelGGL((k_kpp_select<TX>), dim3(1), dim3(KPP_BLOCK), 0, s, (const double*)P,
-                       (const double*)Tb, nblk, n, u[t], Ob, X, d, cidx, t, C);
+    const bool lds = nblk <= KPP_MAXBLK;
+    hipLaunchKernelGGL((k_kpp_select<TX>), dim3(1), dim3(KPP_BLOCK), lds ? (size_t)nblk * 8 : 0, s,
+                       (const double*)P, (const double*)Tb, nblk, n, u[t], X, d, cidx, t, C, lds ? nullptr : Ob);
     check_launch(ctx, s, "kpp_select");
   }
 }
