@@ -181,11 +181,14 @@ __device__ __forceinline__ void diag_shift(const double (&v)[W], double (&w)[W -
 // With a BF16 panel pack (Pk != null, FP32 storage) and k > K0, the block
 // first receives its column update A(k,k) -= sum_{q in [K0,k)} L(k,q) L(k,q)^T
 // from the packed fragments (each wave 32 of the 64 columns), staged in LDS.
+// Wpk (nullable): Winv(k) is also written as BF16 high/low operand
+// fragments for the BF16 panel solve (see k_panel_col).
 template <typename TS>
 __global__ __launch_bounds__(DIAG_THREADS) void k_potrf_diag(const SysDesc* __restrict__ desc,
                                                              SysStatus* __restrict__ st, TS* __restrict__ A,
                                                              TS* __restrict__ Wt, int k, int level,
-                                                             const __bf16* __restrict__ Pk, int K0, int Wp) {
+                                                             const __bf16* __restrict__ Pk, int K0, int Wp,
+                                                             __bf16* __restrict__ Wpk) {
   const int s = blockIdx.x;
   const SysDesc D = desc[s];
   if (k >= D.T || st[s].status != 0 || D.level != level) return;
@@ -277,6 +280,27 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_potrf_diag(const SysDesc* __re
     const int c = e >> 6, r = e & 63;
     tile[e] = (TS)(sh.sU[c * SW_LD + r] * sh.sd[c]);
     wt[e] = (TS)((r >= c) ? sh.sX[c * SW_LD + r] * sh.sd[r] : 0.0);
+  }
+  if (Wpk != nullptr) {
+    // fragment f = 2 cb + ks, part hl (0 high, 1 low): lane l holds Winv(16 cb + (l & 15), 32 ks + 8 (l >> 4) + e)
+    // split from its FP32 value: hi = bf16(w), lo = bf16(w - hi)
+    __bf16* base = Wpk + ((int64_t)s * Wp + (k - K0)) * 16 * FRAG;
+    for (int task = threadIdx.x; task < 8 * 64; task += DIAG_THREADS) {
+      const int f = task >> 6, l = task & 63;
+      const int cb = f >> 1, ks = f & 1;
+      const int row = 16 * cb + (l & 15);
+      bf8 hi, lo;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int col = 32 * ks + 8 * (l >> 4) + e;
+        const float w = (float)((row >= col) ? sh.sX[col * SW_LD + row] * sh.sd[row] : 0.0);
+        const __bf16 h = (__bf16)w;
+        hi[e] = h;
+        lo[e] = (__bf16)(w - (float)h);
+      }
+      *reinterpret_cast<bf8*>(base + (int64_t)(2 * f) * FRAG + l * 8) = hi;
+      *reinterpret_cast<bf8*>(base + (int64_t)(2 * f + 1) * FRAG + l * 8) = lo;
+    }
   }
 }
 
@@ -501,7 +525,7 @@ __global__ __launch_bounds__(256) void k_tile_gemm_bf16(const SysDesc* __restric
 //   L(i,k) -> the FP32 tile, and (do_pack) BF16 fragments of the pack
 constexpr int PC_LD = NB + 1;
 __global__ __launch_bounds__(256) void k_panel_col(const SysDesc* __restrict__ desc, const SysStatus* __restrict__ st,
-                                                   float* __restrict__ A, const float* __restrict__ Wt,
+                                                   float* __restrict__ A, const __bf16* __restrict__ Wpk,
                                                    __bf16* __restrict__ Pk, int K0, int k, int Wp, int level,
                                                    int do_pack) {
   const int s = blockIdx.z;
@@ -532,29 +556,50 @@ __global__ __launch_bounds__(256) void k_panel_col(const SysDesc* __restrict__ d
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // out(r, c) = sum_t C(r, t) W(c, t): A operand W(c0 + il, t), B operand C(r0 + il, t)
-  const float* Wk = Wt + D.w_off + (int64_t)k * TILE;
+  // out(r, c) = sum_{t <= c} C(r, t) Winv(c, t) on BF16 matrix cores with
+  // high/low splits of both operands (three products, FP32 accumulation:
+  // about 16 significant bits per product, below the error of the BF16
+  // updates and corrected by the FP64 refinement); blocks of Winv above its
+  // diagonal are zero and skipped.  A operand: Winv fragments (cb, ks);
+  // B operand: C(16 rb + (lane & 15), 32 ks + 8 (lane >> 4) + e) from LDS.
+  const __bf16* Wf = Wpk + ((int64_t)s * Wp + (k - K0)) * 16 * FRAG + lane * 8;
+  bf8 whi[4][2], wlo[4][2];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+      if (ks == 0 || cb >= 2) {
+        whi[cb][ks] = *reinterpret_cast<const bf8*>(Wf + (int64_t)(2 * (2 * cb + ks)) * FRAG);
+        wlo[cb][ks] = *reinterpret_cast<const bf8*>(Wf + (int64_t)(2 * (2 * cb + ks) + 1) * FRAG);
+      }
   f4 o[4][4];
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) o[cb][rb] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-  for (int kb = 0; kb < NB; kb += 4) {
-    float qv[4], pa[4];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) qv[cb] = Wk[(kb + kg) * NB + 16 * cb + il];
+  for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) pa[rb] = sc[(kb + kg) * PC_LD + 16 * rb + il];
+    for (int ks = 0; ks < 2; ++ks) {
+      bf8 chi, clo;
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
+      for (int e = 0; e < 8; ++e) {
+        const float cv = sc[(32 * ks + 8 * kg + e) * PC_LD + 16 * rb + il];
+        const __bf16 h = (__bf16)cv;
+        chi[e] = h;
+        clo[e] = (__bf16)(cv - (float)h);
+      }
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb) o[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(qv[cb], pa[rb], o[cb][rb], 0, 0, 0);
-  }
+      for (int cb = 2 * ks; cb < 4; ++cb) {
+        o[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wlo[cb][ks], chi, o[cb][rb], 0, 0, 0);
+        o[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(whi[cb][ks], clo, o[cb][rb], 0, 0, 0);
+        o[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(whi[cb][ks], chi, o[cb][rb], 0, 0, 0);
+      }
+    }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // f32 MFMA result: register v of a lane is column 4 (lane >> 4) + v, row lane & 15 of its 16 x 16 block
+  // MFMA result: register v of a lane is column 4 (lane >> 4) + v, row lane & 15 of its 16 x 16 block
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
@@ -673,7 +718,7 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
         return b > 0 ? 2.0 * b * b * b / 3.0 : 0.0;
       }), 0);
       hipLaunchKernelGGL((k_potrf_diag<TS>), dim3(n_sys), dim3(DIAG_THREADS), 0, s, desc, st, A, Wt, k, level,
-                         (const __bf16*)nullptr, 0, 1);
+                         (const __bf16*)nullptr, 0, 1, (__bf16*)nullptr);
       check_launch(ctx, s, "potrf_diag");
     }
     if (k + 1 < Tmax) {
@@ -687,7 +732,9 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
   if (packed) {
     // Two launches per panel column: the diagonal block with its own column
     // update, then the fused column update + panel solve + BF16 packing of
-    // the tiles below it; after the panel, one trailing update.
+    // the tiles below it; after the panel, one trailing update.  Wpk: BF16
+    // high/low fragments of the panel's inverse diagonal blocks.
+    __bf16* Wpk = (__bf16*)ws_get(ctx, "chol_wpk", (size_t)n_sys * Wp * 16 * FRAG * sizeof(__bf16));
     for (int K0 = 0; K0 < Tmax; K0 += Wp) {
       const int K1 = std::min(K0 + Wp, Tmax);
       for (int k = K0; k < K1; ++k) {
@@ -697,7 +744,7 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
             return b > 0 ? 2.0 * b * b * b / 3.0 : 0.0;
           }), 0);
           hipLaunchKernelGGL((k_potrf_diag<TS>), dim3(n_sys), dim3(DIAG_THREADS), 0, s, desc, st, A, Wt, k, level,
-                             (const __bf16*)Pk, K0, Wp);
+                             (const __bf16*)Pk, K0, Wp, Wpk);
           check_launch(ctx, s, "potrf_diag");
         }
         if (k + 1 < Tmax) {
@@ -712,8 +759,8 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
           }));
           const int do_pack = (k + 1 < K1 || K1 < Tmax) ? 1 : 0;
           hipLaunchKernelGGL(k_panel_col, dim3((unsigned)ceil_div(Tmax - k - 1, 4), 1, (unsigned)n_sys), dim3(256), 0,
-                             s, desc, (const SysStatus*)st, (float*)A, (const float*)Wt, (__bf16*)Pk, K0, k, Wp, level,
-                             do_pack);
+                             s, desc, (const SysStatus*)st, (float*)A, (const __bf16*)Wpk, (__bf16*)Pk, K0, k, Wp,
+                             level, do_pack);
           check_launch(ctx, s, "panel_col");
         }
       }
