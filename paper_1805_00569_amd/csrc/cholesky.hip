@@ -40,42 +40,43 @@ __device__ __forceinline__ int64_t tile_index(int i, int j) { return (int64_t)i 
 // P(rbj + cb, ks) P(rbi + rb, ks)^T with v_mfma_f32_16x16x32_bf16 (FP32
 // accumulation; the subtraction flips the sign of one BF16 operand, which is
 // exact).  P points at the system's pack plus lane * 8; one 16-byte load per
-// lane and fragment.  Two register buffers: the next step's fragments load
-// while this step's MFMAs run (the clamped extra load re-reads the last step
-// and is unused).  Output element (cb, rb, v) of a lane is row 16 rb +
-// (lane & 15), column 16 cb + 4 (lane >> 4) + v of the 16 x 64-column block.
-template <int NCB>
+// lane and fragment.  The fragments of PK_DEPTH steps are in flight in a
+// register ring, so the loads of a step are issued several steps before its
+// MFMAs (the ring's refills past ks1 re-read the last step and are unused).
+// Output element (cb, rb, v) of a lane is row 16 rb + (lane & 15), column
+// 16 cb + 4 (lane >> 4) + v of the 16 x 64-column block.
+template <int NCB, int PK_DEPTH>
 __device__ __forceinline__ void packed_sub(f4 (&acc)[NCB][4], const __bf16* __restrict__ P, int rbi, int rbj,
                                            int KSW, int ks0, int ks1) {
-  auto load = [&](bf8 (&pa)[4], bf8 (&qv)[NCB], int ks) {
+  if (ks0 >= ks1) return;
+  typedef unsigned u4v __attribute__((ext_vector_type(4)));
+  const u4v sgn{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+  bf8 pa[PK_DEPTH][4], qv[PK_DEPTH][NCB];
+  auto load = [&](int u, int ks) {
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
-      pa[rb] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbi + rb) * KSW + ks) * FRAG);
+      pa[u][rb] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbi + rb) * KSW + ks) * FRAG);
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
-      qv[cb] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbj + cb) * KSW + ks) * FRAG);
+      qv[u][cb] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbj + cb) * KSW + ks) * FRAG);
   };
-  auto step = [&](const bf8 (&pa)[4], const bf8 (&qv)[NCB]) {
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-      typedef unsigned u4v __attribute__((ext_vector_type(4)));
-      const u4v neg = __builtin_bit_cast(u4v, qv[cb]) ^ u4v{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
-      const bf8 nq = __builtin_bit_cast(bf8, neg);
+  for (int u = 0; u < PK_DEPTH; ++u) load(u, min(ks0 + u, ks1 - 1));
+  for (int ks = ks0; ks < ks1; ks += PK_DEPTH) {
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
-        acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nq, pa[rb], acc[cb][rb], 0, 0, 0);
+    for (int u = 0; u < PK_DEPTH; ++u) {
+      if (ks + u < ks1) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          const bf8 nq = __builtin_bit_cast(bf8, __builtin_bit_cast(u4v, qv[u][cb]) ^ sgn);
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb)
+            acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nq, pa[u][rb], acc[cb][rb], 0, 0, 0);
+        }
+      }
+      load(u, min(ks + u + PK_DEPTH, ks1 - 1));
     }
-  };
-  bf8 pa0[4], qv0[NCB], pa1[4], qv1[NCB];
-  int ks = ks0;
-  if (ks < ks1) load(pa0, qv0, ks);
-  for (; ks + 1 < ks1; ks += 2) {
-    load(pa1, qv1, ks + 1);
-    step(pa0, qv0);
-    load(pa0, qv0, min(ks + 2, ks1 - 1));
-    step(pa1, qv1);
   }
-  if (ks < ks1) step(pa0, qv0);
 }
 
 // ---------------------------------------------------------------------------
@@ -206,7 +207,7 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_potrf_diag(const SysDesc* __re
       for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[cb][rb][v] = (float)tile[(16 * (2 * w + cb) + 4 * kg + v) * NB + 16 * rb + il];
-    packed_sub<2>(acc, Pk + D.pk_off + lane * 8, (k - K0) * 4, (k - K0) * 4 + 2 * w, 2 * Wp, 0, 2 * (k - K0));
+    packed_sub<2, 2>(acc, Pk + D.pk_off + lane * 8, (k - K0) * 4, (k - K0) * 4 + 2 * w, 2 * Wp, 0, 2 * (k - K0));
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
@@ -538,6 +539,17 @@ __global__ __launch_bounds__(256) void k_panel_col(const SysDesc* __restrict__ d
   float* sc = sC[w];
   const int KSW = 2 * Wp;
   const int il = lane & 15, kg = lane >> 4;
+  // Winv(k) fragments first: their latency overlaps the column update
+  const __bf16* Wf = Wpk + ((int64_t)s * Wp + (k - K0)) * 16 * FRAG + lane * 8;
+  bf8 whi[4][2], wlo[4][2];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+      if (ks == 0 || cb >= 2) {
+        whi[cb][ks] = *reinterpret_cast<const bf8*>(Wf + (int64_t)(2 * (2 * cb + ks)) * FRAG);
+        wlo[cb][ks] = *reinterpret_cast<const bf8*>(Wf + (int64_t)(2 * (2 * cb + ks) + 1) * FRAG);
+      }
   float* C = A + D.a_off + tile_index(i, k) * TILE;
   f4 acc[4][4];
 #pragma unroll
@@ -546,7 +558,7 @@ __global__ __launch_bounds__(256) void k_panel_col(const SysDesc* __restrict__ d
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[cb][rb][v] = C[(16 * cb + 4 * kg + v) * NB + 16 * rb + il];
-  if (k > K0) packed_sub<4>(acc, Pk + D.pk_off + lane * 8, (i - K0) * 4, (k - K0) * 4, KSW, 0, 2 * (k - K0));
+  if (k > K0) packed_sub<4, 4>(acc, Pk + D.pk_off + lane * 8, (i - K0) * 4, (k - K0) * 4, KSW, 0, 2 * (k - K0));
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
@@ -562,16 +574,6 @@ __global__ __launch_bounds__(256) void k_panel_col(const SysDesc* __restrict__ d
   // updates and corrected by the FP64 refinement); blocks of Winv above its
   // diagonal are zero and skipped.  A operand: Winv fragments (cb, ks);
   // B operand: C(16 rb + (lane & 15), 32 ks + 8 (lane >> 4) + e) from LDS.
-  const __bf16* Wf = Wpk + ((int64_t)s * Wp + (k - K0)) * 16 * FRAG + lane * 8;
-  bf8 whi[4][2], wlo[4][2];
-#pragma unroll
-  for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks)
-      if (ks == 0 || cb >= 2) {
-        whi[cb][ks] = *reinterpret_cast<const bf8*>(Wf + (int64_t)(2 * (2 * cb + ks)) * FRAG);
-        wlo[cb][ks] = *reinterpret_cast<const bf8*>(Wf + (int64_t)(2 * (2 * cb + ks) + 1) * FRAG);
-      }
   f4 o[4][4];
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
@@ -661,7 +663,7 @@ __global__ __launch_bounds__(256) void k_packed_trailing(const SysDesc* __restri
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[cb][rb][v] = C[(16 * cb + 4 * kg + v) * NB + 16 * rb + il];
-  packed_sub<4>(acc, Pk + D.pk_off + lane * 8, (i - K0) * 4, (j - K0) * 4, 2 * Wp, ks0, ks1);
+  packed_sub<4, 2>(acc, Pk + D.pk_off + lane * 8, (i - K0) * 4, (j - K0) * 4, 2 * Wp, ks0, ks1);
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
