@@ -46,10 +46,10 @@ TRAFFIC = {
     "chol_column_bf16": {
         "kernel": "k_panel_col",
         "source": "paper_1805_00569_amd/csrc/cholesky.hip",
-        "regions": ["template <int NCB>\n__device__ __forceinline__ void packed_sub(",
+        "regions": ["template <int NCB, int PK_DEPTH>\n__device__ __forceinline__ void packed_sub(",
                     "__global__ __launch_bounds__(256) void k_panel_col("],
-        "sha256": "414a8265193a8081a958a7885982e64cc1987595a6693f1d4ba52ded699fa81e",
-        "fetch_kib": 131025.86, "write_kib": 73738.84, "fetch_scale": 2.0, "write_scale": 1.0,
+        "sha256": "1b4058398b23271d231b57613a5790b322e4cae0b91530e8eeb9c67f40c18244",
+        "fetch_kib": 129462.2, "write_kib": 73728.8, "fetch_scale": 2.0, "write_scale": 1.0,
     },
 }
 
