@@ -81,28 +81,26 @@ __device__ __forceinline__ void packed_sub(f4 (&acc)[NCB][4], const __bf16* __re
 
 // ---------------------------------------------------------------------------
 // Diagonal block: A(k,k) = L L^T in FP64 and Winv(k) = L^-1, one workgroup of
-// two waves per system, with the matrix held in registers.  The block is
-// factored as A = U D^-1 U^T (U = L D^1/2: the columns of the successive
-// Schur complements, D the pivots), so a column step needs one reciprocal
-// and no square root on its dependency chain; L = U D^-1/2 and
-// L^-1 = D^-1/2 U~^-1 (U~ = U D^-1, unit lower triangular) are formed at the
-// end.
-//   Wave 0 (factor): lane r holds row r of the working matrix.  Step j takes
-//   the pivot d_j from lane j (computed by that lane at the end of step j-1),
-//   publishes column j of the Schur complement (u, zero at and above the
-//   diagonal) and 1/d_j through LDS, and applies a(r, c) -= (u_r / d_j) u_c.
-//   Wave 1 (inverse): lane t holds column t of X = U~^-1 as the right-hand
-//   side e_t of U~ x = e_t and runs the unit forward substitution step j
-//   right after the barrier that publishes column j (a ring of two LDS slots,
-//   one barrier per step).
-// The 64 steps run as 8 straight-line groups of 8; group g keeps only the
-// live columns [8g, 64) in registers (index c - 8g), so register indices are
-// compile-time constants and no step touches a finished column.
+// four waves per system, with the block held in LDS in FP64.  The block is
+// factored blockwise in 16 x 16 sub-blocks (right-looking):
+//   * a sub-block S_bb is factored by one wave as S_bb = U D^-1 U^T (U = the
+//     columns of the successive Schur complements, D the pivots), so a column
+//     step needs one reciprocal and no square root on its dependency chain;
+//     the same wave carries the inverse of the unit factor U~ = U D^-1 along
+//     (row operations applied to the identity), giving L_bb = U D^-1/2 and
+//     L_bb^-1 = D^-1/2 U~^-1.  Lane 4 r + q holds S(r, 4 q + e), e < 4; the
+//     column and inverse row of a step go through LDS inside the wave.
+//   * the sub-blocks below follow on FP64 matrix cores: L_ib = S_ib L_bb^-T
+//     and S_ij -= L_ib L_jb^T, formed by each wave that needs them.
+//   * L^-1 below its diagonal sub-blocks, W_ij = -L_ii^-1 sum_{j<=q<i} L_iq W_qj,
+//     is formed by the waves that are idle while wave 0 updates and factors the
+//     next diagonal sub-block, as soon as its inputs are final.
 // A pivot that is not positive (or NaN) marks the system failed with the
-// LAPACK-style 1-based global column index.
+// LAPACK-style 1-based global column index of the first such pivot.
 // ---------------------------------------------------------------------------
-constexpr int DIAG_THREADS = 128;
-constexpr int SW_LD = NB + 1;   // padded LDS column of the staged results
+constexpr int DIAG_THREADS = 256;
+constexpr int DIAG_PK_DEPTH = 4;   // fragment steps in flight in the fused column update
+constexpr int DG_LD = NB + 1;      // padded LDS column (doubles)
 
 __device__ __forceinline__ double read_lane(double v, int lane) {
   const long long b = __double_as_longlong(v);
@@ -120,70 +118,168 @@ __device__ __forceinline__ double recip(double d) {
   return fma(r, e, r);
 }
 
-struct DiagShared {
-  double slot[2][NB + 2];   // slot[b][c] = u_c of step j (j % 2 == b), 0 for c <= j; slot[b][NB] = 1 / d_j
-  double sU[NB * SW_LD];    // sU[j * SW_LD + r] = u_r of step j (0 above the diagonal)
-  double sX[NB * SW_LD];    // sX[t * SW_LD + j] = X(j, t)
-  double sd[NB];            // pivots, then 1 / sqrt(pivot)
+struct DiagLds {
+  double S[NB * DG_LD];   // working matrix (successive Schur complements), S[c * DG_LD + r]
+  double L[NB * DG_LD];   // factor L
+  double W[NB * DG_LD];   // L^-1; before that the FP32 partial sums of the fused column update, and two
+                          // partial products of the last block row of L^-1 in its unused upper blocks
+  double col[16];         // column j of the sub-block being factored (0 at and above the diagonal)
+  double xrow[16];        // row j of its running inverse
   int fail;
 };
 
-// Steps [J0, J0 + 8) with J0 = NB - W; v[c] holds column J0 + c.
-template <int W>
-__device__ __forceinline__ void diag_group(bool factor_wave, int lane, double (&v)[W], double& piv,
-                                           DiagShared& sh) {
-  constexpr int J0 = NB - W;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int j = J0 + q;
-    double* sl = sh.slot[q & 1];
-    double s = 0.0;
-    if (factor_wave) {
-      if (!(piv > 0.0)) {
-        if (lane == 0) sh.fail = j + 1;
-      } else {
-        const double rcp = recip(piv);
-        const double u = v[q];
-        s = lane > j ? u * rcp : 0.0;
-        sl[lane] = lane > j ? u : 0.0;
-        sh.sU[j * SW_LD + lane] = lane >= j ? u : 0.0;
-        if (lane == 0) {
-          sl[NB] = rcp;
-          sh.sd[j] = piv;
-        }
-        if (q + 1 < W) piv = read_lane(fma(-s, u, v[q + 1]), j + 1);   // next pivot, owned by lane j+1
-      }
-    }
-    __syncthreads();
-    if (sh.fail) return;
-    if (!factor_wave) {
-      const double x = v[q];   // X(j, t)
-      sh.sX[lane * SW_LD + j] = x;
-      s = x * sl[NB];
-    }
-    // a(., c) -= s * u_c for the columns c > j of the group's window
-    const double* col = sl + J0;
-#pragma unroll
-    for (int c = (q + 1) & ~1; c < W; c += 2) {
-      const double2 b = *reinterpret_cast<const double2*>(col + c);
-      if (c > q) v[c] = fma(-s, b.x, v[c]);
-      v[c + 1] = fma(-s, b.y, v[c + 1]);
-    }
-  }
+// Orders LDS traffic between the lanes of one wave: no compiler reordering
+// across it, and every lane has reached it.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
-// drop the group's 8 finished columns
-template <int W>
-__device__ __forceinline__ void diag_shift(const double (&v)[W], double (&w)[W - 8]) {
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Sub-block b (rows and columns [16 b, 16 b + 16)) by one wave: L_bb into
+// sh.L, L_bb^-1 into sh.W.  Returns 0 or the 1-based local column of the
+// first pivot that is not positive.
+__device__ __forceinline__ int diag_sub(DiagLds& sh, int b, int lane) {
+  const int r = lane >> 2, q = lane & 3, o = 16 * b;
+  double a[4], x[4], dc[4], dr = 1.0;
+  int fail = 0;
 #pragma unroll
-  for (int c = 0; c < W - 8; ++c) w[c] = v[c + 8];
+  for (int e = 0; e < 4; ++e) {
+    a[e] = sh.S[(o + 4 * q + e) * DG_LD + o + r];
+    x[e] = (r == 4 * q + e) ? 1.0 : 0.0;
+    dc[e] = 1.0;
+  }
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int jq = j >> 2, je = j & 3;
+    // publish column j of the Schur complement (below the pivot) and row j of the inverse
+    if (q == jq) sh.col[r] = (r > j) ? a[je] : 0.0;
+    if (r == j) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) sh.xrow[4 * q + e] = x[e];
+    }
+    wave_sync();
+    const double2 c01 = *reinterpret_cast<const double2*>(&sh.col[4 * q]);
+    const double2 c23 = *reinterpret_cast<const double2*>(&sh.col[4 * q + 2]);
+    const double2 x01 = *reinterpret_cast<const double2*>(&sh.xrow[4 * q]);
+    const double2 x23 = *reinterpret_cast<const double2*>(&sh.xrow[4 * q + 2]);
+    const double cr = sh.col[r];
+    const double d = read_lane(a[je], 4 * j + jq);   // pivot S(j, j)
+    fail = (fail == 0 && !(d > 0.0)) ? j + 1 : fail;
+    const double sr = cr * recip(d);                  // U~(r, j), 0 for r <= j
+    a[0] = fma(-sr, c01.x, a[0]);
+    a[1] = fma(-sr, c01.y, a[1]);
+    a[2] = fma(-sr, c23.x, a[2]);
+    a[3] = fma(-sr, c23.y, a[3]);
+    x[0] = fma(-sr, x01.x, x[0]);
+    x[1] = fma(-sr, x01.y, x[1]);
+    x[2] = fma(-sr, x23.x, x[2]);
+    x[3] = fma(-sr, x23.y, x[3]);
+    if (q == jq) dc[je] = d;
+    if (r == j) dr = d;
+    wave_sync();
+  }
+  if (fail) return fail;
+  const double rr = 1.0 / sqrt(dr);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int c = 4 * q + e;
+    const double rc = 1.0 / sqrt(dc[e]);
+    sh.L[(o + c) * DG_LD + o + r] = (r >= c) ? a[e] * rc : 0.0;
+    sh.W[(o + c) * DG_LD + o + r] = (r >= c) ? x[e] * rr : 0.0;
+  }
+  return 0;
+}
+
+// The 16 x 16 products below leave lane l holding Z(kl + 4 v, il) of their
+// result Z (il = l & 15, kl = l >> 4), which is also the operand layout of
+// the right factor of a following product.
+// L_ib (i > b) as L_bb^-1 S_ib^T: lane l holds L_ib(il, kl + 4 v)
+__device__ __forceinline__ d4 sub_panel(const DiagLds& sh, int i, int b, int il, int kl) {
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int t = 16 * b + 4 * kk + kl;
+    acc = mfma64(sh.W[t * DG_LD + 16 * b + il], sh.S[t * DG_LD + 16 * i + il], acc);
+  }
+  return acc;
+}
+
+// S_ij -= L_ib L_jb^T
+__device__ __forceinline__ void sub_update(DiagLds& sh, int i, int j, const d4& Li, const d4& Lj, int il, int kl) {
+  d4 acc;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) acc[v] = sh.S[(16 * j + il) * DG_LD + 16 * i + kl + 4 * v];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) acc = mfma64(-Li[kk], Lj[kk], acc);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) sh.S[(16 * j + il) * DG_LD + 16 * i + kl + 4 * v] = acc[v];
+}
+
+__device__ __forceinline__ void store_panel(DiagLds& sh, int i, int b, const d4& Li, int il, int kl) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) sh.L[(16 * b + kl + 4 * v) * DG_LD + 16 * i + il] = Li[v];
+}
+
+// acc += s X Y for 16 x 16 blocks of LDS arrays (top-left corners (xr, xc), (yr, yc))
+__device__ __forceinline__ d4 mm_ss(d4 acc, double s, const double* X, int xr, int xc, const double* Y, int yr, int yc,
+                                    int il, int kl) {
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk)
+    acc = mfma64(s * X[(xc + 4 * kk + kl) * DG_LD + xr + il], Y[(yc + il) * DG_LD + yr + 4 * kk + kl], acc);
+  return acc;
+}
+
+// acc += s X Y with Y a product result held as described above
+__device__ __forceinline__ d4 mm_sr(d4 acc, double s, const double* X, int xr, int xc, const d4& Y, int il, int kl) {
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) acc = mfma64(s * X[(xc + 4 * kk + kl) * DG_LD + xr + il], Y[kk], acc);
+  return acc;
+}
+
+__device__ __forceinline__ void st_blk(double* P, int zr, int zc, const d4& Z, int il, int kl) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) P[(zc + il) * DG_LD + zr + kl + 4 * v] = Z[v];
+}
+
+__device__ __forceinline__ d4 ld_blk(const double* P, int zr, int zc, int il, int kl) {
+  d4 z;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) z[v] = P[(zc + il) * DG_LD + zr + kl + 4 * v];
+  return z;
+}
+
+__device__ __forceinline__ void load4(const float* p, double (&v)[4]) {
+  const float4 f = *reinterpret_cast<const float4*>(p);
+  v[0] = f.x;
+  v[1] = f.y;
+  v[2] = f.z;
+  v[3] = f.w;
+}
+__device__ __forceinline__ void load4(const double* p, double (&v)[4]) {
+  const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
+  v[0] = a.x;
+  v[1] = a.y;
+  v[2] = b.x;
+  v[3] = b.y;
+}
+__device__ __forceinline__ void store4(float* p, const double (&v)[4]) {
+  *reinterpret_cast<float4*>(p) = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+}
+__device__ __forceinline__ void store4(double* p, const double (&v)[4]) {
+  reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
+  reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
 }
 
 // With a BF16 panel pack (Pk != null, FP32 storage) and k > K0, the block
 // first receives its column update A(k,k) -= sum_{q in [K0,k)} L(k,q) L(k,q)^T
-// from the packed fragments (each wave 32 of the 64 columns), staged in LDS.
-// Wpk (nullable): Winv(k) is also written as BF16 high/low operand
-// fragments for the BF16 panel solve (see k_panel_col).
+// from the packed fragments (waves: two column halves x two halves of the
+// fragment steps, summed in LDS).  Wpk (nullable): Winv(k) is also written as
+// BF16 high/low operand fragments for the BF16 panel solve (see k_panel_col).
 template <typename TS>
 __global__ __launch_bounds__(DIAG_THREADS) void k_potrf_diag(const SysDesc* __restrict__ desc,
                                                              SysStatus* __restrict__ st, TS* __restrict__ A,
@@ -192,101 +288,164 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_potrf_diag(const SysDesc* __re
                                                              __bf16* __restrict__ Wpk) {
   const int s = blockIdx.x;
   const SysDesc D = desc[s];
-  if (k >= D.T || st[s].status != 0 || D.level != level) return;
-  __shared__ __align__(16) DiagShared sh;
+  const int status = st[s].status;
+  if (k >= D.T || status != 0 || D.level != level) return;
+  __shared__ __align__(16) DiagLds sh;
   TS* tile = A + D.a_off + tile_index(k, k) * TILE;
-  const int lane = threadIdx.x & 63;
-  const bool factor_wave = threadIdx.x < 64;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int il = lane & 15, kl = lane >> 4;
   const bool fused = std::is_same<TS, float>::value && Pk != nullptr && k > K0;
   if (fused) {
-    const int w = threadIdx.x >> 6, il = lane & 15, kg = lane >> 4;
+    const int ch = w & 1, kh = w >> 1, half = k - K0;
     f4 acc[2][4];
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[cb][rb][v] = (float)tile[(16 * (2 * w + cb) + 4 * kg + v) * NB + 16 * rb + il];
-    packed_sub<2, 2>(acc, Pk + D.pk_off + lane * 8, (k - K0) * 4, (k - K0) * 4 + 2 * w, 2 * Wp, 0, 2 * (k - K0));
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
         for (int v = 0; v < 4; ++v)
-          sh.sX[(16 * (2 * w + cb) + 4 * kg + v) * SW_LD + 16 * rb + il] = (double)acc[cb][rb][v];
+          acc[cb][rb][v] = kh ? 0.f : (float)tile[(16 * (2 * ch + cb) + 4 * kl + v) * NB + 16 * rb + il];
+    packed_sub<2, DIAG_PK_DEPTH>(acc, Pk + D.pk_off + lane * 8, half * 4, half * 4 + 2 * ch, 2 * Wp, kh * half,
+                                 (kh + 1) * half);
+    float* part = reinterpret_cast<float*>(sh.W);
+    if (kh) {
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) part[(16 * (2 * ch + cb) + 4 * kl + v) * NB + 16 * rb + il] = acc[cb][rb][v];
+    }
     __syncthreads();
-  }
-  double v64[NB];
-  if (factor_wave) {
-    // row `lane` of A(k,k); entries above the diagonal are never consumed
-    if (fused) {
+    if (!kh) {
 #pragma unroll
-      for (int c = 0; c < NB; ++c) v64[c] = sh.sX[c * SW_LD + lane];
-    } else {
+      for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-      for (int c = 0; c < NB; ++c) v64[c] = (double)tile[c * NB + lane];
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int c = 16 * (2 * ch + cb) + 4 * kl + v, r = 16 * rb + il;
+            sh.S[c * DG_LD + r] = (double)(acc[cb][rb][v] + part[c * NB + r]);
+          }
     }
   } else {
+    double v[4][4];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) v64[c] = (c == lane) ? 1.0 : 0.0;
+    for (int i = 0; i < 4; ++i) load4(tile + 4 * (t + DIAG_THREADS * i), v[i]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = 4 * (t + DIAG_THREADS * i), c = e >> 6, r = e & 63;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sh.S[c * DG_LD + r + u] = v[i][u];
+    }
   }
-  if (threadIdx.x == 0) sh.fail = 0;
+  if (t == 0) sh.fail = 0;
   __syncthreads();
-  double piv = factor_wave ? read_lane(v64[0], 0) : 0.0;
-  do {
-    diag_group<64>(factor_wave, lane, v64, piv, sh);
+  if (w == 0) {
+    const int f = diag_sub(sh, 0, lane);
+    if (f && lane == 0) sh.fail = f;
+  }
+  __syncthreads();
+  // Block steps b = 0, 1, 2: wave 0 updates diagonal sub-block b + 1 and
+  // factors it at once; the other waves update the rest of the trailing
+  // sub-blocks and form the blocks of L^-1 whose inputs are final.
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
     if (sh.fail) break;
-    double v56[56];
-    diag_shift<64>(v64, v56);
-    diag_group<56>(factor_wave, lane, v56, piv, sh);
-    if (sh.fail) break;
-    double v48[48];
-    diag_shift<56>(v56, v48);
-    diag_group<48>(factor_wave, lane, v48, piv, sh);
-    if (sh.fail) break;
-    double v40[40];
-    diag_shift<48>(v48, v40);
-    diag_group<40>(factor_wave, lane, v40, piv, sh);
-    if (sh.fail) break;
-    double v32[32];
-    diag_shift<40>(v40, v32);
-    diag_group<32>(factor_wave, lane, v32, piv, sh);
-    if (sh.fail) break;
-    double v24[24];
-    diag_shift<32>(v32, v24);
-    diag_group<24>(factor_wave, lane, v24, piv, sh);
-    if (sh.fail) break;
-    double v16[16];
-    diag_shift<24>(v24, v16);
-    diag_group<16>(factor_wave, lane, v16, piv, sh);
-    if (sh.fail) break;
-    double v8[8];
-    diag_shift<16>(v16, v8);
-    diag_group<8>(factor_wave, lane, v8, piv, sh);
-  } while (false);
+    const d4 z = {0.0, 0.0, 0.0, 0.0};
+    if (w == 0) {
+      const d4 Ln = sub_panel(sh, b + 1, b, il, kl);
+      sub_update(sh, b + 1, b + 1, Ln, Ln, il, kl);
+      store_panel(sh, b + 1, b, Ln, il, kl);
+      wave_sync();
+      const int f = diag_sub(sh, b + 1, lane);
+      if (f && lane == 0) sh.fail = 16 * (b + 1) + f;
+    } else if (b == 0) {
+      if (w == 1) {
+        const d4 L2 = sub_panel(sh, 2, 0, il, kl), L1 = sub_panel(sh, 1, 0, il, kl);
+        sub_update(sh, 2, 2, L2, L2, il, kl);
+        sub_update(sh, 2, 1, L2, L1, il, kl);
+        store_panel(sh, 2, 0, L2, il, kl);
+      } else if (w == 2) {
+        const d4 L3 = sub_panel(sh, 3, 0, il, kl), L1 = sub_panel(sh, 1, 0, il, kl);
+        sub_update(sh, 3, 3, L3, L3, il, kl);
+        sub_update(sh, 3, 1, L3, L1, il, kl);
+        store_panel(sh, 3, 0, L3, il, kl);
+      } else {
+        const d4 L3 = sub_panel(sh, 3, 0, il, kl), L2 = sub_panel(sh, 2, 0, il, kl);
+        sub_update(sh, 3, 2, L3, L2, il, kl);
+      }
+    } else if (b == 1) {
+      if (w == 1) {
+        const d4 L3 = sub_panel(sh, 3, 1, il, kl), L2 = sub_panel(sh, 2, 1, il, kl);
+        sub_update(sh, 3, 2, L3, L2, il, kl);
+      } else if (w == 2) {
+        const d4 L3 = sub_panel(sh, 3, 1, il, kl);
+        sub_update(sh, 3, 3, L3, L3, il, kl);
+        store_panel(sh, 3, 1, L3, il, kl);
+      } else {
+        const d4 y = mm_ss(z, 1.0, sh.L, 16, 0, sh.W, 0, 0, il, kl);            // L_10 W_00
+        st_blk(sh.W, 16, 0, mm_sr(z, -1.0, sh.W, 16, 16, y, il, kl), il, kl);   // W_10
+      }
+    } else {
+      if (w == 1) {
+        const d4 y = mm_ss(z, 1.0, sh.L, 32, 16, sh.W, 16, 16, il, kl);         // L_21 W_11
+        st_blk(sh.W, 32, 16, mm_sr(z, -1.0, sh.W, 32, 32, y, il, kl), il, kl);  // W_21
+      } else if (w == 2) {
+        d4 y = mm_ss(z, 1.0, sh.L, 32, 0, sh.W, 0, 0, il, kl);                  // L_20 W_00
+        y = mm_ss(y, 1.0, sh.L, 32, 16, sh.W, 16, 0, il, kl);                   //  + L_21 W_10
+        st_blk(sh.W, 32, 0, mm_sr(z, -1.0, sh.W, 32, 32, y, il, kl), il, kl);   // W_20
+      } else {
+        // the terms of the last block row that do not involve block 2,
+        // parked in unused upper blocks of W
+        d4 y = mm_ss(z, 1.0, sh.L, 48, 0, sh.W, 0, 0, il, kl);                  // L_30 W_00
+        y = mm_ss(y, 1.0, sh.L, 48, 16, sh.W, 16, 0, il, kl);                   //  + L_31 W_10
+        st_blk(sh.W, 0, 48, y, il, kl);
+        st_blk(sh.W, 16, 48, mm_ss(z, 1.0, sh.L, 48, 16, sh.W, 16, 16, il, kl), il, kl);   // L_31 W_11
+      }
+    }
+    __syncthreads();
+  }
   if (sh.fail) {
-    if (threadIdx.x == 0) {
+    if (t == 0) {
       st[s].status = KRR_ENOTSPD;
       st[s].failed_pivot = k * NB + sh.fail;
     }
     return;
   }
+  if (w < 3) {
+    // last block row, column block jb: W_3jb = -L_33^-1 (parked terms + L_32 W_2jb)
+    const d4 z = {0.0, 0.0, 0.0, 0.0};
+    const int jb = 2 - w;
+    const d4 y0 = (w == 0) ? z : ld_blk(sh.W, 16 * jb, 48, il, kl);
+    const d4 y = mm_ss(y0, 1.0, sh.L, 48, 32, sh.W, 32, 16 * jb, il, kl);
+    st_blk(sh.W, 48, 16 * jb, mm_sr(z, -1.0, sh.W, 48, 48, y, il, kl), il, kl);
+  }
   __syncthreads();
-  if (threadIdx.x < NB) sh.sd[threadIdx.x] = 1.0 / sqrt(sh.sd[threadIdx.x]);
-  __syncthreads();
-  // L(r, c) = u_r(c) / sqrt(d_c); W(r, c) = X(r, c) / sqrt(d_r)
+  // L into the tile, L^-1 into Wt (zero above the diagonal)
   TS* wt = Wt + D.w_off + (int64_t)k * TILE;
-  for (int e = threadIdx.x; e < TILE; e += DIAG_THREADS) {
-    const int c = e >> 6, r = e & 63;
-    tile[e] = (TS)(sh.sU[c * SW_LD + r] * sh.sd[c]);
-    wt[e] = (TS)((r >= c) ? sh.sX[c * SW_LD + r] * sh.sd[r] : 0.0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int e = 4 * (t + DIAG_THREADS * i), c = e >> 6, r = e & 63;
+    double lv[4], wv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int rr = r + u;
+      const bool low = (rr >> 4) > (c >> 4) || ((rr >> 4) == (c >> 4) && rr >= c);
+      const double l0 = sh.L[c * DG_LD + rr], w0 = sh.W[c * DG_LD + rr];   // unconditional loads
+      lv[u] = low ? l0 : 0.0;
+      wv[u] = low ? w0 : 0.0;
+    }
+    store4(tile + e, lv);
+    store4(wt + e, wv);
   }
   if (Wpk != nullptr) {
     // fragment f = 2 cb + ks, part hl (0 high, 1 low): lane l holds Winv(16 cb + (l & 15), 32 ks + 8 (l >> 4) + e)
     // split from its FP32 value: hi = bf16(w), lo = bf16(w - hi)
     __bf16* base = Wpk + ((int64_t)s * Wp + (k - K0)) * 16 * FRAG;
-    for (int task = threadIdx.x; task < 8 * 64; task += DIAG_THREADS) {
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int task = t + DIAG_THREADS * it;
       const int f = task >> 6, l = task & 63;
       const int cb = f >> 1, ks = f & 1;
       const int row = 16 * cb + (l & 15);
@@ -294,10 +453,11 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_potrf_diag(const SysDesc* __re
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int col = 32 * ks + 8 * (l >> 4) + e;
-        const float w = (float)((row >= col) ? sh.sX[col * SW_LD + row] * sh.sd[row] : 0.0);
-        const __bf16 h = (__bf16)w;
+        const double w0 = sh.W[col * DG_LD + row];
+        const float wv = (row >= col) ? (float)w0 : 0.f;
+        const __bf16 h = (__bf16)wv;
         hi[e] = h;
-        lo[e] = (__bf16)(w - (float)h);
+        lo[e] = (__bf16)(wv - (float)h);
       }
       *reinterpret_cast<bf8*>(base + (int64_t)(2 * f) * FRAG + l * 8) = hi;
       *reinterpret_cast<bf8*>(base + (int64_t)(2 * f + 1) * FRAG + l * 8) = lo;

@@ -184,6 +184,28 @@ def test_not_spd_reports_pivot_and_keeps_others(ctx, dev):
     np.testing.assert_allclose(models[0].alpha(0).cpu().numpy(), y / 1.5, rtol=1e-15)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+@pytest.mark.parametrize("dup", [(100, 101), (40, 90), (3, 150)])
+def test_not_spd_pivot_inside_tiles(ctx, dev, prec, dup):
+    """Far-apart points (K = I) with point dup[1] a copy of point dup[0] and a
+    negative shift lam: every pivot is 1 + lam except the Schur complement of
+    the copy, (1 + lam) - 1 / (1 + lam) < 0, so the first failing pivot is
+    dup[1] + 1 (1-based).  The pairs put it inside a diagonal tile's third
+    16-column sub-block, across two tiles, and in the last tile."""
+    m = 160
+    X = np.concatenate([np.arange(m)[:, None] * 100.0, np.zeros((m, 1))], axis=1)
+    X[dup[1]] = X[dup[0]]
+    y = np.linspace(-1, 1, m)
+    r = O.fit_one(X, y, 1.0, -0.25)
+    assert r["status"] == O.STATUS_NOT_SPD and r["pivot"] == dup[1] + 1
+    Xg = X if prec == "fp64" else X.astype(np.float32)
+    Xd = _t(Xg, dev)
+    C, a, _ = ctx.partition(Xd, 1, "given", centroids=_t(np.zeros((1, 2), Xg.dtype), dev))
+    models, info, st = ctx.fit(Xd, _t(y.astype(Xg.dtype), dev), a, C, 1, [krr.Params(sigma=1.0, lam=-0.25, prec=prec)])
+    assert st == krr.KRR_ENOTSPD
+    assert info[0]["status"] == krr.KRR_ENOTSPD and info[0]["failed_pivot"] == dup[1] + 1
+
+
 def test_empty_and_tiny_partitions(ctx, dev):
     g = np.random.default_rng(82)
     X = g.standard_normal((70, 3))
