@@ -118,11 +118,19 @@ __device__ __forceinline__ double recip(double d) {
   return fma(r, e, r);
 }
 
+// LDS of the diagonal block (66.7 KB, so that the column kernel that carries
+// it keeps two workgroups per CU).  Sub-blocks (16 x 16) are addressed by
+// their top-left element; S[c * DG_LD + r] is element (r, c).
+//   S: the working matrix (successive Schur complements); a diagonal
+//      sub-block of S is replaced by its factor L_bb once factored, and two
+//      consumed sub-blocks park partial sums of the last block row of L^-1.
+//   W: L^-1 in its lower sub-blocks; the factor's off-diagonal sub-blocks
+//      L_ij (i > j) in the unused upper sub-block (j, i), untransposed
+//      (element (r, c) of L_ij at W[(16 i + c) * DG_LD + 16 j + r]); before
+//      all that, the FP32 partial sums of the fused column update.
 struct DiagLds {
-  double S[NB * DG_LD];   // working matrix (successive Schur complements), S[c * DG_LD + r]
-  double L[NB * DG_LD];   // factor L
-  double W[NB * DG_LD];   // L^-1; before that the FP32 partial sums of the fused column update, and two
-                          // partial products of the last block row of L^-1 in its unused upper blocks
+  double S[NB * DG_LD];
+  double W[NB * DG_LD];
   double col[16];         // column j of the sub-block being factored (0 at and above the diagonal)
   double xrow[16];        // row j of its running inverse
   int fail;
@@ -140,8 +148,8 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Sub-block b (rows and columns [16 b, 16 b + 16)) by one wave: L_bb into
-// sh.L, L_bb^-1 into sh.W.  Returns 0 or the 1-based local column of the
+// Sub-block b (rows and columns [16 b, 16 b + 16)) by one wave: L_bb in
+// place of S_bb, L_bb^-1 into sh.W.  Returns 0 or the 1-based local column of the
 // first pivot that is not positive.
 __device__ __forceinline__ int diag_sub(DiagLds& sh, int b, int lane) {
   const int r = lane >> 2, q = lane & 3, o = 16 * b;
@@ -189,7 +197,7 @@ __device__ __forceinline__ int diag_sub(DiagLds& sh, int b, int lane) {
   for (int e = 0; e < 4; ++e) {
     const int c = 4 * q + e;
     const double rc = 1.0 / sqrt(dc[e]);
-    sh.L[(o + c) * DG_LD + o + r] = (r >= c) ? a[e] * rc : 0.0;
+    sh.S[(o + c) * DG_LD + o + r] = (r >= c) ? a[e] * rc : 0.0;
     sh.W[(o + c) * DG_LD + o + r] = (r >= c) ? x[e] * rr : 0.0;
   }
   return 0;
@@ -220,9 +228,10 @@ __device__ __forceinline__ void sub_update(DiagLds& sh, int i, int j, const d4& 
   for (int v = 0; v < 4; ++v) sh.S[(16 * j + il) * DG_LD + 16 * i + kl + 4 * v] = acc[v];
 }
 
+// L_ib into the upper sub-block (b, i) of W
 __device__ __forceinline__ void store_panel(DiagLds& sh, int i, int b, const d4& Li, int il, int kl) {
 #pragma unroll
-  for (int v = 0; v < 4; ++v) sh.L[(16 * b + kl + 4 * v) * DG_LD + 16 * i + il] = Li[v];
+  for (int v = 0; v < 4; ++v) sh.W[(16 * i + kl + 4 * v) * DG_LD + 16 * b + il] = Li[v];
 }
 
 // acc += s X Y for 16 x 16 blocks of LDS arrays (top-left corners (xr, xc), (yr, yc))
@@ -280,19 +289,15 @@ __device__ __forceinline__ void store4(double* p, const double (&v)[4]) {
 // from the packed fragments (waves: two column halves x two halves of the
 // fragment steps, summed in LDS).  Wpk (nullable): Winv(k) is also written as
 // BF16 high/low operand fragments for the BF16 panel solve (see k_panel_col).
+// The diagonal block k of system s by the DIAG_THREADS threads of a
+// workgroup (thread t); D = desc[s], already checked to be factored in this
+// pass with k < D.T.
 template <typename TS>
-__global__ __launch_bounds__(DIAG_THREADS) void k_potrf_diag(const SysDesc* __restrict__ desc,
-                                                             SysStatus* __restrict__ st, TS* __restrict__ A,
-                                                             TS* __restrict__ Wt, int k, int level,
-                                                             const __bf16* __restrict__ Pk, int K0, int Wp,
-                                                             __bf16* __restrict__ Wpk) {
-  const int s = blockIdx.x;
-  const SysDesc D = desc[s];
-  const int status = st[s].status;
-  if (k >= D.T || status != 0 || D.level != level) return;
-  __shared__ __align__(16) DiagLds sh;
+__device__ __forceinline__ void diag_block(const SysDesc& D, int s, SysStatus* __restrict__ st, TS* __restrict__ A,
+                                           TS* __restrict__ Wt, int k, const __bf16* __restrict__ Pk, int K0, int Wp,
+                                           __bf16* __restrict__ Wpk, DiagLds& sh, int t) {
   TS* tile = A + D.a_off + tile_index(k, k) * TILE;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int lane = t & 63, w = t >> 6;
   const int il = lane & 15, kl = lane >> 4;
   const bool fused = std::is_same<TS, float>::value && Pk != nullptr && k > K0;
   if (fused) {
@@ -384,24 +389,24 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_potrf_diag(const SysDesc* __re
         sub_update(sh, 3, 3, L3, L3, il, kl);
         store_panel(sh, 3, 1, L3, il, kl);
       } else {
-        const d4 y = mm_ss(z, 1.0, sh.L, 16, 0, sh.W, 0, 0, il, kl);            // L_10 W_00
+        const d4 y = mm_ss(z, 1.0, sh.W, 0, 16, sh.W, 0, 0, il, kl);            // L_10 W_00
         st_blk(sh.W, 16, 0, mm_sr(z, -1.0, sh.W, 16, 16, y, il, kl), il, kl);   // W_10
       }
     } else {
       if (w == 1) {
-        const d4 y = mm_ss(z, 1.0, sh.L, 32, 16, sh.W, 16, 16, il, kl);         // L_21 W_11
+        const d4 y = mm_ss(z, 1.0, sh.W, 16, 32, sh.W, 16, 16, il, kl);         // L_21 W_11
         st_blk(sh.W, 32, 16, mm_sr(z, -1.0, sh.W, 32, 32, y, il, kl), il, kl);  // W_21
       } else if (w == 2) {
-        d4 y = mm_ss(z, 1.0, sh.L, 32, 0, sh.W, 0, 0, il, kl);                  // L_20 W_00
-        y = mm_ss(y, 1.0, sh.L, 32, 16, sh.W, 16, 0, il, kl);                   //  + L_21 W_10
+        d4 y = mm_ss(z, 1.0, sh.W, 0, 32, sh.W, 0, 0, il, kl);                  // L_20 W_00
+        y = mm_ss(y, 1.0, sh.W, 16, 32, sh.W, 16, 0, il, kl);                   //  + L_21 W_10
         st_blk(sh.W, 32, 0, mm_sr(z, -1.0, sh.W, 32, 32, y, il, kl), il, kl);   // W_20
       } else {
-        // the terms of the last block row that do not involve block 2,
-        // parked in unused upper blocks of W
-        d4 y = mm_ss(z, 1.0, sh.L, 48, 0, sh.W, 0, 0, il, kl);                  // L_30 W_00
-        y = mm_ss(y, 1.0, sh.L, 48, 16, sh.W, 16, 0, il, kl);                   //  + L_31 W_10
-        st_blk(sh.W, 0, 48, y, il, kl);
-        st_blk(sh.W, 16, 48, mm_ss(z, 1.0, sh.L, 48, 16, sh.W, 16, 16, il, kl), il, kl);   // L_31 W_11
+        // the terms of the last block row that do not involve block 2, parked
+        // in the consumed sub-blocks (1, 0) and (2, 0) of S
+        d4 y = mm_ss(z, 1.0, sh.W, 0, 48, sh.W, 0, 0, il, kl);                  // L_30 W_00
+        y = mm_ss(y, 1.0, sh.W, 16, 48, sh.W, 16, 0, il, kl);                   //  + L_31 W_10
+        st_blk(sh.S, 16, 0, y, il, kl);
+        st_blk(sh.S, 32, 0, mm_ss(z, 1.0, sh.W, 16, 48, sh.W, 16, 16, il, kl), il, kl);   // L_31 W_11
       }
     }
     __syncthreads();
@@ -417,8 +422,8 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_potrf_diag(const SysDesc* __re
     // last block row, column block jb: W_3jb = -L_33^-1 (parked terms + L_32 W_2jb)
     const d4 z = {0.0, 0.0, 0.0, 0.0};
     const int jb = 2 - w;
-    const d4 y0 = (w == 0) ? z : ld_blk(sh.W, 16 * jb, 48, il, kl);
-    const d4 y = mm_ss(y0, 1.0, sh.L, 48, 32, sh.W, 32, 16 * jb, il, kl);
+    const d4 y0 = (w == 0) ? z : ld_blk(sh.S, 16 * (jb + 1), 0, il, kl);
+    const d4 y = mm_ss(y0, 1.0, sh.W, 32, 48, sh.W, 32, 16 * jb, il, kl);
     st_blk(sh.W, 48, 16 * jb, mm_sr(z, -1.0, sh.W, 48, 48, y, il, kl), il, kl);
   }
   __syncthreads();
@@ -430,11 +435,13 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_potrf_diag(const SysDesc* __re
     double lv[4], wv[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int rr = r + u;
-      const bool low = (rr >> 4) > (c >> 4) || ((rr >> 4) == (c >> 4) && rr >= c);
-      const double l0 = sh.L[c * DG_LD + rr], w0 = sh.W[c * DG_LD + rr];   // unconditional loads
-      lv[u] = low ? l0 : 0.0;
-      wv[u] = low ? w0 : 0.0;
+      const int rr = r + u, bi = rr >> 4, bj = c >> 4;
+      // unconditional loads: diagonal sub-blocks of L from S, the others from the upper part of W
+      const double ld = sh.S[c * DG_LD + rr];
+      const double lo = sh.W[(16 * bi + (c & 15)) * DG_LD + 16 * bj + (rr & 15)];
+      const double w0 = sh.W[c * DG_LD + rr];
+      lv[u] = bi > bj ? lo : (bi == bj ? ld : 0.0);
+      wv[u] = (bi > bj || (bi == bj && rr >= c)) ? w0 : 0.0;
     }
     store4(tile + e, lv);
     store4(wt + e, wv);
@@ -463,6 +470,20 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_potrf_diag(const SysDesc* __re
       *reinterpret_cast<bf8*>(base + (int64_t)(2 * f + 1) * FRAG + l * 8) = lo;
     }
   }
+}
+
+template <typename TS>
+__global__ __launch_bounds__(DIAG_THREADS) void k_potrf_diag(const SysDesc* __restrict__ desc,
+                                                             SysStatus* __restrict__ st, TS* __restrict__ A,
+                                                             TS* __restrict__ Wt, int k, int level,
+                                                             const __bf16* __restrict__ Pk, int K0, int Wp,
+                                                             __bf16* __restrict__ Wpk) {
+  const int s = blockIdx.x;
+  const SysDesc D = desc[s];
+  const int status = st[s].status;
+  if (k >= D.T || status != 0 || D.level != level) return;
+  __shared__ __align__(16) DiagLds sh;
+  diag_block<TS>(D, s, st, A, Wt, k, Pk, K0, Wp, Wpk, sh, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -685,18 +706,9 @@ __global__ __launch_bounds__(256) void k_tile_gemm_bf16(const SysDesc* __restric
 //   L(i,k)  = C(i,k) Winv(k)^T                    FP32 matrix cores, C through the wave's LDS
 //   L(i,k) -> the FP32 tile, and (do_pack) BF16 fragments of the pack
 constexpr int PC_LD = NB + 1;
-__global__ __launch_bounds__(256) void k_panel_col(const SysDesc* __restrict__ desc, const SysStatus* __restrict__ st,
-                                                   float* __restrict__ A, const __bf16* __restrict__ Wpk,
-                                                   __bf16* __restrict__ Pk, int K0, int k, int Wp, int level,
-                                                   int do_pack) {
-  const int s = blockIdx.z;
-  const SysDesc D = desc[s];
-  if (st[s].status != 0 || D.level != level) return;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = k + 1 + 4 * blockIdx.x + w;
-  if (i >= D.T) return;
-  __shared__ float sC[4][NB * PC_LD];
-  float* sc = sC[w];
+__device__ __forceinline__ void panel_col_tile(const SysDesc& D, int s, int i, int lane, float* __restrict__ A,
+                                               const __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk, int K0, int k,
+                                               int Wp, int do_pack, float* __restrict__ sc) {
   const int KSW = 2 * Wp;
   const int il = lane & 15, kg = lane >> 4;
   // Winv(k) fragments first: their latency overlaps the column update
@@ -788,6 +800,41 @@ __global__ __launch_bounds__(256) void k_panel_col(const SysDesc* __restrict__ d
       const int rb = (i - K0) * 4 + rbl, ks = 2 * (k - K0) + h;
       *reinterpret_cast<bf8*>(Pout + ((int64_t)rb * KSW + ks) * FRAG) = v;
     }
+}
+
+// diag_next: the first workgroup of each system (tile rows k+1 .. k+4,
+// dispatched before the other workgroups) then factors diagonal block k + 1
+// with its column update over the panel columns [K0, k] (diag_block), which
+// needs only tile row k + 1 of this column; its latency hides behind the
+// other workgroups' tiles.  Grid: n_sys * ng workgroups, ng = tile groups of
+// four rows; workgroup b < n_sys is group 0 of system b, the others follow
+// system by system.
+__global__ __launch_bounds__(256) void k_panel_col(const SysDesc* __restrict__ desc, SysStatus* __restrict__ st,
+                                                   float* __restrict__ A, float* __restrict__ Wt,
+                                                   __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk, int K0, int k,
+                                                   int Wp, int level, int do_pack, int diag_next, int n_sys, int ng) {
+  const int b = blockIdx.x;
+  int s, g;
+  if (b < n_sys) {
+    s = b;
+    g = 0;
+  } else {
+    s = (b - n_sys) / (ng - 1);
+    g = 1 + (b - n_sys) % (ng - 1);
+  }
+  const SysDesc D = desc[s];
+  if (st[s].status != 0 || D.level != level) return;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = k + 1 + 4 * g + w;
+  __shared__ __align__(16) union {
+    float sC[4][NB * PC_LD];   // per wave: the tile being solved
+    DiagLds dg;
+  } lds;
+  if (i < D.T) panel_col_tile(D, s, i, lane, A, Wpk, Pk, K0, k, Wp, do_pack, lds.sC[w]);
+  if (diag_next && g == 0 && k + 1 < D.T) {
+    __syncthreads();   // tile row k + 1 (factor and pack) complete; LDS free
+    diag_block<float>(D, s, st, A, Wt, k + 1, Pk, K0, Wp, Wpk, lds.dg, threadIdx.x);
+  }
 }
 
 // Trailing update A(i,j) -= sum_{q in panel} L(i,q) L(j,q)^T for the lower
@@ -892,15 +939,17 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
     }
   };
   if (packed) {
-    // Two launches per panel column: the diagonal block with its own column
-    // update, then the fused column update + panel solve + BF16 packing of
-    // the tiles below it; after the panel, one trailing update.  Wpk: BF16
-    // high/low fragments of the panel's inverse diagonal blocks.
+    // One launch per panel column: the fused column update + panel solve +
+    // BF16 packing of the tiles below the diagonal, which also factors the
+    // next diagonal block of the panel; the panel's first diagonal block
+    // (after the trailing update) has a launch of its own.  After the panel,
+    // one trailing update.  Wpk: BF16 high/low fragments of the panel's
+    // inverse diagonal blocks.
     __bf16* Wpk = (__bf16*)ws_get(ctx, "chol_wpk", (size_t)n_sys * Wp * 16 * FRAG * sizeof(__bf16));
     for (int K0 = 0; K0 < Tmax; K0 += Wp) {
       const int K1 = std::min(K0 + Wp, Tmax);
       for (int k = K0; k < K1; ++k) {
-        {
+        if (k == K0) {
           KernelTimer kt(ctx, s, "chol_diag", each([&](double m) {
             const double b = std::min<double>(NB, m - k * NB);
             return b > 0 ? 2.0 * b * b * b / 3.0 : 0.0;
@@ -910,19 +959,23 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
           check_launch(ctx, s, "potrf_diag");
         }
         if (k + 1 < Tmax) {
-          // credited: the column update of the tiles below the diagonal and their panel solve;
-          // algorithmic bytes: read those tiles and write their factor (FP32)
+          // credited: the column update of the tiles below the diagonal and their panel solve, and
+          // the next diagonal block inside the panel (its factorisation); algorithmic bytes: read
+          // those tiles and write their factor, read the next diagonal tile and write its factor
+          // and inverse (FP32)
+          const bool nd = k + 1 < K1;
           KernelTimer kt(ctx, s, col_name, each([&](double m) {
-            const double rows = m - (k + 1) * NB;
-            return rows > 0 ? 2.0 * rows * NB * (k - K0) * NB + rows * (double)NB * NB : 0.0;
+            const double rows = m - (k + 1) * NB, b = std::min<double>(NB, rows);
+            return rows > 0 ? 2.0 * rows * NB * (k - K0) * NB + rows * (double)NB * NB + (nd ? 2.0 * b * b * b / 3.0 : 0.0)
+                            : 0.0;
           }), 1, each([&](double m) {
             const double rows = m - (k + 1) * NB;
-            return rows > 0 ? 2.0 * rows * NB * sizeof(float) : 0.0;
+            return rows > 0 ? 2.0 * rows * NB * sizeof(float) + (nd ? 3.0 * NB * NB * sizeof(float) : 0.0) : 0.0;
           }));
           const int do_pack = (k + 1 < K1 || K1 < Tmax) ? 1 : 0;
-          hipLaunchKernelGGL(k_panel_col, dim3((unsigned)ceil_div(Tmax - k - 1, 4), 1, (unsigned)n_sys), dim3(256), 0,
-                             s, desc, (const SysStatus*)st, (float*)A, (const __bf16*)Wpk, (__bf16*)Pk, K0, k, Wp,
-                             level, do_pack);
+          const int ng = ceil_div(Tmax - k - 1, 4);
+          hipLaunchKernelGGL(k_panel_col, dim3((unsigned)(ng * n_sys)), dim3(256), 0, s, desc, st, (float*)A,
+                             (float*)Wt, Wpk, (__bf16*)Pk, K0, k, Wp, level, do_pack, nd ? 1 : 0, n_sys, ng);
           check_launch(ctx, s, "panel_col");
         }
       }
