@@ -133,6 +133,7 @@ struct DiagLds {
   double W[NB * DG_LD];
   double col[16];         // column j of the sub-block being factored (0 at and above the diagonal)
   double xrow[16];        // row j of its running inverse
+  double zv[NB];          // right-hand side block of the fused forward solve
   int fail;
 };
 
@@ -292,10 +293,13 @@ __device__ __forceinline__ void store4(double* p, const double (&v)[4]) {
 // The diagonal block k of system s by the DIAG_THREADS threads of a
 // workgroup (thread t); D = desc[s], already checked to be factored in this
 // pass with k < D.T.
+// zf (nullable, FP64 vectors at D.v_off): forward solve carried along the
+// factorisation; on entry block k holds b_k - sum_{j<k} L(k,j) z_j, and it
+// is replaced by z_k = L(k,k)^-1 (that).
 template <typename TS>
 __device__ __forceinline__ void diag_block(const SysDesc& D, int s, SysStatus* __restrict__ st, TS* __restrict__ A,
                                            TS* __restrict__ Wt, int k, const __bf16* __restrict__ Pk, int K0, int Wp,
-                                           __bf16* __restrict__ Wpk, DiagLds& sh, int t) {
+                                           __bf16* __restrict__ Wpk, double* __restrict__ zf, DiagLds& sh, int t) {
   TS* tile = A + D.a_off + tile_index(k, k) * TILE;
   const int lane = t & 63, w = t >> 6;
   const int il = lane & 15, kl = lane >> 4;
@@ -426,7 +430,22 @@ __device__ __forceinline__ void diag_block(const SysDesc& D, int s, SysStatus* _
     const d4 y = mm_ss(y0, 1.0, sh.W, 32, 48, sh.W, 32, 16 * jb, il, kl);
     st_blk(sh.W, 48, 16 * jb, mm_sr(z, -1.0, sh.W, 48, 48, y, il, kl), il, kl);
   }
+  if (zf != nullptr && t < NB) sh.zv[t] = zf[D.v_off + (int64_t)k * NB + t];
   __syncthreads();
+  if (zf != nullptr) {
+    // z_k(r) = sum_{c <= r} L^-1(r, c) b(c): four threads per row, 16 columns each
+    const int r = t >> 2, q = t & 3;
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int c = 16 * q + u;
+      const double w0 = sh.W[c * DG_LD + r];   // unconditional load; the upper part holds L
+      acc = fma(c <= r ? w0 : 0.0, sh.zv[c], acc);
+    }
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    if (q == 0) zf[D.v_off + (int64_t)k * NB + r] = acc;
+  }
   // L into the tile, L^-1 into Wt (zero above the diagonal)
   TS* wt = Wt + D.w_off + (int64_t)k * TILE;
 #pragma unroll
@@ -477,13 +496,13 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_potrf_diag(const SysDesc* __re
                                                              SysStatus* __restrict__ st, TS* __restrict__ A,
                                                              TS* __restrict__ Wt, int k, int level,
                                                              const __bf16* __restrict__ Pk, int K0, int Wp,
-                                                             __bf16* __restrict__ Wpk) {
+                                                             __bf16* __restrict__ Wpk, double* __restrict__ zf) {
   const int s = blockIdx.x;
   const SysDesc D = desc[s];
   const int status = st[s].status;
   if (k >= D.T || status != 0 || D.level != level) return;
   __shared__ __align__(16) DiagLds sh;
-  diag_block<TS>(D, s, st, A, Wt, k, Pk, K0, Wp, Wpk, sh, threadIdx.x);
+  diag_block<TS>(D, s, st, A, Wt, k, Pk, K0, Wp, Wpk, zf, sh, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -708,7 +727,7 @@ __global__ __launch_bounds__(256) void k_tile_gemm_bf16(const SysDesc* __restric
 constexpr int PC_LD = NB + 1;
 __device__ __forceinline__ void panel_col_tile(const SysDesc& D, int s, int i, int lane, float* __restrict__ A,
                                                const __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk, int K0, int k,
-                                               int Wp, int do_pack, float* __restrict__ sc) {
+                                               int Wp, int do_pack, double* __restrict__ zf, float* __restrict__ sc) {
   const int KSW = 2 * Wp;
   const int il = lane & 15, kg = lane >> 4;
   // Winv(k) fragments first: their latency overlaps the column update
@@ -784,6 +803,32 @@ __device__ __forceinline__ void panel_col_tile(const SysDesc& D, int s, int i, i
         C[c * NB + r] = o[cb][rb][v];
         sc[c * PC_LD + r] = o[cb][rb][v];
       }
+  if (zf != nullptr) {
+    // forward solve: b_i -= L(i,k) z_k (FP64 sums of the stored FP32 factor)
+    const double* zk = zf + D.v_off + (int64_t)k * NB;
+    double zc[4][4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) zc[cb][v] = zk[16 * cb + 4 * kg + v];
+    double pr[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      double a = 0.0;
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) a = fma((double)o[cb][rb][v], zc[cb][v], a);
+      a += __shfl_xor(a, 16, 64);
+      a += __shfl_xor(a, 32, 64);
+      pr[rb] = a;
+    }
+    if (kg == 0) {
+      double* bi = zf + D.v_off + (int64_t)i * NB;
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) bi[16 * rb + il] -= pr[rb];
+    }
+  }
   if (!do_pack) return;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -812,7 +857,8 @@ __device__ __forceinline__ void panel_col_tile(const SysDesc& D, int s, int i, i
 __global__ __launch_bounds__(256) void k_panel_col(const SysDesc* __restrict__ desc, SysStatus* __restrict__ st,
                                                    float* __restrict__ A, float* __restrict__ Wt,
                                                    __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk, int K0, int k,
-                                                   int Wp, int level, int do_pack, int diag_next, int n_sys, int ng) {
+                                                   int Wp, int level, int do_pack, int diag_next, int n_sys, int ng,
+                                                   double* __restrict__ zf) {
   const int b = blockIdx.x;
   int s, g;
   if (b < n_sys) {
@@ -830,10 +876,10 @@ __global__ __launch_bounds__(256) void k_panel_col(const SysDesc* __restrict__ d
     float sC[4][NB * PC_LD];   // per wave: the tile being solved
     DiagLds dg;
   } lds;
-  if (i < D.T) panel_col_tile(D, s, i, lane, A, Wpk, Pk, K0, k, Wp, do_pack, lds.sC[w]);
+  if (i < D.T) panel_col_tile(D, s, i, lane, A, Wpk, Pk, K0, k, Wp, do_pack, zf, lds.sC[w]);
   if (diag_next && g == 0 && k + 1 < D.T) {
     __syncthreads();   // tile row k + 1 (factor and pack) complete; LDS free
-    diag_block<float>(D, s, st, A, Wt, k + 1, Pk, K0, Wp, Wpk, lds.dg, threadIdx.x);
+    diag_block<float>(D, s, st, A, Wt, k + 1, Pk, K0, Wp, Wpk, zf, lds.dg, threadIdx.x);
   }
 }
 
@@ -906,7 +952,7 @@ void launch_update(krr_ctx ctx, hipStream_t s, bool bf16, int mode, const SysDes
 
 template <typename TS>
 void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, int n_sys, int Tmax, TS* A, TS* Wt,
-              bool bf16, int Wp, int level, const SysDesc* hdesc, __bf16* Pk) {
+              bool bf16, int Wp, int level, const SysDesc* hdesc, __bf16* Pk, double* zf) {
   // algorithmic flops of each launch (timing only), from the real sizes m
   auto each = [&](auto&& f) {
     double tot = 0.0;
@@ -927,7 +973,7 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
         return b > 0 ? 2.0 * b * b * b / 3.0 : 0.0;
       }), 0);
       hipLaunchKernelGGL((k_potrf_diag<TS>), dim3(n_sys), dim3(DIAG_THREADS), 0, s, desc, st, A, Wt, k, level,
-                         (const __bf16*)nullptr, 0, 1, (__bf16*)nullptr);
+                         (const __bf16*)nullptr, 0, 1, (__bf16*)nullptr, (double*)nullptr);
       check_launch(ctx, s, "potrf_diag");
     }
     if (k + 1 < Tmax) {
@@ -944,7 +990,9 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
     // next diagonal block of the panel; the panel's first diagonal block
     // (after the trailing update) has a launch of its own.  After the panel,
     // one trailing update.  Wpk: BF16 high/low fragments of the panel's
-    // inverse diagonal blocks.
+    // inverse diagonal blocks.  zf (nullable): the forward solve z = L^-1 b in
+    // place, carried column by column (the column launches subtract
+    // L(i,k) z_k from the blocks below, each diagonal block forms its z_k).
     __bf16* Wpk = (__bf16*)ws_get(ctx, "chol_wpk", (size_t)n_sys * Wp * 16 * FRAG * sizeof(__bf16));
     for (int K0 = 0; K0 < Tmax; K0 += Wp) {
       const int K1 = std::min(K0 + Wp, Tmax);
@@ -955,7 +1003,7 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
             return b > 0 ? 2.0 * b * b * b / 3.0 : 0.0;
           }), 0);
           hipLaunchKernelGGL((k_potrf_diag<TS>), dim3(n_sys), dim3(DIAG_THREADS), 0, s, desc, st, A, Wt, k, level,
-                             (const __bf16*)Pk, K0, Wp, Wpk);
+                             (const __bf16*)Pk, K0, Wp, Wpk, zf);
           check_launch(ctx, s, "potrf_diag");
         }
         if (k + 1 < Tmax) {
@@ -975,7 +1023,7 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
           const int do_pack = (k + 1 < K1 || K1 < Tmax) ? 1 : 0;
           const int ng = ceil_div(Tmax - k - 1, 4);
           hipLaunchKernelGGL(k_panel_col, dim3((unsigned)(ng * n_sys)), dim3(256), 0, s, desc, st, (float*)A,
-                             (float*)Wt, Wpk, (__bf16*)Pk, K0, k, Wp, level, do_pack, nd ? 1 : 0, n_sys, ng);
+                             (float*)Wt, Wpk, (__bf16*)Pk, K0, k, Wp, level, do_pack, nd ? 1 : 0, n_sys, ng, zf);
           check_launch(ctx, s, "panel_col");
         }
       }
@@ -1030,13 +1078,22 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
 // double; FP32 / MIXED -> float.  bf16: BF16 trailing and column updates
 // (MIXED first pass); otherwise FP32 (or FP64) matrix-core updates.  hdesc:
 // host copy of desc (used for the flop counts of timed launches; nullable).
-void cholesky_factor(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, SysStatus* st, int n_sys, int Tmax,
-                     void* A, void* Wt, int level, bool bf16, const SysDesc* hdesc, void* pack) {
+//
+// zfwd (nullable): FP64 vectors (one T*NB block per system at v_off) holding
+// the right-hand sides b; with the BF16 packed path (bf16 and pack) they are
+// replaced by z = L^-1 b during the factorisation and the call returns true;
+// otherwise they are left untouched and the call returns false.
+bool cholesky_factor(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, SysStatus* st, int n_sys, int Tmax,
+                     void* A, void* Wt, int level, bool bf16, const SysDesc* hdesc, void* pack, double* zfwd) {
   const int Wp = ctx->panel_tiles;
-  if (prec == KRR_PREC_FP64)
-    factor_t<double>(ctx, s, desc, st, n_sys, Tmax, (double*)A, (double*)Wt, false, Wp, level, hdesc, nullptr);
-  else
-    factor_t<float>(ctx, s, desc, st, n_sys, Tmax, (float*)A, (float*)Wt, bf16, Wp, level, hdesc, (__bf16*)pack);
+  if (prec == KRR_PREC_FP64) {
+    factor_t<double>(ctx, s, desc, st, n_sys, Tmax, (double*)A, (double*)Wt, false, Wp, level, hdesc, nullptr, nullptr);
+    return false;
+  }
+  const bool packed = bf16 && pack != nullptr;
+  factor_t<float>(ctx, s, desc, st, n_sys, Tmax, (float*)A, (float*)Wt, bf16, Wp, level, hdesc, (__bf16*)pack,
+                  packed ? zfwd : nullptr);
+  return packed && zfwd != nullptr;
 }
 
 // BF16 elements of the panel pack slot of a system with T tile rows (the

@@ -10,8 +10,8 @@
 
 namespace krr {
 
-void cholesky_factor(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, SysStatus* st, int n_sys, int Tmax,
-                     void* A, void* Wt, int level, bool bf16, const SysDesc* hdesc, void* pack);
+bool cholesky_factor(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, SysStatus* st, int n_sys, int Tmax,
+                     void* A, void* Wt, int level, bool bf16, const SysDesc* hdesc, void* pack, double* zfwd);
 int64_t pack_slot_elems(int T, int Wp);
 void trsv_forward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, const SysStatus* st, int n_sys,
                   const void* A, const void* Wt, const double* b, double* z, int skip_converged);
@@ -440,8 +440,11 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
   };
   if (!ctx->serial_fit) {
     form(d_desc, p, n_groups, d_grp, d_grp + n_groups, Tmax);
-    cholesky_factor(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, 0, mixed, desc.data(), pack);
-    trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, rhs, zb, 0);
+    // mixed precision: the BF16 packed factorisation carries the forward solve along (zb = rhs on entry)
+    if (mixed) KRR_HIP(hipMemcpyAsync(zb, rhs, vb, hipMemcpyDeviceToDevice, s));
+    if (!cholesky_factor(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, 0, mixed, desc.data(), pack,
+                         mixed ? zb : nullptr))
+      trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, rhs, zb, 0);
     trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, zb, alpha, nullptr, 0);
   } else {
     // plain per-system sequence: every system formed, factored and solved
@@ -450,7 +453,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
       if (desc[sidx].T == 0) continue;
       form(d_desc + sidx, 1, 1, d_grp + n_groups + n_params, d_grp + n_groups + n_params + 1, desc[sidx].T);
       cholesky_factor(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, desc[sidx].T, A, Wt, 0, mixed,
-                      desc.data() + sidx, pack);
+                      desc.data() + sidx, pack, nullptr);
       trsv_forward(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, A, Wt, rhs, zb, 0);
       trsv_backward(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, A, Wt, zb, alpha, nullptr, 0);
     }
@@ -499,7 +502,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
       hipLaunchKernelGGL(k_restore_tiles, dim3((unsigned)tri(Tmax), (unsigned)n_sys), dim3(256), 0, s,
                          (const SysDesc*)d_desc, (const double*)K64, (float*)A, 1);
       check_launch(ctx, s, "restore_tiles");
-      cholesky_factor(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, 1, false, desc.data(), pack);
+      cholesky_factor(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, 1, false, desc.data(), pack, nullptr);
       trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, rhs, zb, 1);
       trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, zb, alpha, nullptr, 1);
       refine();
