@@ -695,6 +695,108 @@ __global__ __launch_bounds__(KB_MAXP) void k_kbal_event(const int32_t* __restric
   }
 }
 
+// The same event step for p <= 16 centres with the whole workgroup: thread
+// t = 16 j + q serves centre j and block slot q.  Blocks are taken 16 at a
+// time; a 16-lane scan of their counts finds, per centre, the block in which
+// it reaches its need (cap - cs[j]), and the first such block over the open
+// centres holds the event.  Inside it, per-centre ranks of the block's
+// choices (ballots per wave, wave totals in LDS) give the first point whose
+// choice reaches its centre's need.  Result identical to k_kbal_event.
+constexpr int KB_SMALLP = 16;
+__global__ __launch_bounds__(KB_BLOCK) void k_kbal_event16(const int32_t* __restrict__ MB,
+                                                           const int32_t* __restrict__ bc, int64_t nblk, int64_t n,
+                                                           int p, int64_t cap, int32_t* __restrict__ cs,
+                                                           int32_t* __restrict__ full, int64_t* __restrict__ st) {
+  if (st[1]) return;
+  __shared__ int64_t s_min[KB_BLOCK / 64];
+  __shared__ int64_t s_cum[KB_SMALLP];     // per centre: choices in [start, event block)
+  __shared__ int64_t s_need[KB_SMALLP];    // per centre: choices still needed to fill it (huge: closed)
+  __shared__ int32_t s_wc[KB_BLOCK / 64][KB_SMALLP];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int j = t >> 4, q = t & 15;
+  const int64_t start = st[0];
+  const bool open = j < p && !full[j];
+  const int64_t need = open ? cap - cs[j] : INT64_MAX / 2;
+  if (q == 0) s_need[j] = need;
+  // block-wide minimum of an int64 (every thread gets it)
+  auto wg_min = [&](int64_t v) {
+    for (int off = 32; off > 0; off >>= 1) v = min(v, (int64_t)__shfl_xor(v, off, 64));
+    __syncthreads();
+    if (lane == 0) s_min[wv] = v;
+    __syncthreads();
+    int64_t r = s_min[0];
+    for (int w = 1; w < KB_BLOCK / 64; ++w) r = min(r, s_min[w]);
+    return r;
+  };
+  // 1. the event block
+  int64_t cum = 0, B = INT64_MAX;
+  for (int64_t b = start / KB_BLOCK; b < nblk; b += 16) {
+    const int64_t bb = b + q;
+    const int64_t c = (j < p && bb < nblk) ? bc[bb * p + j] : 0;
+    int64_t x = c;   // inclusive scan over the 16 slots of centre j
+    for (int off = 1; off < 16; off <<= 1) {
+      const int64_t y = __shfl_up(x, off, 16);
+      if (q >= off) x += y;
+    }
+    const int64_t incl = cum + x, excl = incl - c;
+    const bool reached = open && bb < nblk && excl < need && incl >= need;
+    B = wg_min(reached ? bb : INT64_MAX);
+    if (B != INT64_MAX) {
+      if (bb == B && j < p) s_cum[j] = excl;   // the slot of block B: choices of j in [start, B)
+      break;
+    }
+    cum += __shfl(x, 15, 16);
+  }
+  if (B == INT64_MAX) {
+    // no centre fills: every remaining choice is final
+    if (q == 0 && j < p) cs[j] += (int32_t)cum;
+    if (t == 0) st[1] = 1;
+    return;
+  }
+  __syncthreads();
+  // 2. inside block B: point i = 256 B + t, its choice jt
+  const int64_t i = B * KB_BLOCK + t;
+  const int jt = (i >= start && i < n) ? MB[i] : -1;
+  for (int jj = 0; jj < p; ++jj) {
+    const uint64_t m = __ballot(jt == jj);
+    if (lane == 0) s_wc[wv][jj] = __popcll(m);
+  }
+  __syncthreads();
+  int64_t cand = INT64_MAX;
+  {
+    // rank of point i among the choices of its centre in [start, i]
+    int64_t rank = 0;
+    for (int jj = 0; jj < p; ++jj) {
+      const uint64_t m = __ballot(jt == jj);
+      if (jt == jj) {
+        rank = __popcll(m & ((2ull << lane) - 1));
+        for (int w = 0; w < wv; ++w) rank += s_wc[w][jj];
+      }
+    }
+    if (jt >= 0 && s_cum[jt] + rank == s_need[jt]) cand = i;
+  }
+  const int64_t istar = wg_min(cand);   // exists: some centre fills inside B
+  // 3. final choices in [start, istar]: the counts before B plus those in B up to istar
+  for (int jj = 0; jj < p; ++jj) {
+    const uint64_t m = __ballot(jt == jj && i <= istar);
+    if (lane == 0) s_wc[wv][jj] = __popcll(m);
+  }
+  __syncthreads();
+  if (t < p) {
+    int64_t c = s_cum[t];
+    for (int w = 0; w < KB_BLOCK / 64; ++w) c += s_wc[w][t];
+    cs[t] += (int32_t)c;
+  }
+  if (t == 0) {
+    if (istar + 1 >= n) {
+      st[1] = 1;
+    } else {
+      full[MB[istar]] = 1;
+      st[0] = istar + 1;
+    }
+  }
+}
+
 __global__ void k_kbal_init(int32_t* __restrict__ cs, int32_t* __restrict__ full, int p, int64_t* __restrict__ st) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < p) {
@@ -923,8 +1025,12 @@ static void partition_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int 
           hipLaunchKernelGGL(k_kbal_choose, dim3((unsigned)nblk), dim3(KB_BLOCK), (size_t)p * 4, s, (const double*)D,
                              n, p, (const int32_t*)full, (const int64_t*)kst, MB, bc);
           check_launch(ctx, s, "kbal_choose");
-          hipLaunchKernelGGL(k_kbal_event, dim3(1), dim3(KB_MAXP), 0, s, (const int32_t*)MB, (const int32_t*)bc, nblk,
-                             n, p, cap, cs, full, kst);
+          if (p <= KB_SMALLP)
+            hipLaunchKernelGGL(k_kbal_event16, dim3(1), dim3(KB_BLOCK), 0, s, (const int32_t*)MB, (const int32_t*)bc,
+                               nblk, n, p, cap, cs, full, kst);
+          else
+            hipLaunchKernelGGL(k_kbal_event, dim3(1), dim3(KB_MAXP), 0, s, (const int32_t*)MB, (const int32_t*)bc,
+                               nblk, n, p, cap, cs, full, kst);
           check_launch(ctx, s, "kbal_event");
         }
       } else {

@@ -64,6 +64,24 @@ def test_kbalance_ragged_capacity(ctx, dev):
     assert sz.cpu().numpy().max() <= 144
 
 
+@pytest.mark.parametrize("p", [1, 2, 13, 16, 17])
+def test_kbalance_many_blocks_with_ties(ctx, dev, p):
+    """K-balance (Algorithm 4) over ~80 blocks of 256 points, several centres
+    filling inside one group of 16 blocks, on integer-grid points where equal
+    distances are common (the lowest centre index wins); p <= 16 and p > 16
+    take different event kernels."""
+    g = np.random.default_rng(40 + p)
+    n = 20011
+    X = g.integers(0, 4, size=(n, 3)).astype(np.float64)
+    X[: n // 3] += 10.0 * g.integers(0, 3, size=(n // 3, 1))   # uneven clusters: centres fill at different times
+    print(f"kbalance n={n} p={p} (ties)", flush=True)
+    C, a, sz = ctx.partition(_t(X, dev), p, "kbalance", lloyd_iters=3, seed=5)
+    Co, ao = O.kbalance(X, p, 3, 5)
+    np.testing.assert_array_equal(a.cpu().numpy(), ao)
+    np.testing.assert_array_equal(C.cpu().numpy(), Co)
+    assert sz.cpu().numpy().max() <= -(-n // p)
+
+
 def test_kmeans_converges_early(ctx, dev):
     # well separated clusters: Lloyd reaches a fixed point before the cap
     w = datagen.small(34, 2000, 4, comps=4, spread=50.0)
