@@ -23,7 +23,8 @@ namespace krr {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
-constexpr int KC = 32;
+constexpr int KCR = 32;          // features per staged block; a wave keeps its test operands of a block in registers
+constexpr int KSR = KCR / 4;     // 4-deep MFMA steps per block
 constexpr int LDX = NB + 1;
 constexpr int MAXM = 8;
 
@@ -32,12 +33,13 @@ struct PredModels {
   const int64_t* voff[MAXM];
   double neg_inv_2s2[MAXM];
   double* out[MAXM];
+  int uq[MAXM];   // first model with the same -1/(2 sigma^2): the kernel values are shared
   int nm;
   int kernel;
 };
 
 template <typename TX>
-__global__ __launch_bounds__(256) void k_predict(const TX* __restrict__ Xt, int d, int64_t k,
+__global__ __launch_bounds__(256, 2) void k_predict(const TX* __restrict__ Xt, int d, int64_t k,
                                                  const int32_t* __restrict__ tperm,
                                                  const int64_t* __restrict__ toff,
                                                  const int32_t* __restrict__ tile_start, int route,
@@ -68,9 +70,9 @@ __global__ __launch_bounds__(256) void k_predict(const TX* __restrict__ Xt, int 
   const int64_t m = xoff[j + 1] - x0;
   const int64_t xbeg = (int64_t)split * cps * NB;
   const int64_t xend = min(m, xbeg + (int64_t)cps * NB);
-  __shared__ double sT[KC * LDX + 1];   // + a spare slot for staged values past d
-  __shared__ double sX[KC * LDX + 1];
-  __shared__ double sNt[NB], sNx[NB];
+  __shared__ double sX[KCR * LDX];   // training block: sX[kk * LDX + row], zero past the features
+  __shared__ double sNp[4][NB];      // training-row norms, four feature quarters
+  __shared__ double sA[MAXM][NB];    // alpha of the chunk, zero past its rows
   __shared__ int64_t srow[NB];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int il = lane & 15, kl = lane >> 4;
@@ -79,20 +81,28 @@ __global__ __launch_bounds__(256) void k_predict(const TX* __restrict__ Xt, int 
     if (t < tcnt) src = (route == KRR_ROUTE_NEAREST) ? (int64_t)tperm[t0 + t] : t0 + t;
     srow[t] = src;
   }
-  // test-point norms
-  if (t < NB) {
-    double nrm = 0.0;
-    const int64_t sr = (t < tcnt) ? ((route == KRR_ROUTE_NEAREST) ? (int64_t)tperm[t0 + t] : t0 + t) : -1;
-    if (sr >= 0)
-      for (int kk = 0; kk < d; ++kk) {
-        const double v = (double)Xt[sr * d + kk];
-        nrm = fma(v, v, nrm);
-      }
-    sNt[t] = nrm;
-  }
   __syncthreads();
+  // this lane's test point (the B operand column) and its features 4 s + kl of a block
   const int tl = 16 * w + il;
-  const double nt = sNt[tl];
+  const int64_t trow = max(srow[tl], (int64_t)0);
+  double bt[KSR];
+  auto load_test = [&](int k0, int kc) {
+#pragma unroll
+    for (int s = 0; s < KSR; ++s) {
+      const int kk = 4 * s + kl;
+      const double v = (double)Xt[trow * d + k0 + min(kk, kc - 1)];   // unconditional, clamped
+      bt[s] = kk < kc ? v : 0.0;
+    }
+  };
+  double nt = 0.0;
+  for (int k0 = 0; k0 < d; k0 += KCR) {
+    load_test(k0, min(KCR, d - k0));
+#pragma unroll
+    for (int s = 0; s < KSR; ++s) nt = fma(bt[s], bt[s], nt);
+  }
+  nt += __shfl_xor(nt, 16, 64);
+  nt += __shfl_xor(nt, 32, 64);
+  const bool one_block = d <= KCR;   // the test operands stay loaded across the chunks
   double part[MAXM];
 #pragma unroll
   for (int q = 0; q < MAXM; ++q) part[q] = 0.0;
@@ -101,64 +111,72 @@ __global__ __launch_bounds__(256) void k_predict(const TX* __restrict__ Xt, int 
     d4 acc[4];
 #pragma unroll
     for (int xb = 0; xb < 4; ++xb) acc[xb] = d4{0.0, 0.0, 0.0, 0.0};
-    double nrm = 0.0;
-    for (int k0 = 0; k0 < d; k0 += KC) {
-      const int kc = min(KC, d - k0);
-      __syncthreads();
-      // unconditional loads from clamped addresses, then select and store
-      TX lt[NB * KC / 256], lx[NB * KC / 256];
+    double nxp = 0.0;   // norm of training row (t & 63) over feature quarter (t >> 6) of the blocks
+    for (int k0 = 0; k0 < d; k0 += KCR) {
+      const int kc = min(KCR, d - k0);
+      if (!one_block) load_test(k0, kc);
+      TX lx[NB * KCR / 256];
 #pragma unroll
-      for (int u = 0; u < NB * KC / 256; ++u) {
-        const int e = t + u * 256;
-        const int row = e / KC, kk = min(e - row * KC, kc - 1);
-        const int64_t sr = srow[row];
-        lt[u] = Xt[max(sr, (int64_t)0) * d + k0 + kk];
-        lx[u] = Xg[(x0 + xc + min((int64_t)row, xcnt - 1)) * d + k0 + kk];
+      for (int u = 0; u < NB * KCR / 256; ++u) {
+        const int e = t + u * 256, row = e / KCR, kk = e - row * KCR;
+        lx[u] = Xg[(x0 + xc + min((int64_t)row, xcnt - 1)) * d + k0 + min(kk, kc - 1)];
       }
-      // stored unconditionally: test slots without a point and training rows
-      // past the chunk are never used; the k slots past d read by the last
-      // 4-wide MFMA step are zeroed below
+      __syncthreads();   // the previous block's readers are done
 #pragma unroll
-      for (int u = 0; u < NB * KC / 256; ++u) {
-        const int e = t + u * 256;
-        const int row = e / KC, kk = e - row * KC;
-        const int slot = (kk < kc) ? kk * LDX + row : KC * LDX;   // past d: the spare slot
-        sT[slot] = (double)lt[u];
-        sX[slot] = (double)lx[u];
-      }
-      const int kc4 = (kc + 3) & ~3;
-      for (int e = t; e < (kc4 - kc) * NB; e += 256) {
-        const int kk = kc + e / NB, row = e % NB;
-        sT[kk * LDX + row] = 0.0;
-        sX[kk * LDX + row] = 0.0;
+      for (int u = 0; u < NB * KCR / 256; ++u) {
+        const int e = t + u * 256, row = e / KCR, kk = e - row * KCR;
+        sX[kk * LDX + row] = kk < kc ? (double)lx[u] : 0.0;
       }
       __syncthreads();
-      if (t < NB)
-        for (int kk = 0; kk < kc; ++kk) nrm = fma(sX[kk * LDX + t], sX[kk * LDX + t], nrm);
-      for (int kb = 0; kb < kc; kb += 4) {
-        const int ko = (kb + kl) * LDX;
-        const double bt = sT[ko + 16 * w + il];
 #pragma unroll
-        for (int xb = 0; xb < 4; ++xb)
-          acc[xb] = __builtin_amdgcn_mfma_f64_16x16x4f64(sX[ko + 16 * xb + il], bt, acc[xb], 0, 0, 0);
+      for (int u = 0; u < KCR / 4; ++u) {
+        const double v = sX[((t >> 6) * (KCR / 4) + u) * LDX + (t & 63)];
+        nxp = fma(v, v, nxp);
+      }
+#pragma unroll
+      for (int s = 0; s < KSR; ++s) {
+        if (4 * s < kc) {
+          const int ko = (4 * s + kl) * LDX;
+#pragma unroll
+          for (int xb = 0; xb < 4; ++xb)
+            acc[xb] = __builtin_amdgcn_mfma_f64_16x16x4f64(sX[ko + 16 * xb + il], bt[s], acc[xb], 0, 0, 0);
+        }
+        if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);   // bounds the operand loads in flight
       }
     }
-    if (t < NB) sNx[t] = nrm;
+    sNp[t >> 6][t & 63] = nxp;
+#pragma unroll
+    for (int q = 0; q < MAXM; ++q)
+      if (q < M.nm && t < NB) {
+        const double av = M.alpha[q][M.voff[q][j] + xc + min((int64_t)t, xcnt - 1)];
+        sA[q][t] = t < xcnt ? av : 0.0;
+      }
     __syncthreads();
+    // rows past the chunk carry alpha = 0 (their kernel values are finite)
 #pragma unroll
     for (int xb = 0; xb < 4; ++xb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int xl = 16 * xb + kl + 4 * v;   // FP64 MFMA result row of register v
-        if (xl < xcnt) {
-          const double G = acc[xb][v];
-          const double d2 = fmax(0.0, (nt + sNx[xl]) - 2.0 * G);
+        const double G = acc[xb][v];
+        const double nx = (sNp[0][xl] + sNp[1][xl]) + (sNp[2][xl] + sNp[3][xl]);
+        const double d2 = fmax(0.0, (nt + nx) - 2.0 * G);
+        double kv[MAXM];
 #pragma unroll
-          for (int q = 0; q < MAXM; ++q) {
-            if (q < M.nm) {
-              const double kv = (M.kernel == KRR_KERNEL_GAUSSIAN) ? exp(d2 * M.neg_inv_2s2[q]) : G;
-              part[q] = fma(M.alpha[q][M.voff[q][j] + xc + xl], kv, part[q]);
+        for (int q = 0; q < MAXM; ++q) {
+          if (q < M.nm) {
+            if (M.kernel != KRR_KERNEL_GAUSSIAN) {
+              kv[q] = G;
+            } else if (M.uq[q] == q) {
+              kv[q] = exp(d2 * M.neg_inv_2s2[q]);
+            } else {
+              double s0 = 0.0;
+#pragma unroll
+              for (int q2 = 0; q2 < q; ++q2)
+                if (M.uq[q] == q2) s0 = kv[q2];
+              kv[q] = s0;
             }
+            part[q] = fma(sA[q][xl], kv[q], part[q]);
           }
         }
       }
@@ -289,6 +307,9 @@ void predict_group(krr_ctx ctx, hipStream_t s, const krr_model* models, int nm, 
     M.alpha[q] = models[q]->alpha;
     M.voff[q] = models[q]->d_voff;
     M.neg_inv_2s2[q] = -1.0 / (2.0 * models[q]->params.sigma * models[q]->params.sigma);
+    M.uq[q] = q;
+    for (int q2 = q - 1; q2 >= 0; --q2)
+      if (M.neg_inv_2s2[q2] == M.neg_inv_2s2[q]) M.uq[q] = q2;
     M.out[q] = dst[q];
     KRR_REQUIRE(models[q]->params.kernel == M.kernel, "models of one call must share the kernel");
   }
