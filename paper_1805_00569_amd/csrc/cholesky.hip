@@ -725,6 +725,13 @@ __global__ __launch_bounds__(256) void k_tile_gemm_bf16(const SysDesc* __restric
 //   L(i,k)  = C(i,k) Winv(k)^T                    FP32 matrix cores, C through the wave's LDS
 //   L(i,k) -> the FP32 tile, and (do_pack) BF16 fragments of the pack
 constexpr int PC_LD = NB + 1;
+// Workgroups go to the chip's 8 XCDs in turn (workgroup b to XCD b % 8), and
+// each XCD has its own L2.  The update kernels place all workgroups of
+// system s on XCD s % 8 (slot b / 8 of that XCD), so that the operands a
+// system's workgroups share are fetched into one L2.  Grids hold
+// 8 * ceil(n_sys / 8) * (workgroups per system); the padding exits at once.
+constexpr int NXCD = 8;
+
 __device__ __forceinline__ void panel_col_tile(const SysDesc& D, int s, int i, int lane, float* __restrict__ A,
                                                const __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk, int K0, int k,
                                                int Wp, int do_pack, double* __restrict__ zf, float* __restrict__ sc) {
@@ -851,23 +858,25 @@ __device__ __forceinline__ void panel_col_tile(const SysDesc& D, int s, int i, i
 // dispatched before the other workgroups) then factors diagonal block k + 1
 // with its column update over the panel columns [K0, k] (diag_block), which
 // needs only tile row k + 1 of this column; its latency hides behind the
-// other workgroups' tiles.  Grid: n_sys * ng workgroups, ng = tile groups of
-// four rows; workgroup b < n_sys is group 0 of system b, the others follow
-// system by system.
+// other workgroups' tiles.  ng = tile groups of four rows per system; on
+// each XCD the slots hold first group 0 of its U = ceil(n_sys / 8) systems,
+// then the other groups system by system.
 __global__ __launch_bounds__(256) void k_panel_col(const SysDesc* __restrict__ desc, SysStatus* __restrict__ st,
                                                    float* __restrict__ A, float* __restrict__ Wt,
                                                    __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk, int K0, int k,
                                                    int Wp, int level, int do_pack, int diag_next, int n_sys, int ng,
                                                    double* __restrict__ zf) {
-  const int b = blockIdx.x;
-  int s, g;
-  if (b < n_sys) {
-    s = b;
+  const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD, U = (n_sys + NXCD - 1) / NXCD;
+  int u, g;
+  if (slot < U) {
+    u = slot;
     g = 0;
   } else {
-    s = (b - n_sys) / (ng - 1);
-    g = 1 + (b - n_sys) % (ng - 1);
+    u = (slot - U) / (ng - 1);
+    g = 1 + (slot - U) % (ng - 1);
   }
+  const int s = xcd + NXCD * u;
+  if (s >= n_sys) return;
   const SysDesc D = desc[s];
   if (st[s].status != 0 || D.level != level) return;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -886,19 +895,22 @@ __global__ __launch_bounds__(256) void k_panel_col(const SysDesc* __restrict__ d
 // Trailing update A(i,j) -= sum_{q in panel} L(i,q) L(j,q)^T for the lower
 // triangle i >= j >= i0, from the packed fragment columns [ks0, ks1): 128 x 128
 // super-tiles (blockIdx.x = triangle index), one 64 x 64 tile per wavefront,
-// accumulators starting from the C tile; systems along blockIdx.z.
+// accumulators starting from the C tile; workgroups placed by system on the XCDs (NXCD).
 __global__ __launch_bounds__(256) void k_packed_trailing(const SysDesc* __restrict__ desc,
                                                          const SysStatus* __restrict__ st, float* __restrict__ A,
                                                          const __bf16* __restrict__ Pk, int K0, int ks0, int ks1,
-                                                         int i0, int Wp, int level) {
-  const int s = blockIdx.z;
+                                                         int i0, int Wp, int level, int n_sys, int ntri) {
+  // XCD placement (see NXCD): slot = system-major (system, super-tile)
+  const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
+  const int s = xcd + NXCD * (slot / ntri);
+  if (s >= n_sys) return;
   const SysDesc D = desc[s];
   if (st[s].status != 0 || D.level != level) return;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int R = D.T - i0;
   if (R <= 0) return;
   const int NS = (R + 1) / 2;
-  const int bx = blockIdx.x;
+  const int bx = slot % ntri;
   int I = (int)((sqrt(8.0 * (double)bx + 1.0) - 1.0) * 0.5);
   while (I * (I + 1) / 2 > bx) --I;
   while ((I + 1) * (I + 2) / 2 <= bx) ++I;
@@ -1022,7 +1034,8 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
           }));
           const int do_pack = (k + 1 < K1 || K1 < Tmax) ? 1 : 0;
           const int ng = ceil_div(Tmax - k - 1, 4);
-          hipLaunchKernelGGL(k_panel_col, dim3((unsigned)(ng * n_sys)), dim3(256), 0, s, desc, st, (float*)A,
+          hipLaunchKernelGGL(k_panel_col, dim3((unsigned)(NXCD * ceil_div(n_sys, NXCD) * ng)), dim3(256), 0, s, desc,
+                             st, (float*)A,
                              (float*)Wt, Wpk, (__bf16*)Pk, K0, k, Wp, level, do_pack, nd ? 1 : 0, n_sys, ng, zf);
           check_launch(ctx, s, "panel_col");
         }
@@ -1039,9 +1052,10 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
           return n > 0 ? n * (n + 1.0) * sizeof(float) : 0.0;
         }));
         const int64_t NS = (R + 1) / 2;
-        hipLaunchKernelGGL(k_packed_trailing, dim3((unsigned)(NS * (NS + 1) / 2), 1, (unsigned)n_sys), dim3(256), 0,
-                           s, desc, (const SysStatus*)st, (float*)A, (const __bf16*)Pk, K0, 0, 2 * (K1 - K0), K1, Wp,
-                           level);
+        const int ntri = (int)(NS * (NS + 1) / 2);
+        hipLaunchKernelGGL(k_packed_trailing, dim3((unsigned)(NXCD * ceil_div(n_sys, NXCD) * ntri)), dim3(256), 0, s,
+                           desc, (const SysStatus*)st, (float*)A, (const __bf16*)Pk, K0, 0, 2 * (K1 - K0), K1, Wp,
+                           level, n_sys, ntri);
         check_launch(ctx, s, "packed_trailing");
       }
     }
