@@ -207,29 +207,47 @@ __global__ void k_transpose(const double* __restrict__ C, int p, int d, double* 
 // Stable grouping of n keys in [0, p): perm lists the indices of key 0 in
 // increasing order, then key 1, ...; offsets[j] is where key j starts.
 // ---------------------------------------------------------------------------
+// Rank of each key among the earlier keys of its block that are equal, and
+// the block's count per key: inside a wave one ballot per distinct key, then
+// the counts of the earlier waves (LDS, [wave][key]).
 __global__ __launch_bounds__(GROUP_BLOCK) void k_group_local(const int32_t* __restrict__ key, int64_t n,
                                                              int p, int32_t* __restrict__ local_rank,
                                                              int32_t* __restrict__ blockcounts,
                                                              const int32_t* __restrict__ skip) {
   if (skip != nullptr && *skip) return;
-  __shared__ int32_t sk[GROUP_BLOCK];
-  extern __shared__ int32_t cnt[];
-  for (int j = threadIdx.x; j < p; j += GROUP_BLOCK) cnt[j] = 0;
+  constexpr int NWV = GROUP_BLOCK / 64;
+  extern __shared__ int32_t wc[];   // [NWV][p]
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int e = threadIdx.x; e < NWV * p; e += GROUP_BLOCK) wc[e] = 0;
+  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * GROUP_BLOCK + threadIdx.x;
   const int kv = (i < n) ? key[i] : -1;
-  sk[threadIdx.x] = kv;
-  __syncthreads();
-  if (i < n) {
-    int rank = 0;
-    for (int l = 0; l < (int)threadIdx.x; ++l) rank += (sk[l] == kv);
-    local_rank[i] = rank;
-    atomicAdd(&cnt[kv], 1);
+  int rw = 0;
+  unsigned long long todo = __ballot(kv >= 0);
+  while (todo != 0ull) {
+    const int leader = __ffsll(todo) - 1;
+    const int kk = __shfl(kv, leader, 64);
+    const unsigned long long m = __ballot(kv == kk);
+    if (kv == kk) rw = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == leader) wc[w * p + kk] = __popcll(m);
+    todo &= ~m;
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < p; j += GROUP_BLOCK)
-    blockcounts[(int64_t)blockIdx.x * p + j] = cnt[j];
+  if (kv >= 0) {
+    int r = rw;
+    for (int u = 0; u < w; ++u) r += wc[u * p + kv];
+    local_rank[i] = r;
+  }
+  for (int j = threadIdx.x; j < p; j += GROUP_BLOCK) {
+    int c = 0;
+    for (int u = 0; u < NWV; ++u) c += wc[u * p + j];
+    blockcounts[(int64_t)blockIdx.x * p + j] = c;
+  }
 }
 
+// Per key j: exclusive prefix of the per-block counts (block offsets) and the
+// total; one wave per key (lane l takes a contiguous run of blocks, then a
+// 64-lane scan of the run sums).  Then the key offsets in key order.
 __global__ __launch_bounds__(1024) void k_group_scan(const int32_t* __restrict__ blockcounts, int64_t nblocks,
                                                      int p, int32_t* __restrict__ blockoffs,
                                                      int64_t* __restrict__ offsets,
@@ -237,26 +255,27 @@ __global__ __launch_bounds__(1024) void k_group_scan(const int32_t* __restrict__
                                                      const int32_t* __restrict__ skip) {
   if (skip != nullptr && *skip) return;
   extern __shared__ int64_t tot[];
-  for (int j = threadIdx.x; j < p; j += blockDim.x) {
-    int64_t run = 0;
-    int64_t b = 0;
-    for (; b + 8 <= nblocks; b += 8) {
-      int32_t c[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) c[q] = blockcounts[(b + q) * p + j];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        blockoffs[(b + q) * p + j] = (int32_t)run;
-        run += c[q];
-      }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int64_t per = (nblocks + 63) / 64;
+  const int64_t b0 = min(nblocks, lane * per), b1 = min(nblocks, b0 + per);
+  for (int j = w; j < p; j += nw) {
+    int64_t sum = 0;
+    for (int64_t b = b0; b < b1; ++b) sum += blockcounts[b * p + j];
+    int64_t x = sum;   // inclusive scan over the lanes
+    for (int off = 1; off < 64; off <<= 1) {
+      const int64_t y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
     }
-    for (; b < nblocks; ++b) {
+    int64_t run = x - sum;
+    for (int64_t b = b0; b < b1; ++b) {
       const int32_t c = blockcounts[b * p + j];
       blockoffs[b * p + j] = (int32_t)run;
       run += c;
     }
-    tot[j] = run;
-    if (sizes64 != nullptr) sizes64[j] = run;
+    if (lane == 63) {
+      tot[j] = x;
+      if (sizes64 != nullptr) sizes64[j] = x;
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -406,11 +425,21 @@ __global__ __launch_bounds__(KPP_BLOCK) void k_kpp_update(const TX* __restrict__
   sd[threadIdx.x] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int cnt = (int)min((int64_t)KPP_BLOCK, n - (int64_t)blockIdx.x * KPP_BLOCK);
+    // sequential prefix in point order, 16 loads at a time; past the block's
+    // points the weights are 0 and leave the sum unchanged
     double acc = sd[0];
-    for (int q = 1; q < cnt; ++q) {
-      acc = add_sep(acc, sd[q]);
-      sd[q] = acc;
+#pragma unroll 1
+    for (int q0 = 0; q0 < KPP_BLOCK; q0 += 16) {
+      double x[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) x[u] = sd[q0 + u];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        if (q0 + u > 0) acc = add_sep(acc, x[u]);
+        x[u] = acc;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) sd[q0 + u] = x[u];
     }
     Tb[blockIdx.x] = acc;
   }
@@ -949,10 +978,11 @@ void group_by_key(krr_ctx ctx, hipStream_t s, const int32_t* key, int64_t n, int
   int32_t* rank = (int32_t*)w;
   int32_t* bc = rank + n;
   int32_t* bo = bc + nblk * p;
-  hipLaunchKernelGGL(k_group_local, dim3(nblk), dim3(GROUP_BLOCK), (size_t)p * 4, s, key, n, p, rank, bc,
+  hipLaunchKernelGGL(k_group_local, dim3(nblk), dim3(GROUP_BLOCK), (size_t)(GROUP_BLOCK / 64) * p * 4, s, key, n, p,
+                     rank, bc,
                      skip);
   check_launch(ctx, s, "group_local");
-  hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(std::min(1024, ((p + 63) / 64) * 64)), (size_t)p * 8, s,
+  hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(std::min(1024, 64 * p)), (size_t)p * 8, s,
                      (const int32_t*)bc, nblk, p, bo, offsets, sizes64, skip);
   check_launch(ctx, s, "group_scan");
   hipLaunchKernelGGL(k_group_scatter, dim3(nblk), dim3(GROUP_BLOCK), 0, s, key, n, p, (const int32_t*)rank,
