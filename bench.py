@@ -42,14 +42,16 @@ HBM_PEAK = 8000.0  # GB/s
 # reads for a plain 1 GiB device copy (FETCH_SIZE reads 512 MiB: x2.0;
 # WRITE_SIZE reads 1 GiB: x1.0).  Valid only while the kernel's source is the
 # one measured (sha256 over the listed source regions); otherwise null.
+# HBM bytes per launch of a kernel class from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# runs (KiB per dispatch, scaled by the same counters on a plain device copy).
+# Valid only for the source they were taken on: the sha256 of the kernel's
+# whole source file must match, else the figure is reported as null.
 TRAFFIC = {
     "chol_column_bf16": {
         "kernel": "k_panel_col",
         "source": "paper_1805_00569_amd/csrc/cholesky.hip",
-        "regions": ["template <int NCB, int PK_DEPTH>\n__device__ __forceinline__ void packed_sub(",
-                    "__global__ __launch_bounds__(256) void k_panel_col("],
-        "sha256": "1b4058398b23271d231b57613a5790b322e4cae0b91530e8eeb9c67f40c18244",
-        "fetch_kib": 129462.2, "write_kib": 73728.8, "fetch_scale": 2.0, "write_scale": 1.0,
+        "sha256": "ec0063506f97200d89cae4c2e3ccfa464607bceb9d8cbfc201448e243b2fbd51",
+        "fetch_kib": 118758.8, "write_kib": 79691.9, "fetch_scale": 2.0, "write_scale": 1.0,
     },
 }
 
@@ -60,14 +62,11 @@ def _traffic_bytes(cls):
     if t is None:
         return None
     try:
-        src = open(os.path.join(ROOT, t["source"])).read()
-        text = ""
-        for sig in t["regions"]:
-            a = src.index(sig)
-            text += src[a:src.index("\n}\n", a) + 3]
-    except (OSError, ValueError):
+        with open(os.path.join(ROOT, t["source"]), "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
         return None
-    if hashlib.sha256(text.encode()).hexdigest() != t["sha256"]:
+    if digest != t["sha256"]:
         return None
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
 
