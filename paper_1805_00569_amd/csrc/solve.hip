@@ -152,22 +152,47 @@ __global__ __launch_bounds__(TRSV_THREADS) void k_trsv_fwd(const SysDesc* __rest
 
 // x = L^-T z (and alpha += x when `alpha_acc` is given), tile row i from the
 // last: u = z_i - sum_{j>i} L(j,i)^T x_j, then x_i = Winv(i)^T u.
-template <typename TS>
+// Largest T whose solution vector the backward solve keeps in LDS.
+constexpr int TRSV_XL_MAXT = 128;
+
+// x = L^-T z, tile row by tile row from the last: u = z_i - sum_{j>i} L(j,i)^T x_j,
+// then x_i = Winv(i)^T u.  Winv(i) comes from LDS: groups 1..3 load the next
+// step's block into the other half of a double buffer while group 0 forms
+// x_i.  XL: x stays in LDS (T <= TRSV_XL_MAXT) and is written out at the end;
+// otherwise it is read back from global memory.  alpha_acc (nullable):
+// x is also added to it.
+template <typename TS, bool XL>
 __global__ __launch_bounds__(TRSV_THREADS) void k_trsv_bwd(const SysDesc* __restrict__ desc,
                                                            const SysStatus* __restrict__ st,
                                                            const TS* __restrict__ A, const TS* __restrict__ Wt,
                                                            const double* __restrict__ z, double* __restrict__ x,
                                                            double* __restrict__ alpha_acc, int skip_converged) {
-  constexpr int TRSV_JB = TrsvJB<TS>::value - (sizeof(TS) == 4 ? 1 : 0);   // the x blocks are FP64
+  // tiles in flight per group: the FP64 x blocks take registers unless they come from LDS
+  constexpr int TRSV_JB = TrsvJB<TS>::value - (sizeof(TS) == 4 && !XL ? 1 : 0);
   const int s = blockIdx.x;
   const SysDesc D = desc[s];
   if (skip_system(st[s], skip_converged)) return;
   __shared__ double sp[TRSV_G][NB];
   __shared__ double su[NB];
+  extern __shared__ double dyn[];
+  TS* sW = reinterpret_cast<TS*>(dyn);             // [2][TILE]
+  double* sx = dyn + (2 * TILE * sizeof(TS)) / 8;   // XL: [T * NB]
   const int t = threadIdx.x, grp = t >> 8, rq = t & 15, cg = (t >> 4) & 15;
   const TS* Ab = A + D.a_off;
   const double* zz = z + D.v_off;
   double* xx = x + D.v_off;
+  const double* xs = XL ? sx : xx;
+  // Winv of the last tile row into buffer (T - 1) & 1
+  if (D.T > 0) {
+    const TS* W = Wt + D.w_off + (int64_t)(D.T - 1) * TILE;
+    for (int e = 4 * t; e < TILE; e += 4 * TRSV_THREADS) {
+      TS v[4];
+      load4(W + e, v);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sW[((D.T - 1) & 1) * TILE + e + k] = v[k];
+    }
+  }
+  __syncthreads();
   for (int i = D.T - 1; i >= 0; --i) {
     double part[4] = {0.0, 0.0, 0.0, 0.0};
     int j = i + 1 + grp;
@@ -179,7 +204,8 @@ __global__ __launch_bounds__(TRSV_THREADS) void k_trsv_bwd(const SysDesc* __rest
         const TS* L = Ab + tile_index(j + TRSV_G * u, i) * TILE;   // (L^T)(i,j) = L(j,i)^T
 #pragma unroll
         for (int q = 0; q < 4; ++q) load4(L + (cg + 16 * q) * NB + 4 * rq, lv[u][q]);
-        load4(xx + (j + TRSV_G * u) * NB + 4 * rq, xv[u]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) xv[u][k] = xs[(j + TRSV_G * u) * NB + 4 * rq + k];
       }
 #pragma unroll
       for (int u = 0; u < TRSV_JB; ++u)
@@ -191,7 +217,8 @@ __global__ __launch_bounds__(TRSV_THREADS) void k_trsv_bwd(const SysDesc* __rest
     for (; j < D.T; j += TRSV_G) {
       const TS* L = Ab + tile_index(j, i) * TILE;
       double xv[4];
-      load4(xx + j * NB + 4 * rq, xv);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) xv[k] = xs[j * NB + 4 * rq + k];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         TS lv[4];
@@ -215,26 +242,44 @@ __global__ __launch_bounds__(TRSV_THREADS) void k_trsv_bwd(const SysDesc* __rest
     __syncthreads();
     if (grp == 0) {
       // x_i[c] = sum_r W(r, c) u[r], W(r, c) at c * NB + r
-      const TS* W = Wt + D.w_off + (int64_t)i * TILE;
+      const TS* W = sW + (i & 1) * TILE;
       double ur[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) ur[k] = su[4 * rq + k];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int c = cg + 16 * q;
-        TS wv[4];
-        load4(W + c * NB + 4 * rq, wv);
         double p = 0.0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) p = fma((double)wv[k], ur[k], p);
+        for (int k = 0; k < 4; ++k) p = fma((double)W[c * NB + 4 * rq + k], ur[k], p);
         const double v = quad16_sum(p);
         if (rq == 0) {
-          xx[i * NB + c] = v;
-          if (alpha_acc != nullptr) alpha_acc[D.v_off + i * NB + c] += v;
+          if (XL) {
+            sx[i * NB + c] = v;
+          } else {
+            xx[i * NB + c] = v;
+            if (alpha_acc != nullptr) alpha_acc[D.v_off + i * NB + c] += v;
+          }
         }
+      }
+    } else if (i > 0) {
+      // the next step's Winv into the other buffer
+      const TS* W = Wt + D.w_off + (int64_t)(i - 1) * TILE;
+      for (int e = 4 * (t - 256); e < TILE; e += 4 * (TRSV_THREADS - 256)) {
+        TS v[4];
+        load4(W + e, v);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sW[((i - 1) & 1) * TILE + e + k] = v[k];
       }
     }
     __syncthreads();
+  }
+  if (XL) {
+    for (int e = t; e < D.T * NB; e += TRSV_THREADS) {
+      const double v = sx[e];
+      xx[e] = v;
+      if (alpha_acc != nullptr) alpha_acc[D.v_off + e] += v;
+    }
   }
 }
 
@@ -399,14 +444,27 @@ void trsv_forward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, con
 }
 
 void trsv_backward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, const SysStatus* st, int n_sys,
-                   const void* A, const void* Wt, const double* z, double* x, double* alpha_acc, int skip_converged) {
+                   int Tmax, const void* A, const void* Wt, const double* z, double* x, double* alpha_acc,
+                   int skip_converged) {
   KernelTimer kt(ctx, s, "trsv_backward", 0.0, 0);
-  if (prec == KRR_PREC_FP64)
-    hipLaunchKernelGGL((k_trsv_bwd<double>), dim3(n_sys), dim3(TRSV_THREADS), 0, s, desc, st, (const double*)A,
-                       (const double*)Wt, z, x, alpha_acc, skip_converged);
-  else
-    hipLaunchKernelGGL((k_trsv_bwd<float>), dim3(n_sys), dim3(TRSV_THREADS), 0, s, desc, st, (const float*)A,
-                       (const float*)Wt, z, x, alpha_acc, skip_converged);
+  const bool xl = Tmax <= TRSV_XL_MAXT;
+  const size_t ts = prec == KRR_PREC_FP64 ? sizeof(double) : sizeof(float);
+  const size_t lds = 2 * TILE * ts + (xl ? (size_t)std::max(Tmax, 1) * NB * sizeof(double) : 0);
+  if (prec == KRR_PREC_FP64) {
+    if (xl)
+      hipLaunchKernelGGL((k_trsv_bwd<double, true>), dim3(n_sys), dim3(TRSV_THREADS), lds, s, desc, st,
+                         (const double*)A, (const double*)Wt, z, x, alpha_acc, skip_converged);
+    else
+      hipLaunchKernelGGL((k_trsv_bwd<double, false>), dim3(n_sys), dim3(TRSV_THREADS), lds, s, desc, st,
+                         (const double*)A, (const double*)Wt, z, x, alpha_acc, skip_converged);
+  } else {
+    if (xl)
+      hipLaunchKernelGGL((k_trsv_bwd<float, true>), dim3(n_sys), dim3(TRSV_THREADS), lds, s, desc, st,
+                         (const float*)A, (const float*)Wt, z, x, alpha_acc, skip_converged);
+    else
+      hipLaunchKernelGGL((k_trsv_bwd<float, false>), dim3(n_sys), dim3(TRSV_THREADS), lds, s, desc, st,
+                         (const float*)A, (const float*)Wt, z, x, alpha_acc, skip_converged);
+  }
   check_launch(ctx, s, "trsv_bwd");
 }
 
