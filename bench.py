@@ -23,6 +23,12 @@ import os
 import sys
 import time
 
+# The serving leg runs four worker streams beside the main one; with HIP's
+# default of four hardware queues per process they share queues and a
+# predict launch can wait behind a whole fit kernel.  Eight queues give every
+# stream its own (set before the HIP runtime starts; a caller's value wins).
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))

@@ -233,7 +233,10 @@ krr_status krr_model_free(krr_model model);
  * concurrently on the device.  A request's result depends only on its own
  * data (the batch it joins changes no arithmetic of a fit, and only the
  * summation split of a prediction).  Latency of a request = time from its
- * submit call to the end of the batch that served it. */
+ * submit call to the end of the batch that served it.  Every worker has its
+ * own stream; for predict batches not to queue behind fit kernels the process
+ * needs a hardware queue per stream (HIP's GPU_MAX_HW_QUEUES, default 4, set
+ * before the runtime starts, at least workers + 1). */
 typedef struct krr_server_s* krr_server;
 
 typedef struct {
