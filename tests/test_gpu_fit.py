@@ -143,6 +143,64 @@ def test_mixed_precision_refines_to_1e6(ctx, dev, sigma):
     assert _pred_rel(yhat, yo, w.yt) < 1e-6
 
 
+@pytest.mark.parametrize("panel", [1, 3, 16])
+def test_mixed_ragged_partitions_panels(ctx, dev, panel):
+    """Mixed precision over k-means partitions of uneven size (systems with
+    different tile counts in one batch) and panel widths that put diagonal
+    blocks both at panel starts and inside the column launches (which also
+    carry the forward solve of the first pass): alpha within 1e-6 of FP64."""
+    w = datagen.small(75, 3000, 12, k=150, p=5, comps=5, dtype=np.float32)
+    print(f"mixed ragged panel={panel}", flush=True)
+    ctx.set_option(krr.OPT_PANEL_TILES, panel)
+    try:
+        params = [krr.Params(sigma=1.5, lam=1e-2, prec="mixed", refine_tol=1e-8, max_refine=40),
+                  krr.Params(sigma=0.7, lam=1e-3, prec="mixed", refine_tol=1e-8, max_refine=40)]
+        models, info, st, oms, X, a = _fit_both(ctx, dev, w, 5, params, method="kmeans", iters=8, seed=7)
+    finally:
+        ctx.set_option(krr.OPT_PANEL_TILES, 16)
+    assert st == 0, info
+    sizes = np.bincount(a, minlength=5)
+    assert len(set(-(-sizes // 64))) > 1   # systems of different tile counts
+    for q in range(2):
+        for j in range(5):
+            assert info[q * 5 + j]["rel_residual"] <= 1e-8
+            assert _rel(models[q].alpha(j).cpu().numpy(), oms[q].alphas[j]) < 1e-6, (q, j)
+
+
+_LARGE = {}
+
+
+def _large_system():
+    """m = 8,300 points in 4 dimensions (FP32-representable) and the oracle's
+    alpha for sigma = 0.5, lambda = 1e-2 (computed once)."""
+    if not _LARGE:
+        g = np.random.default_rng(85)
+        m = 8300
+        X = g.uniform(-1.0, 1.0, size=(m, 4)).astype(np.float32)
+        y = (np.sin(X.astype(np.float64) @ np.array([1.0, -2.0, 0.5, 1.5]))
+             + 0.1 * g.standard_normal(m)).astype(np.float32)
+        ref = O.fit_one(X.astype(np.float64), y.astype(np.float64), 0.5, 1e-2)
+        _LARGE.update(X=X, y=y, alpha=ref["alpha"])
+    return _LARGE["X"], _LARGE["y"], _LARGE["alpha"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_large_system_backward_solve_from_global(ctx, dev, prec):
+    """One system of m = 8,300 (130 tile rows: the backward solve keeps its
+    solution in global memory rather than LDS) against the FP64 oracle."""
+    X, y, alpha_ref = _large_system()
+    print(f"large system m={X.shape[0]} {prec}", flush=True)
+    Xg = X.astype(np.float64) if prec == "fp64" else X
+    yg = y.astype(np.float64) if prec == "fp64" else y
+    Xd = _t(Xg, dev)
+    C, a, _ = ctx.partition(Xd, 1, "given", centroids=_t(np.zeros((1, 4), Xg.dtype), dev))
+    models, info, st = ctx.fit(Xd, _t(yg, dev), a, C, 1,
+                               [krr.Params(sigma=0.5, lam=1e-2, prec=prec, refine_tol=1e-8, max_refine=40)])
+    assert st == 0 and info[0]["status"] == 0
+    err = _rel(models[0].alpha(0).cpu().numpy(), alpha_ref)
+    assert err < (1e-10 if prec == "fp64" else 1e-6), err
+
+
 def test_linear_kernel_is_primal_ridge(ctx, dev):
     """Linear kernel through the GPU path equals x^T (X^T X + lam I)^-1 X^T y
     (Eq. 2 with Table 1's linear kernel)."""
