@@ -44,8 +44,10 @@ __device__ __forceinline__ int64_t tile_index(int i, int j) { return (int64_t)i 
 // Settings are visited by group (grp_first[g], then grp_next[...]): the
 // kernel values are computed once per group and written to every setting of
 // the group with its own shift.
+// Four workgroups per CU (registers capped at 128): the exponentials and the
+// stores of one workgroup overlap the loads and MFMAs of the others.
 template <typename TX, int STORE>
-__global__ __launch_bounds__(256) void k_form(const TX* __restrict__ Xg, int d, const SysDesc* __restrict__ desc,
+__global__ __launch_bounds__(256, 4) void k_form(const TX* __restrict__ Xg, int d, const SysDesc* __restrict__ desc,
                                               int p, int n_groups, const int32_t* __restrict__ grp_first,
                                               const int32_t* __restrict__ grp_next, void* __restrict__ Aout,
                                               double* __restrict__ K64) {
