@@ -42,9 +42,12 @@ __device__ __forceinline__ double mul_sep(double a, double b) {
   return a * b;
 }
 
+// Sequential sum over the features (the additions stay in order; the
+// unrolling only lets the loads of eight features issue together).
 template <typename TX>
 __device__ __forceinline__ double dist2_rows(const TX* __restrict__ a, const TX* __restrict__ b, int d) {
   double acc = 0.0;
+#pragma unroll 8
   for (int k = 0; k < d; ++k) acc = sqdiff_acc(acc, (double)a[k], (double)b[k]);
   return acc;
 }
