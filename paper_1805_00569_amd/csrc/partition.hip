@@ -366,7 +366,14 @@ __global__ __launch_bounds__(MEANS_THREADS) void k_means_partial(const TX* __res
   for (int f = threadIdx.x; f < d; f += MEANS_THREADS) {
     double acc = 0.0;
     int q = 0;
-    for (; q + 8 <= nr; q += 8) {   // 8 independent loads, then 8 ordered adds
+    for (; q + 32 <= nr; q += 32) {   // 32 independent loads, then 32 ordered adds
+      double v[32];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) v[u] = (double)X[rows[q + u] + f];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) acc = add_sep(acc, v[u]);
+    }
+    for (; q + 8 <= nr; q += 8) {
       double v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) v[u] = (double)X[rows[q + u] + f];
