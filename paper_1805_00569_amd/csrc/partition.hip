@@ -83,19 +83,26 @@ __global__ __launch_bounds__(256) void k_assign(const TX* __restrict__ X, int64_
   const int rows = (int)min((int64_t)AROWS, n - row0);
   const TX* src = X + row0 * d;
   const int tot = rows * d;
-  // batches of 8 unconditional loads from clamped addresses, then the stores
+  // batches of 8 unconditional loads from clamped addresses, then the stores;
+  // (row, feature) of element e0 + 256 u follow from those of e0 by steps of
+  // 256 = sq d + sr (one division per batch)
+  const int sq = 256 / d, sr = 256 - sq * d;
   for (int e0 = threadIdx.x; e0 < tot; e0 += 8 * 256) {
     TX v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) v[u] = src[min(e0 + u * 256, tot - 1)];
+    int r = e0 / d, k = e0 - r * d;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = e0 + u * 256;
       // out-of-range elements go to a spare LDS slot instead of a conditional store
-      const int ec = min(e, tot - 1);
-      const int r = ec / d;
-      const int k = ec - r * d;
       sX[(e < tot) ? (k * ld + r) : d * ld] = v[u];
+      k += sr;
+      r += sq;
+      if (k >= d) {
+        k -= d;
+        ++r;
+      }
     }
   }
   __syncthreads();
