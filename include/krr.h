@@ -133,7 +133,8 @@ krr_status  krr_create(int device, size_t hbm_budget_bytes, krr_ctx* out);
 krr_status  krr_destroy(krr_ctx ctx);
 const char* krr_last_error(krr_ctx ctx);
 krr_status  krr_set_option(krr_ctx ctx, int32_t option, int64_t value);
-/* Bytes of device memory currently held by the context (workspace + models). */
+/* Bytes of device memory currently held by the context (workspace + models +
+ * released model blocks kept for reuse by later models of the same size). */
 krr_status  krr_memory_in_use(krr_ctx ctx, size_t* bytes);
 /* Timing record of the launches made since timing was enabled or last
  * reported: synchronises the device and writes a NUL-terminated JSON object
@@ -207,7 +208,9 @@ krr_status krr_select(krr_ctx ctx, hipStream_t stream,
  * krr_model_alpha: copy alpha of partition j (m_j FP64 values, in the order
  * of increasing original point index within the partition) to device memory
  * `alpha` (asynchronous on `stream`); *m receives m_j (host).
- * krr_model_free: release a model (NULL is accepted). */
+ * krr_model_free: release a model (NULL is accepted); waits for the device,
+ * then keeps the model's memory in its context for reuse by later models
+ * (see krr_memory_in_use; freed by krr_destroy or under budget pressure). */
 krr_status krr_model_alpha(krr_ctx ctx, hipStream_t stream, krr_model model, int32_t j,
                            double* alpha, int64_t* m);
 krr_status krr_model_free(krr_model model);

@@ -7,8 +7,25 @@
 
 namespace krr {
 
+// Released model blocks are kept for reuse by later models of the same
+// rounded size, so fits repeated with the same shapes allocate nothing; the
+// cache holds at most MODEL_CACHE_BLOCKS blocks, is emptied before an
+// allocation would exceed the budget, and is freed with the context.  Its
+// bytes count as held by the context.
+constexpr size_t MODEL_CACHE_BLOCKS = 64;
+
+static void drop_model_cache(krr_ctx ctx) {
+  if (ctx->model_cache.empty()) return;
+  (void)hipDeviceSynchronize();
+  for (auto& kv : ctx->model_cache) (void)hipFree(kv.second);
+  ctx->model_cache.clear();
+  ctx->cache_bytes = 0;
+}
+
 static void charge(krr_ctx ctx, size_t add) {
-  if (ctx->budget != 0 && ctx->ws_bytes + ctx->model_bytes + add > ctx->budget)
+  if (ctx->budget == 0) return;
+  if (ctx->ws_bytes + ctx->model_bytes + ctx->cache_bytes + add > ctx->budget) drop_model_cache(ctx);
+  if (ctx->ws_bytes + ctx->model_bytes + add > ctx->budget)
     fail(KRR_EBUDGET, "HBM budget exceeded: holding " + std::to_string(ctx->ws_bytes + ctx->model_bytes) +
                           " bytes, need " + std::to_string(add) + " more, budget " + std::to_string(ctx->budget));
 }
@@ -41,6 +58,14 @@ void* ws_get(krr_ctx ctx, const std::string& name, size_t bytes) {
 void* model_alloc(krr_ctx ctx, size_t bytes) {
   bytes = (bytes + 255) & ~size_t(255);
   if (bytes == 0) bytes = 256;
+  const auto it = ctx->model_cache.find(bytes);
+  if (it != ctx->model_cache.end()) {
+    void* p = it->second;
+    ctx->model_cache.erase(it);
+    ctx->cache_bytes -= bytes;
+    ctx->model_bytes += bytes;
+    return p;
+  }
   charge(ctx, bytes);
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) {
@@ -51,12 +76,18 @@ void* model_alloc(krr_ctx ctx, size_t bytes) {
   return p;
 }
 
+// The caller guarantees that no queued work still uses the block.
 void model_release(krr_ctx ctx, void* p, size_t bytes) {
   if (p == nullptr) return;
   bytes = (bytes + 255) & ~size_t(255);
   if (bytes == 0) bytes = 256;
-  (void)hipFree(p);
   ctx->model_bytes -= std::min(ctx->model_bytes, bytes);
+  if (ctx->model_cache.size() < MODEL_CACHE_BLOCKS) {
+    ctx->model_cache.emplace(bytes, p);
+    ctx->cache_bytes += bytes;
+  } else {
+    (void)hipFree(p);
+  }
 }
 
 void* pinned_get(krr_ctx ctx, size_t bytes) {
@@ -192,6 +223,7 @@ krr_status krr_destroy(krr_ctx ctx) {
   (void)hipDeviceSynchronize();
   for (auto& kv : ctx->ws)
     if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+  drop_model_cache(ctx);
   for (auto& p : ctx->pending) {
     (void)hipEventDestroy(p.a);
     (void)hipEventDestroy(p.b);
@@ -255,7 +287,7 @@ krr_status krr_timing_report(krr_ctx ctx, char* buf, size_t cap, size_t* needed)
 
 krr_status krr_memory_in_use(krr_ctx ctx, size_t* bytes) {
   if (ctx == nullptr || bytes == nullptr) return KRR_EINVAL;
-  *bytes = ctx->ws_bytes + ctx->model_bytes;
+  *bytes = ctx->ws_bytes + ctx->model_bytes + ctx->cache_bytes;
   return KRR_OK;
 }
 

@@ -130,6 +130,8 @@ struct krr_ctx_s {
   std::map<std::string, krr::DevBuf> ws;
   size_t ws_bytes = 0;
   size_t model_bytes = 0;
+  std::multimap<size_t, void*> model_cache;   // released model blocks by rounded size, for reuse
+  size_t cache_bytes = 0;
   int n_models = 0;
   int n_datas = 0;
   int panel_tiles = 16;

@@ -543,7 +543,9 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
     return;
   }
 
-  // 11. models: alpha of setting q is the contiguous range of its p systems
+  // 11. models: alpha of setting q is the contiguous range of its p systems;
+  // their offset tables go up from one pinned slice per model (one wait)
+  int64_t* voff_pin = (int64_t*)pinned_get(ctx, (size_t)n_params * (p + 1) * 8);
   for (int q = 0; q < n_params; ++q) {
     krr_model M = new krr_model_s();
     M->ctx = ctx;
@@ -557,6 +559,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
       M->alpha = (double*)model_alloc(ctx, M->bytes);
     } catch (...) {
       delete M;
+      (void)hipStreamSynchronize(s);   // earlier models' uploads still read their pinned slices
       throw;
     }
     ctx->n_models += 1;
@@ -568,11 +571,12 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
     for (int jp = 0; jp < p; ++jp) M->lambda_eff[jp] = desc[q * p + jp].lambda;
     if (v1 > v0)
       KRR_HIP(hipMemcpyAsync(M->alpha, alpha + v0, (size_t)(v1 - v0) * 8, hipMemcpyDeviceToDevice, s));
-    std::memcpy(pin, M->voff.data(), (size_t)(p + 1) * 8);
-    KRR_HIP(hipMemcpyAsync(M->d_voff, pin, (size_t)(p + 1) * 8, hipMemcpyHostToDevice, s));
-    KRR_HIP(hipStreamSynchronize(s));
+    int64_t* vp = voff_pin + (size_t)q * (p + 1);
+    std::memcpy(vp, M->voff.data(), (size_t)(p + 1) * 8);
+    KRR_HIP(hipMemcpyAsync(M->d_voff, vp, (size_t)(p + 1) * 8, hipMemcpyHostToDevice, s));
     models[q] = M;
   }
+  KRR_HIP(hipStreamSynchronize(s));   // the pinned slices are reused by the next call
 }
 
 }  // namespace krr

@@ -264,6 +264,34 @@ def test_not_spd_pivot_inside_tiles(ctx, dev, prec, dup):
     assert info[0]["status"] == krr.KRR_ENOTSPD and info[0]["failed_pivot"] == dup[1] + 1
 
 
+def test_model_memory_reused(dev):
+    """Models freed by the caller leave their memory in the context for later
+    models of the same size: a repeated fit holds no more memory and gives the
+    same alpha."""
+    w = datagen.small(88, 1500, 6, k=40, p=3, comps=3, dtype=np.float64)
+    X, y = _t(w.X, dev), _t(w.y, dev)
+    params = [krr.Params(sigma=1.5, lam=1e-2, prec="fp64"), krr.Params(sigma=0.8, lam=1e-2, prec="fp64")]
+    c = krr.Context(dev.index or 0)
+    try:
+        C, a, _ = c.partition(X, 3, "kmeans", lloyd_iters=4, seed=1)
+        m1, _, st1 = c.fit(X, y, a, C, 3, params)
+        a1 = [m1[q].alpha(j).cpu().numpy() for q in range(2) for j in range(3)]
+        for m in m1:
+            m.free()
+        held = c.memory_in_use()
+        m2, _, st2 = c.fit(X, y, a, C, 3, params)
+        assert st1 == 0 and st2 == 0
+        assert c.memory_in_use() == held
+        a2 = [m2[q].alpha(j).cpu().numpy() for q in range(2) for j in range(3)]
+        for u, v in zip(a1, a2):
+            np.testing.assert_array_equal(u, v)
+        for m in m2:
+            m.free()
+        assert c.memory_in_use() == held
+    finally:
+        c.close()
+
+
 def test_empty_and_tiny_partitions(ctx, dev):
     g = np.random.default_rng(82)
     X = g.standard_normal((70, 3))
