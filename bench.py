@@ -25,9 +25,15 @@ import time
 
 # The serving leg runs four worker streams beside the main one; with HIP's
 # default of four hardware queues per process they share queues and a
-# predict launch can wait behind a whole fit kernel.  Eight queues give every
-# stream its own (set before the HIP runtime starts; a caller's value wins).
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+# predict launch can wait behind a whole fit kernel.  At least eight queues
+# give every stream its own (set before the HIP runtime starts; a larger
+# value in the environment is kept).
+try:
+    _hwq = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+except ValueError:
+    _hwq = 4
+if _hwq < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 import numpy as np
 
