@@ -43,9 +43,15 @@ __device__ __forceinline__ int64_t tile_index(int i, int j) { return (int64_t)i 
 // lane and fragment.  The fragments of PK_DEPTH steps are in flight in a
 // register ring, so the loads of a step are issued several steps before its
 // MFMAs (the ring's refills past ks1 re-read the last step and are unused).
+// The loop runs whole rounds of the ring with no condition and the remaining
+// steps follow it (WHOLE: the step count is a multiple of PK_DEPTH and there
+// are none): MFMAs under a branch inside the loop let the compiler move the
+// prefetched loads into the branch, next to their use.  Scheduling
+// barriers keep the ring order (prologue) and each step's operand handling
+// inside its step, so that a step waits only for its own loads.
 // Output element (cb, rb, v) of a lane is row 16 rb + (lane & 15), column
 // 16 cb + 4 (lane >> 4) + v of the 16 x 64-column block.
-template <int NCB, int PK_DEPTH>
+template <int NCB, int PK_DEPTH, bool WHOLE = false>
 __device__ __forceinline__ void packed_sub(f4 (&acc)[NCB][4], const __bf16* __restrict__ P, int rbi, int rbj,
                                            int KSW, int ks0, int ks1) {
   if (ks0 >= ks1) return;
@@ -60,22 +66,34 @@ __device__ __forceinline__ void packed_sub(f4 (&acc)[NCB][4], const __bf16* __re
     for (int cb = 0; cb < NCB; ++cb)
       qv[u][cb] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbj + cb) * KSW + ks) * FRAG);
   };
+  auto step = [&](int u) {
 #pragma unroll
-  for (int u = 0; u < PK_DEPTH; ++u) load(u, min(ks0 + u, ks1 - 1));
-  for (int ks = ks0; ks < ks1; ks += PK_DEPTH) {
+    for (int cb = 0; cb < NCB; ++cb) {
+      const bf8 nq = __builtin_bit_cast(bf8, __builtin_bit_cast(u4v, qv[u][cb]) ^ sgn);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+        acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nq, pa[u][rb], acc[cb][rb], 0, 0, 0);
+    }
+  };
+#pragma unroll
+  for (int u = 0; u < PK_DEPTH; ++u) {
+    load(u, min(ks0 + u, ks1 - 1));
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  const int rounds = (ks1 - ks0) / PK_DEPTH, rest = (ks1 - ks0) - rounds * PK_DEPTH;
+  int ks = ks0;
+  for (int g = 0; g < rounds; ++g, ks += PK_DEPTH) {
 #pragma unroll
     for (int u = 0; u < PK_DEPTH; ++u) {
-      if (ks + u < ks1) {
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          const bf8 nq = __builtin_bit_cast(bf8, __builtin_bit_cast(u4v, qv[u][cb]) ^ sgn);
-#pragma unroll
-          for (int rb = 0; rb < 4; ++rb)
-            acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nq, pa[u][rb], acc[cb][rb], 0, 0, 0);
-        }
-      }
+      step(u);
       load(u, min(ks + u + PK_DEPTH, ks1 - 1));
+      __builtin_amdgcn_sched_barrier(0);
     }
+  }
+  if constexpr (!WHOLE) {   // WHOLE: the caller guarantees rest == 0
+#pragma unroll
+    for (int u = 0; u < PK_DEPTH - 1; ++u)
+      if (u < rest) step(u);
   }
 }
 
@@ -756,7 +774,7 @@ __device__ __forceinline__ void panel_col_tile(const SysDesc& D, int s, int i, i
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[cb][rb][v] = C[(16 * cb + 4 * kg + v) * NB + 16 * rb + il];
-  if (k > K0) packed_sub<4, 4>(acc, Pk + D.pk_off + lane * 8, (i - K0) * 4, (k - K0) * 4, KSW, 0, 2 * (k - K0));
+  if (k > K0) packed_sub<4, 2, true>(acc, Pk + D.pk_off + lane * 8, (i - K0) * 4, (k - K0) * 4, KSW, 0, 2 * (k - K0));
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
@@ -892,11 +910,47 @@ __global__ __launch_bounds__(256) void k_panel_col(const SysDesc* __restrict__ d
   }
 }
 
+// Super-tile order of the trailing update: bands of TRAIL_BAND super-rows,
+// column by column inside a band (rows ascending).  A band's row fragments
+// stay in L2 while its columns stream past, and each column's fragments are
+// read by consecutive workgroups; in row-major order a column's fragments
+// are evicted before the next super-row reuses them.  Returns false past the
+// system's NS (NS + 1) / 2 super-tiles.
+constexpr int TRAIL_BAND = 8;
+__device__ __forceinline__ bool trail_decode(int bx, int NS, int& I, int& J) {
+  if (bx >= NS * (NS + 1) / 2) return false;
+  int lo = 0, hi = min(NS, TRAIL_BAND);
+  for (;;) {
+    const int cnt = (hi * (hi + 1) - lo * (lo + 1)) / 2;
+    if (bx < cnt) break;
+    bx -= cnt;
+    lo = hi;
+    hi = min(NS, lo + TRAIL_BAND);
+  }
+  const int h = hi - lo;
+  if (bx < lo * h) {   // columns left of the band: h super-tiles each
+    J = bx / h;
+    I = lo + bx % h;
+    return true;
+  }
+  bx -= lo * h;        // columns inside the band: column J has hi - J super-tiles
+  J = lo;
+  while (bx >= hi - J) {
+    bx -= hi - J;
+    ++J;
+  }
+  I = J + bx;
+  return true;
+}
+
 // Trailing update A(i,j) -= sum_{q in panel} L(i,q) L(j,q)^T for the lower
 // triangle i >= j >= i0, from the packed fragment columns [ks0, ks1): 128 x 128
-// super-tiles (blockIdx.x = triangle index), one 64 x 64 tile per wavefront,
-// accumulators starting from the C tile; workgroups placed by system on the XCDs (NXCD).
-__global__ __launch_bounds__(256) void k_packed_trailing(const SysDesc* __restrict__ desc,
+// super-tiles (blockIdx.x = position in the banded order of trail_decode), one
+// 64 x 64 tile per wavefront, accumulators starting from the C tile;
+// workgroups placed by system on the XCDs (NXCD).  The step count 2 (K1 - K0)
+// is even, so the two-step fragment ring has no remainder; two workgroups per
+// CU (at most 256 registers per lane).
+__global__ __launch_bounds__(256, 2) void k_packed_trailing(const SysDesc* __restrict__ desc,
                                                          const SysStatus* __restrict__ st, float* __restrict__ A,
                                                          const __bf16* __restrict__ Pk, int K0, int ks0, int ks1,
                                                          int i0, int Wp, int level, int n_sys, int ntri) {
@@ -910,12 +964,8 @@ __global__ __launch_bounds__(256) void k_packed_trailing(const SysDesc* __restri
   const int R = D.T - i0;
   if (R <= 0) return;
   const int NS = (R + 1) / 2;
-  const int bx = slot % ntri;
-  int I = (int)((sqrt(8.0 * (double)bx + 1.0) - 1.0) * 0.5);
-  while (I * (I + 1) / 2 > bx) --I;
-  while ((I + 1) * (I + 2) / 2 <= bx) ++I;
-  const int J = bx - I * (I + 1) / 2;
-  if (I >= NS) return;
+  int I, J;
+  if (!trail_decode(slot % ntri, NS, I, J)) return;
   const int i = i0 + 2 * I + (w & 1);
   const int j = i0 + 2 * J + (w >> 1);
   if (i >= D.T || j > i) return;       // waves are independent: no barrier follows
@@ -928,7 +978,7 @@ __global__ __launch_bounds__(256) void k_packed_trailing(const SysDesc* __restri
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[cb][rb][v] = C[(16 * cb + 4 * kg + v) * NB + 16 * rb + il];
-  packed_sub<4, 2>(acc, Pk + D.pk_off + lane * 8, (i - K0) * 4, (j - K0) * 4, 2 * Wp, ks0, ks1);
+  packed_sub<4, 2, true>(acc, Pk + D.pk_off + lane * 8, (i - K0) * 4, (j - K0) * 4, 2 * Wp, ks0, ks1);
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
