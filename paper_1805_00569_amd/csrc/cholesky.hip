@@ -766,14 +766,19 @@ __device__ __forceinline__ void panel_col_tile(const SysDesc& D, int s, int i, i
         whi[cb][ks] = *reinterpret_cast<const bf8*>(Wf + (int64_t)(2 * (2 * cb + ks)) * FRAG);
         wlo[cb][ks] = *reinterpret_cast<const bf8*>(Wf + (int64_t)(2 * (2 * cb + ks) + 1) * FRAG);
       }
+  // element (16 cb + 4 kg + v, 16 rb + il) of the tile: a scalar base per
+  // column block cb, one per-lane offset, the rest immediate
   float* C = A + D.a_off + tile_index(i, k) * TILE;
+  const int lo = 4 * kg * NB + il;
   f4 acc[4][4];
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb)
+  for (int cb = 0; cb < 4; ++cb) {
+    const float* Cc = C + 16 * cb * NB;
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[cb][rb][v] = C[(16 * cb + 4 * kg + v) * NB + 16 * rb + il];
+      for (int v = 0; v < 4; ++v) acc[cb][rb][v] = Cc[lo + v * NB + 16 * rb];
+  }
   if (k > K0) packed_sub<4, 2, true>(acc, Pk + D.pk_off + lane * 8, (i - K0) * 4, (k - K0) * 4, KSW, 0, 2 * (k - K0));
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
@@ -818,16 +823,20 @@ __device__ __forceinline__ void panel_col_tile(const SysDesc& D, int s, int i, i
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   // MFMA result: register v of a lane is column 4 (lane >> 4) + v, row lane & 15 of its 16 x 16 block
+  int lo2;   // the offset recomputed here, not held in registers across the products
+  asm volatile("" : "=v"(lo2) : "0"(lo));
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb)
+  for (int cb = 0; cb < 4; ++cb) {
+    float* Cc = C + 16 * cb * NB;
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int c = 16 * cb + 4 * kg + v, r = 16 * rb + il;
-        C[c * NB + r] = o[cb][rb][v];
+        Cc[lo2 + v * NB + 16 * rb] = o[cb][rb][v];
         sc[c * PC_LD + r] = o[cb][rb][v];
       }
+  }
   if (zf != nullptr) {
     // forward solve: b_i -= L(i,k) z_k (FP64 sums of the stored FP32 factor)
     const double* zk = zf + D.v_off + (int64_t)k * NB;
@@ -897,7 +906,8 @@ __global__ __launch_bounds__(256) void k_panel_col(const SysDesc* __restrict__ d
   if (s >= n_sys) return;
   const SysDesc D = desc[s];
   if (st[s].status != 0 || D.level != level) return;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // wave-uniform wave index: the tile bases stay in scalar registers
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int i = k + 1 + 4 * g + w;
   __shared__ __align__(16) union {
     float sC[4][NB * PC_LD];   // per wave: the tile being solved
@@ -947,9 +957,14 @@ __device__ __forceinline__ bool trail_decode(int bx, int NS, int& I, int& J) {
 // triangle i >= j >= i0, from the packed fragment columns [ks0, ks1): 128 x 128
 // super-tiles (blockIdx.x = position in the banded order of trail_decode), one
 // 64 x 64 tile per wavefront, accumulators starting from the C tile;
-// workgroups placed by system on the XCDs (NXCD).  The step count 2 (K1 - K0)
-// is even, so the two-step fragment ring has no remainder; two workgroups per
-// CU (at most 256 registers per lane).
+// workgroups placed by system on the XCDs (NXCD).  A step's operands are the
+// fragments of the super-tile's four tile rows (ib, ib + 1, jb, jb + 1; four
+// row blocks each): the workgroup loads them once (four 16-byte loads per
+// thread, TR_RD steps ahead into registers), writes them to one of two LDS
+// stages, and each wave reads the eight it multiplies, so that a fragment is
+// fetched from L2 once per workgroup instead of once per wave.  The step
+// count 2 (K1 - K0) is a multiple of TR_RD.
+constexpr int TR_RD = 2;
 __global__ __launch_bounds__(256, 2) void k_packed_trailing(const SysDesc* __restrict__ desc,
                                                          const SysStatus* __restrict__ st, float* __restrict__ A,
                                                          const __bf16* __restrict__ Pk, int K0, int ks0, int ks1,
@@ -960,31 +975,90 @@ __global__ __launch_bounds__(256, 2) void k_packed_trailing(const SysDesc* __res
   if (s >= n_sys) return;
   const SysDesc D = desc[s];
   if (st[s].status != 0 || D.level != level) return;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int R = D.T - i0;
+  const int T = D.T;
+  const int R = T - i0;
   if (R <= 0) return;
   const int NS = (R + 1) / 2;
   int I, J;
-  if (!trail_decode(slot % ntri, NS, I, J)) return;
-  const int i = i0 + 2 * I + (w & 1);
-  const int j = i0 + 2 * J + (w >> 1);
-  if (i >= D.T || j > i) return;       // waves are independent: no barrier follows
-  float* C = A + D.a_off + tile_index(i, j) * TILE;
-  const int il = lane & 15, kg = lane >> 4;
+  if (!trail_decode(slot % ntri, NS, I, J)) return;   // uniform: the whole workgroup leaves
+  // the wave index as a wave-uniform value: tile and fragment bases stay in
+  // scalar registers and the addresses need one per-lane offset each
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int ib = i0 + 2 * I, jb = i0 + 2 * J;
+  const int i = ib + (w & 1), j = jb + (w >> 1);
+  const bool act = i < T && j <= i;
+  __shared__ __align__(16) bf8 sF[2][16][64];   // [stage][4 * row set + row block][lane]
+  // C tile (clamped to a valid tile for the idle waves, which store nothing)
+  const int ic = min(i, T - 1);
+  float* C = A + D.a_off + tile_index(ic, min(j, ic)) * TILE;
+  // element (16 cb + 4 (lane >> 4) + v, 16 rb + (lane & 15)) of the tile: a
+  // scalar base per column block cb, one per-lane offset, the rest immediate
+  const int lo = 4 * (lane >> 4) * NB + (lane & 15);
   f4 acc[4][4];
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb)
+  for (int cb = 0; cb < 4; ++cb) {
+    const float* Cc = C + 16 * cb * NB;
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[cb][rb][v] = C[(16 * cb + 4 * kg + v) * NB + 16 * rb + il];
-  packed_sub<4, 2, true>(acc, Pk + D.pk_off + lane * 8, (i - K0) * 4, (j - K0) * 4, 2 * Wp, ks0, ks1);
+      for (int v = 0; v < 4; ++v) acc[cb][rb][v] = Cc[lo + v * NB + 16 * rb];
+  }
+  // this thread loads row block w of row set q (0: ib, 1: ib + 1, 2: jb, 3: jb + 1; clamped to T - 1)
+  const int KSW = 2 * Wp;
+  const __bf16* src[4];
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb)
+  for (int q = 0; q < 4; ++q) {
+    const int row = min((q < 2 ? ib : jb) + (q & 1), T - 1);
+    src[q] = Pk + D.pk_off + lane * 8 + ((int64_t)((row - K0) * 4 + w) * KSW) * FRAG;
+  }
+  typedef unsigned u4v __attribute__((ext_vector_type(4)));
+  const u4v sgn{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+  bf8 rg[TR_RD][4];
+#pragma unroll
+  for (int u = 0; u < TR_RD; ++u) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      rg[u][q] = *reinterpret_cast<const bf8*>(src[q] + (int64_t)min(ks0 + u, ks1 - 1) * FRAG);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  const int fi = 4 * (w & 1), fj = 8 + 4 * (w >> 1);
+  for (int ks = ks0; ks < ks1; ks += TR_RD) {
+#pragma unroll
+    for (int u = 0; u < TR_RD; ++u) {
+      // stage u & 1: its readers of two steps ago passed the previous barrier
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sF[u & 1][4 * q + w][lane] = rg[u][q];
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        rg[u][q] = *reinterpret_cast<const bf8*>(src[q] + (int64_t)min(ks + u + TR_RD, ks1 - 1) * FRAG);
+      if (act) {
+        bf8 pa[4], qv[4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) pa[rb] = sF[u & 1][fi + rb][lane];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+          qv[cb] = __builtin_bit_cast(bf8, __builtin_bit_cast(u4v, sF[u & 1][fj + cb][lane]) ^ sgn);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb)
+            acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qv[cb], pa[rb], acc[cb][rb], 0, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  if (!act) return;
+  int lo2;   // the offset recomputed here, not held in registers across the loop
+  asm volatile("" : "=v"(lo2) : "0"(lo));
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    float* Cc = C + 16 * cb * NB;
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) C[(16 * cb + 4 * kg + v) * NB + 16 * rb + il] = acc[cb][rb][v];
+      for (int v = 0; v < 4; ++v) Cc[lo2 + v * NB + 16 * rb] = acc[cb][rb][v];
+  }
 }
 
 template <typename TS>
