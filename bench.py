@@ -52,18 +52,15 @@ HBM_PEAK = 8000.0  # GB/s
 # runs of this benchmark (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch,
 # averaged over the kernel's dispatches), each scaled by what the same counter
 # reads for a plain 1 GiB device copy (FETCH_SIZE reads 512 MiB: x2.0;
-# WRITE_SIZE reads 1 GiB: x1.0).  Valid only while the kernel's source is the
-# one measured (sha256 over the listed source regions); otherwise null.
-# HBM bytes per launch of a kernel class from rocprofv3 FETCH_SIZE / WRITE_SIZE
-# runs (KiB per dispatch, scaled by the same counters on a plain device copy).
-# Valid only for the source they were taken on: the sha256 of the kernel's
-# whole source file must match, else the figure is reported as null.
+# WRITE_SIZE reads 1 GiB: x1.0).  Valid only for the source they were taken
+# on: the sha256 of the kernel's whole source file must match, else the figure
+# is reported as null.
 TRAFFIC = {
     "chol_column_bf16": {
         "kernel": "k_panel_col",
         "source": "paper_1805_00569_amd/csrc/cholesky.hip",
-        "sha256": "ec0063506f97200d89cae4c2e3ccfa464607bceb9d8cbfc201448e243b2fbd51",
-        "fetch_kib": 118758.8, "write_kib": 79691.9, "fetch_scale": 2.0, "write_scale": 1.0,
+        "sha256": "849d5adb54e6ae6faaf8bd5691c1d339566d8b506b1545e9b949eb7767dcb7bf",
+        "fetch_kib": 118846.4, "write_kib": 79707.7, "fetch_scale": 2.0, "write_scale": 1.0,
     },
 }
 
