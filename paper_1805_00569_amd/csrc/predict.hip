@@ -25,15 +25,20 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int KCR = 32;          // features per staged block; a wave keeps its test operands of a block in registers
 constexpr int KSR = KCR / 4;     // 4-deep MFMA steps per block
-constexpr int LDX = NB + 1;
+// training block in LDS, row-major with a row pitch of KCR + 4 doubles: the
+// staging stores (consecutive features of a row) and the MFMA operand reads
+// (16 rows x 4 features per instruction) both touch every bank pair at most
+// twice, the minimum for 64 eight-byte accesses
+constexpr int LDR = KCR + 4;
 constexpr int MAXM = 8;
 
 struct PredModels {
   const double* alpha[MAXM];
   const int64_t* voff[MAXM];
-  double neg_inv_2s2[MAXM];
   double* out[MAXM];
-  int uq[MAXM];   // first model with the same -1/(2 sigma^2): the kernel values are shared
+  double negu[MAXM];   // the distinct -1/(2 sigma^2) of the models (nu of them)
+  int uidx[MAXM];      // model q uses negu[uidx[q]]: the kernel values are shared
+  int nu;
   int nm;
   int kernel;
 };
@@ -70,9 +75,8 @@ __global__ __launch_bounds__(256, 2) void k_predict(const TX* __restrict__ Xt, i
   const int64_t m = xoff[j + 1] - x0;
   const int64_t xbeg = (int64_t)split * cps * NB;
   const int64_t xend = min(m, xbeg + (int64_t)cps * NB);
-  __shared__ double sX[KCR * LDX];   // training block: sX[kk * LDX + row], zero past the features
+  __shared__ double sX[NB * LDR];    // training block: sX[row * LDR + kk], zero past the features
   __shared__ double sNp[4][NB];      // training-row norms, four feature quarters
-  __shared__ double sA[MAXM][NB];    // alpha of the chunk, zero past its rows
   __shared__ int64_t srow[NB];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int il = lane & 15, kl = lane >> 4;
@@ -103,83 +107,122 @@ __global__ __launch_bounds__(256, 2) void k_predict(const TX* __restrict__ Xt, i
   nt += __shfl_xor(nt, 16, 64);
   nt += __shfl_xor(nt, 32, 64);
   const bool one_block = d <= KCR;   // the test operands stay loaded across the chunks
+  // The chunks of this split and their feature blocks run as one sequence of
+  // block steps; the loads of step b + 1 (training block and test operands)
+  // are issued before the products of step b, so their latency overlaps the
+  // matrix cores and the exponentials.
+  const int nblk = (d + KCR - 1) / KCR;
+  const int64_t nsteps = xend > xbeg ? ((xend - xbeg + NB - 1) / NB) * nblk : 0;
+  TX lx[NB * KCR / 256];
+  TX btn[KSR];       // test operands of the step's block (raw; zeroed past d when used)
+  auto fetch = [&](int64_t b) {
+    const int64_t xc = xbeg + (b / nblk) * NB;
+    const int k0 = (int)(b % nblk) * KCR;
+    const int64_t xcnt = min((int64_t)NB, xend - xc);
+    const int kc = min(KCR, d - k0);
+#pragma unroll
+    for (int u = 0; u < NB * KCR / 256; ++u) {
+      const int e = t + u * 256, row = e / KCR, kk = e - row * KCR;
+      lx[u] = Xg[(x0 + xc + min((int64_t)row, xcnt - 1)) * d + k0 + min(kk, kc - 1)];
+    }
+    if (!one_block) {
+#pragma unroll
+      for (int s = 0; s < KSR; ++s) btn[s] = Xt[trow * d + k0 + min(4 * s + kl, kc - 1)];
+    }
+  };
+  __shared__ double sA[2][MAXM][NB];   // alpha of the chunk (by chunk parity), zero past its rows
   double part[MAXM];
 #pragma unroll
   for (int q = 0; q < MAXM; ++q) part[q] = 0.0;
-  for (int64_t xc = xbeg; xc < xend; xc += NB) {
+  d4 acc[4];
+  double nxp = 0.0;   // norm of training row (t & 63) over feature quarter (t >> 6) of the blocks
+  if (nsteps > 0) fetch(0);
+  for (int64_t b = 0; b < nsteps; ++b) {
+    const int kb = (int)(b % nblk);
+    const int64_t xc = xbeg + (b / nblk) * NB;
     const int64_t xcnt = min((int64_t)NB, xend - xc);
-    d4 acc[4];
+    const int k0 = kb * KCR, kc = min(KCR, d - k0);
+    const int buf = (int)((b / nblk) & 1);
+    if (kb == 0) {
 #pragma unroll
-    for (int xb = 0; xb < 4; ++xb) acc[xb] = d4{0.0, 0.0, 0.0, 0.0};
-    double nxp = 0.0;   // norm of training row (t & 63) over feature quarter (t >> 6) of the blocks
-    for (int k0 = 0; k0 < d; k0 += KCR) {
-      const int kc = min(KCR, d - k0);
-      if (!one_block) load_test(k0, kc);
-      TX lx[NB * KCR / 256];
-#pragma unroll
-      for (int u = 0; u < NB * KCR / 256; ++u) {
-        const int e = t + u * 256, row = e / KCR, kk = e - row * KCR;
-        lx[u] = Xg[(x0 + xc + min((int64_t)row, xcnt - 1)) * d + k0 + min(kk, kc - 1)];
-      }
-      __syncthreads();   // the previous block's readers are done
-#pragma unroll
-      for (int u = 0; u < NB * KCR / 256; ++u) {
-        const int e = t + u * 256, row = e / KCR, kk = e - row * KCR;
-        sX[kk * LDX + row] = kk < kc ? (double)lx[u] : 0.0;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < KCR / 4; ++u) {
-        const double v = sX[((t >> 6) * (KCR / 4) + u) * LDX + (t & 63)];
-        nxp = fma(v, v, nxp);
-      }
-#pragma unroll
-      for (int s = 0; s < KSR; ++s) {
-        if (4 * s < kc) {
-          const int ko = (4 * s + kl) * LDX;
-#pragma unroll
-          for (int xb = 0; xb < 4; ++xb)
-            acc[xb] = __builtin_amdgcn_mfma_f64_16x16x4f64(sX[ko + 16 * xb + il], bt[s], acc[xb], 0, 0, 0);
-        }
-        if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);   // bounds the operand loads in flight
-      }
+      for (int xb = 0; xb < 4; ++xb) acc[xb] = d4{0.0, 0.0, 0.0, 0.0};
+      nxp = 0.0;
     }
-    sNp[t >> 6][t & 63] = nxp;
+    __syncthreads();   // the previous block's readers are done
 #pragma unroll
-    for (int q = 0; q < MAXM; ++q)
-      if (q < M.nm && t < NB) {
-        const double av = M.alpha[q][M.voff[q][j] + xc + min((int64_t)t, xcnt - 1)];
-        sA[q][t] = t < xcnt ? av : 0.0;
-      }
+    for (int u = 0; u < NB * KCR / 256; ++u) {
+      const int e = t + u * 256, row = e / KCR, kk = e - row * KCR;
+      sX[row * LDR + kk] = kk < kc ? (double)lx[u] : 0.0;
+    }
+    if (kb == 0 && t < NB) {   // alpha of the chunk (read at its last block)
+#pragma unroll
+      for (int q = 0; q < MAXM; ++q)
+        if (q < M.nm) {
+          const double a = M.alpha[q][M.voff[q][j] + xc + min((int64_t)t, xcnt - 1)];
+          sA[buf][q][t] = t < xcnt ? a : 0.0;
+        }
+    }
+    if (!one_block) {
+#pragma unroll
+      for (int s = 0; s < KSR; ++s) bt[s] = 4 * s + kl < kc ? (double)btn[s] : 0.0;
+    }
     __syncthreads();
+    if (b + 1 < nsteps) fetch(b + 1);
+#pragma unroll
+    for (int u = 0; u < KCR / 4; ++u) {
+      const double v = sX[(t & 63) * LDR + (t >> 6) * (KCR / 4) + u];
+      nxp = fma(v, v, nxp);
+    }
+#pragma unroll
+    for (int s = 0; s < KSR; ++s) {
+      if (4 * s < kc) {
+        const int ko = 4 * s + kl;
+#pragma unroll
+        for (int xb = 0; xb < 4; ++xb)
+          acc[xb] = __builtin_amdgcn_mfma_f64_16x16x4f64(sX[(16 * xb + il) * LDR + ko], bt[s], acc[xb], 0, 0, 0);
+      }
+      if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);   // bounds the operand loads in flight
+    }
+    if (kb != nblk - 1) continue;
+    sNp[t >> 6][t & 63] = nxp;
+    __syncthreads();
+    // squared distances of the lane's 16 (training row, test point) pairs;
     // rows past the chunk carry alpha = 0 (their kernel values are finite)
+    double d2[16];
 #pragma unroll
     for (int xb = 0; xb < 4; ++xb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int xl = 16 * xb + kl + 4 * v;   // FP64 MFMA result row of register v
-        const double G = acc[xb][v];
         const double nx = (sNp[0][xl] + sNp[1][xl]) + (sNp[2][xl] + sNp[3][xl]);
-        const double d2 = fmax(0.0, (nt + nx) - 2.0 * G);
-        double kv[MAXM];
+        d2[4 * xb + v] = fmax(0.0, (nt + nx) - 2.0 * acc[xb][v]);
+      }
+    // per half of the elements, one distinct sigma at a time: its 8 kernel
+    // values in one branch-free block (independent exponentials the
+    // scheduler interleaves), then the models that use it; every model sums
+    // its elements in the same order
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll 1
+      for (int u = 0; u < M.nu; ++u) {
+        double kv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int el = 8 * h + e;
+          kv[e] = M.kernel == KRR_KERNEL_GAUSSIAN ? exp(d2[el] * M.negu[u]) : acc[el >> 2][el & 3];
+        }
 #pragma unroll
         for (int q = 0; q < MAXM; ++q) {
-          if (q < M.nm) {
-            if (M.kernel != KRR_KERNEL_GAUSSIAN) {
-              kv[q] = G;
-            } else if (M.uq[q] == q) {
-              kv[q] = exp(d2 * M.neg_inv_2s2[q]);
-            } else {
-              double s0 = 0.0;
+          if (q < M.nm && M.uidx[q] == u) {
 #pragma unroll
-              for (int q2 = 0; q2 < q; ++q2)
-                if (M.uq[q] == q2) s0 = kv[q2];
-              kv[q] = s0;
+            for (int e = 0; e < 8; ++e) {
+              const int el = 8 * h + e;
+              part[q] = fma(sA[buf][q][16 * (el >> 2) + kl + 4 * (el & 3)], kv[e], part[q]);
             }
-            part[q] = fma(sA[q][xl], kv[q], part[q]);
           }
         }
       }
+    }
   }
   // lanes il, il+16, il+32, il+48 hold partial sums of the same test point
 #pragma unroll
@@ -306,10 +349,11 @@ void predict_group(krr_ctx ctx, hipStream_t s, const krr_model* models, int nm, 
   for (int q = 0; q < nm; ++q) {
     M.alpha[q] = models[q]->alpha;
     M.voff[q] = models[q]->d_voff;
-    M.neg_inv_2s2[q] = -1.0 / (2.0 * models[q]->params.sigma * models[q]->params.sigma);
-    M.uq[q] = q;
-    for (int q2 = q - 1; q2 >= 0; --q2)
-      if (M.neg_inv_2s2[q2] == M.neg_inv_2s2[q]) M.uq[q] = q2;
+    const double ng = -1.0 / (2.0 * models[q]->params.sigma * models[q]->params.sigma);
+    int u = 0;
+    while (u < M.nu && M.negu[u] != ng) ++u;
+    if (u == M.nu) M.negu[M.nu++] = ng;
+    M.uidx[q] = u;
     M.out[q] = dst[q];
     KRR_REQUIRE(models[q]->params.kernel == M.kernel, "models of one call must share the kernel");
   }
