@@ -12,6 +12,7 @@ Ridge Regression on Parallel and Distributed Systems" (ICS'18):
   (K + lambda I) alpha = y, prediction, MSE (Eq. 3).
 * Table 1: Gaussian and linear kernels.
 * Section 2.4, Algorithm 2: K-means (assignment, change count, mean update).
+* Section 3.2, Algorithm 3 (DC-KRR): random even partition, averaged models.
 * Section 4.3, Algorithm 4: K-balance (capacity-constrained greedy pass in
   sample order, then centre recompute); Algorithm 5 (BKRR2): per-partition
   fits, nearest-centre routing of test points, MSE reduce, best parameters.
@@ -36,6 +37,9 @@ Readings taken where the paper is silent (each is listed in the design notes):
 * Member sums for means are sequential in increasing point index.
 * K-balance capacity is ceil(n/p); the recompute of centres (optional in the
   paper) is done.
+* DC-KRR's shuffle (Algorithm 3) is a keyed Feistel permutation with
+  cycle-walking, and the even split gives partition j the shuffled rows
+  [floor(j n / p), floor((j + 1) n / p)); see ``shuffle_positions``.
 """
 from __future__ import annotations
 
@@ -226,9 +230,75 @@ def kbalance(X, p, iters, seed):
     return C2, MB
 
 
+# ---------------------------------------------------------------------------
+# DC-KRR divide step (Section 3.2, Algorithm 3): shuffle the rows of [X, y],
+# then hand them out evenly by rows
+# ---------------------------------------------------------------------------
+
+SHUFFLE_ROUNDS = 8
+
+
+def _mix64(z: int) -> int:
+    """Output function of SplitMix64 (Steele, Lea, Flood 2014): two
+    xor-shift-multiply rounds and a final xor-shift of a 64-bit value."""
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def shuffle_positions(n: int, seed: int) -> np.ndarray:
+    """pos[i] = the row that point i takes in the shuffled matrix of Algorithm 3.
+
+    The paper does not say how to shuffle.  Here the shuffle is a keyed
+    pseudo-random permutation, computed for every point on its own: a
+    balanced Feistel network of SHUFFLE_ROUNDS rounds on b-bit values (b the
+    smallest even number >= 2 with 2^b >= n; halves of h = b/2 bits; round r
+    maps (L, R) to (R, L xor F_r(R)) with F_r(R) = the low h bits of the
+    SplitMix64 output function of (K_r + R) mod 2^64, K_r = the r-th
+    SplitMix64 output of the seed), restricted to [0, n) by cycle-walking
+    (Black & Rogaway, "Ciphers with arbitrary finite domains", CT-RSA 2002):
+    an image outside [0, n) is mapped again until it falls inside."""
+    keys = splitmix64_outputs(seed, SHUFFLE_ROUNDS)
+    b = 2
+    while (1 << b) < n:
+        b += 2
+    h = b // 2
+    mask = (1 << h) - 1
+
+    def feistel(v: int) -> int:
+        left, right = v >> h, v & mask
+        for key in keys:
+            left, right = right, left ^ (_mix64((key + right) & MASK64) & mask)
+        return (left << h) | right
+
+    pos = np.empty(n, dtype=np.int64)
+    for i in range(n):
+        v = feistel(i)
+        while v >= n:
+            v = feistel(v)
+        pos[i] = v
+    return pos
+
+
+def random_partition(X: np.ndarray, p: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """Algorithm 3's even split of the shuffled rows: shuffled row pos goes to
+    partition j with floor(j n / p) <= pos < floor((j + 1) n / p), i.e.
+    j = ceil((pos + 1) p / n) - 1 (sizes differ by at most one).  The centres
+    (for nearest-centre routing; Algorithm 3 itself averages all models) are
+    the member means, summed as in Algorithm 2's mean step."""
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[0]
+    pos = shuffle_positions(n, seed)
+    a = (((pos + 1) * p + n - 1) // n - 1).astype(np.int32)
+    C, _ = member_means(X, a, np.zeros((p, X.shape[1])))
+    return C, a
+
+
 def partition(X, p, method, iters=20, seed=0, centroids=None):
     """Returns (centroids p x d FP64, assignment int32[n], sizes int64[p])."""
-    if method == "given":
+    if method == "random":
+        C, a = random_partition(X, p, seed)
+    elif method == "given":
         C = np.asarray(centroids, dtype=np.float64)
         a, _ = assign(X, C)
     elif method == "kmeans":

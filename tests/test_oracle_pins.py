@@ -241,6 +241,52 @@ def test_empty_cluster_keeps_centre():
     assert C[0, 0] == 0.05
 
 
+# ---------------------------------------------------------------- DC-KRR random partition
+
+def _split_bounds(n, p):
+    return [(j * n) // p for j in range(p + 1)]
+
+
+def test_shuffle_is_a_permutation():
+    """Algorithm 3 shuffles the rows: every point gets a distinct row in
+    [0, n), including sizes that need cycle-walking (n not a power of 4) and
+    the degenerate n = 1, 2."""
+    for n in (1, 2, 3, 4, 5, 16, 17, 100, 1000, 4095, 4096, 4097):
+        pos = O.shuffle_positions(n, 11)
+        assert sorted(pos.tolist()) == list(range(n)), n
+
+
+def test_shuffle_depends_on_seed_and_is_not_trivial():
+    """A fixed seed gives a fixed shuffle, another seed another one, and the
+    shuffle is not the identity or a rotation: the first half of the points
+    lands on both halves of the rows in about equal numbers."""
+    n = 4096
+    a, b, c = O.shuffle_positions(n, 1), O.shuffle_positions(n, 1), O.shuffle_positions(n, 2)
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+    first_half_low = np.count_nonzero(a[: n // 2] < n // 2)
+    assert abs(first_half_low - n // 4) < n // 16
+    assert np.count_nonzero(np.diff(a) == 1) < n // 64
+
+
+def test_random_partition_is_the_even_split_of_the_shuffle():
+    """Partition j holds exactly the points whose shuffled row lies in
+    [floor(j n/p), floor((j+1) n/p)): sizes differ by at most one, p = 1 puts
+    every point in partition 0 and p = n gives one point per partition."""
+    g = np.random.default_rng(4)
+    for n, p in ((1000, 7), (4097, 16), (10, 10), (37, 1), (5, 3)):
+        X = g.standard_normal((n, 3))
+        C, a = O.random_partition(X, p, 9)
+        pos = O.shuffle_positions(n, 9)
+        lo = _split_bounds(n, p)
+        for i in range(n):
+            assert lo[a[i]] <= pos[i] < lo[a[i] + 1]
+        sizes = np.bincount(a, minlength=p)
+        assert sizes.tolist() == [lo[j + 1] - lo[j] for j in range(p)]
+        assert sizes.max() - sizes.min() <= 1
+        for j in range(p):   # centres are the member means
+            np.testing.assert_allclose(C[j], X[a == j].mean(axis=0), rtol=0, atol=1e-13)
+
+
 # ---------------------------------------------------------------- K-balance
 
 def test_kbalance_equal_sizes_and_greedy_rule():
