@@ -60,8 +60,13 @@ typedef enum { KRR_F32 = 0, KRR_F64 = 1 } krr_dtype;
 /* Partitioning methods.  KMEANS: k-means++ seeding + Lloyd (Algorithm 2);
  * KBALANCE: K-means followed by the capacity-ceil(n/p) greedy pass and the
  * centre recompute (Algorithm 4); GIVEN: assign to caller-supplied centres
- * (the assignment step of Algorithm 2). */
-typedef enum { KRR_PART_KMEANS = 0, KRR_PART_KBALANCE = 1, KRR_PART_GIVEN = 2 } krr_part;
+ * (the assignment step of Algorithm 2); RANDOM: DC-KRR's divide step
+ * (Algorithm 3): the rows are shuffled by a permutation keyed by `seed`
+ * (Feistel network with SplitMix64 round keys, cycle-walked to [0, n)) and
+ * partition j takes the shuffled rows [floor(j n/p), floor((j+1) n/p));
+ * centroids are the member means (lloyd_iters is ignored).  Algorithm 3
+ * then averages all models: KRR_ROUTE_AVERAGE with lambda_times_m = 1. */
+typedef enum { KRR_PART_KMEANS = 0, KRR_PART_KBALANCE = 1, KRR_PART_GIVEN = 2, KRR_PART_RANDOM = 3 } krr_part;
 
 /* Working precision of a fit.
  * FP64:  kernel matrix, Cholesky and solves in FP64.

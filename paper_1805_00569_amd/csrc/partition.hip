@@ -895,6 +895,46 @@ struct SplitMix64 {
   double uniform() { return (double)(next() >> 11) * 0x1.0p-53; }
 };
 
+// DC-KRR divide step (Algorithm 3): the rows are shuffled and handed out
+// evenly.  The shuffle is a keyed pseudo-random permutation that every point
+// evaluates on its own: a balanced Feistel network of SHUFFLE_ROUNDS rounds on
+// 2h-bit values (2^2h >= n), round r mapping (L, R) to (R, L xor F_r(R)) with
+// F_r(R) = the low h bits of the SplitMix64 output function of K_r + R (K_r =
+// the r-th SplitMix64 output of the seed), restricted to [0, n) by
+// cycle-walking (Black and Rogaway, CT-RSA 2002): an image outside [0, n) is
+// mapped again.  The walk ends because the point's own cycle returns to it.
+// Shuffled row pos belongs to partition j = ceil((pos + 1) p / n) - 1, i.e.
+// floor(j n / p) <= pos < floor((j + 1) n / p).
+constexpr int SHUFFLE_ROUNDS = 8;
+struct ShuffleKeys {
+  uint64_t k[SHUFFLE_ROUNDS];
+};
+
+__device__ __forceinline__ uint64_t splitmix_out(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_random_assign(int64_t n, int p, int h, const ShuffleKeys K,
+                                                       int32_t* __restrict__ assign) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t mask = (1ull << h) - 1ull;
+  uint64_t v = (uint64_t)i;
+  do {
+    uint64_t left = v >> h, right = v & mask;
+#pragma unroll
+    for (int r = 0; r < SHUFFLE_ROUNDS; ++r) {
+      const uint64_t t = left ^ (splitmix_out(K.k[r] + right) & mask);
+      left = right;
+      right = t;
+    }
+    v = (left << h) | right;
+  } while (v >= (uint64_t)n);
+  assign[i] = (int32_t)((((int64_t)v + 1) * p + n - 1) / n - 1);
+}
+
 template <typename TX>
 void assign_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, const double* CT, int p,
               int32_t* out, double* D, const int32_t* prev, int32_t* delta, const int32_t* skip,
@@ -1024,7 +1064,21 @@ template <typename TX>
 static void partition_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, int p, int method,
                         int iters, uint64_t seed, double* C, int32_t* assign, int64_t* sizes) {
   double* CT = (double*)ws_get(ctx, "part_ct", (size_t)p * d * 8);
-  if (method == KRR_PART_GIVEN) {
+  if (method == KRR_PART_RANDOM) {
+    // Algorithm 3: shuffled even split; centres = member means (for routing)
+    ShuffleKeys K;
+    SplitMix64 g{seed};
+    for (int r = 0; r < SHUFFLE_ROUNDS; ++r) K.k[r] = g.next();
+    int b = 2;
+    while ((int64_t(1) << b) < n) b += 2;
+    hipLaunchKernelGGL(k_random_assign, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, n, p, b / 2, K, assign);
+    check_launch(ctx, s, "random_assign");
+    char* w = (char*)ws_get(ctx, "rand_perm", (size_t)n * 4 + (size_t)(p + 1) * 8 + 16);
+    int32_t* perm = (int32_t*)w;
+    int64_t* off = (int64_t*)(perm + n + (n & 1));
+    group_by_key(ctx, s, assign, n, p, perm, off, nullptr, nullptr);
+    means_t(ctx, s, X, n, d, perm, off, C, p, nullptr, nullptr, nullptr);
+  } else if (method == KRR_PART_GIVEN) {
     transpose_centroids(ctx, s, C, p, d, CT);
     assign_t(ctx, s, X, n, d, CT, p, assign, nullptr, nullptr, nullptr, nullptr, false);
   } else {

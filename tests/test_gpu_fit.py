@@ -90,6 +90,28 @@ def test_ragged_partitions_fp64(ctx, dev, n, d, p, panel):
     assert best == O.select(mo)
 
 
+def test_dckrr_random_partition_average_route_fp64(ctx, dev):
+    """DC-KRR (Algorithm 3): random even partition, per-partition systems
+    (K + lambda m I) alpha = y, prediction averaged over all models, best
+    setting by MSE -- against the oracle."""
+    w = datagen.small(61, 3001, 6, k=200, p=4, comps=4, dtype=np.float64)
+    print("dc-krr n=3001 d=6 p=4", flush=True)
+    params = [krr.Params(sigma=s_, lam=1e-4, prec="fp64", lambda_times_m=True) for s_ in (0.8, 2.0)]
+    models, info, st, oms, X, a = _fit_both(ctx, dev, w, 4, params, method="random", seed=17)
+    assert st == 0
+    assert sorted(int(i["m"]) for i in info[:4]) == [750, 750, 750, 751]
+    for q in range(2):
+        for j in range(4):
+            assert _rel(models[q].alpha(j).cpu().numpy(), oms[q].alphas[j]) < 1e-10, (q, j)
+        yhat = ctx.predict(models[q], _t(w.Xt, dev), route="average").cpu().numpy()
+        yo, _ = O.predict(oms[q], w.Xt, "average")
+        assert _pred_rel(yhat, yo, w.yt) < 1e-10
+    mse, best = ctx.select(models, _t(w.Xt, dev), _t(w.yt, dev), route="average")
+    mo = [O.mse(O.predict(om, w.Xt, "average")[0], w.yt) for om in oms]
+    np.testing.assert_allclose(mse, mo, rtol=1e-10)
+    assert best == O.select(mo)
+
+
 def test_batch_invariance_serial_equals_batched(ctx, dev):
     """The plain per-system launch sequence gives bitwise the same alpha as
     the batched one."""

@@ -82,6 +82,24 @@ def test_kbalance_many_blocks_with_ties(ctx, dev, p):
     assert sz.cpu().numpy().max() <= -(-n // p)
 
 
+@pytest.mark.parametrize("n,d,p,seed,dtype", [(20011, 90, 16, 5, np.float32), (4096, 8, 7, 1, np.float64),
+                                              (65536, 4, 64, 9, np.float32), (5, 3, 5, 2, np.float64),
+                                              (37, 2, 1, 3, np.float32)])
+def test_random_partition_bitexact(ctx, dev, n, d, p, seed, dtype):
+    """DC-KRR divide step (Algorithm 3): the shuffled even split and its
+    member-mean centres, bit for bit; sizes differ by at most one (n = 65536
+    needs no cycle-walking, 20011 does)."""
+    print(f"random partition n={n} d={d} p={p} seed={seed}", flush=True)
+    g = np.random.default_rng(n + p)
+    X = (g.standard_normal((n, d)) * g.uniform(0.5, 2, d)).astype(dtype)
+    C, a, sz = ctx.partition(_t(X, dev), p, "random", seed=seed)
+    Co, ao = O.random_partition(X, p, seed)
+    np.testing.assert_array_equal(a.cpu().numpy(), ao)
+    np.testing.assert_array_equal(sz.cpu().numpy(), np.bincount(ao, minlength=p))
+    np.testing.assert_array_equal(C.cpu().numpy(), Co)
+    assert sz.max().item() - sz.min().item() <= 1
+
+
 def test_kmeans_converges_early(ctx, dev):
     # well separated clusters: Lloyd reaches a fixed point before the cap
     w = datagen.small(34, 2000, 4, comps=4, spread=50.0)
