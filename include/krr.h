@@ -81,8 +81,11 @@ typedef enum { KRR_PREC_FP64 = 0, KRR_PREC_FP32 = 1, KRR_PREC_MIXED = 2 } krr_pr
 /* Prediction routes.  NEAREST: model of the nearest centre (KKRR2 / BKRR2,
  * Section 4.2, Algorithm 5).  AVERAGE: mean of all p models (KKRR / DC-KRR,
  * Section 4.1, Algorithm 3).  ALL: the k x p matrix of every model's
- * prediction (input of the label-based choice of BKRR3, Algorithm 6). */
-typedef enum { KRR_ROUTE_NEAREST = 0, KRR_ROUTE_AVERAGE = 1, KRR_ROUTE_ALL = 2 } krr_route;
+ * prediction.  LABEL (krr_select only: it needs the labels): per point, the
+ * one of the p models whose prediction is closest to the point's label
+ * (BKRR3 / KKRR3, Section 4.4, Algorithm 6; the error lower bound of the
+ * partitioned methods). */
+typedef enum { KRR_ROUTE_NEAREST = 0, KRR_ROUTE_AVERAGE = 1, KRR_ROUTE_ALL = 2, KRR_ROUTE_LABEL = 3 } krr_route;
 
 /* Table 1: Gaussian exp(-||a-b||^2 / (2 sigma^2)); linear a^T b. */
 typedef enum { KRR_KERNEL_GAUSSIAN = 0, KRR_KERNEL_LINEAR = 1 } krr_kernel;
@@ -203,7 +206,10 @@ krr_status krr_predict(krr_ctx ctx, hipStream_t stream, krr_model model,
 /* ---- select (Eq. 3; Algorithm 5 model choice) ----------------------------
  * Predicts the k validation points Xv with every model, mse_out[i] =
  * mean((yhat_i - yv)^2) (host, n_models), *best_out = index of the lowest MSE
- * (strict "<": the first model wins ties; host).  Synchronises `stream`. */
+ * (strict "<": the first model wins ties; host).  route: NEAREST, AVERAGE or
+ * LABEL (yhat_i per point = the partition model closest to its label, i.e.
+ * the squared error is the minimum over the p models; Algorithm 6); ALL is
+ * rejected with KRR_EINVAL.  Synchronises `stream`. */
 krr_status krr_select(krr_ctx ctx, hipStream_t stream,
                       const krr_model* models, int32_t n_models,
                       const void* Xv, const void* yv, int32_t dtype, int64_t k, int32_t route,

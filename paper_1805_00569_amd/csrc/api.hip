@@ -364,7 +364,8 @@ krr_status krr_select(krr_ctx ctx, hipStream_t stream, const krr_model* models, 
     for (int i = 0; i < n_models; ++i) KRR_REQUIRE(models[i] && models[i]->ctx == ctx, "bad model handle");
     KRR_REQUIRE(dtype == KRR_F32 || dtype == KRR_F64, "dtype must be KRR_F32 or KRR_F64");
     KRR_REQUIRE(k >= 1 && k < (int64_t(1) << 31) - 1, "k must be >= 1");
-    KRR_REQUIRE(route == KRR_ROUTE_NEAREST || route == KRR_ROUTE_AVERAGE, "route must be NEAREST or AVERAGE");
+    KRR_REQUIRE(route == KRR_ROUTE_NEAREST || route == KRR_ROUTE_AVERAGE || route == KRR_ROUTE_LABEL,
+                "route must be NEAREST, AVERAGE or LABEL");
     run_select(ctx, stream, models, n_models, Xv, yv, dtype, k, route, mse_out, best_out);
   });
 }

@@ -271,15 +271,23 @@ __global__ void k_row_mean(const double* __restrict__ all, int64_t k, int p, dou
   out[i] = s / (double)p;
 }
 
+// Block sums of the squared errors.  yhat holds pc predictions per point
+// (row-major k x pc); a point's error is the smallest over them (pc = 1: the
+// plain error; pc = p: the label-based choice of Algorithm 6).
 template <typename TY>
-__global__ __launch_bounds__(256) void k_sqerr(const double* __restrict__ yhat, const TY* __restrict__ y, int64_t k,
-                                               double* __restrict__ partial) {
+__global__ __launch_bounds__(256) void k_sqerr(const double* __restrict__ yhat, int pc, const TY* __restrict__ y,
+                                               int64_t k, double* __restrict__ partial) {
   __shared__ double sred[256];
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double e = 0.0;
   if (i < k) {
-    const double dlt = yhat[i] - (double)y[i];
+    const double yi = (double)y[i];
+    double dlt = yhat[i * pc] - yi;
     e = dlt * dlt;
+    for (int j = 1; j < pc; ++j) {
+      dlt = yhat[i * pc + j] - yi;
+      e = fmin(e, dlt * dlt);
+    }
   }
   sred[threadIdx.x] = e;
   __syncthreads();
@@ -422,9 +430,12 @@ void run_predict(krr_ctx ctx, hipStream_t s, krr_model model, const void* Xt, in
 void run_select(krr_ctx ctx, hipStream_t s, const krr_model* models, int n_models, const void* Xv, const void* yv,
                 int dtype, int64_t k, int route, double* mse, int32_t* best) {
   const int64_t nb = ceil_div(k, 256);
-  char* w = (char*)ws_get(ctx, "select", (size_t)k * 8 * MAXM + (size_t)nb * 8 + (size_t)n_models * 8 + 512);
+  const bool label = route == KRR_ROUTE_LABEL;   // every model's prediction per point, then the closest
+  int pmax = 1;
+  for (int i = 0; i < n_models && label; ++i) pmax = std::max(pmax, (int)models[i]->data->p);
+  char* w = (char*)ws_get(ctx, "select", (size_t)k * pmax * 8 * MAXM + (size_t)nb * 8 + (size_t)n_models * 8 + 512);
   double* yh = (double*)w;
-  double* partial = yh + k * MAXM;
+  double* partial = yh + k * pmax * MAXM;
   double* d_mse = partial + nb;
   int32_t* d_best = (int32_t*)(d_mse + n_models);
   // models fitted together share their partitioning: route the points once
@@ -439,15 +450,16 @@ void run_select(krr_ctx ctx, hipStream_t s, const krr_model* models, int n_model
       ++nm;
     Routing R;
     if (route == KRR_ROUTE_NEAREST) R = route_points(ctx, s, *D, Xv, dtype, k, "_sel" + std::to_string(tag++));
+    const int pc = label ? D->p : 1;
     double* dst[MAXM];
-    for (int q = 0; q < nm; ++q) dst[q] = yh + (size_t)q * k;
-    predict_models(ctx, s, models + done, nm, Xv, dtype, k, route, R, dst);
+    for (int q = 0; q < nm; ++q) dst[q] = yh + (size_t)q * k * pc;
+    predict_models(ctx, s, models + done, nm, Xv, dtype, k, label ? (int)KRR_ROUTE_ALL : route, R, dst);
     for (int q = 0; q < nm; ++q) {
       if (dtype == KRR_F64)
-        hipLaunchKernelGGL((k_sqerr<double>), dim3((unsigned)nb), dim3(256), 0, s, (const double*)dst[q],
+        hipLaunchKernelGGL((k_sqerr<double>), dim3((unsigned)nb), dim3(256), 0, s, (const double*)dst[q], pc,
                            (const double*)yv, k, partial);
       else
-        hipLaunchKernelGGL((k_sqerr<float>), dim3((unsigned)nb), dim3(256), 0, s, (const double*)dst[q],
+        hipLaunchKernelGGL((k_sqerr<float>), dim3((unsigned)nb), dim3(256), 0, s, (const double*)dst[q], pc,
                            (const float*)yv, k, partial);
       check_launch(ctx, s, "sqerr");
       hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, s, (const double*)partial, nb, k, d_mse + done + q);

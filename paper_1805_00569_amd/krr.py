@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EBUDGET", -4: "ENOTSPD
 F32, F64 = 0, 1
 PART = {"kmeans": 0, "kbalance": 1, "given": 2, "random": 3}
 PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
-ROUTE = {"nearest": 0, "average": 1, "all": 2}
+ROUTE = {"nearest": 0, "average": 1, "all": 2, "label": 3}
 KERNEL = {"gaussian": 0, "linear": 1}
 OPT_PANEL_TILES, OPT_SERIAL_FIT, OPT_SYNC_CHECK, OPT_TIMING = 0, 1, 2, 3
 

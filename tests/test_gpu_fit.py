@@ -112,6 +112,35 @@ def test_dckrr_random_partition_average_route_fp64(ctx, dev):
     assert best == O.select(mo)
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_label_route_selection_is_the_lower_bound(ctx, dev, dtype):
+    """BKRR3 / KKRR3 (Algorithm 6): per held-out point the partition model
+    closest to its label.  The MSE matches the oracle's label choice, is at
+    most the NEAREST and AVERAGE MSEs, and predict() refuses the route (it
+    has no labels)."""
+    w = datagen.small(62, 2500, 5, k=300, p=5, comps=5, dtype=dtype)
+    print(f"label route n=2500 p=5 {dtype.__name__}", flush=True)
+    params = [krr.Params(sigma=s_, lam=1e-3, prec="fp64") for s_ in (0.6, 1.5, 3.0)]
+    models, info, st, oms, X, a = _fit_both(ctx, dev, w, 5, params, method="kbalance", iters=6, seed=4)
+    assert st == 0
+    Xv, yv = _t(w.Xt, dev), _t(w.yt.astype(dtype), dev)
+    yt = w.yt.astype(dtype).astype(np.float64)
+    mse_l, best_l = ctx.select(models, Xv, yv, route="label")
+    mse_n, _ = ctx.select(models, Xv, yv, route="nearest")
+    mse_a, _ = ctx.select(models, Xv, yv, route="average")
+    mo = []
+    for om in oms:
+        allp, _ = O.predict(om, w.Xt, "all")
+        chosen, _ = O.label_oracle_select(allp, yt)
+        mo.append(O.mse(chosen, yt))
+    np.testing.assert_allclose(mse_l, mo, rtol=1e-10)
+    assert best_l == O.select(mo)
+    assert all(l <= n_ * (1 + 1e-12) and l <= a_ * (1 + 1e-12) for l, n_, a_ in zip(mse_l, mse_n, mse_a))
+    with pytest.raises(krr.KrrError) as e:
+        ctx.predict(models[0], Xv, route="label")
+    assert e.value.status == krr.KRR_EINVAL
+
+
 def test_batch_invariance_serial_equals_batched(ctx, dev):
     """The plain per-system launch sequence gives bitwise the same alpha as
     the batched one."""
