@@ -748,6 +748,8 @@ constexpr int PC_LD = NB + 1;
 // system s on XCD s % 8 (slot b / 8 of that XCD), so that the operands a
 // system's workgroups share are fetched into one L2.  Grids hold
 // 8 * ceil(n_sys / 8) * (workgroups per system); the padding exits at once.
+// A batch of fewer than 8 systems would leave XCDs idle that way: it keeps
+// the plain order, a system's workgroups spread over all XCDs.
 constexpr int NXCD = 8;
 
 __device__ __forceinline__ void panel_col_tile(const SysDesc& D, int s, int i, int lane, float* __restrict__ A,
@@ -893,17 +895,25 @@ __global__ __launch_bounds__(256) void k_panel_col(const SysDesc* __restrict__ d
                                                    __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk, int K0, int k,
                                                    int Wp, int level, int do_pack, int diag_next, int n_sys, int ng,
                                                    double* __restrict__ zf) {
-  const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD, U = (n_sys + NXCD - 1) / NXCD;
-  int u, g;
-  if (slot < U) {
-    u = slot;
-    g = 0;
+  int s, g;
+  if (n_sys < NXCD) {
+    // fewer systems than XCDs: workgroups in turn over all XCDs (group 0 of every system first)
+    if ((int)blockIdx.x >= n_sys * ng) return;
+    g = blockIdx.x / n_sys;
+    s = blockIdx.x % n_sys;
   } else {
-    u = (slot - U) / (ng - 1);
-    g = 1 + (slot - U) % (ng - 1);
+    const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD, U = (n_sys + NXCD - 1) / NXCD;
+    int u;
+    if (slot < U) {
+      u = slot;
+      g = 0;
+    } else {
+      u = (slot - U) / (ng - 1);
+      g = 1 + (slot - U) % (ng - 1);
+    }
+    s = xcd + NXCD * u;
+    if (s >= n_sys) return;
   }
-  const int s = xcd + NXCD * u;
-  if (s >= n_sys) return;
   const SysDesc D = desc[s];
   if (st[s].status != 0 || D.level != level) return;
   // wave-uniform wave index: the tile bases stay in scalar registers
@@ -970,9 +980,17 @@ __global__ __launch_bounds__(256, 2) void k_packed_trailing(const SysDesc* __res
                                                          const __bf16* __restrict__ Pk, int K0, int ks0, int ks1,
                                                          int i0, int Wp, int level, int n_sys, int ntri) {
   // XCD placement (see NXCD): slot = system-major (system, super-tile)
-  const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
-  const int s = xcd + NXCD * (slot / ntri);
-  if (s >= n_sys) return;
+  int s, bxs;
+  if (n_sys < NXCD) {   // fewer systems than XCDs: workgroups in turn over all XCDs
+    if ((int)blockIdx.x >= n_sys * ntri) return;
+    s = blockIdx.x / ntri;
+    bxs = blockIdx.x % ntri;
+  } else {
+    const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
+    s = xcd + NXCD * (slot / ntri);
+    if (s >= n_sys) return;
+    bxs = slot % ntri;
+  }
   const SysDesc D = desc[s];
   if (st[s].status != 0 || D.level != level) return;
   const int T = D.T;
@@ -980,7 +998,7 @@ __global__ __launch_bounds__(256, 2) void k_packed_trailing(const SysDesc* __res
   if (R <= 0) return;
   const int NS = (R + 1) / 2;
   int I, J;
-  if (!trail_decode(slot % ntri, NS, I, J)) return;   // uniform: the whole workgroup leaves
+  if (!trail_decode(bxs, NS, I, J)) return;   // uniform: the whole workgroup leaves
   // the wave index as a wave-uniform value: tile and fragment bases stay in
   // scalar registers and the addresses need one per-lane offset each
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
