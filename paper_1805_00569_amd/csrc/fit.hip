@@ -16,8 +16,8 @@ int64_t pack_slot_elems(int T, int Wp);
 void trsv_forward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, const SysStatus* st, int n_sys,
                   const void* A, const void* Wt, const double* b, double* z, int skip_converged);
 void trsv_backward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, const SysStatus* st, int n_sys,
-                   int Tmax, const void* A, const void* Wt, const double* z, double* x, double* alpha_acc,
-                   int skip_converged);
+                   int Tmax, int64_t v_tot, const void* A, const void* Wt, const double* z, double* x,
+                   double* alpha_acc, int skip_converged);
 void residual_check(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, int n_sys, int p, int n_groups,
                     const int32_t* grp_first, const int32_t* grp_next, int Tmax, const double* K64,
                     const double* alpha, const double* y, double* r, double* P, const int64_t* p_off, double* rn,
@@ -448,7 +448,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
     if (!cholesky_factor(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, 0, mixed, desc.data(), pack,
                          mixed ? zb : nullptr))
       trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, rhs, zb, 0);
-    trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, zb, alpha, nullptr, 0);
+    trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, Tmax, v_tot, A, Wt, zb, alpha, nullptr, 0);
   } else {
     // plain per-system sequence: every system formed, factored and solved
     // by its own launches, one after another
@@ -458,7 +458,8 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
       cholesky_factor(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, desc[sidx].T, A, Wt, 0, mixed,
                       desc.data() + sidx, pack, nullptr);
       trsv_forward(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, A, Wt, rhs, zb, 0);
-      trsv_backward(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, desc[sidx].T, A, Wt, zb, alpha, nullptr, 0);
+      trsv_backward(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, desc[sidx].T, v_tot, A, Wt, zb, alpha, nullptr,
+                    0);
     }
   }
 
@@ -483,7 +484,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
         KRR_HIP(hipStreamSynchronize(s));
         if (*act_h == 0) break;
         trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, rb, zb, 1);
-        trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, zb, db, alpha, 1);
+        trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, Tmax, v_tot, A, Wt, zb, db, alpha, 1);
       }
     };
     refine();
@@ -507,7 +508,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
       check_launch(ctx, s, "restore_tiles");
       cholesky_factor(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, 1, false, desc.data(), pack, nullptr);
       trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, rhs, zb, 1);
-      trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, zb, alpha, nullptr, 1);
+      trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, Tmax, v_tot, A, Wt, zb, alpha, nullptr, 1);
       refine();
     }
   }

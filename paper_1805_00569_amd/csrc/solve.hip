@@ -152,51 +152,59 @@ __global__ __launch_bounds__(TRSV_THREADS) void k_trsv_fwd(const SysDesc* __rest
 
 // x = L^-T z (and alpha += x when `alpha_acc` is given), tile row i from the
 // last: u = z_i - sum_{j>i} L(j,i)^T x_j, then x_i = Winv(i)^T u.
-// Largest T whose solution vector the backward solve keeps in LDS.
+// Systems with T <= TRSV_XL_MAXT are solved whole by one workgroup each with x
+// in LDS.  Larger systems go band by band (TRSV_BAND tile rows, bands at
+// absolute multiples of TRSV_BAND, from the last): one workgroup per system
+// solves the band's rows against the band only, and k_trsv_bwd_upd then
+// subtracts the band's contribution from every tile row above it, one
+// workgroup per (tile row, system), into a working copy zw of z.  Which path a
+// system takes depends on its own T only, so results do not depend on the batch.
 constexpr int TRSV_XL_MAXT = 128;
+constexpr int TRSV_BAND = 16;
 
-// x = L^-T z, tile row by tile row from the last: u = z_i - sum_{j>i} L(j,i)^T x_j,
-// then x_i = Winv(i)^T u.  Winv(i) comes from LDS: groups 1..3 load the next
-// step's block into the other half of a double buffer while group 0 forms
-// x_i.  XL: x stays in LDS (T <= TRSV_XL_MAXT) and is written out at the end;
-// otherwise it is read back from global memory.  alpha_acc (nullable):
-// x is also added to it.
-template <typename TS, bool XL>
+// Tile rows [lo, hi) from the last: BAND = false, the whole system (lo = 0,
+// hi = T, right-hand side z); BAND = true, the band starting at i0 (right-hand
+// side z for the last band, else zw).  Winv(i) comes from LDS: groups 1..3 load
+// the next step's block into the other half of a double buffer while group 0
+// forms x_i; the rows' x stay in LDS and are written out at the end.
+template <typename TS, bool BAND>
 __global__ __launch_bounds__(TRSV_THREADS) void k_trsv_bwd(const SysDesc* __restrict__ desc,
                                                            const SysStatus* __restrict__ st,
                                                            const TS* __restrict__ A, const TS* __restrict__ Wt,
-                                                           const double* __restrict__ z, double* __restrict__ x,
-                                                           double* __restrict__ alpha_acc, int skip_converged) {
-  // tiles in flight per group: the FP64 x blocks take registers unless they come from LDS
-  constexpr int TRSV_JB = TrsvJB<TS>::value - (sizeof(TS) == 4 && !XL ? 1 : 0);
+                                                           const double* __restrict__ z,
+                                                           const double* __restrict__ zw, double* __restrict__ x,
+                                                           double* __restrict__ alpha_acc, int skip_converged,
+                                                           int i0) {
+  constexpr int TRSV_JB = TrsvJB<TS>::value;
   const int s = blockIdx.x;
   const SysDesc D = desc[s];
+  if (BAND ? (D.T <= TRSV_XL_MAXT || i0 >= D.T) : D.T > TRSV_XL_MAXT) return;
   if (skip_system(st[s], skip_converged)) return;
+  const int lo = BAND ? i0 : 0, hi = BAND ? min(i0 + TRSV_BAND, D.T) : D.T;
   __shared__ double sp[TRSV_G][NB];
   __shared__ double su[NB];
   extern __shared__ double dyn[];
   TS* sW = reinterpret_cast<TS*>(dyn);             // [2][TILE]
-  double* sx = dyn + (2 * TILE * sizeof(TS)) / 8;   // XL: [T * NB]
+  double* sx = dyn + (2 * TILE * sizeof(TS)) / 8;   // [(hi - lo) * NB]: x of rows lo ..
   const int t = threadIdx.x, grp = t >> 8, rq = t & 15, cg = (t >> 4) & 15;
   const TS* Ab = A + D.a_off;
-  const double* zz = z + D.v_off;
+  const double* zz = ((BAND && hi < D.T) ? zw : z) + D.v_off;
   double* xx = x + D.v_off;
-  const double* xs = XL ? sx : xx;
-  // Winv of the last tile row into buffer (T - 1) & 1
-  if (D.T > 0) {
-    const TS* W = Wt + D.w_off + (int64_t)(D.T - 1) * TILE;
+  // Winv of the last tile row into buffer (hi - 1) & 1
+  if (hi > lo) {
+    const TS* W = Wt + D.w_off + (int64_t)(hi - 1) * TILE;
     for (int e = 4 * t; e < TILE; e += 4 * TRSV_THREADS) {
       TS v[4];
       load4(W + e, v);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) sW[((D.T - 1) & 1) * TILE + e + k] = v[k];
+      for (int k = 0; k < 4; ++k) sW[((hi - 1) & 1) * TILE + e + k] = v[k];
     }
   }
   __syncthreads();
-  for (int i = D.T - 1; i >= 0; --i) {
+  for (int i = hi - 1; i >= lo; --i) {
     double part[4] = {0.0, 0.0, 0.0, 0.0};
     int j = i + 1 + grp;
-    for (; j + TRSV_G * (TRSV_JB - 1) < D.T; j += TRSV_G * TRSV_JB) {
+    for (; j + TRSV_G * (TRSV_JB - 1) < hi; j += TRSV_G * TRSV_JB) {
       TS lv[TRSV_JB][4][4];
       double xv[TRSV_JB][4];
 #pragma unroll
@@ -205,7 +213,7 @@ __global__ __launch_bounds__(TRSV_THREADS) void k_trsv_bwd(const SysDesc* __rest
 #pragma unroll
         for (int q = 0; q < 4; ++q) load4(L + (cg + 16 * q) * NB + 4 * rq, lv[u][q]);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) xv[u][k] = xs[(j + TRSV_G * u) * NB + 4 * rq + k];
+        for (int k = 0; k < 4; ++k) xv[u][k] = sx[(j + TRSV_G * u - lo) * NB + 4 * rq + k];
       }
 #pragma unroll
       for (int u = 0; u < TRSV_JB; ++u)
@@ -214,11 +222,11 @@ __global__ __launch_bounds__(TRSV_THREADS) void k_trsv_bwd(const SysDesc* __rest
 #pragma unroll
           for (int k = 0; k < 4; ++k) part[q] = fma((double)lv[u][q][k], xv[u][k], part[q]);
     }
-    for (; j < D.T; j += TRSV_G) {
+    for (; j < hi; j += TRSV_G) {
       const TS* L = Ab + tile_index(j, i) * TILE;
       double xv[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) xv[k] = xs[j * NB + 4 * rq + k];
+      for (int k = 0; k < 4; ++k) xv[k] = sx[(j - lo) * NB + 4 * rq + k];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         TS lv[4];
@@ -253,16 +261,9 @@ __global__ __launch_bounds__(TRSV_THREADS) void k_trsv_bwd(const SysDesc* __rest
 #pragma unroll
         for (int k = 0; k < 4; ++k) p = fma((double)W[c * NB + 4 * rq + k], ur[k], p);
         const double v = quad16_sum(p);
-        if (rq == 0) {
-          if (XL) {
-            sx[i * NB + c] = v;
-          } else {
-            xx[i * NB + c] = v;
-            if (alpha_acc != nullptr) alpha_acc[D.v_off + i * NB + c] += v;
-          }
-        }
+        if (rq == 0) sx[(i - lo) * NB + c] = v;
       }
-    } else if (i > 0) {
+    } else if (i > lo) {
       // the next step's Winv into the other buffer
       const TS* W = Wt + D.w_off + (int64_t)(i - 1) * TILE;
       for (int e = 4 * (t - 256); e < TILE; e += 4 * (TRSV_THREADS - 256)) {
@@ -274,12 +275,69 @@ __global__ __launch_bounds__(TRSV_THREADS) void k_trsv_bwd(const SysDesc* __rest
     }
     __syncthreads();
   }
-  if (XL) {
-    for (int e = t; e < D.T * NB; e += TRSV_THREADS) {
-      const double v = sx[e];
-      xx[e] = v;
-      if (alpha_acc != nullptr) alpha_acc[D.v_off + e] += v;
+  for (int e = t; e < (hi - lo) * NB; e += TRSV_THREADS) {
+    const double v = sx[e];
+    xx[lo * NB + e] = v;
+    if (alpha_acc != nullptr) alpha_acc[D.v_off + lo * NB + e] += v;
+  }
+}
+
+// Band update of the backward solve: for tile row i < i0 of a system on the
+// band path, zw_i = (z_i for the last band, else zw_i) - sum_{i0<=j<i1}
+// L(j,i)^T x_j.  One workgroup per (i, system); thread t owns rows
+// 4 (t & 15) .. +3 and columns (t >> 4) + 16 q of each tile; fixed order.
+template <typename TS>
+__global__ __launch_bounds__(256) void k_trsv_bwd_upd(const SysDesc* __restrict__ desc,
+                                                      const SysStatus* __restrict__ st, const TS* __restrict__ A,
+                                                      const double* __restrict__ z, double* __restrict__ zw,
+                                                      const double* __restrict__ x, int skip_converged, int i0) {
+  const int i = blockIdx.x, s = blockIdx.y;
+  const SysDesc D = desc[s];
+  if (D.T <= TRSV_XL_MAXT || i0 >= D.T || i >= i0) return;
+  if (skip_system(st[s], skip_converged)) return;
+  const int i1 = min(i0 + TRSV_BAND, D.T);
+  const int t = threadIdx.x, rq = t & 15, cg = t >> 4;
+  const TS* Ab = A + D.a_off;
+  const double* xx = x + D.v_off;
+  double part[4] = {0.0, 0.0, 0.0, 0.0};
+  int j = i0;
+  for (; j + 3 < i1; j += 4) {
+    TS lv[4][4][4];
+    double xv[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const TS* L = Ab + tile_index(j + u, i) * TILE;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) load4(L + (cg + 16 * q) * NB + 4 * rq, lv[u][q]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) xv[u][k] = xx[(j + u) * NB + 4 * rq + k];
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) part[q] = fma((double)lv[u][q][k], xv[u][k], part[q]);
+  }
+  for (; j < i1; ++j) {
+    const TS* L = Ab + tile_index(j, i) * TILE;
+    double xv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xv[k] = xx[j * NB + 4 * rq + k];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      TS lv[4];
+      load4(L + (cg + 16 * q) * NB + 4 * rq, lv);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) part[q] = fma((double)lv[k], xv[k], part[q]);
+    }
+  }
+  const double* src = (i1 == D.T ? z : zw) + D.v_off + (int64_t)i * NB;
+  double* dst = zw + D.v_off + (int64_t)i * NB;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double v = quad16_sum(part[q]);
+    if (rq == 0) dst[cg + 16 * q] = src[cg + 16 * q] - v;
   }
 }
 
@@ -444,28 +502,45 @@ void trsv_forward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, con
 }
 
 void trsv_backward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, const SysStatus* st, int n_sys,
-                   int Tmax, const void* A, const void* Wt, const double* z, double* x, double* alpha_acc,
-                   int skip_converged) {
+                   int Tmax, int64_t v_tot, const void* A, const void* Wt, const double* z, double* x,
+                   double* alpha_acc, int skip_converged) {
   KernelTimer kt(ctx, s, "trsv_backward", 0.0, 0);
-  const bool xl = Tmax <= TRSV_XL_MAXT;
   const size_t ts = prec == KRR_PREC_FP64 ? sizeof(double) : sizeof(float);
-  const size_t lds = 2 * TILE * ts + (xl ? (size_t)std::max(Tmax, 1) * NB * sizeof(double) : 0);
-  if (prec == KRR_PREC_FP64) {
-    if (xl)
-      hipLaunchKernelGGL((k_trsv_bwd<double, true>), dim3(n_sys), dim3(TRSV_THREADS), lds, s, desc, st,
-                         (const double*)A, (const double*)Wt, z, x, alpha_acc, skip_converged);
-    else
-      hipLaunchKernelGGL((k_trsv_bwd<double, false>), dim3(n_sys), dim3(TRSV_THREADS), lds, s, desc, st,
-                         (const double*)A, (const double*)Wt, z, x, alpha_acc, skip_converged);
-  } else {
-    if (xl)
-      hipLaunchKernelGGL((k_trsv_bwd<float, true>), dim3(n_sys), dim3(TRSV_THREADS), lds, s, desc, st,
-                         (const float*)A, (const float*)Wt, z, x, alpha_acc, skip_converged);
-    else
-      hipLaunchKernelGGL((k_trsv_bwd<float, false>), dim3(n_sys), dim3(TRSV_THREADS), lds, s, desc, st,
-                         (const float*)A, (const float*)Wt, z, x, alpha_acc, skip_converged);
-  }
+  const bool f64 = prec == KRR_PREC_FP64;
+  const size_t lds_xl = 2 * TILE * ts + (size_t)std::max(std::min(Tmax, TRSV_XL_MAXT), 1) * NB * sizeof(double);
+  if (f64)
+    hipLaunchKernelGGL((k_trsv_bwd<double, false>), dim3(n_sys), dim3(TRSV_THREADS), lds_xl, s, desc, st,
+                       (const double*)A, (const double*)Wt, z, (const double*)nullptr, x, alpha_acc, skip_converged,
+                       0);
+  else
+    hipLaunchKernelGGL((k_trsv_bwd<float, false>), dim3(n_sys), dim3(TRSV_THREADS), lds_xl, s, desc, st,
+                       (const float*)A, (const float*)Wt, z, (const double*)nullptr, x, alpha_acc, skip_converged,
+                       0);
   check_launch(ctx, s, "trsv_bwd");
+  if (Tmax <= TRSV_XL_MAXT) return;
+  // band path of the systems with T > TRSV_XL_MAXT
+  double* zw = (double*)ws_get(ctx, "trsv_zw", (size_t)std::max<int64_t>(v_tot, 1) * 8);
+  const size_t lds_band = 2 * TILE * ts + (size_t)TRSV_BAND * NB * sizeof(double);
+  for (int b = ceil_div(Tmax, TRSV_BAND) - 1; b >= 0; --b) {
+    const int i0 = b * TRSV_BAND;
+    if (f64)
+      hipLaunchKernelGGL((k_trsv_bwd<double, true>), dim3(n_sys), dim3(TRSV_THREADS), lds_band, s, desc, st,
+                         (const double*)A, (const double*)Wt, z, (const double*)zw, x, alpha_acc, skip_converged,
+                         i0);
+    else
+      hipLaunchKernelGGL((k_trsv_bwd<float, true>), dim3(n_sys), dim3(TRSV_THREADS), lds_band, s, desc, st,
+                         (const float*)A, (const float*)Wt, z, (const double*)zw, x, alpha_acc, skip_converged,
+                         i0);
+    check_launch(ctx, s, "trsv_bwd_band");
+    if (i0 == 0) break;
+    if (f64)
+      hipLaunchKernelGGL((k_trsv_bwd_upd<double>), dim3((unsigned)i0, (unsigned)n_sys), dim3(256), 0, s, desc, st,
+                         (const double*)A, z, zw, (const double*)x, skip_converged, i0);
+    else
+      hipLaunchKernelGGL((k_trsv_bwd_upd<float>), dim3((unsigned)i0, (unsigned)n_sys), dim3(256), 0, s, desc, st,
+                         (const float*)A, z, zw, (const double*)x, skip_converged, i0);
+    check_launch(ctx, s, "trsv_bwd_upd");
+  }
 }
 
 void residual_check(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, int n_sys, int p, int n_groups,

@@ -237,8 +237,8 @@ def _large_system():
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_large_system_backward_solve_from_global(ctx, dev, prec):
-    """One system of m = 8,300 (130 tile rows: the backward solve keeps its
-    solution in global memory rather than LDS) against the FP64 oracle."""
+    """One system of m = 8,300 (130 tile rows: the backward solve goes band
+    by band, with a ragged top band of 2 rows) against the FP64 oracle."""
     X, y, alpha_ref = _large_system()
     print(f"large system m={X.shape[0]} {prec}", flush=True)
     Xg = X.astype(np.float64) if prec == "fp64" else X
@@ -250,6 +250,34 @@ def test_large_system_backward_solve_from_global(ctx, dev, prec):
     assert st == 0 and info[0]["status"] == 0
     err = _rel(models[0].alpha(0).cpu().numpy(), alpha_ref)
     assert err < (1e-10 if prec == "fp64" else 1e-6), err
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_large_and_small_systems_in_one_batch(ctx, dev, prec):
+    """A batch holding a system of 130 tile rows (band-by-band backward
+    solve) and one of 11 (whole-system solve in LDS), two settings, with
+    refinement in mixed precision: every alpha against the FP64 oracle."""
+    X, y, alpha_ref = _large_system()
+    g = np.random.default_rng(86)
+    X2 = (g.uniform(-1.0, 1.0, size=(700, 4)) + 10.0).astype(np.float32)
+    y2 = (np.cos(X2.astype(np.float64).sum(axis=1)) + 0.1 * g.standard_normal(700)).astype(np.float32)
+    Xa, ya = np.concatenate([X, X2]), np.concatenate([y, y2])
+    print(f"large + small systems {prec}", flush=True)
+    Xg = Xa.astype(np.float64) if prec == "fp64" else Xa
+    yg = ya.astype(np.float64) if prec == "fp64" else ya
+    Xd = _t(Xg, dev)
+    C0 = np.array([[0.0] * 4, [10.0] * 4], Xg.dtype)
+    C, a, _ = ctx.partition(Xd, 2, "given", centroids=_t(C0, dev))
+    assert np.array_equal(a.cpu().numpy(), np.repeat([0, 1], [8300, 700]))
+    params = [krr.Params(sigma=0.5, lam=1e-2, prec=prec, refine_tol=1e-8, max_refine=40),
+              krr.Params(sigma=0.8, lam=1e-2, prec=prec, refine_tol=1e-8, max_refine=40)]
+    models, info, st = ctx.fit(Xd, _t(yg, dev), a, C, 2, params)
+    assert st == 0 and all(i["status"] == 0 for i in info)
+    tol = 1e-10 if prec == "fp64" else 1e-6
+    assert _rel(models[0].alpha(0).cpu().numpy(), alpha_ref) < tol
+    for q, sg in enumerate((0.5, 0.8)):
+        ref = O.fit_one(X2.astype(np.float64), y2.astype(np.float64), sg, 1e-2)["alpha"]
+        assert _rel(models[q].alpha(1).cpu().numpy(), ref) < tol, q
 
 
 def test_linear_kernel_is_primal_ridge(ctx, dev):
