@@ -14,7 +14,8 @@ bool cholesky_factor(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, 
                      void* A, void* Wt, int level, bool bf16, const SysDesc* hdesc, void* pack, double* zfwd);
 int64_t pack_slot_elems(int T, int Wp);
 void trsv_forward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, const SysStatus* st, int n_sys,
-                  const void* A, const void* Wt, const double* b, double* z, int skip_converged);
+                  int Tmax, int64_t v_tot, const void* A, const void* Wt, const double* b, double* z,
+                  int skip_converged);
 void trsv_backward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, const SysStatus* st, int n_sys,
                    int Tmax, int64_t v_tot, const void* A, const void* Wt, const double* z, double* x,
                    double* alpha_acc, int skip_converged);
@@ -447,7 +448,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
     if (mixed) KRR_HIP(hipMemcpyAsync(zb, rhs, vb, hipMemcpyDeviceToDevice, s));
     if (!cholesky_factor(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, 0, mixed, desc.data(), pack,
                          mixed ? zb : nullptr))
-      trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, rhs, zb, 0);
+      trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, Tmax, v_tot, A, Wt, rhs, zb, 0);
     trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, Tmax, v_tot, A, Wt, zb, alpha, nullptr, 0);
   } else {
     // plain per-system sequence: every system formed, factored and solved
@@ -457,7 +458,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
       form(d_desc + sidx, 1, 1, d_grp + n_groups + n_params, d_grp + n_groups + n_params + 1, desc[sidx].T);
       cholesky_factor(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, desc[sidx].T, A, Wt, 0, mixed,
                       desc.data() + sidx, pack, nullptr);
-      trsv_forward(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, A, Wt, rhs, zb, 0);
+      trsv_forward(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, desc[sidx].T, v_tot, A, Wt, rhs, zb, 0);
       trsv_backward(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, desc[sidx].T, v_tot, A, Wt, zb, alpha, nullptr,
                     0);
     }
@@ -483,7 +484,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
         KRR_HIP(hipMemcpyAsync(act_h, d_active, 4, hipMemcpyDeviceToHost, s));
         KRR_HIP(hipStreamSynchronize(s));
         if (*act_h == 0) break;
-        trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, rb, zb, 1);
+        trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, Tmax, v_tot, A, Wt, rb, zb, 1);
         trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, Tmax, v_tot, A, Wt, zb, db, alpha, 1);
       }
     };
@@ -507,7 +508,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
                          (const SysDesc*)d_desc, (const double*)K64, (float*)A, 1);
       check_launch(ctx, s, "restore_tiles");
       cholesky_factor(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, 1, false, desc.data(), pack, nullptr);
-      trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, A, Wt, rhs, zb, 1);
+      trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, Tmax, v_tot, A, Wt, rhs, zb, 1);
       trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, Tmax, v_tot, A, Wt, zb, alpha, nullptr, 1);
       refine();
     }

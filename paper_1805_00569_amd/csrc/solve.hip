@@ -63,28 +63,41 @@ __device__ __forceinline__ double quad16_sum(double v) {
   return v;
 }
 
-// z = L^-1 b, tile row by tile row: u = b_i - sum_{j<i} L(i,j) z_j, then
-// z_i = Winv(i) u.
-template <typename TS>
+// Systems with T <= TRSV_XL_MAXT are solved whole by one workgroup each;
+// larger ones band by band (TRSV_BAND tile rows at absolute multiples of
+// TRSV_BAND, from the first): one workgroup per system solves the band's rows
+// against the band, and k_trsv_fwd_upd subtracts the band's contribution from
+// every tile row below it into a working copy bw of b (the path depends on the
+// system's own T only).
+constexpr int TRSV_XL_MAXT = 128;
+constexpr int TRSV_BAND = 16;
+
+// z = L^-1 b over tile rows [lo, hi): u = b_i - sum_{lo<=j<i} L(i,j) z_j, then
+// z_i = Winv(i) u.  BAND = false: the whole system (lo = 0, hi = T); BAND =
+// true: the band starting at i0, right-hand side b for the first band, else bw.
+template <typename TS, bool BAND>
 __global__ __launch_bounds__(TRSV_THREADS) void k_trsv_fwd(const SysDesc* __restrict__ desc,
                                                            const SysStatus* __restrict__ st,
                                                            const TS* __restrict__ A, const TS* __restrict__ Wt,
-                                                           const double* __restrict__ b, double* __restrict__ z,
-                                                           int skip_converged) {
+                                                           const double* __restrict__ b,
+                                                           const double* __restrict__ bw, double* __restrict__ z,
+                                                           int skip_converged, int i0) {
   constexpr int TRSV_JB = TrsvJB<TS>::value;
   const int s = blockIdx.x;
   const SysDesc D = desc[s];
+  if (BAND ? (D.T <= TRSV_XL_MAXT || i0 >= D.T) : D.T > TRSV_XL_MAXT) return;
   if (skip_system(st[s], skip_converged)) return;
+  const int lo = BAND ? i0 : 0, hi = BAND ? min(i0 + TRSV_BAND, D.T) : D.T;
   __shared__ double sred[TRSV_G * 16][NB];
   __shared__ double sv[NB];
   const int t = threadIdx.x, grp = t >> 8, rq = t & 15, cg = (t >> 4) & 15;
   const TS* Ab = A + D.a_off;
-  const double* bb = b + D.v_off;
+  const double* bb = ((BAND && lo > 0) ? bw : b) + D.v_off;
   double* zz = z + D.v_off;
-  for (int i = 0; i < D.T; ++i) {
+  for (int i = lo; i < hi; ++i) {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const TS* row = Ab + tile_index(i, 0) * TILE;   // tiles (i, 0 .. i-1) are contiguous
-    int j = grp;
+    int j = lo + grp;
     for (; j + TRSV_G * (TRSV_JB - 1) < i; j += TRSV_G * TRSV_JB) {
       TS lv[TRSV_JB][4][4];
       double zv[TRSV_JB][4];
@@ -150,6 +163,60 @@ __global__ __launch_bounds__(TRSV_THREADS) void k_trsv_fwd(const SysDesc* __rest
   }
 }
 
+// Band update of the forward solve: for tile row i >= i0 + TRSV_BAND of a
+// system on the band path (i = i0 + TRSV_BAND + blockIdx.x), bw_i = (b_i for
+// the first band, else bw_i) - sum_{i0<=j<i1} L(i,j) z_j.  One workgroup per
+// (i, system); thread t owns rows 4 (t & 15) .. +3 and columns (t >> 4) + 16 q
+// of each tile; fixed order (over the lanes of a wave, then the four waves).
+template <typename TS>
+__global__ __launch_bounds__(256) void k_trsv_fwd_upd(const SysDesc* __restrict__ desc,
+                                                      const SysStatus* __restrict__ st, const TS* __restrict__ A,
+                                                      const double* __restrict__ b, double* __restrict__ bw,
+                                                      const double* __restrict__ z, int skip_converged, int i0) {
+  const int s = blockIdx.y;
+  const SysDesc D = desc[s];
+  const int i = i0 + TRSV_BAND + (int)blockIdx.x;
+  if (D.T <= TRSV_XL_MAXT || i >= D.T) return;
+  if (skip_system(st[s], skip_converged)) return;
+  const int i1 = i0 + TRSV_BAND;
+  __shared__ double sred[4][NB];
+  const int t = threadIdx.x, rq = t & 15, cg = t >> 4, w = t >> 6;
+  const TS* row = A + D.a_off + tile_index(i, 0) * TILE;
+  const double* zz = z + D.v_off;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int j = i0; j < i1; j += 4) {
+    TS lv[4][4][4];
+    double zv[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = cg + 16 * q;
+        load4(row + (int64_t)(j + u) * TILE + c * NB + 4 * rq, lv[u][q]);
+        zv[u][q] = zz[(j + u) * NB + c];
+      }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] = fma((double)lv[u][q][k], zv[u][q], acc[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double v = acc[k];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if ((t & 63) < 16) sred[w][4 * rq + k] = v;
+  }
+  __syncthreads();
+  if (t < NB) {
+    const double sum = (sred[0][t] + sred[1][t]) + (sred[2][t] + sred[3][t]);
+    const double src = (i0 == 0 ? b : bw)[D.v_off + (int64_t)i * NB + t];
+    bw[D.v_off + (int64_t)i * NB + t] = src - sum;
+  }
+}
+
 // x = L^-T z (and alpha += x when `alpha_acc` is given), tile row i from the
 // last: u = z_i - sum_{j>i} L(j,i)^T x_j, then x_i = Winv(i)^T u.
 // Systems with T <= TRSV_XL_MAXT are solved whole by one workgroup each with x
@@ -159,9 +226,6 @@ __global__ __launch_bounds__(TRSV_THREADS) void k_trsv_fwd(const SysDesc* __rest
 // subtracts the band's contribution from every tile row above it, one
 // workgroup per (tile row, system), into a working copy zw of z.  Which path a
 // system takes depends on its own T only, so results do not depend on the batch.
-constexpr int TRSV_XL_MAXT = 128;
-constexpr int TRSV_BAND = 16;
-
 // Tile rows [lo, hi) from the last: BAND = false, the whole system (lo = 0,
 // hi = T, right-hand side z); BAND = true, the band starting at i0 (right-hand
 // side z for the last band, else zw).  Winv(i) comes from LDS: groups 1..3 load
@@ -490,15 +554,38 @@ __global__ void k_ir_check(const SysDesc* __restrict__ desc, SysStatus* __restri
 }  // namespace
 
 void trsv_forward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, const SysStatus* st, int n_sys,
-                  const void* A, const void* Wt, const double* b, double* z, int skip_converged) {
+                  int Tmax, int64_t v_tot, const void* A, const void* Wt, const double* b, double* z,
+                  int skip_converged) {
   KernelTimer kt(ctx, s, "trsv_forward", 0.0, 0);
-  if (prec == KRR_PREC_FP64)
-    hipLaunchKernelGGL((k_trsv_fwd<double>), dim3(n_sys), dim3(TRSV_THREADS), 0, s, desc, st, (const double*)A,
-                       (const double*)Wt, b, z, skip_converged);
+  const bool f64 = prec == KRR_PREC_FP64;
+  if (f64)
+    hipLaunchKernelGGL((k_trsv_fwd<double, false>), dim3(n_sys), dim3(TRSV_THREADS), 0, s, desc, st,
+                       (const double*)A, (const double*)Wt, b, (const double*)nullptr, z, skip_converged, 0);
   else
-    hipLaunchKernelGGL((k_trsv_fwd<float>), dim3(n_sys), dim3(TRSV_THREADS), 0, s, desc, st, (const float*)A,
-                       (const float*)Wt, b, z, skip_converged);
+    hipLaunchKernelGGL((k_trsv_fwd<float, false>), dim3(n_sys), dim3(TRSV_THREADS), 0, s, desc, st,
+                       (const float*)A, (const float*)Wt, b, (const double*)nullptr, z, skip_converged, 0);
   check_launch(ctx, s, "trsv_fwd");
+  if (Tmax <= TRSV_XL_MAXT) return;
+  // band path of the systems with T > TRSV_XL_MAXT
+  double* bw = (double*)ws_get(ctx, "trsv_bw", (size_t)std::max<int64_t>(v_tot, 1) * 8);
+  for (int i0 = 0; i0 < Tmax; i0 += TRSV_BAND) {
+    if (f64)
+      hipLaunchKernelGGL((k_trsv_fwd<double, true>), dim3(n_sys), dim3(TRSV_THREADS), 0, s, desc, st,
+                         (const double*)A, (const double*)Wt, b, (const double*)bw, z, skip_converged, i0);
+    else
+      hipLaunchKernelGGL((k_trsv_fwd<float, true>), dim3(n_sys), dim3(TRSV_THREADS), 0, s, desc, st,
+                         (const float*)A, (const float*)Wt, b, (const double*)bw, z, skip_converged, i0);
+    check_launch(ctx, s, "trsv_fwd_band");
+    const int below = Tmax - (i0 + TRSV_BAND);
+    if (below <= 0) break;
+    if (f64)
+      hipLaunchKernelGGL((k_trsv_fwd_upd<double>), dim3((unsigned)below, (unsigned)n_sys), dim3(256), 0, s, desc,
+                         st, (const double*)A, b, bw, (const double*)z, skip_converged, i0);
+    else
+      hipLaunchKernelGGL((k_trsv_fwd_upd<float>), dim3((unsigned)below, (unsigned)n_sys), dim3(256), 0, s, desc,
+                         st, (const float*)A, b, bw, (const double*)z, skip_converged, i0);
+    check_launch(ctx, s, "trsv_fwd_upd");
+  }
 }
 
 void trsv_backward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, const SysStatus* st, int n_sys,
