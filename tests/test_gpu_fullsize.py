@@ -119,3 +119,35 @@ def test_ragged_kmeans_fp32_fullsize(ctx, dev):
     _check_predictions(ctx, dev, models[0], w.X, a_np, C_np, alphas, 2.0, w.Xt[:384],
                        np.linalg.norm(w.yt[:384]))
     models[0].free()
+
+
+@pytest.mark.parametrize("m,prec", [(32768, "mixed"), (12000, "fp64")])
+def test_single_large_system_fullsize(ctx, dev, m, prec):
+    """One system of the whole training set (p = 1, the exact KRR of
+    Algorithm 1 at a size where every solve goes band by band): m = 32,768
+    mixed with refinement (512 tile rows) and m = 12,000 FP64 (188 tile rows,
+    a ragged top band).  Checks: status and refinement residual, the residual
+    on sampled rows against direct-difference kernel values in FP64, and
+    predictions of sampled test points against Eq. 7 with the GPU's alpha."""
+    print(f"full size: one system m={m} {prec}", flush=True)
+    w = datagen.balanced(seed=2)
+    Xh = w.X[:m] if prec == "mixed" else w.X[:m].astype(np.float64)
+    yh = w.y[:m].astype(Xh.dtype)
+    X, y = _t(Xh, dev), _t(yh, dev)
+    C, a, sz = ctx.partition(X, 1, "given", centroids=_t(np.zeros((1, w.d), Xh.dtype), dev))
+    assert sz.item() == m
+    sigma, lam = 10.0, 0.1
+    prm = krr.Params(sigma=sigma, lam=lam, prec=prec, refine_tol=1e-6, max_refine=30)
+    models, info, st = ctx.fit(X, y, a, C, 1, [prm])
+    assert st == 0 and info[0]["status"] == 0
+    if prec == "mixed":
+        assert info[0]["rel_residual"] <= 1e-6
+    alpha = models[0].alpha(0).cpu().numpy()
+    Xj, yj = Xh.astype(np.float64), yh.astype(np.float64)
+    rows = np.random.default_rng(5).choice(m, 48, replace=False)
+    assert _sampled_residual(Xj, yj, alpha, sigma, lam, rows) < (2e-6 if prec == "mixed" else 1e-10)
+    Xt = w.Xt[:256].astype(Xh.dtype)
+    yhat = ctx.predict(models[0], _t(Xt, dev)).cpu().numpy()
+    yo = O.predict_one(Xj, alpha, Xt.astype(np.float64), sigma)
+    assert np.linalg.norm(yhat - yo) / max(np.linalg.norm(yo), 1e-3 * np.linalg.norm(w.yt[:256])) < 1e-10
+    models[0].free()
