@@ -10,7 +10,7 @@ Ridge Regression on Parallel and Distributed Systems" (ICS'18):
 
 * Section 2.3, Eqs. (6)-(7) and Algorithm 1: kernel matrix, the solve of
   (K + lambda I) alpha = y, prediction, MSE (Eq. 3).
-* Table 1: Gaussian and linear kernels.
+* Table 1: Gaussian, linear, polynomial and sigmoid kernels.
 * Section 2.4, Algorithm 2: K-means (assignment, change count, mean update).
 * Section 3.2, Algorithm 3 (DC-KRR): random even partition, averaged models.
 * Section 4.3, Algorithm 4: K-balance (capacity-constrained greedy pass in
@@ -323,12 +323,24 @@ def gather(a: np.ndarray, p: int):
 # ---------------------------------------------------------------------------
 
 def kernel_matrix(A, B, sigma, kernel="gaussian"):
-    """Table 1: Gaussian exp(-||a-b||^2 / (2 sigma^2)) by direct difference, or
-    linear a^T b."""
-    if kernel == "gaussian":
+    """Table 1: Gaussian exp(-||a-b||^2 / (2 sigma^2)) by direct difference;
+    linear a^T b; polynomial (a x^T y + r)^d given as ("polynomial", a, r, d)
+    with an integer d >= 1; sigmoid tanh(a x^T y + r) given as
+    ("sigmoid", a, r).  The sigmoid kernel is not positive semi-definite in
+    general, so K + lambda I may not be either (the solve then reports the
+    failing pivot)."""
+    name = kernel if isinstance(kernel, str) else kernel[0]
+    if name == "gaussian":
         return np.exp(-dist2(A, B) / (2.0 * sigma * sigma))
-    if kernel == "linear":
-        return np.asarray(A, np.float64) @ np.asarray(B, np.float64).T
+    G = np.asarray(A, np.float64) @ np.asarray(B, np.float64).T
+    if name == "linear":
+        return G
+    if name == "polynomial":
+        _, a, r, deg = kernel
+        return (a * G + r) ** int(deg)
+    if name == "sigmoid":
+        _, a, r = kernel
+        return np.tanh(a * G + r)
     raise ValueError(kernel)
 
 

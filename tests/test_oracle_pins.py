@@ -333,6 +333,34 @@ def test_gaussian_kernel_hand_values():
     assert np.all(np.diag(K) == 1.0)
 
 
+def test_polynomial_and_sigmoid_kernel_hand_values():
+    """Table 1's polynomial (a x^T y + r)^d and sigmoid tanh(a x^T y + r) on
+    hand-computed inner products (exact in binary: x.y = 1*3 + 2*(-1) = 1,
+    x.x = 5, y.y = 10)."""
+    X = np.array([[1.0, 2.0], [3.0, -1.0]])
+    P = O.kernel_matrix(X, X, 1.0, ("polynomial", 0.5, 1.0, 3))
+    assert P.tolist() == [[3.5 ** 3, 1.5 ** 3], [1.5 ** 3, 6.0 ** 3]]
+    S = O.kernel_matrix(X, X, 1.0, ("sigmoid", 0.25, -0.5))
+    np.testing.assert_allclose(S, np.tanh([[0.75, -0.25], [-0.25, 2.0]]), rtol=0, atol=1e-16)
+    # degree 1 with a = 1, r = 0 is the linear kernel
+    assert np.array_equal(O.kernel_matrix(X, X, 1.0, ("polynomial", 1.0, 0.0, 1)), O.kernel_matrix(X, X, 1.0, "linear"))
+
+
+def test_polynomial_kernel_is_psd_and_sigmoid_need_not_be():
+    """With a > 0 and r >= 0 the polynomial kernel matrix is positive
+    semi-definite (a sum of products of PSD Gram matrices); the sigmoid kernel
+    can have a negative eigenvalue, and the solve then reports a pivot."""
+    g = np.random.default_rng(7)
+    X = g.standard_normal((40, 3))
+    P = O.kernel_matrix(X, X, 1.0, ("polynomial", 0.3, 1.0, 4))
+    assert np.linalg.eigvalsh(P).min() > -1e-9 * np.abs(P).max()
+    X2 = np.array([[0.0, 0.0], [3.0, 0.0], [-3.0, 0.0]])
+    S = O.kernel_matrix(X2, X2, 1.0, ("sigmoid", 1.0, -1.0))
+    assert np.linalg.eigvalsh(S).min() < 0
+    r = O.fit_one(X2, np.ones(3), 1.0, 0.0, ("sigmoid", 1.0, -1.0))
+    assert r["status"] == O.STATUS_NOT_SPD and r["pivot"] == 1   # tanh(-1) < 0 on the diagonal
+
+
 def test_kernel_properties():
     g = np.random.default_rng(10)
     X = g.standard_normal((40, 5))
