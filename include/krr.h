@@ -87,8 +87,13 @@ typedef enum { KRR_PREC_FP64 = 0, KRR_PREC_FP32 = 1, KRR_PREC_MIXED = 2 } krr_pr
  * partitioned methods). */
 typedef enum { KRR_ROUTE_NEAREST = 0, KRR_ROUTE_AVERAGE = 1, KRR_ROUTE_ALL = 2, KRR_ROUTE_LABEL = 3 } krr_route;
 
-/* Table 1: Gaussian exp(-||a-b||^2 / (2 sigma^2)); linear a^T b. */
-typedef enum { KRR_KERNEL_GAUSSIAN = 0, KRR_KERNEL_LINEAR = 1 } krr_kernel;
+/* Table 1: Gaussian exp(-||a-b||^2 / (2 sigma^2)); linear a^T b; polynomial
+ * (kernel_a a^T b + kernel_r)^kernel_degree; sigmoid tanh(kernel_a a^T b +
+ * kernel_r).  The sigmoid kernel is not positive semi-definite in general: a
+ * system whose K + lambda I is not positive definite is reported as
+ * KRR_ENOTSPD with its failing pivot, like any other. */
+typedef enum { KRR_KERNEL_GAUSSIAN = 0, KRR_KERNEL_LINEAR = 1, KRR_KERNEL_POLYNOMIAL = 2,
+               KRR_KERNEL_SIGMOID = 3 } krr_kernel;
 
 typedef struct {
   double  sigma;          /* Gaussian width (> 0; ignored by the linear kernel) */
@@ -101,6 +106,10 @@ typedef struct {
   int32_t max_refine;     /* MIXED: at most this many refinement steps (0 = none) */
   int32_t lambda_times_m; /* 1: shift is lambda * m_j per partition (Algorithms 3, 5, 6);
                              0: shift is lambda (Eq. 6 with the 1/n folded in) */
+  double  kernel_a;       /* POLYNOMIAL, SIGMOID: scale a of the inner product (finite) */
+  double  kernel_r;       /* POLYNOMIAL, SIGMOID: offset r (finite) */
+  int32_t kernel_degree;  /* POLYNOMIAL: integer degree d in [1, 64] */
+  int32_t reserved;       /* 0 */
 } krr_fit_params;
 
 typedef struct {

@@ -322,8 +322,15 @@ krr_status krr_fit(krr_ctx ctx, hipStream_t stream, const void* X, const void* y
     KRR_REQUIRE((int64_t)n_params * p <= 65535, "n_params * p must be <= 65535 (systems per batch)");
     for (int q = 0; q < n_params; ++q) {
       const krr_fit_params& P = params[q];
-      KRR_REQUIRE(P.kernel == KRR_KERNEL_GAUSSIAN || P.kernel == KRR_KERNEL_LINEAR, "unknown kernel");
+      KRR_REQUIRE(P.kernel == KRR_KERNEL_GAUSSIAN || P.kernel == KRR_KERNEL_LINEAR ||
+                      P.kernel == KRR_KERNEL_POLYNOMIAL || P.kernel == KRR_KERNEL_SIGMOID,
+                  "unknown kernel");
       KRR_REQUIRE(P.kernel != KRR_KERNEL_GAUSSIAN || P.sigma > 0.0, "sigma must be > 0");
+      KRR_REQUIRE((P.kernel != KRR_KERNEL_POLYNOMIAL && P.kernel != KRR_KERNEL_SIGMOID) ||
+                      (std::isfinite(P.kernel_a) && std::isfinite(P.kernel_r)),
+                  "kernel_a and kernel_r must be finite");
+      KRR_REQUIRE(P.kernel != KRR_KERNEL_POLYNOMIAL || (P.kernel_degree >= 1 && P.kernel_degree <= 64),
+                  "kernel_degree must be in [1, 64]");
       KRR_REQUIRE(std::isfinite(P.lambda), "lambda must be finite");
       KRR_REQUIRE(P.prec == KRR_PREC_FP64 || P.prec == KRR_PREC_FP32 || P.prec == KRR_PREC_MIXED,
                   "unknown precision");

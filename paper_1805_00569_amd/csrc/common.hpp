@@ -49,6 +49,18 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// Table 1's polynomial and sigmoid kernels from the inner product g = x^T y:
+// (a g + r)^d by binary powering and tanh(a g + r); each operation rounded on
+// its own.
+__device__ __forceinline__ double poly_kernel(double g, double a, double r, int deg) {
+  double b = a * g + r, v = 1.0;
+  for (int e = deg; e > 0; e >>= 1) {
+    if (e & 1) v *= b;
+    b *= b;
+  }
+  return v;
+}
+
 // Per-system descriptor of one batched solve (K_s + lambda_s I) alpha_s = y_s.
 struct SysDesc {
   int32_t m;        // number of points in the partition
@@ -63,6 +75,9 @@ struct SysDesc {
   double lambda;       // diagonal shift actually used
   int32_t kernel;      // krr_kernel
   int32_t level;       // precision level that factors this system in the current pass
+  double ka, kr;       // polynomial / sigmoid: a and r of Table 1
+  int32_t kdeg;        // polynomial degree
+  int32_t pad_;
   int64_t pk_off;      // element offset of its BF16 panel-pack slot (mixed precision)
   int64_t k_off;       // mixed precision: element offset of the FP64 kernel tiles (without the
                        // shift) shared by the settings of this partition with the same kernel and sigma
@@ -188,6 +203,7 @@ void run_partition(krr_ctx ctx, hipStream_t s, const void* X, int dtype, int64_t
                    int64_t* sizes);
 
 // ---- fit.hip ----
+bool same_kernel_matrix(const krr_fit_params& a, const krr_fit_params& b);
 // Result of a fit that creates no model (one setting): alpha of partition j is
 // alpha[v_off[j], v_off[j] + m[j]) in the context's workspace, valid until the
 // next fit on the context.  The partition data then lives in the workspace

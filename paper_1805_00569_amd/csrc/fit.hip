@@ -45,9 +45,11 @@ __device__ __forceinline__ int64_t tile_index(int i, int j) { return (int64_t)i 
 // Settings are visited by group (grp_first[g], then grp_next[...]): the
 // kernel values are computed once per group and written to every setting of
 // the group with its own shift.
+// GENERAL: the batch has polynomial or sigmoid settings (without it the
+// code holds only the Gaussian and linear kernels, and fewer registers).
 // Four workgroups per CU (registers capped at 128): the exponentials and the
 // stores of one workgroup overlap the loads and MFMAs of the others.
-template <typename TX, int STORE>
+template <typename TX, int STORE, bool GENERAL>
 __global__ __launch_bounds__(256, 4) void k_form(const TX* __restrict__ Xg, int d, const SysDesc* __restrict__ desc,
                                               int p, int n_groups, const int32_t* __restrict__ grp_first,
                                               const int32_t* __restrict__ grp_next, void* __restrict__ Aout,
@@ -150,6 +152,8 @@ __global__ __launch_bounds__(256, 4) void k_form(const TX* __restrict__ Xg, int 
           if (gr >= m || gc >= m) k = (gr == gc) ? 1.0 : 0.0;
           else if (Dg.kernel == KRR_KERNEL_GAUSSIAN)
             k = (gr == gc) ? 1.0 : exp(fmax(0.0, (sNi[r] + sNj[c]) - 2.0 * G) * Dg.neg_inv_2s2);
+          else if (GENERAL && Dg.kernel == KRR_KERNEL_POLYNOMIAL) k = poly_kernel(G, Dg.ka, Dg.kr, Dg.kdeg);
+          else if (GENERAL && Dg.kernel == KRR_KERNEL_SIGMOID) k = tanh(Dg.ka * G + Dg.kr);
           else k = G;
           kv[cb][rb][v] = k;
           if (STORE == 2) K64[Dg.k_off + toff + c * NB + r] = k;
@@ -244,27 +248,50 @@ __global__ void k_zero_i32(int32_t* a, int n) {
   if (i < n) a[i] = 0;
 }
 
+template <typename TX, bool GENERAL>
+void launch_form_k(hipStream_t s, int prec, dim3 grid, const TX* X, int d, const SysDesc* desc, int p, int n_groups,
+                   const int32_t* grp_first, const int32_t* grp_next, void* A, double* K64) {
+  if (prec == KRR_PREC_FP64)
+    hipLaunchKernelGGL((k_form<TX, 0, GENERAL>), grid, dim3(256), 0, s, X, d, desc, p, n_groups, grp_first,
+                       grp_next, A, K64);
+  else if (prec == KRR_PREC_FP32)
+    hipLaunchKernelGGL((k_form<TX, 1, GENERAL>), grid, dim3(256), 0, s, X, d, desc, p, n_groups, grp_first,
+                       grp_next, A, K64);
+  else
+    hipLaunchKernelGGL((k_form<TX, 2, GENERAL>), grid, dim3(256), 0, s, X, d, desc, p, n_groups, grp_first,
+                       grp_next, A, K64);
+}
+
 template <typename TX>
 void launch_form(krr_ctx ctx, hipStream_t s, int prec, const void* Xg, int d, const SysDesc* desc, int p,
-                 int n_groups, const int32_t* grp_first, const int32_t* grp_next, int Tmax, void* A, double* K64) {
+                 int n_groups, const int32_t* grp_first, const int32_t* grp_next, int Tmax, void* A, double* K64,
+                 bool general) {
   const int64_t ntri = (int64_t)Tmax * (Tmax + 1) / 2;
   if (ntri == 0) return;
   const dim3 grid((unsigned)ntri, (unsigned)p);
   const TX* X = (const TX*)Xg;
   KernelTimer kt(ctx, s, "form_kernel", 0.0, 0);
-  if (prec == KRR_PREC_FP64)
-    hipLaunchKernelGGL((k_form<TX, 0>), grid, dim3(256), 0, s, X, d, desc, p, n_groups, grp_first, grp_next, A,
-                       K64);
-  else if (prec == KRR_PREC_FP32)
-    hipLaunchKernelGGL((k_form<TX, 1>), grid, dim3(256), 0, s, X, d, desc, p, n_groups, grp_first, grp_next, A,
-                       K64);
+  if (general)
+    launch_form_k<TX, true>(s, prec, grid, X, d, desc, p, n_groups, grp_first, grp_next, A, K64);
   else
-    hipLaunchKernelGGL((k_form<TX, 2>), grid, dim3(256), 0, s, X, d, desc, p, n_groups, grp_first, grp_next, A,
-                       K64);
+    launch_form_k<TX, false>(s, prec, grid, X, d, desc, p, n_groups, grp_first, grp_next, A, K64);
   check_launch(ctx, s, "form");
 }
 
 }  // namespace
+
+// Settings whose kernel matrices are equal: the same kernel with the same
+// sigma (Gaussian) or a, r, d (polynomial; a, r for the sigmoid).
+bool same_kernel_matrix(const krr_fit_params& a, const krr_fit_params& b) {
+  if (a.kernel != b.kernel) return false;
+  switch (a.kernel) {
+    case KRR_KERNEL_GAUSSIAN: return a.sigma == b.sigma;
+    case KRR_KERNEL_POLYNOMIAL:
+      return a.kernel_a == b.kernel_a && a.kernel_r == b.kernel_r && a.kernel_degree == b.kernel_degree;
+    case KRR_KERNEL_SIGMOID: return a.kernel_a == b.kernel_a && a.kernel_r == b.kernel_r;
+    default: return true;
+  }
+}
 
 void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype, int64_t n, int d,
              const int32_t* assign, const double* centroids, int p, const krr_fit_params* params, int n_params,
@@ -317,13 +344,14 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
   std::vector<int64_t> p_off(n_sys), n_off(n_sys);
   int64_t a_tot = 0, w_tot = 0, v_tot = 0, p_tot = 0, n_tot = 0, pk_tot = 0;
   // mixed precision: FP64 kernel tiles per (partition, group of settings with
-  // the same kernel and sigma); grp_first / grp_next list each group's settings
+  // the same kernel matrix: same kernel and sigma, or a, r, d); grp_first /
+  // grp_next list each group's settings
   std::vector<int32_t> grp_of(n_params), grp_first, grp_next(n_params, -1);
   for (int q = 0; q < n_params; ++q) {
     int g = -1;
     for (int h = 0; h < (int)grp_first.size() && g < 0; ++h) {
       const krr_fit_params& P0 = params[grp_first[h]];
-      if (P0.kernel == params[q].kernel && (P0.kernel == KRR_KERNEL_LINEAR || P0.sigma == params[q].sigma)) g = h;
+      if (same_kernel_matrix(P0, params[q])) g = h;
     }
     if (g < 0) {
       g = (int)grp_first.size();
@@ -359,6 +387,10 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
       D.neg_inv_2s2 = -1.0 / (2.0 * params[q].sigma * params[q].sigma);
       D.lambda = params[q].lambda_times_m ? params[q].lambda * (double)m : params[q].lambda;
       D.kernel = params[q].kernel;
+      D.ka = params[q].kernel_a;
+      D.kr = params[q].kernel_r;
+      D.kdeg = params[q].kernel_degree;
+      D.pad_ = 0;
       D.level = 0;
       D.pk_off = pk_tot;
       pk_tot += (prec == KRR_PREC_MIXED) ? pack_slot_elems(D.T, ctx->panel_tiles) : 0;
@@ -436,11 +468,14 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
   }
 
   // 6-8. form, factor, solve
+  bool general = false;   // polynomial or sigmoid settings in the batch
+  for (int q = 0; q < n_params; ++q)
+    general |= params[q].kernel == KRR_KERNEL_POLYNOMIAL || params[q].kernel == KRR_KERNEL_SIGMOID;
   auto form = [&](const SysDesc* dd, int pp, int ng, const int32_t* gf, const int32_t* gn, int tmax) {
     if (dtype == KRR_F64)
-      launch_form<double>(ctx, s, prec, data->X, d, dd, pp, ng, gf, gn, tmax, A, K64);
+      launch_form<double>(ctx, s, prec, data->X, d, dd, pp, ng, gf, gn, tmax, A, K64, general);
     else
-      launch_form<float>(ctx, s, prec, data->X, d, dd, pp, ng, gf, gn, tmax, A, K64);
+      launch_form<float>(ctx, s, prec, data->X, d, dd, pp, ng, gf, gn, tmax, A, K64, general);
   };
   if (!ctx->serial_fit) {
     form(d_desc, p, n_groups, d_grp, d_grp + n_groups, Tmax);

@@ -36,14 +36,19 @@ struct PredModels {
   const double* alpha[MAXM];
   const int64_t* voff[MAXM];
   double* out[MAXM];
-  double negu[MAXM];   // the distinct -1/(2 sigma^2) of the models (nu of them)
-  int uidx[MAXM];      // model q uses negu[uidx[q]]: the kernel values are shared
+  double negu[MAXM];   // the distinct kernel settings of the models (nu of them):
+  double ka[MAXM];     //   Gaussian -1/(2 sigma^2); polynomial / sigmoid a, r, d
+  double kr[MAXM];
+  int kdeg[MAXM];
+  int uidx[MAXM];      // model q uses setting uidx[q]: the kernel values are shared
+  int uidx_first[MAXM];   // host bookkeeping: first model of each setting
   int nu;
   int nm;
   int kernel;
 };
 
-template <typename TX>
+// KER: the call's kernel (Table 1), fixed at compile time.
+template <typename TX, int KER>
 __global__ __launch_bounds__(256, 2) void k_predict(const TX* __restrict__ Xt, int d, int64_t k,
                                                  const int32_t* __restrict__ tperm,
                                                  const int64_t* __restrict__ toff,
@@ -209,7 +214,11 @@ __global__ __launch_bounds__(256, 2) void k_predict(const TX* __restrict__ Xt, i
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const int el = 8 * h + e;
-          kv[e] = M.kernel == KRR_KERNEL_GAUSSIAN ? exp(d2[el] * M.negu[u]) : acc[el >> 2][el & 3];
+          const double G = acc[el >> 2][el & 3];
+          if constexpr (KER == KRR_KERNEL_GAUSSIAN) kv[e] = exp(d2[el] * M.negu[u]);
+          else if constexpr (KER == KRR_KERNEL_POLYNOMIAL) kv[e] = poly_kernel(G, M.ka[u], M.kr[u], M.kdeg[u]);
+          else if constexpr (KER == KRR_KERNEL_SIGMOID) kv[e] = tanh(M.ka[u] * G + M.kr[u]);
+          else kv[e] = G;
         }
 #pragma unroll
         for (int q = 0; q < MAXM; ++q) {
@@ -357,10 +366,18 @@ void predict_group(krr_ctx ctx, hipStream_t s, const krr_model* models, int nm, 
   for (int q = 0; q < nm; ++q) {
     M.alpha[q] = models[q]->alpha;
     M.voff[q] = models[q]->d_voff;
-    const double ng = -1.0 / (2.0 * models[q]->params.sigma * models[q]->params.sigma);
+    const krr_fit_params& P = models[q]->params;
+    const double ng = -1.0 / (2.0 * P.sigma * P.sigma);
     int u = 0;
-    while (u < M.nu && M.negu[u] != ng) ++u;
-    if (u == M.nu) M.negu[M.nu++] = ng;
+    while (u < M.nu && !same_kernel_matrix(models[M.uidx_first[u]]->params, P)) ++u;
+    if (u == M.nu) {
+      M.negu[u] = ng;
+      M.ka[u] = P.kernel_a;
+      M.kr[u] = P.kernel_r;
+      M.kdeg[u] = P.kernel_degree;
+      M.uidx_first[u] = q;
+      ++M.nu;
+    }
     M.uidx[q] = u;
     M.out[q] = dst[q];
     KRR_REQUIRE(models[q]->params.kernel == M.kernel, "models of one call must share the kernel");
@@ -377,16 +394,30 @@ void predict_group(krr_ctx ctx, hipStream_t s, const krr_model* models, int nm, 
     KernelTimer kt(ctx, s, "predict", 0.0, 0);
     const dim3 grid = (route == KRR_ROUTE_NEAREST) ? dim3((unsigned)base, 1, (unsigned)nsplit)
                                                    : dim3((unsigned)ceil_div(k, NB), (unsigned)p, (unsigned)nsplit);
-    if (dtype == KRR_F64)
-      hipLaunchKernelGGL((k_predict<double>), grid, dim3(256), 0, s, (const double*)Xt, D.d, k,
-                         (const int32_t*)R.tperm, (const int64_t*)R.toff, (const int32_t*)R.tile_start,
-                         route == KRR_ROUTE_NEAREST ? route : (int)KRR_ROUTE_ALL, (const double*)D.X,
-                         (const int64_t*)D.d_offsets, M, p, cps, npos, part);
-    else
-      hipLaunchKernelGGL((k_predict<float>), grid, dim3(256), 0, s, (const float*)Xt, D.d, k,
-                         (const int32_t*)R.tperm, (const int64_t*)R.toff, (const int32_t*)R.tile_start,
-                         route == KRR_ROUTE_NEAREST ? route : (int)KRR_ROUTE_ALL, (const float*)D.X,
-                         (const int64_t*)D.d_offsets, M, p, cps, npos, part);
+    const int rt = route == KRR_ROUTE_NEAREST ? route : (int)KRR_ROUTE_ALL;
+    auto launch = [&](auto kern, const auto* Xtp, const auto* Xtr) {
+      hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, Xtp, D.d, k, (const int32_t*)R.tperm, (const int64_t*)R.toff,
+                         (const int32_t*)R.tile_start, rt, Xtr, (const int64_t*)D.d_offsets, M, p, cps, npos, part);
+    };
+    if (dtype == KRR_F64) {
+      const double* Xtp = (const double*)Xt;
+      const double* Xtr = (const double*)D.X;
+      switch (M.kernel) {
+        case KRR_KERNEL_GAUSSIAN: launch(k_predict<double, KRR_KERNEL_GAUSSIAN>, Xtp, Xtr); break;
+        case KRR_KERNEL_POLYNOMIAL: launch(k_predict<double, KRR_KERNEL_POLYNOMIAL>, Xtp, Xtr); break;
+        case KRR_KERNEL_SIGMOID: launch(k_predict<double, KRR_KERNEL_SIGMOID>, Xtp, Xtr); break;
+        default: launch(k_predict<double, KRR_KERNEL_LINEAR>, Xtp, Xtr); break;
+      }
+    } else {
+      const float* Xtp = (const float*)Xt;
+      const float* Xtr = (const float*)D.X;
+      switch (M.kernel) {
+        case KRR_KERNEL_GAUSSIAN: launch(k_predict<float, KRR_KERNEL_GAUSSIAN>, Xtp, Xtr); break;
+        case KRR_KERNEL_POLYNOMIAL: launch(k_predict<float, KRR_KERNEL_POLYNOMIAL>, Xtp, Xtr); break;
+        case KRR_KERNEL_SIGMOID: launch(k_predict<float, KRR_KERNEL_SIGMOID>, Xtp, Xtr); break;
+        default: launch(k_predict<float, KRR_KERNEL_LINEAR>, Xtp, Xtr); break;
+      }
+    }
     check_launch(ctx, s, "predict");
   }
   hipLaunchKernelGGL(k_predict_reduce, dim3((unsigned)ceil_div(npos * nm, 256)), dim3(256), 0, s,

@@ -86,7 +86,8 @@ double percentile(std::vector<double> v, double q) {
 
 bool same_setting(const krr_fit_params& a, const krr_fit_params& b) {
   return a.sigma == b.sigma && a.lambda == b.lambda && a.kernel == b.kernel && a.prec == b.prec &&
-         a.refine_tol == b.refine_tol && a.max_refine == b.max_refine && a.lambda_times_m == b.lambda_times_m;
+         a.refine_tol == b.refine_tol && a.max_refine == b.max_refine && a.lambda_times_m == b.lambda_times_m &&
+         a.kernel_a == b.kernel_a && a.kernel_r == b.kernel_r && a.kernel_degree == b.kernel_degree;
 }
 
 }  // namespace
@@ -430,8 +431,11 @@ krr_status krr_server_submit_fit(krr_server S, const float* X, const float* y, i
     return KRR_EINVAL;
   }
   const krr_fit_params& P = *params;
-  if ((P.kernel != KRR_KERNEL_GAUSSIAN && P.kernel != KRR_KERNEL_LINEAR) ||
+  const bool ar = P.kernel == KRR_KERNEL_POLYNOMIAL || P.kernel == KRR_KERNEL_SIGMOID;
+  if ((P.kernel != KRR_KERNEL_GAUSSIAN && P.kernel != KRR_KERNEL_LINEAR && !ar) ||
       (P.kernel == KRR_KERNEL_GAUSSIAN && !(P.sigma > 0.0)) || !std::isfinite(P.lambda) ||
+      (ar && !(std::isfinite(P.kernel_a) && std::isfinite(P.kernel_r))) ||
+      (P.kernel == KRR_KERNEL_POLYNOMIAL && (P.kernel_degree < 1 || P.kernel_degree > 64)) ||
       (P.prec != KRR_PREC_FP64 && P.prec != KRR_PREC_FP32 && P.prec != KRR_PREC_MIXED) || P.max_refine < 0 ||
       P.max_refine > 1000) {
     set_error(S, "fit: bad settings");

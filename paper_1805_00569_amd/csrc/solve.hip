@@ -2,11 +2,14 @@
 // Eq. 6 solved by Cholesky), and the FP64 residual r = y - (K + lambda I) alpha
 // that drives iterative refinement in mixed precision.
 //
-// One workgroup per system walks its tile rows in order.  A tile row's
+// One workgroup per system walks its tile rows in order (systems of more than
+// TRSV_XL_MAXT tile rows: band by band, with the contributions of a solved
+// band to the other rows spread over many workgroups).  A tile row's
 // off-diagonal part is a GEMV over tiles already solved; the diagonal block is
 // applied through the inverse Winv(i) = L(i,i)^-1 kept by the factorisation,
 // so the whole solve is a sequence of dense tile GEMVs.  All sums run in a
-// fixed order: results do not depend on the launch or on the batch.
+// fixed order that depends on the system alone: results do not depend on the
+// launch or on the batch.
 #include "common.hpp"
 
 namespace krr {

@@ -24,7 +24,7 @@ F32, F64 = 0, 1
 PART = {"kmeans": 0, "kbalance": 1, "given": 2, "random": 3}
 PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
 ROUTE = {"nearest": 0, "average": 1, "all": 2, "label": 3}
-KERNEL = {"gaussian": 0, "linear": 1}
+KERNEL = {"gaussian": 0, "linear": 1, "polynomial": 2, "sigmoid": 3}
 OPT_PANEL_TILES, OPT_SERIAL_FIT, OPT_SYNC_CHECK, OPT_TIMING = 0, 1, 2, 3
 
 
@@ -37,7 +37,8 @@ class KrrError(RuntimeError):
 class FitParams(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_double), ("lambda_", ctypes.c_double), ("kernel", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("refine_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
-                ("lambda_times_m", ctypes.c_int32)]
+                ("lambda_times_m", ctypes.c_int32), ("kernel_a", ctypes.c_double), ("kernel_r", ctypes.c_double),
+                ("kernel_degree", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PartInfo(ctypes.Structure):
@@ -145,10 +146,14 @@ class Params:
     refine_tol: float = 1e-6
     max_refine: int = 30
     lambda_times_m: bool = False
+    kernel_a: float = 1.0      # polynomial / sigmoid: (a x^T y + r)^d, tanh(a x^T y + r)
+    kernel_r: float = 1.0
+    kernel_degree: int = 2
 
     def to_c(self):
         return FitParams(float(self.sigma), float(self.lam), KERNEL[self.kernel], PREC[self.prec],
-                         float(self.refine_tol), int(self.max_refine), int(bool(self.lambda_times_m)))
+                         float(self.refine_tol), int(self.max_refine), int(bool(self.lambda_times_m)),
+                         float(self.kernel_a), float(self.kernel_r), int(self.kernel_degree), 0)
 
 
 class Model:

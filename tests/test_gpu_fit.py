@@ -141,6 +141,66 @@ def test_label_route_selection_is_the_lower_bound(ctx, dev, dtype):
     assert e.value.status == krr.KRR_EINVAL
 
 
+def _okernel(q):
+    """The oracle's description of a setting's kernel (Table 1)."""
+    if q.kernel == "polynomial":
+        return ("polynomial", q.kernel_a, q.kernel_r, q.kernel_degree)
+    if q.kernel == "sigmoid":
+        return ("sigmoid", q.kernel_a, q.kernel_r)
+    return q.kernel
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_polynomial_sigmoid_and_gaussian_settings_in_one_batch(ctx, dev, prec):
+    """Table 1's polynomial and sigmoid kernels beside the Gaussian in one
+    batch (two polynomial settings share their kernel matrix): alpha,
+    nearest-centre predictions and selection against the oracle."""
+    w = datagen.small(63, 1800, 5, k=160, p=3, comps=3, dtype=np.float64, spread=1.0)
+    print(f"kernels poly/sigmoid/gaussian {prec}", flush=True)
+    params = [krr.Params(sigma=1.5, lam=1e-2, prec=prec, refine_tol=1e-10, max_refine=40),
+              krr.Params(kernel="polynomial", kernel_a=0.1, kernel_r=1.0, kernel_degree=3, lam=1e-2, prec=prec,
+                         refine_tol=1e-10, max_refine=40),
+              krr.Params(kernel="polynomial", kernel_a=0.1, kernel_r=1.0, kernel_degree=3, lam=1e-1, prec=prec,
+                         refine_tol=1e-10, max_refine=40),
+              krr.Params(kernel="sigmoid", kernel_a=0.02, kernel_r=0.3, lam=1.0, prec=prec, refine_tol=1e-10,
+                         max_refine=40)]
+    X, y = _t(w.X, dev), _t(w.y, dev)
+    C, a, _ = ctx.partition(X, 3, "kbalance", lloyd_iters=5, seed=3)
+    models, info, st = ctx.fit(X, y, a, C, 3, params)
+    assert st == 0 and all(i["status"] == 0 for i in info)
+    a_np, C_np = a.cpu().numpy(), C.cpu().numpy()
+    oms = [O.fit(w.X, w.y, a_np, C_np, 3, q.sigma, q.lam, _okernel(q)) for q in params]
+    tol = 1e-10 if prec == "fp64" else 1e-6
+    for q in range(len(params)):
+        for j in range(3):
+            assert _rel(models[q].alpha(j).cpu().numpy(), oms[q].alphas[j]) < tol, (q, j)
+        yhat = ctx.predict(models[q], _t(w.Xt, dev)).cpu().numpy()
+        yo, _ = O.predict(oms[q], w.Xt)
+        assert _pred_rel(yhat, yo, w.yt) < 10 * tol, q
+    mse, best = ctx.select(models, _t(w.Xt, dev), _t(w.yt, dev))
+    mo = [O.mse(O.predict(om, w.Xt)[0], w.yt) for om in oms]
+    np.testing.assert_allclose(mse, mo, rtol=10 * tol)
+
+
+def test_sigmoid_not_spd_reports_pivot(ctx, dev):
+    """tanh(a x^T y + r) with r < 0 puts a negative value on the diagonal of
+    the first point (x = 0): not positive definite at pivot 1, as the
+    oracle's LAPACK-style check says; kernel arguments are validated."""
+    X = np.array([[0.0, 0.0], [3.0, 0.0], [-3.0, 0.0]] * 30)
+    y = np.linspace(-1.0, 1.0, X.shape[0])
+    r = O.fit_one(X, y, 1.0, 0.0, ("sigmoid", 1.0, -1.0))
+    assert r["status"] == O.STATUS_NOT_SPD and r["pivot"] == 1
+    Xd = _t(X, dev)
+    C, a, _ = ctx.partition(Xd, 1, "given", centroids=_t(np.zeros((1, 2)), dev))
+    models, info, st = ctx.fit(Xd, _t(y, dev), a, C, 1,
+                               [krr.Params(kernel="sigmoid", kernel_a=1.0, kernel_r=-1.0, lam=0.0, prec="fp64")])
+    assert st == krr.KRR_ENOTSPD and info[0]["failed_pivot"] == 1
+    for bad in (dict(kernel_degree=0), dict(kernel_degree=65), dict(kernel_a=float("inf"))):
+        with pytest.raises(krr.KrrError) as e:
+            ctx.fit(Xd, _t(y, dev), a, C, 1, [krr.Params(kernel="polynomial", prec="fp64", **bad)])
+        assert e.value.status == krr.KRR_EINVAL
+
+
 def test_batch_invariance_serial_equals_batched(ctx, dev):
     """The plain per-system launch sequence gives bitwise the same alpha as
     the batched one."""
