@@ -392,10 +392,13 @@ __global__ __launch_bounds__(MEANS_THREADS) void k_means_partial(const TX* __res
   }
 }
 
+// C_j = (sum of the member-block partials in order) / count_j, for partition
+// j = blockIdx.x; CT (nullable) receives the same values transposed (d x p),
+// so the next assignment pass needs no transpose of its own.
 __global__ __launch_bounds__(MEANS_THREADS) void k_means_total(const double* __restrict__ part, int d,
                                                                const int64_t* __restrict__ offsets,
                                                                const int32_t* __restrict__ boff,
-                                                               double* __restrict__ C,
+                                                               double* __restrict__ C, double* __restrict__ CT,
                                                                const int32_t* __restrict__ skip,
                                                                const int32_t* __restrict__ delta,
                                                                int32_t* __restrict__ done_next) {
@@ -410,7 +413,9 @@ __global__ __launch_bounds__(MEANS_THREADS) void k_means_total(const double* __r
   for (int f = threadIdx.x; f < d; f += MEANS_THREADS) {
     double acc = 0.0;
     for (int b = b0; b < b1; ++b) acc = add_sep(acc, part[(int64_t)b * d + f]);
-    C[(int64_t)j * d + f] = acc / (double)cnt;
+    const double v = acc / (double)cnt;
+    C[(int64_t)j * d + f] = v;
+    if (CT != nullptr) CT[(int64_t)f * gridDim.x + j] = v;
   }
 }
 
@@ -964,7 +969,7 @@ void assign_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, const d
 
 template <typename TX>
 void means_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, const int32_t* perm, const int64_t* offsets,
-             double* C, int p, const int32_t* skip, const int32_t* delta, int32_t* done_next) {
+             double* C, double* CT, int p, const int32_t* skip, const int32_t* delta, int32_t* done_next) {
   KernelTimer kt(ctx, s, "lloyd_means", 0.0, 0);
   const int64_t max_blocks = ceil_div(n, MEANS_BLOCK) + p;   // sum over partitions of ceil(m_j / MEANS_BLOCK)
   char* w = (char*)ws_get(ctx, "means", (size_t)max_blocks * d * 8 + (size_t)(p + 1) * 4 + 256);
@@ -976,7 +981,7 @@ void means_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, const in
                      offsets, p, (const int32_t*)boff, part, skip);
   check_launch(ctx, s, "means_partial");
   hipLaunchKernelGGL(k_means_total, dim3((unsigned)p), dim3(MEANS_THREADS), 0, s, (const double*)part, d, offsets,
-                     (const int32_t*)boff, C, skip, delta, done_next);
+                     (const int32_t*)boff, C, CT, skip, delta, done_next);
   check_launch(ctx, s, "means_total");
 }
 
@@ -1077,7 +1082,7 @@ static void partition_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int 
     int32_t* perm = (int32_t*)w;
     int64_t* off = (int64_t*)(perm + n + (n & 1));
     group_by_key(ctx, s, assign, n, p, perm, off, nullptr, nullptr);
-    means_t(ctx, s, X, n, d, perm, off, C, p, nullptr, nullptr, nullptr);
+    means_t(ctx, s, X, n, d, perm, off, C, nullptr, p, nullptr, nullptr, nullptr);
   } else if (method == KRR_PART_GIVEN) {
     transpose_centroids(ctx, s, C, p, d, CT);
     assign_t(ctx, s, X, n, d, CT, p, assign, nullptr, nullptr, nullptr, nullptr, false);
@@ -1095,14 +1100,14 @@ static void partition_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int 
     check_launch(ctx, s, "fill");
     int32_t* cur = assign;
     int32_t* old = prev;
+    // the mean step writes CT beside C, so only the seeds need a transpose
+    transpose_centroids(ctx, s, C, p, d, CT);
     for (int it = 0; it < iters; ++it) {
-      transpose_centroids(ctx, s, C, p, d, CT);
       assign_t(ctx, s, X, n, d, CT, p, cur, nullptr, it == 0 ? nullptr : old, deltas + it, done + it, false);
       group_by_key(ctx, s, cur, n, p, perm, off, nullptr, done + it);
-      means_t(ctx, s, X, n, d, perm, off, C, p, done + it, deltas + it, done + it + 1);
+      means_t(ctx, s, X, n, d, perm, off, C, CT, p, done + it, deltas + it, done + it + 1);
       std::swap(cur, old);
     }
-    transpose_centroids(ctx, s, C, p, d, CT);
     assign_t(ctx, s, X, n, d, CT, p, assign, nullptr, nullptr, nullptr, nullptr, false);
     if (method == KRR_PART_KBALANCE) {
       // Greedy capacity pass over the exact distances to the K-means centres,
@@ -1140,7 +1145,7 @@ static void partition_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int 
       }
       KRR_HIP(hipMemcpyAsync(assign, MB, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
       group_by_key(ctx, s, assign, n, p, perm, off, nullptr, nullptr);
-      means_t(ctx, s, X, n, d, perm, off, C, p, nullptr, nullptr, nullptr);
+      means_t(ctx, s, X, n, d, perm, off, C, nullptr, p, nullptr, nullptr, nullptr);
     }
   }
   // sizes: histogram of the final assignment
