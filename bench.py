@@ -59,8 +59,8 @@ TRAFFIC = {
     "chol_column_bf16": {
         "kernel": "k_panel_col",
         "source": "paper_1805_00569_amd/csrc/cholesky.hip",
-        "sha256": "849d5adb54e6ae6faaf8bd5691c1d339566d8b506b1545e9b949eb7767dcb7bf",
-        "fetch_kib": 118846.4, "write_kib": 79707.7, "fetch_scale": 2.0, "write_scale": 1.0,
+        "sha256": "a75a9d35cd55ecaa37e06a7a2a8ba64045018d7cd4d7da2887fb98b2f6d30ba0",
+        "fetch_kib": 118993.0, "write_kib": 79707.4, "fetch_scale": 2.0, "write_scale": 1.0,
     },
 }
 
