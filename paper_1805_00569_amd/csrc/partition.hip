@@ -62,11 +62,15 @@ __device__ __forceinline__ int first_active_lane() {
 // MODE 0: argmin index (+ change count against `prev`); MODE 1: all p squared
 // distances into D (n x p).  A block stages 64 rows in LDS feature-major
 // (lane = row); its 4 waves take the centre chunks [4c, 4c + 4) with
-// c = wave, wave + 4, ..., so that a wave's centre loads are uniform (scalar)
-// and each SIMD holds several waves.  The per-wave minima are combined with
-// the rule of the sequential scan: lowest value, then lowest index.
+// c = wave, wave + 4, ..., so that a wave's centre values are uniform and
+// each SIMD holds several waves.  CTL: the centres are staged in LDS too
+// (p d doubles; the inner loop then issues only LDS loads, which return in
+// order, instead of scalar loads, whose waits drain every LDS load in
+// flight); otherwise they are read with scalar loads.  The per-wave minima
+// are combined with the rule of the sequential scan: lowest value, then
+// lowest index.
 // ---------------------------------------------------------------------------
-template <typename TX, int MODE>
+template <typename TX, int MODE, bool CTL>
 __global__ __launch_bounds__(256) void k_assign(const TX* __restrict__ X, int64_t n, int d,
                                                 const double* __restrict__ CT, int p,
                                                 int32_t* __restrict__ out, double* __restrict__ D,
@@ -76,6 +80,7 @@ __global__ __launch_bounds__(256) void k_assign(const TX* __restrict__ X, int64_
   if (skip != nullptr && *skip) return;
   extern __shared__ unsigned char smem_raw[];
   TX* sX = reinterpret_cast<TX*>(smem_raw);
+  double* sCT = reinterpret_cast<double*>(smem_raw + ((((size_t)d * (AROWS + 1) + 1) * sizeof(TX) + 15) & ~size_t(15)));
   __shared__ double sbest[4][AROWS];
   __shared__ int32_t sidx[4][AROWS];
   constexpr int ld = AROWS + 1;
@@ -105,6 +110,8 @@ __global__ __launch_bounds__(256) void k_assign(const TX* __restrict__ X, int64_
       }
     }
   }
+  if (CTL)
+    for (int e = threadIdx.x; e < d * p; e += 256) sCT[e] = CT[e];
   __syncthreads();
   const int r = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -120,14 +127,14 @@ __global__ __launch_bounds__(256) void k_assign(const TX* __restrict__ X, int64_
     if (nj == ACH) {
       for (int k = 0; k < d; ++k) {
         const double xk = (double)sX[k * ld + r];
-        const double* c = CT + (int64_t)k * p + j0;
+        const double* c = (CTL ? sCT : CT) + (int64_t)k * p + j0;
 #pragma unroll
         for (int q = 0; q < ACH; ++q) acc[q] = sqdiff_acc(acc[q], xk, c[q]);
       }
     } else {
       for (int k = 0; k < d; ++k) {
         const double xk = (double)sX[k * ld + r];
-        const double* c = CT + (int64_t)k * p + j0;
+        const double* c = (CTL ? sCT : CT) + (int64_t)k * p + j0;
 #pragma unroll
         for (int q = 0; q < ACH; ++q)
           if (q < nj) acc[q] = sqdiff_acc(acc[q], xk, c[q]);
@@ -946,14 +953,22 @@ void assign_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, const d
               bool all) {
   // 64 rows per block staged in LDS (plus a spare slot); very wide rows use the unstaged kernel
   const size_t lds = ((size_t)d * (AROWS + 1) + 1) * sizeof(TX);
+  const size_t lds_ct = ((lds + 15) & ~size_t(15)) + (size_t)p * d * sizeof(double);   // with the centres
   const int64_t nblk = ceil_div(n, AROWS);
   KernelTimer kt(ctx, s, "assign", 0.0, 0);
-  if (lds <= 96 * 1024) {
+  if (lds_ct <= 48 * 1024) {
     if (all)
-      hipLaunchKernelGGL((k_assign<TX, 1>), dim3(nblk), dim3(256), lds, s, X, n, d, CT, p, out, D, prev,
+      hipLaunchKernelGGL((k_assign<TX, 1, true>), dim3(nblk), dim3(256), lds_ct, s, X, n, d, CT, p, out, D, prev,
                          delta, skip);
     else
-      hipLaunchKernelGGL((k_assign<TX, 0>), dim3(nblk), dim3(256), lds, s, X, n, d, CT, p, out, D, prev,
+      hipLaunchKernelGGL((k_assign<TX, 0, true>), dim3(nblk), dim3(256), lds_ct, s, X, n, d, CT, p, out, D, prev,
+                         delta, skip);
+  } else if (lds <= 96 * 1024) {
+    if (all)
+      hipLaunchKernelGGL((k_assign<TX, 1, false>), dim3(nblk), dim3(256), lds, s, X, n, d, CT, p, out, D, prev,
+                         delta, skip);
+    else
+      hipLaunchKernelGGL((k_assign<TX, 0, false>), dim3(nblk), dim3(256), lds, s, X, n, d, CT, p, out, D, prev,
                          delta, skip);
   } else {
     const int64_t nb = ceil_div(n, 256);
