@@ -18,6 +18,7 @@ namespace krr {
 namespace {
 
 constexpr int GROUP_BLOCK = 256;
+constexpr int MEANS_BLOCK = 256;   // members per block of the mean step's sums
 constexpr int KPP_BLOCK = 256;   // k-means++ cumulative-weight block
 constexpr int ACH = 4;           // centres per register chunk in assignment
 constexpr int AROWS = 64;        // rows per assignment block (one per lane)
@@ -264,11 +265,14 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_group_local(const int32_t* __re
 
 // Per key j: exclusive prefix of the per-block counts (block offsets) and the
 // total; one wave per key (lane l takes a contiguous run of blocks, then a
-// 64-lane scan of the run sums).  Then the key offsets in key order.
+// 64-lane scan of the run sums).  Then the key offsets in key order and
+// (mboff, nullable) the mean step's member-block offsets: mboff[j] = number
+// of MEANS_BLOCK-member blocks of the keys < j.
 __global__ __launch_bounds__(1024) void k_group_scan(const int32_t* __restrict__ blockcounts, int64_t nblocks,
                                                      int p, int32_t* __restrict__ blockoffs,
                                                      int64_t* __restrict__ offsets,
                                                      int64_t* __restrict__ sizes64,
+                                                     int32_t* __restrict__ mboff,
                                                      const int32_t* __restrict__ skip) {
   if (skip != nullptr && *skip) return;
   extern __shared__ int64_t tot[];
@@ -297,11 +301,17 @@ __global__ __launch_bounds__(1024) void k_group_scan(const int32_t* __restrict__
   __syncthreads();
   if (threadIdx.x == 0) {
     int64_t o = 0;
+    int32_t mb = 0;
     for (int j = 0; j < p; ++j) {
       offsets[j] = o;
       o += tot[j];
+      if (mboff != nullptr) {
+        mboff[j] = mb;
+        mb += (int32_t)((tot[j] + MEANS_BLOCK - 1) / MEANS_BLOCK);
+      }
     }
     offsets[p] = o;
+    if (mboff != nullptr) mboff[p] = mb;
   }
 }
 
@@ -331,7 +341,6 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_group_scatter(const int32_t* __
 // skipped or changed no assignment), so no workgroup of a launch reads a flag
 // that the same launch writes.
 // ---------------------------------------------------------------------------
-constexpr int MEANS_BLOCK = 256;
 constexpr int MEANS_THREADS = 128;
 
 // boff[j] = number of member blocks of partitions < j (boff[p] = total)
@@ -982,21 +991,28 @@ void assign_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, const d
   check_launch(ctx, s, "assign");
 }
 
+// boff_in (nullable): the member-block offsets, already written by the
+// grouping (group_by_key's mboff); otherwise computed here.
 template <typename TX>
 void means_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, const int32_t* perm, const int64_t* offsets,
-             double* C, double* CT, int p, const int32_t* skip, const int32_t* delta, int32_t* done_next) {
+             double* C, double* CT, int p, const int32_t* skip, const int32_t* delta, int32_t* done_next,
+             const int32_t* boff_in = nullptr) {
   KernelTimer kt(ctx, s, "lloyd_means", 0.0, 0);
   const int64_t max_blocks = ceil_div(n, MEANS_BLOCK) + p;   // sum over partitions of ceil(m_j / MEANS_BLOCK)
   char* w = (char*)ws_get(ctx, "means", (size_t)max_blocks * d * 8 + (size_t)(p + 1) * 4 + 256);
   double* part = (double*)w;
-  int32_t* boff = (int32_t*)(w + (((size_t)max_blocks * d * 8 + 255) & ~size_t(255)));
-  hipLaunchKernelGGL(k_means_blockoff, dim3(1), dim3(1024), 0, s, offsets, p, boff, skip);
-  check_launch(ctx, s, "means_blockoff");
+  const int32_t* boff = boff_in;
+  if (boff == nullptr) {
+    int32_t* bw = (int32_t*)(w + (((size_t)max_blocks * d * 8 + 255) & ~size_t(255)));
+    hipLaunchKernelGGL(k_means_blockoff, dim3(1), dim3(1024), 0, s, offsets, p, bw, skip);
+    check_launch(ctx, s, "means_blockoff");
+    boff = bw;
+  }
   hipLaunchKernelGGL((k_means_partial<TX>), dim3((unsigned)max_blocks), dim3(MEANS_THREADS), 0, s, X, d, perm,
-                     offsets, p, (const int32_t*)boff, part, skip);
+                     offsets, p, boff, part, skip);
   check_launch(ctx, s, "means_partial");
   hipLaunchKernelGGL(k_means_total, dim3((unsigned)p), dim3(MEANS_THREADS), 0, s, (const double*)part, d, offsets,
-                     (const int32_t*)boff, C, CT, skip, delta, done_next);
+                     boff, C, CT, skip, delta, done_next);
   check_launch(ctx, s, "means_total");
 }
 
@@ -1048,7 +1064,7 @@ void assign_nearest(krr_ctx ctx, hipStream_t s, const void* X, int dtype, int64_
 }
 
 void group_by_key(krr_ctx ctx, hipStream_t s, const int32_t* key, int64_t n, int p, int32_t* perm,
-                  int64_t* offsets, int64_t* sizes64, const int32_t* skip) {
+                  int64_t* offsets, int64_t* sizes64, const int32_t* skip, int32_t* mboff) {
   const int64_t nblk = ceil_div(n, GROUP_BLOCK);
   KernelTimer kt(ctx, s, "group", 0.0, 0);
   char* w = (char*)ws_get(ctx, "group", (size_t)n * 4 + (size_t)nblk * p * 8 + 64);
@@ -1060,7 +1076,7 @@ void group_by_key(krr_ctx ctx, hipStream_t s, const int32_t* key, int64_t n, int
                      skip);
   check_launch(ctx, s, "group_local");
   hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(std::min(1024, 64 * p)), (size_t)p * 8, s,
-                     (const int32_t*)bc, nblk, p, bo, offsets, sizes64, skip);
+                     (const int32_t*)bc, nblk, p, bo, offsets, sizes64, mboff, skip);
   check_launch(ctx, s, "group_scan");
   hipLaunchKernelGGL(k_group_scatter, dim3(nblk), dim3(GROUP_BLOCK), 0, s, key, n, p, (const int32_t*)rank,
                      (const int32_t*)bo, (const int64_t*)offsets, perm, skip);
@@ -1104,12 +1120,14 @@ static void partition_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int 
   } else {
     // K-means: k-means++ seeding then Lloyd passes (Algorithm 2).
     kmeanspp_t(ctx, s, X, n, d, p, seed, C);
-    char* w = (char*)ws_get(ctx, "lloyd", (size_t)n * 8 + (size_t)(p + 1) * 8 + (size_t)(2 * iters + 4) * 4 + 64);
+    char* w = (char*)ws_get(ctx, "lloyd", (size_t)n * 8 + (size_t)(p + 1) * 8 + (size_t)(2 * iters + 4) * 4 +
+                                              (size_t)(p + 1) * 4 + 64);
     int32_t* perm = (int32_t*)w;
     int32_t* prev = perm + n;
     int64_t* off = (int64_t*)(prev + n + (n & 1));
     int32_t* deltas = (int32_t*)(off + p + 1);
     int32_t* done = deltas + iters + 1;   // done[it]: pass `it` is past the fixed point
+    int32_t* mboff = done + iters + 2;    // member-block offsets of the mean step (p + 1)
     const int64_t nflags = 2 * (int64_t)iters + 3;
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)ceil_div(nflags, 64)), dim3(64), 0, s, deltas, nflags, 0);
     check_launch(ctx, s, "fill");
@@ -1119,8 +1137,8 @@ static void partition_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int 
     transpose_centroids(ctx, s, C, p, d, CT);
     for (int it = 0; it < iters; ++it) {
       assign_t(ctx, s, X, n, d, CT, p, cur, nullptr, it == 0 ? nullptr : old, deltas + it, done + it, false);
-      group_by_key(ctx, s, cur, n, p, perm, off, nullptr, done + it);
-      means_t(ctx, s, X, n, d, perm, off, C, CT, p, done + it, deltas + it, done + it + 1);
+      group_by_key(ctx, s, cur, n, p, perm, off, nullptr, done + it, mboff);
+      means_t(ctx, s, X, n, d, perm, off, C, CT, p, done + it, deltas + it, done + it + 1, mboff);
       std::swap(cur, old);
     }
     assign_t(ctx, s, X, n, d, CT, p, assign, nullptr, nullptr, nullptr, nullptr, false);
