@@ -502,7 +502,21 @@ __global__ __launch_bounds__(KPP_BLOCK) void k_kpp_select(const double* __restri
   double* sOb = gOb != nullptr ? gOb : shOb;
   __shared__ double s_total;
   __shared__ int64_t s_idx[KPP_BLOCK];
-  if (threadIdx.x == 0) {
+  if (gOb == nullptr) {
+    // offsets in LDS: the block totals come in with one coalesced load, then
+    // thread 0 turns them into the exclusive prefix in place (same order)
+    for (int64_t b = threadIdx.x; b < nblk; b += KPP_BLOCK) shOb[b] = Tb[b];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double o = 0.0;
+      for (int64_t b = 0; b < nblk; ++b) {
+        const double tv = shOb[b];
+        shOb[b] = o;
+        o = add_sep(o, tv);
+      }
+      s_total = o;
+    }
+  } else if (threadIdx.x == 0) {
     double o = 0.0;
     int64_t b = 0;
     for (; b + 8 <= nblk; b += 8) {
