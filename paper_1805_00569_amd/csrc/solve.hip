@@ -72,7 +72,11 @@ __device__ __forceinline__ double quad16_sum(double v) {
 // against the band, and k_trsv_fwd_upd subtracts the band's contribution from
 // every tile row below it into a working copy bw of b (the path depends on the
 // system's own T only).
-constexpr int TRSV_XL_MAXT = 128;
+// Threshold measured on the 96-system batch of m = 4,096 (T = 64): the band
+// path takes the backward solve from 0.85 to 0.79 ms, as its band updates
+// spread the factor over the whole chip while the whole-system path keeps it
+// on one CU per system.
+constexpr int TRSV_XL_MAXT = 32;
 constexpr int TRSV_BAND = 16;
 
 // z = L^-1 b over tile rows [lo, hi): u = b_i - sum_{lo<=j<i} L(i,j) z_j, then

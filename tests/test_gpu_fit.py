@@ -340,6 +340,35 @@ def test_large_and_small_systems_in_one_batch(ctx, dev, prec):
         assert _rel(models[q].alpha(1).cpu().numpy(), ref) < tol, q
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solve_paths_at_the_threshold(ctx, dev, prec):
+    """Systems of 32 tile rows (m = 2,048: whole-system backward solve) and 33
+    (m = 2,049: band by band, the top band and the last tile holding one row)
+    in one batch, two settings: every alpha against the FP64 oracle."""
+    g = np.random.default_rng(87)
+    sizes = (2048, 2049)
+    Xs = [(g.uniform(-1.0, 1.0, size=(m, 4)) + 10.0 * q).astype(np.float32) for q, m in enumerate(sizes)]
+    ys = [(np.sin(Xq.astype(np.float64).sum(axis=1)) + 0.1 * g.standard_normal(len(Xq))).astype(np.float32)
+          for Xq in Xs]
+    print(f"solve threshold m={sizes} {prec}", flush=True)
+    Xa, ya = np.concatenate(Xs), np.concatenate(ys)
+    Xg = Xa.astype(np.float64) if prec == "fp64" else Xa
+    yg = ya.astype(np.float64) if prec == "fp64" else ya
+    Xd = _t(Xg, dev)
+    C0 = np.array([[0.0] * 4, [10.0] * 4], Xg.dtype)
+    C, a, _ = ctx.partition(Xd, 2, "given", centroids=_t(C0, dev))
+    assert np.array_equal(a.cpu().numpy(), np.repeat([0, 1], sizes))
+    sigmas = (0.5, 1.0)
+    params = [krr.Params(sigma=sg, lam=1e-2, prec=prec, refine_tol=1e-8, max_refine=40) for sg in sigmas]
+    models, info, st = ctx.fit(Xd, _t(yg, dev), a, C, 2, params)
+    assert st == 0 and all(i["status"] == 0 for i in info)
+    tol = 1e-10 if prec == "fp64" else 1e-6
+    for q, sg in enumerate(sigmas):
+        for j in range(2):
+            ref = O.fit_one(Xs[j].astype(np.float64), ys[j].astype(np.float64), sg, 1e-2)["alpha"]
+            assert _rel(models[q].alpha(j).cpu().numpy(), ref) < tol, (q, j)
+
+
 def test_linear_kernel_is_primal_ridge(ctx, dev):
     """Linear kernel through the GPU path equals x^T (X^T X + lam I)^-1 X^T y
     (Eq. 2 with Table 1's linear kernel)."""
