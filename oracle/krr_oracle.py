@@ -37,6 +37,12 @@ Readings taken where the paper is silent (each is listed in the design notes):
 * Member sums for means are sequential in increasing point index.
 * K-balance capacity is ceil(n/p); the recompute of centres (optional in the
   paper) is done.
+* The approximate parallel K-balance (Section 4.3, after Algorithm 4) splits
+  the samples in input order into p even segments, rows
+  [floor(q n / p), floor((q + 1) n / p)), as a row scatter would; each
+  segment runs the greedy pass with capacity ceil(n_q / p) (the paper's
+  n / p^2 when p^2 divides n), then the centres are recomputed as member
+  means over all segments.
 * DC-KRR's shuffle (Algorithm 3) is a keyed Feistel permutation with
   cycle-walking, and the even split gives partition j the shuffled rows
   [floor(j n / p), floor((j + 1) n / p)); see ``shuffle_positions``.
@@ -230,6 +236,22 @@ def kbalance(X, p, iters, seed):
     return C2, MB
 
 
+def kbalance_approx(X, p, iters, seed):
+    """Approximate parallel K-balance (Section 4.3): the same K-means centres,
+    the samples split in input order into p even segments (one per node),
+    each segment's own greedy pass with capacity ceil(n_q / p) (n / p^2 per
+    node and centre), then centres recomputed as member means."""
+    C, _ = kmeans(X, p, iters, seed)
+    n = X.shape[0]
+    MB = np.empty(n, dtype=np.int32)
+    for q in range(p):
+        lo, hi = q * n // p, (q + 1) * n // p
+        if hi > lo:
+            MB[lo:hi] = kbalance_greedy(X[lo:hi], C, -(-(hi - lo) // p))
+    C2, _ = member_means(X, MB, C)
+    return C2, MB
+
+
 # ---------------------------------------------------------------------------
 # DC-KRR divide step (Section 3.2, Algorithm 3): shuffle the rows of [X, y],
 # then hand them out evenly by rows
@@ -305,6 +327,8 @@ def partition(X, p, method, iters=20, seed=0, centroids=None):
         C, a = kmeans(X, p, iters, seed)
     elif method == "kbalance":
         C, a = kbalance(X, p, iters, seed)
+    elif method == "kbalance_approx":
+        C, a = kbalance_approx(X, p, iters, seed)
     else:
         raise ValueError(method)
     return C, a, np.bincount(a, minlength=p).astype(np.int64)

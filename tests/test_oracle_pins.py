@@ -323,6 +323,56 @@ def test_kbalance_ragged_capacity():
     assert sizes.sum() == 103 and sizes.max() <= 26
 
 
+def test_kbalance_approx_hand_example():
+    """Section 4.3's approximate parallel K-balance on 8 points in 1-D, p = 2:
+    segments of 4 rows, capacity 2 per segment and centre.  Worked by hand:
+    the first segment's two points past the capacity of the near centre go
+    to the far one, and the second segment mirrors it."""
+    X = np.array([[0.0], [0.1], [0.2], [0.3], [10.0], [10.1], [10.2], [10.3]])
+    C, MB = O.kbalance_approx(X, 2, 5, seed=3)
+    Ck, _ = O.kmeans(X, 2, 5, seed=3)
+    lo = int(np.argmin(Ck[:, 0]))
+    hi = 1 - lo
+    assert abs(Ck[lo, 0] - 0.15) < 1e-12 and abs(Ck[hi, 0] - 10.15) < 1e-12
+    assert MB.tolist() == [lo, lo, hi, hi, hi, hi, lo, lo]
+    # members {0, 0.1, 10.2, 10.3} and {0.2, 0.3, 10, 10.1}
+    assert abs(C[lo, 0] - 5.15) < 1e-12 and abs(C[hi, 0] - 5.15) < 1e-12
+    # the exact K-balance (capacity 4 over all samples) keeps the clusters
+    _, MBx = O.kbalance(X, 2, 5, seed=3)
+    assert MBx.tolist() == [lo] * 4 + [hi] * 4
+
+
+def test_kbalance_approx_segments_replayed():
+    """p^2 divides n: every segment gives every centre exactly n / p^2
+    samples, and each segment is the greedy rule replayed on its own rows."""
+    w = datagen.small(12, 256, 5, comps=6)
+    p, n = 4, 256
+    C, MB = O.kbalance_approx(w.X, p, 8, seed=12)
+    Ck, _ = O.kmeans(w.X, p, 8, seed=12)
+    for q in range(p):
+        seg = MB[q * 64:(q + 1) * 64]
+        assert np.bincount(seg, minlength=p).tolist() == [16] * p
+        CS = [0] * p
+        for i in range(q * 64, (q + 1) * 64):
+            d = [_py_dist2(w.X[i], Ck[j]) for j in range(p)]
+            best = min((j for j in range(p) if CS[j] < 16), key=lambda j: (d[j], j))
+            assert MB[i] == best, (q, i)
+            CS[best] += 1
+    for j in range(p):
+        np.testing.assert_allclose(C[j], w.X[MB == j].astype(np.float64).mean(0), rtol=1e-13, atol=1e-13)
+
+
+def test_kbalance_approx_ragged_segments():
+    """n = 103, p = 4: segments of 25, 26, 26, 26 rows with capacity 7 each,
+    so no centre takes more than 7 of a segment's samples."""
+    w = datagen.small(13, 103, 3, comps=3)
+    _, MB = O.kbalance_approx(w.X, 4, 5, seed=13)
+    bounds = [0, 25, 51, 77, 103]
+    for q in range(4):
+        assert np.bincount(MB[bounds[q]:bounds[q + 1]], minlength=4).max() <= 7
+    assert np.bincount(MB, minlength=4).sum() == 103
+
+
 # ---------------------------------------------------------------- kernel
 
 def test_gaussian_kernel_hand_values():
