@@ -65,8 +65,21 @@ typedef enum { KRR_F32 = 0, KRR_F64 = 1 } krr_dtype;
  * (Feistel network with SplitMix64 round keys, cycle-walked to [0, n)) and
  * partition j takes the shuffled rows [floor(j n/p), floor((j+1) n/p));
  * centroids are the member means (lloyd_iters is ignored).  Algorithm 3
- * then averages all models: KRR_ROUTE_AVERAGE with lambda_times_m = 1. */
-typedef enum { KRR_PART_KMEANS = 0, KRR_PART_KBALANCE = 1, KRR_PART_GIVEN = 2, KRR_PART_RANDOM = 3 } krr_part;
+ * then averages all models: KRR_ROUTE_AVERAGE with lambda_times_m = 1.
+ * KBALANCE_APPROX: the approximate parallel K-balance of Section 4.3: the
+ * same K-means centres; the samples in input order are split into p even
+ * segments, rows [floor(q n/p), floor((q+1) n/p)) (one per node), each
+ * segment runs the greedy pass on its own with capacity ceil(n_q/p) per
+ * centre (the paper's n/p^2), then the centres are recomputed as member
+ * means.  A partition holds at most p * ceil(ceil(n/p)/p) points, and
+ * exactly n/p when p^2 divides n. */
+typedef enum {
+  KRR_PART_KMEANS = 0,
+  KRR_PART_KBALANCE = 1,
+  KRR_PART_GIVEN = 2,
+  KRR_PART_RANDOM = 3,
+  KRR_PART_KBALANCE_APPROX = 4
+} krr_part;
 
 /* Working precision of a fit.
  * FP64:  kernel matrix, Cholesky and solves in FP64.

@@ -301,7 +301,7 @@ krr_status krr_partition(krr_ctx ctx, hipStream_t stream, const void* X, int32_t
     KRR_REQUIRE(n < (int64_t(1) << 31) - 1, "n must fit in int32");
     KRR_REQUIRE(p >= 1 && p <= n && p <= 1024, "p must be in [1, min(n, 1024)]");
     KRR_REQUIRE(method == KRR_PART_KMEANS || method == KRR_PART_KBALANCE || method == KRR_PART_GIVEN ||
-                    method == KRR_PART_RANDOM,
+                    method == KRR_PART_RANDOM || method == KRR_PART_KBALANCE_APPROX,
                 "unknown partition method");
     KRR_REQUIRE(lloyd_iters >= 0 && lloyd_iters <= 100000, "lloyd_iters out of range");
     run_partition(ctx, stream, X, dtype, n, d, p, method, lloyd_iters, seed, centroids, assign, sizes);

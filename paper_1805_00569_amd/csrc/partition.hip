@@ -603,23 +603,31 @@ __device__ __forceinline__ void wave_argmin(double& v, int& j) {
   }
 }
 
+// Segment q = blockIdx.x of nseg covers the samples [floor(q n / nseg),
+// floor((q + 1) n / nseg)) and runs the greedy pass on them alone with
+// capacity `cap` (cap <= 0: ceil(segment size / p)).  One segment is
+// Algorithm 4's pass; p segments with cap <= 0 are the approximate parallel
+// K-balance of Section 4.3 (one segment per node, n / p^2 per node and centre).
 __global__ __launch_bounds__(64) void k_kbalance(const double* __restrict__ D, const int32_t* __restrict__ a0,
-                                                 int64_t n, int p, int64_t cap, int32_t* __restrict__ MB) {
+                                                 int64_t n, int p, int nseg, int64_t cap_in,
+                                                 int32_t* __restrict__ MB) {
   extern __shared__ int32_t sh[];
   int32_t* cs = sh;        // p counts
   int32_t* hist = sh + p;  // p per-chunk counts
   const int lane = threadIdx.x;
+  const int64_t lo = (int64_t)blockIdx.x * n / nseg, hi = ((int64_t)blockIdx.x + 1) * n / nseg;
+  const int64_t cap = cap_in > 0 ? cap_in : (hi - lo + p - 1) / p;
   for (int j = lane; j < p; j += 64) {
     cs[j] = 0;
     hist[j] = 0;
   }
   __builtin_amdgcn_wave_barrier();
-  int next_a = (lane < n) ? a0[lane] : 0;
-  for (int64_t c0 = 0; c0 < n; c0 += 64) {
+  int next_a = (lo + lane < hi) ? a0[lo + lane] : 0;
+  for (int64_t c0 = lo; c0 < hi; c0 += 64) {
     const int64_t i = c0 + lane;
-    const bool valid = i < n;
+    const bool valid = i < hi;
     const int cur_a = next_a;
-    if (c0 + 64 + lane < n) next_a = a0[c0 + 64 + lane];   // prefetch the next chunk
+    if (c0 + 64 + lane < hi) next_a = a0[c0 + 64 + lane];   // prefetch the next chunk
     int bj = -1;
     if (valid) {
       bj = cur_a;
@@ -655,7 +663,7 @@ __global__ __launch_bounds__(64) void k_kbalance(const double* __restrict__ D, c
     } else {
       for (int j = lane; j < p; j += 64) hist[j] = 0;
       __builtin_amdgcn_wave_barrier();
-      const int cnt = (int)min((int64_t)64, n - c0);
+      const int cnt = (int)min((int64_t)64, hi - c0);
       for (int l = 0; l < cnt; ++l) {
         const int64_t ii = c0 + l;
         double v = INFINITY;
@@ -1156,16 +1164,21 @@ static void partition_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int 
       std::swap(cur, old);
     }
     assign_t(ctx, s, X, n, d, CT, p, assign, nullptr, nullptr, nullptr, nullptr, false);
-    if (method == KRR_PART_KBALANCE) {
+    if (method == KRR_PART_KBALANCE || method == KRR_PART_KBALANCE_APPROX) {
       // Greedy capacity pass over the exact distances to the K-means centres,
-      // then the centre recompute of Algorithm 4.
+      // then the centre recompute of Algorithm 4 (approximate parallel
+      // variant: one independent pass per even segment of the samples).
       double* D = (double*)ws_get(ctx, "kbal_d", (size_t)n * p * 8);
       assign_t(ctx, s, X, n, d, CT, p, nullptr, D, nullptr, nullptr, nullptr, true);
       const int32_t* a0 = assign;  // unconstrained nearest centres
       int32_t* MB = prev;
       const int64_t cap = ceil_div(n, p);
       KernelTimer kt(ctx, s, "kbalance_greedy", 0.0, 0);
-      if (p <= KB_MAXP) {
+      if (method == KRR_PART_KBALANCE_APPROX) {
+        hipLaunchKernelGGL(k_kbalance, dim3((unsigned)p), dim3(64), (size_t)p * 8, s, (const double*)D, a0, n, p, p,
+                           (int64_t)0, MB);
+        check_launch(ctx, s, "kbalance_segments");
+      } else if (p <= KB_MAXP) {
         const int64_t nblk = ceil_div(n, KB_BLOCK);
         char* kw = (char*)ws_get(ctx, "kbal_ev", (size_t)nblk * p * 4 + (size_t)p * 8 + 64);
         int64_t* kst = (int64_t*)kw;
@@ -1187,7 +1200,7 @@ static void partition_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int 
           check_launch(ctx, s, "kbal_event");
         }
       } else {
-        hipLaunchKernelGGL(k_kbalance, dim3(1), dim3(64), (size_t)p * 8, s, (const double*)D, a0, n, p, cap, MB);
+        hipLaunchKernelGGL(k_kbalance, dim3(1), dim3(64), (size_t)p * 8, s, (const double*)D, a0, n, p, 1, cap, MB);
         check_launch(ctx, s, "kbalance");
       }
       KRR_HIP(hipMemcpyAsync(assign, MB, (size_t)n * 4, hipMemcpyDeviceToDevice, s));

@@ -21,7 +21,7 @@ KRR_OK, KRR_EINVAL, KRR_ENOMEM, KRR_EBUDGET, KRR_ENOTSPD, KRR_ENOCONV, KRR_EDEVI
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EBUDGET", -4: "ENOTSPD", -5: "ENOCONV",
                 -6: "EDEVICE", -7: "ESTATE"}
 F32, F64 = 0, 1
-PART = {"kmeans": 0, "kbalance": 1, "given": 2, "random": 3}
+PART = {"kmeans": 0, "kbalance": 1, "given": 2, "random": 3, "kbalance_approx": 4}
 PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
 ROUTE = {"nearest": 0, "average": 1, "all": 2, "label": 3}
 KERNEL = {"gaussian": 0, "linear": 1, "polynomial": 2, "sigmoid": 3}

@@ -82,6 +82,39 @@ def test_kbalance_many_blocks_with_ties(ctx, dev, p):
     assert sz.cpu().numpy().max() <= -(-n // p)
 
 
+@pytest.mark.parametrize("case", ["balanced", "ties", "ragged", "one_point_segments"])
+def test_kbalance_approx_bitexact(ctx, dev, case):
+    """Approximate parallel K-balance (Section 4.3): p even segments of the
+    samples, each with its own greedy pass at capacity ceil(n_q / p), then
+    the member-mean centres, bit for bit.  Cases: p^2 | n (every partition
+    exactly n / p), integer-grid ties, a ragged split, and p = n (one sample
+    per segment)."""
+    if case == "balanced":
+        w = datagen.balanced(seed=34, n=8192, k_test=16, p=16)
+        X, p, iters = w.X, 16, 5
+    elif case == "ties":
+        g = np.random.default_rng(41)
+        X = g.integers(0, 4, size=(20011, 3)).astype(np.float64)
+        X[: 20011 // 3] += 10.0 * g.integers(0, 3, size=(20011 // 3, 1))
+        p, iters = 13, 3
+    elif case == "ragged":
+        X, p, iters = datagen.small(35, 1003, 5, comps=3, dtype=np.float64).X, 7, 4
+    else:
+        X = np.random.default_rng(42).standard_normal((300, 4)).astype(np.float32)
+        p, iters = 300, 2
+    n = X.shape[0]
+    print(f"kbalance_approx {case} n={n} p={p}", flush=True)
+    C, a, sz = ctx.partition(_t(X, dev), p, "kbalance_approx", lloyd_iters=iters, seed=11)
+    Co, ao = O.kbalance_approx(X, p, iters, 11)
+    np.testing.assert_array_equal(a.cpu().numpy(), ao)
+    np.testing.assert_array_equal(C.cpu().numpy(), Co)
+    sizes = sz.cpu().numpy()
+    np.testing.assert_array_equal(sizes, np.bincount(ao, minlength=p))
+    if n % (p * p) == 0:
+        assert sizes.tolist() == [n // p] * p
+    assert sizes.max() <= p * -(-(-(-n // p)) // p)
+
+
 @pytest.mark.parametrize("n,d,p,seed,dtype", [(20011, 90, 16, 5, np.float32), (4096, 8, 7, 1, np.float64),
                                               (65536, 4, 64, 9, np.float32), (5, 3, 5, 2, np.float64),
                                               (37, 2, 1, 3, np.float32)])
