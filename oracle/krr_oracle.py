@@ -43,6 +43,8 @@ Readings taken where the paper is silent (each is listed in the design notes):
   segment runs the greedy pass with capacity ceil(n_q / p) (the paper's
   n / p^2 when p^2 divides n), then the centres are recomputed as member
   means over all segments.
+* CSR input (Sections 5.5 and 6) is expanded to the dense n x d matrix;
+  repeated columns of a row are added in storage order in the values' dtype.
 * DC-KRR's shuffle (Algorithm 3) is a keyed Feistel permutation with
   cycle-walking, and the even split gives partition j the shuffled rows
   [floor(j n / p), floor((j + 1) n / p)); see ``shuffle_positions``.
@@ -250,6 +252,35 @@ def kbalance_approx(X, p, iters, seed):
             MB[lo:hi] = kbalance_greedy(X[lo:hi], C, -(-(hi - lo) // p))
     C2, _ = member_means(X, MB, C)
     return C2, MB
+
+
+# ---------------------------------------------------------------------------
+# Sparse input (Section 5.5 and Section 6: the n x d input matrix held in CSR)
+# ---------------------------------------------------------------------------
+
+def csr_to_dense(indptr, indices, values, n: int, d: int) -> np.ndarray:
+    """The dense n x d matrix of a CSR (compressed sparse row) input: row i
+    holds values[k] at column indices[k] for indptr[i] <= k < indptr[i + 1].
+    Columns repeated within a row are added in storage order, starting from
+    zero, in the values' dtype.  A malformed structure (indptr[0] != 0,
+    indptr decreasing, indptr[n] != nnz, a column outside [0, d)) raises
+    ValueError."""
+    indptr = np.asarray(indptr, dtype=np.int64)
+    indices = np.asarray(indices, dtype=np.int64)
+    values = np.asarray(values)
+    nnz = values.shape[0]
+    if indptr.shape != (n + 1,) or indices.shape != (nnz,):
+        raise ValueError("CSR arrays of the wrong length")
+    if indptr[0] != 0 or indptr[n] != nnz or np.any(indptr[1:] < indptr[:-1]):
+        raise ValueError("malformed CSR row pointers")
+    if nnz and (indices.min() < 0 or indices.max() >= d):
+        raise ValueError("CSR column index out of range")
+    X = np.zeros((n, d), dtype=values.dtype)
+    for i in range(n):
+        for k in range(int(indptr[i]), int(indptr[i + 1])):
+            j = int(indices[k])
+            X[i, j] = X[i, j] + values[k]
+    return X
 
 
 # ---------------------------------------------------------------------------

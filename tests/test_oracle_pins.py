@@ -373,6 +373,42 @@ def test_kbalance_approx_ragged_segments():
     assert np.bincount(MB, minlength=4).sum() == 103
 
 
+# ---------------------------------------------------------------- CSR input
+
+def test_csr_hand_example():
+    """3 x 4: an unsorted row with a repeated column (1.5 + 2.25 at (0, 2)),
+    an empty row, and a full row; the dense matrix written out by hand."""
+    indptr = [0, 3, 3, 7]
+    indices = [2, 0, 2, 3, 1, 0, 2]
+    values = np.array([1.5, -1.0, 2.25, 4.0, 5.0, 6.0, 7.0])
+    X = O.csr_to_dense(indptr, indices, values, 3, 4)
+    assert X.tolist() == [[-1.0, 0.0, 3.75, 0.0], [0.0, 0.0, 0.0, 0.0], [6.0, 5.0, 7.0, 4.0]]
+
+
+def test_csr_matches_scipy_with_repeats():
+    """Random CSR with repeated columns and exactly representable values (so
+    the order of the additions cannot matter) against SciPy's expansion."""
+    sp = pytest.importorskip("scipy.sparse")
+    g = np.random.default_rng(51)
+    n, d = 40, 13
+    counts = g.integers(0, 9, n)
+    indptr = np.concatenate([[0], np.cumsum(counts)])
+    indices = g.integers(0, d, indptr[-1]).astype(np.int32)
+    for dtype in (np.float64, np.float32):
+        values = g.integers(-8, 9, indptr[-1]).astype(dtype) * dtype(0.25)
+        X = O.csr_to_dense(indptr, indices, values, n, d)
+        ref = sp.csr_matrix((values, indices, indptr), shape=(n, d)).toarray()
+        assert X.dtype == dtype
+        np.testing.assert_array_equal(X, ref)
+
+
+@pytest.mark.parametrize("indptr,indices", [([0, 2, 1], [0, 1]), ([1, 1, 2], [0, 1]), ([0, 1, 2], [0, 4]),
+                                            ([0, 1, 3], [0, 1]), ([0, 1, 2], [-1, 0])])
+def test_csr_rejects_malformed(indptr, indices):
+    with pytest.raises(ValueError):
+        O.csr_to_dense(indptr, indices, np.ones(len(indices)), 2, 4)
+
+
 # ---------------------------------------------------------------- kernel
 
 def test_gaussian_kernel_hand_values():
