@@ -175,6 +175,22 @@ krr_status  krr_memory_in_use(krr_ctx ctx, size_t* bytes);
  * length. */
 krr_status  krr_timing_report(krr_ctx ctx, char* buf, size_t cap, size_t* needed);
 
+/* ---- sparse input (Section 5.5; Section 6) ---------------------------------
+ * Expands an n x d matrix held in CSR form into the dense row-major matrix
+ * that krr_partition, krr_fit, krr_predict and krr_select take.
+ * indptr:  device, n + 1 int64 row pointers: row i holds the entries
+ *          k in [indptr[i], indptr[i + 1]); indptr[0] = 0, non-decreasing,
+ *          indptr[n] = nnz.
+ * indices: device, nnz int32 column indices in [0, d), any order; a column
+ *          repeated in a row is summed (storage order, in dtype).
+ * values:  device, nnz values of dtype `dtype` (KRR_F32 / KRR_F64).
+ * X:       device, n x d output of the same dtype, fully overwritten.
+ * indices and values may be NULL when nnz = 0.  Synchronises `stream` to
+ * check the structure: a malformed one returns KRR_EINVAL (X then holds
+ * zeros in the malformed rows and entries, the other rows expanded). */
+krr_status krr_csr_to_dense(krr_ctx ctx, hipStream_t stream, const int64_t* indptr, const int32_t* indices,
+                            const void* values, int32_t dtype, int64_t n, int32_t d, int64_t nnz, void* X);
+
 /* ---- partition (Section 2.4 Algorithm 2; Section 4.3 Algorithm 4) --------
  * X:         device, n x d row-major, dtype `dtype` (FP32 values are widened
  *            exactly to FP64 for every distance).

@@ -291,6 +291,18 @@ krr_status krr_memory_in_use(krr_ctx ctx, size_t* bytes) {
   return KRR_OK;
 }
 
+krr_status krr_csr_to_dense(krr_ctx ctx, hipStream_t stream, const int64_t* indptr, const int32_t* indices,
+                            const void* values, int32_t dtype, int64_t n, int32_t d, int64_t nnz, void* X) {
+  return guarded(ctx, [&] {
+    KRR_REQUIRE(indptr && X, "null pointer argument");
+    KRR_REQUIRE(nnz == 0 || (indices && values), "null pointer argument");
+    KRR_REQUIRE(dtype == KRR_F32 || dtype == KRR_F64, "dtype must be KRR_F32 or KRR_F64");
+    KRR_REQUIRE(n >= 1 && d >= 1 && nnz >= 0, "n and d must be >= 1, nnz >= 0");
+    KRR_REQUIRE(n < (int64_t(1) << 31) - 1, "n must fit in int32");
+    run_csr_to_dense(ctx, stream, indptr, indices, values, dtype, n, d, nnz, X);
+  });
+}
+
 krr_status krr_partition(krr_ctx ctx, hipStream_t stream, const void* X, int32_t dtype, int64_t n, int32_t d,
                          int32_t p, int32_t method, int32_t lloyd_iters, uint64_t seed, double* centroids,
                          int32_t* assign, int64_t* sizes) {

@@ -187,6 +187,10 @@ struct KernelTimer {
   ~KernelTimer();
 };
 
+// ---- csr.hip ----
+void run_csr_to_dense(krr_ctx ctx, hipStream_t s, const int64_t* indptr, const int32_t* indices, const void* values,
+                      int dtype, int64_t n, int d, int64_t nnz, void* X);
+
 // ---- partition.hip ----
 void assign_nearest(krr_ctx ctx, hipStream_t s, const void* X, int dtype, int64_t n, int d,
                     const double* C, int p, int32_t* out, const int32_t* prev, int32_t* delta,

@@ -77,6 +77,8 @@ _SIGS = {
     "krr_set_option": ([_P, ctypes.c_int32, ctypes.c_int64], ctypes.c_int),
     "krr_memory_in_use": ([_P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "krr_timing_report": ([_P, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "krr_csr_to_dense": ([_P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, _P],
+                         ctypes.c_int),
     "krr_partition": ([_P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                        ctypes.c_int32, ctypes.c_uint64, _P, _P, _P], ctypes.c_int),
     "krr_fit": ([_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P, _P, ctypes.c_int32,
@@ -221,6 +223,20 @@ class Context:
         buf = ctypes.create_string_buffer(max(need.value, 2) + 4096)
         self._check(self.lib.krr_timing_report(self.h, buf, len(buf), ctypes.byref(need)))
         return json.loads(buf.value.decode() or "{}")
+
+    def csr_to_dense(self, indptr, indices, values, d):
+        """Dense n x d matrix (dtype of `values`) from CSR device tensors:
+        indptr int64[n + 1], indices int32[nnz], values float32/float64[nnz]."""
+        if indptr.dtype != torch.int64 or indices.dtype != torch.int32:
+            raise TypeError("indptr must be int64 and indices int32")
+        n, nnz = indptr.numel() - 1, values.numel()
+        if indices.numel() != nnz:
+            raise ValueError("indices and values differ in length")
+        X = torch.empty((n, d), dtype=values.dtype, device=self.device)
+        self._check(self.lib.krr_csr_to_dense(self.h, _stream(self.device), _ptr(indptr),
+                                              _ptr(indices) if nnz else None, _ptr(values) if nnz else None,
+                                              _dtype_code(values), n, d, nnz, _ptr(X)))
+        return X
 
     def partition(self, X, p, method="kmeans", lloyd_iters=20, seed=0, centroids=None):
         """Returns (centroids p x d FP64, assign int32[n], sizes int64[p])."""
