@@ -141,7 +141,7 @@ typedef struct {
 
 /* Tunables (krr_set_option).  Values apply to later calls on the context. */
 typedef enum {
-  KRR_OPT_PANEL_TILES = 0,  /* Cholesky panel width in 64-wide tiles (1..16, default 16) */
+  KRR_OPT_PANEL_TILES = 0,  /* Cholesky panel width in 64-wide tiles (1..64, default 16) */
   KRR_OPT_SERIAL_FIT = 1,   /* 1: factor the systems one after another, one launch
                                sequence per (partition, setting) -- the plain per-partition
                                baseline; 0 (default): one batched launch sequence */

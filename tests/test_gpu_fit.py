@@ -254,7 +254,7 @@ def test_mixed_precision_refines_to_1e6(ctx, dev, sigma):
     assert _pred_rel(yhat, yo, w.yt) < 1e-6
 
 
-@pytest.mark.parametrize("panel", [1, 3, 16])
+@pytest.mark.parametrize("panel", [1, 3, 16, 40])
 def test_mixed_ragged_partitions_panels(ctx, dev, panel):
     """Mixed precision over k-means partitions of uneven size (systems with
     different tile counts in one batch) and panel widths that put diagonal
@@ -307,6 +307,27 @@ def test_large_system_backward_solve_from_global(ctx, dev, prec):
     C, a, _ = ctx.partition(Xd, 1, "given", centroids=_t(np.zeros((1, 4), Xg.dtype), dev))
     models, info, st = ctx.fit(Xd, _t(yg, dev), a, C, 1,
                                [krr.Params(sigma=0.5, lam=1e-2, prec=prec, refine_tol=1e-8, max_refine=40)])
+    assert st == 0 and info[0]["status"] == 0
+    err = _rel(models[0].alpha(0).cpu().numpy(), alpha_ref)
+    assert err < (1e-10 if prec == "fp64" else 1e-6), err
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_large_system_wide_panel(ctx, dev, prec):
+    """The m = 8,300 system (130 tile rows) with panels of 40 tiles: three
+    full panels with their trailing updates and a ragged last one of 10."""
+    X, y, alpha_ref = _large_system()
+    print(f"large system panel=40 {prec}", flush=True)
+    Xg = X.astype(np.float64) if prec == "fp64" else X
+    yg = y.astype(np.float64) if prec == "fp64" else y
+    Xd = _t(Xg, dev)
+    C, a, _ = ctx.partition(Xd, 1, "given", centroids=_t(np.zeros((1, 4), Xg.dtype), dev))
+    ctx.set_option(krr.OPT_PANEL_TILES, 40)
+    try:
+        models, info, st = ctx.fit(Xd, _t(yg, dev), a, C, 1,
+                                   [krr.Params(sigma=0.5, lam=1e-2, prec=prec, refine_tol=1e-8, max_refine=40)])
+    finally:
+        ctx.set_option(krr.OPT_PANEL_TILES, 16)
     assert st == 0 and info[0]["status"] == 0
     err = _rel(models[0].alpha(0).cpu().numpy(), alpha_ref)
     assert err < (1e-10 if prec == "fp64" else 1e-6), err
