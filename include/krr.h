@@ -195,8 +195,9 @@ krr_status krr_csr_to_dense(krr_ctx ctx, hipStream_t stream, const int64_t* indp
  * X:         device, n x d row-major, dtype `dtype` (FP32 values are widened
  *            exactly to FP64 for every distance).
  * p:         number of partitions (1 <= p <= n, p <= 1024).
- * method:    krr_part.  lloyd_iters: maximum Lloyd passes (KMEANS, KBALANCE);
- *            a pass with no changed assignment ends the loop early.
+ * method:    krr_part.  lloyd_iters: maximum Lloyd passes (KMEANS, KBALANCE,
+ *            KBALANCE_APPROX); a pass with no changed assignment ends the
+ *            loop early.
  * seed:      SplitMix64 seed of the k-means++ draws.
  * centroids: device, p x d FP64; input for GIVEN, output otherwise.
  * assign:    device, n int32 output: partition of each point.  For KMEANS and
