@@ -112,6 +112,30 @@ def test_dckrr_random_partition_average_route_fp64(ctx, dev):
     assert best == O.select(mo)
 
 
+def test_approx_kbalance_nearest_route_fp64(ctx, dev):
+    """BKRR2 on the approximate parallel K-balance (Section 4.3): the
+    partition identical to the oracle's, then per-partition fits and
+    nearest-centre predictions against the oracle, and the best setting."""
+    w = datagen.small(62, 3200, 6, k=300, p=4, comps=4, dtype=np.float64)
+    print("approx k-balance n=3200 d=6 p=4", flush=True)
+    params = [krr.Params(sigma=s_, lam=1e-3, prec="fp64") for s_ in (0.8, 2.0)]
+    models, info, st, oms, X, a = _fit_both(ctx, dev, w, 4, params, method="kbalance_approx", iters=6, seed=19)
+    assert st == 0
+    _, ao = O.kbalance_approx(w.X, 4, 6, 19)
+    np.testing.assert_array_equal(a, ao)
+    assert sorted(int(i["m"]) for i in info[:4]) == [800] * 4   # p^2 divides n
+    for q in range(2):
+        for j in range(4):
+            assert _rel(models[q].alpha(j).cpu().numpy(), oms[q].alphas[j]) < 1e-10, (q, j)
+        yhat = ctx.predict(models[q], _t(w.Xt, dev)).cpu().numpy()
+        yo, _ = O.predict(oms[q], w.Xt)
+        assert _pred_rel(yhat, yo, w.yt) < 1e-10
+    mse, best = ctx.select(models, _t(w.Xt, dev), _t(w.yt, dev))
+    mo = [O.mse(O.predict(om, w.Xt)[0], w.yt) for om in oms]
+    np.testing.assert_allclose(mse, mo, rtol=1e-10)
+    assert best == O.select(mo)
+
+
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_label_route_selection_is_the_lower_bound(ctx, dev, dtype):
     """BKRR3 / KKRR3 (Algorithm 6): per held-out point the partition model
