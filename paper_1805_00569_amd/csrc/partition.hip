@@ -279,19 +279,37 @@ __global__ __launch_bounds__(1024) void k_group_scan(const int32_t* __restrict__
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int64_t per = (nblocks + 63) / 64;
   const int64_t b0 = min(nblocks, lane * per), b1 = min(nblocks, b0 + per);
+  constexpr int SCAN_REG = 8;   // a lane's counts kept in registers when it has at most this many
   for (int j = w; j < p; j += nw) {
+    int32_t cr[SCAN_REG];
     int64_t sum = 0;
-    for (int64_t b = b0; b < b1; ++b) sum += blockcounts[b * p + j];
+    if (per <= SCAN_REG) {
+#pragma unroll
+      for (int u = 0; u < SCAN_REG; ++u) cr[u] = (b0 + u < b1) ? blockcounts[(b0 + u) * p + j] : 0;
+#pragma unroll
+      for (int u = 0; u < SCAN_REG; ++u) sum += cr[u];
+    } else {
+      for (int64_t b = b0; b < b1; ++b) sum += blockcounts[b * p + j];
+    }
     int64_t x = sum;   // inclusive scan over the lanes
     for (int off = 1; off < 64; off <<= 1) {
       const int64_t y = __shfl_up(x, off, 64);
       if (lane >= off) x += y;
     }
     int64_t run = x - sum;
-    for (int64_t b = b0; b < b1; ++b) {
-      const int32_t c = blockcounts[b * p + j];
-      blockoffs[b * p + j] = (int32_t)run;
-      run += c;
+    if (per <= SCAN_REG) {
+#pragma unroll
+      for (int u = 0; u < SCAN_REG; ++u)
+        if (b0 + u < b1) {
+          blockoffs[(b0 + u) * p + j] = (int32_t)run;
+          run += cr[u];
+        }
+    } else {
+      for (int64_t b = b0; b < b1; ++b) {
+        const int32_t c = blockcounts[b * p + j];
+        blockoffs[b * p + j] = (int32_t)run;
+        run += c;
+      }
     }
     if (lane == 63) {
       tot[j] = x;
