@@ -446,7 +446,15 @@ __global__ __launch_bounds__(MEANS_THREADS) void k_means_total(const double* __r
   const int b0 = boff[j], b1 = boff[j + 1];
   for (int f = threadIdx.x; f < d; f += MEANS_THREADS) {
     double acc = 0.0;
-    for (int b = b0; b < b1; ++b) acc = add_sep(acc, part[(int64_t)b * d + f]);
+    int b = b0;
+    for (; b + 8 <= b1; b += 8) {   // 8 independent loads, then 8 ordered adds
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(b + u) * d + f];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = add_sep(acc, v[u]);
+    }
+    for (; b < b1; ++b) acc = add_sep(acc, part[(int64_t)b * d + f]);
     const double v = acc / (double)cnt;
     C[(int64_t)j * d + f] = v;
     if (CT != nullptr) CT[(int64_t)f * gridDim.x + j] = v;
