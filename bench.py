@@ -60,7 +60,7 @@ TRAFFIC = {
         "kernel": "k_panel_col",
         "source": "paper_1805_00569_amd/csrc/cholesky.hip",
         "sha256": "a75a9d35cd55ecaa37e06a7a2a8ba64045018d7cd4d7da2887fb98b2f6d30ba0",
-        "fetch_kib": 118993.0, "write_kib": 79707.4, "fetch_scale": 2.0, "write_scale": 1.0,
+        "fetch_kib": 118856.3, "write_kib": 79706.3, "fetch_scale": 2.0, "write_scale": 1.0,
     },
 }
 
