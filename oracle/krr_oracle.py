@@ -28,13 +28,13 @@ Readings taken where the paper is silent (each is listed in the design notes):
   multiply-add).  Comparisons use the squared value; ties go to the lowest
   centre index (the strict "<" over ascending j of Algorithm 4).
 * K-means initialisation ("randomly" in Algorithm 2) is k-means++ (D^2
-  sampling) driven by SplitMix64 uniforms; cumulative D^2 weights are formed
-  in blocks of 256 points (sequential inside a block, block totals summed
-  sequentially, one final add), see ``kmeanspp``.
+  sampling) driven by SplitMix64 uniforms; the cumulative D^2 weight is the
+  plain sequential running sum in point order, see ``kmeanspp``.
 * Lloyd stops after ``iters`` passes or when no assignment changed; an empty
   cluster keeps its previous centre; the returned partition is the assignment
   to the final centres.
-* Member sums for means are sequential in increasing point index.
+* Member sums for means are one sequential FP64 running sum per (cluster,
+  feature) over the members in increasing point index, then one division.
 * K-balance capacity is ceil(n/p); the recompute of centres (optional in the
   paper) is done.
 * The approximate parallel K-balance (Section 4.3, after Algorithm 4) splits
@@ -58,7 +58,6 @@ import scipy.linalg
 
 MASK64 = (1 << 64) - 1
 GOLDEN_GAMMA = 0x9E3779B97F4A7C15
-KMPP_BLOCK = 256
 
 STATUS_OK, STATUS_NOT_SPD = 0, -4
 
@@ -120,52 +119,50 @@ def assign(X: np.ndarray, C: np.ndarray):
 # K-means (Algorithm 2) with k-means++ initialisation
 # ---------------------------------------------------------------------------
 
-def blocked_cumsum(w: np.ndarray, block: int = KMPP_BLOCK) -> np.ndarray:
-    """Inclusive prefix sums of w: sequential inside each block of `block`
-    entries, block totals summed sequentially, then one add of the block
-    offset to each in-block prefix."""
-    n = w.shape[0]
-    S = np.empty(n, dtype=np.float64)
-    offset = 0.0
-    for b0 in range(0, n, block):
-        inner = np.cumsum(w[b0:b0 + block])        # sequential accumulate
-        S[b0:b0 + block] = offset + inner
-        offset = offset + inner[-1]
-    return S
+def running_sum(w: np.ndarray) -> np.ndarray:
+    """Inclusive prefix sums S_i = (...((w_0 + w_1) + w_2) ... + w_i), FP64,
+    one rounding per addition, strictly in index order.  (NumPy's
+    add.accumulate is this left-to-right recurrence; np.sum is pairwise and
+    is not used for it.)"""
+    return np.add.accumulate(np.asarray(w, dtype=np.float64))
 
 
-def kmeanspp(X: np.ndarray, k: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+def kmeanspp(X: np.ndarray, k: int, seed: int, trace: list | None = None) -> tuple[np.ndarray, np.ndarray]:
     """k-means++ seeding.  First centre: point floor(u_0 n).  Centre t: the
-    smallest i whose cumulative D^2 weight exceeds u_t * (total weight), where
-    D^2 is the squared distance to the nearest centre chosen so far.  Returns
-    (centres k x d FP64, chosen indices)."""
+    smallest i whose cumulative D^2 weight S_i exceeds u_t * S_{n-1}, where
+    D^2 is the squared distance to the nearest centre chosen so far and S is
+    the sequential running sum in point order.  Returns (centres k x d FP64,
+    chosen indices).  `trace` (optional list) receives, for t >= 1, a dict
+    with the threshold, the total and the running sums just below and at the
+    pick (for checking how far a decision is from a rounding tie)."""
     X = np.asarray(X, dtype=np.float64)
     n = X.shape[0]
     u = uniforms(seed, k)
     chosen = [min(int(math.floor(u[0] * n)), n - 1)]
     D2 = dist2(X, X[chosen[0]][None, :])[:, 0]
     for t in range(1, k):
-        S = blocked_cumsum(D2)
+        S = running_sum(D2)
         total = S[-1]
         if not total > 0.0:
             i = min(int(math.floor(u[t] * n)), n - 1)
+            thr = None
         else:
             thr = u[t] * total
             i = int(np.argmax(S > thr))      # first index with S_i > thr
+        if trace is not None:
+            trace.append({"t": t, "pick": i, "thr": thr, "total": float(total),
+                          "below": float(S[i - 1]) if i > 0 else 0.0, "at": float(S[i])})
         chosen.append(i)
         D2 = np.minimum(D2, dist2(X, X[i][None, :])[:, 0])
     return X[chosen].copy(), np.array(chosen, dtype=np.int64)
 
 
-MEANS_BLOCK = 256
-
-
 def member_means(X: np.ndarray, a: np.ndarray, C_prev: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
     """Algorithm 2 mean step: CT_j = (sum of members) / count_j; an empty
     cluster keeps C_prev[j].  Algorithm 2 leaves the order of the sum open;
-    here the members, in increasing index order, are summed in blocks of
-    MEANS_BLOCK consecutive members (sequentially inside a block), and the
-    block totals are summed sequentially."""
+    here it is one running FP64 sum per (cluster, feature) over the members
+    in increasing point index (left to right, one rounding per addition),
+    then one division by the count."""
     X = np.asarray(X, dtype=np.float64)
     k = C_prev.shape[0]
     C = C_prev.copy()
@@ -174,10 +171,7 @@ def member_means(X: np.ndarray, a: np.ndarray, C_prev: np.ndarray) -> tuple[np.n
         if counts[j] == 0:
             continue
         members = X[a == j]                          # increasing index order
-        total = np.zeros(X.shape[1])
-        for b0 in range(0, members.shape[0], MEANS_BLOCK):
-            block = np.cumsum(members[b0:b0 + MEANS_BLOCK], axis=0)[-1]   # sequential accumulate
-            total = total + block
+        total = np.add.accumulate(members, axis=0)[-1]   # sequential down each feature column
         C[j] = total / float(counts[j])
     return C, counts
 
@@ -200,8 +194,9 @@ def lloyd(X: np.ndarray, C0: np.ndarray, iters: int):
     return C, a, len(deltas), deltas
 
 
-def kmeans(X, k, iters, seed):
-    C0, _ = kmeanspp(X, k, seed)
+def kmeans(X, k, iters, seed, trace: list | None = None):
+    """k-means++ seeding, then Lloyd (Algorithm 2); `trace` as in kmeanspp."""
+    C0, _ = kmeanspp(X, k, seed, trace)
     C, a, _, _ = lloyd(X, C0, iters)
     return C, a
 
@@ -227,10 +222,10 @@ def kbalance_greedy(X: np.ndarray, C: np.ndarray, cap: int) -> np.ndarray:
     return MB
 
 
-def kbalance(X, p, iters, seed):
+def kbalance(X, p, iters, seed, trace: list | None = None):
     """K-balance (Algorithm 4): K-means centres, greedy capacity-ceil(n/p)
     pass, then centres recomputed as member means."""
-    C, _ = kmeans(X, p, iters, seed)
+    C, _ = kmeans(X, p, iters, seed, trace)
     n = X.shape[0]
     cap = -(-n // p)
     MB = kbalance_greedy(X, C, cap)

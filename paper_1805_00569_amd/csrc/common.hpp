@@ -196,8 +196,7 @@ void assign_nearest(krr_ctx ctx, hipStream_t s, const void* X, int dtype, int64_
                     const double* C, int p, int32_t* out, const int32_t* prev, int32_t* delta,
                     const int32_t* skip);
 void group_by_key(krr_ctx ctx, hipStream_t s, const int32_t* key, int64_t n, int p,
-                  int32_t* perm, int64_t* offsets, int64_t* sizes64, const int32_t* skip,
-                  int32_t* mboff = nullptr);
+                  int32_t* perm, int64_t* offsets, int64_t* sizes64, const int32_t* skip);
 void gather_rows(krr_ctx ctx, hipStream_t s, const void* X, int dtype, int64_t n, int d,
                  const int32_t* perm, void* Xout);
 void gather_vec_f64(krr_ctx ctx, hipStream_t s, const void* y, int dtype, int64_t n,

@@ -18,7 +18,6 @@ namespace krr {
 namespace {
 
 constexpr int GROUP_BLOCK = 256;
-constexpr int MEANS_BLOCK = 256;   // members per block of the mean step's sums
 constexpr int KPP_BLOCK = 256;   // k-means++ cumulative-weight block
 constexpr int ACH = 4;           // centres per register chunk in assignment
 constexpr int AROWS = 64;        // rows per assignment block (one per lane)
@@ -265,14 +264,11 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_group_local(const int32_t* __re
 
 // Per key j: exclusive prefix of the per-block counts (block offsets) and the
 // total; one wave per key (lane l takes a contiguous run of blocks, then a
-// 64-lane scan of the run sums).  Then the key offsets in key order and
-// (mboff, nullable) the mean step's member-block offsets: mboff[j] = number
-// of MEANS_BLOCK-member blocks of the keys < j.
+// 64-lane scan of the run sums).  Then the key offsets in key order.
 __global__ __launch_bounds__(1024) void k_group_scan(const int32_t* __restrict__ blockcounts, int64_t nblocks,
                                                      int p, int32_t* __restrict__ blockoffs,
                                                      int64_t* __restrict__ offsets,
                                                      int64_t* __restrict__ sizes64,
-                                                     int32_t* __restrict__ mboff,
                                                      const int32_t* __restrict__ skip) {
   if (skip != nullptr && *skip) return;
   extern __shared__ int64_t tot[];
@@ -319,17 +315,11 @@ __global__ __launch_bounds__(1024) void k_group_scan(const int32_t* __restrict__
   __syncthreads();
   if (threadIdx.x == 0) {
     int64_t o = 0;
-    int32_t mb = 0;
     for (int j = 0; j < p; ++j) {
       offsets[j] = o;
       o += tot[j];
-      if (mboff != nullptr) {
-        mboff[j] = mb;
-        mb += (int32_t)((tot[j] + MEANS_BLOCK - 1) / MEANS_BLOCK);
-      }
     }
     offsets[p] = o;
-    if (mboff != nullptr) mboff[p] = mb;
   }
 }
 
@@ -347,117 +337,104 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_group_scatter(const int32_t* __
 }
 
 // ---------------------------------------------------------------------------
-// Means of the grouped members: C[j][f] = (sum of member values) / count_j,
-// FP64; empty partitions keep their centre.  The members of partition j, in
-// increasing point order (the stable grouping perm), are summed in blocks of
-// MEANS_BLOCK consecutive members, sequentially inside a block, and the block
-// totals are summed in block order.  Three launches: block offsets per
-// partition, one workgroup per (partition, block) for the partial sums (rows
-// read through perm, no gathered copy), and the per-partition totals.
-// Lloyd passes: `skip` is this pass's "fixed point reached" flag; block 0 of
-// the final launch writes the next pass's flag (set when this pass was
-// skipped or changed no assignment), so no workgroup of a launch reads a flag
-// that the same launch writes.
+// Means of the grouped members (Algorithm 2's mean step): C[j][f] = (sum of
+// the member values) / count_j in FP64, one running sum per (partition,
+// feature) over the members in increasing point order (the stable grouping
+// perm), one rounding per addition; an empty partition keeps its centre.
+// Workgroup (j, slice) = (blockIdx.x / nsl, blockIdx.x % nsl) owns features
+// [64 slice, 64 slice + 64).  Chunks of MS_CH member rows are staged in LDS
+// (double-buffered; all four waves load, lane = feature, so each row's
+// features are one coalesced load), and wave 0 adds them in order, lane f
+// carrying feature f's sum: the additions of a chunk overlap the loads of
+// the next.  The member indices of chunk c + 2 are fetched while chunk c is
+// summed.  Lloyd passes: `skip` is this pass's "fixed point reached" flag;
+// workgroup 0 writes the next pass's flag (set when this pass was skipped or
+// changed no assignment), so no workgroup of a launch reads a flag that the
+// same launch writes.  CT (nullable) receives the centres transposed (d x p).
 // ---------------------------------------------------------------------------
-constexpr int MEANS_THREADS = 128;
-
-// boff[j] = number of member blocks of partitions < j (boff[p] = total)
-__global__ __launch_bounds__(1024) void k_means_blockoff(const int64_t* __restrict__ offsets, int p,
-                                                         int32_t* __restrict__ boff,
-                                                         const int32_t* __restrict__ skip) {
-  if (skip != nullptr && *skip) return;
-  __shared__ int32_t sc[1024];
-  const int t = threadIdx.x;
-  const int nb = t < p ? (int)((offsets[t + 1] - offsets[t] + MEANS_BLOCK - 1) / MEANS_BLOCK) : 0;
-  sc[t] = nb;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {   // inclusive scan
-    const int v = t >= off ? sc[t - off] : 0;
-    __syncthreads();
-    sc[t] += v;
-    __syncthreads();
-  }
-  if (t < p) boff[t + 1] = sc[t];
-  if (t == 0) boff[0] = 0;
-}
+constexpr int MS_THREADS = 256;
 
 template <typename TX>
-__global__ __launch_bounds__(MEANS_THREADS) void k_means_partial(const TX* __restrict__ X, int d,
-                                                                 const int32_t* __restrict__ perm,
-                                                                 const int64_t* __restrict__ offsets, int p,
-                                                                 const int32_t* __restrict__ boff,
-                                                                 double* __restrict__ part,
-                                                                 const int32_t* __restrict__ skip) {
-  if (skip != nullptr && *skip) return;
-  const int g = blockIdx.x;
-  if (g >= boff[p]) return;
-  int lo = 0, hi = p - 1;   // partition j: boff[j] <= g < boff[j + 1]
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (boff[mid] <= g) lo = mid;
-    else hi = mid - 1;
-  }
-  const int j = lo;
-  const int64_t r0 = offsets[j] + (int64_t)(g - boff[j]) * MEANS_BLOCK;
-  const int nr = (int)min<int64_t>(MEANS_BLOCK, offsets[j + 1] - r0);
-  __shared__ int64_t rows[MEANS_BLOCK];
-  for (int q = threadIdx.x; q < MEANS_BLOCK; q += MEANS_THREADS)
-    rows[q] = (int64_t)perm[r0 + min(q, nr - 1)] * d;   // clamped: in range, never summed past nr
-  __syncthreads();
-  for (int f = threadIdx.x; f < d; f += MEANS_THREADS) {
-    double acc = 0.0;
-    int q = 0;
-    for (; q + 32 <= nr; q += 32) {   // 32 independent loads, then 32 ordered adds
-      double v[32];
-#pragma unroll
-      for (int u = 0; u < 32; ++u) v[u] = (double)X[rows[q + u] + f];
-#pragma unroll
-      for (int u = 0; u < 32; ++u) acc = add_sep(acc, v[u]);
-    }
-    for (; q + 8 <= nr; q += 8) {
-      double v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = (double)X[rows[q + u] + f];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc = add_sep(acc, v[u]);
-    }
-    for (; q < nr; ++q) acc = add_sep(acc, (double)X[rows[q] + f]);
-    part[(int64_t)g * d + f] = acc;
-  }
-}
+struct MeansChunk {
+  static constexpr int CH = sizeof(TX) == 4 ? 256 : 128;   // member rows per staged chunk (64 KiB)
+};
 
-// C_j = (sum of the member-block partials in order) / count_j, for partition
-// j = blockIdx.x; CT (nullable) receives the same values transposed (d x p),
-// so the next assignment pass needs no transpose of its own.
-__global__ __launch_bounds__(MEANS_THREADS) void k_means_total(const double* __restrict__ part, int d,
-                                                               const int64_t* __restrict__ offsets,
-                                                               const int32_t* __restrict__ boff,
-                                                               double* __restrict__ C, double* __restrict__ CT,
-                                                               const int32_t* __restrict__ skip,
-                                                               const int32_t* __restrict__ delta,
-                                                               int32_t* __restrict__ done_next) {
+template <typename TX>
+__global__ __launch_bounds__(MS_THREADS) void k_means_seq(const TX* __restrict__ X, int d, int nsl,
+                                                           const int32_t* __restrict__ perm,
+                                                           const int64_t* __restrict__ offsets, int p,
+                                                           double* __restrict__ C, double* __restrict__ CT,
+                                                           const int32_t* __restrict__ skip,
+                                                           const int32_t* __restrict__ delta,
+                                                           int32_t* __restrict__ done_next) {
+  constexpr int CH = MeansChunk<TX>::CH;
+  constexpr int PER = CH * 64 / MS_THREADS;   // staged elements per thread and chunk
   const int skipped = (skip != nullptr) ? *skip : 0;
   if (done_next != nullptr && blockIdx.x == 0 && threadIdx.x == 0)
     *done_next = (skipped || *delta == 0) ? 1 : 0;
   if (skipped) return;
-  const int j = blockIdx.x;
-  const int64_t cnt = offsets[j + 1] - offsets[j];
+  const int j = blockIdx.x / nsl, f0 = (blockIdx.x - j * nsl) * 64;
+  const int64_t base = offsets[j];
+  const int64_t cnt = offsets[j + 1] - base;
   if (cnt == 0) return;
-  const int b0 = boff[j], b1 = boff[j + 1];
-  for (int f = threadIdx.x; f < d; f += MEANS_THREADS) {
-    double acc = 0.0;
-    int b = b0;
-    for (; b + 8 <= b1; b += 8) {   // 8 independent loads, then 8 ordered adds
-      double v[8];
+  __shared__ __align__(16) TX sX[2][CH * 64];
+  __shared__ int32_t sP[2][CH];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int fl = min(f0 + lane, d - 1);            // clamped feature: lanes past d load a valid value, never summed
+  const int64_t nch = (cnt + CH - 1) / CH;
+  // member index of chunk row r (clamped to the last member: in range, never summed)
+  auto member = [&](int64_t c, int r) { return perm[base + min<int64_t>(c * CH + r, cnt - 1)]; };
+  for (int r = t; r < CH; r += MS_THREADS) sP[0][r] = member(0, r);
+  __syncthreads();
+  {
+    TX v[PER];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(b + u) * d + f];
+    for (int u = 0; u < PER; ++u) v[u] = X[(int64_t)sP[0][w + 4 * u] * d + fl];
+    for (int r = t; r < CH; r += MS_THREADS) sP[1][r] = member(min<int64_t>(1, nch - 1), r);
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc = add_sep(acc, v[u]);
+    for (int u = 0; u < PER; ++u) sX[0][(w + 4 * u) * 64 + lane] = v[u];
+  }
+  __syncthreads();
+  double acc = 0.0;
+  for (int64_t c = 0; c < nch; ++c) {
+    const int cur = (int)(c & 1), nxt = cur ^ 1;
+    const bool more = c + 1 < nch;
+    TX v[PER];
+    int32_t pn[CH / MS_THREADS + 1];
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < PER; ++u) v[u] = X[(int64_t)sP[nxt][w + 4 * u] * d + fl];
+#pragma unroll
+      for (int q = 0; q * MS_THREADS < CH; ++q)
+        if (t + q * MS_THREADS < CH) pn[q] = member(min<int64_t>(c + 2, nch - 1), t + q * MS_THREADS);
     }
-    for (; b < b1; ++b) acc = add_sep(acc, part[(int64_t)b * d + f]);
-    const double v = acc / (double)cnt;
-    C[(int64_t)j * d + f] = v;
-    if (CT != nullptr) CT[(int64_t)f * gridDim.x + j] = v;
+    if (w == 0) {
+      const int nr = (int)min<int64_t>(CH, cnt - c * CH);
+      const TX* col = &sX[cur][lane];
+      int r = 0;
+      for (; r + 16 <= nr; r += 16) {   // 16 LDS loads, then 16 ordered adds
+        double x[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) x[u] = (double)col[(r + u) * 64];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc = add_sep(acc, x[u]);
+      }
+      for (; r < nr; ++r) acc = add_sep(acc, (double)col[r * 64]);
+    }
+    if (more) {
+      // sX[nxt] and sP[cur] were last read before the previous barrier
+#pragma unroll
+      for (int u = 0; u < PER; ++u) sX[nxt][(w + 4 * u) * 64 + lane] = v[u];
+#pragma unroll
+      for (int q = 0; q * MS_THREADS < CH; ++q)
+        if (t + q * MS_THREADS < CH) sP[cur][t + q * MS_THREADS] = pn[q];
+    }
+    __syncthreads();
+  }
+  if (w == 0 && f0 + lane < d) {
+    const double val = acc / (double)cnt;
+    C[(int64_t)j * d + f0 + lane] = val;
+    if (CT != nullptr) CT[(int64_t)(f0 + lane) * p + j] = val;
   }
 }
 
@@ -1039,29 +1016,14 @@ void assign_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, const d
   check_launch(ctx, s, "assign");
 }
 
-// boff_in (nullable): the member-block offsets, already written by the
-// grouping (group_by_key's mboff); otherwise computed here.
 template <typename TX>
-void means_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int d, const int32_t* perm, const int64_t* offsets,
-             double* C, double* CT, int p, const int32_t* skip, const int32_t* delta, int32_t* done_next,
-             const int32_t* boff_in = nullptr) {
+void means_t(krr_ctx ctx, hipStream_t s, const TX* X, int d, const int32_t* perm, const int64_t* offsets,
+             double* C, double* CT, int p, const int32_t* skip, const int32_t* delta, int32_t* done_next) {
   KernelTimer kt(ctx, s, "lloyd_means", 0.0, 0);
-  const int64_t max_blocks = ceil_div(n, MEANS_BLOCK) + p;   // sum over partitions of ceil(m_j / MEANS_BLOCK)
-  char* w = (char*)ws_get(ctx, "means", (size_t)max_blocks * d * 8 + (size_t)(p + 1) * 4 + 256);
-  double* part = (double*)w;
-  const int32_t* boff = boff_in;
-  if (boff == nullptr) {
-    int32_t* bw = (int32_t*)(w + (((size_t)max_blocks * d * 8 + 255) & ~size_t(255)));
-    hipLaunchKernelGGL(k_means_blockoff, dim3(1), dim3(1024), 0, s, offsets, p, bw, skip);
-    check_launch(ctx, s, "means_blockoff");
-    boff = bw;
-  }
-  hipLaunchKernelGGL((k_means_partial<TX>), dim3((unsigned)max_blocks), dim3(MEANS_THREADS), 0, s, X, d, perm,
-                     offsets, p, boff, part, skip);
-  check_launch(ctx, s, "means_partial");
-  hipLaunchKernelGGL(k_means_total, dim3((unsigned)p), dim3(MEANS_THREADS), 0, s, (const double*)part, d, offsets,
-                     boff, C, CT, skip, delta, done_next);
-  check_launch(ctx, s, "means_total");
+  const int nsl = (int)ceil_div(d, 64);
+  hipLaunchKernelGGL((k_means_seq<TX>), dim3((unsigned)(p * nsl)), dim3(MS_THREADS), 0, s, X, d, nsl, perm, offsets,
+                     p, C, CT, skip, delta, done_next);
+  check_launch(ctx, s, "means");
 }
 
 template <typename TX>
@@ -1112,7 +1074,7 @@ void assign_nearest(krr_ctx ctx, hipStream_t s, const void* X, int dtype, int64_
 }
 
 void group_by_key(krr_ctx ctx, hipStream_t s, const int32_t* key, int64_t n, int p, int32_t* perm,
-                  int64_t* offsets, int64_t* sizes64, const int32_t* skip, int32_t* mboff) {
+                  int64_t* offsets, int64_t* sizes64, const int32_t* skip) {
   const int64_t nblk = ceil_div(n, GROUP_BLOCK);
   KernelTimer kt(ctx, s, "group", 0.0, 0);
   char* w = (char*)ws_get(ctx, "group", (size_t)n * 4 + (size_t)nblk * p * 8 + 64);
@@ -1124,7 +1086,7 @@ void group_by_key(krr_ctx ctx, hipStream_t s, const int32_t* key, int64_t n, int
                      skip);
   check_launch(ctx, s, "group_local");
   hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(std::min(1024, 64 * p)), (size_t)p * 8, s,
-                     (const int32_t*)bc, nblk, p, bo, offsets, sizes64, mboff, skip);
+                     (const int32_t*)bc, nblk, p, bo, offsets, sizes64, skip);
   check_launch(ctx, s, "group_scan");
   hipLaunchKernelGGL(k_group_scatter, dim3(nblk), dim3(GROUP_BLOCK), 0, s, key, n, p, (const int32_t*)rank,
                      (const int32_t*)bo, (const int64_t*)offsets, perm, skip);
@@ -1161,21 +1123,19 @@ static void partition_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int 
     int32_t* perm = (int32_t*)w;
     int64_t* off = (int64_t*)(perm + n + (n & 1));
     group_by_key(ctx, s, assign, n, p, perm, off, nullptr, nullptr);
-    means_t(ctx, s, X, n, d, perm, off, C, nullptr, p, nullptr, nullptr, nullptr);
+    means_t(ctx, s, X, d, perm, off, C, nullptr, p, nullptr, nullptr, nullptr);
   } else if (method == KRR_PART_GIVEN) {
     transpose_centroids(ctx, s, C, p, d, CT);
     assign_t(ctx, s, X, n, d, CT, p, assign, nullptr, nullptr, nullptr, nullptr, false);
   } else {
     // K-means: k-means++ seeding then Lloyd passes (Algorithm 2).
     kmeanspp_t(ctx, s, X, n, d, p, seed, C);
-    char* w = (char*)ws_get(ctx, "lloyd", (size_t)n * 8 + (size_t)(p + 1) * 8 + (size_t)(2 * iters + 4) * 4 +
-                                              (size_t)(p + 1) * 4 + 64);
+    char* w = (char*)ws_get(ctx, "lloyd", (size_t)n * 8 + (size_t)(p + 1) * 8 + (size_t)(2 * iters + 4) * 4 + 64);
     int32_t* perm = (int32_t*)w;
     int32_t* prev = perm + n;
     int64_t* off = (int64_t*)(prev + n + (n & 1));
     int32_t* deltas = (int32_t*)(off + p + 1);
     int32_t* done = deltas + iters + 1;   // done[it]: pass `it` is past the fixed point
-    int32_t* mboff = done + iters + 2;    // member-block offsets of the mean step (p + 1)
     const int64_t nflags = 2 * (int64_t)iters + 3;
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)ceil_div(nflags, 64)), dim3(64), 0, s, deltas, nflags, 0);
     check_launch(ctx, s, "fill");
@@ -1185,8 +1145,8 @@ static void partition_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int 
     transpose_centroids(ctx, s, C, p, d, CT);
     for (int it = 0; it < iters; ++it) {
       assign_t(ctx, s, X, n, d, CT, p, cur, nullptr, it == 0 ? nullptr : old, deltas + it, done + it, false);
-      group_by_key(ctx, s, cur, n, p, perm, off, nullptr, done + it, mboff);
-      means_t(ctx, s, X, n, d, perm, off, C, CT, p, done + it, deltas + it, done + it + 1, mboff);
+      group_by_key(ctx, s, cur, n, p, perm, off, nullptr, done + it);
+      means_t(ctx, s, X, d, perm, off, C, CT, p, done + it, deltas + it, done + it + 1);
       std::swap(cur, old);
     }
     assign_t(ctx, s, X, n, d, CT, p, assign, nullptr, nullptr, nullptr, nullptr, false);
@@ -1231,7 +1191,7 @@ static void partition_t(krr_ctx ctx, hipStream_t s, const TX* X, int64_t n, int 
       }
       KRR_HIP(hipMemcpyAsync(assign, MB, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
       group_by_key(ctx, s, assign, n, p, perm, off, nullptr, nullptr);
-      means_t(ctx, s, X, n, d, perm, off, C, nullptr, p, nullptr, nullptr, nullptr);
+      means_t(ctx, s, X, d, perm, off, C, nullptr, p, nullptr, nullptr, nullptr);
     }
   }
   // sizes: histogram of the final assignment

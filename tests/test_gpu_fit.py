@@ -2,8 +2,9 @@
 
 Tolerances: FP64 path 1e-10 relative on alpha and predictions; mixed path
 1e-6 relative after refinement (FP64 residual), as the design requires; FP32
-path bounded by a multiple of kappa * m * u32.  Relative errors of
-predictions are taken against max(||yhat_ref||, 1e-3 ||y_test||) so that a
+path bounded by a multiple of kappa * m * u32.  Every comparison is element
+by element (max |a - b| over max |b|, see tests/_parity.py); errors of
+predictions are scaled by max(max|yhat_ref|, 1e-3 max|y_test|) so that a
 model whose predictions are all ~0 (kernel ~ identity) is judged against the
 scale of the labels."""
 import math
@@ -14,22 +15,13 @@ import torch
 
 import oracle as O
 from paper_1805_00569_amd import datagen, krr
+from _parity import ew, pred_ew
 
 pytestmark = pytest.mark.gpu
 
 
 def _t(a, dev):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-
-
-def _rel(a, b):
-    b = np.asarray(b)
-    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
-
-
-def _pred_rel(yhat, yref, ytrue):
-    den = max(np.linalg.norm(yref), 1e-3 * np.linalg.norm(ytrue), 1e-300)
-    return float(np.linalg.norm(yhat - yref) / den)
 
 
 def _fit_both(ctx, dev, w, p, params, method="given", centroids=None, iters=10, seed=0):
@@ -54,10 +46,10 @@ def test_plain_single_partition_fp64(ctx, dev):
     models, info, st, oms, X, _ = _fit_both(ctx, dev, w, 1, params, centroids=np.zeros((1, 16)))
     assert st == 0 and info[0]["status"] == 0 and info[0]["m"] == 2048
     alpha = models[0].alpha(0).cpu().numpy()
-    assert _rel(alpha, oms[0].alphas[0]) < 1e-10
+    assert ew(alpha, oms[0].alphas[0]) < 1e-10
     yhat = ctx.predict(models[0], _t(w.Xt, dev)).cpu().numpy()
     yo, _ = O.predict(oms[0], w.Xt)
-    assert _pred_rel(yhat, yo, w.yt) < 1e-10
+    assert pred_ew(yhat, yo, w.yt) < 1e-10
     mse, best = ctx.select(models, _t(w.Xt, dev), _t(w.yt, dev))
     assert best == 0 and abs(mse[0] - O.mse(yo, w.yt)) <= 1e-10 * O.mse(yo, w.yt)
 
@@ -79,11 +71,11 @@ def test_ragged_partitions_fp64(ctx, dev, n, d, p, panel):
         for j in range(p):
             assert info[q * p + j]["m"] == int((a == j).sum())
             alpha = models[q].alpha(j).cpu().numpy()
-            assert _rel(alpha, oms[q].alphas[j]) < 1e-10, (q, j)
+            assert ew(alpha, oms[q].alphas[j]) < 1e-10, (q, j)
         for route in ("nearest", "average", "all"):
             yhat = ctx.predict(models[q], _t(w.Xt, dev), route=route).cpu().numpy()
             yo, _ = O.predict(oms[q], w.Xt, route)
-            assert _pred_rel(yhat.ravel(), yo.ravel(), np.repeat(w.yt, p if route == "all" else 1)) < 1e-10, route
+            assert pred_ew(yhat.ravel(), yo.ravel(), np.repeat(w.yt, p if route == "all" else 1)) < 1e-10, route
     mse, best = ctx.select(models, _t(w.Xt, dev), _t(w.yt, dev))
     mo = [O.mse(O.predict(om, w.Xt)[0], w.yt) for om in oms]
     np.testing.assert_allclose(mse, mo, rtol=1e-10)
@@ -102,10 +94,10 @@ def test_dckrr_random_partition_average_route_fp64(ctx, dev):
     assert sorted(int(i["m"]) for i in info[:4]) == [750, 750, 750, 751]
     for q in range(2):
         for j in range(4):
-            assert _rel(models[q].alpha(j).cpu().numpy(), oms[q].alphas[j]) < 1e-10, (q, j)
+            assert ew(models[q].alpha(j).cpu().numpy(), oms[q].alphas[j]) < 1e-10, (q, j)
         yhat = ctx.predict(models[q], _t(w.Xt, dev), route="average").cpu().numpy()
         yo, _ = O.predict(oms[q], w.Xt, "average")
-        assert _pred_rel(yhat, yo, w.yt) < 1e-10
+        assert pred_ew(yhat, yo, w.yt) < 1e-10
     mse, best = ctx.select(models, _t(w.Xt, dev), _t(w.yt, dev), route="average")
     mo = [O.mse(O.predict(om, w.Xt, "average")[0], w.yt) for om in oms]
     np.testing.assert_allclose(mse, mo, rtol=1e-10)
@@ -126,10 +118,10 @@ def test_approx_kbalance_nearest_route_fp64(ctx, dev):
     assert sorted(int(i["m"]) for i in info[:4]) == [800] * 4   # p^2 divides n
     for q in range(2):
         for j in range(4):
-            assert _rel(models[q].alpha(j).cpu().numpy(), oms[q].alphas[j]) < 1e-10, (q, j)
+            assert ew(models[q].alpha(j).cpu().numpy(), oms[q].alphas[j]) < 1e-10, (q, j)
         yhat = ctx.predict(models[q], _t(w.Xt, dev)).cpu().numpy()
         yo, _ = O.predict(oms[q], w.Xt)
-        assert _pred_rel(yhat, yo, w.yt) < 1e-10
+        assert pred_ew(yhat, yo, w.yt) < 1e-10
     mse, best = ctx.select(models, _t(w.Xt, dev), _t(w.yt, dev))
     mo = [O.mse(O.predict(om, w.Xt)[0], w.yt) for om in oms]
     np.testing.assert_allclose(mse, mo, rtol=1e-10)
@@ -197,13 +189,14 @@ def test_polynomial_sigmoid_and_gaussian_settings_in_one_batch(ctx, dev, prec):
     tol = 1e-10 if prec == "fp64" else 1e-6
     for q in range(len(params)):
         for j in range(3):
-            assert _rel(models[q].alpha(j).cpu().numpy(), oms[q].alphas[j]) < tol, (q, j)
+            assert ew(models[q].alpha(j).cpu().numpy(), oms[q].alphas[j]) < tol, (q, j)
         yhat = ctx.predict(models[q], _t(w.Xt, dev)).cpu().numpy()
         yo, _ = O.predict(oms[q], w.Xt)
-        assert _pred_rel(yhat, yo, w.yt) < 10 * tol, q
+        assert pred_ew(yhat, yo, w.yt) < tol, q
     mse, best = ctx.select(models, _t(w.Xt, dev), _t(w.yt, dev))
     mo = [O.mse(O.predict(om, w.Xt)[0], w.yt) for om in oms]
-    np.testing.assert_allclose(mse, mo, rtol=10 * tol)
+    np.testing.assert_allclose(mse, mo, rtol=tol)
+    assert best == O.select(mo)
 
 
 def test_sigmoid_not_spd_reports_pivot(ctx, dev):
@@ -250,7 +243,7 @@ def test_fp32_path(ctx, dev):
     for j in range(2):
         Xj = w.X[a == j].astype(np.float64)
         kappa = np.linalg.cond(O.kernel_matrix(Xj, Xj, 3.0) + 0.1 * np.eye(Xj.shape[0]))
-        err = _rel(models[0].alpha(j).cpu().numpy(), oms[0].alphas[j])
+        err = ew(models[0].alpha(j).cpu().numpy(), oms[0].alphas[j])
         assert err < 20 * kappa * Xj.shape[0] * 6e-8, (err, kappa)
 
 
@@ -267,7 +260,7 @@ def test_mixed_precision_refines_to_1e6(ctx, dev, sigma):
     assert st == 0, info
     for j in range(2):
         assert info[j]["rel_residual"] <= 1e-8
-        err = _rel(models[0].alpha(j).cpu().numpy(), oms[0].alphas[j])
+        err = ew(models[0].alpha(j).cpu().numpy(), oms[0].alphas[j])
         assert err < 1e-6, err
         print(f"partition {j}: refine steps {info[j]['refine_iters']} fallback {info[j]['fallback']} "
               f"alpha err {err:.2e}", flush=True)
@@ -275,7 +268,7 @@ def test_mixed_precision_refines_to_1e6(ctx, dev, sigma):
             assert info[j]["fallback"] == 0
     yhat = ctx.predict(models[0], _t(w.Xt, dev)).cpu().numpy()
     yo, _ = O.predict(oms[0], w.Xt)
-    assert _pred_rel(yhat, yo, w.yt) < 1e-6
+    assert pred_ew(yhat, yo, w.yt) < 1e-6
 
 
 @pytest.mark.parametrize("panel", [1, 3, 16, 40])
@@ -299,7 +292,7 @@ def test_mixed_ragged_partitions_panels(ctx, dev, panel):
     for q in range(2):
         for j in range(5):
             assert info[q * 5 + j]["rel_residual"] <= 1e-8
-            assert _rel(models[q].alpha(j).cpu().numpy(), oms[q].alphas[j]) < 1e-6, (q, j)
+            assert ew(models[q].alpha(j).cpu().numpy(), oms[q].alphas[j]) < 1e-6, (q, j)
 
 
 _LARGE = {}
@@ -332,7 +325,7 @@ def test_large_system_backward_solve_from_global(ctx, dev, prec):
     models, info, st = ctx.fit(Xd, _t(yg, dev), a, C, 1,
                                [krr.Params(sigma=0.5, lam=1e-2, prec=prec, refine_tol=1e-8, max_refine=40)])
     assert st == 0 and info[0]["status"] == 0
-    err = _rel(models[0].alpha(0).cpu().numpy(), alpha_ref)
+    err = ew(models[0].alpha(0).cpu().numpy(), alpha_ref)
     assert err < (1e-10 if prec == "fp64" else 1e-6), err
 
 
@@ -353,7 +346,7 @@ def test_large_system_wide_panel(ctx, dev, prec):
     finally:
         ctx.set_option(krr.OPT_PANEL_TILES, 16)
     assert st == 0 and info[0]["status"] == 0
-    err = _rel(models[0].alpha(0).cpu().numpy(), alpha_ref)
+    err = ew(models[0].alpha(0).cpu().numpy(), alpha_ref)
     assert err < (1e-10 if prec == "fp64" else 1e-6), err
 
 
@@ -379,10 +372,10 @@ def test_large_and_small_systems_in_one_batch(ctx, dev, prec):
     models, info, st = ctx.fit(Xd, _t(yg, dev), a, C, 2, params)
     assert st == 0 and all(i["status"] == 0 for i in info)
     tol = 1e-10 if prec == "fp64" else 1e-6
-    assert _rel(models[0].alpha(0).cpu().numpy(), alpha_ref) < tol
+    assert ew(models[0].alpha(0).cpu().numpy(), alpha_ref) < tol
     for q, sg in enumerate((0.5, 0.8)):
         ref = O.fit_one(X2.astype(np.float64), y2.astype(np.float64), sg, 1e-2)["alpha"]
-        assert _rel(models[q].alpha(1).cpu().numpy(), ref) < tol, q
+        assert ew(models[q].alpha(1).cpu().numpy(), ref) < tol, q
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
@@ -411,7 +404,7 @@ def test_solve_paths_at_the_threshold(ctx, dev, prec):
     for q, sg in enumerate(sigmas):
         for j in range(2):
             ref = O.fit_one(Xs[j].astype(np.float64), ys[j].astype(np.float64), sg, 1e-2)["alpha"]
-            assert _rel(models[q].alpha(j).cpu().numpy(), ref) < tol, (q, j)
+            assert ew(models[q].alpha(j).cpu().numpy(), ref) < tol, (q, j)
 
 
 def test_linear_kernel_is_primal_ridge(ctx, dev):
@@ -436,7 +429,7 @@ def test_lambda_times_m(ctx, dev):
     params = [krr.Params(sigma=1.0, lam=1e-3, prec="fp64", lambda_times_m=True)]
     models, info, st, oms, X, a = _fit_both(ctx, dev, w, 2, params, method="kmeans", iters=3, seed=4)
     for j in range(2):
-        assert _rel(models[0].alpha(j).cpu().numpy(), oms[0].alphas[j]) < 1e-10
+        assert ew(models[0].alpha(j).cpu().numpy(), oms[0].alphas[j]) < 1e-10
 
 
 def test_not_spd_reports_pivot_and_keeps_others(ctx, dev):
@@ -518,11 +511,11 @@ def test_empty_and_tiny_partitions(ctx, dev):
     assert st == 0
     assert [info[j]["m"] for j in range(3)] == [69, 0, 1]
     for j in (0, 2):
-        assert _rel(models[0].alpha(j).cpu().numpy(), oms[0].alphas[j]) < 1e-10
+        assert ew(models[0].alpha(j).cpu().numpy(), oms[0].alphas[j]) < 1e-10
     for route in ("nearest", "average"):
         yhat = ctx.predict(models[0], _t(w.Xt, dev), route=route).cpu().numpy()
         yo, _ = O.predict(oms[0], w.Xt, route)
-        assert _pred_rel(yhat, yo, w.yt) < 1e-10
+        assert pred_ew(yhat, yo, w.yt) < 1e-10
 
 
 def test_fit_rejects_bad_arguments(ctx, dev):

@@ -1,12 +1,18 @@
 """Parity of the partition kernels with the oracle: assignment indices, the
-k-means++ / Lloyd centres and the K-balance memberships must be identical bit
-for bit on the same seeded inputs."""
+Lloyd centres (one sequential sum per cluster and feature on both sides) and
+the K-balance memberships must be identical bit for bit on the same seeded
+inputs.  The k-means++ picks are compared too; the GPU forms the cumulative
+D^2 weights in a different (blocked) order, so each test also checks that
+every pick of the oracle is further from a rounding tie than the bound of
+the two orders (``kpp_ambiguous`` in tests/_parity.py): there the picks must
+agree, and equal picks make every later step bit-exact."""
 import numpy as np
 import pytest
 import torch
 
 import oracle as O
 from paper_1805_00569_amd import datagen
+from _parity import kpp_ambiguous
 
 pytestmark = pytest.mark.gpu
 
@@ -38,18 +44,41 @@ def test_kmeans_seeding_and_lloyd_bitexact(ctx, dev):
     for iters in (0, 1, 7):
         print(f"kmeans iters={iters}", flush=True)
         C, a, sz = ctx.partition(_t(w.X, dev), 16, "kmeans", lloyd_iters=iters, seed=123)
-        C0, idx = O.kmeanspp(w.X, 16, 123)
+        tr = []
+        C0, idx = O.kmeanspp(w.X, 16, 123, tr)
+        assert kpp_ambiguous(tr, w.X.shape[0]) == 0
         Co, ao, _, _ = O.lloyd(w.X, C0, iters)
         np.testing.assert_array_equal(C.cpu().numpy(), Co)
         np.testing.assert_array_equal(a.cpu().numpy(), ao)
         np.testing.assert_array_equal(sz.cpu().numpy(), np.bincount(ao, minlength=16))
 
 
+@pytest.mark.parametrize("n,d,p,dtype", [(20000, 90, 3, np.float32), (9000, 130, 2, np.float64),
+                                         (3001, 7, 5, np.float64)])
+def test_lloyd_means_long_sequential_sums(ctx, dev, n, d, p, dtype):
+    """Clusters of thousands of members (many staged chunks of the mean step)
+    and more than 64 features (several feature slices): the Lloyd centres
+    equal the oracle's sequential member sums bit for bit."""
+    print(f"lloyd means n={n} d={d} p={p} {dtype.__name__}", flush=True)
+    g = np.random.default_rng(n + d)
+    X = (g.standard_normal((n, d)) * g.uniform(0.5, 2, d) + 3.0 * g.standard_normal((1, d))).astype(dtype)
+    C, a, sz = ctx.partition(_t(X, dev), p, "kmeans", lloyd_iters=4, seed=n)
+    tr = []
+    C0, _ = O.kmeanspp(X, p, n, tr)
+    assert kpp_ambiguous(tr, n) == 0
+    Co, ao, _, _ = O.lloyd(X, C0, 4)
+    np.testing.assert_array_equal(a.cpu().numpy(), ao)
+    np.testing.assert_array_equal(C.cpu().numpy(), Co)
+    assert sz.cpu().numpy().max() > 256   # several staged chunks of member rows
+
+
 def test_kbalance_bitexact(ctx, dev):
     w = datagen.balanced(seed=32, n=8192, k_test=16, p=16)
     print("kbalance n=8192 p=16", flush=True)
     C, a, sz = ctx.partition(_t(w.X, dev), 16, "kbalance", lloyd_iters=5, seed=7)
-    Co, ao = O.kbalance(w.X, 16, 5, 7)
+    tr = []
+    Co, ao = O.kbalance(w.X, 16, 5, 7, tr)
+    assert kpp_ambiguous(tr, w.X.shape[0]) == 0
     np.testing.assert_array_equal(a.cpu().numpy(), ao)
     np.testing.assert_array_equal(C.cpu().numpy(), Co)
     assert sz.cpu().numpy().tolist() == [512] * 16
@@ -137,7 +166,9 @@ def test_kmeans_converges_early(ctx, dev):
     # well separated clusters: Lloyd reaches a fixed point before the cap
     w = datagen.small(34, 2000, 4, comps=4, spread=50.0)
     C, a, _ = ctx.partition(_t(w.X, dev), 4, "kmeans", lloyd_iters=50, seed=1)
-    C0, _ = O.kmeanspp(w.X, 4, 1)
+    tr = []
+    C0, _ = O.kmeanspp(w.X, 4, 1, tr)
+    assert kpp_ambiguous(tr, w.X.shape[0]) == 0
     Co, ao, passes, deltas = O.lloyd(w.X, C0, 50)
     assert passes < 50
     np.testing.assert_array_equal(C.cpu().numpy(), Co)

@@ -3,8 +3,8 @@
 A resident BKRR2 model (K-balance partitions, nearest-centre route,
 Algorithm 5) answers predict requests; fit requests are independent
 problems (Eq. 6).  Checks: every result is the same alone and in a mix of
-concurrent requests (1e-12 relative; only the summation split of a
-prediction may differ), predictions and fits agree with the direct library
+concurrent requests (1e-12 relative, element by element; only the
+summation split of a prediction may differ), predictions and fits agree with the direct library
 calls and with the FP64 oracle at the FP32 path's bound, the admission budget
 is respected, and bad requests are rejected before queueing."""
 import numpy as np
@@ -13,15 +13,11 @@ import torch
 
 import oracle as O
 from paper_1805_00569_amd import datagen, krr
+from _parity import ew
 
 pytestmark = pytest.mark.gpu
 
 SIGMA, LAM = 2.0, 1e-2
-
-
-def _rel(a, b):
-    b = np.asarray(b)
-    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
 
 
 @pytest.fixture(scope="module")
@@ -57,7 +53,7 @@ def test_serve_alone_equals_mix(ctx, dev, resident):
 
         # direct library calls give the same numbers
         y_direct = ctx.predict(model, torch.from_numpy(q_alone).to(dev)).cpu().numpy()
-        assert _rel(y_alone, y_direct) < 1e-12
+        assert ew(y_alone, y_direct) < 1e-12
 
         # a burst of mixed requests with the two probes in the middle
         g = np.random.default_rng(11)
@@ -81,8 +77,8 @@ def test_serve_alone_equals_mix(ctx, dev, resident):
         y_mix, info_p = srv.wait(probes["p"])
         al_mix, info_f = srv.wait(probes["f"])
         assert info_p["status"] == 0 and info_f["status"] == 0
-        assert _rel(y_mix, y_alone) < 1e-12
-        assert _rel(al_mix, al_alone) < 1e-12
+        assert ew(y_mix, y_alone) < 1e-12
+        assert ew(al_mix, al_alone) < 1e-12
         batched = 0
         for t in tickets:
             out, inf = srv.wait(t[1])
@@ -90,7 +86,7 @@ def test_serve_alone_equals_mix(ctx, dev, resident):
             batched = max(batched, inf["batch_requests"])
             if t[0] == "predict":
                 ref = ctx.predict(model, torch.from_numpy(datagen.take_rows(pools.queries, t[3], t[2])).to(dev))
-                assert _rel(out, ref.cpu().numpy()) < 1e-12
+                assert ew(out, ref.cpu().numpy()) < 1e-12
         assert batched > 1, "no request was batched with another"
         s = srv.stats()
         assert s["predict_requests"] + s["fit_requests"] == 2 + 2 + len(tickets)
@@ -103,7 +99,7 @@ def test_serve_alone_equals_mix(ctx, dev, resident):
     om = O.fit(Xf, f_y.astype(np.float64), np.zeros(333, np.int32), np.zeros((1, 4)), 1, SIGMA, LAM,
                "gaussian", False)
     kappa = np.linalg.cond(O.kernel_matrix(Xf, Xf, SIGMA) + LAM * np.eye(333))
-    err = _rel(al_alone, om.alphas[0])
+    err = ew(al_alone, om.alphas[0])
     assert err < 20 * kappa * 333 * 6e-8, (err, kappa)
 
 

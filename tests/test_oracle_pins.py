@@ -101,24 +101,31 @@ def test_assign_brute_force_and_ties():
 
 # ---------------------------------------------------------------- k-means++
 
-def test_blocked_cumsum_against_python_and_sequential_when_one_block():
+def _py_running(w):
+    out, acc = [], 0.0
+    for v in w:
+        acc = acc + float(v)
+        out.append(acc)
+    return out
+
+
+def test_running_sum_is_the_left_to_right_recurrence():
+    """The k-means++ cumulative weight: bit for bit the Python left-to-right
+    loop over 5,000 weights spanning 16 decades, and not the pairwise or the
+    blocked order (both differ from it somewhere on these weights)."""
     g = np.random.default_rng(3)
-    w = g.uniform(0, 1, 1000) * 10.0 ** g.integers(-8, 8, 1000)
-    S = O.blocked_cumsum(w, block=256)
-    # independent Python statement of the blocked order
-    off = 0.0
-    for b0 in range(0, 1000, 256):
-        inner = 0.0
-        for i in range(b0, min(b0 + 256, 1000)):
-            inner = inner + float(w[i])
-            assert S[i] == off + inner
-        off = off + inner
+    w = g.uniform(0, 1, 5000) * 10.0 ** g.integers(-8, 8, 5000)
+    S = O.running_sum(w)
+    assert S.tolist() == _py_running(w)
     assert np.all(np.diff(S) >= 0)
-    S1 = O.blocked_cumsum(w[:200], block=256)
-    acc = 0.0
-    for i in range(200):
-        acc = acc + float(w[i])
-        assert S1[i] == acc
+    pairwise = [float(np.sum(w[:i + 1])) for i in range(0, 5000, 97)]
+    assert any(a != b for a, b in zip(pairwise, S[::97]))
+    blocked, off = [], 0.0
+    for b0 in range(0, 5000, 256):
+        inner = _py_running(w[b0:b0 + 256])
+        blocked += [off + v for v in inner]
+        off = off + inner[-1]
+    assert blocked != S.tolist()
 
 
 def test_kmeanspp_is_d2_sampling():
@@ -126,7 +133,7 @@ def test_kmeanspp_is_d2_sampling():
     D2_i / sum(D2) (exactly, up to the grid step)."""
     X = np.array([[0.0], [1.0], [3.0], [6.0], [10.0]])
     D2 = O.dist2(X, X[[0]])[:, 0]            # weights 0, 1, 9, 36, 100
-    S = O.blocked_cumsum(D2)
+    S = O.running_sum(D2)
     grid = (np.arange(20000) + 0.5) / 20000
     picks = np.array([int(np.argmax(S > u * S[-1])) for u in grid])
     freq = np.bincount(picks, minlength=5) / grid.size
@@ -214,21 +221,31 @@ def test_lloyd_objective_nonincreasing_and_fixed_point():
 
 
 def test_member_means_is_the_mean():
-    """Many members (several summation blocks): every centre is the mean of
-    its members within a few ulps of the exactly rounded sum (math.fsum), and
+    """Many members per cluster (750 on average, several hundred more than
+    any block a parallel sum might use): every centre is bit for bit the
+    Python left-to-right sum over its members in increasing index divided by
+    the count, within a few ulps of the exactly rounded mean (math.fsum), and
     a constant cluster reproduces its value exactly."""
     g = np.random.default_rng(3)
     X = g.standard_normal((3000, 3)) * np.array([1.0, 1e3, 1e-3])
     a = g.integers(0, 4, 3000).astype(np.int32)
     X[a == 3] = 0.625
     C, counts = O.member_means(X, a, np.zeros((4, 3)))
+    differs_from_blocked = False
     for j in range(4):
         mem = X[a == j]
         assert counts[j] == mem.shape[0] > 512
         for f in range(3):
+            seq = _py_running(mem[:, f])[-1]
+            assert C[j, f] == seq / mem.shape[0]
             exact = math.fsum(mem[:, f]) / mem.shape[0]
             scale = np.abs(mem[:, f]).sum() / mem.shape[0]
-            assert abs(C[j, f] - exact) <= 64 * np.finfo(float).eps * scale
+            assert abs(C[j, f] - exact) <= 2 * mem.shape[0] * np.finfo(float).eps * scale
+            off = 0.0
+            for b0 in range(0, mem.shape[0], 256):
+                off = off + _py_running(mem[b0:b0 + 256, f])[-1]
+            differs_from_blocked |= off / mem.shape[0] != C[j, f]
+    assert differs_from_blocked
     assert np.all(C[3] == 0.625)
 
 
