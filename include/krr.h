@@ -298,8 +298,12 @@ typedef struct {
   int32_t max_batch_fits;    /* >= 1: fit requests per batch */
   int32_t reserved;          /* must be 0 */
   int64_t max_batch_points;  /* >= 1: query points per predict batch */
-  size_t  hbm_budget_bytes;  /* admission budget of unfinished requests (0 = none);
-                                also the budget of every worker's context */
+  size_t  hbm_budget_bytes;  /* device memory of the serving workers together (0 = none):
+                                split into 2 x the estimate of a full predict batch per
+                                predict worker and equal shares of the rest per fit
+                                worker; admission keeps the estimated memory of
+                                unfinished requests within it, and a fit request above
+                                one fit worker's share is rejected (KRR_EBUDGET) */
 } krr_server_config;
 
 typedef struct {
@@ -321,6 +325,8 @@ typedef struct {
   int64_t fit_batches;
   int64_t failed;            /* completed requests with a status other than KRR_OK */
   int64_t max_inflight_bytes;/* peak estimated memory of admitted, unfinished requests */
+  int64_t max_device_bytes;  /* peak device memory held by the workers' contexts together
+                                (measured after each batch; at most hbm_budget_bytes) */
   double  predict_p50_ms, predict_p99_ms;   /* nearest-rank percentiles of total_ms */
   double  fit_p50_ms, fit_p99_ms;
   double  span_ms;           /* first submit -> last completion */

@@ -14,9 +14,38 @@ namespace krr {
 // bytes count as held by the context.
 constexpr size_t MODEL_CACHE_BLOCKS = 64;
 
+void drain(krr_ctx ctx) {
+  if (ctx->in_call) KRR_HIP(hipStreamSynchronize(ctx->cur_stream));
+  for (auto& m : ctx->marks) KRR_HIP(hipEventSynchronize(m.second));
+}
+
+StreamScope::StreamScope(krr_ctx c, hipStream_t s) : ctx(c) {
+  ctx->cur_stream = s;
+  ctx->in_call = true;
+}
+
+StreamScope::~StreamScope() {
+  ctx->in_call = false;
+  hipEvent_t ev = nullptr;
+  for (auto& m : ctx->marks)
+    if (m.first == ctx->cur_stream) ev = m.second;
+  if (ev == nullptr) {
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipStreamSynchronize(ctx->cur_stream);   // no event: nothing of this call may stay queued
+      return;
+    }
+    ctx->marks.emplace_back(ctx->cur_stream, ev);
+  }
+  if (hipEventRecord(ev, ctx->cur_stream) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(ctx->cur_stream);
+  }
+}
+
 static void drop_model_cache(krr_ctx ctx) {
   if (ctx->model_cache.empty()) return;
-  (void)hipDeviceSynchronize();
+  drain(ctx);
   for (auto& kv : ctx->model_cache) (void)hipFree(kv.second);
   ctx->model_cache.clear();
   ctx->cache_bytes = 0;
@@ -38,7 +67,7 @@ void* ws_get(krr_ctx ctx, const std::string& name, size_t bytes) {
   const size_t old = b.bytes;
   charge(ctx, bytes - old);
   if (b.ptr != nullptr) {
-    KRR_HIP(hipDeviceSynchronize());  // the old buffer may still be in use
+    drain(ctx);  // the old buffer may still be in use by this context's queued work
     KRR_HIP(hipFree(b.ptr));
     b.ptr = nullptr;
     b.bytes = 0;
@@ -90,10 +119,20 @@ void model_release(krr_ctx ctx, void* p, size_t bytes) {
   }
 }
 
+void ws_release_all(krr_ctx ctx) {
+  drain(ctx);
+  for (auto& kv : ctx->ws)
+    if (kv.second.ptr != nullptr) {
+      KRR_HIP(hipFree(kv.second.ptr));
+      ctx->ws_bytes -= kv.second.bytes;
+    }
+  ctx->ws.clear();
+}
+
 void* pinned_get(krr_ctx ctx, size_t bytes) {
   if (ctx->pinned_bytes >= bytes) return ctx->pinned;
   if (ctx->pinned != nullptr) {
-    KRR_HIP(hipDeviceSynchronize());
+    drain(ctx);
     (void)hipHostFree(ctx->pinned);
     ctx->pinned = nullptr;
     ctx->pinned_bytes = 0;
@@ -220,7 +259,13 @@ krr_status krr_destroy(krr_ctx ctx) {
     return KRR_ESTATE;
   }
   (void)hipSetDevice(ctx->device);
-  (void)hipDeviceSynchronize();
+  try {
+    drain(ctx);
+  } catch (const Error&) {
+    (void)hipDeviceSynchronize();
+  }
+  for (auto& m : ctx->marks) (void)hipEventDestroy(m.second);
+  ctx->marks.clear();
   for (auto& kv : ctx->ws)
     if (kv.second.ptr) (void)hipFree(kv.second.ptr);
   drop_model_cache(ctx);
@@ -299,6 +344,7 @@ krr_status krr_csr_to_dense(krr_ctx ctx, hipStream_t stream, const int64_t* indp
     KRR_REQUIRE(dtype == KRR_F32 || dtype == KRR_F64, "dtype must be KRR_F32 or KRR_F64");
     KRR_REQUIRE(n >= 1 && d >= 1 && nnz >= 0, "n and d must be >= 1, nnz >= 0");
     KRR_REQUIRE(n < (int64_t(1) << 31) - 1, "n must fit in int32");
+    StreamScope ss(ctx, stream);
     run_csr_to_dense(ctx, stream, indptr, indices, values, dtype, n, d, nnz, X);
   });
 }
@@ -316,6 +362,7 @@ krr_status krr_partition(krr_ctx ctx, hipStream_t stream, const void* X, int32_t
                     method == KRR_PART_RANDOM || method == KRR_PART_KBALANCE_APPROX,
                 "unknown partition method");
     KRR_REQUIRE(lloyd_iters >= 0 && lloyd_iters <= 100000, "lloyd_iters out of range");
+    StreamScope ss(ctx, stream);
     run_partition(ctx, stream, X, dtype, n, d, p, method, lloyd_iters, seed, centroids, assign, sizes);
   });
 }
@@ -350,6 +397,7 @@ krr_status krr_fit(krr_ctx ctx, hipStream_t stream, const void* X, const void* y
       KRR_REQUIRE(P.max_refine >= 0 && P.max_refine <= 1000, "max_refine out of range");
     }
     for (int q = 0; q < n_params; ++q) models_out[q] = nullptr;
+    StreamScope ss(ctx, stream);
     run_fit(ctx, stream, X, y, dtype, n, d, assign, centroids, p, params, n_params, models_out, info_out);
     for (int q = 0; q < n_params * p; ++q) {
       if (info_out[q].status == KRR_ENOTSPD) st = KRR_ENOTSPD;
@@ -370,6 +418,7 @@ krr_status krr_predict(krr_ctx ctx, hipStream_t stream, krr_model model, const v
     KRR_REQUIRE(k >= 1 && k < (int64_t(1) << 31) - 1, "k must be >= 1");
     KRR_REQUIRE(route == KRR_ROUTE_NEAREST || route == KRR_ROUTE_AVERAGE || route == KRR_ROUTE_ALL,
                 "unknown route");
+    StreamScope ss(ctx, stream);
     run_predict(ctx, stream, model, Xt, dtype, k, route, yhat, route_out);
   });
 }
@@ -385,6 +434,7 @@ krr_status krr_select(krr_ctx ctx, hipStream_t stream, const krr_model* models, 
     KRR_REQUIRE(k >= 1 && k < (int64_t(1) << 31) - 1, "k must be >= 1");
     KRR_REQUIRE(route == KRR_ROUTE_NEAREST || route == KRR_ROUTE_AVERAGE || route == KRR_ROUTE_LABEL,
                 "route must be NEAREST, AVERAGE or LABEL");
+    StreamScope ss(ctx, stream);
     run_select(ctx, stream, models, n_models, Xv, yv, dtype, k, route, mse_out, best_out);
   });
 }
@@ -397,6 +447,7 @@ krr_status krr_model_alpha(krr_ctx ctx, hipStream_t stream, krr_model model, int
     KRR_REQUIRE(j >= 0 && j < model->data->p, "partition index out of range");
     const int64_t mj = model->data->offsets[j + 1] - model->data->offsets[j];
     *m = mj;
+    StreamScope ss(ctx, stream);
     if (mj > 0)
       KRR_HIP(hipMemcpyAsync(alpha, model->alpha + model->voff[j], (size_t)mj * 8, hipMemcpyDeviceToDevice,
                              stream));

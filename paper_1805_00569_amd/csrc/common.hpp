@@ -155,6 +155,11 @@ struct krr_ctx_s {
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   int timing = 0;   // 0 off, 1 matrix-core update kernels, 2 every timed kernel class
+  hipStream_t cur_stream = nullptr;   // stream of the call in progress (valid while in_call)
+  bool in_call = false;
+  // per stream the context has queued work on: an event recorded after that
+  // work (see drain)
+  std::vector<std::pair<hipStream_t, hipEvent_t>> marks;
   std::vector<hipEvent_t> ev_pool;
   std::vector<krr_timed_launch> pending;
   std::map<std::string, krr_timing_agg> timing_agg;
@@ -169,6 +174,19 @@ void* ws_get(krr_ctx ctx, const std::string& name, size_t bytes);
 void* model_alloc(krr_ctx ctx, size_t bytes);
 void model_release(krr_ctx ctx, void* p, size_t bytes);
 void* pinned_get(krr_ctx ctx, size_t bytes);
+// Frees every workspace buffer of the context (after drain).
+void ws_release_all(krr_ctx ctx);
+// Waits until the work this context has queued is done: the current call's
+// stream and the last recorded work on every other stream it has used.  Work
+// of other contexts is not waited for.
+void drain(krr_ctx ctx);
+// Marks a call on `stream`: the context's buffers may be used by work queued
+// on it until the scope ends, when an event is recorded after that work.
+struct StreamScope {
+  krr_ctx ctx;
+  StreamScope(krr_ctx c, hipStream_t s);
+  ~StreamScope();
+};
 void check_launch(krr_ctx ctx, hipStream_t s, const char* what);
 
 // HIP events around one launch of kernel class `cls` (only when timing is on;

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <exception>
 
 namespace krr {
 
@@ -324,6 +325,15 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
     data->ctx = ctx;
     ctx->n_datas += 1;
   }
+  // on an error below, wait for the queued work that reads or writes the
+  // partition data before it is released (the guard unwinds before `data`)
+  struct SyncOnUnwind {
+    hipStream_t st;
+    int n0 = std::uncaught_exceptions();
+    ~SyncOnUnwind() {
+      if (std::uncaught_exceptions() > n0) (void)hipStreamSynchronize(st);
+    }
+  } unwind_sync{s};
   data->p = p;
   data->d = d;
   data->dtype = dtype;
@@ -583,6 +593,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
   // 11. models: alpha of setting q is the contiguous range of its p systems;
   // their offset tables go up from one pinned slice per model (one wait)
   int64_t* voff_pin = (int64_t*)pinned_get(ctx, (size_t)n_params * (p + 1) * 8);
+  std::vector<krr_model> made;
   for (int q = 0; q < n_params; ++q) {
     krr_model M = new krr_model_s();
     M->ctx = ctx;
@@ -595,10 +606,19 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
     try {
       M->alpha = (double*)model_alloc(ctx, M->bytes);
     } catch (...) {
+      // no model is handed out: release the ones made so far (their queued
+      // copies and uploads finish first) and clear the output handles
       delete M;
-      (void)hipStreamSynchronize(s);   // earlier models' uploads still read their pinned slices
+      (void)hipStreamSynchronize(s);
+      for (krr_model P : made) {
+        model_release(ctx, P->alpha, P->bytes);
+        ctx->n_models -= 1;
+        delete P;
+      }
+      for (int q2 = 0; q2 < n_params; ++q2) models[q2] = nullptr;
       throw;
     }
+    made.push_back(M);
     ctx->n_models += 1;
     M->d_voff = (int64_t*)((char*)M->alpha + abytes);
     M->voff.resize(p + 1);

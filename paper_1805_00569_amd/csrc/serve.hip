@@ -10,6 +10,14 @@
 // queues, the admission budget and the statistics are shared under one
 // mutex.  No worker ever synchronises the device: each waits on its own
 // stream only.
+//
+// Device memory: the HBM budget is split between the workers' contexts, so
+// the memory they hold together never exceeds it.  Each predict worker gets
+// twice the estimate of a full predict batch; the fit workers share the rest
+// equally.  A fit request larger than one fit worker's share is rejected at
+// submission, a fit batch is only formed within one share, and a fit worker
+// whose retained workspace plus its next batch would exceed its share frees
+// its workspace first (its stream is idle between batches).
 #include "common.hpp"
 
 #include <algorithm>
@@ -51,6 +59,8 @@ struct Request {
 struct Worker {
   int kind = KIND_PREDICT;
   krr_ctx ctx = nullptr;
+  size_t share = 0;       // device memory the worker's context may hold (0 = no cap)
+  size_t held = 0;        // device memory its context held after its last batch
   hipStream_t stream = nullptr;
   std::thread thread;
   void* host = nullptr;   // pinned staging owned by the worker (the context's own
@@ -104,6 +114,8 @@ struct krr_server_s {
   std::unordered_map<int64_t, krr::Request*> requests;
   int64_t next_ticket = 1;
   size_t inflight = 0;
+  size_t fit_share = 0;       // per fit worker (0 = no cap)
+  size_t max_held = 0;        // peak device memory held by all worker contexts together
   bool stopping = false;
   std::vector<krr::Worker*> workers;
   std::string last_error;
@@ -134,7 +146,10 @@ std::vector<Request*> take_batch(krr_server S, int kind, size_t& need) {
   std::vector<Request*> b;
   std::deque<Request*>& q = S->queue[kind];
   const size_t budget = S->cfg.hbm_budget_bytes;
-  auto fits_budget = [&](size_t add) { return budget == 0 || S->inflight + need + add <= budget; };
+  auto fits_budget = [&](size_t add) {
+    return budget == 0 ||
+           (S->inflight + need + add <= budget && (kind == KIND_PREDICT || need + add <= S->fit_share));
+  };
   if (kind == KIND_PREDICT) {
     int64_t pts = 0;
     while (!q.empty()) {
@@ -191,6 +206,7 @@ int32_t run_predict_batch(krr_server S, Worker* W, const std::vector<Request*>& 
     std::memcpy(h + (size_t)o * d * 4, r->X, (size_t)r->rows * d * 4);
     o += r->rows;
   }
+  StreamScope ss(W->ctx, W->stream);
   char* dv = (char*)ws_get(W->ctx, "serve_predict", xb + (size_t)k * 8);
   double* dy = (double*)(dv + xb);
   KRR_HIP(hipMemcpyAsync(dv, h, (size_t)k * d * 4, hipMemcpyHostToDevice, W->stream));
@@ -228,6 +244,13 @@ int32_t run_fit_batch(krr_server S, Worker* W, const std::vector<Request*>& batc
     std::memcpy(hyv + o, r->y, (size_t)r->rows * 4);
     for (int64_t t = 0; t < r->rows; ++t) ha[o + t] = i;
     o += r->rows;
+  }
+  StreamScope ss(W->ctx, W->stream);
+  size_t need = 0;
+  for (Request* r : batch) need += r->need;
+  if (W->share != 0 && W->held + need > W->share) {
+    ws_release_all(W->ctx);   // retained buffers of earlier batches would not leave room
+    W->held = 0;
   }
   char* dv = (char*)ws_get(W->ctx, "serve_fit", xb + yb + ab + cb);
   KRR_HIP(hipMemcpyAsync(dv, h, xb + yb + ab, hipMemcpyHostToDevice, W->stream));
@@ -285,10 +308,16 @@ void worker_loop(krr_server S, Worker* W) {
       st = KRR_EDEVICE;
       msg = e.what();
     }
+    size_t held = 0;
+    (void)krr_memory_in_use(W->ctx, &held);
     {
       std::lock_guard<std::mutex> lk(S->mu);
       const double t = now_ms();
       S->inflight -= need;
+      W->held = held;
+      size_t tot = 0;
+      for (Worker* V : S->workers) tot += V->held;
+      S->max_held = std::max(S->max_held, tot);
       if (st != KRR_OK) S->last_error = msg;
       S->batches[W->kind] += 1;
       for (Request* r : batch) {
@@ -351,11 +380,27 @@ krr_status krr_server_create(krr_ctx owner, krr_model model, const krr_server_co
   S->d_model = model->data->d;
   S->cfg = *cfg;
   const int nw = cfg->predict_workers + cfg->fit_workers;
+  // split of the budget between the workers' contexts
+  size_t pshare = 0;
+  if (cfg->hbm_budget_bytes != 0) {
+    pshare = 2 * predict_need(cfg->max_batch_points, S->d_model);
+    const size_t preserve = pshare * (size_t)cfg->predict_workers;
+    if (preserve >= cfg->hbm_budget_bytes ||
+        (cfg->fit_workers > 0 && (cfg->hbm_budget_bytes - preserve) / (size_t)cfg->fit_workers < (size_t(1) << 20))) {
+      owner->last_error = "HBM budget of " + std::to_string(cfg->hbm_budget_bytes) +
+                          " bytes leaves no room: the predict workers need " + std::to_string(preserve) +
+                          " bytes for batches of max_batch_points, and every fit worker at least 1 MiB";
+      delete S;
+      return KRR_EINVAL;
+    }
+    S->fit_share = cfg->fit_workers > 0 ? (cfg->hbm_budget_bytes - preserve) / (size_t)cfg->fit_workers : 0;
+  }
   krr_status st = KRR_OK;
   for (int i = 0; i < nw && st == KRR_OK; ++i) {
     Worker* W = new Worker();
     W->kind = i < cfg->predict_workers ? KIND_PREDICT : KIND_FIT;
-    st = krr_create(S->device, cfg->hbm_budget_bytes, &W->ctx);
+    W->share = W->kind == KIND_PREDICT ? pshare : S->fit_share;
+    st = krr_create(S->device, W->share, &W->ctx);
     if (st == KRR_OK) {
       (void)hipSetDevice(S->device);
       if (hipStreamCreateWithFlags(&W->stream, hipStreamNonBlocking) != hipSuccess) st = KRR_EDEVICE;
@@ -455,9 +500,11 @@ krr_status krr_server_submit_fit(krr_server S, const float* X, const float* y, i
   r->d = d;
   r->params = P;
   r->need = fit_need(m, d, P.prec, 16);
-  if (S->cfg.hbm_budget_bytes != 0 && r->need > S->cfg.hbm_budget_bytes) {
+  if (S->cfg.hbm_budget_bytes != 0 && r->need > S->fit_share) {
     delete r;
-    set_error(S, "fit request alone exceeds the HBM budget");
+    set_error(S, "fit request alone (" + std::to_string(fit_need(m, d, P.prec, 16)) +
+                     " bytes) exceeds a fit worker's share of the HBM budget (" + std::to_string(S->fit_share) +
+                     " bytes)");
     return KRR_EBUDGET;
   }
   const krr_status st = submit(S, r);
@@ -501,6 +548,7 @@ krr_status krr_server_stats(krr_server S, int32_t reset, krr_serve_stats* out) {
   out->fit_batches = S->batches[KIND_FIT];
   out->failed = S->failed;
   out->max_inflight_bytes = (int64_t)S->max_inflight;
+  out->max_device_bytes = (int64_t)S->max_held;
   out->predict_p50_ms = percentile(S->latency[KIND_PREDICT], 0.50);
   out->predict_p99_ms = percentile(S->latency[KIND_PREDICT], 0.99);
   out->fit_p50_ms = percentile(S->latency[KIND_FIT], 0.50);
@@ -512,6 +560,8 @@ krr_status krr_server_stats(krr_server S, int32_t reset, krr_serve_stats* out) {
     S->batches[0] = S->batches[1] = 0;
     S->failed = 0;
     S->max_inflight = S->inflight;
+    S->max_held = 0;
+    for (Worker* V : S->workers) S->max_held += V->held;
     S->latency[0].clear();
     S->latency[1].clear();
     S->t_first = S->t_last = -1.0;

@@ -64,6 +64,7 @@ class ServeStats(ctypes.Structure):
                 ("points", ctypes.c_int64), ("fit_rows", ctypes.c_int64),
                 ("predict_batches", ctypes.c_int64), ("fit_batches", ctypes.c_int64),
                 ("failed", ctypes.c_int64), ("max_inflight_bytes", ctypes.c_int64),
+                ("max_device_bytes", ctypes.c_int64),
                 ("predict_p50_ms", ctypes.c_double), ("predict_p99_ms", ctypes.c_double),
                 ("fit_p50_ms", ctypes.c_double), ("fit_p99_ms", ctypes.c_double),
                 ("span_ms", ctypes.c_double)]

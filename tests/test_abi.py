@@ -36,8 +36,8 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(krr.ServerConfig) == 32
     # krr_request_info: 4 x int32 + 3 doubles -> 40 bytes
     assert ctypes.sizeof(krr.RequestInfo) == 40
-    # krr_serve_stats: 8 x int64 + 5 doubles -> 104 bytes
-    assert ctypes.sizeof(krr.ServeStats) == 104
+    # krr_serve_stats: 9 x int64 + 5 doubles -> 112 bytes
+    assert ctypes.sizeof(krr.ServeStats) == 112
 
 
 @pytest.mark.skipif(shutil.which("gcc") is None or not os.path.isdir("/opt/rocm/include"),
@@ -45,7 +45,9 @@ def test_struct_layouts_match_header():
 def test_struct_layouts_match_compiled_header(tmp_path):
     """Sizes and field offsets of the binding's structures equal what a C
     compiler makes of include/krr.h."""
-    structs = {"krr_fit_params": krr.FitParams, "krr_part_info": krr.PartInfo}
+    structs = {"krr_fit_params": krr.FitParams, "krr_part_info": krr.PartInfo,
+               "krr_server_config": krr.ServerConfig, "krr_request_info": krr.RequestInfo,
+               "krr_serve_stats": krr.ServeStats}
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "krr.h"', "int main(void) {"]
     for cname, cls in structs.items():

@@ -528,3 +528,36 @@ def test_fit_rejects_bad_arguments(ctx, dev):
     with pytest.raises(krr.KrrError) as e:
         ctx.fit(X, X[:, 0].contiguous(), a, C, 1, [krr.Params(lam=math.nan)])
     assert e.value.status == krr.KRR_EINVAL
+
+
+def test_fit_budget_failure_on_a_later_model_leaks_nothing(dev):
+    """A budget that holds the workspace, the partition data and the first
+    model but not the second: krr_fit returns KRR_EBUDGET, hands out no model
+    handle, and the context can still be destroyed (no model or partition
+    data left alive on it)."""
+    import ctypes
+    w = datagen.small(91, 1500, 6, k=10, p=3, comps=3, dtype=np.float64)
+    X, y = _t(w.X, dev), _t(w.y, dev)
+    params = [krr.Params(sigma=1.0, lam=1e-2, prec="fp64"), krr.Params(sigma=2.0, lam=1e-2, prec="fp64")]
+    part = krr.Context(0)
+    C, a, _ = part.partition(X, 3, "kmeans", lloyd_iters=5, seed=3)
+    torch.cuda.synchronize()
+    part.close()
+    probe = krr.Context(0)                   # holds exactly what the fit needs
+    models, _, st = probe.fit(X, y, a, C, 3, params)
+    assert st == 0
+    total = probe.memory_in_use()            # workspace + data + both models
+    for m in models:
+        m.free()
+    probe.close()
+    print(f"budget failure: total {total} bytes", flush=True)
+    lim = krr.Context(0, hbm_budget=total - 1)
+    handles = (ctypes.c_void_p * 2)(ctypes.c_void_p(1), ctypes.c_void_p(1))
+    info = (krr.PartInfo * 6)()
+    arr = (krr.FitParams * 2)(*[q.to_c() for q in params])
+    st = lim.lib.krr_fit(lim.h, krr._stream(dev), krr._ptr(X), krr._ptr(y), krr.F64, 1500, 6, krr._ptr(a),
+                         krr._ptr(C), 3, arr, 2, handles, info)
+    assert st == krr.KRR_EBUDGET, lim.lib.krr_last_error(lim.h)
+    assert handles[0] is None and handles[1] is None
+    assert lim.lib.krr_destroy(lim.h) == krr.KRR_OK
+    lim.h = None

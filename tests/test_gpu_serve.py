@@ -126,7 +126,10 @@ def test_serve_predictions_match_oracle(ctx, dev, resident):
 def test_serve_admission_budget(ctx, dev, resident):
     pools, model, *_ = resident
     print("serve: admission budget", flush=True)
-    budget = 8 << 20   # a few fit requests of m <= 740 at a time
+    # 24 MiB: two predict workers hold at most 2 x 2.9 MB (batches of 2,048
+    # points, d = 16); each fit worker gets ~9.7 MB, i.e. three fit requests
+    # of m <= 740 at a time
+    budget = 24 << 20
     srv = krr.Server(ctx, model, predict_workers=2, fit_workers=2, max_batch_fits=4, max_batch_points=2048,
                      hbm_budget=budget)
     try:
@@ -141,8 +144,10 @@ def test_serve_admission_budget(ctx, dev, resident):
             assert inf["status"] == 0
         s = srv.stats()
         assert 0 < s["max_inflight_bytes"] <= budget
+        # device memory actually held by the workers' contexts together
+        assert 0 < s["max_device_bytes"] <= budget
         with pytest.raises(krr.KrrError) as e:
-            srv.submit_fit(datagen.take_rows(pools.fit_X[16], 0, 2000),   # alone above the budget
+            srv.submit_fit(datagen.take_rows(pools.fit_X[16], 0, 2000),   # alone above a fit worker's share
                            datagen.take_rows(pools.fit_y[16][:, None], 0, 2000)[:, 0], _fit_params())
         assert e.value.status == krr.KRR_EBUDGET
         with pytest.raises(krr.KrrError) as e:
@@ -153,3 +158,6 @@ def test_serve_admission_budget(ctx, dev, resident):
         assert e.value.status == krr.KRR_EINVAL
     finally:
         srv.close()
+    with pytest.raises(krr.KrrError) as e:   # a budget the predict workers alone would fill
+        krr.Server(ctx, model, predict_workers=2, fit_workers=1, max_batch_points=2048, hbm_budget=4 << 20)
+    assert e.value.status == krr.KRR_EINVAL
