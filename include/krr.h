@@ -242,6 +242,27 @@ krr_status krr_predict(krr_ctx ctx, hipStream_t stream, krr_model model,
                        const void* Xt, int32_t dtype, int64_t k, int32_t route,
                        double* yhat, int32_t* route_out);
 
+/* ---- predict without device allocation -------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, routes and result as krr_predict (the same kernels with the same
+ * launch shapes, so the values are identical bit for bit), but every
+ * temporary buffer of the call (routes, grouping counts, partial sums, the
+ * per-model matrix of AVERAGE) is carved from a fixed device array of
+ * KRR_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends; the call allocates and frees no device memory and
+ * records no timing events.  A call whose temporaries would not fit returns
+ * KRR_EINVAL before any work is queued, with the bytes it needs in
+ * krr_last_error (NEAREST fits roughly k <= 250,000 points; ALL and AVERAGE
+ * roughly k * p <= 250,000).  Every call on one GPU shares the array, which
+ * keeps the last call's contents (no temporary needs to start at zero):
+ * calls that overlap on one GPU -- other streams, other contexts, other host
+ * threads -- race, and the caller must order them.  Asynchronous. */
+#define KRR_NOALLOC_SCRATCH_BYTES ((size_t)8 << 20)
+krr_status krr_predict_noalloc(krr_ctx ctx, hipStream_t stream, krr_model model,
+                               const void* Xt, int32_t dtype, int64_t k, int32_t route,
+                               double* yhat, int32_t* route_out);
+
 /* ---- select (Eq. 3; Algorithm 5 model choice) ----------------------------
  * Predicts the k validation points Xv with every model, mse_out[i] =
  * mean((yhat_i - yv)^2) (host, n_models), *best_out = index of the lowest MSE

@@ -165,7 +165,7 @@ static hipEvent_t ev_get(krr_ctx ctx) {
 
 KernelTimer::KernelTimer(krr_ctx c, hipStream_t st, const char* name, double f, int major, double by)
     : ctx(c), s(st), cls(name), flops(f), bytes(by) {
-  if (ctx->timing == 0 || (ctx->timing == 1 && !major)) return;
+  if (ctx->timing == 0 || (ctx->timing == 1 && !major) || ctx->noalloc) return;
   a = ev_get(ctx);
   b = ev_get(ctx);
   if (a == nullptr || b == nullptr || hipEventRecord(a, s) != hipSuccess) {
@@ -244,6 +244,12 @@ krr_status krr_create(int device, size_t hbm_budget_bytes, krr_ctx* out) {
   *out = nullptr;
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return KRR_EINVAL;
+  try {   // library set-up on this device: the no-allocation scratch address
+    DeviceGuard g(device);
+    noalloc_scratch_init(device);
+  } catch (const Error& e) {
+    return e.status;
+  }
   krr_ctx c = new (std::nothrow) krr_ctx_s();
   if (c == nullptr) return KRR_ENOMEM;
   c->device = device;
@@ -420,6 +426,19 @@ krr_status krr_predict(krr_ctx ctx, hipStream_t stream, krr_model model, const v
                 "unknown route");
     StreamScope ss(ctx, stream);
     run_predict(ctx, stream, model, Xt, dtype, k, route, yhat, route_out);
+  });
+}
+
+krr_status krr_predict_noalloc(krr_ctx ctx, hipStream_t stream, krr_model model, const void* Xt, int32_t dtype,
+                               int64_t k, int32_t route, double* yhat, int32_t* route_out) {
+  return guarded(ctx, [&] {
+    KRR_REQUIRE(model && Xt && yhat, "null pointer argument");
+    KRR_REQUIRE(model->ctx == ctx, "model belongs to another context");
+    KRR_REQUIRE(dtype == KRR_F32 || dtype == KRR_F64, "dtype must be KRR_F32 or KRR_F64");
+    KRR_REQUIRE(k >= 1 && k < (int64_t(1) << 31) - 1, "k must be >= 1");
+    KRR_REQUIRE(route == KRR_ROUTE_NEAREST || route == KRR_ROUTE_AVERAGE || route == KRR_ROUTE_ALL,
+                "unknown route");
+    run_predict_noalloc(ctx, stream, model, Xt, dtype, k, route, yhat, route_out);
   });
 }
 

@@ -155,6 +155,7 @@ struct krr_ctx_s {
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   int timing = 0;   // 0 off, 1 matrix-core update kernels, 2 every timed kernel class
+  int noalloc = 0;  // inside a no-allocation call: no timing events
   hipStream_t cur_stream = nullptr;   // stream of the call in progress (valid while in_call)
   bool in_call = false;
   // per stream the context has queued work on: an event recorded after that
@@ -213,8 +214,13 @@ void run_csr_to_dense(krr_ctx ctx, hipStream_t s, const int64_t* indptr, const i
 void assign_nearest(krr_ctx ctx, hipStream_t s, const void* X, int dtype, int64_t n, int d,
                     const double* C, int p, int32_t* out, const int32_t* prev, int32_t* delta,
                     const int32_t* skip);
+// Stable grouping of n keys in [0, p): perm lists the points of key 0, then
+// key 1, ... (each in increasing index), offsets[p + 1] the group starts.
+// wsp (nullable): group_ws_bytes(n, p) bytes of device workspace to use
+// instead of the context's pool.
+size_t group_ws_bytes(int64_t n, int p);
 void group_by_key(krr_ctx ctx, hipStream_t s, const int32_t* key, int64_t n, int p,
-                  int32_t* perm, int64_t* offsets, int64_t* sizes64, const int32_t* skip);
+                  int32_t* perm, int64_t* offsets, int64_t* sizes64, const int32_t* skip, void* wsp = nullptr);
 void gather_rows(krr_ctx ctx, hipStream_t s, const void* X, int dtype, int64_t n, int d,
                  const int32_t* perm, void* Xout);
 void gather_vec_f64(krr_ctx ctx, hipStream_t s, const void* y, int dtype, int64_t n,
@@ -223,6 +229,29 @@ void transpose_centroids(krr_ctx ctx, hipStream_t s, const double* C, int p, int
 void run_partition(krr_ctx ctx, hipStream_t s, const void* X, int dtype, int64_t n, int d, int p,
                    int method, int iters, uint64_t seed, double* C, int32_t* assign,
                    int64_t* sizes);
+
+// Bump allocation of 256-byte aligned pieces from a fixed device region (the
+// no-allocation entry points); running out is an argument error.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  void* take(size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    if (bytes == 0) bytes = 256;
+    if (used + bytes > cap)
+      fail(KRR_EINVAL, "scratch of " + std::to_string(cap) + " bytes exhausted (" + std::to_string(used + bytes) +
+                           " needed)");
+    void* p = base + used;
+    used += bytes;
+    return p;
+  }
+};
+inline size_t al256(size_t b) { return b == 0 ? 256 : (b + 255) & ~size_t(255); }
+// A piece of `bytes` from the arena when there is one, else the context's
+// workspace buffer `name`.
+inline void* ws_or_arena(krr_ctx ctx, Arena* ar, const std::string& name, size_t bytes) {
+  return ar != nullptr ? ar->take(bytes) : ws_get(ctx, name, bytes);
+}
 
 // ---- fit.hip ----
 bool same_kernel_matrix(const krr_fit_params& a, const krr_fit_params& b);
@@ -240,7 +269,14 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
 
 // ---- predict.hip ----
 void run_predict(krr_ctx ctx, hipStream_t s, krr_model model, const void* Xt, int dtype, int64_t k,
-                 int route, double* yhat, int32_t* route_out);
+                 int route, double* yhat, int32_t* route_out, Arena* ar = nullptr);
+// The same prediction with every temporary taken from the library's fixed
+// per-device scratch array (no device allocation).
+void run_predict_noalloc(krr_ctx ctx, hipStream_t s, krr_model model, const void* Xt, int dtype, int64_t k,
+                         int route, double* yhat, int32_t* route_out);
+// Once per device, with the device current: record the device address of the
+// no-allocation scratch array.
+void noalloc_scratch_init(int device);
 void run_select(krr_ctx ctx, hipStream_t s, const krr_model* models, int n_models, const void* Xv,
                 const void* yv, int dtype, int64_t k, int route, double* mse, int32_t* best);
 

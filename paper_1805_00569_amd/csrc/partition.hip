@@ -1073,11 +1073,13 @@ void assign_nearest(krr_ctx ctx, hipStream_t s, const void* X, int dtype, int64_
     assign_t(ctx, s, (const float*)X, n, d, CT, p, out, nullptr, prev, delta, skip, false);
 }
 
+size_t group_ws_bytes(int64_t n, int p) { return (size_t)n * 4 + (size_t)ceil_div(n, GROUP_BLOCK) * p * 8 + 64; }
+
 void group_by_key(krr_ctx ctx, hipStream_t s, const int32_t* key, int64_t n, int p, int32_t* perm,
-                  int64_t* offsets, int64_t* sizes64, const int32_t* skip) {
+                  int64_t* offsets, int64_t* sizes64, const int32_t* skip, void* wsp) {
   const int64_t nblk = ceil_div(n, GROUP_BLOCK);
   KernelTimer kt(ctx, s, "group", 0.0, 0);
-  char* w = (char*)ws_get(ctx, "group", (size_t)n * 4 + (size_t)nblk * p * 8 + 64);
+  char* w = wsp != nullptr ? (char*)wsp : (char*)ws_get(ctx, "group", group_ws_bytes(n, p));
   int32_t* rank = (int32_t*)w;
   int32_t* bc = rank + n;
   int32_t* bo = bc + nblk * p;

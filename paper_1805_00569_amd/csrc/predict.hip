@@ -18,6 +18,8 @@
 // independent of the launch shape and of the batch.
 #include "common.hpp"
 
+#include <mutex>
+
 namespace krr {
 
 namespace {
@@ -336,27 +338,54 @@ struct Routing {
   int32_t* tile_start = nullptr;
 };
 
+size_t route_ws_bytes(int64_t k, int p) {
+  const size_t kb = ((size_t)k * 4 + 255) & ~size_t(255);
+  return 2 * kb + (size_t)(p + 1) * 8 + (size_t)(p + 1) * 4 + 512;
+}
+
 Routing route_points(krr_ctx ctx, hipStream_t s, const krr_part_data& D, const void* Xt, int dtype, int64_t k,
-                     const std::string& tag) {
+                     const std::string& tag, Arena* ar = nullptr) {
   const int p = D.p;
   const size_t kb = ((size_t)k * 4 + 255) & ~size_t(255);
-  char* w = (char*)ws_get(ctx, "route" + tag, 2 * kb + (size_t)(p + 1) * 8 + (size_t)(p + 1) * 4 + 512);
+  char* w = (char*)ws_or_arena(ctx, ar, "route" + tag, route_ws_bytes(k, p));
   Routing R;
   R.route = (int32_t*)w;
   R.tperm = (int32_t*)(w + kb);
   R.toff = (int64_t*)(w + 2 * kb);
   R.tile_start = (int32_t*)(w + 2 * kb + (((size_t)(p + 1) * 8 + 255) & ~size_t(255)));
   assign_nearest(ctx, s, Xt, dtype, k, D.d, D.ct_t, p, R.route, nullptr, nullptr, nullptr);
-  group_by_key(ctx, s, R.route, k, p, R.tperm, R.toff, nullptr, nullptr);
+  group_by_key(ctx, s, R.route, k, p, R.tperm, R.toff, nullptr, nullptr,
+               ar != nullptr ? ar->take(group_ws_bytes(k, p)) : nullptr);
   hipLaunchKernelGGL(k_tile_prefix, dim3(1), dim3(64), 0, s, (const int64_t*)R.toff, p, R.tile_start);
   check_launch(ctx, s, "tile_prefix");
   return R;
 }
 
+// Launch shape of the prediction kernel: the training chunks of a partition
+// are split over nsplit workgroups of cps chunks each, writing nsplit x npos
+// x nm partial sums.
+struct PredShape {
+  int64_t nsplit, npos, base;
+  int cps;
+};
+
+PredShape pred_shape(const krr_part_data& D, int64_t k, int route) {
+  const int p = D.p;
+  int64_t max_m = 0;
+  for (int j = 0; j < p; ++j) max_m = std::max(max_m, D.offsets[j + 1] - D.offsets[j]);
+  const int64_t chunks = std::max<int64_t>(1, ceil_div(max_m, NB));
+  PredShape S;
+  S.base = (route == KRR_ROUTE_NEAREST) ? ceil_div(k, NB) + p : ceil_div(k, NB) * p;
+  S.nsplit = std::max<int64_t>(1, std::min<int64_t>(chunks, 2048 / std::max<int64_t>(S.base, 1)));
+  S.cps = (int)ceil_div(chunks, S.nsplit);
+  S.npos = (route == KRR_ROUTE_NEAREST) ? k : k * p;
+  return S;
+}
+
 // Predict with nm (<= MAXM) models that share one partitioning.  `dst[q]`
 // receives k values (NEAREST) or the k x p matrix (ALL) of model q.
 void predict_group(krr_ctx ctx, hipStream_t s, const krr_model* models, int nm, const void* Xt, int dtype, int64_t k,
-                   int route, const Routing& R, double* const* dst) {
+                   int route, const Routing& R, double* const* dst, Arena* ar = nullptr) {
   const krr_part_data& D = *models[0]->data;
   KRR_REQUIRE(dtype == D.dtype, "test inputs must have the dtype of the training inputs");
   const int p = D.p;
@@ -382,14 +411,10 @@ void predict_group(krr_ctx ctx, hipStream_t s, const krr_model* models, int nm, 
     M.out[q] = dst[q];
     KRR_REQUIRE(models[q]->params.kernel == M.kernel, "models of one call must share the kernel");
   }
-  int64_t max_m = 0;
-  for (int j = 0; j < p; ++j) max_m = std::max(max_m, D.offsets[j + 1] - D.offsets[j]);
-  const int64_t chunks = std::max<int64_t>(1, ceil_div(max_m, NB));
-  const int64_t base = (route == KRR_ROUTE_NEAREST) ? ceil_div(k, NB) + p : ceil_div(k, NB) * p;
-  const int64_t nsplit = std::max<int64_t>(1, std::min<int64_t>(chunks, 2048 / std::max<int64_t>(base, 1)));
-  const int cps = (int)ceil_div(chunks, nsplit);
-  const int64_t npos = (route == KRR_ROUTE_NEAREST) ? k : k * p;
-  double* part = (double*)ws_get(ctx, "pred_part", (size_t)nsplit * npos * nm * 8);
+  const PredShape S = pred_shape(D, k, route);
+  const int64_t base = S.base, nsplit = S.nsplit, npos = S.npos;
+  const int cps = S.cps;
+  double* part = (double*)ws_or_arena(ctx, ar, "pred_part", (size_t)nsplit * npos * nm * 8);
   {
     KernelTimer kt(ctx, s, "predict", 0.0, 0);
     const dim3 grid = (route == KRR_ROUTE_NEAREST) ? dim3((unsigned)base, 1, (unsigned)nsplit)
@@ -428,16 +453,16 @@ void predict_group(krr_ctx ctx, hipStream_t s, const krr_model* models, int nm, 
 
 // route AVERAGE: ALL into a workspace, then the mean over the p models
 void predict_models(krr_ctx ctx, hipStream_t s, const krr_model* models, int nm, const void* Xt, int dtype, int64_t k,
-                    int route, const Routing& R, double* const* yhat) {
+                    int route, const Routing& R, double* const* yhat, Arena* ar = nullptr) {
   const int p = models[0]->data->p;
   if (route != KRR_ROUTE_AVERAGE) {
-    predict_group(ctx, s, models, nm, Xt, dtype, k, route, R, yhat);
+    predict_group(ctx, s, models, nm, Xt, dtype, k, route, R, yhat, ar);
     return;
   }
-  double* all = (double*)ws_get(ctx, "pred_all", (size_t)k * p * nm * 8);
+  double* all = (double*)ws_or_arena(ctx, ar, "pred_all", (size_t)k * p * nm * 8);
   double* dst[MAXM];
   for (int q = 0; q < nm; ++q) dst[q] = all + (size_t)q * k * p;
-  predict_group(ctx, s, models, nm, Xt, dtype, k, KRR_ROUTE_ALL, R, dst);
+  predict_group(ctx, s, models, nm, Xt, dtype, k, KRR_ROUTE_ALL, R, dst, ar);
   for (int q = 0; q < nm; ++q) {
     hipLaunchKernelGGL(k_row_mean, dim3((unsigned)ceil_div(k, 256)), dim3(256), 0, s, (const double*)dst[q], k, p,
                        yhat[q]);
@@ -448,14 +473,76 @@ void predict_models(krr_ctx ctx, hipStream_t s, const krr_model* models, int nm,
 }  // namespace
 
 void run_predict(krr_ctx ctx, hipStream_t s, krr_model model, const void* Xt, int dtype, int64_t k, int route,
-                 double* yhat, int32_t* route_out) {
+                 double* yhat, int32_t* route_out, Arena* ar) {
   KRR_REQUIRE(model->data->d > 0, "empty model");
   Routing R;
-  if (route == KRR_ROUTE_NEAREST || route_out != nullptr) R = route_points(ctx, s, *model->data, Xt, dtype, k, "");
+  if (route == KRR_ROUTE_NEAREST || route_out != nullptr)
+    R = route_points(ctx, s, *model->data, Xt, dtype, k, "", ar);
   double* dst[1] = {yhat};
-  predict_models(ctx, s, &model, 1, Xt, dtype, k, route, R, dst);
+  predict_models(ctx, s, &model, 1, Xt, dtype, k, route, R, dst, ar);
   if (route_out != nullptr)
     KRR_HIP(hipMemcpyAsync(route_out, R.route, (size_t)k * 4, hipMemcpyDeviceToDevice, s));
+}
+
+// ---------------------------------------------------------------------------
+// Prediction without device allocation.  Every temporary of run_predict
+// (routes, grouping counts and offsets, partial sums, the ALL matrix of the
+// AVERAGE route) is carved from `scratch`, a fixed array that each GPU the
+// library runs on holds until the process ends.  Its device address differs
+// per GPU and is looked up once per device (noalloc_scratch_init, called when
+// a context is created); host code uses only that address, never the array's
+// name.  Every call on one GPU shares the array: calls that overlap on one
+// GPU race.  No temporary needs to start at zero (every value read is written
+// earlier in the same call), so nothing is cleared.
+// ---------------------------------------------------------------------------
+constexpr size_t NOALLOC_SCRATCH = KRR_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static char* g_scratch_ptr[MAX_DEVICES] = {};
+
+void noalloc_scratch_init(int device) {
+  KRR_REQUIRE(device >= 0 && device < MAX_DEVICES, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device] != nullptr) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || ptr == nullptr)
+    fail(KRR_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[device] = (char*)ptr;
+}
+
+void run_predict_noalloc(krr_ctx ctx, hipStream_t s, krr_model model, const void* Xt, int dtype, int64_t k, int route,
+                         double* yhat, int32_t* route_out) {
+  KRR_REQUIRE(model->data->d > 0, "empty model");
+  char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    base = g_scratch_ptr[ctx->device];
+  }
+  if (base == nullptr) fail(KRR_ESTATE, "scratch address of this device was not set up");
+  // the call's temporaries, in the order run_predict takes them
+  const krr_part_data& D = *model->data;
+  size_t need = 0;
+  if (route == KRR_ROUTE_NEAREST || route_out != nullptr) need += al256(route_ws_bytes(k, D.p)) + al256(group_ws_bytes(k, D.p));
+  const int pr = route == KRR_ROUTE_AVERAGE ? (int)KRR_ROUTE_ALL : route;
+  if (route == KRR_ROUTE_AVERAGE) need += al256((size_t)k * D.p * 8);
+  const PredShape S = pred_shape(D, k, pr);
+  need += al256((size_t)S.nsplit * S.npos * 8);
+  if (need > NOALLOC_SCRATCH)
+    fail(KRR_EINVAL, "krr_predict_noalloc: " + std::to_string(k) + " points with " + std::to_string(D.p) +
+                         " partitions need " + std::to_string(need) + " bytes of scratch; the fixed scratch holds " +
+                         std::to_string(NOALLOC_SCRATCH) + " bytes");
+  Arena ar;
+  ar.base = base;
+  ar.cap = NOALLOC_SCRATCH;
+  struct NoAllocScope {
+    krr_ctx c;
+    explicit NoAllocScope(krr_ctx x) : c(x) { c->noalloc = 1; }
+    ~NoAllocScope() { c->noalloc = 0; }
+  } scope(ctx);
+  run_predict(ctx, s, model, Xt, dtype, k, route, yhat, route_out, &ar);
 }
 
 void run_select(krr_ctx ctx, hipStream_t s, const krr_model* models, int n_models, const void* Xv, const void* yv,

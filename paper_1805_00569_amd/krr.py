@@ -86,6 +86,7 @@ _SIGS = {
                  ctypes.POINTER(FitParams), ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(PartInfo)],
                 ctypes.c_int),
     "krr_predict": ([_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P, _P], ctypes.c_int),
+    "krr_predict_noalloc": ([_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P, _P], ctypes.c_int),
     "krr_select": ([_P, _P, ctypes.POINTER(_P), ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.c_int64,
                     ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "krr_model_alpha": ([_P, _P, _P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
@@ -279,6 +280,14 @@ class Context:
         self._check(self.lib.krr_predict(self.h, _stream(self.device), model.handle, _ptr(Xt), _dtype_code(Xt), k,
                                          ROUTE[route], _ptr(out), _ptr(r)))
         return (out, r) if want_route else out
+
+    def predict_noalloc(self, model, Xt, yhat, route="nearest", route_out=None):
+        """krr_predict_noalloc into caller-allocated outputs: yhat FP64 (k, or
+        k x p for "all"), route_out int32[k] or None."""
+        self._check(self.lib.krr_predict_noalloc(self.h, _stream(self.device), model.handle, _ptr(Xt),
+                                                 _dtype_code(Xt), Xt.shape[0], ROUTE[route], _ptr(yhat),
+                                                 _ptr(route_out)))
+        return yhat
 
     def select(self, models, Xv, yv, route="nearest"):
         k = Xv.shape[0]
