@@ -394,9 +394,23 @@ def kernel_matrix(A, B, sigma, kernel="gaussian"):
     raise ValueError(kernel)
 
 
-def fit_one(Xj, yj, sigma, lam, kernel="gaussian", lambda_times_m=False):
+def solve_lu(A, b):
+    """Solution of the (possibly indefinite) system A x = b by LU with
+    partial pivoting (LAPACK dgetrf / dgetrs through SciPy).  Returns
+    (x, singular): singular when a zero pivot makes A numerically singular."""
+    lu, piv = scipy.linalg.lu_factor(np.asarray(A, np.float64), check_finite=False)
+    if np.any(np.diag(lu) == 0.0):
+        return np.full(A.shape[0], np.nan), True
+    return scipy.linalg.lu_solve((lu, piv), np.asarray(b, np.float64), check_finite=False), False
+
+
+def fit_one(Xj, yj, sigma, lam, kernel="gaussian", lambda_times_m=False, indefinite=False):
     """Solve (K + lambda_eff I) alpha = y by Cholesky (Eq. 6, Algorithm 1).
-    Returns dict(alpha, status, pivot, backward_error, lambda_eff)."""
+    With `indefinite`, a system whose Cholesky factorisation meets a
+    non-positive pivot (the sigmoid kernel of Table 1 is not positive
+    semi-definite in general) is solved by LU with partial pivoting instead
+    (solve_lu) and reported with solver "lu".
+    Returns dict(alpha, status, pivot, backward_error, lambda_eff, solver)."""
     m = Xj.shape[0]
     lam_eff = lam * m if lambda_times_m else lam
     if m == 0:   # an empty partition (K-means may leave a cluster empty) has no system
@@ -410,14 +424,22 @@ def fit_one(Xj, yj, sigma, lam, kernel="gaussian", lambda_times_m=False):
     except np.linalg.LinAlgError as e:
         # LAPACK dpotrf reports the order of the first non-positive leading minor
         piv = _first_bad_pivot(A)
+        if indefinite:
+            alpha, singular = solve_lu(A, yj)
+            if not singular:
+                r = A @ alpha - yj
+                be = np.linalg.norm(r) / (np.linalg.norm(A, 2 if m <= 512 else "fro") * np.linalg.norm(alpha)
+                                          + np.linalg.norm(yj))
+                return {"alpha": alpha, "status": STATUS_OK, "pivot": piv, "backward_error": float(be),
+                        "lambda_eff": lam_eff, "solver": "lu"}
         return {"alpha": np.full(m, np.nan), "status": STATUS_NOT_SPD, "pivot": piv,
-                "backward_error": math.inf, "lambda_eff": lam_eff, "err": str(e)}
+                "backward_error": math.inf, "lambda_eff": lam_eff, "err": str(e), "solver": "none"}
     alpha = scipy.linalg.cho_solve(c, yj, check_finite=False)
     r = A @ alpha - yj
     be = np.linalg.norm(r) / (np.linalg.norm(A, 2 if m <= 512 else "fro") * np.linalg.norm(alpha)
                               + np.linalg.norm(yj))
     return {"alpha": alpha, "status": STATUS_OK, "pivot": 0, "backward_error": float(be),
-            "lambda_eff": lam_eff}
+            "lambda_eff": lam_eff, "solver": "cholesky"}
 
 
 def _first_bad_pivot(A):
@@ -447,14 +469,14 @@ class Model:
         self.infos = infos
 
 
-def fit(X, y, a, centroids, p, sigma, lam, kernel="gaussian", lambda_times_m=False):
+def fit(X, y, a, centroids, p, sigma, lam, kernel="gaussian", lambda_times_m=False, indefinite=False):
     """Per-partition fits (Algorithm 5 training phase)."""
     perm, off = gather(a, p)
     Xparts, alphas, infos = [], [], []
     for j in range(p):
         idx = perm[off[j]:off[j + 1]]
         Xj = np.asarray(X, np.float64)[idx]
-        r = fit_one(Xj, np.asarray(y, np.float64)[idx], sigma, lam, kernel, lambda_times_m)
+        r = fit_one(Xj, np.asarray(y, np.float64)[idx], sigma, lam, kernel, lambda_times_m, indefinite)
         Xparts.append(Xj)
         alphas.append(r["alpha"])
         infos.append(r)

@@ -651,3 +651,66 @@ def test_empty_partition_has_no_system():
     assert m.alphas[1].shape == (0,) and m.infos[1]["status"] == O.STATUS_OK
     yhat, r = O.predict(m, np.zeros((2, 2)))
     assert r.tolist() == [0, 0]
+
+
+def _exact_solve(A, b):
+    """Gauss-Jordan elimination in exact rational arithmetic (any nonzero
+    pivot): the exact solution of A x = b for integer A, b."""
+    from fractions import Fraction
+    n = len(b)
+    M = [[Fraction(int(v)) for v in row] + [Fraction(int(bi))] for row, bi in zip(A, b)]
+    for c in range(n):
+        r = next(i for i in range(c, n) if M[i][c] != 0)
+        M[c], M[r] = M[r], M[c]
+        for i in range(n):
+            if i != c and M[i][c] != 0:
+                f = M[i][c] / M[c][c]
+                M[i] = [a - f * bb for a, bb in zip(M[i], M[c])]
+    return [M[i][n] / M[i][i] for i in range(n)]
+
+
+def test_lu_solve_hand_worked_indefinite_3x3():
+    """A = [[1, 2, 0], [2, 1, 0], [0, 0, -1]] (eigenvalues 3, -1, -1: symmetric
+    indefinite, no Cholesky factor), y = (3, 3, -2): by hand x1 + 2 x2 = 3,
+    2 x1 + x2 = 3 give x1 = x2 = 1, and -x3 = -2 gives x3 = 2."""
+    A = np.array([[1.0, 2.0, 0.0], [2.0, 1.0, 0.0], [0.0, 0.0, -1.0]])
+    x, singular = O.solve_lu(A, np.array([3.0, 3.0, -2.0]))
+    assert not singular
+    np.testing.assert_array_equal(x, [1.0, 1.0, 2.0])
+    with pytest.raises(np.linalg.LinAlgError):
+        scipy.linalg.cho_factor(A)
+
+
+def test_lu_solve_against_exact_rational_elimination():
+    """Random integer symmetric indefinite systems (6 x 6): the oracle's
+    FP64 LU solution agrees with the exact rational solution to a few units
+    of the condition-scaled roundoff."""
+    g = np.random.default_rng(4)
+    for _ in range(5):
+        B = g.integers(-5, 6, (6, 6))
+        A = (B + B.T).astype(np.int64)
+        A[0, 0] = -abs(A[0, 0]) - 1   # at least one negative diagonal entry: not positive definite
+        b = g.integers(-9, 10, 6)
+        exact = np.array([float(v) for v in _exact_solve(A.tolist(), b.tolist())])
+        x, singular = O.solve_lu(A.astype(np.float64), b.astype(np.float64))
+        assert not singular
+        kappa = np.linalg.cond(A.astype(np.float64))
+        assert np.max(np.abs(x - exact)) <= 64 * kappa * 2.0 ** -53 * np.max(np.abs(exact))
+
+
+def test_sigmoid_indefinite_fit_solves_by_lu():
+    """A sigmoid kernel system that is not positive definite: without
+    `indefinite` the oracle reports the failing pivot; with it, it returns
+    the LU solution, whose residual is at the FP64 level and which equals the
+    exact solution of the rounded system within its condition."""
+    X = np.array([[0.0, 1.0], [1.0, 0.0], [1.0, 1.0], [2.0, -1.0]])
+    y = np.array([1.0, -1.0, 0.5, 2.0])
+    ker = ("sigmoid", 1.0, -1.0)
+    r0 = O.fit_one(X, y, 1.0, 0.0, ker)
+    assert r0["status"] == O.STATUS_NOT_SPD and r0["pivot"] >= 1
+    r1 = O.fit_one(X, y, 1.0, 0.0, ker, indefinite=True)
+    assert r1["status"] == O.STATUS_OK and r1["solver"] == "lu"
+    A = O.kernel_matrix(X, X, 1.0, ker)
+    assert np.min(np.linalg.eigvalsh(A)) < 0.0
+    assert r1["backward_error"] < 1e-14
+    np.testing.assert_allclose(A @ r1["alpha"], y, rtol=0, atol=1e-12 * np.linalg.cond(A))
