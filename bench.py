@@ -101,8 +101,11 @@ def main():
     ap.add_argument("--cpu-fits", type=int, default=2, help="oracle fits timed for the CPU baseline")
     ap.add_argument("--panel", type=int, default=0, help="Cholesky panel width in 64-wide tiles (0: library default)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
-    ap.add_argument("--serve-rates", default="100,500,2000", help="Poisson arrival rates (requests/s)")
-    ap.add_argument("--serve-seconds", type=float, default=2.0, help="length of each rate's arrival trace")
+    ap.add_argument("--no-legs", action="store_true", help="skip the plain, stress and ragged workloads")
+    ap.add_argument("--no-dkrr", action="store_true", help="skip the single n = 131,072 system")
+    ap.add_argument("--serve-rates", default="50,100,200,500,1000,2000,5000",
+                    help="Poisson arrival rates (requests/s)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="length of each rate's arrival trace")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
@@ -208,13 +211,14 @@ def main():
                          "lambda": params[state["best"]].lam, "val_mse": state["mse"][state["best"]]},
     }
 
-    out["roofline"] = roofline(timed_kernels, args.steps)
-
     phases = {}
     ctx.set_option(krr.OPT_TIMING, 2)
     step(phases=phases)
     kern = ctx.timing_report()
     ctx.set_option(krr.OPT_TIMING, 0)
+    out["roofline"] = roofline(timed_kernels, args.steps)
+    out["roofline"]["factorisation"] = factorisation_summary(kern, sum(float(m) ** 3 / 3.0 for m in m_sizes),
+                                                             "bf16" if args.prec == "mixed" else args.prec)
     out["phase_ms"] = {k: round(v * 1e3, 3) for k, v in phases.items()}
     out["kernel_ms_per_step"] = {k: round(v["ms"], 3) for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])}
 
@@ -258,6 +262,21 @@ def main():
     # oracle on the host: a bounded sample of the same fits
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, state, ctx, params, args.cpu_fits)
+        out["cpu_gram_baseline"] = cpu_gram_baseline(w, state, params)
+
+    # the other workloads: plain KRR (p = 1), the ragged K-means batch, the
+    # balanced workload far from the identity
+    if not args.no_legs:
+        legs = {}
+        legs_run = [("plain_p1", plain_leg), ("stress_median_sigma", lambda: stress_leg(w, X, y, state)),
+                    ("ragged_kmeans", ragged_leg)]
+        if not args.no_dkrr:
+            legs_run.append(("dkrr_single_131072", dkrr_leg))
+        for name, fn in legs_run:
+            t1 = time.time()
+            legs[name] = fn()
+            print(f"# leg {name} done in {time.time() - t1:.1f}s", file=sys.stderr, flush=True)
+        out["legs"] = legs
 
     if not args.no_serve:
         del X, y, Xv, yv, Xt
@@ -341,7 +360,8 @@ def serving_leg(rates, seconds, seed=5):
                    "fits_per_s": s["fit_requests"] / span, "predictions_per_s": s["points"] / span,
                    "mean_predict_batch": s["predict_requests"] / max(s["predict_batches"], 1),
                    "mean_fit_batch": s["fit_requests"] / max(s["fit_batches"], 1),
-                   "failed": s["failed"] + bad, "max_inflight_bytes": s["max_inflight_bytes"]}
+                   "failed": s["failed"] + bad, "max_inflight_bytes": s["max_inflight_bytes"],
+                   "max_device_bytes": s["max_device_bytes"]}
             res["rates"].append(row)
             print(f"# serving rate {rate:g}/s: {len(trace)} requests, predict p50 {row['predict_p50_ms']:.2f} ms "
                   f"p99 {row['predict_p99_ms']:.2f} ms, fit p50 {row['fit_p50_ms']:.1f} ms",
@@ -353,12 +373,29 @@ def serving_leg(rates, seconds, seed=5):
     return res
 
 
-def roofline(timed, steps):
+def factorisation_summary(kern, chol_flops, prec):
+    """The whole Cholesky factorisation of one step (every chol_* kernel
+    class of a step timed with all classes on): the method's m^3/3 per system
+    over the summed event time, against the matrix-core peak of `prec`."""
+    chol = {k: v for k, v in kern.items() if k.startswith("chol_")}
+    ms = sum(v["ms"] for v in chol.values())
+    tf = chol_flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    return {"classes": {k: round(v["ms"], 4) for k, v in sorted(chol.items())}, "ms_per_step": ms,
+            "flops_per_step": chol_flops, "achieved_tflops": tf, "peak_tflops": PEAK[prec], "frac": tf / PEAK[prec]}
+
+
+def roofline(timed, steps, chol_flops_per_step=None):
     """Roofline entry of the kernel class with the most event time in the
-    timed steps.  The bound is the one its algorithmic intensity (flops per
-    algorithmic HBM byte) puts it under: HBM below the ridge point of the
-    class's matrix-core peak, the matrix cores above it.  achieved =
-    algorithmic bytes (or flops) of its launches / their summed duration."""
+    timed steps.  The Cholesky kernels (classes chol_*) are a dense
+    contraction: they are priced against the matrix-core peak of their
+    operand precision with the method's own flops (the m^3/3 of the
+    factorisation, split by launch; padding and the inverse diagonal blocks
+    are not credited), and their HBM view (algorithmic bytes per launch over
+    the launch time) is reported beside it.  Other classes take the bound
+    their algorithmic intensity puts them under.  achieved = algorithmic
+    flops (or bytes) of the launches / their summed duration.
+    `factorisation`: all chol_* classes together, m^3/3 per system over
+    their summed time, against the same peak."""
     if not timed:
         return None
     name, rec = max(timed.items(), key=lambda kv: kv[1]["ms"])
@@ -370,16 +407,24 @@ def roofline(timed, steps):
            "avg_launch_us": 1e3 * rec["ms"] / cnt, "algorithmic_flops_per_launch": flops / cnt,
            "algorithmic_bytes_per_launch": byts / cnt if byts > 0 else None,
            "intensity_flop_per_byte": flops / byts if byts > 0 else None,
-           "ridge_flop_per_byte": ridge, "mfma_peak_tflops": PEAK[prec],
-           "achieved_tflops": flops / sec / 1e12 if sec > 0 else 0.0}
-    if byts > 0 and flops / byts < ridge:
-        achieved = byts / sec / 1e9 if sec > 0 else 0.0
-        out.update(bound="hbm", achieved=achieved, peak=HBM_PEAK, unit="GB/s", frac=achieved / HBM_PEAK)
-    else:
+           "ridge_flop_per_byte": ridge, "mfma_peak_tflops": PEAK[prec]}
+    if name.startswith("chol_") or not (byts > 0 and flops / byts < ridge):
         achieved = flops / sec / 1e12 if sec > 0 else 0.0
         out.update(bound="mfma", achieved=achieved, peak=PEAK[prec], unit="TFLOP/s", frac=achieved / PEAK[prec])
+        if byts > 0 and sec > 0:
+            gbs = byts / sec / 1e9
+            out["hbm_view"] = {"achieved_gbs": gbs, "peak_gbs": HBM_PEAK, "frac": gbs / HBM_PEAK}
+    else:
+        achieved = byts / sec / 1e9 if sec > 0 else 0.0
+        out.update(bound="hbm", achieved=achieved, peak=HBM_PEAK, unit="GB/s", frac=achieved / HBM_PEAK)
     out["traffic"] = _traffic_bytes(name)
     out["other_timed_classes_ms_per_step"] = {k: v["ms"] / steps for k, v in timed.items() if k != name}
+    chol = {k: v for k, v in timed.items() if k.startswith("chol_")}
+    if chol and chol_flops_per_step:
+        ms = sum(v["ms"] for v in chol.values()) / steps
+        tf = chol_flops_per_step / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        out["factorisation"] = {"classes": sorted(chol), "ms_per_step": ms, "flops_per_step": chol_flops_per_step,
+                                "achieved_tflops": tf, "peak_tflops": PEAK[prec], "frac": tf / PEAK[prec]}
     return {k: out[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")} | \
         {k: v for k, v in out.items() if k not in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
 
@@ -397,16 +442,261 @@ def cpu_baseline(w, state, ctx, params, n_fits):
     info = threadpoolctl.threadpool_info()
     threads = max([i.get("num_threads", 1) for i in info] + [1])
     t = time.perf_counter()
-    alphas = []
     for q in range(n_fits):
-        r = O.fit_one(Xj, yj, params[q].sigma, params[q].lam)
-        alphas.append(r["alpha"])
+        O.fit_one(Xj, yj, params[q].sigma, params[q].lam)
     dt = time.perf_counter() - t
+    with threadpoolctl.threadpool_limits(1):
+        t = time.perf_counter()
+        O.fit_one(Xj, yj, params[0].sigma, params[0].lam)
+        dt1 = time.perf_counter() - t
     m = Xj.shape[0]
     return {"value": n_fits / dt, "unit": "fits/s", "cores": threads, "kind": "oracle",
             "sample": f"{n_fits} fits of partition 0 (m={m}, d={w.d}): direct-difference FP64 kernel "
-                      f"+ LAPACK Cholesky, settings {[(params[q].sigma, params[q].lam) for q in range(n_fits)]}",
-            "seconds": dt, "cpu": _cpu_name(), "os_cpu_count": os.cpu_count()}
+                      f"+ LAPACK Cholesky, settings {[(params[q].sigma, params[q].lam) for q in range(n_fits)]}; "
+                      f"one more fit on one thread",
+            "seconds": dt, "one_thread_fits_per_s": 1.0 / dt1,
+            "blas": sorted({f"{i.get('internal_api')} {i.get('version')}" for i in info}),
+            "cpu": _cpu_name(), "os_cpu_count": os.cpu_count()}
+
+
+def _timed_fit(ctx, X, y, a, C, p, params, reps=3):
+    """Median wall time of `reps` fits (after one warm fit), the infos of the last."""
+    import torch
+    models, info, st = ctx.fit(X, y, a, C, p, params)
+    for m in models:
+        m.free()
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        models, info, st = ctx.fit(X, y, a, C, p, params)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+        for m in models:
+            m.free()
+    return float(np.median(ts)), info, st
+
+
+def plain_leg(reps=5):
+    """Plain KRR (Algorithm 1, p = 1) in FP64: n = 2,048 training and 512 test
+    points, d = 16, sigma = 1, lambda = 1e-3.  Fit (form K, Cholesky, solves),
+    predict, test MSE; alpha and predictions against the oracle; the same in
+    mixed precision with its refinement."""
+    import torch
+    import oracle as O
+    from paper_1805_00569_amd import datagen, krr
+    dev = torch.device("cuda:0")
+    w = datagen.plain_krr()
+    X, y, Xt = (torch.from_numpy(v).to(dev) for v in (w.X, w.y, w.Xt))
+    ctx = krr.Context(0)
+    C, a, _ = ctx.partition(X, 1, "kmeans", lloyd_iters=1, seed=1)
+    om = O.fit(w.X, w.y, a.cpu().numpy(), C.cpu().numpy(), 1, 1.0, 1e-3)
+    yo, _ = O.predict(om, w.Xt)
+    res = {"workload": "plain KRR p=1: n=2048 train, 512 test, d=16, x~N(0,I), y=sin(x0+x1+x2)+0.1N, sigma=1, "
+                       "lambda=1e-3", "fits_per_step": 1}
+    for prec in ("fp64", "mixed"):
+        params = [krr.Params(sigma=1.0, lam=1e-3, prec=prec, refine_tol=1e-10 if prec == "mixed" else 1e-6,
+                             max_refine=30)]
+        tf, info, st = _timed_fit(ctx, X, y, a, C, 1, params, reps)
+        models, info, st = ctx.fit(X, y, a, C, 1, params)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            yhat = ctx.predict(models[0], Xt)
+        torch.cuda.synchronize()
+        tp = (time.perf_counter() - t) / reps
+        yh = yhat.cpu().numpy()
+        al = models[0].alpha(0).cpu().numpy()
+        A = O.kernel_matrix(w.X, w.X, 1.0) + 1e-3 * np.eye(w.n)
+        r = A @ al - w.y
+        res[prec] = {"fit_ms": tf * 1e3, "predict_ms": tp * 1e3, "status": st,
+                     "gflops": fit_flops(w.n, w.d) / tf / 1e9,
+                     "frac_fp64_peak": fit_flops(w.n, w.d) / tf / 1e12 / PEAK["fp64"],
+                     "test_mse": float(np.mean((yh - w.yt) ** 2)),
+                     "rel_residual": float(np.linalg.norm(r) / np.linalg.norm(w.y)),
+                     "alpha_err_vs_oracle": float(np.max(np.abs(al - om.alphas[0])) / np.max(np.abs(om.alphas[0]))),
+                     "pred_err_vs_oracle": float(np.max(np.abs(yh - yo)) / np.max(np.abs(yo))),
+                     "refine_iters": info[0]["refine_iters"], "kappa_est": info[0]["kappa_est"]}
+        for m in models:
+            m.free()
+    res["oracle_test_mse"] = float(np.mean((yo - w.yt) ** 2))
+    ctx.close()
+    return res
+
+
+def stress_leg(w, X, y, state, reps=3):
+    """The balanced workload's data and K-balance partitions with the
+    median-heuristic sigma (K far from the identity, kappa ~ 3e4..7e4 at
+    m = 4,096), lambda in {1e-4, 1e-2}: 32 fits.  Batched mixed precision
+    (alpha to 1e-6 of the FP64 solution) against batched FP64 and the plain
+    per-partition FP64 sequence; refinement steps, fallbacks, the factor's
+    condition estimate, and alpha of partition 0 against the oracle."""
+    import torch
+    import oracle as O
+    from paper_1805_00569_amd import datagen, krr
+    sig = datagen.median_heuristic_sigma(w.X)
+    C, a = state["C"], state["assign"]
+    ctx = krr.Context(0)
+    lams = (1e-4, 1e-2)
+    res = {"workload": f"balanced data and partitions, sigma = median heuristic = {sig:.4f}, lambda in {lams}, "
+                       f"{2 * P_PARTS} fits", "sigma": sig, "fits_per_step": 2 * P_PARTS}
+    out_alpha = {}
+    m_sizes = None
+    for name, prec, serial in (("batched_mixed", "mixed", False), ("batched_fp64", "fp64", False),
+                               ("plain_fp64_per_partition", "fp64", True)):
+        params = [krr.Params(sigma=sig, lam=l, prec=prec, refine_tol=1e-6, max_refine=30) for l in lams]
+        ctx.set_option(krr.OPT_SERIAL_FIT, 1 if serial else 0)
+        tf, info, st = _timed_fit(ctx, X, y, a, C, P_PARTS, params, 1 if serial else reps)
+        ctx.set_option(krr.OPT_SERIAL_FIT, 0)
+        m_sizes = [r["m"] for r in info]
+        fl = sum(fit_flops(m, w.d) for m in m_sizes)
+        row = {"fit_ms": tf * 1e3, "fits_per_s": len(info) / tf, "tflops": fl / tf / 1e12, "status": st}
+        if prec == "mixed":
+            row.update(max_refine_iters=max(r["refine_iters"] for r in info),
+                       fallbacks=sum(r["fallback"] for r in info),
+                       kappa_est_range=[min(r["kappa_est"] for r in info), max(r["kappa_est"] for r in info)],
+                       max_err_est=max(r["err_est"] for r in info),
+                       max_rel_residual=max(r["rel_residual"] for r in info))
+        res[name] = row
+        if not serial:
+            models, info, st = ctx.fit(X, y, a, C, P_PARTS, params)
+            out_alpha[name] = [models[q].alpha(0).cpu().numpy() for q in range(len(lams))]
+            for mdl in models:
+                mdl.free()
+        print(f"# stress {name}: {tf * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    base = res["plain_fp64_per_partition"]["fit_ms"]
+    for k in ("batched_mixed", "batched_fp64", "plain_fp64_per_partition"):
+        res[k]["speedup_vs_plain_fp64"] = base / res[k]["fit_ms"]
+    # partition 0 of both settings against the oracle (alpha error, kappa_2)
+    an = state["assign"].cpu().numpy()
+    idx = np.nonzero(an == 0)[0]
+    Xj = w.X[idx].astype(np.float64)
+    yj = w.y.astype(np.float32).astype(np.float64)[idx]
+    K = O.kernel_matrix(Xj, Xj, sig)
+    ev = np.linalg.eigvalsh(K)
+    chk = []
+    for q, lam in enumerate(lams):
+        ref = O.fit_one(Xj, yj, sig, lam)["alpha"]
+        den = np.max(np.abs(ref))
+        chk.append({"lambda": lam, "kappa2": float((ev[-1] + lam) / (ev[0] + lam)),
+                    "alpha_err_mixed": float(np.max(np.abs(out_alpha["batched_mixed"][q] - ref)) / den),
+                    "alpha_err_fp64": float(np.max(np.abs(out_alpha["batched_fp64"][q] - ref)) / den)})
+    res["oracle_check_partition0"] = chk
+    ctx.close()
+    return res
+
+
+def ragged_leg(reps=3):
+    """Ragged KKRR2 batch: n = 131,072, d = 90, 32-component Gaussian mixture
+    with Zipf(1.1) weights water-filled into [512, 14,000]; K-means (k-means++
+    and 20 Lloyd passes) into 32 partitions; all 32 uneven systems fitted as
+    one batch in FP32 (sigma = 2, lambda = 1e-2), and in mixed precision."""
+    import torch
+    from paper_1805_00569_amd import datagen, krr
+    dev = torch.device("cuda:0")
+    w = datagen.gaussian_mixture(seed=3)
+    X, y = torch.from_numpy(w.X).to(dev), torch.from_numpy(w.y.astype(np.float32)).to(dev)
+    ctx = krr.Context(0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    C, a, sz = ctx.partition(X, 32, "kmeans", lloyd_iters=LLOYD, seed=3)
+    torch.cuda.synchronize()
+    tpart = time.perf_counter() - t
+    sizes = sorted(int(v) for v in sz.cpu().numpy())
+    res = {"workload": "KKRR2 ragged: n=131072, d=90, 32-component GMM (Zipf 1.1, clipped to [512, 14000]), "
+                       "K-means p=32 (k-means++ + 20 Lloyd), 32 uneven systems in one batch, sigma=2, lambda=1e-2",
+           "partition_ms": tpart * 1e3, "sizes_min_median_max": [sizes[0], sizes[len(sizes) // 2], sizes[-1]],
+           "fits_per_step": 32}
+    fl = sum(fit_flops(m, w.d) for m in sizes)
+    res["cholesky_tflop"] = sum(float(m) ** 3 / 3.0 for m in sizes) / 1e12
+    for prec in ("fp32", "mixed"):
+        params = [krr.Params(sigma=2.0, lam=1e-2, prec=prec, refine_tol=1e-6, max_refine=30)]
+        tf, info, st = _timed_fit(ctx, X, y, a, C, 32, params, reps)
+        res[prec] = {"fit_ms": tf * 1e3, "fits_per_s": 32 / tf, "tflops": fl / tf / 1e12, "status": st,
+                     "frac_peak": fl / tf / 1e12 / PEAK["fp32" if prec == "fp32" else "bf16"]}
+        print(f"# ragged {prec}: {tf * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    ctx.close()
+    return res
+
+
+def dkrr_leg():
+    """Exact KRR of one system (Algorithm 1, p = 1) at n = 131,072, d = 90
+    (the balanced workload's generator, sigma = 4, lambda = 1e-2): one fit in
+    FP64 and one in mixed precision (refinement to 1e-8), TFLOP/s of the
+    method's flops against the FP64 and BF16 matrix-core peaks."""
+    import torch
+    from paper_1805_00569_amd import datagen, krr
+    dev = torch.device("cuda:0")
+    w = datagen.balanced(seed=6, n=131072, k_test=512, p=1)
+    res = {"workload": "DKRR single system: n=131072, d=90, sigma=4, lambda=1e-2 (one fit per precision)",
+           "n": w.n, "d": w.d}
+    fl = fit_flops(w.n, w.d)
+    res["fit_tflop"] = fl / 1e12
+    for prec in ("fp64", "mixed"):
+        ctx = krr.Context(0)
+        try:
+            X, y = torch.from_numpy(w.X).to(dev), torch.from_numpy(w.y.astype(np.float32)).to(dev)
+            a = torch.zeros(w.n, dtype=torch.int32, device=dev)
+            C = torch.zeros((1, w.d), dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            models, info, st = ctx.fit(X, y, a, C, 1, [krr.Params(sigma=4.0, lam=1e-2, prec=prec, refine_tol=1e-8,
+                                                                  max_refine=20)])
+            torch.cuda.synchronize()
+            tf = time.perf_counter() - t
+            peak = PEAK["fp64" if prec == "fp64" else "bf16"]
+            res[prec] = {"fit_s": tf, "tflops": fl / tf / 1e12, "frac_peak": fl / tf / 1e12 / peak,
+                         "status": st, "refine_iters": info[0]["refine_iters"], "fallback": info[0]["fallback"],
+                         "rel_residual": info[0]["rel_residual"], "device_bytes": ctx.memory_in_use()}
+            print(f"# dkrr {prec}: {tf:.2f} s", file=sys.stderr, flush=True)
+            models[0].free()
+            del X, y
+        finally:
+            ctx.close()
+            torch.cuda.empty_cache()
+    return res
+
+
+def cpu_gram_baseline(w, state, params, n_parts=P_PARTS):
+    """A tuned CPU baseline beside the oracle: K in Gram form (one dgemm for
+    X X^T, then the exponential), LAPACK dpotrf + dpotrs, for every partition
+    of the first setting on all host cores, and two partitions on one thread;
+    credited with the same algorithmic flops as the GPU fits."""
+    import scipy.linalg
+    import threadpoolctl
+    a = state["assign"].cpu().numpy()
+    yo = w.y.astype(np.float32).astype(np.float64)
+    sig, lam = params[0].sigma, params[0].lam
+
+    def one(j):
+        idx = np.nonzero(a == j)[0]
+        Xj = w.X[idx].astype(np.float64)
+        nr = np.einsum("ij,ij->i", Xj, Xj)
+        G = Xj @ Xj.T
+        D = np.maximum(nr[:, None] + nr[None, :] - 2.0 * G, 0.0)
+        K = np.exp(D * (-1.0 / (2.0 * sig * sig)))
+        K[np.diag_indices_from(K)] = 1.0 + lam
+        c = scipy.linalg.cho_factor(K, lower=True, check_finite=False)
+        scipy.linalg.cho_solve(c, yo[idx], check_finite=False)
+        return idx.size
+
+    t = time.perf_counter()
+    ms = [one(j) for j in range(n_parts)]
+    dt_all = time.perf_counter() - t
+    with threadpoolctl.threadpool_limits(1):
+        t = time.perf_counter()
+        ms1 = [one(j) for j in range(2)]
+        dt_1 = time.perf_counter() - t
+    info = threadpoolctl.threadpool_info()
+    fl = sum(fit_flops(m, w.d) for m in ms)
+    fl1 = sum(fit_flops(m, w.d) for m in ms1)
+    return {"value": n_parts / dt_all, "unit": "fits/s", "gflops": fl / dt_all / 1e9,
+            "cores": max([i.get("num_threads", 1) for i in info] + [1]),
+            "one_thread": {"fits_per_s": 2 / dt_1, "gflops": fl1 / dt_1 / 1e9},
+            "kind": "gram-form dgemm + dpotrf + dpotrs",
+            "blas": sorted({f"{i.get('internal_api')} {i.get('version')}" for i in info}),
+            "sample": f"all {n_parts} partitions of (sigma={sig}, lambda={lam}) on all cores; partitions 0-1 on "
+                      f"one thread"}
 
 
 def _cpu_name():

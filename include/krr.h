@@ -87,8 +87,12 @@ typedef enum {
  *        diagonal blocks factored in FP64; no refinement.
  * MIXED: FP32 storage, BF16 matrix-core trailing updates with FP32
  *        accumulation, FP64 diagonal blocks, then iterative refinement with an
- *        FP64 residual r = y - (K + lambda I) alpha until ||r|| / ||y|| <=
- *        refine_tol. */
+ *        FP64 residual r = y - (K + lambda I) alpha until alpha's estimated
+ *        error is within refine_tol (see krr_fit_params).  A system whose
+ *        BF16-updated factor is not positive definite, whose kappa_est exceeds
+ *        128 (BF16 rounding would not contract), or whose refinement stops
+ *        halving the residual is refactored with FP32 updates and refined again
+ *        (krr_part_info.fallback = 1). */
 typedef enum { KRR_PREC_FP64 = 0, KRR_PREC_FP32 = 1, KRR_PREC_MIXED = 2 } krr_prec;
 
 /* Prediction routes.  NEAREST: model of the nearest centre (KKRR2 / BKRR2,
@@ -115,7 +119,12 @@ typedef struct {
                              as KRR_ENOTSPD with the failing pivot */
   int32_t kernel;         /* krr_kernel */
   int32_t prec;           /* krr_prec */
-  double  refine_tol;     /* MIXED: stop when ||r||/||y|| <= refine_tol (e.g. 1e-6) */
+  double  refine_tol;     /* MIXED: target relative residual and relative error of alpha
+                             (e.g. 1e-6).  A system converges when ||r||/||y|| <= refine_tol
+                             and either kappa_bound * ||r||/||y|| <= refine_tol or, once
+                             corrections have been applied, the error estimate from their
+                             sizes (||delta|| rho / (1 - rho) / ||alpha||, rho the ratio of the
+                             last two corrections) is <= refine_tol */
   int32_t max_refine;     /* MIXED: at most this many refinement steps (0 = none) */
   int32_t lambda_times_m; /* 1: shift is lambda * m_j per partition (Algorithms 3, 5, 6);
                              0: shift is lambda (Eq. 6 with the 1/n folded in) */
@@ -137,6 +146,15 @@ typedef struct {
                              was not positive definite or refinement stalled */
   int32_t reserved;
   double  rel_residual;   /* ||y - (K + lambda I) alpha|| / ||y|| in FP64 (MIXED; -1 otherwise) */
+  double  kappa_est;      /* (max_i L_ii / min_i L_ii)^2 of the factor: a lower bound of the
+                             2-norm condition number of K + lambda I (1 for an empty system) */
+  double  err_est;        /* MIXED: estimated relative error of alpha when refinement stopped
+                             (the smaller of kappa_bound * ||r||/||y|| and the estimate from
+                             the corrections, see refine_tol); -1 otherwise */
+  double  kappa_bound;    /* MIXED: an upper bound of the 2-norm condition number of the FP64
+                             system (Gershgorin's discs; for a positive semi-definite kernel the
+                             smallest eigenvalue is also at least lambda); inf when no bound is
+                             available; -1 otherwise */
 } krr_part_info;
 
 /* Tunables (krr_set_option).  Values apply to later calls on the context. */
@@ -146,10 +164,47 @@ typedef enum {
                                sequence per (partition, setting) -- the plain per-partition
                                baseline; 0 (default): one batched launch sequence */
   KRR_OPT_SYNC_CHECK = 2,   /* 1: synchronise after every launch and report faults (debug) */
-  KRR_OPT_TIMING = 3        /* HIP-event timing of kernel launches: 0 off, 1 the matrix-core
+  KRR_OPT_TIMING = 3,       /* HIP-event timing of kernel launches: 0 off, 1 the matrix-core
                                factorisation updates only, 2 every timed kernel class;
                                setting it clears the record (see krr_timing_report) */
+  KRR_OPT_PERSISTENT = 4,   /* 1: the batched factorisation runs as one persistent launch:
+                               every stage of every system from device task queues, each
+                               system advancing on its own (ragged batches need no barrier
+                               between systems); 0 (default): one launch per stage for the
+                               whole batch.  Both give identical results */
+  KRR_OPT_PERSIST_WAIT_MS = 5, /* longest time a task of the persistent launch waits for its
+                                  system's earlier stages (default 30000 ms); past it the
+                                  launch gives up and the fit returns KRR_EDEVICE */
+  KRR_OPT_GRAPHS = 6,       /* 1: krr_fit and krr_predict run their device work as HIP graph
+                               replays: the second call with the same shapes, settings,
+                               pointers and stream captures it (the first runs eagerly and
+                               sizes the workspace), later calls replay it; krr_fit's
+                               grouping, status readback and model creation stay outside
+                               the graph, and refinement takes its first steps inside it
+                               (device-side early exit), any further ones outside.  Results
+                               are identical to 0 (default), which launches directly.
+                               Setting the option drops the captured graphs */
+  KRR_OPT_AUTOTUNE = 7      /* 1 (default): every system takes the panel width krr_autotune
+                               recorded for its precision and size class (the default width
+                               where none is recorded); a batch whose systems then differ in
+                               width is factored by the persistent launch; 0: every system
+                               takes KRR_OPT_PANEL_TILES */
 } krr_option;
+
+/* ---- autotuning (Cholesky panel width) ------------------------------------
+ * Times fits of n_sys synthetic, well-conditioned systems of m points in d
+ * dimensions at precision prec (krr_prec) for a set of panel widths (2 .. 64
+ * tiles, at most the system's tile rows), and records the fastest for the
+ * size class of m (tile rows rounded up to a power of two) and prec on the
+ * context; later fits give each system the width of its own class (see
+ * KRR_OPT_AUTOTUNE), so a system's result does not depend on the batch.  If
+ * the environment variable KRR_TUNE_CACHE names a file, the record is
+ * appended to it ("prec class width ms" per line) and contexts created later
+ * read it.  *panel_out (host) receives the width, *ms_out (host, nullable)
+ * the median fit time in ms.  Synchronises `stream`; uses the context's
+ * workspace (n_sys m (d + 2) x 4 bytes of trial data besides the fits'). */
+krr_status krr_autotune(krr_ctx ctx, hipStream_t stream, int32_t prec, int64_t m, int32_t d, int32_t n_sys,
+                        int32_t* panel_out, double* ms_out);
 
 /* ---- context ------------------------------------------------------------
  * krr_create: bind a context to `device` (HIP ordinal).  hbm_budget_bytes
@@ -166,6 +221,9 @@ krr_status  krr_set_option(krr_ctx ctx, int32_t option, int64_t value);
 /* Bytes of device memory currently held by the context (workspace + models +
  * released model blocks kept for reuse by later models of the same size). */
 krr_status  krr_memory_in_use(krr_ctx ctx, size_t* bytes);
+/* Graphs captured and graph replays launched on the context (KRR_OPT_GRAPHS;
+ * host outputs). */
+krr_status  krr_graph_counts(krr_ctx ctx, int64_t* captured, int64_t* replayed);
 /* Timing record of the launches made since timing was enabled or last
  * reported: synchronises the device and writes a NUL-terminated JSON object
  * {"<kernel class>": {"count": launches, "ms": summed event time, "flops":

@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libkrr.so")
-SOURCES = ["api.hip", "csr.hip", "partition.hip", "fit.hip", "cholesky.hip", "solve.hip", "predict.hip", "serve.hip"]
+SOURCES = ["api.hip", "csr.hip", "partition.hip", "fit.hip", "cholesky.hip", "solve.hip", "predict.hip", "serve.hip",
+           "tune.hip"]
 ARCH = os.environ.get("KRR_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

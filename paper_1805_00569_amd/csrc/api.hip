@@ -15,6 +15,7 @@ namespace krr {
 constexpr size_t MODEL_CACHE_BLOCKS = 64;
 
 void drain(krr_ctx ctx) {
+  if (ctx->capturing) fail(KRR_ESTATE, "synchronisation inside a graph capture");
   if (ctx->in_call) KRR_HIP(hipStreamSynchronize(ctx->cur_stream));
   for (auto& m : ctx->marks) KRR_HIP(hipEventSynchronize(m.second));
 }
@@ -64,8 +65,11 @@ void* ws_get(krr_ctx ctx, const std::string& name, size_t bytes) {
   if (bytes == 0) bytes = 256;
   DevBuf& b = ctx->ws[name];
   if (b.bytes >= bytes) return b.ptr;
+  if (ctx->capturing) fail(KRR_ESTATE, "workspace '" + name + "' would grow inside a graph capture");
+  ctx->ws_epoch += 1;
   const size_t old = b.bytes;
   charge(ctx, bytes - old);
+  if (name == "persist_plan") ctx->persist.key.clear();   // the cached plan is gone with the buffer
   if (b.ptr != nullptr) {
     drain(ctx);  // the old buffer may still be in use by this context's queued work
     KRR_HIP(hipFree(b.ptr));
@@ -119,6 +123,15 @@ void model_release(krr_ctx ctx, void* p, size_t bytes) {
   }
 }
 
+void graph_drop_all(krr_ctx ctx) {
+  if (ctx->graph_cache.empty() && ctx->graph_seen.empty()) return;
+  drain(ctx);
+  for (auto& kv : ctx->graph_cache)
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  ctx->graph_cache.clear();
+  ctx->graph_seen.clear();
+}
+
 void ws_release_all(krr_ctx ctx) {
   drain(ctx);
   for (auto& kv : ctx->ws)
@@ -127,6 +140,23 @@ void ws_release_all(krr_ctx ctx) {
       ctx->ws_bytes -= kv.second.bytes;
     }
   ctx->ws.clear();
+  ctx->ws_epoch += 1;
+  ctx->persist.key.clear();   // the uploaded plan lived in the workspace
+}
+
+void* pinned_named(krr_ctx ctx, const std::string& name, size_t bytes) {
+  auto& b = ctx->pinned_bufs[name];
+  if (b.second >= bytes) return b.first;
+  if (b.first != nullptr) {
+    drain(ctx);
+    (void)hipHostFree(b.first);
+    b.first = nullptr;
+    b.second = 0;
+  }
+  bytes = std::max(bytes, size_t(1) << 16);
+  KRR_HIP(hipHostMalloc(&b.first, bytes, hipHostMallocDefault));
+  b.second = bytes;
+  return b.first;
 }
 
 void* pinned_get(krr_ctx ctx, size_t bytes) {
@@ -146,7 +176,7 @@ void* pinned_get(krr_ctx ctx, size_t bytes) {
 void check_launch(krr_ctx ctx, hipStream_t s, const char* what) {
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) fail(KRR_EDEVICE, std::string("launch of ") + what + ": " + hipGetErrorString(e));
-  if (ctx->sync_check) {
+  if (ctx->sync_check && !ctx->capturing) {
     const hipError_t e2 = hipStreamSynchronize(s);
     if (e2 != hipSuccess) fail(KRR_EDEVICE, std::string("after ") + what + ": " + hipGetErrorString(e2));
   }
@@ -165,7 +195,7 @@ static hipEvent_t ev_get(krr_ctx ctx) {
 
 KernelTimer::KernelTimer(krr_ctx c, hipStream_t st, const char* name, double f, int major, double by)
     : ctx(c), s(st), cls(name), flops(f), bytes(by) {
-  if (ctx->timing == 0 || (ctx->timing == 1 && !major) || ctx->noalloc) return;
+  if (ctx->timing == 0 || (ctx->timing == 1 && !major) || ctx->noalloc || ctx->capturing) return;
   a = ev_get(ctx);
   b = ev_get(ctx);
   if (a == nullptr || b == nullptr || hipEventRecord(a, s) != hipSuccess) {
@@ -226,6 +256,8 @@ static krr_status guarded(krr_ctx ctx, F&& f) {
   }
 }
 
+krr_status run_guarded(krr_ctx ctx, const std::function<void()>& f) { return guarded(ctx, f); }
+
 }  // namespace krr
 
 krr_part_data::~krr_part_data() {
@@ -254,6 +286,7 @@ krr_status krr_create(int device, size_t hbm_budget_bytes, krr_ctx* out) {
   if (c == nullptr) return KRR_ENOMEM;
   c->device = device;
   c->budget = hbm_budget_bytes;
+  tune_load(c);
   *out = c;
   return KRR_OK;
 }
@@ -270,6 +303,8 @@ krr_status krr_destroy(krr_ctx ctx) {
   } catch (const Error&) {
     (void)hipDeviceSynchronize();
   }
+  for (auto& kv : ctx->graph_cache)
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
   for (auto& m : ctx->marks) (void)hipEventDestroy(m.second);
   ctx->marks.clear();
   for (auto& kv : ctx->ws)
@@ -281,6 +316,8 @@ krr_status krr_destroy(krr_ctx ctx) {
   }
   for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  for (auto& kv : ctx->pinned_bufs)
+    if (kv.second.first) (void)hipHostFree(kv.second.first);
   delete ctx;
   return KRR_OK;
 }
@@ -299,6 +336,20 @@ krr_status krr_set_option(krr_ctx ctx, int32_t option, int64_t value) {
         break;
       case KRR_OPT_SYNC_CHECK:
         ctx->sync_check = value ? 1 : 0;
+        break;
+      case KRR_OPT_PERSISTENT:
+        ctx->persistent = value ? 1 : 0;
+        break;
+      case KRR_OPT_AUTOTUNE:
+        ctx->autotune = value ? 1 : 0;
+        break;
+      case KRR_OPT_GRAPHS:
+        graph_drop_all(ctx);
+        ctx->graphs = value ? 1 : 0;
+        break;
+      case KRR_OPT_PERSIST_WAIT_MS:
+        KRR_REQUIRE(value >= 0, "the wait limit must be >= 0 ms");
+        ctx->persist_wait_ms = value;
         break;
       case KRR_OPT_TIMING:
         KRR_REQUIRE(value >= 0 && value <= 2, "timing must be 0, 1 or 2");
@@ -334,6 +385,13 @@ krr_status krr_timing_report(krr_ctx ctx, char* buf, size_t cap, size_t* needed)
       ctx->timing_agg.clear();
     }
   });
+}
+
+krr_status krr_graph_counts(krr_ctx ctx, int64_t* captured, int64_t* replayed) {
+  if (ctx == nullptr || captured == nullptr || replayed == nullptr) return KRR_EINVAL;
+  *captured = ctx->graph_captures;
+  *replayed = ctx->graph_replays;
+  return KRR_OK;
 }
 
 krr_status krr_memory_in_use(krr_ctx ctx, size_t* bytes) {

@@ -20,6 +20,7 @@
 // for the mixed-precision trailing updates.  Diagonal blocks are always
 // factored and inverted in FP64.
 #include "common.hpp"
+#include "persist_plan.hpp"
 
 #include <type_traits>
 
@@ -316,7 +317,7 @@ __device__ __forceinline__ void store4(double* p, const double (&v)[4]) {
 // is replaced by z_k = L(k,k)^-1 (that).
 template <typename TS>
 __device__ __forceinline__ void diag_block(const SysDesc& D, int s, SysStatus* __restrict__ st, TS* __restrict__ A,
-                                           TS* __restrict__ Wt, int k, const __bf16* __restrict__ Pk, int K0, int Wp,
+                                           TS* __restrict__ Wt, int k, const __bf16* __restrict__ Pk, int K0, int Wp, int wps,
                                            __bf16* __restrict__ Wpk, double* __restrict__ zf, DiagLds& sh, int t) {
   TS* tile = A + D.a_off + tile_index(k, k) * TILE;
   const int lane = t & 63, w = t >> 6;
@@ -486,7 +487,7 @@ __device__ __forceinline__ void diag_block(const SysDesc& D, int s, SysStatus* _
   if (Wpk != nullptr) {
     // fragment f = 2 cb + ks, part hl (0 high, 1 low): lane l holds Winv(16 cb + (l & 15), 32 ks + 8 (l >> 4) + e)
     // split from its FP32 value: hi = bf16(w), lo = bf16(w - hi)
-    __bf16* base = Wpk + ((int64_t)s * Wp + (k - K0)) * 16 * FRAG;
+    __bf16* base = Wpk + ((int64_t)s * wps + (k - K0)) * 16 * FRAG;
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
       const int task = t + DIAG_THREADS * it;
@@ -520,7 +521,7 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_potrf_diag(const SysDesc* __re
   const int status = st[s].status;
   if (k >= D.T || status != 0 || D.level != level) return;
   __shared__ __align__(16) DiagLds sh;
-  diag_block<TS>(D, s, st, A, Wt, k, Pk, K0, Wp, Wpk, zf, sh, threadIdx.x);
+  diag_block<TS>(D, s, st, A, Wt, k, Pk, K0, Wp, Wp, Wpk, zf, sh, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -573,17 +574,12 @@ __device__ __forceinline__ bool locate(int mode, int bx, int i0, int jc, int T, 
   return i < T;
 }
 
+// One output tile (i, j) of a k_tile_gemm launch (see above), by the 256
+// threads of a workgroup.
 template <typename TS, int MODE>
-__global__ __launch_bounds__(256) void k_tile_gemm(const SysDesc* __restrict__ desc,
-                                                   const SysStatus* __restrict__ st, TS* __restrict__ A,
-                                                   const TS* __restrict__ Wt, int i0, int jc, int q0, int q1,
-                                                   int level) {
+__device__ __forceinline__ void tile_gemm_body(const SysDesc& D, TS* __restrict__ A, const TS* __restrict__ Wt,
+                                               int i, int j, int jc, int q0, int q1) {
   typedef typename AccT<TS>::type acc_t;
-  const int s = blockIdx.y;
-  const SysDesc D = desc[s];
-  if (st[s].status != 0 || D.level != level) return;
-  int i, j;
-  if (!locate(MODE, blockIdx.x, i0, jc, D.T, i, j)) return;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int r0 = 32 * (w & 1);
@@ -643,6 +639,19 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const SysDesc* __restrict__ d
         else
           C[e] = (TS)(C[e] - acc[cb][rb][v]);
       }
+}
+
+template <typename TS, int MODE>
+__global__ __launch_bounds__(256) void k_tile_gemm(const SysDesc* __restrict__ desc,
+                                                   const SysStatus* __restrict__ st, TS* __restrict__ A,
+                                                   const TS* __restrict__ Wt, int i0, int jc, int q0, int q1,
+                                                   int level) {
+  const int s = blockIdx.y;
+  const SysDesc D = desc[s];
+  if (st[s].status != 0 || D.level != level) return;
+  int i, j;
+  if (!locate(MODE, blockIdx.x, i0, jc, D.T, i, j)) return;
+  tile_gemm_body<TS, MODE>(D, A, Wt, i, j, jc, q0, q1);
 }
 
 // ---------------------------------------------------------------------------
@@ -754,11 +763,12 @@ constexpr int NXCD = 8;
 
 __device__ __forceinline__ void panel_col_tile(const SysDesc& D, int s, int i, int lane, float* __restrict__ A,
                                                const __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk, int K0, int k,
-                                               int Wp, int do_pack, double* __restrict__ zf, float* __restrict__ sc) {
+                                               int Wp, int wps, int do_pack, double* __restrict__ zf,
+                                               float* __restrict__ sc) {
   const int KSW = 2 * Wp;
   const int il = lane & 15, kg = lane >> 4;
   // Winv(k) fragments first: their latency overlaps the column update
-  const __bf16* Wf = Wpk + ((int64_t)s * Wp + (k - K0)) * 16 * FRAG + lane * 8;
+  const __bf16* Wf = Wpk + ((int64_t)s * wps + (k - K0)) * 16 * FRAG + lane * 8;
   bf8 whi[4][2], wlo[4][2];
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
@@ -883,6 +893,27 @@ __device__ __forceinline__ void panel_col_tile(const SysDesc& D, int s, int i, i
     }
 }
 
+union PcolLds {
+  float sC[4][NB * PC_LD];   // per wave: the tile being solved
+  DiagLds dg;
+};
+
+// Tile-row group g of column k (rows k + 1 + 4 g + w, one per wave w), then
+// for diag_next and g = 0 the diagonal block k + 1 (see k_panel_col).
+__device__ __forceinline__ void pcol_body(const SysDesc& D, int s, SysStatus* __restrict__ st, float* __restrict__ A,
+                                          float* __restrict__ Wt, __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk,
+                                          int K0, int k, int Wp, int wps, int do_pack, int diag_next, int g,
+                                          double* __restrict__ zf, PcolLds& lds) {
+  // wave-uniform wave index: the tile bases stay in scalar registers
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int i = k + 1 + 4 * g + w;
+  if (i < D.T) panel_col_tile(D, s, i, lane, A, Wpk, Pk, K0, k, Wp, wps, do_pack, zf, lds.sC[w]);
+  if (diag_next && g == 0 && k + 1 < D.T) {
+    __syncthreads();   // tile row k + 1 (factor and pack) complete; LDS free
+    diag_block<float>(D, s, st, A, Wt, k + 1, Pk, K0, Wp, wps, Wpk, zf, lds.dg, threadIdx.x);
+  }
+}
+
 // diag_next: the first workgroup of each system (tile rows k+1 .. k+4,
 // dispatched before the other workgroups) then factors diagonal block k + 1
 // with its column update over the panel columns [K0, k] (diag_block), which
@@ -916,18 +947,8 @@ __global__ __launch_bounds__(256) void k_panel_col(const SysDesc* __restrict__ d
   }
   const SysDesc D = desc[s];
   if (st[s].status != 0 || D.level != level) return;
-  // wave-uniform wave index: the tile bases stay in scalar registers
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int i = k + 1 + 4 * g + w;
-  __shared__ __align__(16) union {
-    float sC[4][NB * PC_LD];   // per wave: the tile being solved
-    DiagLds dg;
-  } lds;
-  if (i < D.T) panel_col_tile(D, s, i, lane, A, Wpk, Pk, K0, k, Wp, do_pack, zf, lds.sC[w]);
-  if (diag_next && g == 0 && k + 1 < D.T) {
-    __syncthreads();   // tile row k + 1 (factor and pack) complete; LDS free
-    diag_block<float>(D, s, st, A, Wt, k + 1, Pk, K0, Wp, Wpk, zf, lds.dg, threadIdx.x);
-  }
+  __shared__ __align__(16) PcolLds lds;
+  pcol_body(D, s, st, A, Wt, Wpk, Pk, K0, k, Wp, Wp, do_pack, diag_next, g, zf, lds);
 }
 
 // Super-tile order of the trailing update: bands of TRAIL_BAND super-rows,
@@ -975,6 +996,9 @@ __device__ __forceinline__ bool trail_decode(int bx, int NS, int& I, int& J) {
 // fetched from L2 once per workgroup instead of once per wave.  The step
 // count 2 (K1 - K0) is a multiple of TR_RD.
 constexpr int TR_RD = 2;
+__device__ __forceinline__ void trail_body(const SysDesc& D, int bxs, float* __restrict__ A,
+                                           const __bf16* __restrict__ Pk, int K0, int ks0, int ks1, int i0, int Wp,
+                                           bf8 (&sF)[2][16][64]);
 __global__ __launch_bounds__(256, 2) void k_packed_trailing(const SysDesc* __restrict__ desc,
                                                          const SysStatus* __restrict__ st, float* __restrict__ A,
                                                          const __bf16* __restrict__ Pk, int K0, int ks0, int ks1,
@@ -993,6 +1017,15 @@ __global__ __launch_bounds__(256, 2) void k_packed_trailing(const SysDesc* __res
   }
   const SysDesc D = desc[s];
   if (st[s].status != 0 || D.level != level) return;
+  __shared__ __align__(16) bf8 sF[2][16][64];   // [stage][4 * row set + row block][lane]
+  trail_body(D, bxs, A, Pk, K0, ks0, ks1, i0, Wp, sF);
+}
+
+// Super-tile bxs (banded order) of the packed trailing update of system D
+// (see k_packed_trailing), by the 256 threads of a workgroup.
+__device__ __forceinline__ void trail_body(const SysDesc& D, int bxs, float* __restrict__ A,
+                                           const __bf16* __restrict__ Pk, int K0, int ks0, int ks1, int i0, int Wp,
+                                           bf8 (&sF)[2][16][64]) {
   const int T = D.T;
   const int R = T - i0;
   if (R <= 0) return;
@@ -1005,7 +1038,6 @@ __global__ __launch_bounds__(256, 2) void k_packed_trailing(const SysDesc* __res
   const int ib = i0 + 2 * I, jb = i0 + 2 * J;
   const int i = ib + (w & 1), j = jb + (w >> 1);
   const bool act = i < T && j <= i;
-  __shared__ __align__(16) bf8 sF[2][16][64];   // [stage][4 * row set + row block][lane]
   // C tile (clamped to a valid tile for the idle waves, which store nothing)
   const int ic = min(i, T - 1);
   float* C = A + D.a_off + tile_index(ic, min(j, ic)) * TILE;
@@ -1079,6 +1111,180 @@ __global__ __launch_bounds__(256, 2) void k_packed_trailing(const SysDesc* __res
   }
 }
 
+// ---------------------------------------------------------------------------
+// Persistent factorisation: one launch runs every stage of every system of
+// the batch from the device queues of a PPlan (persist_plan.hpp).  The grid
+// holds as many workgroups as the device keeps resident; workgroup b works
+// from queue b % nq first (the queue of its XCD) and then from the others.
+// A task waits (one lane polling, with sleeps) until its system has finished
+// `need` tasks, runs the same body as the corresponding workgroup of the
+// multi-launch sequence -- so the results are identical bit for bit -- and
+// then counts itself done (every wave's stores released at agent scope
+// before the count, the waiter acquiring after it).  Every wait is bounded:
+// past `wait_ticks` of the device's constant-rate clock, or once another
+// workgroup has given up, the workgroup sets the give-up flag and leaves;
+// the caller then marks the systems failed.  A system that turns out not
+// positive definite is skipped by its later tasks, which still count.
+// ctr: [0, nq) queue heads, [nq, nq + n_sys) tasks done per system,
+// [nq + n_sys] the give-up flag; all zero at launch.
+// ---------------------------------------------------------------------------
+union PersistLds {
+  PcolLds pc;
+  bf8 sF[2][16][64];
+};
+
+// The task bodies as separate (not inlined) functions: each is register-
+// allocated on its own, like the kernel of the multi-launch sequence it comes
+// from, instead of the persistent kernel holding the union of their register
+// needs.  The workgroup's LDS arrives as an LDS-space pointer, so the bodies
+// keep their LDS instructions.
+typedef __attribute__((address_space(3))) PersistLds* lds_ptr;
+
+__device__ __noinline__ void persist_diag_packed(const SysDesc* __restrict__ desc, int s, SysStatus* __restrict__ st,
+                                                 float* __restrict__ A, float* __restrict__ Wt, int k, int K0,
+                                                 __bf16* __restrict__ Pk, int wps, __bf16* __restrict__ Wpk,
+                                                 double* __restrict__ zf, lds_ptr lp) {
+  PersistLds& lds = *(PersistLds*)lp;
+  const SysDesc D = desc[s];
+  diag_block<float>(D, s, st, A, Wt, k, Pk, K0, D.wp, wps, Wpk, zf, lds.pc.dg, threadIdx.x);
+}
+
+__device__ __noinline__ void persist_pcol(const SysDesc* __restrict__ desc, int s, SysStatus* __restrict__ st,
+                                          float* __restrict__ A, float* __restrict__ Wt, __bf16* __restrict__ Wpk,
+                                          __bf16* __restrict__ Pk, int K0, int k, int wps, int do_pack, int diag_next,
+                                          int g, double* __restrict__ zf, lds_ptr lp) {
+  PersistLds& lds = *(PersistLds*)lp;
+  const SysDesc D = desc[s];
+  pcol_body(D, s, st, A, Wt, Wpk, Pk, K0, k, D.wp, wps, do_pack, diag_next, g, zf, lds.pc);
+}
+
+__device__ __noinline__ void persist_trail(const SysDesc* __restrict__ desc, int s, float* __restrict__ A,
+                                           const __bf16* __restrict__ Pk, int K0, int K1, int b, lds_ptr lp) {
+  PersistLds& lds = *(PersistLds*)lp;
+  const SysDesc D = desc[s];
+  trail_body(D, b, A, Pk, K0, 0, 2 * (K1 - K0), K1, D.wp, lds.sF);
+}
+
+template <typename TS>
+__device__ __noinline__ void persist_diag(const SysDesc* __restrict__ desc, int s, SysStatus* __restrict__ st,
+                                          TS* __restrict__ A, TS* __restrict__ Wt, int k, lds_ptr lp) {
+  PersistLds& lds = *(PersistLds*)lp;
+  const SysDesc D = desc[s];
+  diag_block<TS>(D, s, st, A, Wt, k, (const __bf16*)nullptr, 0, 1, 1, (__bf16*)nullptr, (double*)nullptr, lds.pc.dg,
+                 threadIdx.x);
+}
+
+template <typename TS, int MODE>
+__device__ __noinline__ void persist_tile(const SysDesc* __restrict__ desc, int s, TS* __restrict__ A,
+                                          const TS* __restrict__ Wt, int i, int j, int jc, int q0, int q1) {
+  const SysDesc D = desc[s];
+  tile_gemm_body<TS, MODE>(D, A, Wt, i, j, jc, q0, q1);
+}
+
+__device__ __forceinline__ int ld_agent(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename TS, bool PACKED>
+__global__ __launch_bounds__(256, 2) void k_chol_persist(const SysDesc* __restrict__ desc, SysStatus* __restrict__ st,
+                                                      TS* __restrict__ A, TS* __restrict__ Wt,
+                                                      __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk, int wps,
+                                                      double* __restrict__ zf, const PTask* __restrict__ tasks,
+                                                      const int32_t* __restrict__ qoff, int nq,
+                                                      int32_t* __restrict__ ctr, int n_sys, long long wait_ticks) {
+  __shared__ __align__(16) PersistLds lds;
+  __shared__ int s_task, s_go;
+  int32_t* done = ctr + nq;
+  int32_t* giveup = ctr + nq + n_sys;
+  const int t = threadIdx.x;
+  const int home = (int)(blockIdx.x % (unsigned)nq);
+  unsigned exhausted = 0;   // thread 0: queues found empty
+  for (;;) {
+    if (t == 0) {
+      int task = -1;
+      if (!ld_agent(giveup)) {
+        for (int u = 0; u < nq && task < 0; ++u) {
+          const int q = (home + u) % nq;
+          if (exhausted & (1u << q)) continue;
+          const int x = __hip_atomic_fetch_add(&ctr[q], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (x < qoff[q + 1] - qoff[q]) task = qoff[q] + x;
+          else exhausted |= 1u << q;
+        }
+      }
+      int go = 0;
+      if (task >= 0) {
+        const PTask T = tasks[task];
+        int v = ld_agent(done + T.s);
+        if (v >= T.need) {
+          go = 1;
+        } else {
+          const long long t0 = wall_clock64();
+          for (;;) {
+            __builtin_amdgcn_s_sleep(2);
+            v = ld_agent(done + T.s);
+            if (v >= T.need) {
+              go = 1;
+              break;
+            }
+            if (ld_agent(giveup) || wall_clock64() - t0 > wait_ticks) {
+              __hip_atomic_store(giveup, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              break;
+            }
+          }
+        }
+        if (go) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          // a system found not positive definite: its later tasks only count
+          if (ld_agent(&st[T.s].status) != 0) go = 2;
+        }
+      }
+      s_task = task;
+      s_go = go;
+    }
+    __syncthreads();
+    const int task = s_task, go = s_go;
+    if (task < 0 || go == 0) break;
+    const PTask T = tasks[task];
+    if (go == 1) {
+      const lds_ptr lp = (lds_ptr)&lds;
+      if constexpr (PACKED) {
+        if (T.kind == PT_DIAG)
+          persist_diag_packed(desc, T.s, st, (float*)A, (float*)Wt, T.a, T.b, Pk, wps, Wpk, zf, lp);
+        else if (T.kind == PT_PCOL)
+          persist_pcol(desc, T.s, st, (float*)A, (float*)Wt, Wpk, Pk, T.c, T.a, wps, T.flags & PF_PACK,
+                       (T.flags & PF_DIAG_NEXT) ? 1 : 0, T.b, zf, lp);
+        else if (T.kind == PT_PTRAIL)
+          persist_trail(desc, T.s, (float*)A, Pk, T.a, T.c, T.b, lp);
+      } else {
+        if (T.kind == PT_DIAG) {
+          persist_diag<TS>(desc, T.s, st, A, Wt, T.a, lp);
+        } else if (T.kind == PT_COL) {
+          persist_tile<TS, MODE_COL>(desc, T.s, A, Wt, T.a, T.b, T.b, T.c, T.b);
+        } else if (T.kind == PT_TRSM) {
+          persist_tile<TS, MODE_TRSM>(desc, T.s, A, Wt, T.a, T.b, T.b, 0, 1);
+        } else if (T.kind == PT_TRI) {
+          int ii = (int)((sqrt(8.0 * (double)T.a + 1.0) - 1.0) * 0.5);
+          while ((int64_t)ii * (ii + 1) / 2 > T.a) --ii;
+          while ((int64_t)(ii + 1) * (ii + 2) / 2 <= T.a) ++ii;
+          const int jj = T.a - ii * (ii + 1) / 2;
+          persist_tile<TS, MODE_TRI>(desc, T.s, A, Wt, T.c + ii, T.c + jj, 0, T.b, T.c);
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // this wave's stores, before the count
+    __syncthreads();
+    if (t == 0) __hip_atomic_fetch_add(done + T.s, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// After a persistent launch: if a workgroup gave up waiting, every system
+// factored in this pass is marked failed (KRR_EDEVICE).
+__global__ void k_persist_check(const int32_t* __restrict__ giveup, const SysDesc* __restrict__ desc,
+                                SysStatus* __restrict__ st, int n_sys, int level) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n_sys && *giveup && desc[s].level == level) st[s].status = KRR_EDEVICE;
+}
+
 template <typename TS>
 void launch_update(krr_ctx ctx, hipStream_t s, bool bf16, int mode, const SysDesc* desc, SysStatus* st, TS* A,
                    const TS* Wt, int n_sys, int64_t nblk, int i0, int jc, int q0, int q1, int level) {
@@ -1104,6 +1310,97 @@ void launch_update(krr_ctx ctx, hipStream_t s, bool bf16, int mode, const SysDes
   check_launch(ctx, s, "tile_gemm");
 }
 
+__global__ void k_zero_ctr(int32_t* a, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0;
+}
+
+// Resident workgroups of the persistent kernel on the context's device.
+template <typename TS, bool PACKED>
+int persist_grid(krr_ctx ctx) {
+  int per_cu = 0, cus = 0;
+  KRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_chol_persist<TS, PACKED>, 256, 0));
+  KRR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+  return std::max(1, per_cu) * std::max(1, cus);
+}
+
+// Uploads the PPlan of these shapes unless it is the one on the device.
+void persist_upload(krr_ctx ctx, hipStream_t s, const std::vector<int>& T, const std::vector<int>& act,
+                    const std::vector<int>& Wp, bool packed, int tsize) {
+  std::vector<int> key = T;
+  key.insert(key.end(), act.begin(), act.end());
+  key.insert(key.end(), Wp.begin(), Wp.end());
+  key.push_back(packed ? 1 : 0);
+  key.push_back(tsize);
+  auto& pc = ctx->persist;
+  if (pc.key == key) return;
+  if (!pc.key.empty()) drain(ctx);   // an earlier upload may still read the staging buffer
+  const PPlan P = build_plan(T, act, Wp, packed, NXCD);
+  pc.nq = P.nq;
+  pc.ntasks = (int)P.tasks.size();
+  const size_t tb = P.tasks.size() * sizeof(PTask), qb = P.qoff.size() * sizeof(int32_t);
+  char* dev = (char*)ws_get(ctx, "persist_plan", std::max<size_t>(tb + qb + 256, 512));
+  void* h = pinned_named(ctx, "persist_plan", tb + qb + 256);
+  std::memcpy(h, P.tasks.data(), tb);
+  std::memcpy((char*)h + tb, P.qoff.data(), qb);
+  KRR_HIP(hipMemcpyAsync(dev, h, tb + qb, hipMemcpyHostToDevice, s));
+  pc.tasks = dev;
+  pc.qoff_off = tb;
+  pc.key = key;
+  pc.T = T;
+  pc.act = act;
+  pc.wp = Wp;
+  pc.packed = packed ? 1 : 0;
+  pc.tsize = tsize;
+}
+
+// The persistent factorisation of the systems at `level` (the PPlan is kept
+// on the context and rebuilt only when the shapes change).
+// Wp: panel width of the matrix-core path; the packed path takes each
+// system's own width (SysDesc::wp), with wps the stride of the inverse
+// diagonal fragments (Wpk) per system.
+template <typename TS>
+void factor_persistent(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, int n_sys, TS* A, TS* Wt,
+                       bool packed, int Wp, int wps, int level, const SysDesc* hdesc, __bf16* Pk, __bf16* Wpk,
+                       double* zf, double flops, double bytes, const char* cls) {
+  std::vector<int> T(n_sys), act(n_sys), wp(n_sys);
+  for (int i = 0; i < n_sys; ++i) {
+    T[i] = hdesc[i].T;
+    act[i] = hdesc[i].level == level ? 1 : 0;
+    wp[i] = hdesc[i].wp;
+  }
+  persist_upload(ctx, s, T, act, wp, packed, (int)sizeof(TS));
+  auto& pc = ctx->persist;
+  if (ctx->capturing) pc.in_capture = 1;
+  if (pc.ntasks == 0) return;
+  int32_t* ctr = (int32_t*)ws_get(ctx, "persist_ctr", (size_t)(pc.nq + n_sys + 1) * 4);
+  const int nctr = pc.nq + n_sys + 1;
+  hipLaunchKernelGGL(k_zero_ctr, dim3((unsigned)ceil_div(nctr, 256)), dim3(256), 0, s, ctr, nctr);
+  check_launch(ctx, s, "zero_ctr");
+  int khz = 0;
+  KRR_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device));
+  const long long ticks = (long long)std::max(1, khz) * (long long)std::max<int64_t>(ctx->persist_wait_ms, 0);
+  const PTask* tasks = (const PTask*)pc.tasks;
+  const int32_t* qoff = (const int32_t*)((const char*)pc.tasks + pc.qoff_off);
+  {
+    KernelTimer kt(ctx, s, cls, flops, 1, bytes);
+    if (packed) {
+      const int grid = std::min(persist_grid<float, true>(ctx), (int)ceil_div(pc.ntasks, NXCD) * NXCD);
+      hipLaunchKernelGGL((k_chol_persist<float, true>), dim3((unsigned)grid), dim3(256), 0, s, desc, st, (float*)A,
+                         (float*)Wt, Wpk, Pk, wps, zf, tasks, qoff, pc.nq, ctr, n_sys, ticks);
+    } else {
+      const int grid = std::min(persist_grid<TS, false>(ctx), (int)ceil_div(pc.ntasks, NXCD) * NXCD);
+      hipLaunchKernelGGL((k_chol_persist<TS, false>), dim3((unsigned)grid), dim3(256), 0, s, desc, st, A, Wt,
+                         (__bf16*)nullptr, (__bf16*)nullptr, Wp, (double*)nullptr, tasks, qoff, pc.nq, ctr, n_sys,
+                         ticks);
+    }
+    check_launch(ctx, s, "chol_persist");
+  }
+  hipLaunchKernelGGL(k_persist_check, dim3((unsigned)ceil_div(n_sys, 128)), dim3(128), 0, s,
+                     (const int32_t*)(ctr + pc.nq + n_sys), desc, st, n_sys, level);
+  check_launch(ctx, s, "persist_check");
+}
+
 template <typename TS>
 void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, int n_sys, int Tmax, TS* A, TS* Wt,
               bool bf16, int Wp, int level, const SysDesc* hdesc, __bf16* Pk, double* zf) {
@@ -1120,6 +1417,49 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
   const char* col_name = bf16 ? "chol_column_bf16" : (f64 ? "chol_column_f64" : "chol_column_f32");
   const char* trsm_name = f64 ? "chol_trsm_f64" : "chol_trsm_f32";
   const bool packed = std::is_same<TS, float>::value && bf16 && Pk != nullptr;
+  // tasks of the persistent plan: a plan of more than PERSIST_MAX_TASKS (one
+  // system of tens of thousands of rows, say) is not built; its stages run as
+  // launches (the same bodies, the same results), which for so large a
+  // system keep the device as busy
+  constexpr int64_t PERSIST_MAX_TASKS = int64_t(1) << 23;
+  auto plan_tasks = [&]() {
+    int64_t tot = 0;
+    for (int i = 0; i < n_sys && hdesc != nullptr; ++i) {
+      if (hdesc[i].level != level) continue;
+      const int64_t T = hdesc[i].T, w = std::max(1, hdesc[i].wp);
+      for (int64_t K0 = 0; K0 < T; K0 += w) {
+        const int64_t K1 = std::min(K0 + w, T), R = T - K1;
+        if (packed) {
+          tot += 1 + (K1 - K0) * ((T - K0) / 4 + 1);
+          tot += ((R + 1) / 2) * ((R + 1) / 2 + 1) / 2;
+        } else {
+          tot += (K1 - K0) * (2 * (T - K0) + 1) + R * (R + 1) / 2;
+        }
+      }
+    }
+    return tot;
+  };
+  // the launch sequence takes one width for the whole batch: the systems' own
+  // when they share it
+  int uniform = -1;
+  for (int i = 0; i < n_sys && hdesc != nullptr; ++i) {
+    if (hdesc[i].level != level) continue;
+    if (uniform < 0) uniform = hdesc[i].wp;
+    else if (uniform != hdesc[i].wp) uniform = 0;
+  }
+  if (hdesc != nullptr && (packed || !bf16) &&
+      ((ctx->persistent && plan_tasks() <= PERSIST_MAX_TASKS) || uniform == 0)) {
+    // one launch: m^3/3 per system credited; bytes: read and write the lower triangle once
+    const double fl = each([](double m) { return m * m * m / 3.0; });
+    const double by = each([](double m) { return m * (m + 1.0) * sizeof(TS); });
+    const char* cls = packed ? "chol_persist_bf16" : (f64 ? "chol_persist_f64" : "chol_persist_f32");
+    int wps = 1;
+    for (int i = 0; i < n_sys; ++i) wps = std::max(wps, hdesc[i].wp);
+    __bf16* Wpk = packed ? (__bf16*)ws_get(ctx, "chol_wpk", (size_t)n_sys * wps * 16 * FRAG * sizeof(__bf16)) : nullptr;
+    factor_persistent<TS>(ctx, s, desc, st, n_sys, A, Wt, packed, Wp, wps, level, hdesc, Pk, Wpk, zf, fl, by, cls);
+    return;
+  }
+  if (uniform > 0) Wp = uniform;
   auto diag_trsm = [&](int k) {
     {
       KernelTimer kt(ctx, s, "chol_diag", each([&](double m) {
@@ -1229,6 +1569,25 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
 
 }  // namespace
 
+void persist_note_plan(krr_ctx ctx, krr_ctx_s::GraphEntry& e) {
+  auto& pc = ctx->persist;
+  if (!pc.in_capture) return;
+  pc.in_capture = 0;
+  e.plan_key = pc.key;
+  e.plan_T = pc.T;
+  e.plan_act = pc.act;
+  e.plan_wp = pc.wp;
+  e.plan_packed = pc.packed;
+  e.plan_tsize = pc.tsize;
+}
+
+void persist_restore_plan(krr_ctx ctx, hipStream_t s, const krr_ctx_s::GraphEntry& e) {
+  if (e.plan_key.empty() || ctx->persist.key == e.plan_key) return;
+  persist_upload(ctx, s, e.plan_T, e.plan_act, e.plan_wp, e.plan_packed != 0, e.plan_tsize);
+  if (ctx->persist.tasks == nullptr || ctx->persist.key != e.plan_key)
+    fail(KRR_ESTATE, "the persistent plan of a captured graph could not be restored");
+}
+
 // Factor, in place, the systems of the batch whose descriptor carries
 // `level` (the others are left untouched).  prec: KRR_PREC_FP64 -> A, Wt are
 // double; FP32 / MIXED -> float.  bf16: BF16 trailing and column updates
@@ -1241,7 +1600,7 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
 // otherwise they are left untouched and the call returns false.
 bool cholesky_factor(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, SysStatus* st, int n_sys, int Tmax,
                      void* A, void* Wt, int level, bool bf16, const SysDesc* hdesc, void* pack, double* zfwd) {
-  const int Wp = ctx->panel_tiles;
+  const int Wp = ctx->force_wp > 0 ? ctx->force_wp : ctx->panel_tiles;   // the multi-launch path's width
   if (prec == KRR_PREC_FP64) {
     factor_t<double>(ctx, s, desc, st, n_sys, Tmax, (double*)A, (double*)Wt, false, Wp, level, hdesc, nullptr, nullptr);
     return false;

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -77,7 +78,7 @@ struct SysDesc {
   int32_t level;       // precision level that factors this system in the current pass
   double ka, kr;       // polynomial / sigmoid: a and r of Table 1
   int32_t kdeg;        // polynomial degree
-  int32_t pad_;
+  int32_t wp;          // Cholesky panel width of this system (64-wide tiles)
   int64_t pk_off;      // element offset of its BF16 panel-pack slot (mixed precision)
   int64_t k_off;       // mixed precision: element offset of the FP64 kernel tiles (without the
                        // shift) shared by the settings of this partition with the same kernel and sigma
@@ -90,10 +91,16 @@ struct SysStatus {
   int32_t refine_iters;
   int32_t converged;     // refinement reached the tolerance
   int32_t stalled;       // refinement stopped reducing the residual
-  int32_t pad_;
+  int32_t corr;          // corrections applied with the factor in use
   double rel_residual;
   double prev_rel;
   double ynorm;
+  double kappa_l;        // (max_i L_ii / min_i L_ii)^2 of the factor in use: a lower bound of kappa_2(A)
+  double kappa_u;        // an upper bound of kappa_2 of the FP64 system (Gershgorin; -1: not formed)
+  double dnorm;          // ||delta||_inf of the last correction (-1: none yet)
+  double prev_dnorm;     // ||delta||_inf of the one before (-1: none)
+  double anorm;          // ||alpha||_inf after the last correction
+  double err_est;        // estimated relative forward error of alpha (inf-norm; -1: not estimated)
 };
 
 }  // namespace krr
@@ -161,6 +168,36 @@ struct krr_ctx_s {
   // per stream the context has queued work on: an event recorded after that
   // work (see drain)
   std::vector<std::pair<hipStream_t, hipEvent_t>> marks;
+  int persistent = 0;            // factor with the persistent launch (KRR_OPT_PERSISTENT)
+  int autotune = 1;              // give systems the tuned panel width of their size class
+  int force_wp = 0;              // > 0: every system takes this panel width (trial fits)
+  std::map<std::pair<int, int>, int> tune;   // (precision, size class) -> panel width
+  int64_t persist_wait_ms = 30000;   // longest wait of one task before it gives up
+  struct PersistCache {
+    std::vector<int> key;       // shapes the uploaded plan was built for
+    void* tasks = nullptr;      // device: tasks, then the queue offsets
+    size_t qoff_off = 0;
+    int nq = 1, ntasks = 0;
+    std::vector<int> T, act, wp;   // the plan's inputs (to upload it again for a graph replay)
+    int packed = 0, tsize = 0;
+    int in_capture = 0;         // a persistent launch was recorded by the capture in progress
+  } persist;
+  std::map<std::string, std::pair<void*, size_t>> pinned_bufs;   // named pinned staging
+  // HIP graphs of the device phases of fits and predictions (KRR_OPT_GRAPHS):
+  // a call whose key (shapes, settings, pointers, workspace epoch) was seen
+  // once eagerly is captured on its next occurrence and replayed afterwards
+  int graphs = 0;
+  int capturing = 0;            // inside a stream capture: no synchronisation, no allocation
+  uint64_t ws_epoch = 0;        // bumped whenever a workspace buffer moves
+  struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    std::vector<int> plan_key;  // persistent plan the graph's launch reads
+    std::vector<int> plan_T, plan_act, plan_wp;
+    int plan_packed = 0, plan_tsize = 0;
+  };
+  std::map<std::string, GraphEntry> graph_cache;
+  int64_t graph_captures = 0, graph_replays = 0;
+  std::map<std::string, int> graph_seen;
   std::vector<hipEvent_t> ev_pool;
   std::vector<krr_timed_launch> pending;
   std::map<std::string, krr_timing_agg> timing_agg;
@@ -175,8 +212,32 @@ void* ws_get(krr_ctx ctx, const std::string& name, size_t bytes);
 void* model_alloc(krr_ctx ctx, size_t bytes);
 void model_release(krr_ctx ctx, void* p, size_t bytes);
 void* pinned_get(krr_ctx ctx, size_t bytes);
+// Pinned host staging buffer `name`, grown (never shrunk); contents are not
+// preserved across growth.
+void* pinned_named(krr_ctx ctx, const std::string& name, size_t bytes);
+// Runs f with the device of ctx current, translating errors into a status
+// (and ctx->last_error), as every entry point does.
+krr_status run_guarded(krr_ctx ctx, const std::function<void()>& f);
+// Panel width for a system of m points at precision prec: the tuned one of
+// its size class when tuning applies, else the context's default.
+int tuned_panel(krr_ctx ctx, int prec, int64_t m);
+void tune_load(krr_ctx ctx);
 // Frees every workspace buffer of the context (after drain).
 void ws_release_all(krr_ctx ctx);
+// Runs `body` (device work on stream s only, no synchronisation, no
+// allocation) eagerly, or as a replay of its HIP graph: with graphs on, the
+// second call with the same key captures it, later calls replay it.  The key
+// must name everything the device work depends on except the contents of
+// device memory; the workspace epoch is added here.  Returns true if a graph
+// was launched.
+template <typename F>
+bool graph_run(krr_ctx ctx, hipStream_t s, const std::string& key, F&& body);
+void graph_drop_all(krr_ctx ctx);
+// Byte-string key helper.
+template <typename T>
+inline void key_add(std::string& k, const T& v) {
+  k.append(reinterpret_cast<const char*>(&v), sizeof(T));
+}
 // Waits until the work this context has queued is done: the current call's
 // stream and the last recorded work on every other stream it has used.  Work
 // of other contexts is not waited for.
@@ -251,6 +312,58 @@ inline size_t al256(size_t b) { return b == 0 ? 256 : (b + 255) & ~size_t(255); 
 // workspace buffer `name`.
 inline void* ws_or_arena(krr_ctx ctx, Arena* ar, const std::string& name, size_t bytes) {
   return ar != nullptr ? ar->take(bytes) : ws_get(ctx, name, bytes);
+}
+
+// Persistent-plan bookkeeping for graphs: the plan a captured launch reads
+// must be the one on the device when the graph is replayed.
+void persist_note_plan(krr_ctx ctx, krr_ctx_s::GraphEntry& e);
+void persist_restore_plan(krr_ctx ctx, hipStream_t s, const krr_ctx_s::GraphEntry& e);
+
+template <typename F>
+bool graph_run(krr_ctx ctx, hipStream_t s, const std::string& key0, F&& body) {
+  if (!ctx->graphs) {
+    body();
+    return false;
+  }
+  std::string key = key0;
+  key_add(key, ctx->ws_epoch);
+  key_add(key, s);
+  auto it = ctx->graph_cache.find(key);
+  if (it != ctx->graph_cache.end()) {
+    persist_restore_plan(ctx, s, it->second);
+    KRR_HIP(hipGraphLaunch(it->second.exec, s));
+    ctx->graph_replays += 1;
+    return true;
+  }
+  if (ctx->graph_seen[key] == 0) {   // first time: eager (it sizes the workspace)
+    ctx->graph_seen[key] = 1;
+    body();
+    return false;
+  }
+  krr_ctx_s::GraphEntry e;
+  hipGraph_t g = nullptr;
+  KRR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  ctx->capturing = 1;
+  try {
+    body();
+  } catch (...) {
+    ctx->capturing = 0;
+    hipGraph_t junk = nullptr;
+    (void)hipStreamEndCapture(s, &junk);
+    if (junk) (void)hipGraphDestroy(junk);
+    throw;
+  }
+  ctx->capturing = 0;
+  KRR_HIP(hipStreamEndCapture(s, &g));
+  const hipError_t ie = hipGraphInstantiate(&e.exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) fail(KRR_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+  persist_note_plan(ctx, e);
+  auto& slot = ctx->graph_cache[key];
+  slot = e;
+  KRR_HIP(hipGraphLaunch(slot.exec, s));
+  ctx->graph_captures += 1;
+  return true;
 }
 
 // ---- fit.hip ----

@@ -20,10 +20,15 @@ void trsv_forward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, con
 void trsv_backward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, const SysStatus* st, int n_sys,
                    int Tmax, int64_t v_tot, const void* A, const void* Wt, const double* z, double* x,
                    double* alpha_acc, int skip_converged);
+void pivot_range(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, SysStatus* st, int n_sys, const void* A,
+                 int level);
+void correction_norms(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, int n_sys, const double* delta,
+                      const double* alpha);
 void residual_check(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, int n_sys, int p, int n_groups,
                     const int32_t* grp_first, const int32_t* grp_next, int Tmax, const double* K64,
                     const double* alpha, const double* y, double* r, double* P, const int64_t* p_off, double* rn,
-                    double* yn, const int64_t* n_off, double tol, int will_refine, int32_t* active);
+                    double* yn, const int64_t* n_off, double tol, int will_refine, int32_t* active, double* Pabs,
+                    double* glo, double* ghi);
 
 namespace {
 
@@ -197,10 +202,16 @@ __global__ void k_zero_status(SysStatus* st, int n) {
     st[s].refine_iters = 0;
     st[s].converged = 0;
     st[s].stalled = 0;
-    st[s].pad_ = 0;
+    st[s].corr = 0;
     st[s].rel_residual = -1.0;
     st[s].prev_rel = -1.0;
     st[s].ynorm = 0.0;
+    st[s].kappa_l = 1.0;
+    st[s].kappa_u = -1.0;
+    st[s].dnorm = -1.0;
+    st[s].prev_dnorm = -1.0;
+    st[s].anorm = 0.0;
+    st[s].err_est = -1.0;
   }
 }
 
@@ -216,6 +227,11 @@ __global__ void k_reset_level(const SysDesc* __restrict__ desc, SysStatus* __res
     st[s].converged = 0;
     st[s].stalled = 0;
     st[s].prev_rel = -1.0;
+    st[s].corr = 0;
+    st[s].kappa_l = 1.0;
+    st[s].dnorm = -1.0;
+    st[s].prev_dnorm = -1.0;
+    st[s].err_est = -1.0;
   }
 }
 
@@ -294,6 +310,14 @@ bool same_kernel_matrix(const krr_fit_params& a, const krr_fit_params& b) {
   }
 }
 
+// A persistent factorisation that gave up waiting marks its systems
+// KRR_EDEVICE: the whole call fails.
+static void check_gave_up(const SysStatus* st_h, int n_sys) {
+  for (int i = 0; i < n_sys; ++i)
+    if (st_h[i].status == KRR_EDEVICE)
+      fail(KRR_EDEVICE, "the persistent factorisation gave up waiting for a stage (KRR_OPT_PERSIST_WAIT_MS)");
+}
+
 void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype, int64_t n, int d,
              const int32_t* assign, const double* centroids, int p, const krr_fit_params* params, int n_params,
              krr_model* models, krr_part_info* info, FitDirect* direct) {
@@ -343,10 +367,14 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
   data->ct_t = (double*)((char*)data->base + xbytes + cbytes);
   data->d_offsets = (int64_t*)((char*)data->base + xbytes + 2 * cbytes);
   data->offsets = off;
-  gather_rows(ctx, s, X, dtype, n, d, perm, data->X);
   KRR_HIP(hipMemcpyAsync(data->centroids, centroids, (size_t)p * d * 8, hipMemcpyDeviceToDevice, s));
   transpose_centroids(ctx, s, centroids, p, d, data->ct_t);
   KRR_HIP(hipMemcpyAsync(data->d_offsets, off_d, (size_t)(p + 1) * 8, hipMemcpyDeviceToDevice, s));
+  // graphs on a stream other than the legacy default one: the grouped inputs
+  // go to a workspace buffer (a stable address for the replays) and are
+  // copied into the partition data afterwards
+  const bool use_graph = ctx->graphs && s != nullptr && !ctx->serial_fit;
+  void* Xg = use_graph ? ws_get(ctx, "fit_xg", xbytes) : data->X;
 
   // 3. system descriptors
   const int n_sys = n_params * p;
@@ -400,10 +428,10 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
       D.ka = params[q].kernel_a;
       D.kr = params[q].kernel_r;
       D.kdeg = params[q].kernel_degree;
-      D.pad_ = 0;
+      D.wp = ctx->force_wp > 0 ? ctx->force_wp : tuned_panel(ctx, prec, m);
       D.level = 0;
       D.pk_off = pk_tot;
-      pk_tot += (prec == KRR_PREC_MIXED) ? pack_slot_elems(D.T, ctx->panel_tiles) : 0;
+      pk_tot += (prec == KRR_PREC_MIXED) ? pack_slot_elems(D.T, D.wp) : 0;
       D.k_off = k_off[(int64_t)grp_of[q] * p + jp];
       a_tot += tri(D.T) * TILE;
       w_tot += (int64_t)D.T * TILE;
@@ -437,13 +465,20 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
   int64_t* d_noff = d_poff + n_sys;
   int32_t* d_active = (int32_t*)(d_noff + n_sys);
   double* P = nullptr;
+  double* Pabs = nullptr;
   double* rn = nullptr;
   double* yn = nullptr;
+  double* glo = nullptr;
+  double* ghi = nullptr;
   if (mixed) {
     P = (double*)ws_get(ctx, "fit_P", (size_t)std::max<int64_t>(p_tot, 1) * 8);
-    char* nb = (char*)ws_get(ctx, "fit_norms", (size_t)std::max<int64_t>(n_tot, 1) * 16);
+    Pabs = (double*)ws_get(ctx, "fit_Pabs", (size_t)std::max<int64_t>(p_tot, 1) * 8);
+    const int64_t nt1 = std::max<int64_t>(n_tot, 1);
+    char* nb = (char*)ws_get(ctx, "fit_norms", (size_t)nt1 * 32);
     rn = (double*)nb;
-    yn = rn + std::max<int64_t>(n_tot, 1);
+    yn = rn + nt1;
+    glo = yn + nt1;
+    ghi = glo + nt1;
   }
 
   // host -> device descriptors through pinned staging (kept until the sync below)
@@ -466,36 +501,91 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
   KRR_HIP(hipMemcpyAsync(d_desc, pin, (size_t)n_sys * sizeof(SysDesc), hipMemcpyHostToDevice, s));
   KRR_HIP(hipMemcpyAsync(d_poff, pin + (size_t)n_sys * sizeof(SysDesc), (size_t)n_sys * 16, hipMemcpyHostToDevice,
                          s));
-  hipLaunchKernelGGL(k_zero_status, dim3((unsigned)ceil_div(n_sys, 128)), dim3(128), 0, s, d_st, n_sys);
-  check_launch(ctx, s, "zero_status");
 
-  // 5. grouped labels, padded right-hand sides
-  gather_vec_f64(ctx, s, y, dtype, n, perm, yg);
-  if (Tmax > 0) {
-    hipLaunchKernelGGL(k_pad_rhs, dim3((unsigned)ceil_div((int64_t)Tmax * NB, 256), (unsigned)n_sys), dim3(256), 0,
-                       s, (const SysDesc*)d_desc, n_sys, (const double*)yg, rhs);
-    check_launch(ctx, s, "pad_rhs");
-  }
-
-  // 6-8. form, factor, solve
+  // 5-8. grouped inputs, padded right-hand sides, form, factor, solve, and
+  // (mixed precision) the first refinement steps: the device phase of the
+  // fit, which a graph replay may stand in for
   bool general = false;   // polynomial or sigmoid settings in the batch
   for (int q = 0; q < n_params; ++q)
     general |= params[q].kernel == KRR_KERNEL_POLYNOMIAL || params[q].kernel == KRR_KERNEL_SIGMOID;
   auto form = [&](const SysDesc* dd, int pp, int ng, const int32_t* gf, const int32_t* gn, int tmax) {
     if (dtype == KRR_F64)
-      launch_form<double>(ctx, s, prec, data->X, d, dd, pp, ng, gf, gn, tmax, A, K64, general);
+      launch_form<double>(ctx, s, prec, Xg, d, dd, pp, ng, gf, gn, tmax, A, K64, general);
     else
-      launch_form<float>(ctx, s, prec, data->X, d, dd, pp, ng, gf, gn, tmax, A, K64, general);
+      launch_form<float>(ctx, s, prec, Xg, d, dd, pp, ng, gf, gn, tmax, A, K64, general);
   };
-  if (!ctx->serial_fit) {
+  const bool mixed_ref = mixed && Tmax > 0;
+  const int maxr = params[0].max_refine;
+  const double tol = params[0].refine_tol;
+  // refinement step `it` without a host check: the residual and convergence
+  // test, then a correction of the systems still refining (the kernels skip
+  // the others); returns whether the step went on past the test
+  auto refine_step = [&](int it) {
+    const int will = it < maxr ? 1 : 0;
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, d_active, 1);
+    check_launch(ctx, s, "zero_active");
+    residual_check(ctx, s, d_desc, d_st, n_sys, p, n_groups, d_grp, d_grp + n_groups, Tmax, K64, alpha, rhs, rb, P,
+                   d_poff, rn, yn, d_noff, tol, will, d_active, Pabs, glo, ghi);
+    return will != 0;
+  };
+  auto correct = [&]() {
+    trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, Tmax, v_tot, A, Wt, rb, zb, 1);
+    trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, Tmax, v_tot, A, Wt, zb, db, alpha, 1);
+    correction_norms(ctx, s, d_desc, d_st, n_sys, db, alpha);
+  };
+  // refinement steps taken inside the device phase (graphs only; the host
+  // cannot look at the active count there, the kernels of a step whose
+  // systems have all stopped do nothing)
+  const int graph_steps = (use_graph && mixed_ref) ? std::min(maxr, 2) : 0;
+  auto device_phase = [&]() {
+    if (use_graph) gather_rows(ctx, s, X, dtype, n, d, perm, Xg);
+    hipLaunchKernelGGL(k_zero_status, dim3((unsigned)ceil_div(n_sys, 128)), dim3(128), 0, s, d_st, n_sys);
+    check_launch(ctx, s, "zero_status");
+    gather_vec_f64(ctx, s, y, dtype, n, perm, yg);
+    if (Tmax > 0) {
+      hipLaunchKernelGGL(k_pad_rhs, dim3((unsigned)ceil_div((int64_t)Tmax * NB, 256), (unsigned)n_sys), dim3(256),
+                         0, s, (const SysDesc*)d_desc, n_sys, (const double*)yg, rhs);
+      check_launch(ctx, s, "pad_rhs");
+    }
     form(d_desc, p, n_groups, d_grp, d_grp + n_groups, Tmax);
     // mixed precision: the BF16 packed factorisation carries the forward solve along (zb = rhs on entry)
     if (mixed) KRR_HIP(hipMemcpyAsync(zb, rhs, vb, hipMemcpyDeviceToDevice, s));
     if (!cholesky_factor(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, 0, mixed, desc.data(), pack,
                          mixed ? zb : nullptr))
       trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, Tmax, v_tot, A, Wt, rhs, zb, 0);
+    pivot_range(ctx, s, prec, d_desc, d_st, n_sys, A, 0);
     trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, Tmax, v_tot, A, Wt, zb, alpha, nullptr, 0);
+    for (int it = 0; it < graph_steps; ++it)
+      if (refine_step(it)) correct();
+  };
+  if (!ctx->serial_fit) {
+    if (!use_graph) {
+      gather_rows(ctx, s, X, dtype, n, d, perm, Xg);
+      device_phase();
+    } else {
+      // key: everything the device phase reads from the host side
+      std::string key = "fit";
+      for (const void* ptr : {X, y, (const void*)assign, (const void*)Xg})
+        key_add(key, ptr);
+      for (int64_t v : {n, (int64_t)d, (int64_t)p, (int64_t)dtype, (int64_t)prec, (int64_t)Tmax, v_tot,
+                        (int64_t)ctx->panel_tiles, (int64_t)ctx->persistent, (int64_t)graph_steps})
+        key_add(key, v);
+      key.append(reinterpret_cast<const char*>(params), sizeof(krr_fit_params) * n_params);
+      key.append(reinterpret_cast<const char*>(desc.data()), sizeof(SysDesc) * desc.size());
+      key.append(reinterpret_cast<const char*>(grp_first.data()), sizeof(int32_t) * grp_first.size());
+      key.append(reinterpret_cast<const char*>(grp_next.data()), sizeof(int32_t) * grp_next.size());
+      graph_run(ctx, s, key, device_phase);
+    }
   } else {
+    gather_rows(ctx, s, X, dtype, n, d, perm, Xg);
+    hipLaunchKernelGGL(k_zero_status, dim3((unsigned)ceil_div(n_sys, 128)), dim3(128), 0, s, d_st, n_sys);
+    check_launch(ctx, s, "zero_status");
+    gather_vec_f64(ctx, s, y, dtype, n, perm, yg);
+    if (Tmax > 0) {
+      hipLaunchKernelGGL(k_pad_rhs, dim3((unsigned)ceil_div((int64_t)Tmax * NB, 256), (unsigned)n_sys), dim3(256),
+                         0, s, (const SysDesc*)d_desc, n_sys, (const double*)yg, rhs);
+      check_launch(ctx, s, "pad_rhs");
+    }
     // plain per-system sequence: every system formed, factored and solved
     // by its own launches, one after another
     for (int sidx = 0; sidx < n_sys; ++sidx) {
@@ -503,6 +593,7 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
       form(d_desc + sidx, 1, 1, d_grp + n_groups + n_params, d_grp + n_groups + n_params + 1, desc[sidx].T);
       cholesky_factor(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, desc[sidx].T, A, Wt, 0, mixed,
                       desc.data() + sidx, pack, nullptr);
+      pivot_range(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, A, 0);
       trsv_forward(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, desc[sidx].T, v_tot, A, Wt, rhs, zb, 0);
       trsv_backward(ctx, s, prec, d_desc + sidx, d_st + sidx, 1, desc[sidx].T, v_tot, A, Wt, zb, alpha, nullptr,
                     0);
@@ -514,28 +605,22 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
   // are re-formed from the FP64 kernel and refactored with FP32 updates.
   SysStatus* st_h = (SysStatus*)(pin + up_bytes);
   std::vector<int> fallback(n_sys, 0);
-  if (mixed && Tmax > 0) {
-    const int maxr = params[0].max_refine;
-    const double tol = params[0].refine_tol;
+  if (mixed_ref) {
     int32_t* act_h = (int32_t*)(pin + up_bytes + dn_bytes);
-    auto refine = [&]() {
-      for (int it = 0;; ++it) {
-        const int will = it < maxr ? 1 : 0;
-        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, d_active, 1);
-        check_launch(ctx, s, "zero_active");
-        residual_check(ctx, s, d_desc, d_st, n_sys, p, n_groups, d_grp, d_grp + n_groups, Tmax, K64, alpha, rhs, rb,
-                       P, d_poff, rn, yn, d_noff, tol, will, d_active);
-        if (!will) break;
+    // steps [it0, ...) with a look at the active count after each test
+    auto refine = [&](int it0) {
+      for (int it = it0;; ++it) {
+        if (!refine_step(it)) break;
         KRR_HIP(hipMemcpyAsync(act_h, d_active, 4, hipMemcpyDeviceToHost, s));
         KRR_HIP(hipStreamSynchronize(s));
         if (*act_h == 0) break;
-        trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, Tmax, v_tot, A, Wt, rb, zb, 1);
-        trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, Tmax, v_tot, A, Wt, zb, db, alpha, 1);
+        correct();
       }
     };
-    refine();
+    refine(graph_steps);
     KRR_HIP(hipMemcpyAsync(st_h, d_st, dn_bytes, hipMemcpyDeviceToHost, s));
     KRR_HIP(hipStreamSynchronize(s));
+    check_gave_up(st_h, n_sys);
     int n_esc = 0;
     for (int sidx = 0; sidx < n_sys; ++sidx)
       if (desc[sidx].T > 0 && !st_h[sidx].converged) {
@@ -553,15 +638,17 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
                          (const SysDesc*)d_desc, (const double*)K64, (float*)A, 1);
       check_launch(ctx, s, "restore_tiles");
       cholesky_factor(ctx, s, prec, d_desc, d_st, n_sys, Tmax, A, Wt, 1, false, desc.data(), pack, nullptr);
+      pivot_range(ctx, s, prec, d_desc, d_st, n_sys, A, 1);
       trsv_forward(ctx, s, prec, d_desc, d_st, n_sys, Tmax, v_tot, A, Wt, rhs, zb, 1);
       trsv_backward(ctx, s, prec, d_desc, d_st, n_sys, Tmax, v_tot, A, Wt, zb, alpha, nullptr, 1);
-      refine();
+      refine(0);
     }
   }
 
   // 10. status to host
   KRR_HIP(hipMemcpyAsync(st_h, d_st, dn_bytes, hipMemcpyDeviceToHost, s));
   KRR_HIP(hipStreamSynchronize(s));
+  check_gave_up(st_h, n_sys);
   for (int q = 0; q < n_params; ++q)
     for (int jp = 0; jp < p; ++jp) {
       const int sidx = q * p + jp;
@@ -576,9 +663,14 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
       I.fallback = fallback[sidx];
       I.reserved = 0;
       I.rel_residual = mixed ? S.rel_residual : -1.0;
+      I.kappa_est = S.kappa_l;
+      I.kappa_bound = mixed ? S.kappa_u : -1.0;
+      I.err_est = mixed ? S.err_est : -1.0;
       if (mixed && S.status == 0 && !S.converged && desc[sidx].T > 0) I.status = KRR_ENOCONV;
     }
 
+  if (use_graph && Xg != data->X)
+    KRR_HIP(hipMemcpyAsync(data->X, Xg, (size_t)n * d * xes, hipMemcpyDeviceToDevice, s));
   if (direct != nullptr) {
     direct->alpha = alpha;
     direct->v_off.resize(p);

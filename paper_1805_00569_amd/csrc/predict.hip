@@ -475,13 +475,31 @@ void predict_models(krr_ctx ctx, hipStream_t s, const krr_model* models, int nm,
 void run_predict(krr_ctx ctx, hipStream_t s, krr_model model, const void* Xt, int dtype, int64_t k, int route,
                  double* yhat, int32_t* route_out, Arena* ar) {
   KRR_REQUIRE(model->data->d > 0, "empty model");
-  Routing R;
-  if (route == KRR_ROUTE_NEAREST || route_out != nullptr)
-    R = route_points(ctx, s, *model->data, Xt, dtype, k, "", ar);
-  double* dst[1] = {yhat};
-  predict_models(ctx, s, &model, 1, Xt, dtype, k, route, R, dst, ar);
-  if (route_out != nullptr)
-    KRR_HIP(hipMemcpyAsync(route_out, R.route, (size_t)k * 4, hipMemcpyDeviceToDevice, s));
+  auto body = [&]() {
+    Routing R;
+    if (route == KRR_ROUTE_NEAREST || route_out != nullptr)
+      R = route_points(ctx, s, *model->data, Xt, dtype, k, "", ar);
+    double* dst[1] = {yhat};
+    predict_models(ctx, s, &model, 1, Xt, dtype, k, route, R, dst, ar);
+    if (route_out != nullptr)
+      KRR_HIP(hipMemcpyAsync(route_out, R.route, (size_t)k * 4, hipMemcpyDeviceToDevice, s));
+  };
+  if (ar != nullptr || !ctx->graphs || s == nullptr) {
+    body();
+    return;
+  }
+  // key: the call's pointers and sizes, and what the launches take from the model
+  const krr_part_data& D = *model->data;
+  std::string key = "predict";
+  for (const void* p : {(const void*)model, Xt, (const void*)yhat, (const void*)route_out, (const void*)model->alpha,
+                        (const void*)model->d_voff, (const void*)D.X, (const void*)D.ct_t,
+                        (const void*)D.d_offsets})
+    key_add(key, p);
+  for (int64_t v : {(int64_t)dtype, k, (int64_t)route, (int64_t)D.p, (int64_t)D.d})
+    key_add(key, v);
+  key_add(key, model->params);
+  key.append(reinterpret_cast<const char*>(D.offsets.data()), D.offsets.size() * sizeof(int64_t));
+  graph_run(ctx, s, key, body);
 }
 
 // ---------------------------------------------------------------------------

@@ -429,7 +429,7 @@ __global__ __launch_bounds__(256) void k_resid_tiles(const SysDesc* __restrict__
                                                      const int32_t* __restrict__ grp_next,
                                                      const double* __restrict__ K64,
                                                      const double* __restrict__ alpha, double* __restrict__ P,
-                                                     const int64_t* __restrict__ p_off) {
+                                                     const int64_t* __restrict__ p_off, double* __restrict__ Pabs) {
   const int j = blockIdx.y % p, grp = blockIdx.y / p;
   int q = grp_first[grp];
   const SysDesc D0 = desc[q * p + j];
@@ -455,89 +455,184 @@ __global__ __launch_bounds__(256) void k_resid_tiles(const SysDesc* __restrict__
   const bool diag_tile = ii == jj;
   for (; q >= 0; q = grp_next[q]) {
     const int s = q * p + j;
-    if (skip_system(st[s], 1)) continue;   // uniform over the workgroup
+    // the |A| partials are formed once per system (while its kappa bound is
+    // not formed), whatever its status; the residual only for the systems
+    // still refining
+    const bool need_abs = Pabs != nullptr && st[s].kappa_u < 0.0;
+    const bool do_res = !skip_system(st[s], 1);
+    if (!need_abs && !do_res) continue;   // uniform over the workgroup
     const SysDesc D = desc[s];
-    double* Pb = P + p_off[s];
-    const double* aj = alpha + D.v_off + jj * NB + 4 * cbk;
-    double av[4];
+    if (do_res) {
+      double* Pb = P + p_off[s];
+      const double* aj = alpha + D.v_off + jj * NB + 4 * cbk;
+      double av[4];
 #pragma unroll
-    for (int l = 0; l < 4; ++l) av[l] = aj[l];
-    // rows: (K + lambda I)(i,j) alpha_j
-    double rs[4];
+      for (int l = 0; l < 4; ++l) av[l] = aj[l];
+      // rows: (K + lambda I)(i,j) alpha_j
+      double rs[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      double acc = 0.0;
-#pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        double kv = K[l][k];
-        if (diag_tile && rbk == cbk && k == l && ii * NB + 4 * rbk + k < D.m) kv += D.lambda;
-        acc = fma(kv, av[l], acc);
-      }
-      for (int off = 1; off < 16; off <<= 1) acc += __shfl_xor(acc, off, 64);
-      rs[k] = acc;
-    }
-    if (cbk == 0) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) Pb[((int64_t)ii * D.T + jj) * NB + 4 * rbk + k] = rs[k];
-    }
-    if (!diag_tile) {   // columns: K(i,j)^T alpha_i (no shift off the diagonal)
-      const double* ai = alpha + D.v_off + ii * NB + 4 * rbk;
-      double bv[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) bv[k] = ai[k];
-#pragma unroll
-      for (int l = 0; l < 4; ++l) {
+      for (int k = 0; k < 4; ++k) {
         double acc = 0.0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) acc = fma(K[l][k], bv[k], acc);
-        acc += __shfl_xor(acc, 16, 64);
-        acc += __shfl_xor(acc, 32, 64);
-        if ((t & 63) < 16) scol[w][4 * cbk + l] = acc;
+        for (int l = 0; l < 4; ++l) {
+          double kv = K[l][k];
+          if (diag_tile && rbk == cbk && k == l && ii * NB + 4 * rbk + k < D.m) kv += D.lambda;
+          acc = fma(kv, av[l], acc);
+        }
+        for (int off = 1; off < 16; off <<= 1) acc += __shfl_xor(acc, off, 64);
+        rs[k] = acc;
       }
-      __syncthreads();
-      if (t < NB)
-        Pb[((int64_t)jj * D.T + ii) * NB + t] = (scol[0][t] + scol[1][t]) + (scol[2][t] + scol[3][t]);
-      __syncthreads();
+      if (cbk == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Pb[((int64_t)ii * D.T + jj) * NB + 4 * rbk + k] = rs[k];
+      }
+      if (!diag_tile) {   // columns: K(i,j)^T alpha_i (no shift off the diagonal)
+        const double* ai = alpha + D.v_off + ii * NB + 4 * rbk;
+        double bv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) bv[k] = ai[k];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          double acc = 0.0;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) acc = fma(K[l][k], bv[k], acc);
+          acc += __shfl_xor(acc, 16, 64);
+          acc += __shfl_xor(acc, 32, 64);
+          if ((t & 63) < 16) scol[w][4 * cbk + l] = acc;
+        }
+        __syncthreads();
+        if (t < NB)
+          Pb[((int64_t)jj * D.T + ii) * NB + t] = (scol[0][t] + scol[1][t]) + (scol[2][t] + scol[3][t]);
+        __syncthreads();
+      }
+    }
+    if (need_abs) {
+      // the same partials of |A| times ones: row sums of |A| for Gershgorin's bounds
+      double* Ab = Pabs + p_off[s];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          double kv = K[l][k];
+          if (diag_tile && rbk == cbk && k == l && ii * NB + 4 * rbk + k < D.m) kv += D.lambda;
+          acc += fabs(kv);
+        }
+        for (int off = 1; off < 16; off <<= 1) acc += __shfl_xor(acc, off, 64);
+        if (cbk == 0) Ab[((int64_t)ii * D.T + jj) * NB + 4 * rbk + k] = acc;
+      }
+      if (!diag_tile) {
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          double acc = 0.0;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) acc += fabs(K[l][k]);
+          acc += __shfl_xor(acc, 16, 64);
+          acc += __shfl_xor(acc, 32, 64);
+          if ((t & 63) < 16) scol[w][4 * cbk + l] = acc;
+        }
+        __syncthreads();
+        if (t < NB)
+          Ab[((int64_t)jj * D.T + ii) * NB + t] = (scol[0][t] + scol[1][t]) + (scol[2][t] + scol[3][t]);
+        __syncthreads();
+      }
     }
   }
 }
 
 // r_i = y_i - sum_j P(i, j) (fixed j order) and per-tile-row sums of r^2, y^2.
+// First pass (Pabs non-null): per tile row, Gershgorin's bounds over its
+// rows i < m: min_i (2 A_ii - sum_j |A_ij|) into glo and max_i sum_j |A_ij|
+// into ghi.
 __global__ __launch_bounds__(64) void k_resid_reduce(const SysDesc* __restrict__ desc, const SysStatus* __restrict__ st,
                                                      const double* __restrict__ y, const double* __restrict__ P,
                                                      const int64_t* __restrict__ p_off, double* __restrict__ r,
                                                      double* __restrict__ rn, double* __restrict__ yn,
-                                                     const int64_t* __restrict__ n_off) {
+                                                     const int64_t* __restrict__ n_off,
+                                                     const double* __restrict__ Pabs, const double* __restrict__ K64,
+                                                     double* __restrict__ glo, double* __restrict__ ghi) {
   const int s = blockIdx.y;
   const SysDesc D = desc[s];
-  if (skip_system(st[s], 1)) return;
+  const bool need_abs = Pabs != nullptr && st[s].kappa_u < 0.0;
+  const bool do_res = !skip_system(st[s], 1);
+  if (!need_abs && !do_res) return;
   const int i = blockIdx.x;
   if (i >= D.T) return;
   const int lane = threadIdx.x;
-  const double* Pb = P + p_off[s] + (int64_t)i * D.T * NB;
-  double acc = 0.0;
-  for (int j = 0; j < D.T; ++j) acc += Pb[j * NB + lane];
-  const double yv = y[D.v_off + i * NB + lane];
-  const double rv = yv - acc;
-  r[D.v_off + i * NB + lane] = rv;
-  const double r2 = wave_sum(rv * rv);
-  const double y2 = wave_sum(yv * yv);
-  if (lane == 0) {
-    rn[n_off[s] + i] = r2;
-    yn[n_off[s] + i] = y2;
+  if (do_res) {
+    const double* Pb = P + p_off[s] + (int64_t)i * D.T * NB;
+    double acc = 0.0;
+    for (int j = 0; j < D.T; ++j) acc += Pb[j * NB + lane];
+    const double yv = y[D.v_off + i * NB + lane];
+    const double rv = yv - acc;
+    r[D.v_off + i * NB + lane] = rv;
+    const double r2 = wave_sum(rv * rv);
+    const double y2 = wave_sum(yv * yv);
+    if (lane == 0) {
+      rn[n_off[s] + i] = r2;
+      yn[n_off[s] + i] = y2;
+    }
+  }
+  if (need_abs) {
+    const double* Ab = Pabs + p_off[s] + (int64_t)i * D.T * NB;
+    double sa = 0.0;
+    for (int j = 0; j < D.T; ++j) sa += Ab[j * NB + lane];
+    const double aii = K64[D.k_off + tile_index(i, i) * TILE + lane * NB + lane] + D.lambda;
+    const bool in = i * NB + lane < D.m;
+    double lo = in ? 2.0 * aii - sa : INFINITY, hi = in ? sa : 0.0;
+    for (int off = 32; off > 0; off >>= 1) {
+      lo = fmin(lo, __shfl_xor(lo, off, 64));
+      hi = fmax(hi, __shfl_xor(hi, off, 64));
+    }
+    if (lane == 0) {
+      glo[n_off[s] + i] = lo;
+      ghi[n_off[s] + i] = hi;
+    }
   }
 }
 
-// Per system: ||r|| / ||y||, convergence flag, and the refinement step count.
+// Per system: ||r|| / ||y||, the forward-error estimate of alpha, the
+// convergence flag and the refinement step count.
+//
+// The target `tol` bounds the relative error of alpha as well as the
+// relative residual.  Through the residual the error is at most
+// kappa(A) ||r|| / ||y||, with kappa_u, an upper bound of kappa_2(A) for the
+// FP64 system the residual measures, in place of kappa: Gershgorin's discs
+// give lambda_max <= max_i sum_j |A_ij| and lambda_min >= min_i (2 A_ii -
+// sum_j |A_ij|), and for a positive semi-definite kernel (Gaussian, linear,
+// polynomial with a, r >= 0) lambda_min >= lambda as well (computed once, on
+// the first pass).  Once corrections have been applied, their sizes estimate
+// the error directly: refinement contracts the error by rho per step (the
+// ratio of the last two corrections), so about ||delta|| rho / (1 - rho) is
+// left after the last one (||delta|| itself after the first, or when the
+// corrections no longer shrink by half: the error then sits at the level of
+// their fluctuation, the accuracy the FP64 residual allows).  A system
+// converges when its residual and one of the two estimates are within tol.
+// A step that does not halve the residual otherwise stalls it (the caller
+// escalates its precision), and so does a BF16-updated factor whose pivot
+// ratio kappa_l (a lower bound of kappa_2) exceeds 128: its error of order
+// kappa u_bf16 (u_bf16 = 2^-8) would not contract.
 __global__ void k_ir_check(const SysDesc* __restrict__ desc, SysStatus* __restrict__ st, int n_sys,
                            const double* __restrict__ rn, const double* __restrict__ yn,
                            const int64_t* __restrict__ n_off, double tol, int will_refine,
-                           int32_t* __restrict__ active) {
+                           int32_t* __restrict__ active, const double* __restrict__ glo,
+                           const double* __restrict__ ghi) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n_sys) return;
   SysStatus& S = st[s];
-  if (S.status != 0 || S.converged || S.stalled) return;
   const SysDesc D = desc[s];
+  if (glo != nullptr && S.kappa_u < 0.0 && D.T > 0) {
+    double lo = INFINITY, hi = 0.0;
+    for (int i = 0; i < D.T; ++i) {
+      lo = fmin(lo, glo[n_off[s] + i]);
+      hi = fmax(hi, ghi[n_off[s] + i]);
+    }
+    const bool psd = D.kernel == KRR_KERNEL_GAUSSIAN || D.kernel == KRR_KERNEL_LINEAR ||
+                     (D.kernel == KRR_KERNEL_POLYNOMIAL && D.ka >= 0.0 && D.kr >= 0.0);
+    if (psd) lo = fmax(lo, D.lambda);
+    S.kappa_u = lo > 0.0 ? hi / lo : INFINITY;
+  }
+  if (S.status != 0 || S.converged || S.stalled) return;
   double r2 = 0.0, y2 = 0.0;
   for (int i = 0; i < D.T; ++i) {
     r2 += rn[n_off[s] + i];
@@ -548,13 +643,72 @@ __global__ void k_ir_check(const SysDesc* __restrict__ desc, SysStatus* __restri
   S.rel_residual = rel;
   S.prev_rel = rel;
   S.ynorm = sqrt(y2);
-  if (rel <= tol) {
+  const double kest = (S.kappa_u < 0.0 ? INFINITY : fmax(1.0, S.kappa_u)) * rel;
+  double est = kest;
+  if (S.corr >= 1) {
+    const double e = S.dnorm / fmax(S.anorm, 1e-300);
+    est = e;
+    if (S.corr >= 2 && S.prev_dnorm > 0.0) {
+      const double rho = S.dnorm / S.prev_dnorm;
+      if (rho < 0.5) est = e * (rho / (1.0 - rho));
+    }
+  }
+  S.err_est = fmin(est, kest);
+  if (rel <= tol && S.err_est <= tol) {
     S.converged = 1;
-  } else if (prev >= 0.0 && !(rel <= 0.5 * prev)) {
-    S.stalled = 1;  // a step that does not halve the residual: escalate precision
+  } else if ((prev >= 0.0 && !(rel <= 0.5 * prev)) || (D.level == 0 && S.corr == 0 && S.kappa_l > 128.0)) {
+    S.stalled = 1;  // escalate precision
   } else if (will_refine) {
     S.refine_iters += 1;
     atomicAdd(active, 1);
+  }
+}
+
+// kappa_l of the systems factored at `level`: the extreme diagonal entries of
+// their factors (one wave per system).
+template <typename TS>
+__global__ __launch_bounds__(64) void k_pivot_range(const SysDesc* __restrict__ desc, SysStatus* __restrict__ st,
+                                                    const TS* __restrict__ A, int level) {
+  const int s = blockIdx.x;
+  const SysDesc D = desc[s];
+  if (D.level != level || D.m == 0 || st[s].status != 0) return;
+  double lo = INFINITY, hi = 0.0;
+  for (int i = threadIdx.x; i < D.m; i += 64) {
+    const int k = i >> 6, r = i & 63;
+    const double v = fabs((double)A[D.a_off + tile_index(k, k) * TILE + r * NB + r]);
+    lo = fmin(lo, v);
+    hi = fmax(hi, v);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off, 64));
+    hi = fmax(hi, __shfl_xor(hi, off, 64));
+  }
+  if (threadIdx.x == 0) st[s].kappa_l = lo > 0.0 ? (hi / lo) * (hi / lo) : INFINITY;
+}
+
+// After a correction alpha += delta of the systems still refining: the
+// infinity norms of delta and of the new alpha (one wave per system).
+__global__ __launch_bounds__(64) void k_corr_norms(const SysDesc* __restrict__ desc, SysStatus* __restrict__ st,
+                                                   const double* __restrict__ delta,
+                                                   const double* __restrict__ alpha) {
+  const int s = blockIdx.x;
+  if (skip_system(st[s], 1)) return;
+  const SysDesc D = desc[s];
+  double dm = 0.0, am = 0.0;
+  for (int i = threadIdx.x; i < D.m; i += 64) {
+    dm = fmax(dm, fabs(delta[D.v_off + i]));
+    am = fmax(am, fabs(alpha[D.v_off + i]));
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    dm = fmax(dm, __shfl_xor(dm, off, 64));
+    am = fmax(am, __shfl_xor(am, off, 64));
+  }
+  if (threadIdx.x == 0) {
+    SysStatus& S = st[s];
+    S.prev_dnorm = S.dnorm;
+    S.dnorm = dm;
+    S.anorm = am;
+    S.corr += 1;
   }
 }
 
@@ -637,20 +791,40 @@ void trsv_backward(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, co
   }
 }
 
+void pivot_range(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, SysStatus* st, int n_sys, const void* A,
+                 int level) {
+  if (prec == KRR_PREC_FP64)
+    hipLaunchKernelGGL((k_pivot_range<double>), dim3(n_sys), dim3(64), 0, s, desc, st, (const double*)A, level);
+  else
+    hipLaunchKernelGGL((k_pivot_range<float>), dim3(n_sys), dim3(64), 0, s, desc, st, (const float*)A, level);
+  check_launch(ctx, s, "pivot_range");
+}
+
+void correction_norms(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, int n_sys, const double* delta,
+                      const double* alpha) {
+  hipLaunchKernelGGL(k_corr_norms, dim3(n_sys), dim3(64), 0, s, desc, st, delta, alpha);
+  check_launch(ctx, s, "corr_norms");
+}
+
+// Pabs (nullable): on the first pass, the |A| partials and Gershgorin's
+// bounds per tile row (glo, ghi) are formed beside the residual.
 void residual_check(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, int n_sys, int p, int n_groups,
                     const int32_t* grp_first, const int32_t* grp_next, int Tmax, const double* K64,
                     const double* alpha, const double* y, double* r, double* P, const int64_t* p_off, double* rn,
-                    double* yn, const int64_t* n_off, double tol, int will_refine, int32_t* active) {
+                    double* yn, const int64_t* n_off, double tol, int will_refine, int32_t* active, double* Pabs,
+                    double* glo, double* ghi) {
   const int64_t ntri = (int64_t)Tmax * (Tmax + 1) / 2;
   KernelTimer kt(ctx, s, "ir_residual", 0.0, 0);
   hipLaunchKernelGGL(k_resid_tiles, dim3((unsigned)ntri, (unsigned)(n_groups * p)), dim3(256), 0, s, desc,
-                     (const SysStatus*)st, p, grp_first, grp_next, K64, alpha, P, p_off);
+                     (const SysStatus*)st, p, grp_first, grp_next, K64, alpha, P, p_off, Pabs);
   check_launch(ctx, s, "resid_tiles");
   hipLaunchKernelGGL(k_resid_reduce, dim3((unsigned)Tmax, (unsigned)n_sys), dim3(64), 0, s, desc,
-                     (const SysStatus*)st, y, (const double*)P, p_off, r, rn, yn, n_off);
+                     (const SysStatus*)st, y, (const double*)P, p_off, r, rn, yn, n_off, (const double*)Pabs, K64,
+                     glo, ghi);
   check_launch(ctx, s, "resid_reduce");
   hipLaunchKernelGGL(k_ir_check, dim3((unsigned)ceil_div(n_sys, 64)), dim3(64), 0, s, desc, st, n_sys,
-                     (const double*)rn, (const double*)yn, n_off, tol, will_refine, active);
+                     (const double*)rn, (const double*)yn, n_off, tol, will_refine, active,
+                     Pabs != nullptr ? (const double*)glo : nullptr, (const double*)ghi);
   check_launch(ctx, s, "ir_check");
 }
 

@@ -25,7 +25,9 @@ PART = {"kmeans": 0, "kbalance": 1, "given": 2, "random": 3, "kbalance_approx": 
 PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
 ROUTE = {"nearest": 0, "average": 1, "all": 2, "label": 3}
 KERNEL = {"gaussian": 0, "linear": 1, "polynomial": 2, "sigmoid": 3}
-OPT_PANEL_TILES, OPT_SERIAL_FIT, OPT_SYNC_CHECK, OPT_TIMING = 0, 1, 2, 3
+OPT_PANEL_TILES, OPT_SERIAL_FIT, OPT_SYNC_CHECK, OPT_TIMING, OPT_PERSISTENT, OPT_PERSIST_WAIT_MS, OPT_GRAPHS = \
+    0, 1, 2, 3, 4, 5, 6
+OPT_AUTOTUNE = 7
 
 
 class KrrError(RuntimeError):
@@ -44,7 +46,8 @@ class FitParams(ctypes.Structure):
 class PartInfo(ctypes.Structure):
     _fields_ = [("partition", ctypes.c_int32), ("param", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("failed_pivot", ctypes.c_int32), ("refine_iters", ctypes.c_int32),
-                ("fallback", ctypes.c_int32), ("reserved", ctypes.c_int32), ("rel_residual", ctypes.c_double)]
+                ("fallback", ctypes.c_int32), ("reserved", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("kappa_est", ctypes.c_double), ("err_est", ctypes.c_double), ("kappa_bound", ctypes.c_double)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -77,6 +80,9 @@ _SIGS = {
     "krr_last_error": ([_P], ctypes.c_char_p),
     "krr_set_option": ([_P, ctypes.c_int32, ctypes.c_int64], ctypes.c_int),
     "krr_memory_in_use": ([_P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "krr_autotune": ([_P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "krr_graph_counts": ([_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "krr_timing_report": ([_P, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "krr_csr_to_dense": ([_P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, _P],
                          ctypes.c_int),
@@ -215,6 +221,20 @@ class Context:
         v = ctypes.c_size_t(0)
         self._check(self.lib.krr_memory_in_use(self.h, ctypes.byref(v)))
         return v.value
+
+    def autotune(self, prec, m, d, n_sys=8):
+        """Time trial fits and record the fastest panel width for (prec, size
+        class of m) on this context.  Returns (width, median fit ms)."""
+        w, ms = ctypes.c_int32(0), ctypes.c_double(0.0)
+        self._check(self.lib.krr_autotune(self.h, _stream(self.device), PREC[prec], int(m), int(d), int(n_sys),
+                                          ctypes.byref(w), ctypes.byref(ms)))
+        return w.value, ms.value
+
+    def graph_counts(self):
+        """(graphs captured, graph replays) on this context."""
+        c, r = ctypes.c_int64(0), ctypes.c_int64(0)
+        self._check(self.lib.krr_graph_counts(self.h, ctypes.byref(c), ctypes.byref(r)))
+        return c.value, r.value
 
     def timing_report(self):
         """Per-kernel-class event timing since the last report (see

@@ -30,8 +30,8 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     # krr_fit_params: double, double, int32, int32, double, int32, int32, double, double, int32, int32 -> 64 bytes
     assert ctypes.sizeof(krr.FitParams) == 64
-    # krr_part_info: 8 x int32 + double -> 40 bytes
-    assert ctypes.sizeof(krr.PartInfo) == 40
+    # krr_part_info: 8 x int32 + 4 doubles -> 64 bytes
+    assert ctypes.sizeof(krr.PartInfo) == 64
     # krr_server_config: 4 x int32, int64, size_t -> 32 bytes
     assert ctypes.sizeof(krr.ServerConfig) == 32
     # krr_request_info: 4 x int32 + 3 doubles -> 40 bytes

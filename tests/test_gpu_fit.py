@@ -183,6 +183,10 @@ def test_polynomial_sigmoid_and_gaussian_settings_in_one_batch(ctx, dev, prec):
     X, y = _t(w.X, dev), _t(w.y, dev)
     C, a, _ = ctx.partition(X, 3, "kbalance", lloyd_iters=5, seed=3)
     models, info, st = ctx.fit(X, y, a, C, 3, params)
+    for r in info:
+        print(f"  setting {r['param']} part {r['partition']}: status {r['status']} steps {r['refine_iters']} "
+              f"fallback {r['fallback']} kappa_est {r['kappa_est']:.3g} err_est {r['err_est']:.2e} "
+              f"rel_res {r['rel_residual']:.2e}", flush=True)
     assert st == 0 and all(i["status"] == 0 for i in info)
     a_np, C_np = a.cpu().numpy(), C.cpu().numpy()
     oms = [O.fit(w.X, w.y, a_np, C_np, 3, q.sigma, q.lam, _okernel(q)) for q in params]
@@ -259,11 +263,12 @@ def test_mixed_precision_refines_to_1e6(ctx, dev, sigma):
     models, info, st, oms, X, a = _fit_both(ctx, dev, w, 2, params, method="kbalance", iters=5, seed=3)
     assert st == 0, info
     for j in range(2):
-        assert info[j]["rel_residual"] <= 1e-8
+        assert info[j]["rel_residual"] <= 1e-8 and 0 <= info[j]["err_est"] <= 1e-8
         err = ew(models[0].alpha(j).cpu().numpy(), oms[0].alphas[j])
         assert err < 1e-6, err
         print(f"partition {j}: refine steps {info[j]['refine_iters']} fallback {info[j]['fallback']} "
-              f"alpha err {err:.2e}", flush=True)
+              f"kappa_est {info[j]['kappa_est']:.3g} err_est {info[j]['err_est']:.2e} alpha err {err:.2e}",
+              flush=True)
         if sigma is not None:
             assert info[j]["fallback"] == 0
     yhat = ctx.predict(models[0], _t(w.Xt, dev)).cpu().numpy()

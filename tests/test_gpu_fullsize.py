@@ -17,6 +17,8 @@ checked through what the oracle can compute one by one: the residual
 (K + lambda I) alpha - y on sampled rows (Eq. 6, kernel values by direct
 difference, FP64), and predictions of sampled test points against Eq. 7
 evaluated with the GPU's alpha.  Every comparison is element by element."""
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -94,6 +96,74 @@ def test_balanced_mixed_fullsize(ctx, dev):
 
 
 @pytest.mark.timeout(900)
+def test_balanced_stress_mixed_fullsize(ctx, dev):
+    """The balanced workload with the median-heuristic sigma (about 12.7),
+    which takes K far from the identity: kappa_2(K + lambda I) is about
+    3e4..7e4 at m = 4,096 for both lambdas (the smallest eigenvalues come
+    from K itself).  Mixed precision must still deliver alpha within 1e-6 of
+    the FP64 oracle; the BF16-updated factor cannot (kappa u_bf16 >> 1), so
+    these systems are expected to take the FP32-update fallback, and the
+    count is reported.  The FP64 path is checked by its backward error
+    (<= 10 m u64, the stress reading for kappa > 1e4) and its forward error
+    is reported."""
+    w = datagen.balanced(seed=2)
+    sig = datagen.median_heuristic_sigma(w.X)
+    print(f"full size stress: balanced n=65536 d=90 p=16, sigma={sig:.4f}, mixed", flush=True)
+    X, y = _t(w.X, dev), _t(w.y.astype(np.float32), dev)
+    C, a, sz = ctx.partition(X, 16, "kbalance", lloyd_iters=20, seed=2)
+    a_np = a.cpu().numpy()
+    lams = (1e-4, 1e-2)
+    params = [krr.Params(sigma=sig, lam=l, prec="mixed", refine_tol=1e-6, max_refine=30) for l in lams]
+    models, info, st = ctx.fit(X, y, a, C, 16, params)
+    assert st == 0 and all(r["status"] == 0 for r in info), [r for r in info if r["status"] != 0]
+    nfb = sum(r["fallback"] for r in info)
+    print(f"  fallbacks {nfb}/32, refine steps max {max(r['refine_iters'] for r in info)}, "
+          f"kappa_est {min(r['kappa_est'] for r in info):.3g}..{max(r['kappa_est'] for r in info):.3g}, "
+          f"kappa_bound {min(r['kappa_bound'] for r in info):.3g}..{max(r['kappa_bound'] for r in info):.3g}, "
+          f"err_est max {max(r['err_est'] for r in info):.2e}", flush=True)
+    assert all(0 <= r["err_est"] <= 1e-6 and r["rel_residual"] <= 1e-6 for r in info)
+    yo = w.y.astype(np.float32).astype(np.float64)
+    perm, off = O.gather(a_np, 16)
+    checked = (0, 5, 10, 15)
+    jobs = [(w.X[perm[off[j]:off[j + 1]]].astype(np.float64), yo[perm[off[j]:off[j + 1]]], sig, lam, "gaussian",
+             False) for lam in lams for j in checked]
+    refs = oracle_alphas(jobs)
+    for i, (lam, j) in enumerate([(lam, j) for lam in lams for j in checked]):
+        q = lams.index(lam)
+        err = ew(models[q].alpha(j).cpu().numpy(), refs[i])
+        r = info[q * 16 + j]
+        print(f"  lambda {lam:g} partition {j}: alpha err {err:.2e}, steps {r['refine_iters']}, "
+              f"fallback {r['fallback']}, kappa_est {r['kappa_est']:.3g}, kappa_bound {r['kappa_bound']:.3g}, "
+              f"err_est {r['err_est']:.2e}", flush=True)
+        assert err < 1e-6, (lam, j, err)
+    for m in models:
+        m.free()
+    # FP64 path on the same systems: backward error and the condition number of one of them
+    p64 = [krr.Params(sigma=sig, lam=l, prec="fp64") for l in lams]
+    m64, i64, st = ctx.fit(X, y, a, C, 16, p64)
+    assert st == 0
+    idx = perm[off[0]:off[1]]
+    Xj = w.X[idx].astype(np.float64)
+    Aj = O.kernel_matrix(Xj, Xj, sig)
+    ev = np.linalg.eigvalsh(Aj)
+    for q, lam in enumerate(lams):
+        A = Aj + lam * np.eye(Aj.shape[0])
+        kappa = (ev[-1] + lam) / (ev[0] + lam)
+        al = m64[q].alpha(0).cpu().numpy()
+        be = np.linalg.norm(A @ al - yo[idx]) / (np.linalg.norm(A, 2) * np.linalg.norm(al) + np.linalg.norm(yo[idx]))
+        fe = ew(al, refs[lams.index(lam) * len(checked)])
+        print(f"  fp64 lambda {lam:g} partition 0: kappa {kappa:.3g} (estimate {i64[q * 16]['kappa_est']:.3g}), "
+              f"backward error {be:.2e}, alpha err vs oracle {fe:.2e}", flush=True)
+        assert be <= 10 * Aj.shape[0] * 2.0 ** -53
+        assert i64[q * 16]["kappa_est"] <= kappa * (1 + 1e-6)   # a lower bound of kappa_2
+        kb = [r["kappa_bound"] for r in info if r["partition"] == 0 and r["param"] == q][0]
+        assert kb >= kappa * (1 - 1e-6)                         # the mixed fit's bound is an upper bound
+        assert fe <= kappa * 1e-13
+    for m in m64:
+        m.free()
+
+
+@pytest.mark.timeout(900)
 def test_ragged_kmeans_fp32_fullsize(ctx, dev):
     print("full size: ragged n=131072 d=90, 32 k-means partitions, FP32", flush=True)
     w = datagen.gaussian_mixture(seed=3)
@@ -165,3 +235,52 @@ def test_single_large_system_fullsize(ctx, dev, m, prec):
     yo = O.predict_one(Xj, alpha, Xt.astype(np.float64), sigma)
     assert pred_ew(yhat, yo, w.yt[:256]) < 1e-10
     models[0].free()
+
+
+@pytest.mark.timeout(900)
+def test_dkrr_single_system_131072(dev):
+    """Exact KRR (Algorithm 1, p = 1) of one system of n = 131,072 points,
+    d = 90 -- the DKRR size the paper's distributed solver stops scaling at
+    (Section 5.2): 2,048 tile rows, 8.6e9 tile elements (element offsets past
+    2^31).  FP64: residual of 64 sampled rows against direct-difference FP64
+    kernel values within 1e-10 of max |y|, and sampled predictions against
+    Eq. 7 evaluated with the GPU's alpha.  Mixed precision: alpha within 1e-6
+    of the FP64 alpha (element-wise) and its own sampled residual rows."""
+    w = datagen.balanced(seed=6, n=131072, k_test=512, p=1)
+    sig, lam = 4.0, 1e-2
+    yo = w.y.astype(np.float32).astype(np.float64)
+    g = np.random.default_rng(1)
+    rows = g.choice(w.n, 64, replace=False)
+    alphas = {}
+    for prec in ("fp64", "mixed"):
+        print(f"DKRR n=131072 d=90 single system, {prec}", flush=True)
+        ctx = krr.Context(0)
+        try:
+            X, y = _t(w.X, dev), _t(w.y.astype(np.float32), dev)
+            a = torch.zeros(w.n, dtype=torch.int32, device=dev)
+            C = torch.zeros((1, w.d), dtype=torch.float64, device=dev)
+            t0 = time.time()
+            models, info, st = ctx.fit(X, y, a, C, 1, [krr.Params(sigma=sig, lam=lam, prec=prec, refine_tol=1e-8,
+                                                                  max_refine=20)])
+            torch.cuda.synchronize()
+            print(f"  fit {time.time() - t0:.1f} s, status {st}, refine {info[0]['refine_iters']}, "
+                  f"fallback {info[0]['fallback']}", flush=True)
+            assert st == 0 and info[0]["m"] == w.n
+            al = models[0].alpha(0).cpu().numpy()
+            alphas[prec] = al
+            res = _sampled_residual(w.X.astype(np.float64), yo, al, sig, lam, rows)
+            print(f"  sampled residual {res:.2e}", flush=True)
+            assert res < (1e-10 if prec == "fp64" else 1e-8)
+            if prec == "fp64":
+                Xt = w.Xt[:64]
+                yh = ctx.predict(models[0], _t(Xt, dev)).cpu().numpy()
+                ye = O.predict_one(w.X.astype(np.float64), al, Xt.astype(np.float64), sig)
+                assert pred_ew(yh, ye, w.yt[:64]) < 1e-10
+            models[0].free()
+            del X, y
+        finally:
+            ctx.close()
+            torch.cuda.empty_cache()
+    err = ew(alphas["mixed"], alphas["fp64"])
+    print(f"  mixed vs fp64 alpha err {err:.2e}", flush=True)
+    assert err < 1e-6
