@@ -227,8 +227,9 @@ def main():
         C, a = state["C"], state["assign"]
         comp = {}
 
-        def time_fit(prec, serial, reps=1):
+        def time_fit(prec, serial, reps=1, persistent=0):
             ctx.set_option(krr.OPT_SERIAL_FIT, 1 if serial else 0)
+            ctx.set_option(krr.OPT_PERSISTENT, persistent)
             try:
                 models, info2, st2 = ctx.fit(X, y, a, C, P_PARTS, settings(prec))   # warm
                 for m in models:
@@ -243,14 +244,17 @@ def main():
                 return (time.perf_counter() - t) / reps, info2
             finally:
                 ctx.set_option(krr.OPT_SERIAL_FIT, 0)
+                ctx.set_option(krr.OPT_PERSISTENT, 0)
 
-        for name, prec, serial, reps in (("batched_" + args.prec, args.prec, False, 3),
-                                         ("batched_fp64", "fp64", False, 1),
-                                         ("batched_fp32", "fp32", False, 1),
-                                         ("plain_fp64_per_partition", "fp64", True, 1)):
+        for name, prec, serial, reps, pers in (("batched_" + args.prec, args.prec, False, 3, 0),
+                                               ("batched_" + args.prec + "_persistent", args.prec, False, 3, 1),
+                                               ("batched_fp64", "fp64", False, 1, 0),
+                                               ("batched_fp64_persistent", "fp64", False, 1, 1),
+                                               ("batched_fp32", "fp32", False, 1, 0),
+                                               ("plain_fp64_per_partition", "fp64", True, 1, 0)):
             if name in comp:
                 continue
-            tt, inf = time_fit(prec, serial, reps)
+            tt, inf = time_fit(prec, serial, reps, pers)
             comp[name] = {"fit_ms": round(tt * 1e3, 3), "fits_per_s": n_fits / tt,
                           "tflops": flops_fit / tt / 1e12}
             print(f"# {name}: {tt * 1e3:.1f} ms", file=sys.stderr, flush=True)
@@ -590,7 +594,9 @@ def ragged_leg(reps=3):
     """Ragged KKRR2 batch: n = 131,072, d = 90, 32-component Gaussian mixture
     with Zipf(1.1) weights water-filled into [512, 14,000]; K-means (k-means++
     and 20 Lloyd passes) into 32 partitions; all 32 uneven systems fitted as
-    one batch in FP32 (sigma = 2, lambda = 1e-2), and in mixed precision."""
+    one batch in FP32 (sigma = 2, lambda = 1e-2), and in mixed precision;
+    each with one launch per factorisation stage and with the persistent
+    launch."""
     import torch
     from paper_1805_00569_amd import datagen, krr
     dev = torch.device("cuda:0")
@@ -611,10 +617,14 @@ def ragged_leg(reps=3):
     res["cholesky_tflop"] = sum(float(m) ** 3 / 3.0 for m in sizes) / 1e12
     for prec in ("fp32", "mixed"):
         params = [krr.Params(sigma=2.0, lam=1e-2, prec=prec, refine_tol=1e-6, max_refine=30)]
-        tf, info, st = _timed_fit(ctx, X, y, a, C, 32, params, reps)
-        res[prec] = {"fit_ms": tf * 1e3, "fits_per_s": 32 / tf, "tflops": fl / tf / 1e12, "status": st,
-                     "frac_peak": fl / tf / 1e12 / PEAK["fp32" if prec == "fp32" else "bf16"]}
-        print(f"# ragged {prec}: {tf * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        for pers in (0, 1):   # one launch per stage / the persistent launch
+            ctx.set_option(krr.OPT_PERSISTENT, pers)
+            tf, info, st = _timed_fit(ctx, X, y, a, C, 32, params, reps)
+            key = prec + ("_persistent" if pers else "")
+            res[key] = {"fit_ms": tf * 1e3, "fits_per_s": 32 / tf, "tflops": fl / tf / 1e12, "status": st,
+                        "frac_peak": fl / tf / 1e12 / PEAK["fp32" if prec == "fp32" else "bf16"]}
+            print(f"# ragged {key}: {tf * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        ctx.set_option(krr.OPT_PERSISTENT, 0)
     ctx.close()
     return res
 

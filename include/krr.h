@@ -108,7 +108,8 @@ typedef enum { KRR_ROUTE_NEAREST = 0, KRR_ROUTE_AVERAGE = 1, KRR_ROUTE_ALL = 2, 
  * (kernel_a a^T b + kernel_r)^kernel_degree; sigmoid tanh(kernel_a a^T b +
  * kernel_r).  The sigmoid kernel is not positive semi-definite in general: a
  * system whose K + lambda I is not positive definite is reported as
- * KRR_ENOTSPD with its failing pivot, like any other. */
+ * KRR_ENOTSPD with its failing pivot, like any other, unless its setting
+ * asks for the LU solve (krr_fit_params.indefinite). */
 typedef enum { KRR_KERNEL_GAUSSIAN = 0, KRR_KERNEL_LINEAR = 1, KRR_KERNEL_POLYNOMIAL = 2,
                KRR_KERNEL_SIGMOID = 3 } krr_kernel;
 
@@ -131,7 +132,13 @@ typedef struct {
   double  kernel_a;       /* POLYNOMIAL, SIGMOID: scale a of the inner product (finite) */
   double  kernel_r;       /* POLYNOMIAL, SIGMOID: offset r (finite) */
   int32_t kernel_degree;  /* POLYNOMIAL: integer degree d in [1, 64] */
-  int32_t reserved;       /* 0 */
+  int32_t indefinite;     /* 0 or 1.  1: a system whose Cholesky factorisation meets a
+                             non-positive pivot (an indefinite K + lambda I, e.g. from the
+                             sigmoid kernel) is solved instead by Gaussian elimination (the
+                             paper's other solver, Implementation Details): LU with partial
+                             pivoting of the FP64 system, with no refinement; it reports
+                             solver = 1 and status KRR_OK, or KRR_ENOTSPD if a pivot column
+                             is entirely zero.  0: such a system is reported as KRR_ENOTSPD */
 } krr_fit_params;
 
 typedef struct {
@@ -144,7 +151,10 @@ typedef struct {
   int32_t fallback;       /* MIXED: 0 = BF16 trailing updates sufficed; 1 = the system was
                              refactored with FP32 trailing updates after its BF16 factor
                              was not positive definite or refinement stalled */
-  int32_t reserved;
+  int32_t solver;         /* 0: Cholesky (Eq. 6); 1: LU with partial pivoting (an indefinite
+                             system of a setting with indefinite = 1; failed_pivot then keeps
+                             the Cholesky pivot that rejected it, and rel_residual, err_est
+                             and kappa_bound are -1) */
   double  rel_residual;   /* ||y - (K + lambda I) alpha|| / ||y|| in FP64 (MIXED; -1 otherwise) */
   double  kappa_est;      /* (max_i L_ii / min_i L_ii)^2 of the factor: a lower bound of the
                              2-norm condition number of K + lambda I (1 for an empty system) */

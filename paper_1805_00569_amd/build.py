@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libkrr.so")
 SOURCES = ["api.hip", "csr.hip", "partition.hip", "fit.hip", "cholesky.hip", "solve.hip", "predict.hip", "serve.hip",
-           "tune.hip"]
+           "tune.hip", "lu.hip"]
 ARCH = os.environ.get("KRR_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

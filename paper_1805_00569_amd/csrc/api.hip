@@ -69,7 +69,8 @@ void* ws_get(krr_ctx ctx, const std::string& name, size_t bytes) {
   ctx->ws_epoch += 1;
   const size_t old = b.bytes;
   charge(ctx, bytes - old);
-  if (name == "persist_plan") ctx->persist.key.clear();   // the cached plan is gone with the buffer
+  for (int i = 0; i < krr_ctx_s::PersistCache::kSlots; ++i)   // a cached plan is gone with its buffer
+    if (name == "persist_plan" + std::to_string(i)) ctx->persist.slot[i] = krr_ctx_s::PersistPlan{};
   if (b.ptr != nullptr) {
     drain(ctx);  // the old buffer may still be in use by this context's queued work
     KRR_HIP(hipFree(b.ptr));
@@ -141,7 +142,7 @@ void ws_release_all(krr_ctx ctx) {
     }
   ctx->ws.clear();
   ctx->ws_epoch += 1;
-  ctx->persist.key.clear();   // the uploaded plan lived in the workspace
+  for (auto& pl : ctx->persist.slot) pl = krr_ctx_s::PersistPlan{};   // the plans lived in the workspace
 }
 
 void* pinned_named(krr_ctx ctx, const std::string& name, size_t bytes) {
@@ -459,6 +460,7 @@ krr_status krr_fit(krr_ctx ctx, hipStream_t stream, const void* X, const void* y
                   "unknown precision");
       KRR_REQUIRE(P.prec == params[0].prec, "all settings of one call must share the precision");
       KRR_REQUIRE(P.max_refine >= 0 && P.max_refine <= 1000, "max_refine out of range");
+      KRR_REQUIRE(P.indefinite == 0 || P.indefinite == 1, "indefinite must be 0 or 1");
     }
     for (int q = 0; q < n_params; ++q) models_out[q] = nullptr;
     StreamScope ss(ctx, stream);

@@ -1185,20 +1185,48 @@ __device__ __forceinline__ int ld_agent(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Index of the XCD (accelerator complex die) the calling wave runs on.
+__device__ __forceinline__ int xcd_id() {
+  unsigned x;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(x));
+  return (int)(x & (NXCD - 1));
+}
+
+// Counter block of a persistent launch (int32, zeroed before it):
+// [nq queue heads][n_sys tasks done per system][give-up flag][nq queue owners]
+inline int persist_ctr_count(int nq, int n_sys) { return 2 * nq + n_sys + 1; }
+
+// The persistent factorisation: workgroups take tasks from the plan's
+// queues and run each once its system has finished `need` tasks.
+//
+// local = 1 (one queue per XCD): every queue is served by the workgroups of
+// a single XCD (the queue's owner: its own XCD, claimed at first use, or
+// another XCD that has drained its own queues and finds it unclaimed), and a
+// system's tasks all sit in one queue, so every dependency stays inside one
+// XCD and its shared L2: a task publishes its results by waiting for its
+// stores to reach the L2 before it counts itself done (no L2 write-back),
+// and a waiting task drops the stale lines of its compute unit's L1 before
+// it reads them.
+// local = 0 (one shared queue): any workgroup takes any task; results cross
+// XCDs, so every task ends with an agent-scope release (L2 write-back) and
+// starts with an agent-scope acquire (L2 invalidation).
 template <typename TS, bool PACKED>
 __global__ __launch_bounds__(256, 2) void k_chol_persist(const SysDesc* __restrict__ desc, SysStatus* __restrict__ st,
                                                       TS* __restrict__ A, TS* __restrict__ Wt,
                                                       __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk, int wps,
                                                       double* __restrict__ zf, const PTask* __restrict__ tasks,
                                                       const int32_t* __restrict__ qoff, int nq,
-                                                      int32_t* __restrict__ ctr, int n_sys, long long wait_ticks) {
+                                                      int32_t* __restrict__ ctr, int n_sys, long long wait_ticks,
+                                                      int local) {
   __shared__ __align__(16) PersistLds lds;
   __shared__ int s_task, s_go;
   int32_t* done = ctr + nq;
   int32_t* giveup = ctr + nq + n_sys;
+  int32_t* owner = ctr + nq + n_sys + 1;
   const int t = threadIdx.x;
-  const int home = (int)(blockIdx.x % (unsigned)nq);
-  unsigned exhausted = 0;   // thread 0: queues found empty
+  const int me = local ? xcd_id() : 0;
+  const int home = local ? me % nq : (int)(blockIdx.x % (unsigned)nq);
+  unsigned exhausted = 0;   // thread 0: queues found empty (or owned by another XCD)
   for (;;) {
     if (t == 0) {
       int task = -1;
@@ -1206,6 +1234,20 @@ __global__ __launch_bounds__(256, 2) void k_chol_persist(const SysDesc* __restri
         for (int u = 0; u < nq && task < 0; ++u) {
           const int q = (home + u) % nq;
           if (exhausted & (1u << q)) continue;
+          if (local) {
+            int o = ld_agent(owner + q);
+            if (o == 0) {
+              int expect = 0;
+              o = __hip_atomic_compare_exchange_strong(owner + q, &expect, me + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT)
+                      ? me + 1
+                      : expect;
+            }
+            if (o != me + 1) {
+              exhausted |= 1u << q;
+              continue;
+            }
+          }
           const int x = __hip_atomic_fetch_add(&ctr[q], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           if (x < qoff[q + 1] - qoff[q]) task = qoff[q] + x;
           else exhausted |= 1u << q;
@@ -1233,7 +1275,7 @@ __global__ __launch_bounds__(256, 2) void k_chol_persist(const SysDesc* __restri
           }
         }
         if (go) {
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          if (!local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
           // a system found not positive definite: its later tasks only count
           if (ld_agent(&st[T.s].status) != 0) go = 2;
         }
@@ -1245,6 +1287,10 @@ __global__ __launch_bounds__(256, 2) void k_chol_persist(const SysDesc* __restri
     const int task = s_task, go = s_go;
     if (task < 0 || go == 0) break;
     const PTask T = tasks[task];
+    // drop this compute unit's L1 copies of what the earlier tasks wrote (a
+    // workgroup-scope invalidation leaves the L1 alone outside thread-group
+    // split mode, so the agent-scope one is taken; it keeps dirty L2 lines)
+    if (local && go == 1) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (go == 1) {
       const lds_ptr lp = (lds_ptr)&lds;
       if constexpr (PACKED) {
@@ -1271,9 +1317,15 @@ __global__ __launch_bounds__(256, 2) void k_chol_persist(const SysDesc* __restri
         }
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // this wave's stores, before the count
+    // every wave's stores have reached the L2 before the task counts as done
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    if (t == 0) __hip_atomic_fetch_add(done + T.s, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (t == 0) {
+      if (local)
+        __hip_atomic_fetch_add(done + T.s, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      else
+        __hip_atomic_fetch_add(done + T.s, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
@@ -1324,34 +1376,65 @@ int persist_grid(krr_ctx ctx) {
   return std::max(1, per_cu) * std::max(1, cus);
 }
 
-// Uploads the PPlan of these shapes unless it is the one on the device.
-void persist_upload(krr_ctx ctx, hipStream_t s, const std::vector<int>& T, const std::vector<int>& act,
-                    const std::vector<int>& Wp, bool packed, int tsize) {
+// Slot of the context's plan cache holding the PPlan of these shapes,
+// uploaded unless resident.  force_slot >= 0: upload into that slot (graph
+// replays re-install the plan their launch reads).  Replacing a slot's plan
+// waits for the context's queued work, which may still read it; inside a
+// graph capture that is an error (ESTATE), so only a free slot is taken there.
+int persist_upload(krr_ctx ctx, hipStream_t s, const std::vector<int>& T, const std::vector<int>& act,
+                   const std::vector<int>& Wp, bool packed, int tsize, int force_slot) {
   std::vector<int> key = T;
   key.insert(key.end(), act.begin(), act.end());
   key.insert(key.end(), Wp.begin(), Wp.end());
   key.push_back(packed ? 1 : 0);
   key.push_back(tsize);
   auto& pc = ctx->persist;
-  if (pc.key == key) return;
-  if (!pc.key.empty()) drain(ctx);   // an earlier upload may still read the staging buffer
+  constexpr int NS = krr_ctx_s::PersistCache::kSlots;
+  int slot = force_slot;
+  if (slot < 0) {
+    for (int i = 0; i < NS; ++i)
+      if (pc.slot[i].key == key) {
+        pc.slot[i].used = ++pc.clock;
+        return i;
+      }
+    slot = 0;
+    for (int i = 0; i < NS; ++i) {
+      if (pc.slot[i].key.empty()) {
+        slot = i;
+        break;
+      }
+      if (pc.slot[i].used < pc.slot[slot].used) slot = i;
+    }
+  } else if (pc.slot[slot].key == key) {
+    pc.slot[slot].used = ++pc.clock;
+    return slot;
+  }
+  auto& pl = pc.slot[slot];
+  if (!pl.key.empty()) {
+    if (ctx->capturing) fail(KRR_ESTATE, "persistent plan cache full inside a graph capture");
+    drain(ctx);   // queued work may still read this slot's plan or its staging buffer
+  }
   const PPlan P = build_plan(T, act, Wp, packed, NXCD);
-  pc.nq = P.nq;
-  pc.ntasks = (int)P.tasks.size();
   const size_t tb = P.tasks.size() * sizeof(PTask), qb = P.qoff.size() * sizeof(int32_t);
-  char* dev = (char*)ws_get(ctx, "persist_plan", std::max<size_t>(tb + qb + 256, 512));
-  void* h = pinned_named(ctx, "persist_plan", tb + qb + 256);
+  const std::string name = "persist_plan" + std::to_string(slot);
+  char* dev = (char*)ws_get(ctx, name, std::max<size_t>(tb + qb + 256, 512));
+  void* h = pinned_named(ctx, name, tb + qb + 256);
   std::memcpy(h, P.tasks.data(), tb);
   std::memcpy((char*)h + tb, P.qoff.data(), qb);
   KRR_HIP(hipMemcpyAsync(dev, h, tb + qb, hipMemcpyHostToDevice, s));
-  pc.tasks = dev;
-  pc.qoff_off = tb;
-  pc.key = key;
-  pc.T = T;
-  pc.act = act;
-  pc.wp = Wp;
-  pc.packed = packed ? 1 : 0;
-  pc.tsize = tsize;
+  if (ctx->capturing) pc.fresh.push_back(slot);
+  pl.key = key;
+  pl.tasks = dev;
+  pl.qoff_off = tb;
+  pl.nq = P.nq;
+  pl.ntasks = (int)P.tasks.size();
+  pl.T = T;
+  pl.act = act;
+  pl.wp = Wp;
+  pl.packed = packed ? 1 : 0;
+  pl.tsize = tsize;
+  pl.used = ++pc.clock;
+  return slot;
 }
 
 // The persistent factorisation of the systems at `level` (the PPlan is kept
@@ -1369,12 +1452,13 @@ void factor_persistent(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatu
     act[i] = hdesc[i].level == level ? 1 : 0;
     wp[i] = hdesc[i].wp;
   }
-  persist_upload(ctx, s, T, act, wp, packed, (int)sizeof(TS));
-  auto& pc = ctx->persist;
-  if (ctx->capturing) pc.in_capture = 1;
+  const int slot = persist_upload(ctx, s, T, act, wp, packed, (int)sizeof(TS), -1);
+  const auto& pc = ctx->persist.slot[slot];
+  if (ctx->capturing) ctx->persist.captured.push_back(slot);
   if (pc.ntasks == 0) return;
-  int32_t* ctr = (int32_t*)ws_get(ctx, "persist_ctr", (size_t)(pc.nq + n_sys + 1) * 4);
-  const int nctr = pc.nq + n_sys + 1;
+  const int nctr = persist_ctr_count(pc.nq, n_sys);
+  int32_t* ctr = (int32_t*)ws_get(ctx, "persist_ctr", (size_t)nctr * 4);
+  const int local = pc.nq == NXCD ? 1 : 0;
   hipLaunchKernelGGL(k_zero_ctr, dim3((unsigned)ceil_div(nctr, 256)), dim3(256), 0, s, ctr, nctr);
   check_launch(ctx, s, "zero_ctr");
   int khz = 0;
@@ -1387,12 +1471,12 @@ void factor_persistent(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatu
     if (packed) {
       const int grid = std::min(persist_grid<float, true>(ctx), (int)ceil_div(pc.ntasks, NXCD) * NXCD);
       hipLaunchKernelGGL((k_chol_persist<float, true>), dim3((unsigned)grid), dim3(256), 0, s, desc, st, (float*)A,
-                         (float*)Wt, Wpk, Pk, wps, zf, tasks, qoff, pc.nq, ctr, n_sys, ticks);
+                         (float*)Wt, Wpk, Pk, wps, zf, tasks, qoff, pc.nq, ctr, n_sys, ticks, local);
     } else {
       const int grid = std::min(persist_grid<TS, false>(ctx), (int)ceil_div(pc.ntasks, NXCD) * NXCD);
       hipLaunchKernelGGL((k_chol_persist<TS, false>), dim3((unsigned)grid), dim3(256), 0, s, desc, st, A, Wt,
                          (__bf16*)nullptr, (__bf16*)nullptr, Wp, (double*)nullptr, tasks, qoff, pc.nq, ctr, n_sys,
-                         ticks);
+                         ticks, local);
     }
     check_launch(ctx, s, "chol_persist");
   }
@@ -1571,21 +1655,25 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
 
 void persist_note_plan(krr_ctx ctx, krr_ctx_s::GraphEntry& e) {
   auto& pc = ctx->persist;
-  if (!pc.in_capture) return;
-  pc.in_capture = 0;
-  e.plan_key = pc.key;
-  e.plan_T = pc.T;
-  e.plan_act = pc.act;
-  e.plan_wp = pc.wp;
-  e.plan_packed = pc.packed;
-  e.plan_tsize = pc.tsize;
+  for (int sl : pc.captured) e.plans.emplace_back(sl, pc.slot[sl]);
+  pc.captured.clear();
+  pc.fresh.clear();
+}
+
+void persist_capture_aborted(krr_ctx ctx) {
+  auto& pc = ctx->persist;
+  for (int sl : pc.fresh) pc.slot[sl] = krr_ctx_s::PersistPlan{};
+  pc.fresh.clear();
+  pc.captured.clear();
 }
 
 void persist_restore_plan(krr_ctx ctx, hipStream_t s, const krr_ctx_s::GraphEntry& e) {
-  if (e.plan_key.empty() || ctx->persist.key == e.plan_key) return;
-  persist_upload(ctx, s, e.plan_T, e.plan_act, e.plan_wp, e.plan_packed != 0, e.plan_tsize);
-  if (ctx->persist.tasks == nullptr || ctx->persist.key != e.plan_key)
-    fail(KRR_ESTATE, "the persistent plan of a captured graph could not be restored");
+  for (const auto& [sl, pl] : e.plans) {
+    if (ctx->persist.slot[sl].key == pl.key) continue;
+    persist_upload(ctx, s, pl.T, pl.act, pl.wp, pl.packed != 0, pl.tsize, sl);
+    if (ctx->persist.slot[sl].tasks != pl.tasks)
+      fail(KRR_ESTATE, "the persistent plan of a captured graph could not be restored");
+  }
 }
 
 // Factor, in place, the systems of the batch whose descriptor carries

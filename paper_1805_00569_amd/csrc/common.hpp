@@ -173,14 +173,24 @@ struct krr_ctx_s {
   int force_wp = 0;              // > 0: every system takes this panel width (trial fits)
   std::map<std::pair<int, int>, int> tune;   // (precision, size class) -> panel width
   int64_t persist_wait_ms = 30000;   // longest wait of one task before it gives up
-  struct PersistCache {
-    std::vector<int> key;       // shapes the uploaded plan was built for
+  // Task plans of the persistent factorisation, uploaded once per set of
+  // shapes into one of a few workspace slots (a fit at several refinement
+  // levels, or graphs of several shapes, then find their plans resident).
+  struct PersistPlan {
+    std::vector<int> key;       // shapes the plan was built for (empty: free slot)
     void* tasks = nullptr;      // device: tasks, then the queue offsets
     size_t qoff_off = 0;
     int nq = 1, ntasks = 0;
     std::vector<int> T, act, wp;   // the plan's inputs (to upload it again for a graph replay)
     int packed = 0, tsize = 0;
-    int in_capture = 0;         // a persistent launch was recorded by the capture in progress
+    uint64_t used = 0;          // last use (least recently used slot is replaced)
+  };
+  struct PersistCache {
+    static constexpr int kSlots = 4;
+    PersistPlan slot[kSlots];
+    uint64_t clock = 0;
+    std::vector<int> captured;  // slots whose plans the capture in progress reads
+    std::vector<int> fresh;     // slots whose upload the capture in progress recorded
   } persist;
   std::map<std::string, std::pair<void*, size_t>> pinned_bufs;   // named pinned staging
   // HIP graphs of the device phases of fits and predictions (KRR_OPT_GRAPHS):
@@ -191,9 +201,7 @@ struct krr_ctx_s {
   uint64_t ws_epoch = 0;        // bumped whenever a workspace buffer moves
   struct GraphEntry {
     hipGraphExec_t exec = nullptr;
-    std::vector<int> plan_key;  // persistent plan the graph's launch reads
-    std::vector<int> plan_T, plan_act, plan_wp;
-    int plan_packed = 0, plan_tsize = 0;
+    std::vector<std::pair<int, PersistPlan>> plans;   // (slot, plan) of the graph's persistent launches
   };
   std::map<std::string, GraphEntry> graph_cache;
   int64_t graph_captures = 0, graph_replays = 0;
@@ -318,6 +326,8 @@ inline void* ws_or_arena(krr_ctx ctx, Arena* ar, const std::string& name, size_t
 // must be the one on the device when the graph is replayed.
 void persist_note_plan(krr_ctx ctx, krr_ctx_s::GraphEntry& e);
 void persist_restore_plan(krr_ctx ctx, hipStream_t s, const krr_ctx_s::GraphEntry& e);
+// Forgets the plans whose upload an abandoned capture recorded (never ran).
+void persist_capture_aborted(krr_ctx ctx);
 
 template <typename F>
 bool graph_run(krr_ctx ctx, hipStream_t s, const std::string& key0, F&& body) {
@@ -340,18 +350,39 @@ bool graph_run(krr_ctx ctx, hipStream_t s, const std::string& key0, F&& body) {
     body();
     return false;
   }
+  if (ctx->graph_seen[key] == 2) {   // its capture failed: direct launches from now on
+    body();
+    return false;
+  }
   krr_ctx_s::GraphEntry e;
   hipGraph_t g = nullptr;
   KRR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   ctx->capturing = 1;
+  bool redo = false;
   try {
     body();
+  } catch (const Error& err) {
+    ctx->capturing = 0;
+    hipGraph_t junk = nullptr;
+    (void)hipStreamEndCapture(s, &junk);
+    if (junk) (void)hipGraphDestroy(junk);
+    persist_capture_aborted(ctx);
+    // a step that cannot be captured (a wait, a workspace that must grow):
+    // nothing recorded has run, so the call runs directly instead
+    if (err.status != KRR_ESTATE) throw;
+    redo = true;
   } catch (...) {
     ctx->capturing = 0;
     hipGraph_t junk = nullptr;
     (void)hipStreamEndCapture(s, &junk);
     if (junk) (void)hipGraphDestroy(junk);
+    persist_capture_aborted(ctx);
     throw;
+  }
+  if (redo) {
+    ctx->graph_seen[key] = 2;
+    body();
+    return false;
   }
   ctx->capturing = 0;
   KRR_HIP(hipStreamEndCapture(s, &g));
@@ -365,6 +396,16 @@ bool graph_run(krr_ctx ctx, hipStream_t s, const std::string& key0, F&& body) {
   ctx->graph_captures += 1;
   return true;
 }
+
+// ---- lu.hip ----
+// Systems `which` (indices into the batch; hdesc: host descriptors) solved
+// by LU with partial pivoting in FP64 from the grouped points Xg (dtype) and
+// labels y (FP64, grouped order); alpha (padded, at each system's v_off) is
+// written.  Returns per listed system 0, or the 1-based column whose pivot
+// candidates were all zero (alpha of that system is then not written).
+std::vector<int32_t> lu_solve_systems(krr_ctx ctx, hipStream_t s, const std::vector<int>& which,
+                                      const SysDesc* hdesc, const void* Xg, int dtype, int d, const double* y,
+                                      double* alpha);
 
 // ---- fit.hip ----
 bool same_kernel_matrix(const krr_fit_params& a, const krr_fit_params& b);

@@ -649,6 +649,18 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
   KRR_HIP(hipMemcpyAsync(st_h, d_st, dn_bytes, hipMemcpyDeviceToHost, s));
   KRR_HIP(hipStreamSynchronize(s));
   check_gave_up(st_h, n_sys);
+  // systems Cholesky rejected, of settings that ask for it: Gaussian
+  // elimination (LU with partial pivoting) of the FP64 system
+  std::vector<int> lu_sys;
+  for (int sidx = 0; sidx < n_sys; ++sidx)
+    if (desc[sidx].T > 0 && st_h[sidx].status == KRR_ENOTSPD && params[desc[sidx].param].indefinite)
+      lu_sys.push_back(sidx);
+  std::vector<int32_t> lu_bad = lu_solve_systems(ctx, s, lu_sys, desc.data(), Xg, dtype, d, yg, alpha);
+  std::vector<int> solver(n_sys, 0);
+  for (size_t i = 0; i < lu_sys.size(); ++i) {
+    solver[lu_sys[i]] = 1;
+    if (lu_bad[i] == 0) st_h[lu_sys[i]].status = KRR_OK;
+  }
   for (int q = 0; q < n_params; ++q)
     for (int jp = 0; jp < p; ++jp) {
       const int sidx = q * p + jp;
@@ -661,12 +673,13 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
       I.failed_pivot = S.failed_pivot;
       I.refine_iters = S.refine_iters;
       I.fallback = fallback[sidx];
-      I.reserved = 0;
-      I.rel_residual = mixed ? S.rel_residual : -1.0;
+      I.solver = solver[sidx];
+      const bool chol = solver[sidx] == 0;
+      I.rel_residual = mixed && chol ? S.rel_residual : -1.0;
       I.kappa_est = S.kappa_l;
-      I.kappa_bound = mixed ? S.kappa_u : -1.0;
-      I.err_est = mixed ? S.err_est : -1.0;
-      if (mixed && S.status == 0 && !S.converged && desc[sidx].T > 0) I.status = KRR_ENOCONV;
+      I.kappa_bound = mixed && chol ? S.kappa_u : -1.0;
+      I.err_est = mixed && chol ? S.err_est : -1.0;
+      if (mixed && chol && S.status == 0 && !S.converged && desc[sidx].T > 0) I.status = KRR_ENOCONV;
     }
 
   if (use_graph && Xg != data->X)

@@ -482,7 +482,7 @@ krr_status krr_server_submit_fit(krr_server S, const float* X, const float* y, i
       (ar && !(std::isfinite(P.kernel_a) && std::isfinite(P.kernel_r))) ||
       (P.kernel == KRR_KERNEL_POLYNOMIAL && (P.kernel_degree < 1 || P.kernel_degree > 64)) ||
       (P.prec != KRR_PREC_FP64 && P.prec != KRR_PREC_FP32 && P.prec != KRR_PREC_MIXED) || P.max_refine < 0 ||
-      P.max_refine > 1000) {
+      P.max_refine > 1000 || (P.indefinite != 0 && P.indefinite != 1)) {
     set_error(S, "fit: bad settings");
     return KRR_EINVAL;
   }

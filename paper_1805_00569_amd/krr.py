@@ -40,13 +40,13 @@ class FitParams(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_double), ("lambda_", ctypes.c_double), ("kernel", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("refine_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
                 ("lambda_times_m", ctypes.c_int32), ("kernel_a", ctypes.c_double), ("kernel_r", ctypes.c_double),
-                ("kernel_degree", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("kernel_degree", ctypes.c_int32), ("indefinite", ctypes.c_int32)]
 
 
 class PartInfo(ctypes.Structure):
     _fields_ = [("partition", ctypes.c_int32), ("param", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("failed_pivot", ctypes.c_int32), ("refine_iters", ctypes.c_int32),
-                ("fallback", ctypes.c_int32), ("reserved", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("fallback", ctypes.c_int32), ("solver", ctypes.c_int32), ("rel_residual", ctypes.c_double),
                 ("kappa_est", ctypes.c_double), ("err_est", ctypes.c_double), ("kappa_bound", ctypes.c_double)]
 
 
@@ -159,11 +159,13 @@ class Params:
     kernel_a: float = 1.0      # polynomial / sigmoid: (a x^T y + r)^d, tanh(a x^T y + r)
     kernel_r: float = 1.0
     kernel_degree: int = 2
+    indefinite: bool = False   # solve systems Cholesky rejects by LU with partial pivoting
 
     def to_c(self):
         return FitParams(float(self.sigma), float(self.lam), KERNEL[self.kernel], PREC[self.prec],
                          float(self.refine_tol), int(self.max_refine), int(bool(self.lambda_times_m)),
-                         float(self.kernel_a), float(self.kernel_r), int(self.kernel_degree), 0)
+                         float(self.kernel_a), float(self.kernel_r), int(self.kernel_degree),
+                         int(bool(self.indefinite)))
 
 
 class Model:
@@ -292,10 +294,12 @@ class Context:
             mdl._m = sizes
         return models, infos, st
 
-    def predict(self, model, Xt, route="nearest", want_route=False):
+    def predict(self, model, Xt, route="nearest", want_route=False, out=None):
+        """Predictions FP64 (k, or k x p for "all"), into `out` when given."""
         k = Xt.shape[0]
         p = len(model._m)
-        out = torch.empty((k, p) if route == "all" else (k,), dtype=torch.float64, device=self.device)
+        if out is None:
+            out = torch.empty((k, p) if route == "all" else (k,), dtype=torch.float64, device=self.device)
         r = torch.empty(k, dtype=torch.int32, device=self.device) if want_route else None
         self._check(self.lib.krr_predict(self.h, _stream(self.device), model.handle, _ptr(Xt), _dtype_code(Xt), k,
                                          ROUTE[route], _ptr(out), _ptr(r)))

@@ -2,15 +2,18 @@
 // (paper_1805_00569_amd/csrc/persist_plan.hpp): workers take tasks from the
 // queues in order (their own queue first, then the others), wait until their
 // system has finished `need` tasks, run for a random time and count the task
-// done.  Checks, for ragged batches: every task is taken once, no worker ever
-// waits forever (the simulation would stall), a task starts only after every
-// task of its system's earlier stages, and each system's tasks cover its
-// factorisation exactly (every tile below the diagonal solved once, every
-// diagonal block factored once, every trailing tile updated once per panel).
+// done.  With one queue per XCD, worker w runs on XCD w % X (X XCDs hold
+// workers, drawn from the seed) and a queue is served only by the XCD that
+// claimed it first.  Checks, for ragged batches: every task is taken once,
+// no worker ever waits forever (the simulation would stall), a task starts
+// only after every task of its system's earlier stages, every system's
+// tasks run on one XCD, and each system's tasks cover its factorisation
+// exactly (every tile below the diagonal solved once, every diagonal block
+// factored once, every trailing tile updated once per panel).
 //
 // Usage: persist_sim <seed> <workers> <packed 0|1> <Wp> <T_0> <T_1> ...
 // (Wp = 0: every system draws its own panel width in [1, 24])
-// Prints "OK <tasks> <makespan>" or "FAIL <reason>".
+// Prints "OK <tasks> <makespan> <queues>" or "FAIL <reason>".
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -148,14 +151,27 @@ int main(int argc, char** argv) {
     bool finished = false;
   };
   std::vector<Wk> wk(W);
+  const bool local = P.nq == 8;
+  const int nxcd = local ? 1 + (int)(seed % 8u) : 1;   // XCDs that hold workers
+  std::vector<int> owner(P.nq, -1), sys_xcd(n, -1);
   auto take = [&](int w) {
-    const int home = w % P.nq;
+    const int xcd = w % nxcd;
+    const int home = local ? xcd % P.nq : w % P.nq;
     for (int u = 0; u < P.nq; ++u) {
       const int q = (home + u) % P.nq;
+      if (local) {
+        if (owner[q] < 0) owner[q] = xcd;   // claim
+        if (owner[q] != xcd) continue;
+      }
       if (head[q] < P.qoff[q + 1] - P.qoff[q]) {
         const int x = P.qoff[q] + head[q]++;
         if (taken[x]) return -2;
         taken[x] = 1;
+        if (local) {
+          const int sy = P.tasks[x].s;
+          if (sys_xcd[sy] >= 0 && sys_xcd[sy] != xcd) return -3;
+          sys_xcd[sy] = xcd;
+        }
         return x;
       }
     }
@@ -183,6 +199,7 @@ int main(int argc, char** argv) {
       if (k.task < 0) {
         const int x = take(w);
         if (x == -2) return fail("double_take", w);
+        if (x == -3) return fail("system_on_two_xcds", w);
         if (x < 0) {
           k.finished = true;
           continue;

@@ -222,6 +222,57 @@ def test_sigmoid_not_spd_reports_pivot(ctx, dev):
         assert e.value.status == krr.KRR_EINVAL
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_sigmoid_indefinite_systems_solved_by_lu(ctx, dev, prec):
+    """Sigmoid kernel tanh(0.1 x^T y - 0.1) with lambda = 1: every one of the
+    four ragged partitions (473..740 points) has K + lambda I indefinite
+    (19..28 negative eigenvalues, condition numbers 3e3..2e4).  With
+    indefinite = 1 Cholesky rejects each and LU with partial pivoting solves
+    it (solver 1, status OK, failed_pivot = the oracle's Cholesky pivot),
+    alpha against the oracle's LU; the same setting without the flag reports
+    KRR_ENOTSPD, and a Gaussian setting in the batch keeps Cholesky."""
+    w = datagen.small(71, 2400, 6, k=100, p=4, comps=4, dtype=np.float64 if prec == "fp64" else np.float32,
+                      spread=1.0)
+    g = np.random.default_rng(1)
+    Cc = w.X[g.choice(w.n, 4, replace=False)].astype(np.float64)
+    print(f"sigmoid indefinite -> LU ({prec})", flush=True)
+    X, y = _t(w.X, dev), _t(w.y.astype(w.X.dtype), dev)
+    C, a, _ = ctx.partition(X, 4, "given", centroids=_t(Cc, dev))
+    sig = dict(kernel="sigmoid", kernel_a=0.1, kernel_r=-0.1, lam=1.0, prec=prec, refine_tol=1e-10, max_refine=30)
+    params = [krr.Params(indefinite=True, **sig), krr.Params(sigma=1.0, lam=1e-2, prec=prec, refine_tol=1e-10,
+                                                             max_refine=30, indefinite=True)]
+    models, info, st = ctx.fit(X, y, a, C, 4, params)
+    for r in info:
+        print(f"  setting {r['param']} part {r['partition']} m {r['m']}: status {r['status']} solver {r['solver']} "
+              f"pivot {r['failed_pivot']}", flush=True)
+    assert st == 0
+    a_np = a.cpu().numpy()
+    om = O.fit(w.X, w.y.astype(w.X.dtype), a_np, Cc, 4, 1.0, 1.0, ("sigmoid", 0.1, -0.1), indefinite=True)
+    og = O.fit(w.X, w.y.astype(w.X.dtype), a_np, Cc, 4, 1.0, 1e-2)
+    for j in range(4):
+        r = info[j]
+        assert om.infos[j]["solver"] == "lu"
+        # the pivot that rejects the system: FP64 Cholesky's exactly; FP32 updates may meet it elsewhere
+        piv_ok = r["failed_pivot"] == om.infos[j]["pivot"] if prec == "fp64" else r["failed_pivot"] > 0
+        assert r["solver"] == 1 and r["status"] == 0 and piv_ok, r
+        assert r["rel_residual"] == -1.0 and r["err_est"] == -1.0
+        assert ew(models[0].alpha(j).cpu().numpy(), om.alphas[j]) < 1e-9, j
+        assert info[4 + j]["solver"] == 0 and info[4 + j]["status"] == 0
+        assert ew(models[1].alpha(j).cpu().numpy(), og.alphas[j]) < (1e-10 if prec == "fp64" else 1e-6), j
+    yhat = ctx.predict(models[0], _t(w.Xt, dev)).cpu().numpy()
+    yo, _ = O.predict(om, w.Xt)
+    assert pred_ew(yhat, yo, w.yt) < 1e-9
+    for m in models:
+        m.free()
+    m2, info2, st2 = ctx.fit(X, y, a, C, 4, [krr.Params(**sig)])
+    assert st2 == krr.KRR_ENOTSPD
+    assert all(r["status"] == krr.KRR_ENOTSPD and r["solver"] == 0 and r["failed_pivot"] > 0 for r in info2)
+    if prec == "fp64":
+        assert [r["failed_pivot"] for r in info2] == [om.infos[j]["pivot"] for j in range(4)]
+    for m in m2:
+        m.free()
+
+
 def test_batch_invariance_serial_equals_batched(ctx, dev):
     """The plain per-system launch sequence gives bitwise the same alpha as
     the batched one."""

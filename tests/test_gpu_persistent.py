@@ -1,6 +1,6 @@
 """The persistent factorisation (one launch for every stage of every system,
-device task queues, KRR_OPT_PERSISTENT = 1, the default) against the
-multi-launch sequence (KRR_OPT_PERSISTENT = 0): the same tile bodies run in
+device task queues, KRR_OPT_PERSISTENT = 1) against the multi-launch
+sequence (KRR_OPT_PERSISTENT = 0, the default): the same tile bodies run in
 the same order inside each system, so alpha, the refinement record and the
 predictions must be identical bit for bit -- for balanced and ragged batches,
 in mixed precision (BF16 packed path and its FP32-update fallback), FP32 and
@@ -29,7 +29,7 @@ def _fit(ctx, X, y, a, C, p, params, persistent):
     try:
         models, info, st = ctx.fit(X, y, a, C, p, params)
     finally:
-        ctx.set_option(krr.OPT_PERSISTENT, 1)
+        ctx.set_option(krr.OPT_PERSISTENT, 0)
     alphas = [[m.alpha(j).cpu().numpy() for j in range(p)] for m in models]
     return models, info, st, alphas
 

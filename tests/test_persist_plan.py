@@ -1,9 +1,10 @@
 """CPU checks of the persistent factorisation's task plan and queue protocol
 (paper_1805_00569_amd/csrc/persist_plan.hpp), by an event simulation in
 tests/persist_sim.cpp: every task taken once, no deadlock under random task
-times with own-queue-first dispatch and stealing, a task starts only after
-its system's earlier stages, and the tasks of each system cover its blocked
-factorisation exactly.  Batches: the balanced workload (96 systems of 64
+times with own-queue-first dispatch, a task starts only after its system's
+earlier stages, every system runs on the one XCD that owns its queue (also
+when only some XCDs hold workers and the others' queues are claimed), and
+the tasks of each system cover its blocked factorisation exactly.  Batches: the balanced workload (96 systems of 64
 tile rows), ragged K-means-sized batches (sizes up to 219 tile rows, i.e.
 m = 14,000), one very large system, and tiny or degenerate shapes."""
 import os
