@@ -82,6 +82,8 @@ struct SysDesc {
   int64_t pk_off;      // element offset of its BF16 panel-pack slot (mixed precision)
   int64_t k_off;       // mixed precision: element offset of the FP64 kernel tiles (without the
                        // shift) shared by the settings of this partition with the same kernel and sigma
+  int32_t g_sys;       // the system of this partition in the first setting that shares its kernel tiles
+  int32_t pad_;
 };
 
 // Device-side status of one system.

@@ -433,6 +433,8 @@ void run_fit(krr_ctx ctx, hipStream_t s, const void* X, const void* y, int dtype
       D.pk_off = pk_tot;
       pk_tot += (prec == KRR_PREC_MIXED) ? pack_slot_elems(D.T, D.wp) : 0;
       D.k_off = k_off[(int64_t)grp_of[q] * p + jp];
+      D.g_sys = grp_first[grp_of[q]] * p + jp;
+      D.pad_ = 0;
       a_tot += tri(D.T) * TILE;
       w_tot += (int64_t)D.T * TILE;
       v_tot += (int64_t)D.T * NB;

@@ -342,21 +342,25 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_group_scatter(const int32_t* __
 // feature) over the members in increasing point order (the stable grouping
 // perm), one rounding per addition; an empty partition keeps its centre.
 // Workgroup (j, slice) = (blockIdx.x / nsl, blockIdx.x % nsl) owns features
-// [64 slice, 64 slice + 64).  Chunks of MS_CH member rows are staged in LDS
-// (double-buffered; all four waves load, lane = feature, so each row's
-// features are one coalesced load), and wave 0 adds them in order, lane f
-// carrying feature f's sum: the additions of a chunk overlap the loads of
-// the next.  The member indices of chunk c + 2 are fetched while chunk c is
-// summed.  Lloyd passes: `skip` is this pass's "fixed point reached" flag;
-// workgroup 0 writes the next pass's flag (set when this pass was skipped or
-// changed no assignment), so no workgroup of a launch reads a flag that the
-// same launch writes.  CT (nullable) receives the centres transposed (d x p).
+// [MS_W slice, MS_W slice + MS_W): narrow slices give p * ceil(d / MS_W)
+// workgroups, so that many running sums advance at once.  Chunks of CH
+// member rows are staged in LDS (double-buffered; all threads load, 16
+// rows of MS_W features per load instruction), and lanes 0 .. MS_W - 1 of
+// wave 0 add them in order, lane f carrying feature f's sum: the additions
+// of a chunk overlap the loads of the next.  The member indices of chunk
+// c + 2 are fetched while chunk c is summed.  Lloyd passes: `skip` is this
+// pass's "fixed point reached" flag; workgroup 0 writes the next pass's flag
+// (set when this pass was skipped or changed no assignment), so no
+// workgroup of a launch reads a flag that the same launch writes.  CT
+// (nullable) receives the centres transposed (d x p).
 // ---------------------------------------------------------------------------
 constexpr int MS_THREADS = 256;
+constexpr int MS_W = 16;                         // features per workgroup
+constexpr int MS_RPL = MS_THREADS / MS_W;        // rows per load instruction of the workgroup
 
 template <typename TX>
 struct MeansChunk {
-  static constexpr int CH = sizeof(TX) == 4 ? 256 : 128;   // member rows per staged chunk (64 KiB)
+  static constexpr int CH = sizeof(TX) == 4 ? 1024 : 512;   // member rows per staged chunk (64 KiB)
 };
 
 template <typename TX>
@@ -368,19 +372,19 @@ __global__ __launch_bounds__(MS_THREADS) void k_means_seq(const TX* __restrict__
                                                            const int32_t* __restrict__ delta,
                                                            int32_t* __restrict__ done_next) {
   constexpr int CH = MeansChunk<TX>::CH;
-  constexpr int PER = CH * 64 / MS_THREADS;   // staged elements per thread and chunk
+  constexpr int PER = CH / MS_RPL;   // staged elements per thread and chunk
   const int skipped = (skip != nullptr) ? *skip : 0;
   if (done_next != nullptr && blockIdx.x == 0 && threadIdx.x == 0)
     *done_next = (skipped || *delta == 0) ? 1 : 0;
   if (skipped) return;
-  const int j = blockIdx.x / nsl, f0 = (blockIdx.x - j * nsl) * 64;
+  const int j = blockIdx.x / nsl, f0 = (blockIdx.x - j * nsl) * MS_W;
   const int64_t base = offsets[j];
   const int64_t cnt = offsets[j + 1] - base;
   if (cnt == 0) return;
-  __shared__ __align__(16) TX sX[2][CH * 64];
+  __shared__ __align__(16) TX sX[2][CH * MS_W];
   __shared__ int32_t sP[2][CH];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int fl = min(f0 + lane, d - 1);            // clamped feature: lanes past d load a valid value, never summed
+  const int t = threadIdx.x, fl = t % MS_W, rr = t / MS_W, w = t >> 6, lane = t & 63;
+  const int fc = min(f0 + fl, d - 1);   // clamped feature: lanes past d load a valid value, never summed
   const int64_t nch = (cnt + CH - 1) / CH;
   // member index of chunk row r (clamped to the last member: in range, never summed)
   auto member = [&](int64_t c, int r) { return perm[base + min<int64_t>(c * CH + r, cnt - 1)]; };
@@ -389,10 +393,10 @@ __global__ __launch_bounds__(MS_THREADS) void k_means_seq(const TX* __restrict__
   {
     TX v[PER];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) v[u] = X[(int64_t)sP[0][w + 4 * u] * d + fl];
+    for (int u = 0; u < PER; ++u) v[u] = X[(int64_t)sP[0][rr + MS_RPL * u] * d + fc];
     for (int r = t; r < CH; r += MS_THREADS) sP[1][r] = member(min<int64_t>(1, nch - 1), r);
 #pragma unroll
-    for (int u = 0; u < PER; ++u) sX[0][(w + 4 * u) * 64 + lane] = v[u];
+    for (int u = 0; u < PER; ++u) sX[0][(rr + MS_RPL * u) * MS_W + fl] = v[u];
   }
   __syncthreads();
   double acc = 0.0;
@@ -400,38 +404,36 @@ __global__ __launch_bounds__(MS_THREADS) void k_means_seq(const TX* __restrict__
     const int cur = (int)(c & 1), nxt = cur ^ 1;
     const bool more = c + 1 < nch;
     TX v[PER];
-    int32_t pn[CH / MS_THREADS + 1];
+    int32_t pn[CH / MS_THREADS];
     if (more) {
 #pragma unroll
-      for (int u = 0; u < PER; ++u) v[u] = X[(int64_t)sP[nxt][w + 4 * u] * d + fl];
+      for (int u = 0; u < PER; ++u) v[u] = X[(int64_t)sP[nxt][rr + MS_RPL * u] * d + fc];
 #pragma unroll
-      for (int q = 0; q * MS_THREADS < CH; ++q)
-        if (t + q * MS_THREADS < CH) pn[q] = member(min<int64_t>(c + 2, nch - 1), t + q * MS_THREADS);
+      for (int q = 0; q < CH / MS_THREADS; ++q) pn[q] = member(min<int64_t>(c + 2, nch - 1), t + q * MS_THREADS);
     }
-    if (w == 0) {
+    if (w == 0 && lane < MS_W) {
       const int nr = (int)min<int64_t>(CH, cnt - c * CH);
       const TX* col = &sX[cur][lane];
       int r = 0;
       for (; r + 16 <= nr; r += 16) {   // 16 LDS loads, then 16 ordered adds
         double x[16];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) x[u] = (double)col[(r + u) * 64];
+        for (int u = 0; u < 16; ++u) x[u] = (double)col[(r + u) * MS_W];
 #pragma unroll
         for (int u = 0; u < 16; ++u) acc = add_sep(acc, x[u]);
       }
-      for (; r < nr; ++r) acc = add_sep(acc, (double)col[r * 64]);
+      for (; r < nr; ++r) acc = add_sep(acc, (double)col[r * MS_W]);
     }
     if (more) {
       // sX[nxt] and sP[cur] were last read before the previous barrier
 #pragma unroll
-      for (int u = 0; u < PER; ++u) sX[nxt][(w + 4 * u) * 64 + lane] = v[u];
+      for (int u = 0; u < PER; ++u) sX[nxt][(rr + MS_RPL * u) * MS_W + fl] = v[u];
 #pragma unroll
-      for (int q = 0; q * MS_THREADS < CH; ++q)
-        if (t + q * MS_THREADS < CH) sP[cur][t + q * MS_THREADS] = pn[q];
+      for (int q = 0; q < CH / MS_THREADS; ++q) sP[cur][t + q * MS_THREADS] = pn[q];
     }
     __syncthreads();
   }
-  if (w == 0 && f0 + lane < d) {
+  if (w == 0 && lane < MS_W && f0 + lane < d) {
     const double val = acc / (double)cnt;
     C[(int64_t)j * d + f0 + lane] = val;
     if (CT != nullptr) CT[(int64_t)(f0 + lane) * p + j] = val;
@@ -1020,7 +1022,7 @@ template <typename TX>
 void means_t(krr_ctx ctx, hipStream_t s, const TX* X, int d, const int32_t* perm, const int64_t* offsets,
              double* C, double* CT, int p, const int32_t* skip, const int32_t* delta, int32_t* done_next) {
   KernelTimer kt(ctx, s, "lloyd_means", 0.0, 0);
-  const int nsl = (int)ceil_div(d, 64);
+  const int nsl = (int)ceil_div(d, MS_W);
   hipLaunchKernelGGL((k_means_seq<TX>), dim3((unsigned)(p * nsl)), dim3(MS_THREADS), 0, s, X, d, nsl, perm, offsets,
                      p, C, CT, skip, delta, done_next);
   check_launch(ctx, s, "means");

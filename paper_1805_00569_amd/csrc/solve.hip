@@ -453,89 +453,84 @@ __global__ __launch_bounds__(256) void k_resid_tiles(const SysDesc* __restrict__
     K[l][3] = u1.y;
   }
   const bool diag_tile = ii == jj;
+  // partials of |K| times ones (row sums of |K| for Gershgorin's bounds):
+  // the shift only moves the diagonal, so they are formed once for the
+  // settings that share K, while any of them has no kappa bound yet, into
+  // the slot of the group's first system
+  bool need_abs = false;
+  if (Pabs != nullptr)
+    for (int q2 = q; q2 >= 0 && !need_abs; q2 = grp_next[q2]) need_abs = st[q2 * p + j].kappa_u < 0.0;
+  if (need_abs) {   // uniform over the workgroup
+    double* Ab = Pabs + p_off[q * p + j];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double acc = 0.0;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) acc += fabs(K[l][k]);
+      for (int off = 1; off < 16; off <<= 1) acc += __shfl_xor(acc, off, 64);
+      if (cbk == 0) Ab[((int64_t)ii * D0.T + jj) * NB + 4 * rbk + k] = acc;
+    }
+    if (!diag_tile) {
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc += fabs(K[l][k]);
+        acc += __shfl_xor(acc, 16, 64);
+        acc += __shfl_xor(acc, 32, 64);
+        if ((t & 63) < 16) scol[w][4 * cbk + l] = acc;
+      }
+      __syncthreads();
+      if (t < NB)
+        Ab[((int64_t)jj * D0.T + ii) * NB + t] = (scol[0][t] + scol[1][t]) + (scol[2][t] + scol[3][t]);
+      __syncthreads();
+    }
+  }
   for (; q >= 0; q = grp_next[q]) {
     const int s = q * p + j;
-    // the |A| partials are formed once per system (while its kappa bound is
-    // not formed), whatever its status; the residual only for the systems
-    // still refining
-    const bool need_abs = Pabs != nullptr && st[s].kappa_u < 0.0;
-    const bool do_res = !skip_system(st[s], 1);
-    if (!need_abs && !do_res) continue;   // uniform over the workgroup
+    if (skip_system(st[s], 1)) continue;   // uniform over the workgroup: the residual only for the systems still refining
     const SysDesc D = desc[s];
-    if (do_res) {
-      double* Pb = P + p_off[s];
-      const double* aj = alpha + D.v_off + jj * NB + 4 * cbk;
-      double av[4];
+    double* Pb = P + p_off[s];
+    const double* aj = alpha + D.v_off + jj * NB + 4 * cbk;
+    double av[4];
 #pragma unroll
-      for (int l = 0; l < 4; ++l) av[l] = aj[l];
-      // rows: (K + lambda I)(i,j) alpha_j
-      double rs[4];
+    for (int l = 0; l < 4; ++l) av[l] = aj[l];
+    // rows: (K + lambda I)(i,j) alpha_j
+    double rs[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        double acc = 0.0;
+    for (int k = 0; k < 4; ++k) {
+      double acc = 0.0;
 #pragma unroll
-        for (int l = 0; l < 4; ++l) {
-          double kv = K[l][k];
-          if (diag_tile && rbk == cbk && k == l && ii * NB + 4 * rbk + k < D.m) kv += D.lambda;
-          acc = fma(kv, av[l], acc);
-        }
-        for (int off = 1; off < 16; off <<= 1) acc += __shfl_xor(acc, off, 64);
-        rs[k] = acc;
+      for (int l = 0; l < 4; ++l) {
+        double kv = K[l][k];
+        if (diag_tile && rbk == cbk && k == l && ii * NB + 4 * rbk + k < D.m) kv += D.lambda;
+        acc = fma(kv, av[l], acc);
       }
-      if (cbk == 0) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) Pb[((int64_t)ii * D.T + jj) * NB + 4 * rbk + k] = rs[k];
-      }
-      if (!diag_tile) {   // columns: K(i,j)^T alpha_i (no shift off the diagonal)
-        const double* ai = alpha + D.v_off + ii * NB + 4 * rbk;
-        double bv[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) bv[k] = ai[k];
-#pragma unroll
-        for (int l = 0; l < 4; ++l) {
-          double acc = 0.0;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) acc = fma(K[l][k], bv[k], acc);
-          acc += __shfl_xor(acc, 16, 64);
-          acc += __shfl_xor(acc, 32, 64);
-          if ((t & 63) < 16) scol[w][4 * cbk + l] = acc;
-        }
-        __syncthreads();
-        if (t < NB)
-          Pb[((int64_t)jj * D.T + ii) * NB + t] = (scol[0][t] + scol[1][t]) + (scol[2][t] + scol[3][t]);
-        __syncthreads();
-      }
+      for (int off = 1; off < 16; off <<= 1) acc += __shfl_xor(acc, off, 64);
+      rs[k] = acc;
     }
-    if (need_abs) {
-      // the same partials of |A| times ones: row sums of |A| for Gershgorin's bounds
-      double* Ab = Pabs + p_off[s];
+    if (cbk == 0) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < 4; ++k) Pb[((int64_t)ii * D.T + jj) * NB + 4 * rbk + k] = rs[k];
+    }
+    if (!diag_tile) {   // columns: K(i,j)^T alpha_i (no shift off the diagonal)
+      const double* ai = alpha + D.v_off + ii * NB + 4 * rbk;
+      double bv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) bv[k] = ai[k];
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
         double acc = 0.0;
 #pragma unroll
-        for (int l = 0; l < 4; ++l) {
-          double kv = K[l][k];
-          if (diag_tile && rbk == cbk && k == l && ii * NB + 4 * rbk + k < D.m) kv += D.lambda;
-          acc += fabs(kv);
-        }
-        for (int off = 1; off < 16; off <<= 1) acc += __shfl_xor(acc, off, 64);
-        if (cbk == 0) Ab[((int64_t)ii * D.T + jj) * NB + 4 * rbk + k] = acc;
+        for (int k = 0; k < 4; ++k) acc = fma(K[l][k], bv[k], acc);
+        acc += __shfl_xor(acc, 16, 64);
+        acc += __shfl_xor(acc, 32, 64);
+        if ((t & 63) < 16) scol[w][4 * cbk + l] = acc;
       }
-      if (!diag_tile) {
-#pragma unroll
-        for (int l = 0; l < 4; ++l) {
-          double acc = 0.0;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) acc += fabs(K[l][k]);
-          acc += __shfl_xor(acc, 16, 64);
-          acc += __shfl_xor(acc, 32, 64);
-          if ((t & 63) < 16) scol[w][4 * cbk + l] = acc;
-        }
-        __syncthreads();
-        if (t < NB)
-          Ab[((int64_t)jj * D.T + ii) * NB + t] = (scol[0][t] + scol[1][t]) + (scol[2][t] + scol[3][t]);
-        __syncthreads();
-      }
+      __syncthreads();
+      if (t < NB)
+        Pb[((int64_t)jj * D.T + ii) * NB + t] = (scol[0][t] + scol[1][t]) + (scol[2][t] + scol[3][t]);
+      __syncthreads();
     }
   }
 }
@@ -574,10 +569,13 @@ __global__ __launch_bounds__(64) void k_resid_reduce(const SysDesc* __restrict__
     }
   }
   if (need_abs) {
-    const double* Ab = Pabs + p_off[s] + (int64_t)i * D.T * NB;
-    double sa = 0.0;
-    for (int j = 0; j < D.T; ++j) sa += Ab[j * NB + lane];
-    const double aii = K64[D.k_off + tile_index(i, i) * TILE + lane * NB + lane] + D.lambda;
+    // row sums of |K| of the settings sharing K (the group's first system), with the diagonal moved by the shift
+    const double* Ab = Pabs + p_off[D.g_sys] + (int64_t)i * D.T * NB;
+    double sk = 0.0;
+    for (int j = 0; j < D.T; ++j) sk += Ab[j * NB + lane];
+    const double kii = K64[D.k_off + tile_index(i, i) * TILE + lane * NB + lane];
+    const double aii = kii + D.lambda;
+    const double sa = sk - fabs(kii) + fabs(aii);
     const bool in = i * NB + lane < D.m;
     double lo = in ? 2.0 * aii - sa : INFINITY, hi = in ? sa : 0.0;
     for (int off = 32; off > 0; off >>= 1) {
