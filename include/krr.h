@@ -194,11 +194,17 @@ typedef enum {
                                (device-side early exit), any further ones outside.  Results
                                are identical to 0 (default), which launches directly.
                                Setting the option drops the captured graphs */
-  KRR_OPT_AUTOTUNE = 7      /* 1 (default): every system takes the panel width krr_autotune
+  KRR_OPT_AUTOTUNE = 7,     /* 1 (default): every system takes the panel width krr_autotune
                                recorded for its precision and size class (the default width
                                where none is recorded); a batch whose systems then differ in
                                width is factored by the persistent launch; 0: every system
                                takes KRR_OPT_PANEL_TILES */
+  KRR_OPT_FACTOR_STREAMS = 8 /* 1..4 (default 2): the launch-sequence factorisation splits the
+                               batch into this many groups of consecutive systems (of about
+                               equal work, at least 8 systems each) and factors them at the
+                               same time on as many streams, so that one group's
+                               latency-bound launches leave room for the others'; results are
+                               identical for every value */
 } krr_option;
 
 /* ---- autotuning (Cholesky panel width) ------------------------------------

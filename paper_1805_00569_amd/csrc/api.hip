@@ -288,6 +288,20 @@ krr_status krr_create(int device, size_t hbm_budget_bytes, krr_ctx* out) {
   c->device = device;
   c->budget = hbm_budget_bytes;
   tune_load(c);
+  {
+    DeviceGuard g(device);
+    bool ok = true;
+    for (auto& st : c->side) ok = ok && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+    for (auto& ev : c->side_ev) ok = ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      for (auto ev : c->side_ev)
+        if (ev) (void)hipEventDestroy(ev);
+      for (auto st : c->side)
+        if (st) (void)hipStreamDestroy(st);
+      delete c;
+      return KRR_EDEVICE;
+    }
+  }
   *out = c;
   return KRR_OK;
 }
@@ -319,6 +333,10 @@ krr_status krr_destroy(krr_ctx ctx) {
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   for (auto& kv : ctx->pinned_bufs)
     if (kv.second.first) (void)hipHostFree(kv.second.first);
+  for (auto ev : ctx->side_ev)
+    if (ev) (void)hipEventDestroy(ev);
+  for (auto st : ctx->side)
+    if (st) (void)hipStreamDestroy(st);
   delete ctx;
   return KRR_OK;
 }
@@ -340,6 +358,10 @@ krr_status krr_set_option(krr_ctx ctx, int32_t option, int64_t value) {
         break;
       case KRR_OPT_PERSISTENT:
         ctx->persistent = value ? 1 : 0;
+        break;
+      case KRR_OPT_FACTOR_STREAMS:
+        KRR_REQUIRE(value >= 1 && value <= krr_ctx_s::kMaxFactorStreams, "factor streams must be 1..4");
+        ctx->factor_streams = (int)value;
         break;
       case KRR_OPT_AUTOTUNE:
         ctx->autotune = value ? 1 : 0;

@@ -1485,9 +1485,11 @@ void factor_persistent(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatu
   check_launch(ctx, s, "persist_check");
 }
 
+// grp: -1 for a whole batch; >= 0 for one group of systems of a batch split
+// over streams (the call then takes neither the persistent path nor a split).
 template <typename TS>
 void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, int n_sys, int Tmax, TS* A, TS* Wt,
-              bool bf16, int Wp, int level, const SysDesc* hdesc, __bf16* Pk, double* zf) {
+              bool bf16, int Wp, int level, const SysDesc* hdesc, __bf16* Pk, double* zf, int grp = -1) {
   // algorithmic flops of each launch (timing only), from the real sizes m
   auto each = [&](auto&& f) {
     double tot = 0.0;
@@ -1531,7 +1533,7 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
     if (uniform < 0) uniform = hdesc[i].wp;
     else if (uniform != hdesc[i].wp) uniform = 0;
   }
-  if (hdesc != nullptr && (packed || !bf16) &&
+  if (grp < 0 && hdesc != nullptr && (packed || !bf16) &&
       ((ctx->persistent && plan_tasks() <= PERSIST_MAX_TASKS) || uniform == 0)) {
     // one launch: m^3/3 per system credited; bytes: read and write the lower triangle once
     const double fl = each([](double m) { return m * m * m / 3.0; });
@@ -1544,6 +1546,49 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
     return;
   }
   if (uniform > 0) Wp = uniform;
+  // Groups of consecutive systems of about equal work (m^3), at least NXCD
+  // systems each, factored at the same time on the call's stream and the
+  // context's side streams: one group's launches that are bound by the
+  // latency of the diagonal chain leave CUs idle, which the other groups'
+  // launches fill.  Each system's arithmetic is unchanged.
+  if (grp < 0 && hdesc != nullptr && ctx->factor_streams > 1) {
+    std::vector<double> w(n_sys, 0.0);
+    double tot = 0.0;
+    int n_act = 0;
+    for (int i = 0; i < n_sys; ++i)
+      if (hdesc[i].level == level && hdesc[i].T > 0) {
+        w[i] = std::pow((double)hdesc[i].T, 3.0);
+        tot += w[i];
+        ++n_act;
+      }
+    const int G = std::min(ctx->factor_streams, n_act / NXCD);
+    if (G > 1) {
+      std::vector<int> cut{0};
+      double acc = 0.0;
+      for (int i = 0; i < n_sys && (int)cut.size() < G; ++i) {
+        acc += w[i];
+        if (acc >= tot * (double)cut.size() / G && i + 1 < n_sys) cut.push_back(i + 1);
+      }
+      cut.push_back(n_sys);
+      const int ng = (int)cut.size() - 1;
+      KRR_HIP(hipEventRecord(ctx->side_ev[0], s));
+      for (int g = 1; g < ng; ++g) KRR_HIP(hipStreamWaitEvent(ctx->side[g - 1], ctx->side_ev[0], 0));
+      for (int g = 0; g < ng; ++g) {
+        const int lo = cut[g], cnt = cut[g + 1] - cut[g];
+        int tg = 0;
+        for (int i = lo; i < lo + cnt; ++i)
+          if (hdesc[i].level == level) tg = std::max(tg, (int)hdesc[i].T);
+        if (tg == 0) continue;
+        factor_t<TS>(ctx, g == 0 ? s : ctx->side[g - 1], desc + lo, st + lo, cnt, tg, A, Wt, bf16, Wp, level,
+                     hdesc + lo, Pk, zf, g);
+      }
+      for (int g = 1; g < ng; ++g) {
+        KRR_HIP(hipEventRecord(ctx->side_ev[g], ctx->side[g - 1]));
+        KRR_HIP(hipStreamWaitEvent(s, ctx->side_ev[g], 0));
+      }
+      return;
+    }
+  }
   auto diag_trsm = [&](int k) {
     {
       KernelTimer kt(ctx, s, "chol_diag", each([&](double m) {
@@ -1571,7 +1616,9 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
     // inverse diagonal blocks.  zf (nullable): the forward solve z = L^-1 b in
     // place, carried column by column (the column launches subtract
     // L(i,k) z_k from the blocks below, each diagonal block forms its z_k).
-    __bf16* Wpk = (__bf16*)ws_get(ctx, "chol_wpk", (size_t)n_sys * Wp * 16 * FRAG * sizeof(__bf16));
+    // one buffer per group of a split batch (the groups run at the same time)
+    __bf16* Wpk = (__bf16*)ws_get(ctx, grp > 0 ? "chol_wpk" + std::to_string(grp) : std::string("chol_wpk"),
+                                  (size_t)n_sys * Wp * 16 * FRAG * sizeof(__bf16));
     for (int K0 = 0; K0 < Tmax; K0 += Wp) {
       const int K1 = std::min(K0 + Wp, Tmax);
       for (int k = K0; k < K1; ++k) {

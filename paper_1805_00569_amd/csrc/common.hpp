@@ -166,6 +166,13 @@ struct krr_ctx_s {
   int timing = 0;   // 0 off, 1 matrix-core update kernels, 2 every timed kernel class
   int noalloc = 0;  // inside a no-allocation call: no timing events
   hipStream_t cur_stream = nullptr;   // stream of the call in progress (valid while in_call)
+  // Streams beside the call's stream (default priority) on which groups of
+  // systems of a batch are factored at the same time (KRR_OPT_FACTOR_STREAMS);
+  // every use forks from and joins back into the call's stream.
+  static constexpr int kMaxFactorStreams = 4;
+  hipStream_t side[kMaxFactorStreams - 1] = {};
+  hipEvent_t side_ev[kMaxFactorStreams] = {};   // fork, then one join per side stream
+  int factor_streams = 2;
   bool in_call = false;
   // per stream the context has queued work on: an event recorded after that
   // work (see drain)

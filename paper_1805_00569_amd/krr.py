@@ -28,6 +28,7 @@ KERNEL = {"gaussian": 0, "linear": 1, "polynomial": 2, "sigmoid": 3}
 OPT_PANEL_TILES, OPT_SERIAL_FIT, OPT_SYNC_CHECK, OPT_TIMING, OPT_PERSISTENT, OPT_PERSIST_WAIT_MS, OPT_GRAPHS = \
     0, 1, 2, 3, 4, 5, 6
 OPT_AUTOTUNE = 7
+OPT_FACTOR_STREAMS = 8
 
 
 class KrrError(RuntimeError):
