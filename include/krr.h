@@ -242,9 +242,12 @@ krr_status  krr_memory_in_use(krr_ctx ctx, size_t* bytes);
 krr_status  krr_graph_counts(krr_ctx ctx, int64_t* captured, int64_t* replayed);
 /* Timing record of the launches made since timing was enabled or last
  * reported: synchronises the device and writes a NUL-terminated JSON object
- * {"<kernel class>": {"count": launches, "ms": summed event time, "flops":
- * summed algorithmic flops}, ...} into buf (host, cap bytes, truncated if
- * short).  *needed (host, nullable) receives the full length including the
+ * {"<kernel class>": {"count": launches, "ms": summed event time, "busy_ms":
+ * time covered by at least one of the class's launches (launches on several
+ * streams overlap), "flops": summed algorithmic flops, "bytes": summed
+ * algorithmic bytes}, ...} into buf (host, cap bytes, truncated if short);
+ * the class "chol" unites the intervals of all "chol_*" classes (the
+ * factorisation's wall time).  *needed (host, nullable) receives the full length including the
  * NUL.  The record is cleared when buf is given; buf = NULL only queries the
  * length. */
 krr_status  krr_timing_report(krr_ctx ctx, char* buf, size_t cap, size_t* needed);

@@ -209,17 +209,45 @@ KernelTimer::~KernelTimer() {
   if (hipEventRecord(b, s) == hipSuccess) ctx->pending.push_back({cls, a, b, flops, bytes});
 }
 
+// Adds the pending launches to the per-class totals: summed durations, and
+// the time covered by the union of a class's launch intervals (all positions
+// relative to the first pending launch's start event); the classes named
+// "chol_*" are also united into the class "chol" (the factorisation).
 static void collect_timing(krr_ctx ctx) {
   KRR_HIP(hipDeviceSynchronize());
+  std::map<std::string, std::vector<std::pair<float, float>>> iv;
+  const hipEvent_t ref = ctx->pending.empty() ? nullptr : ctx->pending.front().a;
   for (auto& p : ctx->pending) {
-    float ms = 0.f;
+    float ms = 0.f, t0 = 0.f, t1 = 0.f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       krr_timing_agg& g = ctx->timing_agg[p.cls];
       g.count += 1;
       g.ms += ms;
       g.flops += p.flops;
       g.bytes += p.bytes;
+      if (hipEventElapsedTime(&t0, ref, p.a) == hipSuccess && hipEventElapsedTime(&t1, ref, p.b) == hipSuccess) {
+        iv[p.cls].emplace_back(t0, t1);
+        if (std::strncmp(p.cls, "chol_", 5) == 0) iv["chol"].emplace_back(t0, t1);
+      }
     }
+  }
+  for (auto& kv : iv) {
+    auto& v = kv.second;
+    std::sort(v.begin(), v.end());
+    double busy = 0.0, lo = v.front().first, hi = v.front().second;
+    for (const auto& x : v) {
+      if (x.first > hi) {
+        busy += hi - lo;
+        lo = x.first;
+        hi = x.second;
+      } else {
+        hi = std::max(hi, (double)x.second);
+      }
+    }
+    busy += hi - lo;
+    ctx->timing_agg[kv.first].busy_ms += busy;
+  }
+  for (auto& p : ctx->pending) {
     ctx->ev_pool.push_back(p.a);
     ctx->ev_pool.push_back(p.b);
   }
@@ -393,9 +421,10 @@ krr_status krr_timing_report(krr_ctx ctx, char* buf, size_t cap, size_t* needed)
     bool first = true;
     char tmp[256];
     for (auto& kv : ctx->timing_agg) {
-      std::snprintf(tmp, sizeof(tmp), "%s\"%s\": {\"count\": %lld, \"ms\": %.6f, \"flops\": %.6e, \"bytes\": %.6e}",
-                    first ? "" : ", ", kv.first.c_str(), (long long)kv.second.count, kv.second.ms, kv.second.flops,
-                    kv.second.bytes);
+      std::snprintf(tmp, sizeof(tmp),
+                    "%s\"%s\": {\"count\": %lld, \"ms\": %.6f, \"busy_ms\": %.6f, \"flops\": %.6e, \"bytes\": %.6e}",
+                    first ? "" : ", ", kv.first.c_str(), (long long)kv.second.count, kv.second.ms, kv.second.busy_ms,
+                    kv.second.flops, kv.second.bytes);
       js += tmp;
       first = false;
     }

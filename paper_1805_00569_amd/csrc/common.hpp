@@ -142,7 +142,8 @@ struct krr_timed_launch {
 
 struct krr_timing_agg {
   int64_t count = 0;
-  double ms = 0.0;
+  double ms = 0.0;       // summed launch durations
+  double busy_ms = 0.0;  // time covered by at least one launch of the class (launches on several streams overlap)
   double flops = 0.0;
   double bytes = 0.0;
 };

@@ -115,3 +115,36 @@ def test_persistent_gives_up_when_forced(ctx, dev):
         assert np.array_equal(again[0].alpha(j).cpu().numpy(), ref[0].alpha(j).cpu().numpy())
     again[0].free()
     ref[0].free()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp32", "fp64"])
+def test_factor_streams_give_identical_results(ctx, dev, prec):
+    """KRR_OPT_FACTOR_STREAMS: the launch sequence split into groups of
+    systems factored at the same time on 1, 2, 3 or 4 streams gives the same
+    alpha bit for bit (ragged K-means batch of 24 systems, 16 and 8 of them
+    needed for two groups of eight), and the context keeps working."""
+    w = datagen.small(900, 20000, 12, k=200, p=24, comps=24, dtype=np.float64 if prec == "fp64" else np.float32)
+    X, y = _t(w.X, dev), _t(w.y.astype(w.X.dtype), dev)
+    C, a, sz = ctx.partition(X, 24, "kmeans", lloyd_iters=6, seed=3)
+    print(f"factor streams {prec}: sizes {sorted(sz.cpu().numpy().tolist())[:3]}..{int(sz.max())}", flush=True)
+    params = [krr.Params(sigma=2.0, lam=1e-2, prec=prec, refine_tol=1e-8, max_refine=30)]
+    ref = None
+    try:
+        for fs in (1, 2, 3, 4):
+            ctx.set_option(krr.OPT_FACTOR_STREAMS, fs)
+            models, info, st = ctx.fit(X, y, a, C, 24, params)
+            assert st == 0
+            al = [models[0].alpha(j).cpu().numpy() for j in range(24)]
+            rows = [(r["status"], r["refine_iters"], r["fallback"]) for r in info]
+            for m in models:
+                m.free()
+            if ref is None:
+                ref = (al, rows)
+            else:
+                assert rows == ref[1], fs
+                for j in range(24):
+                    assert np.array_equal(al[j], ref[0][j]), (fs, j)
+    finally:
+        ctx.set_option(krr.OPT_FACTOR_STREAMS, 2)
+    with pytest.raises(krr.KrrError):
+        ctx.set_option(krr.OPT_FACTOR_STREAMS, 5)
