@@ -757,8 +757,10 @@ constexpr int PC_LD = NB + 1;
 // system s on XCD s % 8 (slot b / 8 of that XCD), so that the operands a
 // system's workgroups share are fetched into one L2.  Grids hold
 // 8 * ceil(n_sys / 8) * (workgroups per system); the padding exits at once.
-// A batch of fewer than 8 systems would leave XCDs idle that way: it keeps
-// the plain order, a system's workgroups spread over all XCDs.
+// A batch of fewer than 8 systems would leave XCDs idle that way, and so
+// would a ragged batch whose largest systems hold most of the work (one XCD
+// each): those launches ("spread") keep the plain order, a system's
+// workgroups spread over all XCDs.
 constexpr int NXCD = 8;
 
 __device__ __forceinline__ void panel_col_tile(const SysDesc& D, int s, int i, int lane, float* __restrict__ A,
@@ -925,10 +927,10 @@ __global__ __launch_bounds__(256) void k_panel_col(const SysDesc* __restrict__ d
                                                    float* __restrict__ A, float* __restrict__ Wt,
                                                    __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk, int K0, int k,
                                                    int Wp, int level, int do_pack, int diag_next, int n_sys, int ng,
-                                                   double* __restrict__ zf) {
+                                                   double* __restrict__ zf, int spread) {
   int s, g;
-  if (n_sys < NXCD) {
-    // fewer systems than XCDs: workgroups in turn over all XCDs (group 0 of every system first)
+  if (spread) {
+    // workgroups in turn over all XCDs (group 0 of every system first)
     if ((int)blockIdx.x >= n_sys * ng) return;
     g = blockIdx.x / n_sys;
     s = blockIdx.x % n_sys;
@@ -1002,10 +1004,10 @@ __device__ __forceinline__ void trail_body(const SysDesc& D, int bxs, float* __r
 __global__ __launch_bounds__(256, 2) void k_packed_trailing(const SysDesc* __restrict__ desc,
                                                          const SysStatus* __restrict__ st, float* __restrict__ A,
                                                          const __bf16* __restrict__ Pk, int K0, int ks0, int ks1,
-                                                         int i0, int Wp, int level, int n_sys, int ntri) {
+                                                         int i0, int Wp, int level, int n_sys, int ntri, int spread) {
   // XCD placement (see NXCD): slot = system-major (system, super-tile)
   int s, bxs;
-  if (n_sys < NXCD) {   // fewer systems than XCDs: workgroups in turn over all XCDs
+  if (spread) {   // workgroups in turn over all XCDs
     if ((int)blockIdx.x >= n_sys * ntri) return;
     s = blockIdx.x / ntri;
     bxs = blockIdx.x % ntri;
@@ -1619,6 +1621,19 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
     // one buffer per group of a split batch (the groups run at the same time)
     __bf16* Wpk = (__bf16*)ws_get(ctx, grp > 0 ? "chol_wpk" + std::to_string(grp) : std::string("chol_wpk"),
                                   (size_t)n_sys * Wp * 16 * FRAG * sizeof(__bf16));
+    // placement (see NXCD): spread over all XCDs for fewer than 8 systems, or
+    // when the largest system is more than twice the median one (ragged: the
+    // largest systems hold most of the work); else one XCD per system
+    int spread = n_sys < NXCD ? 1 : 0;
+    if (!spread && hdesc != nullptr) {
+      std::vector<int> ts;
+      for (int i = 0; i < n_sys; ++i)
+        if (hdesc[i].level == level && hdesc[i].T > 0) ts.push_back(hdesc[i].T);
+      if (!ts.empty()) {
+        std::nth_element(ts.begin(), ts.begin() + ts.size() / 2, ts.end());
+        if (Tmax > 2 * ts[ts.size() / 2]) spread = 1;
+      }
+    }
     for (int K0 = 0; K0 < Tmax; K0 += Wp) {
       const int K1 = std::min(K0 + Wp, Tmax);
       for (int k = K0; k < K1; ++k) {
@@ -1649,7 +1664,7 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
           const int ng = ceil_div(Tmax - k - 1, 4);
           hipLaunchKernelGGL(k_panel_col, dim3((unsigned)(NXCD * ceil_div(n_sys, NXCD) * ng)), dim3(256), 0, s, desc,
                              st, (float*)A,
-                             (float*)Wt, Wpk, (__bf16*)Pk, K0, k, Wp, level, do_pack, nd ? 1 : 0, n_sys, ng, zf);
+                             (float*)Wt, Wpk, (__bf16*)Pk, K0, k, Wp, level, do_pack, nd ? 1 : 0, n_sys, ng, zf, spread);
           check_launch(ctx, s, "panel_col");
         }
       }
@@ -1668,7 +1683,7 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
         const int ntri = (int)(NS * (NS + 1) / 2);
         hipLaunchKernelGGL(k_packed_trailing, dim3((unsigned)(NXCD * ceil_div(n_sys, NXCD) * ntri)), dim3(256), 0, s,
                            desc, (const SysStatus*)st, (float*)A, (const __bf16*)Pk, K0, 0, 2 * (K1 - K0), K1, Wp,
-                           level, n_sys, ntri);
+                           level, n_sys, ntri, spread);
         check_launch(ctx, s, "packed_trailing");
       }
     }
