@@ -59,8 +59,8 @@ TRAFFIC = {
     "chol_column_bf16": {
         "kernel": "k_panel_col",
         "source": "paper_1805_00569_amd/csrc/cholesky.hip",
-        "sha256": "6c0b68f003e2eae9410283d5ec55c118fef9f6d7c537af0d7d57bb3b3ec9182f",
-        "fetch_kib": 118932.4, "write_kib": 79709.8, "fetch_scale": 2.0, "write_scale": 1.0,
+        "sha256": "db4b0a29cad697ec59d97ffc824d7c3af980d6a2cad5661c0f2b717972dec686",
+        "fetch_kib": 58807.2, "write_kib": 39846.3, "fetch_scale": 2.0, "write_scale": 1.0,
     },
 }
 

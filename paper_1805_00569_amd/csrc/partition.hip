@@ -414,25 +414,15 @@ __global__ __launch_bounds__(MS_THREADS) void k_means_seq(const TX* __restrict__
     if (w == 0 && lane < MS_W) {
       const int nr = (int)min<int64_t>(CH, cnt - c * CH);
       const TX* col = &sX[cur][lane];
-      const int nb = nr / 16;   // whole batches of 16 rows
-      // software-pipelined: the LDS loads of batch b + 1 are issued before
-      // the 16 ordered adds of batch b, so their latency hides behind them
-      TX x[16], xn[16];
-      if (nb > 0) {
+      int r = 0;
+      for (; r + 16 <= nr; r += 16) {   // 16 LDS loads, then 16 ordered adds
+        double x[16];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) x[u] = col[u * MS_W];
+        for (int u = 0; u < 16; ++u) x[u] = (double)col[(r + u) * MS_W];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc = add_sep(acc, x[u]);
       }
-      for (int b = 0; b < nb; ++b) {
-        const int rn = 16 * min(b + 1, nb - 1);   // the last batch reloads itself (in range, unused)
-#pragma unroll
-        for (int u = 0; u < 16; ++u) xn[u] = col[(rn + u) * MS_W];
-        __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the adds
-#pragma unroll
-        for (int u = 0; u < 16; ++u) acc = add_sep(acc, (double)x[u]);
-#pragma unroll
-        for (int u = 0; u < 16; ++u) x[u] = xn[u];
-      }
-      for (int r = 16 * nb; r < nr; ++r) acc = add_sep(acc, (double)col[r * MS_W]);
+      for (; r < nr; ++r) acc = add_sep(acc, (double)col[r * MS_W]);
     }
     if (more) {
       // sX[nxt] and sP[cur] were last read before the previous barrier
