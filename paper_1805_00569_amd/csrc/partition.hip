@@ -344,10 +344,11 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_group_scatter(const int32_t* __
 // Workgroup (j, slice) = (blockIdx.x / nsl, blockIdx.x % nsl) owns features
 // [MS_W slice, MS_W slice + MS_W): narrow slices give p * ceil(d / MS_W)
 // workgroups, so that many running sums advance at once.  Chunks of CH
-// member rows are staged in LDS (double-buffered; all threads load, 16
-// rows of MS_W features per load instruction), and lanes 0 .. MS_W - 1 of
-// wave 0 add them in order, lane f carrying feature f's sum: the additions
-// of a chunk overlap the loads of the next.  The member indices of chunk
+// member rows are staged in LDS feature-major (double-buffered; all threads
+// load, 16 rows of MS_W features per load instruction), and lanes 0 ..
+// MS_W - 1 of wave 0 add them in order, lane f carrying feature f's sum and
+// reading four rows per LDS load: the additions of a chunk overlap the
+// loads of the next.  The member indices of chunk
 // c + 2 are fetched while chunk c is summed.  Lloyd passes: `skip` is this
 // pass's "fixed point reached" flag; workgroup 0 writes the next pass's flag
 // (set when this pass was skipped or changed no assignment), so no
@@ -361,6 +362,10 @@ constexpr int MS_RPL = MS_THREADS / MS_W;        // rows per load instruction of
 template <typename TX>
 struct MeansChunk {
   static constexpr int CH = sizeof(TX) == 4 ? 1024 : 512;   // member rows per staged chunk (64 KiB)
+  // the stage is feature-major: feature f's CH rows at f * PITCH (padded so
+  // that the staging stores and the adders' 16-byte loads of four rows meet
+  // distinct banks)
+  static constexpr int PITCH = CH + 4;
 };
 
 template <typename TX>
@@ -381,7 +386,8 @@ __global__ __launch_bounds__(MS_THREADS) void k_means_seq(const TX* __restrict__
   const int64_t base = offsets[j];
   const int64_t cnt = offsets[j + 1] - base;
   if (cnt == 0) return;
-  __shared__ __align__(16) TX sX[2][CH * MS_W];
+  constexpr int PITCH = MeansChunk<TX>::PITCH;
+  __shared__ __align__(16) TX sX[2][MS_W * PITCH];
   __shared__ int32_t sP[2][CH];
   const int t = threadIdx.x, fl = t % MS_W, rr = t / MS_W, w = t >> 6, lane = t & 63;
   const int fc = min(f0 + fl, d - 1);   // clamped feature: lanes past d load a valid value, never summed
@@ -396,7 +402,7 @@ __global__ __launch_bounds__(MS_THREADS) void k_means_seq(const TX* __restrict__
     for (int u = 0; u < PER; ++u) v[u] = X[(int64_t)sP[0][rr + MS_RPL * u] * d + fc];
     for (int r = t; r < CH; r += MS_THREADS) sP[1][r] = member(min<int64_t>(1, nch - 1), r);
 #pragma unroll
-    for (int u = 0; u < PER; ++u) sX[0][(rr + MS_RPL * u) * MS_W + fl] = v[u];
+    for (int u = 0; u < PER; ++u) sX[0][fl * PITCH + rr + MS_RPL * u] = v[u];
   }
   __syncthreads();
   double acc = 0.0;
@@ -413,21 +419,27 @@ __global__ __launch_bounds__(MS_THREADS) void k_means_seq(const TX* __restrict__
     }
     if (w == 0 && lane < MS_W) {
       const int nr = (int)min<int64_t>(CH, cnt - c * CH);
-      const TX* col = &sX[cur][lane];
+      const TX* col = &sX[cur][lane * PITCH];   // this lane's feature, rows contiguous
+      typedef TX tx4 __attribute__((ext_vector_type(4)));
       int r = 0;
-      for (; r + 16 <= nr; r += 16) {   // 16 LDS loads, then 16 ordered adds
-        double x[16];
+      for (; r + 64 <= nr; r += 64) {   // 16 loads of four rows, then 64 ordered adds
+        tx4 x[16];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) x[u] = (double)col[(r + u) * MS_W];
+        for (int u = 0; u < 16; ++u) x[u] = *reinterpret_cast<const tx4*>(col + r + 4 * u);
 #pragma unroll
-        for (int u = 0; u < 16; ++u) acc = add_sep(acc, x[u]);
+        for (int u = 0; u < 16; ++u) {
+          acc = add_sep(acc, (double)x[u][0]);
+          acc = add_sep(acc, (double)x[u][1]);
+          acc = add_sep(acc, (double)x[u][2]);
+          acc = add_sep(acc, (double)x[u][3]);
+        }
       }
-      for (; r < nr; ++r) acc = add_sep(acc, (double)col[r * MS_W]);
+      for (; r < nr; ++r) acc = add_sep(acc, (double)col[r]);
     }
     if (more) {
       // sX[nxt] and sP[cur] were last read before the previous barrier
 #pragma unroll
-      for (int u = 0; u < PER; ++u) sX[nxt][(rr + MS_RPL * u) * MS_W + fl] = v[u];
+      for (int u = 0; u < PER; ++u) sX[nxt][fl * PITCH + rr + MS_RPL * u] = v[u];
 #pragma unroll
       for (int q = 0; q < CH / MS_THREADS; ++q) sP[cur][t + q * MS_THREADS] = pn[q];
     }
