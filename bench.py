@@ -608,7 +608,8 @@ def ragged_leg(reps=3):
     and 20 Lloyd passes) into 32 partitions; all 32 uneven systems fitted as
     one batch in FP32 (sigma = 2, lambda = 1e-2), and in mixed precision;
     each with one launch per factorisation stage and with the persistent
-    launch."""
+    launch; and in FP32 with autotuned panel widths per size class (the
+    persistent launch, since the systems' widths then differ)."""
     import torch
     from paper_1805_00569_amd import datagen, krr
     dev = torch.device("cuda:0")
@@ -637,6 +638,28 @@ def ragged_leg(reps=3):
                         "frac_peak": fl / tf / 1e12 / PEAK["fp32" if prec == "fp32" else "bf16"]}
             print(f"# ragged {key}: {tf * 1e3:.1f} ms", file=sys.stderr, flush=True)
         ctx.set_option(krr.OPT_PERSISTENT, 0)
+    # autotuned panel widths: one tuning per size class present (trial fits of
+    # eight systems of the class's largest size, in the persistent launch),
+    # then the fit, where the systems' widths differ and the batch runs as
+    # the persistent launch
+    tctx = krr.Context(0)
+    tctx.set_option(krr.OPT_PERSISTENT, 1)   # trials in the launch mode the tuned widths will run in
+    tuned = {}
+    t = time.perf_counter()
+    classes = {}
+    for m in sizes:
+        c = max(0, (int(math.ceil(m / 64)) - 1).bit_length())
+        classes[c] = max(classes.get(c, 0), m)
+    for c, m in sorted(classes.items()):
+        wdt, tms = tctx.autotune("fp32", m, w.d, n_sys=8)
+        tuned[str(m)] = {"panel_tiles": wdt, "trial_fit_ms": tms}
+    res["autotune"] = {"seconds": time.perf_counter() - t, "by_class_largest_m": tuned}
+    params = [krr.Params(sigma=2.0, lam=1e-2, prec="fp32", refine_tol=1e-6, max_refine=30)]
+    tf, info, st = _timed_fit(tctx, X, y, a, C, 32, params, reps)
+    res["fp32_autotuned"] = {"fit_ms": tf * 1e3, "fits_per_s": 32 / tf, "tflops": fl / tf / 1e12, "status": st,
+                             "frac_peak": fl / tf / 1e12 / PEAK["fp32"]}
+    print(f"# ragged fp32_autotuned: {tf * 1e3:.1f} ms (tuned widths {tuned})", file=sys.stderr, flush=True)
+    tctx.close()
     ctx.close()
     return res
 
