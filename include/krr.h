@@ -204,7 +204,11 @@ typedef enum {
                                equal work, at least 8 systems each) and factors them at the
                                same time on as many streams, so that one group's
                                latency-bound launches leave room for the others'; results are
-                               identical for every value */
+                               identical for every value */,
+  KRR_OPT_COLUMN_PAIRS = 9  /* 1 (default): the mixed-precision launch sequence updates two
+                               panel columns per launch in one pass over each tile row's
+                               packed operands (the diagonal blocks two columns ahead); 0: one
+                               column per launch.  Results are identical bit for bit */
 } krr_option;
 
 /* ---- autotuning (Cholesky panel width) ------------------------------------

@@ -394,6 +394,9 @@ krr_status krr_set_option(krr_ctx ctx, int32_t option, int64_t value) {
       case KRR_OPT_AUTOTUNE:
         ctx->autotune = value ? 1 : 0;
         break;
+      case KRR_OPT_COLUMN_PAIRS:
+        ctx->column_pairs = value ? 1 : 0;
+        break;
       case KRR_OPT_GRAPHS:
         graph_drop_all(ctx);
         ctx->graphs = value ? 1 : 0;

@@ -763,28 +763,28 @@ constexpr int PC_LD = NB + 1;
 // workgroups spread over all XCDs.
 constexpr int NXCD = 8;
 
-__device__ __forceinline__ void panel_col_tile(const SysDesc& D, int s, int i, int lane, float* __restrict__ A,
-                                               const __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk, int K0, int k,
-                                               int Wp, int wps, int do_pack, double* __restrict__ zf,
-                                               float* __restrict__ sc) {
-  const int KSW = 2 * Wp;
-  const int il = lane & 15, kg = lane >> 4;
-  // Winv(k) fragments first: their latency overlaps the column update
+// Winv(k) as BF16 high/low operand fragments (cb, ks) of the panel solve;
+// the blocks above Winv's diagonal (cb < 2, ks = 1) are zero and not loaded.
+struct WinvFrags {
+  bf8 hi[4][2], lo[4][2];
+};
+
+__device__ __forceinline__ void load_winv(const __bf16* __restrict__ Wpk, int s, int wps, int K0, int k, int lane,
+                                          WinvFrags& W) {
   const __bf16* Wf = Wpk + ((int64_t)s * wps + (k - K0)) * 16 * FRAG + lane * 8;
-  bf8 whi[4][2], wlo[4][2];
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks)
       if (ks == 0 || cb >= 2) {
-        whi[cb][ks] = *reinterpret_cast<const bf8*>(Wf + (int64_t)(2 * (2 * cb + ks)) * FRAG);
-        wlo[cb][ks] = *reinterpret_cast<const bf8*>(Wf + (int64_t)(2 * (2 * cb + ks) + 1) * FRAG);
+        W.hi[cb][ks] = *reinterpret_cast<const bf8*>(Wf + (int64_t)(2 * (2 * cb + ks)) * FRAG);
+        W.lo[cb][ks] = *reinterpret_cast<const bf8*>(Wf + (int64_t)(2 * (2 * cb + ks) + 1) * FRAG);
       }
-  // element (16 cb + 4 kg + v, 16 rb + il) of the tile: a scalar base per
-  // column block cb, one per-lane offset, the rest immediate
-  float* C = A + D.a_off + tile_index(i, k) * TILE;
-  const int lo = 4 * kg * NB + il;
-  f4 acc[4][4];
+}
+
+// element (16 cb + 4 kg + v, 16 rb + il) of the tile C: a scalar base per
+// column block cb, one per-lane offset lo = 4 kg NB + il, the rest immediate
+__device__ __forceinline__ void load_ctile(const float* __restrict__ C, int lo, f4 (&acc)[4][4]) {
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) {
     const float* Cc = C + 16 * cb * NB;
@@ -793,16 +793,41 @@ __device__ __forceinline__ void panel_col_tile(const SysDesc& D, int s, int i, i
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[cb][rb][v] = Cc[lo + v * NB + 16 * rb];
   }
-  if (k > K0) packed_sub<4, 2, true>(acc, Pk + D.pk_off + lane * 8, (i - K0) * 4, (k - K0) * 4, KSW, 0, 2 * (k - K0));
+}
+
+__device__ __forceinline__ void store_ctile(float* __restrict__ C, int lo, const f4 (&acc)[4][4]) {
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    float* Cc = C + 16 * cb * NB;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Cc[lo + v * NB + 16 * rb] = acc[cb][rb][v];
+  }
+}
+
+__device__ __forceinline__ void lds_wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The panel solve of tile (i, k) from its updated value in acc:
+// L(i,k) = C(i,k) Winv(k)^T into the FP32 tile C and the wave's LDS tile sc
+// (left there for the caller), and (do_pack) BF16 fragments of the pack;
+// zf: b_i -= L(i,k) z_k.
+__device__ __forceinline__ void tile_solve(const SysDesc& D, int i, int lane, float* __restrict__ C, int lo,
+                                           const WinvFrags& W, __bf16* __restrict__ Pk, int K0, int k, int KSW,
+                                           int do_pack, double* __restrict__ zf, float* __restrict__ sc,
+                                           const f4 (&acc)[4][4]) {
+  const int il = lane & 15, kg = lane >> 4;
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) sc[(16 * cb + 4 * kg + v) * PC_LD + 16 * rb + il] = acc[cb][rb][v];
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  lds_wave_fence();
   // out(r, c) = sum_{t <= c} C(r, t) Winv(c, t) on BF16 matrix cores with
   // high/low splits of both operands (three products, FP32 accumulation:
   // about 16 significant bits per product, below the error of the BF16
@@ -828,14 +853,12 @@ __device__ __forceinline__ void panel_col_tile(const SysDesc& D, int s, int i, i
       }
 #pragma unroll
       for (int cb = 2 * ks; cb < 4; ++cb) {
-        o[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wlo[cb][ks], chi, o[cb][rb], 0, 0, 0);
-        o[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(whi[cb][ks], clo, o[cb][rb], 0, 0, 0);
-        o[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(whi[cb][ks], chi, o[cb][rb], 0, 0, 0);
+        o[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W.lo[cb][ks], chi, o[cb][rb], 0, 0, 0);
+        o[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W.hi[cb][ks], clo, o[cb][rb], 0, 0, 0);
+        o[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W.hi[cb][ks], chi, o[cb][rb], 0, 0, 0);
       }
     }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  lds_wave_fence();
   // MFMA result: register v of a lane is column 4 (lane >> 4) + v, row lane & 15 of its 16 x 16 block
   int lo2;   // the offset recomputed here, not held in registers across the products
   asm volatile("" : "=v"(lo2) : "0"(lo));
@@ -878,9 +901,7 @@ __device__ __forceinline__ void panel_col_tile(const SysDesc& D, int s, int i, i
     }
   }
   if (!do_pack) return;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  lds_wave_fence();
   __bf16* Pout = Pk + D.pk_off + lane * 8;
 #pragma unroll
   for (int rbl = 0; rbl < 4; ++rbl)
@@ -893,6 +914,121 @@ __device__ __forceinline__ void panel_col_tile(const SysDesc& D, int s, int i, i
       const int rb = (i - K0) * 4 + rbl, ks = 2 * (k - K0) + h;
       *reinterpret_cast<bf8*>(Pout + ((int64_t)rb * KSW + ks) * FRAG) = v;
     }
+}
+
+__device__ __forceinline__ void panel_col_tile(const SysDesc& D, int s, int i, int lane, float* __restrict__ A,
+                                               const __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk, int K0, int k,
+                                               int Wp, int wps, int do_pack, double* __restrict__ zf,
+                                               float* __restrict__ sc) {
+  const int KSW = 2 * Wp;
+  // Winv(k) fragments first: their latency overlaps the column update
+  WinvFrags W;
+  load_winv(Wpk, s, wps, K0, k, lane, W);
+  float* C = A + D.a_off + tile_index(i, k) * TILE;
+  const int lo = 4 * (lane >> 4) * NB + (lane & 15);
+  f4 acc[4][4];
+  load_ctile(C, lo, acc);
+  if (k > K0) packed_sub<4, 2, true>(acc, Pk + D.pk_off + lane * 8, (i - K0) * 4, (k - K0) * 4, KSW, 0, 2 * (k - K0));
+  tile_solve(D, i, lane, C, lo, W, Pk, K0, k, KSW, do_pack, zf, sc, acc);
+}
+
+// acc0 -= sum_{ks in [ks0, ks1)} P(rbj0 + cb, ks) P(rbi + rb, ks)^T and acc1
+// the same with rbj1: one pass over the row fragments (rbi) for two panel
+// columns.  Each accumulator takes exactly the MFMAs packed_sub would give
+// it, in the same order; (ks1 - ks0) is a multiple of PK_DEPTH.
+template <int PK_DEPTH>
+__device__ __forceinline__ void packed_sub2(f4 (&acc0)[4][4], f4 (&acc1)[4][4], const __bf16* __restrict__ P,
+                                            int rbi, int rbj0, int rbj1, int KSW, int ks0, int ks1) {
+  if (ks0 >= ks1) return;
+  typedef unsigned u4v __attribute__((ext_vector_type(4)));
+  const u4v sgn{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+  bf8 pa[PK_DEPTH][4], q0[PK_DEPTH][4], q1[PK_DEPTH][4];
+  auto load = [&](int u, int ks) {
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+      pa[u][rb] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbi + rb) * KSW + ks) * FRAG);
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      q0[u][cb] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbj0 + cb) * KSW + ks) * FRAG);
+      q1[u][cb] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbj1 + cb) * KSW + ks) * FRAG);
+    }
+  };
+  auto step = [&](int u) {
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const bf8 n0 = __builtin_bit_cast(bf8, __builtin_bit_cast(u4v, q0[u][cb]) ^ sgn);
+      const bf8 n1 = __builtin_bit_cast(bf8, __builtin_bit_cast(u4v, q1[u][cb]) ^ sgn);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        acc0[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n0, pa[u][rb], acc0[cb][rb], 0, 0, 0);
+        acc1[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n1, pa[u][rb], acc1[cb][rb], 0, 0, 0);
+      }
+    }
+  };
+#pragma unroll
+  for (int u = 0; u < PK_DEPTH; ++u) {
+    load(u, min(ks0 + u, ks1 - 1));
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  for (int ks = ks0; ks < ks1; ks += PK_DEPTH) {
+#pragma unroll
+    for (int u = 0; u < PK_DEPTH; ++u) {
+      step(u);
+      load(u, min(ks + u + PK_DEPTH, ks1 - 1));
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+// Tile row i of columns c and c + 1 of the panel in one pass over the row's
+// fragments: both columns' updates over the panel columns [K0, c), the
+// panel solve of column c, then column c + 1's last term L(i,c) L(c+1,c)^T
+// (operands: BF16 of L(i,c) from the wave's LDS, equal to what the pack
+// holds, and L(c+1,c) from the pack) and its panel solve.  Results equal
+// two single-column passes bit for bit.  Column c is always packed (column
+// c + 1 reads it); pack1 for column c + 1.
+__device__ __forceinline__ void pair_tile(const SysDesc& D, int s, int i, int lane, float* __restrict__ A,
+                                          const __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk, int K0, int c,
+                                          int Wp, int wps, int pack1, double* __restrict__ zf, float* __restrict__ sc) {
+  const int KSW = 2 * Wp, il = lane & 15, kg = lane >> 4;
+  WinvFrags W;
+  load_winv(Wpk, s, wps, K0, c, lane, W);
+  float* C0 = A + D.a_off + tile_index(i, c) * TILE;
+  float* C1 = C0 + TILE;   // tile (i, c + 1)
+  const int lo = 4 * kg * NB + il;
+  f4 acc0[4][4], acc1[4][4];
+  load_ctile(C0, lo, acc0);
+  load_ctile(C1, lo, acc1);
+  const __bf16* P = Pk + D.pk_off + lane * 8;
+  const int rbi = (i - K0) * 4, rbj = (c - K0) * 4;
+  packed_sub2<1>(acc0, acc1, P, rbi, rbj, rbj + 4, KSW, 0, 2 * (c - K0));
+  tile_solve(D, i, lane, C0, lo, W, Pk, K0, c, KSW, 1, zf, sc, acc0);
+  lds_wave_fence();
+  {
+    typedef unsigned u4v __attribute__((ext_vector_type(4)));
+    const u4v sgn{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int ks = 2 * (c - K0) + h, cl = 32 * h + 8 * kg;
+      bf8 pa[4], qv[4];
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) qv[cb] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbj + 4 + cb) * KSW + ks) * FRAG);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) pa[rb][e] = (__bf16)sc[(cl + e) * PC_LD + 16 * rb + il];
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        const bf8 nq = __builtin_bit_cast(bf8, __builtin_bit_cast(u4v, qv[cb]) ^ sgn);
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+          acc1[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nq, pa[rb], acc1[cb][rb], 0, 0, 0);
+      }
+    }
+  }
+  lds_wave_fence();
+  load_winv(Wpk, s, wps, K0, c + 1, lane, W);
+  tile_solve(D, i, lane, C1, lo, W, Pk, K0, c + 1, KSW, pack1, zf, sc, acc1);
 }
 
 union PcolLds {
@@ -951,6 +1087,119 @@ __global__ __launch_bounds__(256) void k_panel_col(const SysDesc* __restrict__ d
   if (st[s].status != 0 || D.level != level) return;
   __shared__ __align__(16) PcolLds lds;
   pcol_body(D, s, st, A, Wt, Wpk, Pk, K0, k, Wp, Wp, do_pack, diag_next, g, zf, lds);
+}
+
+// System s and tile-row group g of workgroup blockIdx.x in the placement of
+// k_panel_col (ng groups per system); false for the grid's padding.
+__device__ __forceinline__ bool group_of(int spread, int n_sys, int ng, int& s, int& g) {
+  if (spread) {
+    if ((int)blockIdx.x >= n_sys * ng) return false;
+    g = blockIdx.x / n_sys;
+    s = blockIdx.x % n_sys;
+    return true;
+  }
+  const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD, U = (n_sys + NXCD - 1) / NXCD;
+  int u;
+  if (slot < U) {
+    u = slot;
+    g = 0;
+  } else {
+    u = (slot - U) / (ng - 1);
+    g = 1 + (slot - U) % (ng - 1);
+  }
+  s = xcd + NXCD * u;
+  return s < n_sys;
+}
+
+// Columns c and c + 1 of the panel [K0, K0 + Wp) in one launch, for the tile
+// rows below c + 1 (pair_tile, one row per wave).  On entry the columns
+// before c are final for every row, and so are the diagonal blocks c and
+// c + 1 (Winv fragments, z), and L(c+1, c).  Group 0 (rows c + 2, c + 3)
+// carries the diagonal chain two columns ahead, so that the next launch
+// finds the same: diagonal block c + 2 (its update reads row c + 2's
+// fragments of columns c and c + 1, just packed by wave 0), then tile
+// (c+3, c+2) -- whose update over the columns before c wave 2 has already
+// summed and parked in the FP32 tile, the rest reading row c + 3's fragments
+// packed by wave 1 -- then diagonal block c + 3.  Every tile and block takes
+// the operations of the single-column sequence in the same order, so the
+// factor is the same bit for bit.
+__device__ __forceinline__ void ppair_body(const SysDesc& D, int s, SysStatus* __restrict__ st, float* __restrict__ A,
+                                           float* __restrict__ Wt, __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk,
+                                           int K0, int c, int Wp, int wps, int pack1, int g, double* __restrict__ zf,
+                                           PcolLds& lds) {
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (g > 0) {
+    const int i = c + 4 * g + w;
+    if (i < D.T) pair_tile(D, s, i, lane, A, Wpk, Pk, K0, c, Wp, wps, pack1, zf, lds.sC[w]);
+    return;
+  }
+  const int kend = min(K0 + Wp, (int)D.T);
+  const bool d2 = c + 2 < kend, d3 = c + 3 < kend;   // uniform over the workgroup
+  const int KSW = 2 * Wp, lo = 4 * (lane >> 4) * NB + (lane & 15);
+  const __bf16* P = Pk + D.pk_off + lane * 8;
+  float* C32 = A + D.a_off + tile_index(c + 3, c + 2) * TILE;
+  if (w < 2) {
+    if (c + 2 + w < D.T) pair_tile(D, s, c + 2 + w, lane, A, Wpk, Pk, K0, c, Wp, wps, pack1, zf, lds.sC[w]);
+  } else if (w == 2 && d3 && c > K0) {
+    f4 acc[4][4];
+    load_ctile(C32, lo, acc);
+    packed_sub<4, 2, true>(acc, P, (c + 3 - K0) * 4, (c + 2 - K0) * 4, KSW, 0, 2 * (c - K0));
+    store_ctile(C32, lo, acc);
+  }
+  if (!d2) return;
+  __syncthreads();   // rows c + 2 and c + 3 packed, the parked sum stored; LDS free
+  diag_block<float>(D, s, st, A, Wt, c + 2, Pk, K0, Wp, wps, Wpk, zf, lds.dg, threadIdx.x);
+  if (!d3) return;
+  __syncthreads();
+  if (lds.dg.fail) return;   // the system failed at block c + 2 (status set)
+  __syncthreads();           // every wave has read the flag before the LDS is reused
+  if (w == 0) {
+    WinvFrags W;
+    load_winv(Wpk, s, wps, K0, c + 2, lane, W);
+    f4 acc[4][4];
+    load_ctile(C32, lo, acc);
+    packed_sub<4, 2, true>(acc, P, (c + 3 - K0) * 4, (c + 2 - K0) * 4, KSW, 2 * (c - K0), 2 * (c + 2 - K0));
+    tile_solve(D, c + 3, lane, C32, lo, W, Pk, K0, c + 2, KSW, 1, zf, lds.sC[0], acc);
+  }
+  __syncthreads();
+  diag_block<float>(D, s, st, A, Wt, c + 3, Pk, K0, Wp, wps, Wpk, zf, lds.dg, threadIdx.x);
+}
+
+// Columns c, c + 1 of the panel (ppair_body); ng = tile-row groups of four
+// per system (group 0: rows c + 2, c + 3), placed as in k_panel_col.
+__global__ __launch_bounds__(256, 2) void k_panel_pair(const SysDesc* __restrict__ desc, SysStatus* __restrict__ st,
+                                                    float* __restrict__ A, float* __restrict__ Wt,
+                                                    __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk, int K0, int c,
+                                                    int Wp, int level, int pack1, int n_sys, int ng,
+                                                    double* __restrict__ zf, int spread) {
+  int s, g;
+  if (!group_of(spread, n_sys, ng, s, g)) return;
+  const SysDesc D = desc[s];
+  if (st[s].status != 0 || D.level != level) return;
+  __shared__ __align__(16) PcolLds lds;
+  ppair_body(D, s, st, A, Wt, Wpk, Pk, K0, c, Wp, Wp, pack1, g, zf, lds);
+}
+
+// The head of a panel that runs as column pairs, one workgroup per system:
+// diagonal block K0, tile (K0+1, K0) (its panel solve; no update inside the
+// panel yet), diagonal block K0 + 1.
+__global__ __launch_bounds__(256) void k_panel_head(const SysDesc* __restrict__ desc, SysStatus* __restrict__ st,
+                                                    float* __restrict__ A, float* __restrict__ Wt,
+                                                    __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk, int K0, int Wp,
+                                                    int level, double* __restrict__ zf) {
+  const int s = blockIdx.x;
+  const SysDesc D = desc[s];
+  if (K0 >= D.T || st[s].status != 0 || D.level != level) return;
+  __shared__ __align__(16) PcolLds lds;
+  diag_block<float>(D, s, st, A, Wt, K0, Pk, K0, Wp, Wp, Wpk, zf, lds.dg, threadIdx.x);
+  if (K0 + 1 >= D.T || K0 + 1 >= K0 + Wp) return;
+  __syncthreads();
+  if (lds.dg.fail) return;
+  __syncthreads();
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (w == 0) panel_col_tile(D, s, K0 + 1, lane, A, Wpk, Pk, K0, K0, Wp, Wp, 1, zf, lds.sC[0]);
+  __syncthreads();
+  diag_block<float>(D, s, st, A, Wt, K0 + 1, Pk, K0, Wp, Wp, Wpk, zf, lds.dg, threadIdx.x);
 }
 
 // Super-tile order of the trailing update: bands of TRAIL_BAND super-rows,
@@ -1636,36 +1885,71 @@ void factor_t(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatus* st, in
     }
     for (int K0 = 0; K0 < Tmax; K0 += Wp) {
       const int K1 = std::min(K0 + Wp, Tmax);
-      for (int k = K0; k < K1; ++k) {
-        if (k == K0) {
-          KernelTimer kt(ctx, s, "chol_diag", each([&](double m) {
-            const double b = std::min<double>(NB, m - k * NB);
-            return b > 0 ? 2.0 * b * b * b / 3.0 : 0.0;
-          }), 0);
-          hipLaunchKernelGGL((k_potrf_diag<TS>), dim3(n_sys), dim3(DIAG_THREADS), 0, s, desc, st, A, Wt, k, level,
-                             (const __bf16*)Pk, K0, Wp, Wpk, zf);
-          check_launch(ctx, s, "potrf_diag");
+      auto diag_flops = [&](int k) {
+        return each([&](double m) {
+          const double b = std::min<double>(NB, m - k * NB);
+          return b > 0 ? 2.0 * b * b * b / 3.0 : 0.0;
+        });
+      };
+      // credited to the launch of column k: the column update of the tiles
+      // below the diagonal and their panel solve, and the next diagonal block
+      // inside the panel (its factorisation); algorithmic bytes: read those
+      // tiles and write their factor, read the next diagonal tile and write
+      // its factor and inverse (FP32)
+      auto col_flops = [&](int k) {
+        const bool nd = k + 1 < K1;
+        return each([&](double m) {
+          const double rows = m - (k + 1) * NB, b = std::min<double>(NB, rows);
+          return rows > 0 ? 2.0 * rows * NB * (k - K0) * NB + rows * (double)NB * NB + (nd ? 2.0 * b * b * b / 3.0 : 0.0)
+                          : 0.0;
+        });
+      };
+      auto col_bytes = [&](int k) {
+        const bool nd = k + 1 < K1;
+        return each([&](double m) {
+          const double rows = m - (k + 1) * NB;
+          return rows > 0 ? 2.0 * rows * NB * sizeof(float) + (nd ? 3.0 * NB * NB * sizeof(float) : 0.0) : 0.0;
+        });
+      };
+      auto single_column = [&](int k) {
+        const bool nd = k + 1 < K1;
+        KernelTimer kt(ctx, s, col_name, col_flops(k), 1, col_bytes(k));
+        const int do_pack = (k + 1 < K1 || K1 < Tmax) ? 1 : 0;
+        const int ng = ceil_div(Tmax - k - 1, 4);
+        hipLaunchKernelGGL(k_panel_col, dim3((unsigned)(NXCD * ceil_div(n_sys, NXCD) * ng)), dim3(256), 0, s, desc,
+                           st, (float*)A, (float*)Wt, Wpk, (__bf16*)Pk, K0, k, Wp, level, do_pack, nd ? 1 : 0, n_sys, ng,
+                           zf, spread);
+        check_launch(ctx, s, "panel_col");
+      };
+      if (ctx->column_pairs && K1 - K0 >= 2) {
+        // column pairs: the head (diagonal blocks K0 and K0 + 1), then columns
+        // (K0, K0 + 1), (K0 + 2, K0 + 3), ... two per launch; an odd width's
+        // last column on its own
+        {
+          KernelTimer kt(ctx, s, "chol_diag", diag_flops(K0), 0);
+          hipLaunchKernelGGL(k_panel_head, dim3(n_sys), dim3(256), 0, s, desc, st, (float*)A, (float*)Wt, Wpk,
+                             (__bf16*)Pk, K0, Wp, level, zf);
+          check_launch(ctx, s, "panel_head");
         }
-        if (k + 1 < Tmax) {
-          // credited: the column update of the tiles below the diagonal and their panel solve, and
-          // the next diagonal block inside the panel (its factorisation); algorithmic bytes: read
-          // those tiles and write their factor, read the next diagonal tile and write its factor
-          // and inverse (FP32)
-          const bool nd = k + 1 < K1;
-          KernelTimer kt(ctx, s, col_name, each([&](double m) {
-            const double rows = m - (k + 1) * NB, b = std::min<double>(NB, rows);
-            return rows > 0 ? 2.0 * rows * NB * (k - K0) * NB + rows * (double)NB * NB + (nd ? 2.0 * b * b * b / 3.0 : 0.0)
-                            : 0.0;
-          }), 1, each([&](double m) {
-            const double rows = m - (k + 1) * NB;
-            return rows > 0 ? 2.0 * rows * NB * sizeof(float) + (nd ? 3.0 * NB * NB * sizeof(float) : 0.0) : 0.0;
-          }));
-          const int do_pack = (k + 1 < K1 || K1 < Tmax) ? 1 : 0;
-          const int ng = ceil_div(Tmax - k - 1, 4);
-          hipLaunchKernelGGL(k_panel_col, dim3((unsigned)(NXCD * ceil_div(n_sys, NXCD) * ng)), dim3(256), 0, s, desc,
-                             st, (float*)A,
-                             (float*)Wt, Wpk, (__bf16*)Pk, K0, k, Wp, level, do_pack, nd ? 1 : 0, n_sys, ng, zf, spread);
-          check_launch(ctx, s, "panel_col");
+        int c = K0;
+        for (; c + 1 < K1 && c + 2 < Tmax; c += 2) {
+          KernelTimer kt(ctx, s, col_name, col_flops(c) + col_flops(c + 1), 1, col_bytes(c) + col_bytes(c + 1));
+          const int pack1 = (c + 2 < K1 || K1 < Tmax) ? 1 : 0;
+          const int ng = 1 + ceil_div(Tmax - c - 4, 4);
+          hipLaunchKernelGGL(k_panel_pair, dim3((unsigned)(NXCD * ceil_div(n_sys, NXCD) * ng)), dim3(256), 0, s, desc,
+                             st, (float*)A, (float*)Wt, Wpk, (__bf16*)Pk, K0, c, Wp, level, pack1, n_sys, ng, zf, spread);
+          check_launch(ctx, s, "panel_pair");
+        }
+        if ((K1 - K0) % 2 == 1 && K1 < Tmax) single_column(K1 - 1);
+      } else {
+        for (int k = K0; k < K1; ++k) {
+          if (k == K0) {
+            KernelTimer kt(ctx, s, "chol_diag", diag_flops(k), 0);
+            hipLaunchKernelGGL((k_potrf_diag<TS>), dim3(n_sys), dim3(DIAG_THREADS), 0, s, desc, st, A, Wt, k, level,
+                               (const __bf16*)Pk, K0, Wp, Wpk, zf);
+            check_launch(ctx, s, "potrf_diag");
+          }
+          if (k + 1 < Tmax) single_column(k);
         }
       }
       if (K1 < Tmax) {

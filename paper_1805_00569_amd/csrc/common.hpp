@@ -174,6 +174,7 @@ struct krr_ctx_s {
   hipStream_t side[kMaxFactorStreams - 1] = {};
   hipEvent_t side_ev[kMaxFactorStreams] = {};   // fork, then one join per side stream
   int factor_streams = 2;
+  int column_pairs = 1;
   bool in_call = false;
   // per stream the context has queued work on: an event recorded after that
   // work (see drain)

@@ -29,6 +29,7 @@ OPT_PANEL_TILES, OPT_SERIAL_FIT, OPT_SYNC_CHECK, OPT_TIMING, OPT_PERSISTENT, OPT
     0, 1, 2, 3, 4, 5, 6
 OPT_AUTOTUNE = 7
 OPT_FACTOR_STREAMS = 8
+OPT_COLUMN_PAIRS = 9
 
 
 class KrrError(RuntimeError):

@@ -1,0 +1,112 @@
+"""KRR_OPT_COLUMN_PAIRS: the mixed-precision launch sequence that updates two
+panel columns per launch (one pass over each tile row's packed operands, the
+diagonal blocks carried two columns ahead) against one column per launch.
+Every tile and diagonal block takes the same operations in the same order,
+so alpha, the refinement record, the fallback flags and any failure (status,
+pivot) must be identical bit for bit: even and odd panel widths (odd: the
+panel's last column runs alone), a width of two (head launch only), ragged
+systems whose tile rows end inside a pair, one and two factorisation
+streams, and systems that fall back to FP32 updates.  Both are also checked
+against the FP64 oracle on one partition."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1805_00569_amd import datagen, krr
+from _parity import ew
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _run(ctx, X, y, a, C, p, params, pairs):
+    ctx.set_option(krr.OPT_COLUMN_PAIRS, pairs)
+    try:
+        models, info, st = ctx.fit(X, y, a, C, p, params)
+    finally:
+        ctx.set_option(krr.OPT_COLUMN_PAIRS, 1)
+    alphas = [[m.alpha(j).cpu().numpy() for j in range(p)] for m in models]
+    rows = [(r["status"], r["failed_pivot"], r["refine_iters"], r["fallback"]) for r in info]
+    for m in models:
+        m.free()
+    return st, rows, alphas
+
+
+CASES = [
+    # name, n, d, p, sigma (None: median heuristic), panel, factor streams
+    ("ragged_w16", 24000, 12, 12, 2.0, 16, 1),
+    ("ragged_w16_two_streams", 24000, 12, 16, 2.0, 16, 2),
+    ("ragged_w5", 16000, 10, 10, 2.0, 5, 1),
+    ("ragged_w3", 12000, 8, 9, 1.5, 3, 2),
+    ("ragged_w2", 9000, 8, 8, 1.5, 2, 1),
+    ("ragged_w7_fallback", 12000, 10, 9, None, 7, 1),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_column_pairs_equal_single_columns(ctx, dev, case):
+    name, n, d, p, sigma, panel, fs = case
+    w = datagen.small(500 + n + p, n, d, k=300, p=p, comps=p, dtype=np.float32)
+    if sigma is None:
+        sigma = datagen.median_heuristic_sigma(w.X)
+    X, y = _t(w.X, dev), _t(w.y.astype(np.float32), dev)
+    C, a, sz = ctx.partition(X, p, "kmeans", lloyd_iters=6, seed=p)
+    sizes = sorted(sz.cpu().numpy().tolist())
+    print(f"column pairs: {name} sizes {sizes[0]}..{sizes[-1]} sigma={sigma:.3f} panel={panel} streams={fs}",
+          flush=True)
+    params = [krr.Params(sigma=sigma, lam=1e-2, prec="mixed", refine_tol=1e-8, max_refine=30),
+              krr.Params(sigma=sigma * 1.5, lam=1e-3, prec="mixed", refine_tol=1e-8, max_refine=30)]
+    ctx.set_option(krr.OPT_PANEL_TILES, panel)
+    ctx.set_option(krr.OPT_AUTOTUNE, 0)
+    ctx.set_option(krr.OPT_FACTOR_STREAMS, fs)
+    try:
+        st1, rows1, al1 = _run(ctx, X, y, a, C, p, params, 0)
+        st2, rows2, al2 = _run(ctx, X, y, a, C, p, params, 1)
+    finally:
+        ctx.set_option(krr.OPT_PANEL_TILES, 16)
+        ctx.set_option(krr.OPT_AUTOTUNE, 1)
+        ctx.set_option(krr.OPT_FACTOR_STREAMS, 2)
+    assert st1 == st2 == 0
+    assert rows1 == rows2
+    for q in range(len(params)):
+        for j in range(p):
+            assert np.array_equal(al1[q][j], al2[q][j]), (q, j)
+    # the largest partition against the oracle
+    j = int(np.argmax(sz.cpu().numpy()))
+    perm, off = O.gather(a.cpu().numpy(), p)
+    idx = perm[off[j]:off[j + 1]]
+    r = O.fit_one(w.X[idx].astype(np.float64), w.y[idx].astype(np.float64), params[0].sigma, params[0].lam)
+    err = ew(al2[0][j], r["alpha"])
+    print(f"  partition {j} (m={int(sz[j])}): alpha vs oracle {err:.2e}; fallbacks {sum(r[3] for r in rows2)}",
+          flush=True)
+    assert err <= 1e-6
+
+
+def test_column_pairs_report_the_same_failure(ctx, dev):
+    """A sigmoid setting whose systems are indefinite (Cholesky rejects them;
+    no LU requested): the same status and failed pivot from both launch
+    sequences, through the BF16 attempt and the FP32-update fallback."""
+    w = datagen.small(71, 2400, 6, k=100, p=4, comps=4, dtype=np.float32, spread=1.0)
+    X, y = _t(w.X, dev), _t(w.y.astype(np.float32), dev)
+    C, a, _ = ctx.partition(X, 4, "kmeans", lloyd_iters=5, seed=5)
+    params = [krr.Params(kernel="sigmoid", kernel_a=0.1, kernel_r=-0.1, lam=1.0, prec="mixed", refine_tol=1e-8,
+                         max_refine=20),
+              krr.Params(sigma=1.5, lam=1e-2, prec="mixed", refine_tol=1e-8, max_refine=20)]
+    ctx.set_option(krr.OPT_PANEL_TILES, 3)
+    ctx.set_option(krr.OPT_AUTOTUNE, 0)
+    try:
+        st1, rows1, al1 = _run(ctx, X, y, a, C, 4, params, 0)
+        st2, rows2, al2 = _run(ctx, X, y, a, C, 4, params, 1)
+    finally:
+        ctx.set_option(krr.OPT_PANEL_TILES, 16)
+        ctx.set_option(krr.OPT_AUTOTUNE, 1)
+    print(f"column pairs failure rows: {rows2}", flush=True)
+    assert st1 == st2 == krr.KRR_ENOTSPD
+    assert rows1 == rows2
+    assert any(r[0] == krr.KRR_ENOTSPD and r[1] > 0 for r in rows2[:4])
+    for j in range(4):
+        assert np.array_equal(al1[1][j], al2[1][j]), j
