@@ -57,10 +57,10 @@ HBM_PEAK = 8000.0  # GB/s
 # is reported as null.
 TRAFFIC = {
     "chol_column_bf16": {
-        "kernel": "k_panel_col",
+        "kernel": "k_panel_pair",
         "source": "paper_1805_00569_amd/csrc/cholesky.hip",
-        "sha256": "db4b0a29cad697ec59d97ffc824d7c3af980d6a2cad5661c0f2b717972dec686",
-        "fetch_kib": 58807.2, "write_kib": 39846.3, "fetch_scale": 2.0, "write_scale": 1.0,
+        "sha256": "bdc873ad670bc66087d980dee224ca029d82920014b7bfd1a7b7a78e366e51b4",
+        "fetch_kib": 74893.5, "write_kib": 80944.6, "fetch_scale": 2.0, "write_scale": 1.0,
     },
 }
 
