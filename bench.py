@@ -99,7 +99,10 @@ def main():
     ap.add_argument("--no-baselines", action="store_true", help="skip the plain/batched comparisons")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing on the host")
     ap.add_argument("--cpu-fits", type=int, default=4, help="oracle fits (one per partition) timed for the CPU baseline")
-    ap.add_argument("--panel", type=int, default=0, help="Cholesky panel width in 64-wide tiles (0: library default)")
+    ap.add_argument("--panel", type=int, default=0,
+                    help="Cholesky panel width in 64-wide tiles (0: the library's autotuner picks it for the "
+                         "workload's precision and system size, from trial fits of as many synthetic systems)")
+    ap.add_argument("--no-autotune", action="store_true", help="with --panel 0: the library's default width")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-legs", action="store_true", help="skip the plain, stress and ragged workloads")
     ap.add_argument("--no-dkrr", action="store_true", help="skip the single n = 131,072 system")
@@ -142,6 +145,16 @@ def main():
 
     params = settings(args.prec)
     n_fits = len(params) * P_PARTS
+    tuned = None
+    if not args.panel and not args.no_autotune:
+        # the library's panel-width autotuner for this workload's size class
+        # (trial fits of n_fits synthetic systems of n / p points), outside the
+        # timed region; the fits below take the width it records
+        t1 = time.perf_counter()
+        wdt, tms = ctx.autotune(args.prec, args.n // P_PARTS, X.shape[1], n_sys=n_fits)
+        tuned = {"panel_tiles": wdt, "trial_fit_ms": tms, "seconds": time.perf_counter() - t1}
+        print(f"# autotuned panel width {wdt} tiles ({tms:.2f} ms trial fit, {tuned['seconds']:.1f} s)",
+              file=sys.stderr, flush=True)
     state = {}
 
     def step(prec_params=params, phases=None):
@@ -209,7 +222,9 @@ def main():
                                "p=16 K-balance partitions of 4096, 3 sigma x 2 lambda = 96 fits per step, "
                                "select on 6554 held-out, predict 8192 test (nearest centre)",
                    "n": args.n, "d": d, "p": P_PARTS, "fits_per_step": n_fits, "precision": args.prec,
-                   "sigmas": SIGMAS, "lambdas": LAMBDAS, "lloyd_iters": LLOYD},
+                   "sigmas": SIGMAS, "lambdas": LAMBDAS, "lloyd_iters": LLOYD,
+                   "panel_tiles": args.panel if args.panel else (tuned["panel_tiles"] if tuned else 16),
+                   "panel_autotuned": tuned},
         "tflops": (flops_fit + flops_pred) / step_s / 1e12,
         "fit_status": state["status"],
         "max_refine_iters": max(r["refine_iters"] for r in info),
