@@ -4,6 +4,8 @@ through the C ABI against krr_predict on the same model and inputs -- the
 same kernels with the same launch shapes, so the values must agree bit for
 bit -- and against the FP64 oracle at the FP64 tolerance (1e-10), on two
 calls in a row, the second with fewer points, for every route."""
+import gc
+
 import numpy as np
 import pytest
 import torch
@@ -46,11 +48,19 @@ def test_noalloc_equals_predict_on_two_calls(fitted, route):
         shape = (k, p) if route == "all" else (k,)
         out = torch.full(shape, float("nan"), dtype=torch.float64, device=dev)
         rout = torch.full((k,), -7, dtype=torch.int32, device=dev)
-        torch.cuda.synchronize()
-        mem0, alloc0 = ctx.memory_in_use(), torch.cuda.memory_allocated(dev)
-        ctx.predict_noalloc(model, Xt, out, route=route, route_out=rout)
-        torch.cuda.synchronize()
-        assert ctx.memory_in_use() == mem0 and torch.cuda.memory_allocated(dev) == alloc0
+        # no collection inside the measured call: freeing an unreachable tensor
+        # left by earlier tests would move torch's count without any allocation
+        gc.collect()
+        gc.disable()
+        try:
+            torch.cuda.synchronize()
+            mem0, alloc0 = ctx.memory_in_use(), torch.cuda.memory_allocated(dev)
+            ctx.predict_noalloc(model, Xt, out, route=route, route_out=rout)
+            torch.cuda.synchronize()
+            mem1, alloc1 = ctx.memory_in_use(), torch.cuda.memory_allocated(dev)
+        finally:
+            gc.enable()
+        assert mem1 == mem0 and alloc1 == alloc0
         ref, rref = ctx.predict(model, Xt, route=route, want_route=True)
         got = out.cpu().numpy()
         assert np.array_equal(got, ref.cpu().numpy()), (route, k)
