@@ -58,6 +58,7 @@ HBM_PEAK = 8000.0  # GB/s
 TRAFFIC = {
     "chol_column_bf16": {
         "kernel": "k_panel_pair",
+        "panel_tiles": 16,
         "source": "paper_1805_00569_amd/csrc/cholesky.hip",
         "sha256": "bdc873ad670bc66087d980dee224ca029d82920014b7bfd1a7b7a78e366e51b4",
         "fetch_kib": 74893.5, "write_kib": 80944.6, "fetch_scale": 2.0, "write_scale": 1.0,
@@ -65,10 +66,10 @@ TRAFFIC = {
 }
 
 
-def _traffic_bytes(cls):
+def _traffic_bytes(cls, panel_tiles):
     import hashlib
     t = TRAFFIC.get(cls)
-    if t is None:
+    if t is None or t["panel_tiles"] != panel_tiles:   # bytes per launch depend on the panel width
         return None
     try:
         with open(os.path.join(ROOT, t["source"]), "rb") as f:
@@ -239,7 +240,7 @@ def main():
     step(phases=phases)
     kern = ctx.timing_report()
     ctx.set_option(krr.OPT_TIMING, 0)
-    out["roofline"] = roofline(timed_kernels, args.steps)
+    out["roofline"] = roofline(timed_kernels, args.steps, panel_tiles=out["config"]["panel_tiles"])
     out["roofline"]["factorisation"] = factorisation_summary(kern, sum(float(m) ** 3 / 3.0 for m in m_sizes),
                                                              "bf16" if args.prec == "mixed" else args.prec)
     out["phase_ms"] = {k: round(v * 1e3, 3) for k, v in phases.items()}
@@ -417,7 +418,7 @@ def factorisation_summary(kern, chol_flops, prec):
             "flops_per_step": chol_flops, "achieved_tflops": tf, "peak_tflops": PEAK[prec], "frac": tf / PEAK[prec]}
 
 
-def roofline(timed, steps, chol_flops_per_step=None):
+def roofline(timed, steps, chol_flops_per_step=None, panel_tiles=None):
     """Roofline entry of the kernel class with the most event time in the
     timed steps.  The Cholesky kernels (classes chol_*) are a dense
     contraction: they are priced against the matrix-core peak of their
@@ -458,7 +459,7 @@ def roofline(timed, steps, chol_flops_per_step=None):
     if busy > 0:
         out["busy_ms_per_step"] = rec["busy_ms"] / steps
         out["achieved_over_busy_time"] = (flops / busy / 1e12) if out["unit"] == "TFLOP/s" else (byts / busy / 1e9)
-    out["traffic"] = _traffic_bytes(name)
+    out["traffic"] = _traffic_bytes(name, panel_tiles)
     out["other_timed_classes_ms_per_step"] = {k: v["ms"] / steps for k, v in timed.items() if k != name}
     chol = {k: v for k, v in timed.items() if k.startswith("chol_")}
     if chol and chol_flops_per_step:

@@ -216,7 +216,8 @@ typedef enum {
  * dimensions at precision prec (krr_prec) for a set of panel widths (2 .. 64
  * tiles, at most the system's tile rows), and records the fastest for the
  * size class of m (tile rows rounded up to a power of two) and prec on the
- * context; later fits give each system the width of its own class (see
+ * context (a wider width replaces a narrower one only when its fit is more
+ * than 3 % faster: timing noise does not move the choice); later fits give each system the width of its own class (see
  * KRR_OPT_AUTOTUNE), so a system's result does not depend on the batch.  If
  * the environment variable KRR_TUNE_CACHE names a file, the record is
  * appended to it ("prec class width ms" per line) and contexts created later

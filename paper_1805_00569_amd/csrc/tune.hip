@@ -132,7 +132,11 @@ int run_autotune(krr_ctx ctx, hipStream_t s, int prec, int64_t m, int d, int n_s
         ts.push_back(ms);
       }
       std::sort(ts.begin(), ts.end());
-      if (ts[1] < best_t) {
+      // candidates ascend: a wider panel must be faster by more than the
+      // timing noise to replace a narrower one (ties keep the narrower width,
+      // which also needs the smaller pack)
+      constexpr double kTieMargin = 0.03;
+      if (ts[1] < best_t * (1.0 - kTieMargin)) {
         best_t = ts[1];
         best = w;
       }
