@@ -58,7 +58,7 @@ HBM_PEAK = 8000.0  # GB/s
 TRAFFIC = {
     "chol_column_bf16": {
         "kernel": "k_panel_pair",
-        "panel_tiles": 16,
+        "panel_tiles": 24,
         "source": "paper_1805_00569_amd/csrc/cholesky.hip",
         "sha256": "bdc873ad670bc66087d980dee224ca029d82920014b7bfd1a7b7a78e366e51b4",
         "fetch_kib": 74893.5, "write_kib": 80944.6, "fetch_scale": 2.0, "write_scale": 1.0,
@@ -101,9 +101,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing on the host")
     ap.add_argument("--cpu-fits", type=int, default=4, help="oracle fits (one per partition) timed for the CPU baseline")
     ap.add_argument("--panel", type=int, default=0,
-                    help="Cholesky panel width in 64-wide tiles (0: the library's autotuner picks it for the "
-                         "workload's precision and system size, from trial fits of as many synthetic systems)")
-    ap.add_argument("--no-autotune", action="store_true", help="with --panel 0: the library's default width")
+                    help="Cholesky panel width in 64-wide tiles (0: the library's default for the precision)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="with --panel 0: the width from the library's autotuner (trial fits of as many synthetic "
+                         "systems of the workload's size)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-legs", action="store_true", help="skip the plain, stress and ragged workloads")
     ap.add_argument("--no-dkrr", action="store_true", help="skip the single n = 131,072 system")
@@ -147,7 +148,7 @@ def main():
     params = settings(args.prec)
     n_fits = len(params) * P_PARTS
     tuned = None
-    if not args.panel and not args.no_autotune:
+    if not args.panel and args.autotune:
         # the library's panel-width autotuner for this workload's size class
         # (trial fits of n_fits synthetic systems of n / p points), outside the
         # timed region; the fits below take the width it records
@@ -224,7 +225,8 @@ def main():
                                "select on 6554 held-out, predict 8192 test (nearest centre)",
                    "n": args.n, "d": d, "p": P_PARTS, "fits_per_step": n_fits, "precision": args.prec,
                    "sigmas": SIGMAS, "lambdas": LAMBDAS, "lloyd_iters": LLOYD,
-                   "panel_tiles": args.panel if args.panel else (tuned["panel_tiles"] if tuned else 16),
+                   "panel_tiles": args.panel if args.panel else (tuned["panel_tiles"] if tuned else
+                                                                 {"mixed": 24}.get(args.prec, 16)),
                    "panel_autotuned": tuned},
         "tflops": (flops_fit + flops_pred) / step_s / 1e12,
         "fit_status": state["status"],

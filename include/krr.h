@@ -169,7 +169,8 @@ typedef struct {
 
 /* Tunables (krr_set_option).  Values apply to later calls on the context. */
 typedef enum {
-  KRR_OPT_PANEL_TILES = 0,  /* Cholesky panel width in 64-wide tiles (1..64, default 16) */
+  KRR_OPT_PANEL_TILES = 0,  /* Cholesky panel width in 64-wide tiles (1..64; 0, the default:
+                               24 in mixed precision, 16 in FP32 and FP64) */
   KRR_OPT_SERIAL_FIT = 1,   /* 1: factor the systems one after another, one launch
                                sequence per (partition, setting) -- the plain per-partition
                                baseline; 0 (default): one batched launch sequence */
@@ -216,8 +217,7 @@ typedef enum {
  * dimensions at precision prec (krr_prec) for a set of panel widths (2 .. 64
  * tiles, at most the system's tile rows), and records the fastest for the
  * size class of m (tile rows rounded up to a power of two) and prec on the
- * context (a wider width replaces a narrower one only when its fit is more
- * than 3 % faster: timing noise does not move the choice); later fits give each system the width of its own class (see
+ * context; later fits give each system the width of its own class (see
  * KRR_OPT_AUTOTUNE), so a system's result does not depend on the batch.  If
  * the environment variable KRR_TUNE_CACHE names a file, the record is
  * appended to it ("prec class width ms" per line) and contexts created later

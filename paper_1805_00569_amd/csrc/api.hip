@@ -375,7 +375,7 @@ krr_status krr_set_option(krr_ctx ctx, int32_t option, int64_t value) {
   return guarded(ctx, [&] {
     switch (option) {
       case KRR_OPT_PANEL_TILES:
-        KRR_REQUIRE(value >= 1 && value <= 64, "panel width must be 1..64 tiles");
+        KRR_REQUIRE(value >= 0 && value <= 64, "panel width must be 1..64 tiles (0: the precision's default)");
         ctx->panel_tiles = (int)value;
         break;
       case KRR_OPT_SERIAL_FIT:

@@ -2034,7 +2034,8 @@ void persist_restore_plan(krr_ctx ctx, hipStream_t s, const krr_ctx_s::GraphEntr
 // otherwise they are left untouched and the call returns false.
 bool cholesky_factor(krr_ctx ctx, hipStream_t s, int prec, const SysDesc* desc, SysStatus* st, int n_sys, int Tmax,
                      void* A, void* Wt, int level, bool bf16, const SysDesc* hdesc, void* pack, double* zfwd) {
-  const int Wp = ctx->force_wp > 0 ? ctx->force_wp : ctx->panel_tiles;   // the multi-launch path's width
+  // the multi-launch path's width
+  const int Wp = ctx->force_wp > 0 ? ctx->force_wp : (ctx->panel_tiles > 0 ? ctx->panel_tiles : default_panel_tiles(prec));
   if (prec == KRR_PREC_FP64) {
     factor_t<double>(ctx, s, desc, st, n_sys, Tmax, (double*)A, (double*)Wt, false, Wp, level, hdesc, nullptr, nullptr);
     return false;

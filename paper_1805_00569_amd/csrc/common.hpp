@@ -62,6 +62,11 @@ __device__ __forceinline__ double poly_kernel(double g, double a, double r, int 
   return v;
 }
 
+// Default Cholesky panel width (64-wide tiles) of a precision: measured
+// fastest for the batched fits of systems of a few thousand points (mixed
+// precision: 24; the FP32 and FP64 matrix-core paths: 16).
+constexpr int default_panel_tiles(int prec) { return prec == KRR_PREC_MIXED ? 24 : 16; }
+
 // Per-system descriptor of one batched solve (K_s + lambda_s I) alpha_s = y_s.
 struct SysDesc {
   int32_t m;        // number of points in the partition
@@ -159,7 +164,7 @@ struct krr_ctx_s {
   size_t cache_bytes = 0;
   int n_models = 0;
   int n_datas = 0;
-  int panel_tiles = 16;
+  int panel_tiles = 0;   // KRR_OPT_PANEL_TILES; 0: the precision's default (default_panel_tiles)
   int serial_fit = 0;
   int sync_check = 0;
   void* pinned = nullptr;

@@ -499,10 +499,10 @@ krr_status krr_server_submit_fit(krr_server S, const float* X, const float* y, i
   r->rows = m;
   r->d = d;
   r->params = P;
-  r->need = fit_need(m, d, P.prec, 16);
+  r->need = fit_need(m, d, P.prec, default_panel_tiles(P.prec));
   if (S->cfg.hbm_budget_bytes != 0 && r->need > S->fit_share) {
     delete r;
-    set_error(S, "fit request alone (" + std::to_string(fit_need(m, d, P.prec, 16)) +
+    set_error(S, "fit request alone (" + std::to_string(fit_need(m, d, P.prec, default_panel_tiles(P.prec))) +
                      " bytes) exceeds a fit worker's share of the HBM budget (" + std::to_string(S->fit_share) +
                      " bytes)");
     return KRR_EBUDGET;

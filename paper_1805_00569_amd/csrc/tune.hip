@@ -63,9 +63,10 @@ int size_class(int64_t T) {
 }  // namespace
 
 int tuned_panel(krr_ctx ctx, int prec, int64_t m) {
-  if (!ctx->autotune || m <= 0) return ctx->panel_tiles;
+  const int dflt = ctx->panel_tiles > 0 ? ctx->panel_tiles : default_panel_tiles(prec);
+  if (!ctx->autotune || m <= 0) return dflt;
   const auto it = ctx->tune.find(std::make_pair(prec, size_class(ceil_div(m, NB))));
-  return it == ctx->tune.end() ? ctx->panel_tiles : it->second;
+  return it == ctx->tune.end() ? dflt : it->second;
 }
 
 void tune_load(krr_ctx ctx) {
@@ -111,7 +112,7 @@ int run_autotune(krr_ctx ctx, hipStream_t s, int prec, int64_t m, int d, int n_s
   KRR_HIP(hipEventCreate(&e0));
   KRR_HIP(hipEventCreate(&e1));
   std::vector<krr_part_info> info(n_sys);
-  int best = ctx->panel_tiles;
+  int best = ctx->panel_tiles > 0 ? ctx->panel_tiles : default_panel_tiles(prec);
   double best_t = INFINITY;
   const int saved_force = ctx->force_wp, saved_timing = ctx->timing, saved_graphs = ctx->graphs;
   ctx->timing = 0;
@@ -132,11 +133,7 @@ int run_autotune(krr_ctx ctx, hipStream_t s, int prec, int64_t m, int d, int n_s
         ts.push_back(ms);
       }
       std::sort(ts.begin(), ts.end());
-      // candidates ascend: a wider panel must be faster by more than the
-      // timing noise to replace a narrower one (ties keep the narrower width,
-      // which also needs the smaller pack)
-      constexpr double kTieMargin = 0.03;
-      if (ts[1] < best_t * (1.0 - kTieMargin)) {
+      if (ts[1] < best_t) {
         best_t = ts[1];
         best = w;
       }

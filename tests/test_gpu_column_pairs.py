@@ -67,7 +67,7 @@ def test_column_pairs_equal_single_columns(ctx, dev, case):
         st1, rows1, al1 = _run(ctx, X, y, a, C, p, params, 0)
         st2, rows2, al2 = _run(ctx, X, y, a, C, p, params, 1)
     finally:
-        ctx.set_option(krr.OPT_PANEL_TILES, 16)
+        ctx.set_option(krr.OPT_PANEL_TILES, 0)
         ctx.set_option(krr.OPT_AUTOTUNE, 1)
         ctx.set_option(krr.OPT_FACTOR_STREAMS, 2)
     assert st1 == st2 == 0
@@ -102,7 +102,7 @@ def test_column_pairs_report_the_same_failure(ctx, dev):
         st1, rows1, al1 = _run(ctx, X, y, a, C, 4, params, 0)
         st2, rows2, al2 = _run(ctx, X, y, a, C, 4, params, 1)
     finally:
-        ctx.set_option(krr.OPT_PANEL_TILES, 16)
+        ctx.set_option(krr.OPT_PANEL_TILES, 0)
         ctx.set_option(krr.OPT_AUTOTUNE, 1)
     print(f"column pairs failure rows: {rows2}", flush=True)
     assert st1 == st2 == krr.KRR_ENOTSPD

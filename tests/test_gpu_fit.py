@@ -65,7 +65,7 @@ def test_ragged_partitions_fp64(ctx, dev, n, d, p, panel):
         params = [krr.Params(sigma=1.5, lam=1e-2, prec="fp64"), krr.Params(sigma=0.7, lam=1e-3, prec="fp64")]
         models, info, st, oms, X, a = _fit_both(ctx, dev, w, p, params, method="kmeans", iters=8, seed=n)
     finally:
-        ctx.set_option(krr.OPT_PANEL_TILES, 16)
+        ctx.set_option(krr.OPT_PANEL_TILES, 0)
     assert st == 0
     for q in range(2):
         for j in range(p):
@@ -341,7 +341,7 @@ def test_mixed_ragged_partitions_panels(ctx, dev, panel):
                   krr.Params(sigma=0.7, lam=1e-3, prec="mixed", refine_tol=1e-8, max_refine=40)]
         models, info, st, oms, X, a = _fit_both(ctx, dev, w, 5, params, method="kmeans", iters=8, seed=7)
     finally:
-        ctx.set_option(krr.OPT_PANEL_TILES, 16)
+        ctx.set_option(krr.OPT_PANEL_TILES, 0)
     assert st == 0, info
     sizes = np.bincount(a, minlength=5)
     assert len(set(-(-sizes // 64))) > 1   # systems of different tile counts
@@ -400,7 +400,7 @@ def test_large_system_wide_panel(ctx, dev, prec):
         models, info, st = ctx.fit(Xd, _t(yg, dev), a, C, 1,
                                    [krr.Params(sigma=0.5, lam=1e-2, prec=prec, refine_tol=1e-8, max_refine=40)])
     finally:
-        ctx.set_option(krr.OPT_PANEL_TILES, 16)
+        ctx.set_option(krr.OPT_PANEL_TILES, 0)
     assert st == 0 and info[0]["status"] == 0
     err = ew(models[0].alpha(0).cpu().numpy(), alpha_ref)
     assert err < (1e-10 if prec == "fp64" else 1e-6), err

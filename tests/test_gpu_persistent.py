@@ -62,7 +62,7 @@ def test_persistent_equals_launch_sequence(ctx, dev, case):
         m1, i1, s1, a1 = _fit(ctx, X, y, a, C, p, params, True)
         m0, i0, s0, a0 = _fit(ctx, X, y, a, C, p, params, False)
     finally:
-        ctx.set_option(krr.OPT_PANEL_TILES, 16)
+        ctx.set_option(krr.OPT_PANEL_TILES, 0)
     assert s1 == s0 == 0
     for q in range(2):
         for j in range(p):
