@@ -60,8 +60,8 @@ TRAFFIC = {
         "kernel": "k_panel_pair",
         "panel_tiles": 24,
         "source": "paper_1805_00569_amd/csrc/cholesky.hip",
-        "sha256": "bdc873ad670bc66087d980dee224ca029d82920014b7bfd1a7b7a78e366e51b4",
-        "fetch_kib": 74893.5, "write_kib": 80944.6, "fetch_scale": 2.0, "write_scale": 1.0,
+        "sha256": "75537a54ca7d13b1cc6bce39a6e39e1195a50500ffa91dbcdb3812478e7a11e2",
+        "fetch_kib": 98383.3, "write_kib": 81160.8, "fetch_scale": 2.0, "write_scale": 1.0,
     },
 }
 
