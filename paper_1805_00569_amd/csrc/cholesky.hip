@@ -1183,6 +1183,20 @@ __global__ __launch_bounds__(256, 2) void k_panel_pair(const SysDesc* __restrict
 // The head of a panel that runs as column pairs, one workgroup per system:
 // diagonal block K0, tile (K0+1, K0) (its panel solve; no update inside the
 // panel yet), diagonal block K0 + 1.
+__device__ __forceinline__ void phead_body(const SysDesc& D, int s, SysStatus* __restrict__ st, float* __restrict__ A,
+                                           float* __restrict__ Wt, __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk,
+                                           int K0, int Wp, int wps, double* __restrict__ zf, PcolLds& lds) {
+  diag_block<float>(D, s, st, A, Wt, K0, Pk, K0, Wp, wps, Wpk, zf, lds.dg, threadIdx.x);
+  if (K0 + 1 >= D.T || K0 + 1 >= K0 + Wp) return;
+  __syncthreads();
+  if (lds.dg.fail) return;
+  __syncthreads();
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (w == 0) panel_col_tile(D, s, K0 + 1, lane, A, Wpk, Pk, K0, K0, Wp, wps, 1, zf, lds.sC[0]);
+  __syncthreads();
+  diag_block<float>(D, s, st, A, Wt, K0 + 1, Pk, K0, Wp, wps, Wpk, zf, lds.dg, threadIdx.x);
+}
+
 __global__ __launch_bounds__(256) void k_panel_head(const SysDesc* __restrict__ desc, SysStatus* __restrict__ st,
                                                     float* __restrict__ A, float* __restrict__ Wt,
                                                     __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk, int K0, int Wp,
@@ -1191,15 +1205,7 @@ __global__ __launch_bounds__(256) void k_panel_head(const SysDesc* __restrict__ 
   const SysDesc D = desc[s];
   if (K0 >= D.T || st[s].status != 0 || D.level != level) return;
   __shared__ __align__(16) PcolLds lds;
-  diag_block<float>(D, s, st, A, Wt, K0, Pk, K0, Wp, Wp, Wpk, zf, lds.dg, threadIdx.x);
-  if (K0 + 1 >= D.T || K0 + 1 >= K0 + Wp) return;
-  __syncthreads();
-  if (lds.dg.fail) return;
-  __syncthreads();
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (w == 0) panel_col_tile(D, s, K0 + 1, lane, A, Wpk, Pk, K0, K0, Wp, Wp, 1, zf, lds.sC[0]);
-  __syncthreads();
-  diag_block<float>(D, s, st, A, Wt, K0 + 1, Pk, K0, Wp, Wp, Wpk, zf, lds.dg, threadIdx.x);
+  phead_body(D, s, st, A, Wt, Wpk, Pk, K0, Wp, Wp, zf, lds);
 }
 
 // Super-tile order of the trailing update: bands of TRAIL_BAND super-rows,
@@ -1409,6 +1415,24 @@ __device__ __noinline__ void persist_pcol(const SysDesc* __restrict__ desc, int 
   pcol_body(D, s, st, A, Wt, Wpk, Pk, K0, k, D.wp, wps, do_pack, diag_next, g, zf, lds.pc);
 }
 
+__device__ __noinline__ void persist_phead(const SysDesc* __restrict__ desc, int s, SysStatus* __restrict__ st,
+                                           float* __restrict__ A, float* __restrict__ Wt, __bf16* __restrict__ Wpk,
+                                           __bf16* __restrict__ Pk, int K0, int wps, double* __restrict__ zf,
+                                           lds_ptr lp) {
+  PersistLds& lds = *(PersistLds*)lp;
+  const SysDesc D = desc[s];
+  phead_body(D, s, st, A, Wt, Wpk, Pk, K0, D.wp, wps, zf, lds.pc);
+}
+
+__device__ __noinline__ void persist_ppair(const SysDesc* __restrict__ desc, int s, SysStatus* __restrict__ st,
+                                           float* __restrict__ A, float* __restrict__ Wt, __bf16* __restrict__ Wpk,
+                                           __bf16* __restrict__ Pk, int K0, int c, int wps, int pack1, int g,
+                                           double* __restrict__ zf, lds_ptr lp) {
+  PersistLds& lds = *(PersistLds*)lp;
+  const SysDesc D = desc[s];
+  ppair_body(D, s, st, A, Wt, Wpk, Pk, K0, c, D.wp, wps, pack1, g, zf, lds.pc);
+}
+
 __device__ __noinline__ void persist_trail(const SysDesc* __restrict__ desc, int s, float* __restrict__ A,
                                            const __bf16* __restrict__ Pk, int K0, int K1, int b, lds_ptr lp) {
   PersistLds& lds = *(PersistLds*)lp;
@@ -1552,6 +1576,10 @@ __global__ __launch_bounds__(256, 2) void k_chol_persist(const SysDesc* __restri
                        (T.flags & PF_DIAG_NEXT) ? 1 : 0, T.b, zf, lp);
         else if (T.kind == PT_PTRAIL)
           persist_trail(desc, T.s, (float*)A, Pk, T.a, T.c, T.b, lp);
+        else if (T.kind == PT_PHEAD)
+          persist_phead(desc, T.s, st, (float*)A, (float*)Wt, Wpk, Pk, T.a, wps, zf, lp);
+        else if (T.kind == PT_PPAIR)
+          persist_ppair(desc, T.s, st, (float*)A, (float*)Wt, Wpk, Pk, T.c, T.a, wps, T.flags & PF_PACK, T.b, zf, lp);
       } else {
         if (T.kind == PT_DIAG) {
           persist_diag<TS>(desc, T.s, st, A, Wt, T.a, lp);
@@ -1632,12 +1660,14 @@ int persist_grid(krr_ctx ctx) {
 // replays re-install the plan their launch reads).  Replacing a slot's plan
 // waits for the context's queued work, which may still read it; inside a
 // graph capture that is an error (ESTATE), so only a free slot is taken there.
+// mode: 0 the matrix-core path, 1 the packed path, 2 the packed path in
+// column-pair stages.
 int persist_upload(krr_ctx ctx, hipStream_t s, const std::vector<int>& T, const std::vector<int>& act,
-                   const std::vector<int>& Wp, bool packed, int tsize, int force_slot) {
+                   const std::vector<int>& Wp, int mode, int tsize, int force_slot) {
   std::vector<int> key = T;
   key.insert(key.end(), act.begin(), act.end());
   key.insert(key.end(), Wp.begin(), Wp.end());
-  key.push_back(packed ? 1 : 0);
+  key.push_back(mode);
   key.push_back(tsize);
   auto& pc = ctx->persist;
   constexpr int NS = krr_ctx_s::PersistCache::kSlots;
@@ -1665,7 +1695,7 @@ int persist_upload(krr_ctx ctx, hipStream_t s, const std::vector<int>& T, const 
     if (ctx->capturing) fail(KRR_ESTATE, "persistent plan cache full inside a graph capture");
     drain(ctx);   // queued work may still read this slot's plan or its staging buffer
   }
-  const PPlan P = build_plan(T, act, Wp, packed, NXCD);
+  const PPlan P = build_plan(T, act, Wp, mode != 0, NXCD, mode == 2);
   const size_t tb = P.tasks.size() * sizeof(PTask), qb = P.qoff.size() * sizeof(int32_t);
   const std::string name = "persist_plan" + std::to_string(slot);
   char* dev = (char*)ws_get(ctx, name, std::max<size_t>(tb + qb + 256, 512));
@@ -1682,7 +1712,7 @@ int persist_upload(krr_ctx ctx, hipStream_t s, const std::vector<int>& T, const 
   pl.T = T;
   pl.act = act;
   pl.wp = Wp;
-  pl.packed = packed ? 1 : 0;
+  pl.packed = mode;
   pl.tsize = tsize;
   pl.used = ++pc.clock;
   return slot;
@@ -1703,7 +1733,7 @@ void factor_persistent(krr_ctx ctx, hipStream_t s, const SysDesc* desc, SysStatu
     act[i] = hdesc[i].level == level ? 1 : 0;
     wp[i] = hdesc[i].wp;
   }
-  const int slot = persist_upload(ctx, s, T, act, wp, packed, (int)sizeof(TS), -1);
+  const int slot = persist_upload(ctx, s, T, act, wp, packed ? (ctx->column_pairs ? 2 : 1) : 0, (int)sizeof(TS), -1);
   const auto& pc = ctx->persist.slot[slot];
   if (ctx->capturing) ctx->persist.captured.push_back(slot);
   if (pc.ntasks == 0) return;
@@ -2016,7 +2046,7 @@ void persist_capture_aborted(krr_ctx ctx) {
 void persist_restore_plan(krr_ctx ctx, hipStream_t s, const krr_ctx_s::GraphEntry& e) {
   for (const auto& [sl, pl] : e.plans) {
     if (ctx->persist.slot[sl].key == pl.key) continue;
-    persist_upload(ctx, s, pl.T, pl.act, pl.wp, pl.packed != 0, pl.tsize, sl);
+    persist_upload(ctx, s, pl.T, pl.act, pl.wp, pl.packed, pl.tsize, sl);
     if (ctx->persist.slot[sl].tasks != pl.tasks)
       fail(KRR_ESTATE, "the persistent plan of a captured graph could not be restored");
   }

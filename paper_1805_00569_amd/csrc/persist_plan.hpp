@@ -40,11 +40,14 @@ enum PTaskKind : int32_t {
   PT_PTRAIL = 2,  // packed trailing update: panel start a = K0, super-tile b, first trailing row c = K1
   PT_COL = 3,     // column update of tile (a = i, b = k) over the panel columns [c = K0, k)
   PT_TRSM = 4,    // panel solve of tile (a = i, b = k)
-  PT_TRI = 5      // trailing update: triangle index a, panel [b = K0, c = K1)
+  PT_TRI = 5,     // trailing update: triangle index a, panel [b = K0, c = K1)
+  PT_PHEAD = 6,   // packed panel head (column pairs): diagonal block a = K0, tile (K0+1, K0), diagonal block K0 + 1
+  PT_PPAIR = 7    // packed column pair a = c, c + 1, tile-row group b = g (0: rows c+2, c+3 and the diagonal
+                  // chain two columns ahead; g > 0: rows c+4g .. +3), panel start c = K0
 };
 
 enum PTaskFlags : int32_t {
-  PF_PACK = 1,       // PT_PCOL: write the BF16 operand fragments of the column
+  PF_PACK = 1,       // PT_PCOL: write the BF16 operand fragments of the column (PT_PPAIR: of column c + 1)
   PF_DIAG_NEXT = 2   // PT_PCOL, group 0: then factor diagonal block k + 1
 };
 
@@ -65,12 +68,15 @@ struct PPlan {
 
 // Stages of one system with T tile rows, panel width Wp.  packed: the BF16
 // packed path (diagonal block, then one stage per panel column with the next
-// diagonal block carried by group 0, then the packed trailing update);
+// diagonal block carried by group 0, then the packed trailing update; with
+// `pairs`, a panel of two or more columns runs as its head, one stage per
+// pair of columns and, for an odd width, its last column on its own -- the
+// stages of the launch sequence with column pairs);
 // otherwise the matrix-core path (per column: column update, diagonal block,
 // panel solve; then the trailing triangle).  `work` receives a relative work
 // estimate per stage.
 inline void plan_stages(int s, int T, int Wp, bool packed, std::vector<std::vector<PTask>>& stages,
-                        std::vector<double>& work) {
+                        std::vector<double>& work, bool pairs = false) {
   auto add = [&](std::vector<PTask>&& st, double w) {
     stages.push_back(std::move(st));
     work.push_back(w);
@@ -78,7 +84,28 @@ inline void plan_stages(int s, int T, int Wp, bool packed, std::vector<std::vect
   const double tile3 = 64.0 * 64.0 * 64.0;
   for (int K0 = 0; K0 < T; K0 += Wp) {
     const int K1 = std::min(K0 + Wp, T);
-    if (packed) {
+    if (packed && pairs && K1 - K0 >= 2) {
+      add({PTask{PT_PHEAD, s, K0, 0, 0, 0, 0, 0}}, tile3 * 3.0);
+      for (int c = K0; c + 1 < K1 && c + 2 < T; c += 2) {
+        const int ng = 1 + std::max(0, (T - c - 4 + 3) / 4);
+        const int32_t fl = (c + 2 < K1 || K1 < T) ? PF_PACK : 0;
+        std::vector<PTask> st;
+        for (int g = 0; g < ng; ++g) st.push_back(PTask{PT_PPAIR, s, c, g, K0, fl, 0, 0});
+        add(std::move(st), tile3 * (double)(T - c - 2) * (2.0 + 2.0 * (c - K0)));
+      }
+      if ((K1 - K0) % 2 == 1 && K1 < T) {
+        const int k = K1 - 1, ng = (T - k - 1 + 3) / 4;
+        std::vector<PTask> st;
+        for (int g = 0; g < ng; ++g) st.push_back(PTask{PT_PCOL, s, k, g, K0, PF_PACK, 0, 0});
+        add(std::move(st), tile3 * (double)(T - k - 1) * (1.0 + 2.0 * (k - K0)));
+      }
+      if (K1 < T) {
+        const int R = T - K1, NS = (R + 1) / 2, ntri = NS * (NS + 1) / 2;
+        std::vector<PTask> st;
+        for (int b = 0; b < ntri; ++b) st.push_back(PTask{PT_PTRAIL, s, K0, b, K1, 0, 0, 0});
+        add(std::move(st), tile3 * 2.0 * (K1 - K0) * (double)R * (R + 1) / 2.0);
+      }
+    } else if (packed) {
       add({PTask{PT_DIAG, s, K0, K0, 0, 0, 0, 0}}, tile3);
       for (int k = K0; k < K1; ++k) {
         if (k + 1 >= T) continue;
@@ -121,9 +148,9 @@ inline void plan_stages(int s, int T, int Wp, bool packed, std::vector<std::vect
 
 // Plan for the systems with T[s] > 0 and active[s] != 0 (the others get no
 // task); system s takes panels of Wp[s] tiles.  nq_max: 8 (one queue per
-// XCD) or 1.
+// XCD) or 1.  pairs: the packed path's column-pair stages.
 inline PPlan build_plan(const std::vector<int>& T, const std::vector<int>& active, const std::vector<int>& Wp,
-                        bool packed, int nq_max) {
+                        bool packed, int nq_max, bool pairs = false) {
   const int n = (int)T.size();
   PPlan P;
   P.total.assign(n, 0);
@@ -140,7 +167,7 @@ inline PPlan build_plan(const std::vector<int>& T, const std::vector<int>& activ
     ++n_act;
     std::vector<std::vector<PTask>> st;
     std::vector<double> w;
-    plan_stages(s, T[s], Wp[s], packed, st, w);
+    plan_stages(s, T[s], Wp[s], packed, st, w, pairs);
     double left = std::accumulate(w.begin(), w.end(), 0.0);
     tot[s] = left;
     int need = 0;

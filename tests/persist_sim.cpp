@@ -11,7 +11,7 @@
 // exactly (every tile below the diagonal solved once, every diagonal block
 // factored once, every trailing tile updated once per panel).
 //
-// Usage: persist_sim <seed> <workers> <packed 0|1> <Wp> <T_0> <T_1> ...
+// Usage: persist_sim <seed> <workers> <mode 0|1|2> <Wp> <T_0> <T_1> ...  (mode 2: column pairs)
 // (Wp = 0: every system draws its own panel width in [1, 24])
 // Prints "OK <tasks> <makespan> <queues>" or "FAIL <reason>".
 #include <cstdio>
@@ -36,7 +36,8 @@ int main(int argc, char** argv) {
   if (argc < 6) return fail("usage");
   const unsigned seed = (unsigned)std::atoi(argv[1]);
   const int W = std::atoi(argv[2]);
-  const bool packed = std::atoi(argv[3]) != 0;
+  const int mode = std::atoi(argv[3]);   // 0 matrix-core path, 1 packed, 2 packed with column pairs
+  const bool packed = mode != 0;
   const int Wp = std::atoi(argv[4]);
   std::vector<int> T, act;
   for (int i = 5; i < argc; ++i) {
@@ -48,7 +49,7 @@ int main(int argc, char** argv) {
   std::vector<int> Wps(n, Wp);
   for (int s = 0; s < n; ++s)
     if (Wp == 0) Wps[s] = 1 + (int)(wrng() % 24u);
-  const PPlan P = build_plan(T, act, Wps, packed, 8);
+  const PPlan P = build_plan(T, act, Wps, packed, 8, mode == 2);
   const int nt = (int)P.tasks.size();
   // coverage of each system's tasks
   for (int s = 0; s < n; ++s) {
@@ -67,6 +68,30 @@ int main(int argc, char** argv) {
           if (i < Ts) solved[{i, t.a}]++;
         }
         if (t.flags & PF_DIAG_NEXT) diag[t.a + 1]++;
+      }
+      if (t.kind == PT_PHEAD) {
+        const int K0 = t.a, kend = std::min(K0 + Wps[s], Ts);
+        diag[K0]++;
+        if (K0 + 1 < kend) {
+          solved[{K0 + 1, K0}]++;
+          diag[K0 + 1]++;
+        }
+      }
+      if (t.kind == PT_PPAIR) {
+        const int c = t.a, g = t.b, K0 = t.c, kend = std::min(K0 + Wps[s], Ts);
+        const int r0 = g == 0 ? c + 2 : c + 4 * g, nr = g == 0 ? 2 : 4;
+        for (int w = 0; w < nr; ++w) {
+          const int i = r0 + w;
+          if (i < Ts) {
+            solved[{i, c}]++;
+            solved[{i, c + 1}]++;
+          }
+        }
+        if (g == 0 && c + 2 < kend) diag[c + 2]++;
+        if (g == 0 && c + 3 < kend) {
+          solved[{c + 3, c + 2}]++;
+          diag[c + 3]++;
+        }
       }
       if (t.kind == PT_TRSM) solved[{t.a, t.b}]++;
       if (t.kind == PT_PTRAIL) {

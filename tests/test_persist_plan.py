@@ -4,7 +4,8 @@ tests/persist_sim.cpp: every task taken once, no deadlock under random task
 times with own-queue-first dispatch, a task starts only after its system's
 earlier stages, every system runs on the one XCD that owns its queue (also
 when only some XCDs hold workers and the others' queues are claimed), and
-the tasks of each system cover its blocked factorisation exactly.  Batches: the balanced workload (96 systems of 64
+the tasks of each system cover its blocked factorisation exactly (one column
+per stage, or the column-pair stages).  Batches: the balanced workload (96 systems of 64
 tile rows), ragged K-means-sized batches (sizes up to 219 tile rows, i.e.
 m = 14,000), one very large system, and tiny or degenerate shapes."""
 import os
@@ -41,14 +42,16 @@ def _ragged_tiles(seed, n_sys=32):
     return np.ceil(m / 64).astype(int)
 
 
-@pytest.mark.parametrize("packed", [True, False])
+# packed: 0 the FP32/FP64 matrix-core path, 1 the BF16 packed path, 2 the
+# packed path with column-pair stages
+@pytest.mark.parametrize("packed", [1, 0, 2])
 def test_balanced_batch(sim, packed):
     out = _run(sim, 1, 512, packed, 16, [64] * 96)
     assert out[3] == "8"   # one queue per XCD
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
-@pytest.mark.parametrize("packed", [True, False])
+@pytest.mark.parametrize("packed", [1, 0, 2])
 def test_ragged_batches(sim, seed, packed):
     _run(sim, 10 + seed, 512, packed, 16, _ragged_tiles(seed))
 
@@ -57,19 +60,24 @@ def test_ragged_batches(sim, seed, packed):
 def test_few_workers_and_odd_panels(sim, workers):
     _run(sim, 5, workers, True, 5, [13, 1, 2, 40, 7, 7, 9, 3, 64])
     _run(sim, 6, workers, False, 3, [13, 1, 2, 40, 7])
+    _run(sim, 7, workers, 2, 5, [13, 1, 2, 40, 7, 7, 9, 3, 64])
+    _run(sim, 8, workers, 2, 2, [13, 1, 2, 3, 4, 40])
 
 
 def test_one_large_system(sim):
     out = _run(sim, 7, 512, True, 16, [256])
     assert out[3] == "1"   # fewer systems than XCDs: one shared queue
+    out = _run(sim, 7, 512, 2, 24, [256])
+    assert out[3] == "1"
 
 
 def test_single_tiles(sim):
     _run(sim, 8, 8, True, 16, [1] * 9)
     _run(sim, 9, 8, False, 16, [1, 1])
+    _run(sim, 10, 8, 2, 16, [1] * 9 + [2, 3])
 
 
-@pytest.mark.parametrize("packed", [True, False])
+@pytest.mark.parametrize("packed", [1, 0, 2])
 def test_per_system_panel_widths(sim, packed):
     """Each system with its own panel width (as the autotuner may choose)."""
     _run(sim, 21, 256, packed, 0, _ragged_tiles(4, n_sys=24))
