@@ -1089,6 +1089,237 @@ __global__ __launch_bounds__(256) void k_panel_col(const SysDesc* __restrict__ d
   pcol_body(D, s, st, A, Wt, Wpk, Pk, K0, k, Wp, Wp, do_pack, diag_next, g, zf, lds);
 }
 
+// Rows c + 2 (waves 0, 1) and c + 3 (waves 2, 3) of columns c and c + 1 for
+// the chain workgroup of a column-pair launch, each row split over two waves
+// by column-block halves (wave parity hf: column blocks 2 hf and 2 hf + 1 of
+// the tiles), the row's tile shared through its LDS tile.  With `park`, row
+// c + 3's waves also sum tile (c+3, c+2)'s update over the panel columns
+// before c and leave it in the FP32 tile.  Every element takes the
+// operations of pair_tile in the same order (its MFMAs; the forward-solve sum
+// over the whole tile, read back from LDS, by one wave), so the results are
+// the same bit for bit.  All four waves pass the same barriers.
+__device__ __forceinline__ void chain_rows(const SysDesc& D, int s, int w, int lane, float* __restrict__ A,
+                                           const __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk, int K0, int c,
+                                           int Wp, int wps, int pack1, bool park, double* __restrict__ zf,
+                                           PcolLds& lds) {
+  typedef unsigned u4v __attribute__((ext_vector_type(4)));
+  const u4v sgn{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+  const int ri = w >> 1, hf = w & 1, i = c + 2 + ri;
+  const bool valid = i < D.T, dopark = valid && park && ri == 1;
+  const int KSW = 2 * Wp, il = lane & 15, kg = lane >> 4, lo = 4 * kg * NB + il;
+  float* sc = lds.sC[ri];
+  float* C0 = A + D.a_off + tile_index(valid ? i : c + 1, c) * TILE;   // (c+1, c) stands in when row i is absent
+  float* C1 = C0 + TILE;
+  float* CP = A + D.a_off + tile_index(c + 3, c + 2) * TILE;
+  const __bf16* P = Pk + D.pk_off + lane * 8;
+  const int rbi = (i - K0) * 4, rbj = (c - K0) * 4, rbp = (c + 2 - K0) * 4;
+  f4 a0[2][4], a1[2][4], ap[2][4];
+  auto load_half = [&](const float* C, f4 (&acc)[2][4]) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const float* Cc = C + 16 * (2 * hf + u) * NB;
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][rb][v] = Cc[lo + v * NB + 16 * rb];
+    }
+  };
+  if (valid) {
+    load_half(C0, a0);
+    load_half(C1, a1);
+    if (dopark) load_half(CP, ap);
+    // the update over the panel columns before c: row i's fragments once for
+    // both columns (and the parked tile), each accumulator's steps in order;
+    // a two-step operand ring (the step count is even) keeps the next step's
+    // loads in flight during a step's products, the refill past the end
+    // re-reading the last step
+    const int nks = 2 * (c - K0);
+    bf8 pa[2][4], q0[2][2], q1[2][2], qp[2][2];
+    auto load = [&](int b, int ks) {
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+        pa[b][rb] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbi + rb) * KSW + ks) * FRAG);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int cb = 2 * hf + u;
+        q0[b][u] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbj + cb) * KSW + ks) * FRAG);
+        q1[b][u] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbj + 4 + cb) * KSW + ks) * FRAG);
+        if (dopark) qp[b][u] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbp + cb) * KSW + ks) * FRAG);
+      }
+    };
+    auto step = [&](int b) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const bf8 n0 = __builtin_bit_cast(bf8, __builtin_bit_cast(u4v, q0[b][u]) ^ sgn);
+        const bf8 n1 = __builtin_bit_cast(bf8, __builtin_bit_cast(u4v, q1[b][u]) ^ sgn);
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+          a0[u][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n0, pa[b][rb], a0[u][rb], 0, 0, 0);
+          a1[u][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n1, pa[b][rb], a1[u][rb], 0, 0, 0);
+        }
+        if (dopark) {
+          const bf8 np = __builtin_bit_cast(bf8, __builtin_bit_cast(u4v, qp[b][u]) ^ sgn);
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb)
+            ap[u][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(np, pa[b][rb], ap[u][rb], 0, 0, 0);
+        }
+      }
+    };
+    if (nks > 0) {
+      load(0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      for (int ks = 0; ks < nks; ks += 2) {
+        load(1, ks + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        step(0);
+        load(0, min(ks + 2, nks - 1));
+        __builtin_amdgcn_sched_barrier(0);
+        step(1);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    if (dopark) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        float* Cc = CP + 16 * (2 * hf + u) * NB;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Cc[lo + v * NB + 16 * rb] = ap[u][rb][v];
+      }
+    }
+  }
+  // the panel solve of column k (acc: this wave's column blocks of the
+  // updated tile): the tile in LDS, then out(r, c') = sum_{t <= c'} C(r, t)
+  // Winv(c', t) for this wave's column blocks (tile_solve's products), L to
+  // the tile and LDS, the forward-solve update of row i by wave hf = 0, and
+  // this wave's half of the BF16 pack
+  auto solve_half = [&](int k, float* C, f4 (&acc)[2][4], int do_pack) {
+    if (valid) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) sc[(16 * (2 * hf + u) + 4 * kg + v) * PC_LD + 16 * rb + il] = acc[u][rb][v];
+    }
+    __syncthreads();
+    f4 o[2][4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) o[u][rb] = f4{0.f, 0.f, 0.f, 0.f};
+    if (valid) {
+      // Winv(k) fragments of this wave's column blocks (blocks 0, 1 take only ks = 0)
+      const __bf16* Wf = Wpk + ((int64_t)s * wps + (k - K0)) * 16 * FRAG + lane * 8;
+      bf8 whi[2][2], wlo[2][2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+          if (ks <= hf) {
+            const int cb = 2 * hf + u;
+            whi[u][ks] = *reinterpret_cast<const bf8*>(Wf + (int64_t)(2 * (2 * cb + ks)) * FRAG);
+            wlo[u][ks] = *reinterpret_cast<const bf8*>(Wf + (int64_t)(2 * (2 * cb + ks) + 1) * FRAG);
+          }
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+          if (ks > hf) continue;
+          bf8 chi, clo;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const float cv = sc[(32 * ks + 8 * kg + e) * PC_LD + 16 * rb + il];
+            const __bf16 h = (__bf16)cv;
+            chi[e] = h;
+            clo[e] = (__bf16)(cv - (float)h);
+          }
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            o[u][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wlo[u][ks], chi, o[u][rb], 0, 0, 0);
+            o[u][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(whi[u][ks], clo, o[u][rb], 0, 0, 0);
+            o[u][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(whi[u][ks], chi, o[u][rb], 0, 0, 0);
+          }
+        }
+    }
+    __syncthreads();   // every read of the updated tile is done
+    if (valid) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int cb = 2 * hf + u;
+        float* Cc = C + 16 * cb * NB;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            Cc[lo + v * NB + 16 * rb] = o[u][rb][v];
+            sc[(16 * cb + 4 * kg + v) * PC_LD + 16 * rb + il] = o[u][rb][v];
+          }
+      }
+    }
+    __syncthreads();
+    if (valid && zf != nullptr && hf == 0) {
+      const double* zk = zf + D.v_off + (int64_t)k * NB;
+      double pr[4];
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        double a = 0.0;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            a = fma((double)sc[(16 * cb + 4 * kg + v) * PC_LD + 16 * rb + il], zk[16 * cb + 4 * kg + v], a);
+        a += __shfl_xor(a, 16, 64);
+        a += __shfl_xor(a, 32, 64);
+        pr[rb] = a;
+      }
+      if (kg == 0) {
+        double* bi = zf + D.v_off + (int64_t)i * NB;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) bi[16 * rb + il] -= pr[rb];
+      }
+    }
+    if (valid && do_pack) {
+      __bf16* Pout = Pk + D.pk_off + lane * 8;
+#pragma unroll
+      for (int rbl = 0; rbl < 4; ++rbl) {
+        const int r = 16 * rbl + il, cl = 32 * hf + 8 * kg;
+        bf8 v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (__bf16)sc[(cl + e) * PC_LD + r];
+        *reinterpret_cast<bf8*>(Pout + ((int64_t)(rbi + rbl) * KSW + 2 * (k - K0) + hf) * FRAG) = v;
+      }
+    }
+  };
+  solve_half(c, C0, a0, 1);
+  // column c + 1's last term L(i,c) L(c+1,c)^T: BF16 of L(i,c) from LDS (what
+  // the pack holds) and row c + 1's fragments of column c from the pack
+  if (valid) {
+#pragma unroll
+    for (int h2 = 0; h2 < 2; ++h2) {
+      const int ks = 2 * (c - K0) + h2, cl = 32 * h2 + 8 * kg;
+      bf8 pa[4], qv[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+        qv[u] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbj + 4 + 2 * hf + u) * KSW + ks) * FRAG);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) pa[rb][e] = (__bf16)sc[(cl + e) * PC_LD + 16 * rb + il];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const bf8 nq = __builtin_bit_cast(bf8, __builtin_bit_cast(u4v, qv[u]) ^ sgn);
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+          a1[u][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nq, pa[rb], a1[u][rb], 0, 0, 0);
+      }
+    }
+  }
+  __syncthreads();   // L(i,c) read from LDS by both waves of the row
+  solve_half(c + 1, C1, a1, pack1);
+}
+
 // System s and tile-row group g of workgroup blockIdx.x in the placement of
 // k_panel_col (ng groups per system); false for the grid's padding.
 __device__ __forceinline__ bool group_of(int spread, int n_sys, int ng, int& s, int& g) {
@@ -1138,14 +1369,7 @@ __device__ __forceinline__ void ppair_body(const SysDesc& D, int s, SysStatus* _
   const int KSW = 2 * Wp, lo = 4 * (lane >> 4) * NB + (lane & 15);
   const __bf16* P = Pk + D.pk_off + lane * 8;
   float* C32 = A + D.a_off + tile_index(c + 3, c + 2) * TILE;
-  if (w < 2) {
-    if (c + 2 + w < D.T) pair_tile(D, s, c + 2 + w, lane, A, Wpk, Pk, K0, c, Wp, wps, pack1, zf, lds.sC[w]);
-  } else if (w == 2 && d3 && c > K0) {
-    f4 acc[4][4];
-    load_ctile(C32, lo, acc);
-    packed_sub<4, 2, true>(acc, P, (c + 3 - K0) * 4, (c + 2 - K0) * 4, KSW, 0, 2 * (c - K0));
-    store_ctile(C32, lo, acc);
-  }
+  chain_rows(D, s, w, lane, A, Wpk, Pk, K0, c, Wp, wps, pack1, d3 && c > K0, zf, lds);
   if (!d2) return;
   __syncthreads();   // rows c + 2 and c + 3 packed, the parked sum stored; LDS free
   diag_block<float>(D, s, st, A, Wt, c + 2, Pk, K0, Wp, wps, Wpk, zf, lds.dg, threadIdx.x);
