@@ -60,8 +60,8 @@ TRAFFIC = {
         "kernel": "k_panel_pair",
         "panel_tiles": 24,
         "source": "paper_1805_00569_amd/csrc/cholesky.hip",
-        "sha256": "75537a54ca7d13b1cc6bce39a6e39e1195a50500ffa91dbcdb3812478e7a11e2",
-        "fetch_kib": 98383.3, "write_kib": 81160.8, "fetch_scale": 2.0, "write_scale": 1.0,
+        "sha256": "8adba628d36874ba6d36b24b23dbd729ab5d33773406f4314a37aac7d082e238",
+        "fetch_kib": 99908.9, "write_kib": 81117.5, "fetch_scale": 2.0, "write_scale": 1.0,
     },
 }
 
