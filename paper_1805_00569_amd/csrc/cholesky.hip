@@ -1320,6 +1320,123 @@ __device__ __forceinline__ void chain_rows(const SysDesc& D, int s, int w, int l
   solve_half(c + 1, C1, a1, pack1);
 }
 
+// Tile (i, k) of the diagonal chain (i = k + 1) once diagonal block k is
+// factored, by the four waves of the workgroup, wave w owning column block w:
+// the last NUPD fragment steps of its update (tile (c+3, c+2) of a column
+// pair: panel columns c and c + 1, its earlier columns already summed in the
+// FP32 tile; a panel head's tile (K0+1, K0): none), its panel solve, the
+// forward-solve update of row i (wave 0, from LDS) and the pack.  Every
+// element takes the operations of panel_col_tile in the same order.
+template <int NUPD>
+__device__ __forceinline__ void chain_tile(const SysDesc& D, int s, int w, int lane, float* __restrict__ C,
+                                           const __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk, int K0, int k,
+                                           int Wp, int wps, double* __restrict__ zf, float* __restrict__ sc) {
+  typedef unsigned u4v __attribute__((ext_vector_type(4)));
+  const u4v sgn{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+  const int KSW = 2 * Wp, il = lane & 15, kg = lane >> 4, lo = 4 * kg * NB + il;
+  const int i = k + 1, cb = w;
+  const __bf16* P = Pk + D.pk_off + lane * 8;
+  const int rbi = (i - K0) * 4, rbk = (k - K0) * 4;
+  f4 acc[4];
+  const float* Cc = C + 16 * cb * NB;
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[rb][v] = Cc[lo + v * NB + 16 * rb];
+  // its last NUPD steps, all loads issued first
+  const int ks0 = 2 * (k - K0) - NUPD;
+  bf8 pa[NUPD > 0 ? NUPD : 1][4], qv[NUPD > 0 ? NUPD : 1];
+#pragma unroll
+  for (int u = 0; u < NUPD; ++u) {
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+      pa[u][rb] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbi + rb) * KSW + ks0 + u) * FRAG);
+    qv[u] = *reinterpret_cast<const bf8*>(P + ((int64_t)(rbk + cb) * KSW + ks0 + u) * FRAG);
+  }
+#pragma unroll
+  for (int u = 0; u < NUPD; ++u) {
+    const bf8 nq = __builtin_bit_cast(bf8, __builtin_bit_cast(u4v, qv[u]) ^ sgn);
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nq, pa[u][rb], acc[rb], 0, 0, 0);
+  }
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sc[(16 * cb + 4 * kg + v) * PC_LD + 16 * rb + il] = acc[rb][v];
+  __syncthreads();
+  // out(r, c') for this wave's column block (tile_solve's products)
+  const __bf16* Wf = Wpk + ((int64_t)s * wps + (k - K0)) * 16 * FRAG + lane * 8;
+  const int nks = cb >= 2 ? 2 : 1;
+  bf8 whi[2], wlo[2];
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks)
+    if (ks < nks) {
+      whi[ks] = *reinterpret_cast<const bf8*>(Wf + (int64_t)(2 * (2 * cb + ks)) * FRAG);
+      wlo[ks] = *reinterpret_cast<const bf8*>(Wf + (int64_t)(2 * (2 * cb + ks) + 1) * FRAG);
+    }
+  f4 o[4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    o[rb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      if (ks >= nks) continue;
+      bf8 chi, clo;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float cv = sc[(32 * ks + 8 * kg + e) * PC_LD + 16 * rb + il];
+        const __bf16 h = (__bf16)cv;
+        chi[e] = h;
+        clo[e] = (__bf16)(cv - (float)h);
+      }
+      o[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wlo[ks], chi, o[rb], 0, 0, 0);
+      o[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(whi[ks], clo, o[rb], 0, 0, 0);
+      o[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(whi[ks], chi, o[rb], 0, 0, 0);
+    }
+  }
+  __syncthreads();   // every read of the updated tile is done
+  float* Cw = C + 16 * cb * NB;
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Cw[lo + v * NB + 16 * rb] = o[rb][v];
+      sc[(16 * cb + 4 * kg + v) * PC_LD + 16 * rb + il] = o[rb][v];
+    }
+  __syncthreads();
+  if (zf != nullptr && w == 0) {
+    const double* zk = zf + D.v_off + (int64_t)k * NB;
+    double pr[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      double a = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          a = fma((double)sc[(16 * cc + 4 * kg + v) * PC_LD + 16 * rb + il], zk[16 * cc + 4 * kg + v], a);
+      a += __shfl_xor(a, 16, 64);
+      a += __shfl_xor(a, 32, 64);
+      pr[rb] = a;
+    }
+    if (kg == 0) {
+      double* bi = zf + D.v_off + (int64_t)i * NB;
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) bi[16 * rb + il] -= pr[rb];
+    }
+  }
+  // pack: wave w writes row block w of both column halves
+  __bf16* Pout = Pk + D.pk_off + lane * 8;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = 16 * w + il, cl = 32 * h + 8 * kg;
+    bf8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (__bf16)sc[(cl + e) * PC_LD + r];
+    *reinterpret_cast<bf8*>(Pout + ((int64_t)(rbi + w) * KSW + 2 * (k - K0) + h) * FRAG) = v;
+  }
+}
+
 // System s and tile-row group g of workgroup blockIdx.x in the placement of
 // k_panel_col (ng groups per system); false for the grid's padding.
 __device__ __forceinline__ bool group_of(int spread, int n_sys, int ng, int& s, int& g) {
@@ -1377,14 +1494,7 @@ __device__ __forceinline__ void ppair_body(const SysDesc& D, int s, SysStatus* _
   __syncthreads();
   if (lds.dg.fail) return;   // the system failed at block c + 2 (status set)
   __syncthreads();           // every wave has read the flag before the LDS is reused
-  if (w == 0) {
-    WinvFrags W;
-    load_winv(Wpk, s, wps, K0, c + 2, lane, W);
-    f4 acc[4][4];
-    load_ctile(C32, lo, acc);
-    packed_sub<4, 2, true>(acc, P, (c + 3 - K0) * 4, (c + 2 - K0) * 4, KSW, 2 * (c - K0), 2 * (c + 2 - K0));
-    tile_solve(D, c + 3, lane, C32, lo, W, Pk, K0, c + 2, KSW, 1, zf, lds.sC[0], acc);
-  }
+  chain_tile<4>(D, s, w, lane, C32, Wpk, Pk, K0, c + 2, Wp, wps, zf, lds.sC[0]);
   __syncthreads();
   diag_block<float>(D, s, st, A, Wt, c + 3, Pk, K0, Wp, wps, Wpk, zf, lds.dg, threadIdx.x);
 }
@@ -1416,7 +1526,7 @@ __device__ __forceinline__ void phead_body(const SysDesc& D, int s, SysStatus* _
   if (lds.dg.fail) return;
   __syncthreads();
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (w == 0) panel_col_tile(D, s, K0 + 1, lane, A, Wpk, Pk, K0, K0, Wp, wps, 1, zf, lds.sC[0]);
+  chain_tile<0>(D, s, w, lane, A + D.a_off + tile_index(K0 + 1, K0) * TILE, Wpk, Pk, K0, K0, Wp, wps, zf, lds.sC[0]);
   __syncthreads();
   diag_block<float>(D, s, st, A, Wt, K0 + 1, Pk, K0, Wp, wps, Wpk, zf, lds.dg, threadIdx.x);
 }
