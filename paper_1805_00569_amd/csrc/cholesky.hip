@@ -1464,13 +1464,13 @@ __device__ __forceinline__ bool group_of(int spread, int n_sys, int ng, int& s, 
 // before c are final for every row, and so are the diagonal blocks c and
 // c + 1 (Winv fragments, z), and L(c+1, c).  Group 0 (rows c + 2, c + 3)
 // carries the diagonal chain two columns ahead, so that the next launch
-// finds the same: diagonal block c + 2 (its update reads row c + 2's
-// fragments of columns c and c + 1, just packed by wave 0), then tile
-// (c+3, c+2) -- whose update over the columns before c wave 2 has already
-// summed and parked in the FP32 tile, the rest reading row c + 3's fragments
-// packed by wave 1 -- then diagonal block c + 3.  Every tile and block takes
-// the operations of the single-column sequence in the same order, so the
-// factor is the same bit for bit.
+// finds the same: rows c + 2 and c + 3 on all four waves (chain_rows, which
+// also sums tile (c+3, c+2)'s update over the columns before c and parks it
+// in the FP32 tile), diagonal block c + 2 (its update reads row c + 2's
+// fragments of columns c and c + 1, just packed), the rest of tile
+// (c+3, c+2) (chain_tile), then diagonal block c + 3.  Every tile and block
+// takes the operations of the single-column sequence in the same order, so
+// the factor is the same bit for bit.
 __device__ __forceinline__ void ppair_body(const SysDesc& D, int s, SysStatus* __restrict__ st, float* __restrict__ A,
                                            float* __restrict__ Wt, __bf16* __restrict__ Wpk, __bf16* __restrict__ Pk,
                                            int K0, int c, int Wp, int wps, int pack1, int g, double* __restrict__ zf,
@@ -1483,8 +1483,6 @@ __device__ __forceinline__ void ppair_body(const SysDesc& D, int s, SysStatus* _
   }
   const int kend = min(K0 + Wp, (int)D.T);
   const bool d2 = c + 2 < kend, d3 = c + 3 < kend;   // uniform over the workgroup
-  const int KSW = 2 * Wp, lo = 4 * (lane >> 4) * NB + (lane & 15);
-  const __bf16* P = Pk + D.pk_off + lane * 8;
   float* C32 = A + D.a_off + tile_index(c + 3, c + 2) * TILE;
   chain_rows(D, s, w, lane, A, Wpk, Pk, K0, c, Wp, wps, pack1, d3 && c > K0, zf, lds);
   if (!d2) return;
