@@ -60,8 +60,8 @@ TRAFFIC = {
         "kernel": "k_panel_pair",
         "panel_tiles": 24,
         "source": "paper_1805_00569_amd/csrc/cholesky.hip",
-        "sha256": "8adba628d36874ba6d36b24b23dbd729ab5d33773406f4314a37aac7d082e238",
-        "fetch_kib": 99908.9, "write_kib": 81117.5, "fetch_scale": 2.0, "write_scale": 1.0,
+        "sha256": "bd0c75d982325251c8810b1ab750ffc266dd1f1d7e87ef6121bbd7b3c73050e5",
+        "fetch_kib": 99769.4, "write_kib": 81118.6, "fetch_scale": 2.0, "write_scale": 1.0,
     },
 }
 
