@@ -33,8 +33,10 @@ Readings taken where the paper is silent (each is listed in the design notes):
 * Lloyd stops after ``iters`` passes or when no assignment changed; an empty
   cluster keeps its previous centre; the returned partition is the assignment
   to the final centres.
-* Member sums for means are one sequential FP64 running sum per (cluster,
-  feature) over the members in increasing point index, then one division.
+* The mean of a cluster (Algorithm 2) is its members' exactly rounded FP64
+  sum (the exact sum of the values rounded once, to nearest, ties to even;
+  ``math.fsum``) divided by the count in FP64; it depends on no order of the
+  members.
 * K-balance capacity is ceil(n/p); the recompute of centres (optional in the
   paper) is done.
 * The approximate parallel K-balance (Section 4.3, after Algorithm 4) splits
@@ -159,10 +161,10 @@ def kmeanspp(X: np.ndarray, k: int, seed: int, trace: list | None = None) -> tup
 
 def member_means(X: np.ndarray, a: np.ndarray, C_prev: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
     """Algorithm 2 mean step: CT_j = (sum of members) / count_j; an empty
-    cluster keeps C_prev[j].  Algorithm 2 leaves the order of the sum open;
-    here it is one running FP64 sum per (cluster, feature) over the members
-    in increasing point index (left to right, one rounding per addition),
-    then one division by the count."""
+    cluster keeps C_prev[j].  Algorithm 2 leaves the rounding of the sum open;
+    here it is the exact sum of the member values rounded once to FP64
+    (math.fsum: nearest, ties to even), which no order of the members
+    changes, then one FP64 division by the count."""
     X = np.asarray(X, dtype=np.float64)
     k = C_prev.shape[0]
     C = C_prev.copy()
@@ -170,8 +172,8 @@ def member_means(X: np.ndarray, a: np.ndarray, C_prev: np.ndarray) -> tuple[np.n
     for j in range(k):
         if counts[j] == 0:
             continue
-        members = X[a == j]                          # increasing index order
-        total = np.add.accumulate(members, axis=0)[-1]   # sequential down each feature column
+        members = X[a == j]
+        total = np.array([math.fsum(members[:, f]) for f in range(members.shape[1])])
         C[j] = total / float(counts[j])
     return C, counts
 

@@ -10,6 +10,7 @@
 // the squared value; the strict "<" over ascending centre index sends ties to
 // the lowest index, as in Algorithm 4.
 #include "common.hpp"
+#include "exact_sum.hpp"
 
 #include <cmath>
 
@@ -337,119 +338,116 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_group_scatter(const int32_t* __
 }
 
 // ---------------------------------------------------------------------------
-// Means of the grouped members (Algorithm 2's mean step): C[j][f] = (sum of
-// the member values) / count_j in FP64, one running sum per (partition,
-// feature) over the members in increasing point order (the stable grouping
-// perm), one rounding per addition; an empty partition keeps its centre.
-// Workgroup (j, slice) = (blockIdx.x / nsl, blockIdx.x % nsl) owns features
-// [MS_W slice, MS_W slice + MS_W): narrow slices give p * ceil(d / MS_W)
-// workgroups, so that many running sums advance at once.  Chunks of CH
-// member rows are staged in LDS feature-major (double-buffered; all threads
-// load, 16 rows of MS_W features per load instruction), and lanes 0 ..
-// MS_W - 1 of wave 0 add them in order, lane f carrying feature f's sum and
-// reading four rows per LDS load: the additions of a chunk overlap the
-// loads of the next.  The member indices of chunk
-// c + 2 are fetched while chunk c is summed.  Lloyd passes: `skip` is this
-// pass's "fixed point reached" flag; workgroup 0 writes the next pass's flag
-// (set when this pass was skipped or changed no assignment), so no
-// workgroup of a launch reads a flag that the same launch writes.  CT
-// (nullable) receives the centres transposed (d x p).
+// Means of the grouped members (Algorithm 2's mean step): C[j][f] = (exactly
+// rounded sum of the member values) / count_j in FP64; an empty partition
+// keeps its centre.  The sums are integer sums of the values' units
+// (exact_sum.hpp), which take the members in any order: workgroup (j, slice,
+// split) adds the member rows [cnt split / rs, cnt (split + 1) / rs) of
+// partition j (in the stable grouping perm) for the MS_W features of slice
+// `slice`; thread (feature fl, row subset rr) adds rows rr, rr + RR, ... into
+// its own limbs in LDS (8 rows' loads issued together, then one LDS atomic add
+// per term), and the workgroup writes the per-feature limb sums of its rows to
+// P.  k_means_round adds the rs partial limb sets of each (j, f), rounds once
+// and divides by the count.  Lloyd passes: `skip` is this pass's "fixed point
+// reached" flag; k_means_round's first thread writes the next pass's flag (set
+// when this pass was skipped or changed no assignment), so no workgroup of a
+// launch reads a flag that the same launch writes.  CT (nullable) receives the
+// centres transposed (d x p).
 // ---------------------------------------------------------------------------
-constexpr int MS_THREADS = 256;
-constexpr int MS_W = 16;                         // features per workgroup
-constexpr int MS_RPL = MS_THREADS / MS_W;        // rows per load instruction of the workgroup
+constexpr int MS_W = 16;   // features per workgroup
+constexpr int MS_B = 8;    // rows per thread whose loads issue together
 
 template <typename TX>
-struct MeansChunk {
-  static constexpr int CH = sizeof(TX) == 4 ? 1024 : 512;   // member rows per staged chunk (64 KiB)
-  // the stage is feature-major: feature f's CH rows at f * PITCH (padded so
-  // that the staging stores and the adders' 16-byte loads of four rows meet
-  // distinct banks)
-  static constexpr int PITCH = CH + 4;
+struct MeansCfg {
+  static constexpr int THREADS = sizeof(TX) == 4 ? 256 : 64;   // FP64: 66 limbs per thread in LDS
+  static constexpr int RR = THREADS / MS_W;                     // row subsets of a workgroup
 };
 
 template <typename TX>
-__global__ __launch_bounds__(MS_THREADS) void k_means_seq(const TX* __restrict__ X, int d, int nsl,
-                                                           const int32_t* __restrict__ perm,
-                                                           const int64_t* __restrict__ offsets, int p,
-                                                           double* __restrict__ C, double* __restrict__ CT,
-                                                           const int32_t* __restrict__ skip,
-                                                           const int32_t* __restrict__ delta,
-                                                           int32_t* __restrict__ done_next) {
-  constexpr int CH = MeansChunk<TX>::CH;
-  constexpr int PER = CH / MS_RPL;   // staged elements per thread and chunk
+__global__ __launch_bounds__(MeansCfg<TX>::THREADS) void k_means_acc(const TX* __restrict__ X, int d, int nsl, int rs,
+                                                                      const int32_t* __restrict__ perm,
+                                                                      const int64_t* __restrict__ offsets,
+                                                                      int64_t* __restrict__ P,
+                                                                      const int32_t* __restrict__ skip) {
+  constexpr int NL = ExactSum<TX>::NL, NT = MeansCfg<TX>::THREADS, RR = MeansCfg<TX>::RR;
+  constexpr int NORM_EVERY = ExactSum<TX>::ADDS;
+  static_assert(NORM_EVERY % MS_B == 0, "normalisation at whole batches");
+  if (skip != nullptr && *skip) return;
+  const int split = blockIdx.x % rs, js = blockIdx.x / rs;
+  const int j = js / nsl, slice = js - j * nsl;
+  const int64_t base = offsets[j], cnt = offsets[j + 1] - base;
+  const int64_t r0 = cnt * split / rs, r1 = cnt * (split + 1) / rs;
+  __shared__ int64_t acc[NL * NT];   // acc[k * NT + t]: thread t's limb k
+  const int t = threadIdx.x, fl = t % MS_W, rr = t / MS_W;
+  const int f = slice * MS_W + fl;
+  const bool live = f < d;
+  const int fc = min(f, d - 1);   // lanes past d load a valid value and add zero
+  int64_t* mine = acc + t;
+  for (int k = 0; k < NL; ++k) mine[k * NT] = 0;
+  auto get = [&](int k) { return mine[k * NT]; };
+  auto set = [&](int k, int64_t v) { mine[k * NT] = v; };
+  int since = 0;
+  for (int64_t r = r0 + rr; r < r1; r += (int64_t)RR * MS_B) {
+    int32_t pi[MS_B];
+    TX v[MS_B];
+#pragma unroll
+    for (int u = 0; u < MS_B; ++u) pi[u] = perm[base + min(r + (int64_t)RR * u, r1 - 1)];
+#pragma unroll
+    for (int u = 0; u < MS_B; ++u) v[u] = X[(int64_t)pi[u] * d + fc];
+#pragma unroll
+    for (int u = 0; u < MS_B; ++u) {
+      const bool ok = live && r + (int64_t)RR * u < r1;
+      const XsTerms tm = xs_terms(v[u]);
+      atomicAdd(reinterpret_cast<unsigned long long*>(mine + tm.l0 * NT), (unsigned long long)(ok ? tm.c0 : 0));
+      if (sizeof(TX) == 8)
+        atomicAdd(reinterpret_cast<unsigned long long*>(mine + tm.l1 * NT), (unsigned long long)(ok ? tm.c1 : 0));
+    }
+    since += MS_B;
+    if (since == NORM_EVERY) {
+      xs_normalise<NL>(get, set);
+      since = 0;
+    }
+  }
+  xs_normalise<NL>(get, set);
+  __syncthreads();
+  // per (feature, limb): the sum over the row subsets (each limb below 2^32
+  // but the signed top one, so the sum stays far from overflow)
+  int64_t* out = P + (int64_t)blockIdx.x * MS_W * NL;
+  for (int e = t; e < MS_W * NL; e += NT) {
+    const int f2 = e / NL, k = e - f2 * NL;
+    int64_t s = 0;
+#pragma unroll
+    for (int q = 0; q < RR; ++q) s += acc[k * NT + q * MS_W + f2];
+    out[e] = s;
+  }
+}
+
+template <typename TX>
+__global__ __launch_bounds__(64) void k_means_round(int d, int nsl, int rs, int p,
+                                                    const int64_t* __restrict__ offsets,
+                                                    const int64_t* __restrict__ P, double* __restrict__ C,
+                                                    double* __restrict__ CT, const int32_t* __restrict__ skip,
+                                                    const int32_t* __restrict__ delta,
+                                                    int32_t* __restrict__ done_next) {
+  constexpr int NL = ExactSum<TX>::NL;
   const int skipped = (skip != nullptr) ? *skip : 0;
   if (done_next != nullptr && blockIdx.x == 0 && threadIdx.x == 0)
     *done_next = (skipped || *delta == 0) ? 1 : 0;
   if (skipped) return;
-  const int j = blockIdx.x / nsl, f0 = (blockIdx.x - j * nsl) * MS_W;
-  const int64_t base = offsets[j];
-  const int64_t cnt = offsets[j + 1] - base;
+  const int64_t id = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (id >= (int64_t)p * d) return;
+  const int j = (int)(id / d), f = (int)(id - (int64_t)j * d);
+  const int64_t cnt = offsets[j + 1] - offsets[j];
   if (cnt == 0) return;
-  constexpr int PITCH = MeansChunk<TX>::PITCH;
-  __shared__ __align__(16) TX sX[2][MS_W * PITCH];
-  __shared__ int32_t sP[2][CH];
-  const int t = threadIdx.x, fl = t % MS_W, rr = t / MS_W, w = t >> 6, lane = t & 63;
-  const int fc = min(f0 + fl, d - 1);   // clamped feature: lanes past d load a valid value, never summed
-  const int64_t nch = (cnt + CH - 1) / CH;
-  // member index of chunk row r (clamped to the last member: in range, never summed)
-  auto member = [&](int64_t c, int r) { return perm[base + min<int64_t>(c * CH + r, cnt - 1)]; };
-  for (int r = t; r < CH; r += MS_THREADS) sP[0][r] = member(0, r);
-  __syncthreads();
-  {
-    TX v[PER];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) v[u] = X[(int64_t)sP[0][rr + MS_RPL * u] * d + fc];
-    for (int r = t; r < CH; r += MS_THREADS) sP[1][r] = member(min<int64_t>(1, nch - 1), r);
-#pragma unroll
-    for (int u = 0; u < PER; ++u) sX[0][fl * PITCH + rr + MS_RPL * u] = v[u];
-  }
-  __syncthreads();
-  double acc = 0.0;
-  for (int64_t c = 0; c < nch; ++c) {
-    const int cur = (int)(c & 1), nxt = cur ^ 1;
-    const bool more = c + 1 < nch;
-    TX v[PER];
-    int32_t pn[CH / MS_THREADS];
-    if (more) {
-#pragma unroll
-      for (int u = 0; u < PER; ++u) v[u] = X[(int64_t)sP[nxt][rr + MS_RPL * u] * d + fc];
-#pragma unroll
-      for (int q = 0; q < CH / MS_THREADS; ++q) pn[q] = member(min<int64_t>(c + 2, nch - 1), t + q * MS_THREADS);
-    }
-    if (w == 0 && lane < MS_W) {
-      const int nr = (int)min<int64_t>(CH, cnt - c * CH);
-      const TX* col = &sX[cur][lane * PITCH];   // this lane's feature, rows contiguous
-      typedef TX tx4 __attribute__((ext_vector_type(4)));
-      int r = 0;
-      for (; r + 64 <= nr; r += 64) {   // 16 loads of four rows, then 64 ordered adds
-        tx4 x[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) x[u] = *reinterpret_cast<const tx4*>(col + r + 4 * u);
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          acc = add_sep(acc, (double)x[u][0]);
-          acc = add_sep(acc, (double)x[u][1]);
-          acc = add_sep(acc, (double)x[u][2]);
-          acc = add_sep(acc, (double)x[u][3]);
-        }
-      }
-      for (; r < nr; ++r) acc = add_sep(acc, (double)col[r]);
-    }
-    if (more) {
-      // sX[nxt] and sP[cur] were last read before the previous barrier
-#pragma unroll
-      for (int u = 0; u < PER; ++u) sX[nxt][fl * PITCH + rr + MS_RPL * u] = v[u];
-#pragma unroll
-      for (int q = 0; q < CH / MS_THREADS; ++q) sP[cur][t + q * MS_THREADS] = pn[q];
-    }
-    __syncthreads();
-  }
-  if (w == 0 && lane < MS_W && f0 + lane < d) {
-    const double val = acc / (double)cnt;
-    C[(int64_t)j * d + f0 + lane] = val;
-    if (CT != nullptr) CT[(int64_t)(f0 + lane) * p + j] = val;
-  }
+  const int slice = f / MS_W, fl = f - slice * MS_W;
+  int64_t limb[NL];
+  for (int k = 0; k < NL; ++k) limb[k] = 0;
+  const int64_t* src = P + ((int64_t)(j * nsl + slice) * rs * MS_W + fl) * NL;
+  for (int s = 0; s < rs; ++s, src += (int64_t)MS_W * NL)
+    for (int k = 0; k < NL; ++k) limb[k] += src[k];
+  const double val = xs_round<TX>(limb) / (double)cnt;
+  C[(int64_t)j * d + f] = val;
+  if (CT != nullptr) CT[(int64_t)f * p + j] = val;
 }
 
 // ---------------------------------------------------------------------------
@@ -1034,10 +1032,17 @@ template <typename TX>
 void means_t(krr_ctx ctx, hipStream_t s, const TX* X, int d, const int32_t* perm, const int64_t* offsets,
              double* C, double* CT, int p, const int32_t* skip, const int32_t* delta, int32_t* done_next) {
   KernelTimer kt(ctx, s, "lloyd_means", 0.0, 0);
+  constexpr int NL = ExactSum<TX>::NL;
   const int nsl = (int)ceil_div(d, MS_W);
-  hipLaunchKernelGGL((k_means_seq<TX>), dim3((unsigned)(p * nsl)), dim3(MS_THREADS), 0, s, X, d, nsl, perm, offsets,
-                     p, C, CT, skip, delta, done_next);
-  check_launch(ctx, s, "means");
+  // row splits: about 1,024 workgroups in all
+  const int rs = (int)std::max<int64_t>(1, std::min<int64_t>(64, ceil_div(1024, (int64_t)p * nsl)));
+  int64_t* P = (int64_t*)ws_get(ctx, "means_part", (size_t)p * nsl * rs * MS_W * NL * sizeof(int64_t));
+  hipLaunchKernelGGL((k_means_acc<TX>), dim3((unsigned)(p * nsl * rs)), dim3(MeansCfg<TX>::THREADS), 0, s, X, d, nsl,
+                     rs, perm, offsets, P, skip);
+  check_launch(ctx, s, "means_acc");
+  hipLaunchKernelGGL((k_means_round<TX>), dim3((unsigned)ceil_div((int64_t)p * d, 64)), dim3(64), 0, s, d, nsl, rs, p,
+                     offsets, (const int64_t*)P, C, CT, skip, delta, done_next);
+  check_launch(ctx, s, "means_round");
 }
 
 template <typename TX>

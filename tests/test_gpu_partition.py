@@ -1,6 +1,6 @@
 """Parity of the partition kernels with the oracle: assignment indices, the
-Lloyd centres (one sequential sum per cluster and feature on both sides) and
-the K-balance memberships must be identical bit for bit on the same seeded
+Lloyd centres (the exactly rounded member sums divided by the count on both
+sides) and the K-balance memberships must be identical bit for bit on the same seeded
 inputs.  The k-means++ picks are compared too; the GPU forms the cumulative
 D^2 weights in a different (blocked) order, so each test also checks that
 every pick of the oracle is further from a rounding tie than the bound of
@@ -55,10 +55,11 @@ def test_kmeans_seeding_and_lloyd_bitexact(ctx, dev):
 
 @pytest.mark.parametrize("n,d,p,dtype", [(20000, 90, 3, np.float32), (9000, 130, 2, np.float64),
                                          (3001, 7, 5, np.float64)])
-def test_lloyd_means_long_sequential_sums(ctx, dev, n, d, p, dtype):
-    """Clusters of thousands of members (many staged chunks of the mean step)
-    and more than 64 features (several feature slices): the Lloyd centres
-    equal the oracle's sequential member sums bit for bit."""
+def test_lloyd_means_long_sums(ctx, dev, n, d, p, dtype):
+    """Clusters of hundreds to thousands of members (many row splits of the
+    mean step; in FP64 several limb normalisations per thread) and more than
+    64 features (several feature slices): the Lloyd centres equal the
+    oracle's exactly rounded means bit for bit."""
     print(f"lloyd means n={n} d={d} p={p} {dtype.__name__}", flush=True)
     g = np.random.default_rng(n + d)
     X = (g.standard_normal((n, d)) * g.uniform(0.5, 2, d) + 3.0 * g.standard_normal((1, d))).astype(dtype)
@@ -69,7 +70,7 @@ def test_lloyd_means_long_sequential_sums(ctx, dev, n, d, p, dtype):
     Co, ao, _, _ = O.lloyd(X, C0, 4)
     np.testing.assert_array_equal(a.cpu().numpy(), ao)
     np.testing.assert_array_equal(C.cpu().numpy(), Co)
-    assert sz.cpu().numpy().max() > 256   # several staged chunks of member rows
+    assert sz.cpu().numpy().max() > 256   # clusters of hundreds of members
 
 
 def test_kbalance_bitexact(ctx, dev):
@@ -181,3 +182,31 @@ def test_partition_rejects_bad_arguments(ctx, dev):
     with pytest.raises(krr.KrrError) as e:
         ctx.partition(X, 11, "kmeans")
     assert e.value.status == krr.KRR_EINVAL
+
+
+@pytest.mark.parametrize("n,d,p,dtype", [(6000, 20, 3, np.float32), (6000, 20, 3, np.float64),
+                                         (140000, 5, 1, np.float32)])
+def test_means_exact_over_the_whole_range(ctx, dev, n, d, p, dtype):
+    """Member means of the random even split (no distances, so any finite
+    values may be used): magnitudes over most of the format's exponent range,
+    subnormals, large values that cancel, exact zeros and a column of tiny
+    values; the centres equal the oracle's exactly rounded means bit for bit.
+    Rows 0..9 hold planted extremes.  The single partition of 140,000 rows
+    gives each thread of the mean step more than 128 terms (limbs normalised
+    inside the loop, not only at its end)."""
+    print(f"means whole range n={n} d={d} p={p} {dtype.__name__}", flush=True)
+    g = np.random.default_rng(77)
+    lo, hi = (-140, 100) if dtype == np.float32 else (-1060, 1000)
+    e = g.integers(lo, hi, (n, d)).astype(float)
+    X = (g.standard_normal((n, d)) * np.exp2(e)).astype(dtype)
+    big = np.finfo(dtype).max / 8
+    X[0:4, 0] = [big, -big, big, -big]               # cancel exactly
+    X[4:8, 1] = np.finfo(dtype).smallest_subnormal   # subnormal terms
+    X[8:10, :] = 0.0
+    X[:, 2] = np.finfo(dtype).smallest_subnormal * g.integers(-5, 6, n)   # a column of tiny values
+    C, a, sz = ctx.partition(_t(X, dev), p, "random", seed=5)
+    Co, ao = O.random_partition(X, p, 5)
+    np.testing.assert_array_equal(a.cpu().numpy(), ao)
+    Cg = C.cpu().numpy()
+    np.testing.assert_array_equal(Cg, Co)
+    assert np.array_equal(np.signbit(Cg), np.signbit(Co))   # same sign of zero too

@@ -175,15 +175,15 @@ def _py_lloyd(X, C0, iters):
         delta = len(a) if prev is None else sum(1 for u, v in zip(a, prev) if u != v)
         prev = a
         for j in range(k):
-            s = [0.0] * d
+            s = [Fraction(0)] * d   # exact rational sums
             c = 0
             for i, x in enumerate(X):
                 if a[i] == j:
                     c += 1
                     for f in range(d):
-                        s[f] = s[f] + x[f]
+                        s[f] = s[f] + Fraction(x[f])
             if c:
-                C[j] = [s[f] / c for f in range(d)]
+                C[j] = [float(s[f]) / c for f in range(d)]
         if delta == 0:
             break
     return np.array(C), np.array(asg(), dtype=np.int32)
@@ -221,32 +221,31 @@ def test_lloyd_objective_nonincreasing_and_fixed_point():
 
 
 def test_member_means_is_the_mean():
-    """Many members per cluster (750 on average, several hundred more than
-    any block a parallel sum might use): every centre is bit for bit the
-    Python left-to-right sum over its members in increasing index divided by
-    the count, within a few ulps of the exactly rounded mean (math.fsum), and
-    a constant cluster reproduces its value exactly."""
+    """Many members per cluster (750 on average) with features of very
+    different scales: every centre is bit for bit the exact rational sum of
+    its members rounded once to the nearest double, divided by the count; the
+    centres do not change when the points are permuted; for some features
+    that differs from the left-to-right running sum (so the order-free
+    reading is what is pinned); a constant cluster reproduces its value."""
     g = np.random.default_rng(3)
     X = g.standard_normal((3000, 3)) * np.array([1.0, 1e3, 1e-3])
     a = g.integers(0, 4, 3000).astype(np.int32)
     X[a == 3] = 0.625
     C, counts = O.member_means(X, a, np.zeros((4, 3)))
-    differs_from_blocked = False
+    differs_from_running = False
     for j in range(4):
         mem = X[a == j]
         assert counts[j] == mem.shape[0] > 512
         for f in range(3):
-            seq = _py_running(mem[:, f])[-1]
-            assert C[j, f] == seq / mem.shape[0]
-            exact = math.fsum(mem[:, f]) / mem.shape[0]
-            scale = np.abs(mem[:, f]).sum() / mem.shape[0]
-            assert abs(C[j, f] - exact) <= 2 * mem.shape[0] * np.finfo(float).eps * scale
-            off = 0.0
-            for b0 in range(0, mem.shape[0], 256):
-                off = off + _py_running(mem[b0:b0 + 256, f])[-1]
-            differs_from_blocked |= off / mem.shape[0] != C[j, f]
-    assert differs_from_blocked
+            exact = float(sum((Fraction(v) for v in mem[:, f].tolist()), Fraction(0)))
+            assert C[j, f] == exact / mem.shape[0]
+            differs_from_running |= _py_running(mem[:, f])[-1] != exact
+    assert differs_from_running
     assert np.all(C[3] == 0.625)
+    perm = g.permutation(3000)
+    Cp, counts_p = O.member_means(X[perm], a[perm], np.zeros((4, 3)))
+    np.testing.assert_array_equal(Cp, C)
+    np.testing.assert_array_equal(counts_p, counts)
 
 
 def test_empty_cluster_keeps_centre():
