@@ -344,23 +344,24 @@ __global__ __launch_bounds__(GROUP_BLOCK) void k_group_scatter(const int32_t* __
 // (exact_sum.hpp), which take the members in any order: workgroup (j, slice,
 // split) adds the member rows [cnt split / rs, cnt (split + 1) / rs) of
 // partition j (in the stable grouping perm) for the MS_W features of slice
-// `slice`; thread (feature fl, row subset rr) adds rows rr, rr + RR, ... into
-// its own limbs in LDS (8 rows' loads issued together, then one LDS atomic add
-// per term), and the workgroup writes the per-feature limb sums of its rows to
-// P.  k_means_round adds the rs partial limb sets of each (j, f), rounds once
+// `slice`: it stages up to MS_CH member indices in LDS (one coalesced pass),
+// then thread (feature fl, row subset rr) adds rows rr, rr + RR, ... into its
+// own limbs in LDS (B rows' loads issued together, then one LDS atomic add per
+// term), and the workgroup writes the per-feature limb sums of its rows to P.  k_means_round adds the rs partial limb sets of each (j, f), rounds once
 // and divides by the count.  Lloyd passes: `skip` is this pass's "fixed point
 // reached" flag; k_means_round's first thread writes the next pass's flag (set
 // when this pass was skipped or changed no assignment), so no workgroup of a
 // launch reads a flag that the same launch writes.  CT (nullable) receives the
 // centres transposed (d x p).
 // ---------------------------------------------------------------------------
-constexpr int MS_W = 16;   // features per workgroup
-constexpr int MS_B = 8;    // rows per thread whose loads issue together
+constexpr int MS_W = 16;      // features per workgroup
+constexpr int MS_CH = 1024;   // member indices a workgroup stages in LDS at once
 
 template <typename TX>
 struct MeansCfg {
   static constexpr int THREADS = sizeof(TX) == 4 ? 256 : 64;   // FP64: 66 limbs per thread in LDS
   static constexpr int RR = THREADS / MS_W;                     // row subsets of a workgroup
+  static constexpr int B = sizeof(TX) == 4 ? 16 : 8;            // rows per thread whose loads issue together
 };
 
 template <typename TX>
@@ -369,15 +370,16 @@ __global__ __launch_bounds__(MeansCfg<TX>::THREADS) void k_means_acc(const TX* _
                                                                       const int64_t* __restrict__ offsets,
                                                                       int64_t* __restrict__ P,
                                                                       const int32_t* __restrict__ skip) {
-  constexpr int NL = ExactSum<TX>::NL, NT = MeansCfg<TX>::THREADS, RR = MeansCfg<TX>::RR;
+  constexpr int NL = ExactSum<TX>::NL, NT = MeansCfg<TX>::THREADS, RR = MeansCfg<TX>::RR, B = MeansCfg<TX>::B;
   constexpr int NORM_EVERY = ExactSum<TX>::ADDS;
-  static_assert(NORM_EVERY % MS_B == 0, "normalisation at whole batches");
+  static_assert(NORM_EVERY % B == 0, "normalisation at whole batches");
   if (skip != nullptr && *skip) return;
   const int split = blockIdx.x % rs, js = blockIdx.x / rs;
   const int j = js / nsl, slice = js - j * nsl;
   const int64_t base = offsets[j], cnt = offsets[j + 1] - base;
   const int64_t r0 = cnt * split / rs, r1 = cnt * (split + 1) / rs;
   __shared__ int64_t acc[NL * NT];   // acc[k * NT + t]: thread t's limb k
+  __shared__ int32_t sP[MS_CH];
   const int t = threadIdx.x, fl = t % MS_W, rr = t / MS_W;
   const int f = slice * MS_W + fl;
   const bool live = f < d;
@@ -387,26 +389,29 @@ __global__ __launch_bounds__(MeansCfg<TX>::THREADS) void k_means_acc(const TX* _
   auto get = [&](int k) { return mine[k * NT]; };
   auto set = [&](int k, int64_t v) { mine[k * NT] = v; };
   int since = 0;
-  for (int64_t r = r0 + rr; r < r1; r += (int64_t)RR * MS_B) {
-    int32_t pi[MS_B];
-    TX v[MS_B];
+  for (int64_t c0 = r0; c0 < r1; c0 += MS_CH) {
+    const int nr = (int)min<int64_t>(MS_CH, r1 - c0);
+    for (int q = t; q < MS_CH; q += NT) sP[q] = perm[base + c0 + min(q, nr - 1)];
+    __syncthreads();
+    for (int q0 = rr; q0 < nr; q0 += RR * B) {
+      TX v[B];
 #pragma unroll
-    for (int u = 0; u < MS_B; ++u) pi[u] = perm[base + min(r + (int64_t)RR * u, r1 - 1)];
+      for (int u = 0; u < B; ++u) v[u] = X[(int64_t)sP[min(q0 + RR * u, nr - 1)] * d + fc];
 #pragma unroll
-    for (int u = 0; u < MS_B; ++u) v[u] = X[(int64_t)pi[u] * d + fc];
-#pragma unroll
-    for (int u = 0; u < MS_B; ++u) {
-      const bool ok = live && r + (int64_t)RR * u < r1;
-      const XsTerms tm = xs_terms(v[u]);
-      atomicAdd(reinterpret_cast<unsigned long long*>(mine + tm.l0 * NT), (unsigned long long)(ok ? tm.c0 : 0));
-      if (sizeof(TX) == 8)
-        atomicAdd(reinterpret_cast<unsigned long long*>(mine + tm.l1 * NT), (unsigned long long)(ok ? tm.c1 : 0));
+      for (int u = 0; u < B; ++u) {
+        const bool ok = live && q0 + RR * u < nr;
+        const XsTerms tm = xs_terms(v[u]);
+        atomicAdd(reinterpret_cast<unsigned long long*>(mine + tm.l0 * NT), (unsigned long long)(ok ? tm.c0 : 0));
+        if (sizeof(TX) == 8)
+          atomicAdd(reinterpret_cast<unsigned long long*>(mine + tm.l1 * NT), (unsigned long long)(ok ? tm.c1 : 0));
+      }
+      since += B;
+      if (since == NORM_EVERY) {
+        xs_normalise<NL>(get, set);
+        since = 0;
+      }
     }
-    since += MS_B;
-    if (since == NORM_EVERY) {
-      xs_normalise<NL>(get, set);
-      since = 0;
-    }
+    __syncthreads();   // every read of sP done before the next chunk's indices
   }
   xs_normalise<NL>(get, set);
   __syncthreads();
@@ -422,29 +427,50 @@ __global__ __launch_bounds__(MeansCfg<TX>::THREADS) void k_means_acc(const TX* _
   }
 }
 
+// Workgroup of 256 threads: RoundCfg::PAIRS (partition, feature) pairs; thread
+// (pair, limb) adds that limb over the row splits, then one thread per pair
+// rounds.
 template <typename TX>
-__global__ __launch_bounds__(64) void k_means_round(int d, int nsl, int rs, int p,
-                                                    const int64_t* __restrict__ offsets,
-                                                    const int64_t* __restrict__ P, double* __restrict__ C,
-                                                    double* __restrict__ CT, const int32_t* __restrict__ skip,
-                                                    const int32_t* __restrict__ delta,
-                                                    int32_t* __restrict__ done_next) {
-  constexpr int NL = ExactSum<TX>::NL;
+struct RoundCfg {
+  static constexpr int PAIRS = 256 / ExactSum<TX>::NL;
+};
+
+template <typename TX>
+__global__ __launch_bounds__(256) void k_means_round(int d, int nsl, int rs, int p,
+                                                     const int64_t* __restrict__ offsets,
+                                                     const int64_t* __restrict__ P, double* __restrict__ C,
+                                                     double* __restrict__ CT, const int32_t* __restrict__ skip,
+                                                     const int32_t* __restrict__ delta,
+                                                     int32_t* __restrict__ done_next) {
+  constexpr int NL = ExactSum<TX>::NL, PAIRS = RoundCfg<TX>::PAIRS;
   const int skipped = (skip != nullptr) ? *skip : 0;
   if (done_next != nullptr && blockIdx.x == 0 && threadIdx.x == 0)
     *done_next = (skipped || *delta == 0) ? 1 : 0;
   if (skipped) return;
-  const int64_t id = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (id >= (int64_t)p * d) return;
+  __shared__ int64_t sL[PAIRS * NL];
+  const int t = threadIdx.x;
+  const int64_t pd = (int64_t)p * d;
+  if (t < PAIRS * NL) {
+    const int64_t id = (int64_t)blockIdx.x * PAIRS + t / NL;
+    const int k = t % NL;
+    int64_t s = 0;
+    if (id < pd) {
+      const int j = (int)(id / d), f = (int)(id - (int64_t)j * d);
+      const int slice = f / MS_W, fl = f - slice * MS_W;
+      const int64_t* src = P + ((int64_t)(j * nsl + slice) * rs * MS_W + fl) * NL + k;
+      for (int q = 0; q < rs; ++q) s += src[(int64_t)q * MS_W * NL];
+    }
+    sL[t] = s;
+  }
+  __syncthreads();
+  if (t >= PAIRS) return;
+  const int64_t id = (int64_t)blockIdx.x * PAIRS + t;
+  if (id >= pd) return;
   const int j = (int)(id / d), f = (int)(id - (int64_t)j * d);
   const int64_t cnt = offsets[j + 1] - offsets[j];
   if (cnt == 0) return;
-  const int slice = f / MS_W, fl = f - slice * MS_W;
   int64_t limb[NL];
-  for (int k = 0; k < NL; ++k) limb[k] = 0;
-  const int64_t* src = P + ((int64_t)(j * nsl + slice) * rs * MS_W + fl) * NL;
-  for (int s = 0; s < rs; ++s, src += (int64_t)MS_W * NL)
-    for (int k = 0; k < NL; ++k) limb[k] += src[k];
+  for (int k = 0; k < NL; ++k) limb[k] = sL[t * NL + k];
   const double val = xs_round<TX>(limb) / (double)cnt;
   C[(int64_t)j * d + f] = val;
   if (CT != nullptr) CT[(int64_t)f * p + j] = val;
@@ -1040,8 +1066,8 @@ void means_t(krr_ctx ctx, hipStream_t s, const TX* X, int d, const int32_t* perm
   hipLaunchKernelGGL((k_means_acc<TX>), dim3((unsigned)(p * nsl * rs)), dim3(MeansCfg<TX>::THREADS), 0, s, X, d, nsl,
                      rs, perm, offsets, P, skip);
   check_launch(ctx, s, "means_acc");
-  hipLaunchKernelGGL((k_means_round<TX>), dim3((unsigned)ceil_div((int64_t)p * d, 64)), dim3(64), 0, s, d, nsl, rs, p,
-                     offsets, (const int64_t*)P, C, CT, skip, delta, done_next);
+  hipLaunchKernelGGL((k_means_round<TX>), dim3((unsigned)ceil_div((int64_t)p * d, RoundCfg<TX>::PAIRS)), dim3(256), 0,
+                     s, d, nsl, rs, p, offsets, (const int64_t*)P, C, CT, skip, delta, done_next);
   check_launch(ctx, s, "means_round");
 }
 

@@ -420,9 +420,10 @@ __global__ __launch_bounds__(256) void k_trsv_bwd_upd(const SysDesc* __restrict_
 // contributes A(i,j) alpha_j to row block i and, off the diagonal,
 // A(i,j)^T alpha_i to row block j; partials go to P[(row block, col block)]
 // of the system and are summed in column-block order by k_resid_reduce.
-// Row sums combine the 16 column blocks with a butterfly over 16 lanes;
-// column sums combine the 16 row blocks with a butterfly over the 4 lane
-// groups of a wave and then over the 4 waves in LDS (fixed orders).
+// Each thread sums its 4 x 4 block along rows and along columns; the 16
+// threads' partials of one row (column) meet in LDS, where wave 0 adds the
+// row partials and wave 1 the column partials in a fixed order (lane
+// shuffles for these sums had made the kernel bound by LDS permutes).
 __global__ __launch_bounds__(256) void k_resid_tiles(const SysDesc* __restrict__ desc,
                                                      const SysStatus* __restrict__ st, int p,
                                                      const int32_t* __restrict__ grp_first,
@@ -439,8 +440,11 @@ __global__ __launch_bounds__(256) void k_resid_tiles(const SysDesc* __restrict__
   while ((int64_t)(ii + 1) * (ii + 2) / 2 <= bx) ++ii;
   const int jj = bx - ii * (ii + 1) / 2;
   if (ii >= D0.T) return;
-  __shared__ double scol[4][NB];
-  const int t = threadIdx.x, cbk = t & 15, rbk = t >> 4, w = t >> 6;
+  // sr[c][r]: row r's partial from column group c; sc[r][c]: column c's
+  // partial from row group r (rows padded to 66 doubles)
+  __shared__ __align__(16) double sr[16][NB + 2];
+  __shared__ __align__(16) double sc[16][NB + 2];
+  const int t = threadIdx.x, cbk = t & 15, rbk = t >> 4, w = t >> 6, lane = t & 63;
   const double* Kt = K64 + D0.k_off + tile_index(ii, jj) * TILE;
   double K[4][4];   // K[l][k] = K(4 rbk + k, 4 cbk + l)
 #pragma unroll
@@ -453,6 +457,28 @@ __global__ __launch_bounds__(256) void k_resid_tiles(const SysDesc* __restrict__
     K[l][3] = u1.y;
   }
   const bool diag_tile = ii == jj;
+  // the thread's row and column partials into LDS, then the fixed-order sums
+  // of wave 0 (rows, into row block ii, column block jj) and wave 1 (columns,
+  // into row block jj, column block ii; off the diagonal only)
+  auto reduce_out = [&](const double (&rs)[4], const double (&cs)[4], double* out, int T) {
+    *reinterpret_cast<double2*>(&sr[cbk][4 * rbk]) = make_double2(rs[0], rs[1]);
+    *reinterpret_cast<double2*>(&sr[cbk][4 * rbk + 2]) = make_double2(rs[2], rs[3]);
+    *reinterpret_cast<double2*>(&sc[rbk][4 * cbk]) = make_double2(cs[0], cs[1]);
+    *reinterpret_cast<double2*>(&sc[rbk][4 * cbk + 2]) = make_double2(cs[2], cs[3]);
+    __syncthreads();
+    if (w == 0) {
+      double a = 0.0;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) a += sr[c][lane];
+      out[((int64_t)ii * T + jj) * NB + lane] = a;
+    } else if (w == 1 && !diag_tile) {
+      double a = 0.0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) a += sc[r][lane];
+      out[((int64_t)jj * T + ii) * NB + lane] = a;
+    }
+    __syncthreads();   // before the next use of sr / sc
+  };
   // partials of |K| times ones (row sums of |K| for Gershgorin's bounds):
   // the shift only moves the diagonal, so they are formed once for the
   // settings that share K, while any of them has no kappa bound yet, into
@@ -461,42 +487,36 @@ __global__ __launch_bounds__(256) void k_resid_tiles(const SysDesc* __restrict__
   if (Pabs != nullptr)
     for (int q2 = q; q2 >= 0 && !need_abs; q2 = grp_next[q2]) need_abs = st[q2 * p + j].kappa_u < 0.0;
   if (need_abs) {   // uniform over the workgroup
-    double* Ab = Pabs + p_off[q * p + j];
+    double rs[4], cs[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       double acc = 0.0;
 #pragma unroll
       for (int l = 0; l < 4; ++l) acc += fabs(K[l][k]);
-      for (int off = 1; off < 16; off <<= 1) acc += __shfl_xor(acc, off, 64);
-      if (cbk == 0) Ab[((int64_t)ii * D0.T + jj) * NB + 4 * rbk + k] = acc;
+      rs[k] = acc;
     }
-    if (!diag_tile) {
 #pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        double acc = 0.0;
+    for (int l = 0; l < 4; ++l) {
+      double acc = 0.0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) acc += fabs(K[l][k]);
-        acc += __shfl_xor(acc, 16, 64);
-        acc += __shfl_xor(acc, 32, 64);
-        if ((t & 63) < 16) scol[w][4 * cbk + l] = acc;
-      }
-      __syncthreads();
-      if (t < NB)
-        Ab[((int64_t)jj * D0.T + ii) * NB + t] = (scol[0][t] + scol[1][t]) + (scol[2][t] + scol[3][t]);
-      __syncthreads();
+      for (int k = 0; k < 4; ++k) acc += fabs(K[l][k]);
+      cs[l] = acc;
     }
+    reduce_out(rs, cs, Pabs + p_off[q * p + j], D0.T);
   }
   for (; q >= 0; q = grp_next[q]) {
     const int s = q * p + j;
     if (skip_system(st[s], 1)) continue;   // uniform over the workgroup: the residual only for the systems still refining
     const SysDesc D = desc[s];
-    double* Pb = P + p_off[s];
     const double* aj = alpha + D.v_off + jj * NB + 4 * cbk;
-    double av[4];
+    const double* ai = alpha + D.v_off + ii * NB + 4 * rbk;
+    double av[4], bv[4];
 #pragma unroll
     for (int l = 0; l < 4; ++l) av[l] = aj[l];
-    // rows: (K + lambda I)(i,j) alpha_j
-    double rs[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) bv[k] = ai[k];
+    // rows: (K + lambda I)(i,j) alpha_j; columns: K(i,j)^T alpha_i (no shift off the diagonal)
+    double rs[4], cs[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       double acc = 0.0;
@@ -506,32 +526,16 @@ __global__ __launch_bounds__(256) void k_resid_tiles(const SysDesc* __restrict__
         if (diag_tile && rbk == cbk && k == l && ii * NB + 4 * rbk + k < D.m) kv += D.lambda;
         acc = fma(kv, av[l], acc);
       }
-      for (int off = 1; off < 16; off <<= 1) acc += __shfl_xor(acc, off, 64);
       rs[k] = acc;
     }
-    if (cbk == 0) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) Pb[((int64_t)ii * D.T + jj) * NB + 4 * rbk + k] = rs[k];
+    for (int l = 0; l < 4; ++l) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc = fma(K[l][k], bv[k], acc);
+      cs[l] = acc;
     }
-    if (!diag_tile) {   // columns: K(i,j)^T alpha_i (no shift off the diagonal)
-      const double* ai = alpha + D.v_off + ii * NB + 4 * rbk;
-      double bv[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) bv[k] = ai[k];
-#pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc = fma(K[l][k], bv[k], acc);
-        acc += __shfl_xor(acc, 16, 64);
-        acc += __shfl_xor(acc, 32, 64);
-        if ((t & 63) < 16) scol[w][4 * cbk + l] = acc;
-      }
-      __syncthreads();
-      if (t < NB)
-        Pb[((int64_t)jj * D.T + ii) * NB + t] = (scol[0][t] + scol[1][t]) + (scol[2][t] + scol[3][t]);
-      __syncthreads();
-    }
+    reduce_out(rs, cs, P + p_off[s], D.T);
   }
 }
 
