@@ -177,6 +177,27 @@ def test_kmeans_converges_early(ctx, dev):
     np.testing.assert_array_equal(a.cpu().numpy(), ao)
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_kmeans_with_empty_clusters(ctx, dev, dtype):
+    """Three distinct rows, each repeated, and p = 5: after three k-means++
+    picks every D^2 weight is zero, so the last picks duplicate earlier
+    centres (total 0: the point at floor(u n)), ties send every point to the
+    lowest-index duplicate, and the other duplicates stay empty and keep their
+    centres through the Lloyd passes; all of it bit for bit."""
+    print(f"kmeans empty clusters {dtype.__name__}", flush=True)
+    rows = np.array([[0.0, 1.0, 2.0], [5.0, -1.0, 0.5], [-3.0, 4.0, 1.5]])
+    X = np.repeat(rows, [120, 90, 90], axis=0).astype(dtype)
+    X = X[np.random.default_rng(8).permutation(X.shape[0])]
+    C, a, sz = ctx.partition(_t(X, dev), 5, "kmeans", lloyd_iters=6, seed=4)
+    C0, _ = O.kmeanspp(X, 5, 4)
+    Co, ao, _, _ = O.lloyd(X, C0, 6)
+    np.testing.assert_array_equal(a.cpu().numpy(), ao)
+    np.testing.assert_array_equal(C.cpu().numpy(), Co)
+    szo = np.bincount(ao, minlength=5)
+    np.testing.assert_array_equal(sz.cpu().numpy(), szo)
+    assert (szo == 0).sum() == 2
+
+
 def test_partition_rejects_bad_arguments(ctx, dev):
     from paper_1805_00569_amd import krr
     X = torch.zeros((10, 3), dtype=torch.float32, device=dev)
