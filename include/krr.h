@@ -361,9 +361,11 @@ krr_status krr_select(krr_ctx ctx, hipStream_t stream,
  * krr_model_alpha: copy alpha of partition j (m_j FP64 values, in the order
  * of increasing original point index within the partition) to device memory
  * `alpha` (asynchronous on `stream`); *m receives m_j (host).
- * krr_model_free: release a model (NULL is accepted); waits for the device,
- * then keeps the model's memory in its context for reuse by later models
- * (see krr_memory_in_use; freed by krr_destroy or under budget pressure). */
+ * krr_model_free: release a model (NULL is accepted); waits for the work its
+ * context has queued (on every stream the context has used; other contexts'
+ * work is not waited for), then keeps the model's memory in its context for
+ * reuse by later models (see krr_memory_in_use; freed by krr_destroy or under
+ * budget pressure). */
 krr_status krr_model_alpha(krr_ctx ctx, hipStream_t stream, krr_model model, int32_t j,
                            double* alpha, int64_t* m);
 krr_status krr_model_free(krr_model model);

@@ -591,7 +591,14 @@ krr_status krr_model_free(krr_model model) {
   if (model == nullptr) return KRR_OK;
   krr_ctx ctx = model->ctx;
   (void)hipSetDevice(ctx->device);
-  (void)hipDeviceSynchronize();
+  // only this context's queued work can still read the model (every entry
+  // point checks that a model belongs to the calling context): wait for that,
+  // not for the whole device
+  try {
+    drain(ctx);
+  } catch (const Error&) {
+    (void)hipDeviceSynchronize();
+  }
   model_release(ctx, model->alpha, model->bytes);
   model->data.reset();
   ctx->n_models -= 1;
